@@ -1,0 +1,317 @@
+"""FP64 CPU oracle of the 3D-density-histogram edge-bundling iteration (arXiv 1504.02687).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg of the
+benchmark may import this package; the GPU library and its Python binding never do.
+It shares no code with the GPU path. The arithmetic lives in ``oracle.c`` (plain
+loops, one function per step of the method); this module marshals numpy arrays and
+strings the steps together in the paper's order (Section 3, Fig. 1):
+
+    resample -> splat (Eq. 1/3) -> box chain (Section 3.1) -> density stack (Eq. 3/4)
+    -> gradient -> advection with step halving (Eq. 5) -> Laplacian smoothing.
+
+Functions without an independent pin are marked "parity unpinned" in their docstring.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+import subprocess
+from typing import List, Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile oracle.c with gcc (FP contraction off so the source order is the arithmetic)."""
+    if force or not os.path.exists(_LIB):
+        cmd = ["gcc", "-O2", "-fopenmp", "-ffp-contract=off", "-fno-fast-math", "-shared",
+               "-fPIC", "-o", _LIB + ".tmp", _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(_LIB + ".tmp", _LIB)
+    return _LIB
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        L = ctypes.CDLL(_LIB)
+        P = ctypes.c_void_p
+        i64, i32, f64, u32 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double, ctypes.c_uint32
+        sig = {
+            "orc_num_threads": (ctypes.c_int, []),
+            "orc_set_threads": (None, [ctypes.c_int]),
+            "orc_sigma": (f64, [ctypes.c_int, ctypes.c_int]),
+            "orc_bandwidth": (f64, [ctypes.c_int, f64, f64]),
+            "orc_polyline_length": (f64, [P, i64]),
+            "orc_sample_count": (i64, [f64, f64]),
+            "orc_resample_counts": (i64, [i64, P, P, f64, P, P]),
+            "orc_resample": (None, [i64, P, P, P, P, P]),
+            "orc_splat": (None, [i64, P, P, P, P, i32, i32, i32, P]),
+            "orc_box_brute": (None, [i32, i32, P, i32, P]),
+            "orc_integral_image": (None, [i32, i32, P, P]),
+            "orc_box_integral": (None, [i32, i32, P, i32, P]),
+            "orc_box_chain": (None, [i32, i32, i32, i32, i32, P, P, i32]),
+            "orc_density": (None, [i32, i32, i32, i32, i32, P, P, P, P]),
+            "orc_gradient": (None, [i32, i32, i32, P, P]),
+            "orc_bilinear": (f64, [i32, i32, P, i32, i32, f64, f64]),
+            "orc_advect": (None, [i64, P, P, P, i32, i32, i32, P, P, f64, i32, f64, f64,
+                                  P, P, P, P, P]),
+            "orc_laplacian": (None, [i64, P, P, f64, i32, P]),
+            "orc_ink": (f64, [i64, P, P]),
+        }
+        for name, (res, args) in sig.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _p(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# ----------------------------------------------------------------------- parameters
+
+@dataclasses.dataclass
+class Params:
+    """Parameters of the method (Sections 3.1-3.3 and 5); defaults are the paper's."""
+
+    grid_w: int
+    grid_h: int
+    radii: List[int]
+    delta: float = 1.0          # sampling step (px)
+    passes: int = 3             # box passes (Section 3.1: three)
+    h_max: Optional[float] = None   # None: 2 sigma(r_0) (Section 3.3, Fig. 2)
+    lam: float = 0.9            # bandwidth decay (Fig. 2)
+    eps: float = 1e-6           # Eq. 5 epsilon
+    max_halvings: int = 8       # K
+    smooth_weight: float = 0.5  # Laplacian weight s
+    smooth_passes: int = 1
+    pass_weights: Optional[List[float]] = None   # a_k; None: only the last pass
+    amb_tol: float = 1e-5       # decision margin treated as ambiguous in parity checks
+    bbox: tuple = (0.0, 0.0, 1.0, 1.0)
+
+    def radius(self, it: int) -> int:
+        return int(self.radii[min(it, len(self.radii) - 1)])
+
+    def a(self) -> np.ndarray:
+        if self.pass_weights is None:
+            a = np.zeros(self.passes)
+            a[-1] = 1.0
+            return a
+        return _c(self.pass_weights, np.float64)
+
+    def hmax(self) -> float:
+        if self.h_max is not None and self.h_max > 0:
+            return float(self.h_max)
+        return 2.0 * sigma(self.radius(0), self.passes)
+
+    def bandwidth(self, it: int) -> float:
+        return float(lib().orc_bandwidth(it, self.hmax(), self.lam))
+
+
+def params_for(w) -> Params:
+    """Parameters of a ``workloads.Workload``."""
+    return Params(grid_w=w.grid_w, grid_h=w.grid_h, radii=list(w.radii), delta=w.delta,
+                  passes=w.passes, lam=w.lam, bbox=tuple(w.bbox))
+
+
+def sigma(r: int, passes: int) -> float:
+    return float(lib().orc_sigma(r, passes))
+
+
+# ----------------------------------------------------------------------- steps
+
+def initial_state(node_xy, src, dst, p: Params):
+    """Two-point polylines (source, target) in pixel units (FP64)."""
+    xy = np.asarray(node_xy, dtype=np.float64)
+    x0, y0, x1, y1 = p.bbox
+    px = (xy[:, 0] - x0) / (x1 - x0) * p.grid_w
+    py = (xy[:, 1] - y0) / (y1 - y0) * p.grid_h
+    pts = np.stack([px, py], axis=1)
+    E = len(src)
+    out = np.empty((E, 2, 2), dtype=np.float64)
+    out[:, 0] = pts[np.asarray(src)]
+    out[:, 1] = pts[np.asarray(dst)]
+    off = np.arange(0, 2 * E + 1, 2, dtype=np.int64)
+    return off, out.reshape(-1, 2)
+
+
+def polyline_length(xy) -> float:
+    xy = _c(xy, np.float64)
+    return float(lib().orc_polyline_length(_p(xy), xy.shape[0]))
+
+
+def sample_count(L: float, delta: float) -> int:
+    return int(lib().orc_sample_count(L, delta))
+
+
+def resample(off, xy, delta):
+    """Uniform-arclength resampling of every polyline; returns (off_out, xy_out, lens)."""
+    off = _c(off, np.int64)
+    xy = _c(xy, np.float64)
+    E = off.shape[0] - 1
+    counts = np.empty(E, np.int64)
+    lens = np.empty(E, np.float64)
+    N = lib().orc_resample_counts(E, _p(off), _p(xy), delta, _p(counts), _p(lens))
+    off_out = np.zeros(E + 1, np.int64)
+    np.cumsum(counts, out=off_out[1:])
+    assert off_out[-1] == N
+    xy_out = np.empty((N, 2), np.float64)
+    lib().orc_resample(E, _p(off), _p(xy), _p(off_out), _p(lens), _p(xy_out))
+    return off_out, xy_out, lens
+
+
+def splat(off, xy, group, B, W, H, weight=None):
+    off = _c(off, np.int64)
+    xy = _c(xy, np.float64)
+    group = _c(group, np.int32)
+    weight = None if weight is None else _c(weight, np.int32)
+    hist = np.empty((B, H, W), np.int64)
+    lib().orc_splat(off.shape[0] - 1, _p(off), _p(xy), _p(group), _p(weight), B, W, H, _p(hist))
+    return hist
+
+
+def box_brute(m, r):
+    m = _c(m, np.int64)
+    H, W = m.shape
+    out = np.empty_like(m)
+    lib().orc_box_brute(W, H, _p(m), r, _p(out))
+    return out
+
+
+def integral_image(m):
+    m = _c(m, np.int64)
+    H, W = m.shape
+    out = np.empty((H + 1, W + 1), np.int64)
+    lib().orc_integral_image(W, H, _p(m), _p(out))
+    return out
+
+
+def box_integral(m, r):
+    m = _c(m, np.int64)
+    H, W = m.shape
+    out = np.empty_like(m)
+    lib().orc_box_integral(W, H, _p(m), r, _p(out))
+    return out
+
+
+def box_chain(hist, passes, r, brute=False):
+    """S[k, b] = pass k+1 of the box chain on group b (int64, exact)."""
+    hist = _c(hist, np.int64)
+    B, H, W = hist.shape
+    S = np.empty((passes, B, H, W), np.int64)
+    lib().orc_box_chain(B, W, H, passes, r, _p(hist), _p(S), 1 if brute else 0)
+    return S
+
+
+def density(S, r, a, M):
+    S = _c(S, np.int64)
+    P, B, H, W = S.shape
+    a = _c(a, np.float64)
+    M = _c(M, np.float64)
+    rho = np.empty((B, H, W), np.float64)
+    lib().orc_density(B, W, H, P, r, _p(S), _p(a), _p(M), _p(rho))
+    return rho
+
+
+def gradient(rho):
+    rho = _c(rho, np.float64)
+    B, H, W = rho.shape
+    g = np.empty((B, H, W, 2), np.float64)
+    lib().orc_gradient(B, W, H, _p(rho), _p(g))
+    return g
+
+
+def bilinear(m, x, y, comp=0):
+    """Bilinear sample of a [H, W] or [H, W, C] map at pixel-unit position (x, y)."""
+    m = _c(m, np.float64)
+    H, W = m.shape[:2]
+    stride = 1 if m.ndim == 2 else m.shape[2]
+    return float(lib().orc_bilinear(W, H, _p(m), stride, comp, float(x), float(y)))
+
+
+def advect(off, xy, group, rho, grad, h, K=8, eps=1e-6, amb_tol=1e-5):
+    off = _c(off, np.int64)
+    xy = _c(xy, np.float64)
+    group = _c(group, np.int32)
+    rho = _c(rho, np.float64)
+    grad = _c(grad, np.float64)
+    B, H, W = rho.shape
+    N = xy.shape[0]
+    out = np.empty((N, 2), np.float64)
+    jacc = np.empty(N, np.int32)
+    jfirm = np.empty(N, np.int32)
+    amb = np.empty(N, np.uint32)
+    d = np.empty((N, 2), np.float64)
+    lib().orc_advect(off.shape[0] - 1, _p(off), _p(xy), _p(group), B, W, H, _p(rho), _p(grad),
+                     h, K, eps, amb_tol, _p(out), _p(jacc), _p(jfirm), _p(amb), _p(d))
+    return {"xy": out, "jacc": jacc, "jfirm": jfirm, "amb": amb, "dir": d}
+
+
+def laplacian(off, xy, s=0.5, passes=1):
+    off = _c(off, np.int64)
+    xy = _c(xy, np.float64)
+    out = np.empty_like(xy)
+    lib().orc_laplacian(off.shape[0] - 1, _p(off), _p(xy), s, passes, _p(out))
+    return out
+
+
+def ink(off, xy) -> float:
+    off = _c(off, np.int64)
+    xy = _c(xy, np.float64)
+    return float(lib().orc_ink(off.shape[0] - 1, _p(off), _p(xy)))
+
+
+# ----------------------------------------------------------------------- iteration
+
+def iterate(off, xy, group, M, p: Params, it: int, weight=None, skip_resample=False,
+            keep_maps=True):
+    """One bundling iteration (Fig. 1) from the polyline state (off, xy).
+
+    Returns a dict with the samples, histogram, box passes, density, gradient, the
+    advection record and the new polyline state.
+    """
+    B = int(np.asarray(M).shape[0])
+    W, H = p.grid_w, p.grid_h
+    r = p.radius(it)
+    if skip_resample:
+        s_off, s_xy = _c(off, np.int64), _c(xy, np.float64)
+    else:
+        s_off, s_xy, _ = resample(off, xy, p.delta)
+    hist = splat(s_off, s_xy, group, B, W, H, weight)
+    S = box_chain(hist, p.passes, r)
+    rho = density(S, r, p.a(), M)
+    g = gradient(rho)
+    h = p.bandwidth(it)
+    adv = advect(s_off, s_xy, group, rho, g, h, p.max_halvings, p.eps, p.amb_tol)
+    new_xy = laplacian(s_off, adv["xy"], p.smooth_weight, p.smooth_passes)
+    out = {"off": s_off, "samples": s_xy, "adv": adv, "xy": new_xy, "h": h, "r": r}
+    if keep_maps:
+        out.update(hist=hist, S=S, rho=rho, grad=g)
+    return out
+
+
+def run(node_xy, src, dst, group, M, p: Params, n_iters: int, weight=None):
+    """T iterations from the straight edges; returns the final state and point counts."""
+    off, xy = initial_state(node_xy, src, dst, p)
+    counts = []
+    for it in range(n_iters):
+        res = iterate(off, xy, group, M, p, it, weight, keep_maps=False)
+        off, xy = res["off"], res["xy"]
+        counts.append(int(off[-1]))
+    return off, xy, counts

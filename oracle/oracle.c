@@ -1,0 +1,413 @@
+/*
+ * Plain FP64 CPU oracle of one iteration of 3D-density-histogram edge bundling
+ * (Moura, "3D Density Histograms for Criteria-driven Edge Bundling", arXiv 1504.02687).
+ *
+ * TEST INFRASTRUCTURE ONLY. This file is the slow, obviously correct statement of
+ * what the GPU path computes. Only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark may load it. It shares no code, header, table or helper with
+ * the GPU library, and the GPU library never calls it.
+ *
+ * Conventions (the readings of the paper that the GPU path follows too):
+ *   - points are in pixel units; pixel (u,v) covers [u,u+1) x [v,v+1);
+ *   - polylines are stored in CSR form: off[E+1] (int64) and xy[2*N] (x,y interleaved);
+ *   - maps are [B][H][W] row-major, index (b*H + v)*W + u;
+ *   - every function is a direct loop over its definition: no blocking or fusion.
+ *
+ * Parity pins: every function here is pinned by the CPU tests against closed forms,
+ * brute force or invariants (see the header comment of each function). The
+ * whole-method behaviour against the paper's drawings is parity unpinned: the
+ * paper's figures and datasets are not available.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define EXPORT __attribute__((visibility("default")))
+
+/* ------------------------------------------------------------------ threads */
+
+EXPORT int orc_num_threads(void) {
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+EXPORT void orc_set_threads(int n) {
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
+/* ------------------------------------------------ O7: iteration schedule (Sec. 3.3)
+ * The bandwidth decays geometrically, h_i = lambda^i * h_max (Sec. 2.1 and 3.3), with
+ * h_max a multiple of sigma (2 sigma in the paper's convergence figure).
+ * Reading: sigma of P passes of a (2r+1)-wide box is the standard deviation of the
+ * P-fold convolution of a discrete uniform on {-r..r}: each has variance r(r+1)/3,
+ * so sigma^2 = P r (r+1) / 3.
+ * Pins: the variance of the P-pass impulse response computed by the box chain.
+ */
+EXPORT double orc_sigma(int r, int passes) {
+    return sqrt((double)passes * (double)r * (double)(r + 1) / 3.0);
+}
+
+EXPORT double orc_bandwidth(int iter, double h_max, double lambda) {
+    double h = h_max;
+    for (int i = 0; i < iter; ++i) h *= lambda;
+    return h;
+}
+
+/* ------------------------------------------------ O1: resampling (Sec. 2.1, Sec. 3)
+ * Edges are polylines of sample points spaced by the sampling step delta with fixed
+ * end points; at the start of every iteration each polyline is resampled so that its
+ * points are equally spaced again. Reading: uniform arclength, n = max(1, ceil(L/delta))
+ * + 1 points, point k at arclength k L / (n-1), linear interpolation on the segment
+ * that holds that arclength, end points copied exactly.
+ * Pins: closed form on straight segments, exact end points, counts of axis-aligned
+ * integer-length edges, idempotence on already uniform polylines.
+ */
+EXPORT double orc_polyline_length(const double *xy, int64_t m) {
+    double L = 0.0;
+    for (int64_t j = 0; j + 1 < m; ++j) {
+        double dx = xy[2 * (j + 1)] - xy[2 * j];
+        double dy = xy[2 * (j + 1) + 1] - xy[2 * j + 1];
+        L += sqrt(dx * dx + dy * dy);
+    }
+    return L;
+}
+
+EXPORT int64_t orc_sample_count(double L, double delta) {
+    double q = ceil(L / delta);
+    int64_t n = (int64_t)q;
+    if (n < 1) n = 1;
+    return n + 1;
+}
+
+/* Per-edge lengths and sample counts of the polylines (off, xy); returns the total. */
+EXPORT int64_t orc_resample_counts(int64_t E, const int64_t *off, const double *xy,
+                                   double delta, int64_t *counts, double *lens) {
+    int64_t total = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : total)
+    for (int64_t e = 0; e < E; ++e) {
+        double L = orc_polyline_length(xy + 2 * off[e], off[e + 1] - off[e]);
+        lens[e] = L;
+        counts[e] = orc_sample_count(L, delta);
+        total += counts[e];
+    }
+    return total;
+}
+
+/* Resample every polyline into off_out/xy_out; lens[] are the lengths from above. */
+EXPORT void orc_resample(int64_t E, const int64_t *off_in, const double *xy_in,
+                         const int64_t *off_out, const double *lens, double *xy_out) {
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t e = 0; e < E; ++e) {
+        const double *p = xy_in + 2 * off_in[e];
+        int64_t m = off_in[e + 1] - off_in[e];
+        double *o = xy_out + 2 * off_out[e];
+        int64_t n = off_out[e + 1] - off_out[e];
+        double L = lens[e];
+        o[0] = p[0];
+        o[1] = p[1];
+        o[2 * (n - 1)] = p[2 * (m - 1)];
+        o[2 * (n - 1) + 1] = p[2 * (m - 1) + 1];
+        int64_t j = 0;          /* current segment (p_j, p_j+1) */
+        double C = 0.0;         /* arclength at p_j */
+        double ell = hypot(p[2] - p[0], p[3] - p[1]);
+        for (int64_t k = 1; k + 1 < n; ++k) {
+            double s = (double)k * L / (double)(n - 1);
+            /* move to the last segment whose start arclength is <= s */
+            while (j < m - 2 && C + ell <= s) {
+                C += ell;
+                ++j;
+                ell = hypot(p[2 * (j + 1)] - p[2 * j], p[2 * (j + 1) + 1] - p[2 * j + 1]);
+            }
+            double t = ell > 0.0 ? (s - C) / ell : 0.0;
+            if (t < 0.0) t = 0.0;
+            if (t > 1.0) t = 1.0;
+            o[2 * k] = p[2 * j] + t * (p[2 * (j + 1)] - p[2 * j]);
+            o[2 * k + 1] = p[2 * j + 1] + t * (p[2 * (j + 1) + 1] - p[2 * j + 1]);
+        }
+    }
+}
+
+/* ------------------------------------------------ O2: splatting (Sec. 3.1 Eq. 1, Sec. 3.2 Eq. 3)
+ * H(u,v,b) is the weighted count of edges of bin b present at pixel (u,v). Reading: every
+ * sample point of an edge (end points included) adds the edge weight to the pixel that
+ * contains it, index clamp(floor(x), 0, W-1), clamp(floor(y), 0, H-1). Mixing across bins
+ * is applied after smoothing (linearity), so each point lands in one layer only.
+ * Pins: total mass = sum of n_e * w_e, brute force, edge-permutation invariance, transpose.
+ */
+static int64_t clamp_index(double x, int64_t n) {
+    double f = floor(x);
+    if (f < 0.0) return 0;
+    if (f > (double)(n - 1)) return n - 1;
+    return (int64_t)f;
+}
+
+EXPORT void orc_splat(int64_t E, const int64_t *off, const double *xy, const int32_t *group,
+                      const int32_t *weight, int32_t B, int32_t W, int32_t H, int64_t *hist) {
+    memset(hist, 0, sizeof(int64_t) * (size_t)B * (size_t)W * (size_t)H);
+    for (int64_t e = 0; e < E; ++e) {
+        int64_t w = weight ? weight[e] : 1;
+        int64_t b = group[e];
+        for (int64_t k = off[e]; k < off[e + 1]; ++k) {
+            int64_t u = clamp_index(xy[2 * k], W);
+            int64_t v = clamp_index(xy[2 * k + 1], H);
+            hist[(b * H + v) * W + u] += w;
+        }
+    }
+}
+
+/* ------------------------------------------------ O3: box smoothing (Sec. 3.1)
+ * The Gaussian of Eq. 2 is approximated by P repeated averaging (box) filters computed
+ * from integral images. Reading: zero padding outside the grid and integer window sums;
+ * the (2r+1)^2 divisors are applied once at the end (in the density step).
+ * orc_box_brute is the literal window sum; orc_box_integral computes the same sums from
+ * an integral image and its four corners. The tests require both to agree exactly.
+ */
+EXPORT void orc_box_brute(int32_t W, int32_t H, const int64_t *in, int32_t r, int64_t *out) {
+    for (int64_t v = 0; v < H; ++v)
+        for (int64_t u = 0; u < W; ++u) {
+            int64_t acc = 0;
+            for (int64_t dv = -r; dv <= r; ++dv)
+                for (int64_t du = -r; du <= r; ++du) {
+                    int64_t x = u + du, y = v + dv;
+                    if (x >= 0 && x < W && y >= 0 && y < H) acc += in[y * W + x];
+                }
+            out[v * W + u] = acc;
+        }
+}
+
+/* I has (H+1) x (W+1) entries; I(u,v) = sum of in(u',v') over u' < u, v' < v. */
+EXPORT void orc_integral_image(int32_t W, int32_t H, const int64_t *in, int64_t *I) {
+    int64_t W1 = (int64_t)W + 1;
+    for (int64_t u = 0; u <= W; ++u) I[u] = 0;
+    for (int64_t v = 0; v < H; ++v) {
+        I[(v + 1) * W1] = 0;
+        for (int64_t u = 0; u < W; ++u)
+            I[(v + 1) * W1 + u + 1] = in[v * W + u] + I[v * W1 + u + 1] + I[(v + 1) * W1 + u]
+                                      - I[v * W1 + u];
+    }
+}
+
+EXPORT void orc_box_integral(int32_t W, int32_t H, const int64_t *in, int32_t r, int64_t *out) {
+    int64_t W1 = (int64_t)W + 1;
+    int64_t *I = (int64_t *)malloc(sizeof(int64_t) * (size_t)W1 * (size_t)(H + 1));
+    orc_integral_image(W, H, in, I);
+    for (int64_t v = 0; v < H; ++v) {
+        int64_t v0 = v - r < 0 ? 0 : v - r;
+        int64_t v1 = v + r + 1 > H ? H : v + r + 1;
+        for (int64_t u = 0; u < W; ++u) {
+            int64_t u0 = u - r < 0 ? 0 : u - r;
+            int64_t u1 = u + r + 1 > W ? W : u + r + 1;
+            out[v * W + u] = I[v1 * W1 + u1] - I[v0 * W1 + u1] - I[v1 * W1 + u0] + I[v0 * W1 + u0];
+        }
+    }
+    free(I);
+}
+
+/* S[k][b] for k = 0..P-1 is pass k+1 applied to pass k (pass 0 input is hist[b]). */
+EXPORT void orc_box_chain(int32_t B, int32_t W, int32_t H, int32_t P, int32_t r,
+                          const int64_t *hist, int64_t *S, int32_t brute) {
+    int64_t plane = (int64_t)W * H;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t kb = 0; kb < B; ++kb) {
+        const int64_t *src = hist + kb * plane;
+        for (int64_t k = 0; k < P; ++k) {
+            int64_t *dst = S + (k * B + kb) * plane;
+            if (brute)
+                orc_box_brute(W, H, src, r, dst);
+            else
+                orc_box_integral(W, H, src, r, dst);
+            src = dst;
+        }
+    }
+}
+
+/* ------------------------------------------------ O4: density stack (Sec. 3.2 Eq. 3-4)
+ * Layer l of the 3D density is the smoothed histogram of every bin b weighted by the
+ * interaction matrix, rho_l = sum_b M[l][b] * Sbar_b (Eq. 3 with smoothing moved after
+ * mixing, which is exact because the box chain is linear). Sbar_b = sum_k a_k S_b^k /
+ * (2r+1)^(2k) normalises pass k to an average; the plain method uses a = (0,...,0,1).
+ * Pins: M = identity gives each group's own map; B = 1 is the 2D method; permutation
+ * equivariance in the group labels.
+ */
+EXPORT void orc_density(int32_t B, int32_t W, int32_t H, int32_t P, int32_t r, const int64_t *S,
+                        const double *a, const double *M, double *rho) {
+    int64_t plane = (int64_t)W * H;
+    double c = (double)(2 * r + 1) * (double)(2 * r + 1);
+#pragma omp parallel for schedule(static)
+    for (int64_t px = 0; px < plane; ++px) {
+        for (int64_t l = 0; l < B; ++l) {
+            double acc = 0.0;
+            for (int64_t b = 0; b < B; ++b) {
+                double sbar = 0.0, ck = 1.0;
+                for (int64_t k = 0; k < P; ++k) {
+                    ck *= c;
+                    sbar += a[k] * ((double)S[(k * B + b) * plane + px] / ck);
+                }
+                acc += M[l * B + b] * sbar;
+            }
+            rho[l * plane + px] = acc;
+        }
+    }
+}
+
+/* Gradient of the density (Sec. 3.3 Eq. 5). Reading: central differences at pixel
+ * centres with zero density outside the grid; grad has [B][H][W][2] entries (gx, gy).
+ * Pins: exact on linear maps in the interior; sign and factor 1/2.
+ */
+EXPORT void orc_gradient(int32_t B, int32_t W, int32_t H, const double *rho, double *grad) {
+    int64_t plane = (int64_t)W * H;
+#pragma omp parallel for schedule(static)
+    for (int64_t l = 0; l < B; ++l)
+        for (int64_t v = 0; v < H; ++v)
+            for (int64_t u = 0; u < W; ++u) {
+                const double *m = rho + l * plane;
+                double xl = u > 0 ? m[v * W + u - 1] : 0.0;
+                double xr = u + 1 < W ? m[v * W + u + 1] : 0.0;
+                double yd = v > 0 ? m[(v - 1) * W + u] : 0.0;
+                double yu = v + 1 < H ? m[(v + 1) * W + u] : 0.0;
+                int64_t i = l * plane + v * W + u;
+                grad[2 * i] = 0.5 * (xr - xl);
+                grad[2 * i + 1] = 0.5 * (yu - yd);
+            }
+}
+
+/* Bilinear sample of a map whose pixel (u,v) value sits at the pixel centre (u+1/2, v+1/2);
+ * taps are clamped into the grid. stride/comp select one component of an interleaved map.
+ * Pins: reproduces linear functions exactly away from the border.
+ */
+EXPORT double orc_bilinear(int32_t W, int32_t H, const double *map, int32_t stride, int32_t comp,
+                           double x, double y) {
+    double fx = x - 0.5, fy = y - 0.5;
+    double u0f = floor(fx), v0f = floor(fy);
+    double tx = fx - u0f, ty = fy - v0f;
+    int64_t u0 = (int64_t)u0f, v0 = (int64_t)v0f, u1 = u0 + 1, v1 = v0 + 1;
+    if (u0 < 0) u0 = 0;
+    if (u0 > W - 1) u0 = W - 1;
+    if (u1 < 0) u1 = 0;
+    if (u1 > W - 1) u1 = W - 1;
+    if (v0 < 0) v0 = 0;
+    if (v0 > H - 1) v0 = H - 1;
+    if (v1 < 0) v1 = 0;
+    if (v1 > H - 1) v1 = H - 1;
+    double f00 = map[(v0 * W + u0) * stride + comp], f10 = map[(v0 * W + u1) * stride + comp];
+    double f01 = map[(v1 * W + u0) * stride + comp], f11 = map[(v1 * W + u1) * stride + comp];
+    return (1.0 - tx) * (1.0 - ty) * f00 + tx * (1.0 - ty) * f10 + (1.0 - tx) * ty * f01 +
+           tx * ty * f11;
+}
+
+/* ------------------------------------------------ O5: advection with step halving (Sec. 3.3)
+ * Each interior point x of an edge in bin b moves along the normalised gradient of layer
+ * l = b (Eq. 5): d = g / max(|g|, eps) with g the bilinear gradient at x. The step starts
+ * at m = h and is halved until the density at the new place is not lower than at x, or
+ * until m reaches zero. Readings: at most K halvings (tries m = h / 2^j for j = 0..K),
+ * then the point stays; candidates are clamped into [0, W - 2^-8] x [0, H - 2^-8] before
+ * their density is read; end points never move.
+ *
+ * Outputs per point: the moved position, jacc = accepted j (-1: no move, -2: end point),
+ * dir = d, and for decision parity amb = bitmask of tries whose density margin is within
+ * amb_tol * (|rho(x)| + |rho(x')|) of zero (ambiguous in finite precision), evaluated up
+ * to the first unambiguous acceptance, whose index is written to jfirm (-1 if none).
+ * Pins: every accepted move satisfies rho(x') >= rho(x); zero gradient gives no move; a
+ * point near an isolated smoothed impulse moves radially in closed form; a straight edge
+ * on a pixel-centre row of a symmetric map never leaves the row.
+ */
+EXPORT void orc_advect(int64_t E, const int64_t *off, const double *xy, const int32_t *group,
+                       int32_t B, int32_t W, int32_t H, const double *rho, const double *grad,
+                       double h, int32_t K, double eps, double amb_tol, double *xy_out,
+                       int32_t *jacc, int32_t *jfirm, uint32_t *amb, double *dir) {
+    (void)B;
+    int64_t plane = (int64_t)W * H;
+    double xmax = (double)W - 1.0 / 256.0, ymax = (double)H - 1.0 / 256.0;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t e = 0; e < E; ++e) {
+        const double *rl = rho + (int64_t)group[e] * plane;
+        const double *gl = grad + (int64_t)group[e] * plane * 2;
+        for (int64_t i = off[e]; i < off[e + 1]; ++i) {
+            double x = xy[2 * i], y = xy[2 * i + 1];
+            xy_out[2 * i] = x;
+            xy_out[2 * i + 1] = y;
+            dir[2 * i] = 0.0;
+            dir[2 * i + 1] = 0.0;
+            amb[i] = 0;
+            if (i == off[e] || i == off[e + 1] - 1) {
+                jacc[i] = -2;
+                jfirm[i] = -2;
+                continue;
+            }
+            double gx = orc_bilinear(W, H, gl, 2, 0, x, y);
+            double gy = orc_bilinear(W, H, gl, 2, 1, x, y);
+            double nrm = sqrt(gx * gx + gy * gy);
+            double den = nrm > eps ? nrm : eps;
+            double dx = gx / den, dy = gy / den;
+            dir[2 * i] = dx;
+            dir[2 * i + 1] = dy;
+            double r0 = orc_bilinear(W, H, rl, 1, 0, x, y);
+            int32_t acc = -1, firm = -1;
+            uint32_t mask = 0;
+            double m = h;
+            for (int32_t j = 0; j <= K; ++j, m *= 0.5) {
+                double cx = x + m * dx, cy = y + m * dy;
+                if (cx < 0.0) cx = 0.0;
+                if (cx > xmax) cx = xmax;
+                if (cy < 0.0) cy = 0.0;
+                if (cy > ymax) cy = ymax;
+                double r1 = orc_bilinear(W, H, rl, 1, 0, cx, cy);
+                double margin = r1 - r0;
+                int ambiguous = fabs(margin) <= amb_tol * (fabs(r0) + fabs(r1));
+                if (ambiguous) mask |= 1u << j;
+                if (acc < 0 && r1 >= r0) {
+                    acc = j;
+                    xy_out[2 * i] = cx;
+                    xy_out[2 * i + 1] = cy;
+                }
+                if (!ambiguous && r1 >= r0) {
+                    firm = j;
+                    break;
+                }
+            }
+            jacc[i] = acc;
+            jfirm[i] = firm;
+            amb[i] = mask;
+        }
+    }
+}
+
+/* ------------------------------------------------ O6: Laplacian smoothing (Sec. 2.1, Sec. 3.3)
+ * After advection every polyline is smoothed like FDEB/KDEEB do. Reading: Jacobi passes
+ * y_j = (1-s) x_j + (s/2)(x_{j-1} + x_{j+1}) on interior points, end points fixed.
+ * Pins: uniform straight polylines and linear sequences are fixed points; zig-zag closed form.
+ */
+EXPORT void orc_laplacian(int64_t E, const int64_t *off, const double *xy_in, double s,
+                          int32_t passes, double *xy_out) {
+    int64_t N = off[E];
+    double *tmp = (double *)malloc(sizeof(double) * 2 * (size_t)(N > 0 ? N : 1));
+    memcpy(xy_out, xy_in, sizeof(double) * 2 * (size_t)N);
+    for (int32_t p = 0; p < passes; ++p) {
+        memcpy(tmp, xy_out, sizeof(double) * 2 * (size_t)N);
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int64_t e = 0; e < E; ++e)
+            for (int64_t i = off[e] + 1; i + 1 < off[e + 1]; ++i)
+                for (int c = 0; c < 2; ++c)
+                    xy_out[2 * i + c] =
+                        (1.0 - s) * tmp[2 * i + c] + 0.5 * s * (tmp[2 * (i - 1) + c] + tmp[2 * (i + 1) + c]);
+    }
+    free(tmp);
+}
+
+/* Total polyline length ("ink") in FP64. */
+EXPORT double orc_ink(int64_t E, const int64_t *off, const double *xy) {
+    double total = 0.0;
+    for (int64_t e = 0; e < E; ++e) total += orc_polyline_length(xy + 2 * off[e], off[e + 1] - off[e]);
+    return total;
+}

@@ -1,0 +1,438 @@
+"""Pins of the FP64 oracle against closed forms, brute force and invariants.
+
+Each pin is computed independently of the oracle's own code (numpy/scipy brute
+force or a closed form), so that a plausible mistake in the oracle (a dropped term,
+a wrong sign, an off-by-one window, a transposed operand) fails at least one test.
+"""
+
+import math
+
+import numpy as np
+import pytest
+import scipy.ndimage
+import scipy.signal
+
+import oracle as O
+
+
+def rng(seed=0):
+    return np.random.default_rng(seed)
+
+
+# ------------------------------------------------------------------ resampling (Sec. 2.1, 3)
+
+def test_resample_straight_axis_closed_form():
+    off = np.array([0, 2], np.int64)
+    xy = np.array([[10.25, 20.5], [110.25, 20.5]])
+    o, s, _ = O.resample(off, xy, 1.0)
+    assert o[-1] == 101
+    np.testing.assert_array_equal(s[:, 1], 20.5)
+    np.testing.assert_allclose(s[:, 0], 10.25 + np.arange(101), atol=1e-12)
+
+
+def test_resample_diagonal_closed_form():
+    off = np.array([0, 2], np.int64)
+    xy = np.array([[0.0, 0.0], [30.0, 40.0]])
+    o, s, lens = O.resample(off, xy, 1.0)
+    assert lens[0] == 50.0 and o[-1] == 51
+    k = np.arange(51)
+    np.testing.assert_allclose(s, np.stack([0.6 * k, 0.8 * k], 1), atol=1e-12)
+
+
+@pytest.mark.parametrize("L,delta,n", [(37.0, 1.0, 38), (37.0, 4.0, 11), (0.0, 1.0, 2),
+                                       (0.3, 1.0, 2), (1.0, 1.0, 2), (2.5, 1.0, 4)])
+def test_sample_count(L, delta, n):
+    off = np.array([0, 2], np.int64)
+    xy = np.array([[5.0, 7.0], [5.0 + L, 7.0]])
+    o, s, _ = O.resample(off, xy, delta)
+    assert o[-1] == n
+    np.testing.assert_array_equal(s[0], xy[0])
+    np.testing.assert_array_equal(s[-1], xy[1])
+
+
+def _np_resample(p, delta):
+    seg = np.hypot(*np.diff(p, axis=0).T)
+    C = np.concatenate([[0.0], np.cumsum(seg)])
+    L = C[-1]
+    n = max(1, math.ceil(L / delta)) + 1
+    s = np.arange(n) * L / (n - 1)
+    return np.stack([np.interp(s, C, p[:, 0]), np.interp(s, C, p[:, 1])], 1)
+
+
+def test_resample_matches_numpy_interp_on_random_polylines():
+    g = rng(1)
+    polys = [np.cumsum(g.normal(0, 3, (int(m), 2)), 0) + 100 for m in g.integers(2, 40, 50)]
+    off = np.concatenate([[0], np.cumsum([len(p) for p in polys])]).astype(np.int64)
+    o, s, _ = O.resample(off, np.concatenate(polys), 1.0)
+    for e, p in enumerate(polys):
+        ref = _np_resample(p, 1.0)
+        got = s[o[e]:o[e + 1]]
+        assert got.shape == ref.shape
+        np.testing.assert_allclose(got, ref, atol=1e-9)
+        np.testing.assert_array_equal(got[0], p[0])
+        np.testing.assert_array_equal(got[-1], p[-1])
+
+
+def test_resample_idempotent_on_straight_polylines():
+    g = rng(2)
+    t = np.sort(g.random(30))
+    t[0], t[-1] = 0.0, 1.0
+    # collinear, uneven spacing, length 100.5 (away from an integer: counts are then
+    # unambiguous; at integer lengths the FP64 sum may land on either side)
+    p = np.stack([3.0 + 80.4 * t, 5.0 + 60.3 * t], 1)
+    off = np.array([0, 30], np.int64)
+    o1, s1, _ = O.resample(off, p, 1.0)
+    o2, s2, _ = O.resample(o1, s1, 1.0)
+    assert o1[-1] == 102 and o2[-1] == 102
+    np.testing.assert_allclose(s2, s1, atol=1e-9)
+
+
+# ------------------------------------------------------------------ splat (Eq. 1 / Eq. 3)
+
+def _np_splat(off, xy, group, B, W, H, weight=None):
+    h = np.zeros((B, H, W), np.int64)
+    E = len(off) - 1
+    eid = np.repeat(np.arange(E), np.diff(off))
+    w = np.ones(E, np.int64) if weight is None else weight.astype(np.int64)
+    u = np.clip(np.floor(xy[:, 0]), 0, W - 1).astype(np.int64)
+    v = np.clip(np.floor(xy[:, 1]), 0, H - 1).astype(np.int64)
+    np.add.at(h, (group[eid], v, u), w[eid])
+    return h
+
+
+def _random_points(g, E, W, H, B):
+    counts = g.integers(2, 30, E)
+    off = np.concatenate([[0], np.cumsum(counts)]).astype(np.int64)
+    xy = np.stack([g.uniform(-2, W + 2, off[-1]), g.uniform(-2, H + 2, off[-1])], 1)
+    group = g.integers(0, B, E).astype(np.int32)
+    return off, xy, group
+
+
+def test_splat_matches_bruteforce_and_mass():
+    g = rng(3)
+    W, H, B, E = 37, 29, 3, 200
+    off, xy, group = _random_points(g, E, W, H, B)
+    weight = g.integers(1, 5, E).astype(np.int32)
+    h = O.splat(off, xy, group, B, W, H, weight)
+    np.testing.assert_array_equal(h, _np_splat(off, xy, group, B, W, H, weight))
+    assert h.sum() == (np.diff(off) * weight).sum()
+
+
+def test_splat_pixel_boundaries_and_clamp():
+    off = np.array([0, 5], np.int64)
+    xy = np.array([[5.0, 3.0], [4.999999, 3.0], [16.0, 0.0], [-0.5, 15.9], [15.99, -3.0]])
+    h = O.splat(off, xy, np.zeros(1, np.int32), 1, 16, 16)
+    assert h[0, 3, 5] == 1 and h[0, 3, 4] == 1 and h[0, 0, 15] == 2 and h[0, 15, 0] == 1
+
+
+def test_splat_permutation_and_transpose():
+    g = rng(4)
+    W = H = 32
+    off, xy, group = _random_points(g, 100, W, H, 2)
+    h = O.splat(off, xy, group, 2, W, H)
+    perm = g.permutation(100)
+    cnt = np.diff(off)[perm]
+    off2 = np.concatenate([[0], np.cumsum(cnt)]).astype(np.int64)
+    xy2 = np.concatenate([xy[off[e]:off[e + 1]] for e in perm])
+    np.testing.assert_array_equal(O.splat(off2, xy2, group[perm], 2, W, H), h)
+    ht = O.splat(off, xy[:, ::-1], group, 2, W, H)
+    np.testing.assert_array_equal(ht, h.transpose(0, 2, 1))
+
+
+# ------------------------------------------------------------------ box chain (Sec. 3.1)
+
+@pytest.mark.parametrize("W,H,r", [(17, 11, 1), (20, 20, 3), (16, 9, 4), (8, 8, 7)])
+def test_box_brute_integral_scipy_agree(W, H, r):
+    m = rng(5).integers(0, 1000, (H, W)).astype(np.int64)
+    ref = scipy.signal.convolve2d(m, np.ones((2 * r + 1, 2 * r + 1), np.int64), mode="same")
+    np.testing.assert_array_equal(O.box_brute(m, r), ref)
+    np.testing.assert_array_equal(O.box_integral(m, r), ref)
+
+
+def test_integral_image_corner_is_total():
+    m = rng(6).integers(0, 50, (13, 21)).astype(np.int64)
+    I = O.integral_image(m)
+    assert I[-1, -1] == m.sum()
+    np.testing.assert_array_equal(I[1:, 1:], m.cumsum(0).cumsum(1))
+    assert (I[0] == 0).all() and (I[:, 0] == 0).all()
+
+
+@pytest.mark.parametrize("P,r", [(1, 2), (3, 2), (3, 4), (2, 5)])
+def test_box_chain_impulse_closed_form(P, r):
+    W = H = 2 * P * r + 9
+    c = W // 2
+    hist = np.zeros((1, H, W), np.int64)
+    hist[0, c, c] = 1
+    S = O.box_chain(hist, P, r)
+    S2 = O.box_chain(hist, P, r, brute=True)
+    np.testing.assert_array_equal(S, S2)
+    k = np.ones(1, np.int64)
+    for _ in range(P):
+        k = np.convolve(k, np.ones(2 * r + 1, np.int64))     # coefficients of (1+z+..+z^2r)^P
+    ref = np.zeros((H, W), np.int64)
+    ref[c - P * r:c + P * r + 1, c - P * r:c + P * r + 1] = np.outer(k, k)
+    np.testing.assert_array_equal(S[-1, 0], ref)
+    if P >= 1:
+        first = np.zeros((H, W), np.int64)
+        first[c - r:c + r + 1, c - r:c + r + 1] = 1
+        np.testing.assert_array_equal(S[0, 0], first)
+    # mass and per-axis variance of P passes: sigma^2 = P r (r+1) / 3
+    assert S[-1, 0].sum() == (2 * r + 1) ** (2 * P)
+    d = np.arange(W) - c
+    prof = S[-1, 0].sum(0).astype(np.float64)
+    var = (prof * d ** 2).sum() / prof.sum()
+    assert abs(var - O.sigma(r, P) ** 2) < 1e-9
+
+
+def test_box_chain_mass_conserved_away_from_border():
+    P, r, W = 3, 3, 48
+    hist = np.zeros((2, W, W), np.int64)
+    g = rng(7)
+    inner = slice(P * r + 1, W - P * r - 1)
+    hist[:, inner, inner] = g.integers(0, 9, hist[:, inner, inner].shape)
+    S = O.box_chain(hist, P, r)
+    np.testing.assert_array_equal(S[-1].sum((1, 2)), hist.sum((1, 2)) * (2 * r + 1) ** (2 * P))
+
+
+# ------------------------------------------------------------------ density stack (Eq. 3 / Eq. 4)
+
+def test_density_preserves_constant_maps_in_interior():
+    P, r, W = 3, 2, 40
+    hist = np.full((1, W, W), 7, np.int64)
+    S = O.box_chain(hist, P, r)
+    rho = O.density(S, r, np.array([0, 0, 1.0]), np.ones((1, 1)))
+    m = P * r
+    np.testing.assert_allclose(rho[0, m:W - m, m:W - m], 7.0, rtol=1e-15)
+    rho1 = O.density(S, r, np.array([1.0, 0, 0]), np.ones((1, 1)))
+    np.testing.assert_allclose(rho1[0, r:W - r, r:W - r], 7.0, rtol=1e-15)
+
+
+def _float_box(m, r, P):
+    k = np.ones((2 * r + 1, 2 * r + 1)) / (2 * r + 1) ** 2
+    for _ in range(P):
+        m = scipy.signal.convolve2d(m, k, mode="same")
+    return m
+
+
+def test_density_equals_mixing_before_smoothing():
+    """Eq. 3 mixes at the histogram and smooths afterwards; the oracle mixes after smoothing."""
+    g = rng(8)
+    B, W, H, P, r = 3, 24, 20, 3, 2
+    hist = g.integers(0, 20, (B, H, W)).astype(np.int64)
+    M = g.normal(0, 1, (B, B))
+    rho = O.density(O.box_chain(hist, P, r), r, np.array([0, 0, 1.0]), M)
+    for l in range(B):
+        mixed = np.tensordot(M[l], hist.astype(np.float64), axes=1)
+        np.testing.assert_allclose(rho[l], _float_box(mixed, r, P), rtol=1e-10, atol=1e-10)
+
+
+def test_density_identity_and_permutation():
+    g = rng(9)
+    B, W, P, r = 4, 16, 3, 1
+    hist = g.integers(0, 20, (B, W, W)).astype(np.int64)
+    S = O.box_chain(hist, P, r)
+    a = np.array([0.2, 0.3, 0.5])
+    rho_I = O.density(S, r, a, np.eye(B))
+    for b in range(B):
+        rho_b = O.density(O.box_chain(hist[b:b + 1], P, r), r, a, np.ones((1, 1)))
+        np.testing.assert_array_equal(rho_I[b], rho_b[0])
+    M = g.normal(0, 1, (B, B))
+    perm = g.permutation(B)
+    rho = O.density(S, r, a, M)
+    rho_p = O.density(O.box_chain(hist[perm], P, r), r, a, M[np.ix_(perm, perm)])
+    np.testing.assert_allclose(rho_p, rho[perm], rtol=1e-14, atol=1e-14)
+
+
+def test_eq4_fixture():
+    import os
+    import workloads
+    path = os.path.join(os.path.dirname(__file__), "golden", "eq4_interaction.txt")
+    rows = [ln.split() for ln in open(path) if ln.strip() and not ln.startswith("#")]
+    for B, alpha, diag, off in rows:
+        M = workloads.interaction_eq4(int(B), float(alpha))
+        assert M[0, 0] == np.float32(float(diag))
+        assert M[0, 1] == np.float32(float(off))
+
+
+# ------------------------------------------------------------------ gradient and bilinear
+
+def test_gradient_of_linear_map_is_exact_inside():
+    W, H = 12, 9
+    v, u = np.mgrid[0:H, 0:W]
+    rho = (3.0 + 0.75 * u - 1.25 * v)[None].astype(np.float64)
+    g = O.gradient(rho)
+    np.testing.assert_allclose(g[0, 1:-1, 1:-1, 0], 0.75, rtol=1e-15)
+    np.testing.assert_allclose(g[0, 1:-1, 1:-1, 1], -1.25, rtol=1e-15)
+    # zero outside the grid
+    np.testing.assert_allclose(g[0, 4, 0, 0], 0.5 * (rho[0, 4, 1] - 0.0))
+    np.testing.assert_allclose(g[0, H - 1, 5, 1], 0.5 * (0.0 - rho[0, H - 2, 5]))
+
+
+def test_bilinear_reproduces_linear_functions_and_scipy():
+    W, H = 10, 7
+    v, u = np.mgrid[0:H, 0:W]
+    m = 2.0 + 0.5 * u + 0.25 * v
+    g = rng(10)
+    for x, y in g.uniform(0.5, [W - 0.5, H - 0.5], (50, 2)):
+        assert abs(O.bilinear(m, x, y) - (2.0 + 0.5 * (x - 0.5) + 0.25 * (y - 0.5))) < 1e-12
+    r = g.random((H, W))
+    for x, y in g.uniform(-1, [W + 1, H + 1], (80, 2)):
+        ref = scipy.ndimage.map_coordinates(r, [[y - 0.5], [x - 0.5]], order=1, mode="nearest")[0]
+        assert abs(O.bilinear(r, x, y) - ref) < 1e-12
+    assert O.bilinear(r, 3.5, 2.5) == r[2, 3]
+
+
+# ------------------------------------------------------------------ advection (Eq. 5 + halving)
+
+def _bump(W, c, P, r):
+    hist = np.zeros((1, W, W), np.int64)
+    hist[0, c, c] = 1000
+    S = O.box_chain(hist, P, r)
+    rho = O.density(S, r, np.array([0, 0, 1.0]), np.ones((1, 1)))
+    return rho, O.gradient(rho)
+
+
+def test_advect_accepts_only_non_lower_density_and_end_points_fixed():
+    g = rng(11)
+    W, B = 48, 2
+    hist = g.integers(0, 5, (B, W, W)).astype(np.int64)
+    rho = O.density(O.box_chain(hist, 3, 3), 3, np.array([0, 0, 1.0]), np.array([[1, -.1], [-.1, 1]]))
+    grad = O.gradient(rho)
+    off, xy, group = _random_points(g, 60, W, W, B)
+    xy = np.clip(xy, 0, W - 1 / 256)
+    res = O.advect(off, xy, group, rho, grad, h=6.0)
+    moved = res["jacc"] >= 0
+    assert moved.sum() > 0.5 * len(xy) - 2 * 60
+    for i in np.nonzero(moved)[0]:
+        e = np.searchsorted(off, i, side="right") - 1
+        m = rho[group[e]]
+        # independent bilinear (scipy, pixel centres at +1/2, nearest-edge clamping)
+        r0 = scipy.ndimage.map_coordinates(m, [[xy[i, 1] - .5], [xy[i, 0] - .5]], order=1, mode="nearest")[0]
+        r1 = scipy.ndimage.map_coordinates(m, [[res["xy"][i, 1] - .5], [res["xy"][i, 0] - .5]], order=1, mode="nearest")[0]
+        assert r1 >= r0 - 1e-12 * abs(r0)
+        step = np.hypot(*(res["xy"][i] - xy[i]))
+        assert step <= 6.0 / 2 ** res["jacc"][i] + 1e-9
+    ends = np.concatenate([off[:-1], off[1:] - 1])
+    np.testing.assert_array_equal(res["xy"][ends], xy[ends])
+    assert (res["jacc"][ends] == -2).all()
+
+
+def test_advect_flat_map_does_not_move():
+    W = 32
+    rho = np.full((1, W, W), 5.0)
+    grad = O.gradient(rho)     # zero inside, non-zero only on the border pixels
+    off = np.array([0, 3], np.int64)
+    xy = np.array([[10.2, 10.7], [15.3, 16.1], [20.0, 20.0]])
+    res = O.advect(off, xy, np.zeros(1, np.int32), rho, grad, h=4.0)
+    np.testing.assert_array_equal(res["xy"], xy)
+    assert res["jacc"][1] == 0
+
+
+@pytest.mark.parametrize("x,h", [(26.5, 2.0), (26.5, 12.0), (27.25, 3.0), (36.0, 9.0), (38.0, 40.0), (31.0, 5.0)])
+def test_advect_toward_isolated_bump_closed_form(x, h):
+    """On the row through a symmetric bump the gradient points at the peak and the halving
+    loop accepts the first step that does not end farther from the peak than it started."""
+    W, c, P, r = 64, 32, 3, 3
+    rho, grad = _bump(W, c, P, r)
+    y = c + 0.5
+    off = np.array([0, 3], np.int64)
+    xy = np.array([[1.0, 1.0], [x, y], [60.0, 60.0]])
+    res = O.advect(off, xy, np.zeros(1, np.int32), rho, grad, h=h, K=8)
+    peak = c + 0.5
+    sgn = 1.0 if peak > x else -1.0
+    expect = x
+    for j in range(9):
+        cand = x + sgn * h / 2 ** j
+        if abs(cand - peak) <= abs(x - peak):
+            expect = cand
+            break
+    assert res["xy"][1, 1] == y
+    assert abs(res["xy"][1, 0] - expect) < 1e-12
+    assert res["dir"][1, 0] == pytest.approx(sgn) and res["dir"][1, 1] == 0.0
+
+
+# ------------------------------------------------------------------ Laplacian
+
+def test_laplacian_fixed_points_and_zigzag():
+    j = np.arange(12, dtype=np.float64)
+    off = np.array([0, 12, 24], np.int64)
+    line = np.stack([1.0 + 2.0 * j, -3.0 + 0.5 * j], 1)
+    zig = np.stack([j, (-1.0) ** j], 1)
+    out = O.laplacian(off, np.concatenate([line, zig]), s=0.3, passes=1)
+    np.testing.assert_allclose(out[:12], line, atol=1e-12)
+    np.testing.assert_allclose(out[13:23, 1], (-1.0) ** j[1:11] * (1 - 2 * 0.3), atol=1e-12)
+    np.testing.assert_allclose(out[13:23, 0], j[1:11], atol=1e-12)
+    np.testing.assert_array_equal(out[[0, 11, 12, 23]], np.concatenate([line, zig])[[0, 11, 12, 23]])
+
+
+def test_ink_of_known_polylines():
+    off = np.array([0, 2, 5], np.int64)
+    xy = np.array([[0, 0], [3, 4], [0, 0], [1, 0], [1, 1]], np.float64)
+    assert O.ink(off, xy) == 7.0
+
+
+# ------------------------------------------------------------------ whole iterations
+
+def _params(W, radii, **kw):
+    return O.Params(grid_w=W, grid_h=W, radii=radii, **kw)
+
+
+def test_straight_horizontal_edge_stays_on_its_row():
+    W = 64
+    p = _params(W, [4])
+    node = np.array([[10.25 / W, 30.5 / W], [50.75 / W, 30.5 / W]], np.float32)
+    off, xy, counts = O.run(node, np.array([0]), np.array([1]), np.zeros(1, np.int32),
+                            np.ones((1, 1)), p, 5)
+    np.testing.assert_array_equal(xy[:, 1], 30.5)
+    # points slide along the line only (toward the edge's own density peak at its middle),
+    # end points stay, and the result is mirror-symmetric about the midpoint x = 30.5
+    assert xy[0, 0] == 10.25 and xy[-1, 0] == 50.75
+    assert xy[:, 0].min() >= 10.25 and xy[:, 0].max() <= 50.75
+    np.testing.assert_allclose(xy[:, 0] + xy[::-1, 0], 61.0, atol=1e-6)
+    assert counts[0] == 42
+
+
+def test_two_parallel_edges_attract():
+    W = 64
+    p = _params(W, [4])
+    node = np.array([[10, 28.5], [54, 28.5], [10, 33.5], [54, 33.5]], np.float32) / W
+    off, xy, _ = O.run(node, np.array([0, 2]), np.array([1, 3]), np.zeros(2, np.int32),
+                       np.ones((1, 1)), p, 4)
+    mid0 = xy[off[0]:off[1]][len(xy[off[0]:off[1]]) // 2, 1]
+    mid1 = xy[off[1]:off[2]][len(xy[off[1]:off[2]]) // 2, 1]
+    assert mid1 - mid0 < 5.0 - 1.0
+
+
+def test_identity_interaction_equals_independent_runs():
+    g = rng(12)
+    W = 64
+    p = _params(W, [3, 2])
+    node = g.random((40, 2)).astype(np.float32)
+    src, dst = np.arange(0, 20), np.arange(20, 40)
+    group = (np.arange(20) % 2).astype(np.int32)
+    off, xy, _ = O.run(node, src, dst, group, np.eye(2), p, 2)
+    for b in range(2):
+        sel = np.nonzero(group == b)[0]
+        o2, x2, _ = O.run(node, src[sel], dst[sel], np.zeros(len(sel), np.int32), np.ones((1, 1)), p, 2)
+        mine = np.concatenate([xy[off[e]:off[e + 1]] for e in sel])
+        np.testing.assert_array_equal(mine, x2)
+
+
+def test_transposed_input_gives_transposed_output():
+    g = rng(13)
+    W = 64
+    p = _params(W, [3])
+    node = g.random((30, 2)).astype(np.float32)
+    src, dst = np.arange(15), np.arange(15, 30)
+    grp = np.zeros(15, np.int32)
+    off, xy, _ = O.run(node, src, dst, grp, np.ones((1, 1)), p, 3)
+    off_t, xy_t, _ = O.run(node[:, ::-1].copy(), src, dst, grp, np.ones((1, 1)), p, 3)
+    np.testing.assert_array_equal(off, off_t)
+    np.testing.assert_allclose(xy_t[:, ::-1], xy, atol=1e-9)
+
+
+def test_schedule_values():
+    p = _params(256, [8])
+    assert abs(p.hmax() - 2 * math.sqrt(3 * 8 * 9 / 3)) < 1e-12
+    h = [p.bandwidth(i) for i in range(10)]
+    np.testing.assert_allclose(h, [16.97056 * 0.9 ** i for i in range(10)], rtol=1e-6)
