@@ -1,0 +1,191 @@
+/*
+ * hb.h -- C ABI of the MI355X (gfx950) edge-bundling hot path.
+ *
+ * The library runs the per-iteration loop of 3D-density-histogram edge bundling
+ * (Moura, arXiv 1504.02687, Section 3 and Fig. 1) on one GPU:
+ *
+ *   resample every edge polyline into equally spaced points   (Section 2.1, Section 3)
+ *   splat the points into one integer histogram per edge group (Section 3.1 Eq. 1, 3.2 Eq. 3)
+ *   smooth each histogram with P box passes via integral sums  (Section 3.1)
+ *   mix the smoothed maps through the interaction matrix M     (Section 3.2 Eq. 3-4)
+ *   move interior points along the normalised density gradient with step halving
+ *                                                              (Section 3.3 Eq. 5)
+ *   Laplacian-smooth every polyline                            (Section 3.3)
+ *
+ * Conventions for every call:
+ *   - Return value: HB_OK (0) or a negative hb_status. Calls never abort. The text of the
+ *     last error of a context is returned by hb_last_error(ctx).
+ *   - A HIP failure is sticky: after HB_EDEVICE the context only accepts hb_destroy.
+ *   - Inputs are owned by the caller and are not retained: the library copies them. By
+ *     default pointers are host pointers and the call returns after the copy; with
+ *     HB_DEVICE_PTRS they are device pointers on the context's device, read in stream
+ *     order on the context's stream before the call returns.
+ *   - Outputs go to caller-allocated buffers (host, or device with HB_DEVICE_PTRS). A
+ *     buffer that is too small gives HB_EINVAL; query sizes with hb_get_num_points.
+ *   - Coordinates of points are pixel units of the grid: pixel (u, v) covers
+ *     [u, u+1) x [v, v+1). Node coordinates are in user units and are mapped from the
+ *     bounding box bbox = [x0, y0, x1, y1] to [0, W] x [0, H].
+ *   - Polylines are stored in CSR form: offsets[E+1] (int64, offsets[0] = 0) and
+ *     xy[N][2] (float32, x then y). Every polyline has at least two points; its first and
+ *     last points are the edge's end points and never move.
+ *   - Maps are [B][H][W] row-major.
+ *   - One context per host thread; calls on one context must not overlap.
+ */
+#ifndef HB_H
+#define HB_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hb_ctx hb_ctx;
+typedef int32_t hb_status;
+
+enum {
+    HB_OK = 0,
+    HB_EINVAL = -1,     /* bad argument, size or index */
+    HB_ENOMEM = -2,     /* device allocation failed */
+    HB_EDEVICE = -3,    /* HIP error (sticky) */
+    HB_ESTATE = -4,     /* call order: e.g. hb_run before graph, groups and parameters */
+    HB_EOVERFLOW = -5   /* integer range of the histogram or the box sums would be exceeded */
+};
+
+/* flags of the data-movement calls */
+enum { HB_DEVICE_PTRS = 1u };
+
+/* flags of hb_run */
+enum {
+    HB_RUN_SAMPLES_GIVEN = 1u,     /* the first iteration takes the current polylines as its
+                                      sample points (no resampling in that iteration) */
+    HB_RUN_RECORD_DECISIONS = 2u,  /* keep the accepted halving index of every sample point of
+                                      the last iteration (hb_get_decisions) */
+    HB_RUN_ASYNC = 4u              /* return without waiting; errors surface at hb_sync */
+};
+
+/* which point set hb_get_num_points / hb_get_points read */
+enum {
+    HB_POINTS_STATE = 0,    /* the current polylines (after the last Laplacian smoothing) */
+    HB_POINTS_SAMPLES = 1   /* the sample points of the last iteration (after resampling) */
+};
+
+/* map kinds of hb_get_map */
+enum {
+    HB_MAP_HIST = 0,        /* int32 [H][W]: histogram of group b (Eq. 1) */
+    HB_MAP_BOX = 1,         /* int64 [H][W]: box pass k (1..P) of group b, un-normalised sums */
+    HB_MAP_DENSITY = 2,     /* float32 [H][W]: layer l of the density stack (Eq. 3) */
+    HB_MAP_GRAD = 3         /* float32 [H][W][2]: central-difference gradient of layer l */
+};
+
+#define HB_MAX_GROUPS 64
+#define HB_MAX_PASSES 8
+#define HB_MAX_GRID 8192
+#define HB_MAX_HALVINGS 30
+
+/*
+ * Parameters of the method. Section numbers refer to the paper.
+ */
+typedef struct hb_params {
+    uint32_t struct_size;       /* sizeof(hb_params), for ABI versioning */
+    int32_t grid_w, grid_h;     /* histogram size W x H (Section 5: dominant side 800) */
+    float bbox[4];              /* node-coordinate box [x0, y0, x1, y1] mapped to [0,W]x[0,H] */
+    float delta_px;             /* sampling step between resampled points (Section 2.1) */
+    int32_t box_passes;         /* P repeated box filters (Section 3.1: 3) */
+    int32_t n_radii;            /* length of radius_per_iter (>= 1) */
+    const int32_t *radius_per_iter; /* box radius r_i per iteration; the last value repeats.
+                                       Copied by hb_set_params. */
+    float h_max_px;             /* first step h_max; <= 0 selects 2 sigma(r_0) with
+                                   sigma(r)^2 = P r (r+1) / 3 (Section 3.3, Fig. 2) */
+    float lambda;               /* bandwidth decay h_i = lambda^i h_max (Section 2.1: 0.5..0.9) */
+    float eps;                  /* epsilon of Eq. 5 (density units per pixel) */
+    int32_t max_halvings;       /* K: step halvings tried before a point stays (Section 3.3) */
+    float smooth_weight;        /* Laplacian weight s in y = (1-s) x + s (x- + x+)/2 */
+    int32_t smooth_passes;      /* Jacobi passes of the Laplacian smoothing (1) */
+    const float *pass_weights;  /* a[P]: density = sum_k a_k * pass_k / (2r+1)^(2k);
+                                   NULL selects the last pass only. Copied. */
+    float capacity_factor;      /* point-buffer capacity relative to the first sample count
+                                   (>= 1.1; grown automatically when exceeded) */
+} hb_params;
+
+/* Fill p with the paper's defaults for a W x H grid: bbox [0,0,1,1], delta 1 px, P = 3,
+ * radius W/32 for every iteration, h_max = 2 sigma(r_0), lambda 0.9, eps 1e-6, K = 8,
+ * s = 0.5, one smoothing pass, last-pass density, capacity factor 2. Host only. */
+void hb_default_params(hb_params *p, int32_t grid_w, int32_t grid_h);
+
+/* Check p without a context or a device (the same checks hb_set_params makes). */
+hb_status hb_validate_params(const hb_params *p);
+
+/* Create a context on HIP device `device`. hip_stream is a hipStream_t on that device or
+ * NULL (the context creates its own stream of default priority). */
+hb_status hb_create(hb_ctx **out, int32_t device, void *hip_stream);
+
+/* Free every device buffer of ctx; NULL is accepted. Waits for the context's stream. */
+void hb_destroy(hb_ctx *ctx);
+
+/* Set the parameters (Section 3; see hb_params). May be called between runs. */
+hb_status hb_set_params(hb_ctx *ctx, const hb_params *p);
+
+/* Set the graph G = {N, E} (Section 3.1): node positions node_xy[n_nodes][2] in user
+ * coordinates, edges (src[e], dst[e]) with integer weights weight[e] >= 1 (NULL: all 1).
+ * Resets the polylines to the straight segments and the iteration counter to 0.
+ * Requires hb_set_params first (the grid and the bounding box). */
+hb_status hb_set_graph(hb_ctx *ctx, int32_t n_nodes, const float *node_xy, int64_t n_edges,
+                       const int32_t *src, const int32_t *dst, const int32_t *weight,
+                       uint32_t flags);
+
+/* Set the edge groups b_e in [0, B) and the B x B interaction matrix M (Section 3.2 Eq. 3):
+ * M[l * B + b] is the weight of bin b on layer l. B in [1, 64]. */
+hb_status hb_set_groups(hb_ctx *ctx, int32_t n_groups, const int32_t *group, const float *M,
+                        uint32_t flags);
+
+/* Run n_iters iterations of the loop above, continuing the iteration counter (which sets
+ * the radius r_i and the step h_i). Stream ordered; waits at the end unless HB_RUN_ASYNC. */
+hb_status hb_run(hb_ctx *ctx, int32_t n_iters, uint32_t flags);
+
+/* Wait for the context's stream and report deferred errors of an asynchronous run. */
+hb_status hb_sync(hb_ctx *ctx);
+
+/* Number of points of the state or of the last sample set (HB_POINTS_*). */
+hb_status hb_get_num_points(hb_ctx *ctx, int32_t which, int64_t *n_points);
+
+/* Copy offsets[E+1] and xy[N][2] of the state or of the last samples. cap_points is the
+ * capacity of xy in points. */
+hb_status hb_get_points(hb_ctx *ctx, int32_t which, int64_t *offsets, float *xy,
+                        int64_t cap_points, uint32_t flags);
+
+/* Replace the polylines (resume from saved points, or inject test inputs). Every edge
+ * needs at least two points. The iteration counter is not changed. */
+hb_status hb_set_points(hb_ctx *ctx, const int64_t *offsets, const float *xy,
+                        int64_t n_points, uint32_t flags);
+
+/* Copy one map of the last iteration: kind HB_MAP_*, group (or layer) index, pass (1..P,
+ * for HB_MAP_BOX only). bytes is the size of out. */
+hb_status hb_get_map(hb_ctx *ctx, int32_t kind, int32_t group, int32_t pass, void *out,
+                     int64_t bytes, uint32_t flags);
+
+/* Accepted halving index j (step h / 2^j) of every sample point of the last iteration run
+ * with HB_RUN_RECORD_DECISIONS: -1 no move, -2 end point. */
+hb_status hb_get_decisions(hb_ctx *ctx, int8_t *jacc, int64_t cap_points, uint32_t flags);
+
+/* Sample-point counts N_i of the iterations of the last hb_run (host array of n_iters). */
+hb_status hb_get_iter_counts(hb_ctx *ctx, int64_t *counts, int32_t cap);
+
+/* Total polyline length of the state ("ink"), summed in FP64. */
+hb_status hb_get_ink(hb_ctx *ctx, double *ink);
+
+/* Iteration counter (the index i of the next iteration). */
+hb_status hb_get_iteration(hb_ctx *ctx, int32_t *iter);
+hb_status hb_set_iteration(hb_ctx *ctx, int32_t iter);
+
+/* Message of the last error of ctx (ctx NULL: of the calling thread). */
+const char *hb_last_error(const hb_ctx *ctx);
+
+/* Library version string. */
+const char *hb_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HB_H */

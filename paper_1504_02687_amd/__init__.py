@@ -1,0 +1,383 @@
+"""Python binding of the MI355X edge-bundling library (``libhb.so``, C ABI in ``include/hb.h``).
+
+Argument marshalling only: every step of the bundling iteration runs in the HIP kernels of
+``libhb.so``. Arrays may be numpy arrays (host) or torch CUDA tensors (device, passed with
+``HB_DEVICE_PTRS``); torch is only used for device memory and the current stream. If the
+library has not been built, ``load()`` raises: there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libhb.so")
+
+HB_OK, HB_EINVAL, HB_ENOMEM, HB_EDEVICE, HB_ESTATE, HB_EOVERFLOW = 0, -1, -2, -3, -4, -5
+HB_DEVICE_PTRS = 1
+HB_RUN_SAMPLES_GIVEN, HB_RUN_RECORD_DECISIONS, HB_RUN_ASYNC = 1, 2, 4
+HB_POINTS_STATE, HB_POINTS_SAMPLES = 0, 1
+HB_MAP_HIST, HB_MAP_BOX, HB_MAP_DENSITY, HB_MAP_GRAD = 0, 1, 2, 3
+HB_MAX_GROUPS, HB_MAX_PASSES = 64, 8
+
+STATUS_NAMES = {0: "HB_OK", -1: "HB_EINVAL", -2: "HB_ENOMEM", -3: "HB_EDEVICE",
+                -4: "HB_ESTATE", -5: "HB_EOVERFLOW"}
+
+
+class HBError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class hb_params(ctypes.Structure):
+    _fields_ = [
+        ("struct_size", ctypes.c_uint32),
+        ("grid_w", ctypes.c_int32),
+        ("grid_h", ctypes.c_int32),
+        ("bbox", ctypes.c_float * 4),
+        ("delta_px", ctypes.c_float),
+        ("box_passes", ctypes.c_int32),
+        ("n_radii", ctypes.c_int32),
+        ("radius_per_iter", ctypes.POINTER(ctypes.c_int32)),
+        ("h_max_px", ctypes.c_float),
+        ("lambda_", ctypes.c_float),
+        ("eps", ctypes.c_float),
+        ("max_halvings", ctypes.c_int32),
+        ("smooth_weight", ctypes.c_float),
+        ("smooth_passes", ctypes.c_int32),
+        ("pass_weights", ctypes.POINTER(ctypes.c_float)),
+        ("capacity_factor", ctypes.c_float),
+    ]
+
+
+_lib = None
+
+# name -> (restype, argtypes)
+_SIGS = {
+    "hb_default_params": (None, [ctypes.POINTER(hb_params), ctypes.c_int32, ctypes.c_int32]),
+    "hb_validate_params": (ctypes.c_int32, [ctypes.POINTER(hb_params)]),
+    "hb_create": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32, ctypes.c_void_p]),
+    "hb_destroy": (None, [ctypes.c_void_p]),
+    "hb_set_params": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(hb_params)]),
+    "hb_set_graph": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
+    "hb_set_groups": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_uint32]),
+    "hb_run": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32]),
+    "hb_sync": (ctypes.c_int32, [ctypes.c_void_p]),
+    "hb_get_num_points": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
+    "hb_get_points": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_int64, ctypes.c_uint32]),
+    "hb_set_points": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                       ctypes.c_uint32]),
+    "hb_get_map": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                    ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32]),
+    "hb_get_decisions": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32]),
+    "hb_get_iter_counts": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int32]),
+    "hb_get_ink": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double)]),
+    "hb_get_iteration": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32)]),
+    "hb_set_iteration": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "hb_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "hb_version": (ctypes.c_char_p, []),
+}
+
+
+def load():
+    """Load libhb.so (built in-tree by ``build()``); raise if it is missing."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build() or python -m paper_1504_02687_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+def build(verbose: bool = False) -> str:
+    from . import build as _b
+    return _b.build(verbose)
+
+
+def exported_symbols() -> Sequence[str]:
+    return list(_SIGS)
+
+
+# ------------------------------------------------------------------ marshalling
+
+def _is_torch(x) -> bool:
+    return type(x).__module__.startswith("torch")
+
+
+def _arr(x, dtype):
+    """(pointer, keepalive, is_device) of a numpy array or torch tensor with the given dtype."""
+    if x is None:
+        return None, None, False
+    if _is_torch(x):
+        import torch
+        tdt = {np.float32: torch.float32, np.int32: torch.int32, np.int64: torch.int64,
+               np.int8: torch.int8, np.float64: torch.float64}[np.dtype(dtype).type]
+        if x.dtype != tdt or not x.is_contiguous():
+            x = x.to(tdt).contiguous()
+        return x.data_ptr(), x, x.is_cuda
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return a.ctypes.data, a, False
+
+
+def _check(ctx, st):
+    if st != HB_OK:
+        msg = load().hb_last_error(ctx)
+        raise HBError(st, msg.decode() if msg else "")
+
+
+def _flags(*devs):
+    d = [v for v in devs if v is not None]
+    if any(d) and not all(d):
+        raise ValueError("mix of host and device arrays in one call")
+    return HB_DEVICE_PTRS if d and all(d) else 0
+
+
+# ------------------------------------------------------------------ the C calls
+
+def hb_default_params(grid_w: int, grid_h: int) -> hb_params:
+    p = hb_params()
+    load().hb_default_params(ctypes.byref(p), grid_w, grid_h)
+    return p
+
+
+def hb_validate_params(p: hb_params) -> int:
+    return int(load().hb_validate_params(ctypes.byref(p)))
+
+
+def hb_create(device: int = 0, stream: Optional[int] = None):
+    ctx = ctypes.c_void_p()
+    st = load().hb_create(ctypes.byref(ctx), device, ctypes.c_void_p(stream) if stream else None)
+    _check(None, st)
+    return ctx
+
+
+def hb_destroy(ctx) -> None:
+    load().hb_destroy(ctx)
+
+
+def hb_set_params(ctx, p: hb_params) -> None:
+    _check(ctx, load().hb_set_params(ctx, ctypes.byref(p)))
+
+
+def hb_set_graph(ctx, node_xy, src, dst, weight=None) -> None:
+    pn, kn, dn = _arr(node_xy, np.float32)
+    ps, ks, ds = _arr(src, np.int32)
+    pd, kd, dd = _arr(dst, np.int32)
+    pw, kw, dw = _arr(weight, np.int32)
+    flags = _flags(dn, ds, dd, dw if weight is not None else None)
+    n_nodes = int(kn.shape[0])
+    _check(ctx, load().hb_set_graph(ctx, n_nodes, pn, int(ks.shape[0]), ps, pd, pw, flags))
+
+
+def hb_set_groups(ctx, group, M) -> None:
+    pg, kg, dg = _arr(group, np.int32)
+    pm, km, dm = _arr(M, np.float32)
+    B = int(km.shape[0])
+    _check(ctx, load().hb_set_groups(ctx, B, pg, pm, _flags(dg, dm)))
+
+
+def hb_run(ctx, n_iters: int, flags: int = 0) -> None:
+    _check(ctx, load().hb_run(ctx, n_iters, flags))
+
+
+def hb_sync(ctx) -> None:
+    _check(ctx, load().hb_sync(ctx))
+
+
+def hb_get_num_points(ctx, which: int = HB_POINTS_STATE) -> int:
+    n = ctypes.c_int64()
+    _check(ctx, load().hb_get_num_points(ctx, which, ctypes.byref(n)))
+    return int(n.value)
+
+
+def hb_get_points(ctx, which: int = HB_POINTS_STATE, n_edges: Optional[int] = None, device=None):
+    """Offsets [E+1] (int64) and xy [N, 2] (float32) as numpy arrays, or torch tensors on
+    ``device`` when given."""
+    n = hb_get_num_points(ctx, which)
+    if n_edges is None:
+        raise ValueError("n_edges is required")
+    if device is not None:
+        import torch
+        off = torch.empty(n_edges + 1, dtype=torch.int64, device=device)
+        xy = torch.empty((n, 2), dtype=torch.float32, device=device)
+        _check(ctx, load().hb_get_points(ctx, which, off.data_ptr(), xy.data_ptr(), n, HB_DEVICE_PTRS))
+        return off, xy
+    off = np.empty(n_edges + 1, np.int64)
+    xy = np.empty((n, 2), np.float32)
+    _check(ctx, load().hb_get_points(ctx, which, off.ctypes.data, xy.ctypes.data, n, 0))
+    return off, xy
+
+
+def hb_set_points(ctx, offsets, xy) -> None:
+    po, ko, do = _arr(offsets, np.int64)
+    px, kx, dx = _arr(xy, np.float32)
+    n = int(kx.shape[0])
+    _check(ctx, load().hb_set_points(ctx, po, px, n, _flags(do, dx)))
+
+
+def hb_get_map(ctx, kind: int, group: int, grid_w: int, grid_h: int, pass_: int = 0):
+    dtype, extra = {HB_MAP_HIST: (np.int32, ()), HB_MAP_BOX: (np.int64, ()),
+                    HB_MAP_DENSITY: (np.float32, ()), HB_MAP_GRAD: (np.float32, (2,))}[kind]
+    out = np.empty((grid_h, grid_w) + extra, dtype)
+    _check(ctx, load().hb_get_map(ctx, kind, group, pass_, out.ctypes.data, out.nbytes, 0))
+    return out
+
+
+def hb_get_decisions(ctx) -> np.ndarray:
+    n = hb_get_num_points(ctx, HB_POINTS_SAMPLES)
+    out = np.empty(n, np.int8)
+    _check(ctx, load().hb_get_decisions(ctx, out.ctypes.data, n, 0))
+    return out
+
+
+def hb_get_iter_counts(ctx, n_iters: int) -> np.ndarray:
+    out = np.zeros(max(1, n_iters), np.int64)
+    _check(ctx, load().hb_get_iter_counts(ctx, out.ctypes.data, len(out)))
+    return out[:n_iters]
+
+
+def hb_get_ink(ctx) -> float:
+    v = ctypes.c_double()
+    _check(ctx, load().hb_get_ink(ctx, ctypes.byref(v)))
+    return float(v.value)
+
+
+def hb_get_iteration(ctx) -> int:
+    v = ctypes.c_int32()
+    _check(ctx, load().hb_get_iteration(ctx, ctypes.byref(v)))
+    return int(v.value)
+
+
+def hb_set_iteration(ctx, it: int) -> None:
+    _check(ctx, load().hb_set_iteration(ctx, it))
+
+
+def hb_last_error(ctx=None) -> str:
+    m = load().hb_last_error(ctx)
+    return m.decode() if m else ""
+
+
+def hb_version() -> str:
+    return load().hb_version().decode()
+
+
+# ------------------------------------------------------------------ convenience
+
+def make_params(grid_w: int, grid_h: int, radii: Sequence[int], *, delta: float = 1.0,
+                passes: int = 3, h_max: float = 0.0, lam: float = 0.9, eps: float = 1e-6,
+                max_halvings: int = 8, smooth_weight: float = 0.5,
+                pass_weights: Optional[Sequence[float]] = None, bbox=(0.0, 0.0, 1.0, 1.0),
+                capacity_factor: float = 2.0):
+    """hb_params plus the arrays it points to (keep both alive until hb_set_params)."""
+    p = hb_default_params(grid_w, grid_h)
+    r = (ctypes.c_int32 * len(radii))(*[int(v) for v in radii])
+    p.radius_per_iter = ctypes.cast(r, ctypes.POINTER(ctypes.c_int32))
+    p.n_radii = len(radii)
+    p.delta_px = delta
+    p.box_passes = passes
+    p.h_max_px = h_max
+    p.lambda_ = lam
+    p.eps = eps
+    p.max_halvings = max_halvings
+    p.smooth_weight = smooth_weight
+    for i in range(4):
+        p.bbox[i] = bbox[i]
+    p.capacity_factor = capacity_factor
+    keep = [r]
+    if pass_weights is not None:
+        a = (ctypes.c_float * passes)(*[float(v) for v in pass_weights])
+        p.pass_weights = ctypes.cast(a, ctypes.POINTER(ctypes.c_float))
+        keep.append(a)
+    return p, keep
+
+
+class Bundler:
+    """One library context on one GPU (owns an ``hb_ctx``)."""
+
+    def __init__(self, device: int = 0, stream: Optional[int] = None):
+        self.ctx = hb_create(device, stream)
+        self.n_edges = 0
+        self.grid = (0, 0)
+
+    def close(self):
+        if self.ctx is not None:
+            hb_destroy(self.ctx)
+            self.ctx = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, grid_w, grid_h, radii, **kw):
+        p, keep = make_params(grid_w, grid_h, radii, **kw)
+        hb_set_params(self.ctx, p)
+        del keep
+        self.grid = (grid_w, grid_h)
+
+    def set_graph(self, node_xy, src, dst, weight=None):
+        hb_set_graph(self.ctx, node_xy, src, dst, weight)
+        self.n_edges = int(len(src))
+
+    def set_groups(self, group, M):
+        hb_set_groups(self.ctx, group, M)
+
+    def set_workload(self, w, **kw):
+        """Parameters, graph and groups of a ``workloads.Workload``."""
+        self.set_params(w.grid_w, w.grid_h, w.radii, delta=w.delta, passes=w.passes, lam=w.lam,
+                        bbox=w.bbox, **kw)
+        self.set_graph(w.node_xy, w.src, w.dst, w.weight)
+        self.set_groups(w.group, w.M)
+
+    def run(self, n_iters, flags=0):
+        hb_run(self.ctx, n_iters, flags)
+
+    def sync(self):
+        hb_sync(self.ctx)
+
+    def points(self, which=HB_POINTS_STATE, device=None):
+        return hb_get_points(self.ctx, which, self.n_edges, device)
+
+    def set_points(self, offsets, xy):
+        hb_set_points(self.ctx, offsets, xy)
+
+    def map(self, kind, group, pass_=0):
+        return hb_get_map(self.ctx, kind, group, self.grid[0], self.grid[1], pass_)
+
+    def decisions(self):
+        return hb_get_decisions(self.ctx)
+
+    def iter_counts(self, n):
+        return hb_get_iter_counts(self.ctx, n)
+
+    def ink(self):
+        return hb_get_ink(self.ctx)
+
+    @property
+    def iteration(self):
+        return hb_get_iteration(self.ctx)
+
+    @iteration.setter
+    def iteration(self, it):
+        hb_set_iteration(self.ctx, it)

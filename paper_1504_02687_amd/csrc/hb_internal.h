@@ -1,0 +1,91 @@
+// Internal declarations of the HIP bundling library: the per-graph launch descriptor
+// shared by every kernel, status bits, and the kernel launchers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/hb.h"
+
+namespace hb {
+
+// Device status bits (a single int32 per context, read by every kernel at entry).
+enum : int32_t {
+    ST_POINT_OVERFLOW = 1,   // the next sample set does not fit the point buffers
+    ST_HIST_OVERFLOW = 2,    // counts could exceed int32 / int64 box sums could overflow
+    ST_STOP = ST_POINT_OVERFLOW | ST_HIST_OVERFLOW,
+};
+
+constexpr int kBlock = 256;            // threads per block of every kernel
+constexpr int kWavesPerBlock = kBlock / 64;
+constexpr int kScanTile = 1024;        // edges per scan tile (4 per thread)
+constexpr int kColSeg = 128;           // rows per thread in the column box pass
+
+// One graph of one iteration. Every kernel takes an array of these (one per graph of a
+// batch) and finds its graph from blockIdx via the blk_* prefixes, so a single graph is
+// a batch of one.
+struct GDesc {
+    // first block of this graph in each launch shape
+    int64_t blk_edge;    // one wave per edge, kWavesPerBlock edges per block
+    int64_t blk_scan;    // one block per scan tile
+    int64_t blk_row;     // one block per map row (B * H rows)
+    int64_t blk_col;     // one thread per (group, row segment, column)
+    int64_t blk_px;      // one thread per pixel (W * H)
+    int64_t blk_pxb;     // one thread per layer pixel (B * W * H)
+    int64_t blk_edget;   // one thread per edge
+
+    int64_t n_edges;
+    int64_t cap;         // capacity of the point buffers, in points
+    int32_t B, W, H, P;
+    int32_t r, K, record, wmax;
+    double h, eps, s, delta;
+    double a[HB_MAX_PASSES];    // density weight of each pass
+    double ck[HB_MAX_PASSES];   // (2r+1)^(2k), k = 1..P
+
+    const int32_t *group;
+    const int32_t *weight;      // nullptr: unit weights
+    const float *M;             // B x B, M[l * B + b]
+
+    const float2 *pin;          // polylines read by resampling
+    const int64_t *off_in;      // their offsets
+    float2 *samples;            // sample points written by resampling / read by advection
+    int64_t *off_s;             // sample offsets (also the offsets of the new polylines)
+    float2 *pnew;               // new polylines written by advection + smoothing
+
+    int64_t *counts;            // per edge: sample count of the next resampling
+    double *lens;               // per edge: length of the polyline the counts come from
+    int64_t *tsum;              // per scan tile partial sums
+    int64_t *total;             // sample count of this iteration (device scalar)
+
+    int32_t *hist;              // [B][H][W]
+    int64_t *box;               // [P][B][H][W]
+    int64_t *tmp;               // [B][H][W] row-pass output
+    float *rho;                 // [B][H][W]
+    float2 *grad;               // [B][H][W]
+    int8_t *jacc;               // [cap] accepted halving per sample (record != 0)
+    int32_t *status;
+};
+
+// Launch-shape block counts of one graph (host side).
+struct Shape {
+    int64_t edge, scan, row, col, px, pxb, edget;
+};
+Shape shape_of(int64_t n_edges, int32_t B, int32_t W, int32_t H);
+
+// Launchers (all asynchronous on `st`). desc points to device memory holding ng
+// descriptors; tot is the sum of the per-graph shapes.
+hipError_t launch_init_state(const GDesc *desc, int ng, const Shape &tot, const float2 *nodes,
+                             const int32_t *src, const int32_t *dst, double x0, double y0,
+                             double x1, double y1, hipStream_t st);
+hipError_t launch_lengths(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
+hipError_t launch_scan(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
+hipError_t launch_resample_splat(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
+hipError_t launch_splat_given(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
+hipError_t launch_clear_hist(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
+hipError_t launch_box_pass(const GDesc *desc, int ng, const Shape &tot, int max_w, int pass,
+                           hipStream_t st);
+hipError_t launch_density_grad(const GDesc *desc, int ng, const Shape &tot, int bmax,
+                               hipStream_t st);
+hipError_t launch_advect_smooth(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
+
+}  // namespace hb

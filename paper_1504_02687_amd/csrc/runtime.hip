@@ -1,0 +1,944 @@
+// Host runtime of the bundling library: contexts, parameter validation, device buffers,
+// the per-iteration launch schedule, automatic growth of the point buffers, and the C ABI
+// declared in include/hb.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "hb_internal.h"
+
+using hb::GDesc;
+using hb::Shape;
+
+#define HB_API extern "C" __attribute__((visibility("default")))
+
+static thread_local std::string g_thread_err;
+
+struct hb_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool sticky = false;
+    std::string err;
+
+    // parameters
+    hb_params P{};
+    std::vector<int32_t> radii;
+    std::vector<float> passw;
+    bool have_params = false;
+
+    // graph and groups
+    int64_t E = 0;
+    int32_t wmax = 1;
+    bool have_graph = false;
+    int32_t B = 0;
+    bool have_groups = false;
+    int32_t *d_group = nullptr, *d_weight = nullptr;
+    float *d_M = nullptr;
+
+    // points: state = (pts[ps], off[os]); last samples = (pts[ss], off[so])
+    float2 *pts[2] = {nullptr, nullptr};
+    int64_t *off[2] = {nullptr, nullptr};
+    int64_t cap = 0;
+    int ps = 0, os = 0, ss = 0, so = 0;
+    int64_t n_state = 0, n_samples = 0;
+    bool have_samples = false;
+
+    int64_t *d_counts = nullptr, *d_tsum = nullptr, *d_totals = nullptr;
+    double *d_lens = nullptr;
+    int32_t *d_status = nullptr;
+    int totals_cap = 0;
+
+    // maps of the last iteration
+    int32_t *d_hist = nullptr;
+    int64_t *d_box = nullptr, *d_tmp = nullptr;
+    float *d_rho = nullptr;
+    float2 *d_grad = nullptr;
+    int32_t map_B = 0, map_W = 0, map_H = 0, map_P = 0;
+    bool have_maps = false;
+
+    int8_t *d_jacc = nullptr;
+    int64_t jacc_cap = 0;
+    bool have_jacc = false;
+
+    // descriptor table: pinned staging + device copy
+    GDesc *h_desc = nullptr, *d_desc = nullptr;
+    size_t desc_cap = 0;
+    hipEvent_t desc_done = nullptr;
+
+    int32_t iter = 0;
+    std::vector<int64_t> last_counts;
+
+    // pending asynchronous run
+    bool pending = false;
+    int32_t pend_start = 0, pend_T = 0;
+    uint32_t pend_flags = 0;
+    std::vector<int> pend_ps, pend_os;
+};
+
+// ------------------------------------------------------------------ errors
+
+static hb_status fail(hb_ctx *c, hb_status st, const std::string &msg) {
+    if (c) c->err = msg; else g_thread_err = msg;
+    return st;
+}
+
+static hb_status fail_dev(hb_ctx *c, hipError_t e, const char *what) {
+    c->sticky = true;
+    char buf[512];
+    snprintf(buf, sizeof buf, "HIP error %d (%s) in %s", (int)e, hipGetErrorString(e), what);
+    c->err = buf;
+    return HB_EDEVICE;
+}
+
+#define HIPCHK(c, expr)                                   \
+    do {                                                  \
+        hipError_t e_ = (expr);                           \
+        if (e_ != hipSuccess) return fail_dev(c, e_, #expr); \
+    } while (0)
+
+#define CHKST(expr)                       \
+    do {                                  \
+        hb_status s_ = (expr);            \
+        if (s_ != HB_OK) return s_;       \
+    } while (0)
+
+// Makes ctx's device current for the duration of an API call.
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        int cur = -1;
+        if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+    }
+};
+
+#define ENTER(c)                                                                  \
+    if (!(c)) return fail(nullptr, HB_EINVAL, "null context");                    \
+    if ((c)->sticky) return fail(c, HB_EDEVICE, "context has a sticky HIP error: " + (c)->err); \
+    DeviceGuard guard_(c->device);                                                \
+    if (!guard_.ok) return fail(c, HB_EDEVICE, "hipSetDevice failed");
+
+// ------------------------------------------------------------------ allocation
+
+template <typename T>
+static hb_status dalloc(hb_ctx *c, T **p, size_t count, const char *what) {
+    if (*p) {
+        (void)hipFree(*p);
+        *p = nullptr;
+    }
+    if (count == 0) count = 1;
+    if (getenv("HB_TEST_FAIL_ALLOC")) return fail(c, HB_ENOMEM, std::string("simulated allocation failure: ") + what);
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        char buf[256];
+        snprintf(buf, sizeof buf, "hipMalloc of %zu bytes for %s failed", count * sizeof(T), what);
+        return fail(c, HB_ENOMEM, buf);
+    }
+    return HB_OK;
+}
+
+template <typename T>
+static void dfree(T **p) {
+    if (*p) (void)hipFree(*p);
+    *p = nullptr;
+}
+
+// ------------------------------------------------------------------ parameters
+
+static double sigma_of(int r, int passes) {
+    return std::sqrt((double)passes * (double)r * (double)(r + 1) / 3.0);
+}
+
+HB_API void hb_default_params(hb_params *p, int32_t grid_w, int32_t grid_h) {
+    if (!p) return;
+    static thread_local int32_t r_default[1];
+    memset(p, 0, sizeof *p);
+    p->struct_size = sizeof(hb_params);
+    p->grid_w = grid_w;
+    p->grid_h = grid_h;
+    p->bbox[0] = 0.0f;
+    p->bbox[1] = 0.0f;
+    p->bbox[2] = 1.0f;
+    p->bbox[3] = 1.0f;
+    p->delta_px = 1.0f;
+    p->box_passes = 3;
+    r_default[0] = std::max(1, std::min(grid_w, grid_h) / 32);
+    p->n_radii = 1;
+    p->radius_per_iter = r_default;
+    p->h_max_px = 0.0f;
+    p->lambda = 0.9f;
+    p->eps = 1e-6f;
+    p->max_halvings = 8;
+    p->smooth_weight = 0.5f;
+    p->smooth_passes = 1;
+    p->pass_weights = nullptr;
+    p->capacity_factor = 2.0f;
+}
+
+static hb_status validate(hb_ctx *c, const hb_params *p) {
+    if (!p) return fail(c, HB_EINVAL, "params is NULL");
+    if (p->struct_size != sizeof(hb_params))
+        return fail(c, HB_EINVAL, "params.struct_size does not match sizeof(hb_params)");
+    if (p->grid_w < 2 || p->grid_h < 2 || p->grid_w > HB_MAX_GRID || p->grid_h > HB_MAX_GRID)
+        return fail(c, HB_EINVAL, "grid size out of range [2, 8192]");
+    for (int i = 0; i < 4; ++i)
+        if (!std::isfinite(p->bbox[i])) return fail(c, HB_EINVAL, "bbox is not finite");
+    if (!(p->bbox[2] > p->bbox[0]) || !(p->bbox[3] > p->bbox[1]))
+        return fail(c, HB_EINVAL, "bbox must have x1 > x0 and y1 > y0");
+    if (!(p->delta_px > 0.0f) || !std::isfinite(p->delta_px))
+        return fail(c, HB_EINVAL, "delta_px must be positive");
+    if (p->box_passes < 1 || p->box_passes > HB_MAX_PASSES)
+        return fail(c, HB_EINVAL, "box_passes out of range [1, 8]");
+    if (p->n_radii < 1 || !p->radius_per_iter)
+        return fail(c, HB_EINVAL, "radius_per_iter needs at least one value");
+    const int side = std::min(p->grid_w, p->grid_h);
+    for (int i = 0; i < p->n_radii; ++i) {
+        int r = p->radius_per_iter[i];
+        if (r < 0 || 2 * r + 1 > side)
+            return fail(c, HB_EINVAL, "box radius must satisfy 0 <= r and 2r+1 <= min(W, H)");
+    }
+    if (!std::isfinite(p->h_max_px)) return fail(c, HB_EINVAL, "h_max_px is not finite");
+    if (!(p->lambda > 0.0f) || p->lambda > 1.0f) return fail(c, HB_EINVAL, "lambda must be in (0, 1]");
+    if (!(p->eps > 0.0f) || !std::isfinite(p->eps)) return fail(c, HB_EINVAL, "eps must be positive");
+    if (p->max_halvings < 0 || p->max_halvings > HB_MAX_HALVINGS)
+        return fail(c, HB_EINVAL, "max_halvings out of range [0, 30]");
+    if (!(p->smooth_weight >= 0.0f) || p->smooth_weight > 1.0f)
+        return fail(c, HB_EINVAL, "smooth_weight must be in [0, 1]");
+    if (p->smooth_passes != 1) return fail(c, HB_EINVAL, "smooth_passes must be 1");
+    if (p->pass_weights)
+        for (int k = 0; k < p->box_passes; ++k)
+            if (!std::isfinite(p->pass_weights[k])) return fail(c, HB_EINVAL, "pass_weights not finite");
+    if (!(p->capacity_factor == 0.0f || (p->capacity_factor >= 1.1f && p->capacity_factor <= 64.0f)))
+        return fail(c, HB_EINVAL, "capacity_factor must be 0 (default) or in [1.1, 64]");
+    return HB_OK;
+}
+
+HB_API hb_status hb_validate_params(const hb_params *p) { return validate(nullptr, p); }
+
+static int radius_at(const hb_ctx *c, int it) {
+    return c->radii[std::min<size_t>((size_t)it, c->radii.size() - 1)];
+}
+
+static double hmax_of(const hb_ctx *c) {
+    if (c->P.h_max_px > 0.0f) return (double)c->P.h_max_px;
+    return 2.0 * sigma_of(radius_at(c, 0), c->P.box_passes);
+}
+
+static double bandwidth_at(const hb_ctx *c, int it) {
+    double h = hmax_of(c);
+    for (int i = 0; i < it; ++i) h *= (double)c->P.lambda;
+    return h;
+}
+
+// ------------------------------------------------------------------ buffers
+
+static hb_status ensure_totals(hb_ctx *c, int n) {
+    if (n <= c->totals_cap) return HB_OK;
+    CHKST(dalloc(c, &c->d_totals, (size_t)n, "iteration totals"));
+    c->totals_cap = n;
+    return HB_OK;
+}
+
+static hb_status ensure_desc(hb_ctx *c, size_t n) {
+    if (n <= c->desc_cap) return HB_OK;
+    if (c->desc_done) HIPCHK(c, hipEventSynchronize(c->desc_done));
+    if (c->h_desc) (void)hipHostFree(c->h_desc);
+    c->h_desc = nullptr;
+    HIPCHK(c, hipHostMalloc((void **)&c->h_desc, n * sizeof(GDesc), hipHostMallocDefault));
+    CHKST(dalloc(c, &c->d_desc, n, "descriptor table"));
+    c->desc_cap = n;
+    return HB_OK;
+}
+
+// Grow both point buffers to hold at least `need` points, keeping the state and samples.
+static hb_status ensure_capacity(hb_ctx *c, int64_t need) {
+    if (need <= c->cap) return HB_OK;
+    int64_t ncap = std::max<int64_t>(need, c->cap + c->cap / 2);
+    ncap = std::max<int64_t>(ncap, 1024);
+    float2 *np[2] = {nullptr, nullptr};
+    for (int i = 0; i < 2; ++i) {
+        hb_status s = dalloc(c, &np[i], (size_t)ncap, "point buffer");
+        if (s != HB_OK) {
+            dfree(&np[0]);
+            dfree(&np[1]);
+            return s;
+        }
+    }
+    if (c->pts[c->ps] && c->n_state > 0)
+        HIPCHK(c, hipMemcpyAsync(np[c->ps], c->pts[c->ps], sizeof(float2) * c->n_state,
+                                 hipMemcpyDeviceToDevice, c->stream));
+    if (c->have_samples && c->ss != c->ps && c->n_samples > 0)
+        HIPCHK(c, hipMemcpyAsync(np[c->ss], c->pts[c->ss], sizeof(float2) * c->n_samples,
+                                 hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int i = 0; i < 2; ++i) {
+        dfree(&c->pts[i]);
+        c->pts[i] = np[i];
+    }
+    if (c->d_jacc) {
+        dfree(&c->d_jacc);
+        c->jacc_cap = 0;
+        c->have_jacc = false;
+    }
+    c->cap = ncap;
+    return HB_OK;
+}
+
+static hb_status ensure_maps(hb_ctx *c) {
+    const int B = c->B, W = c->P.grid_w, H = c->P.grid_h, P = c->P.box_passes;
+    if (c->d_hist && c->map_B == B && c->map_W == W && c->map_H == H && c->map_P == P) return HB_OK;
+    const size_t plane = (size_t)B * W * H;
+    c->have_maps = false;
+    CHKST(dalloc(c, &c->d_hist, plane, "histogram"));
+    CHKST(dalloc(c, &c->d_box, plane * P, "box passes"));
+    CHKST(dalloc(c, &c->d_tmp, plane, "row-pass scratch"));
+    CHKST(dalloc(c, &c->d_rho, plane, "density"));
+    CHKST(dalloc(c, &c->d_grad, plane, "gradient"));
+    c->map_B = B;
+    c->map_W = W;
+    c->map_H = H;
+    c->map_P = P;
+    return HB_OK;
+}
+
+// Descriptor with every field that does not change between iterations.
+static GDesc base_desc(const hb_ctx *c) {
+    GDesc d;
+    memset(&d, 0, sizeof d);
+    const Shape s = hb::shape_of(c->E, std::max(1, c->B), c->P.grid_w, c->P.grid_h);
+    (void)s;
+    d.n_edges = c->E;
+    d.cap = c->cap;
+    d.B = std::max(1, c->B);
+    d.W = c->P.grid_w;
+    d.H = c->P.grid_h;
+    d.P = c->P.box_passes;
+    d.K = c->P.max_halvings;
+    d.wmax = c->wmax;
+    d.eps = (double)c->P.eps;
+    d.s = (double)c->P.smooth_weight;
+    d.delta = (double)c->P.delta_px;
+    for (int k = 0; k < d.P; ++k)
+        d.a[k] = c->passw.empty() ? (k == d.P - 1 ? 1.0 : 0.0) : (double)c->passw[k];
+    d.group = c->d_group;
+    d.weight = c->d_weight;
+    d.M = c->d_M;
+    d.counts = c->d_counts;
+    d.lens = c->d_lens;
+    d.tsum = c->d_tsum;
+    d.total = c->d_totals;
+    d.hist = c->d_hist;
+    d.box = c->d_box;
+    d.tmp = c->d_tmp;
+    d.rho = c->d_rho;
+    d.grad = c->d_grad;
+    d.jacc = c->d_jacc;
+    d.status = c->d_status;
+    return d;
+}
+
+static void set_iter_scalars(const hb_ctx *c, GDesc &d, int it) {
+    d.r = radius_at(c, it);
+    d.h = bandwidth_at(c, it);
+    const double w = (double)(2 * d.r + 1) * (double)(2 * d.r + 1);
+    double ck = 1.0;
+    for (int k = 0; k < d.P; ++k) {
+        ck *= w;
+        d.ck[k] = ck;
+    }
+}
+
+// Upload n descriptors from the pinned staging table.
+static hb_status upload_desc(hb_ctx *c, size_t n) {
+    HIPCHK(c, hipMemcpyAsync(c->d_desc, c->h_desc, n * sizeof(GDesc), hipMemcpyHostToDevice,
+                             c->stream));
+    HIPCHK(c, hipEventRecord(c->desc_done, c->stream));
+    return HB_OK;
+}
+
+static hb_status wait_desc(hb_ctx *c) {
+    if (c->desc_done) HIPCHK(c, hipEventSynchronize(c->desc_done));
+    return HB_OK;
+}
+
+static hb_status read_scalar(hb_ctx *c, const int64_t *dptr, int64_t *out) {
+    HIPCHK(c, hipMemcpyAsync(out, dptr, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return HB_OK;
+}
+
+// ------------------------------------------------------------------ lifecycle
+
+HB_API hb_status hb_create(hb_ctx **out, int32_t device, void *hip_stream) {
+    if (!out) return fail(nullptr, HB_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+        return fail(nullptr, HB_EDEVICE, "no HIP device");
+    if (device < 0 || device >= ndev) return fail(nullptr, HB_EINVAL, "device index out of range");
+    hb_ctx *c = new hb_ctx();
+    c->device = device;
+    DeviceGuard guard(device);
+    if (!guard.ok) {
+        delete c;
+        return fail(nullptr, HB_EDEVICE, "hipSetDevice failed");
+    }
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return fail(nullptr, HB_EDEVICE, "hipStreamCreate failed");
+        }
+        c->own_stream = true;
+    }
+    if (hipEventCreateWithFlags(&c->desc_done, hipEventDisableTiming) != hipSuccess ||
+        dalloc(c, &c->d_status, 1, "status") != HB_OK) {
+        std::string m = c->err.empty() ? "event creation failed" : c->err;
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        if (c->desc_done) (void)hipEventDestroy(c->desc_done);
+        delete c;
+        return fail(nullptr, HB_ENOMEM, m);
+    }
+    if (hipMemsetAsync(c->d_status, 0, sizeof(int32_t), c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
+        dfree(&c->d_status);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        (void)hipEventDestroy(c->desc_done);
+        delete c;
+        return fail(nullptr, HB_EDEVICE, "status initialisation failed");
+    }
+    *out = c;
+    return HB_OK;
+}
+
+HB_API void hb_destroy(hb_ctx *c) {
+    if (!c) return;
+    {
+        DeviceGuard guard(c->device);
+        (void)hipStreamSynchronize(c->stream);
+        dfree(&c->d_group);
+        dfree(&c->d_weight);
+        dfree(&c->d_M);
+        for (int i = 0; i < 2; ++i) {
+            dfree(&c->pts[i]);
+            dfree(&c->off[i]);
+        }
+        dfree(&c->d_counts);
+        dfree(&c->d_tsum);
+        dfree(&c->d_totals);
+        dfree(&c->d_lens);
+        dfree(&c->d_status);
+        dfree(&c->d_hist);
+        dfree(&c->d_box);
+        dfree(&c->d_tmp);
+        dfree(&c->d_rho);
+        dfree(&c->d_grad);
+        dfree(&c->d_jacc);
+        dfree(&c->d_desc);
+        if (c->h_desc) (void)hipHostFree(c->h_desc);
+        if (c->desc_done) (void)hipEventDestroy(c->desc_done);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    }
+    delete c;
+}
+
+HB_API const char *hb_last_error(const hb_ctx *c) { return c ? c->err.c_str() : g_thread_err.c_str(); }
+
+HB_API const char *hb_version(void) { return "hb 0.1 gfx950"; }
+
+static hb_status finish_pending(hb_ctx *c);
+
+HB_API hb_status hb_set_params(hb_ctx *c, const hb_params *p) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    CHKST(validate(c, p));
+    if (c->have_graph && (p->grid_w != c->P.grid_w || p->grid_h != c->P.grid_h))
+        c->have_samples = false;
+    c->P = *p;
+    c->radii.assign(p->radius_per_iter, p->radius_per_iter + p->n_radii);
+    c->passw.clear();
+    if (p->pass_weights) c->passw.assign(p->pass_weights, p->pass_weights + p->box_passes);
+    c->P.radius_per_iter = nullptr;
+    c->P.pass_weights = nullptr;
+    if (c->P.capacity_factor == 0.0f) c->P.capacity_factor = 2.0f;
+    c->have_params = true;
+    c->have_maps = false;
+    return HB_OK;
+}
+
+// Copy `count` elements of a caller array (host, or device with HB_DEVICE_PTRS) to host.
+template <typename T>
+static hb_status to_host(hb_ctx *c, std::vector<T> &dst, const T *src, size_t count, uint32_t flags) {
+    dst.resize(count);
+    if (count == 0) return HB_OK;
+    if (flags & HB_DEVICE_PTRS) {
+        HIPCHK(c, hipMemcpyAsync(dst.data(), src, count * sizeof(T), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    } else {
+        memcpy(dst.data(), src, count * sizeof(T));
+    }
+    return HB_OK;
+}
+
+template <typename T>
+static hb_status upload(hb_ctx *c, T *dst, const std::vector<T> &src) {
+    if (src.empty()) return HB_OK;
+    HIPCHK(c, hipMemcpyAsync(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return HB_OK;
+}
+
+// Lay out the descriptor of a setup kernel on the state (pin/off_in) in slot 0.
+static hb_status setup_scan_total(hb_ctx *c, int64_t *total_out) {
+    // Scan the counts of the current state into off[1 - os] to learn the next sample count.
+    CHKST(ensure_desc(c, 1));
+    CHKST(ensure_totals(c, 1));
+    CHKST(wait_desc(c));
+    GDesc d = base_desc(c);
+    set_iter_scalars(c, d, c->iter);
+    d.cap = INT64_MAX;
+    d.wmax = 0;   // no range checks: this scan only sizes the buffers
+    d.off_s = c->off[1 - c->os];
+    d.total = c->d_totals;
+    d.r = 0;
+    c->h_desc[0] = d;
+    CHKST(upload_desc(c, 1));
+    const Shape s = hb::shape_of(c->E, d.B, d.W, d.H);
+    HIPCHK(c, hb::launch_scan(c->d_desc, 1, s, c->stream));
+    CHKST(read_scalar(c, c->d_totals, total_out));
+    return HB_OK;
+}
+
+HB_API hb_status hb_set_graph(hb_ctx *c, int32_t n_nodes, const float *node_xy, int64_t n_edges,
+                              const int32_t *src, const int32_t *dst, const int32_t *weight,
+                              uint32_t flags) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    if (!c->have_params) return fail(c, HB_ESTATE, "hb_set_params must come before hb_set_graph");
+    if (n_edges < 0 || n_nodes < 0) return fail(c, HB_EINVAL, "negative size");
+    if (n_edges > ((int64_t)1 << 31)) return fail(c, HB_EINVAL, "too many edges");
+    if (n_edges > 0 && (n_nodes < 1 || !node_xy || !src || !dst))
+        return fail(c, HB_EINVAL, "nodes, src and dst are required");
+    std::vector<float> hx;
+    std::vector<int32_t> hs, ht, hw;
+    CHKST(to_host(c, hx, node_xy, (size_t)n_nodes * 2, flags));
+    CHKST(to_host(c, hs, src, (size_t)n_edges, flags));
+    CHKST(to_host(c, ht, dst, (size_t)n_edges, flags));
+    if (weight) CHKST(to_host(c, hw, weight, (size_t)n_edges, flags));
+    for (float v : hx)
+        if (!std::isfinite(v)) return fail(c, HB_EINVAL, "node coordinates must be finite");
+    for (int64_t e = 0; e < n_edges; ++e)
+        if (hs[e] < 0 || hs[e] >= n_nodes || ht[e] < 0 || ht[e] >= n_nodes)
+            return fail(c, HB_EINVAL, "edge end point out of range");
+    int32_t wmax = 1;
+    for (int32_t w : hw) {
+        if (w < 1) return fail(c, HB_EINVAL, "edge weights must be >= 1");
+        wmax = std::max(wmax, w);
+    }
+    const int64_t E = n_edges;
+    c->have_graph = false;
+    c->have_samples = false;
+    c->have_jacc = false;
+    if (E != c->E) c->have_groups = false;
+    c->E = E;
+    c->wmax = wmax;
+    CHKST(dalloc(c, &c->d_weight, hw.empty() ? 1 : hw.size(), "weights"));
+    if (hw.empty()) dfree(&c->d_weight);
+    else CHKST(upload(c, c->d_weight, hw));
+    if (!c->have_groups) {
+        CHKST(dalloc(c, &c->d_group, (size_t)E, "groups"));
+        std::vector<int32_t> zero((size_t)E, 0);
+        CHKST(upload(c, c->d_group, zero));
+    }
+    for (int i = 0; i < 2; ++i) CHKST(dalloc(c, &c->off[i], (size_t)E + 1, "offsets"));
+    CHKST(dalloc(c, &c->d_counts, (size_t)E, "counts"));
+    CHKST(dalloc(c, &c->d_lens, (size_t)E, "lengths"));
+    CHKST(dalloc(c, &c->d_tsum, (size_t)(E / hb::kScanTile + 1), "scan tiles"));
+    for (int i = 0; i < 2; ++i) dfree(&c->pts[i]);
+    c->cap = 0;
+    c->n_state = 0;
+    c->n_samples = 0;
+    c->ps = c->os = 0;
+    CHKST(ensure_capacity(c, std::max<int64_t>(2 * E, 1024)));
+
+    // straight two-point polylines from the nodes
+    float2 *d_nodes = nullptr;
+    int32_t *d_src = nullptr, *d_dst = nullptr;
+    hb_status st = dalloc(c, &d_nodes, (size_t)std::max(1, n_nodes), "nodes");
+    if (st == HB_OK) st = dalloc(c, &d_src, (size_t)E, "src");
+    if (st == HB_OK) st = dalloc(c, &d_dst, (size_t)E, "dst");
+    if (st == HB_OK && n_nodes > 0) {
+        if (hipMemcpyAsync(d_nodes, hx.data(), hx.size() * sizeof(float), hipMemcpyHostToDevice, c->stream) != hipSuccess)
+            st = fail_dev(c, hipGetLastError(), "node upload");
+    }
+    if (st == HB_OK) st = upload(c, d_src, hs);
+    if (st == HB_OK) st = upload(c, d_dst, ht);
+    if (st == HB_OK) st = ensure_desc(c, 1);
+    if (st == HB_OK) st = wait_desc(c);
+    if (st == HB_OK) {
+        GDesc d = base_desc(c);
+        set_iter_scalars(c, d, 0);
+        d.pnew = c->pts[0];
+        d.off_s = c->off[0];
+        c->h_desc[0] = d;
+        st = upload_desc(c, 1);
+        if (st == HB_OK) {
+            const Shape s = hb::shape_of(E, d.B, d.W, d.H);
+            hipError_t e = hb::launch_init_state(c->d_desc, 1, s, d_nodes, d_src, d_dst,
+                                                 c->P.bbox[0], c->P.bbox[1], c->P.bbox[2],
+                                                 c->P.bbox[3], c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) st = fail_dev(c, e, "initial polylines");
+        }
+    }
+    dfree(&d_nodes);
+    dfree(&d_src);
+    dfree(&d_dst);
+    if (st != HB_OK) return st;
+    c->ps = 0;
+    c->os = 0;
+    c->n_state = 2 * E;
+    c->iter = 0;
+    int64_t n0 = 0;
+    CHKST(setup_scan_total(c, &n0));
+    CHKST(ensure_capacity(c, (int64_t)std::ceil((double)n0 * c->P.capacity_factor) + 64));
+    c->have_graph = true;
+    return HB_OK;
+}
+
+HB_API hb_status hb_set_groups(hb_ctx *c, int32_t n_groups, const int32_t *group, const float *M,
+                               uint32_t flags) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    if (!c->have_graph) return fail(c, HB_ESTATE, "hb_set_graph must come before hb_set_groups");
+    if (n_groups < 1 || n_groups > HB_MAX_GROUPS) return fail(c, HB_EINVAL, "n_groups out of range [1, 64]");
+    if (!M || (c->E > 0 && !group)) return fail(c, HB_EINVAL, "group and M are required");
+    std::vector<int32_t> hg;
+    std::vector<float> hm;
+    CHKST(to_host(c, hg, group, (size_t)c->E, flags));
+    CHKST(to_host(c, hm, M, (size_t)n_groups * n_groups, flags));
+    for (int32_t b : hg)
+        if (b < 0 || b >= n_groups) return fail(c, HB_EINVAL, "group index out of range [0, B)");
+    for (float v : hm)
+        if (!std::isfinite(v)) return fail(c, HB_EINVAL, "interaction matrix must be finite");
+    CHKST(dalloc(c, &c->d_group, std::max<size_t>(1, hg.size()), "groups"));
+    CHKST(upload(c, c->d_group, hg));
+    CHKST(dalloc(c, &c->d_M, hm.size(), "interaction matrix"));
+    CHKST(upload(c, c->d_M, hm));
+    c->B = n_groups;
+    c->have_groups = true;
+    c->have_maps = false;
+    return HB_OK;
+}
+
+// ------------------------------------------------------------------ the iteration loop
+
+static hb_status enqueue_run(hb_ctx *c, int T, uint32_t flags);
+
+HB_API hb_status hb_run(hb_ctx *c, int32_t n_iters, uint32_t flags) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    if (!c->have_params || !c->have_graph || !c->have_groups)
+        return fail(c, HB_ESTATE, "hb_run needs parameters, graph and groups");
+    if (n_iters < 0) return fail(c, HB_EINVAL, "n_iters must be >= 0");
+    if (flags & ~(uint32_t)(HB_RUN_SAMPLES_GIVEN | HB_RUN_RECORD_DECISIONS | HB_RUN_ASYNC))
+        return fail(c, HB_EINVAL, "unknown run flags");
+    c->last_counts.clear();
+    if (n_iters == 0) return HB_OK;
+    if ((flags & HB_RUN_SAMPLES_GIVEN) &&
+        (double)c->n_state * (double)c->wmax >= 2147483647.0)
+        return fail(c, HB_EOVERFLOW, "histogram counts could exceed int32");
+    CHKST(enqueue_run(c, n_iters, flags));
+    if (flags & HB_RUN_ASYNC) return HB_OK;
+    return finish_pending(c);
+}
+
+static hb_status enqueue_run(hb_ctx *c, int T, uint32_t flags) {
+    CHKST(ensure_maps(c));
+    CHKST(ensure_totals(c, T));
+    const bool record = (flags & HB_RUN_RECORD_DECISIONS) != 0;
+    if (record && c->jacc_cap < c->cap) {
+        CHKST(dalloc(c, &c->d_jacc, (size_t)c->cap, "decisions"));
+        c->jacc_cap = c->cap;
+    }
+    CHKST(ensure_desc(c, (size_t)T));
+    CHKST(wait_desc(c));
+    HIPCHK(c, hipMemsetAsync(c->d_totals, 0xff, sizeof(int64_t) * T, c->stream));
+
+    c->pend_ps.assign(T, 0);
+    c->pend_os.assign(T, 0);
+    int ps = c->ps, os = c->os;
+    int last_ss = 0, last_so = 0;
+    for (int it = 0; it < T; ++it) {
+        c->pend_ps[it] = ps;
+        c->pend_os[it] = os;
+        const bool given = it == 0 && (flags & HB_RUN_SAMPLES_GIVEN);
+        last_ss = given ? ps : 1 - ps;
+        last_so = given ? os : 1 - os;
+        GDesc d = base_desc(c);
+        set_iter_scalars(c, d, c->iter + it);
+        d.record = record && it == T - 1;
+        d.jacc = c->d_jacc;
+        d.total = c->d_totals + it;
+        if (given) {
+            d.samples = c->pts[ps];
+            d.off_s = c->off[os];
+            d.pnew = c->pts[1 - ps];
+            ps = 1 - ps;
+        } else {
+            d.pin = c->pts[ps];
+            d.off_in = c->off[os];
+            d.samples = c->pts[1 - ps];
+            d.off_s = c->off[1 - os];
+            d.pnew = c->pts[ps];
+            os = 1 - os;
+        }
+        c->h_desc[it] = d;
+    }
+    CHKST(upload_desc(c, (size_t)T));
+
+    const int W = c->P.grid_w, H = c->P.grid_h, B = c->B;
+    const Shape s = hb::shape_of(c->E, B, W, H);
+    for (int it = 0; it < T; ++it) {
+        const GDesc *dd = c->d_desc + it;
+        const bool given = it == 0 && (flags & HB_RUN_SAMPLES_GIVEN);
+        if (!given) HIPCHK(c, hb::launch_scan(dd, 1, s, c->stream));
+        HIPCHK(c, hb::launch_clear_hist(dd, 1, s, c->stream));
+        if (given) HIPCHK(c, hb::launch_splat_given(dd, 1, s, c->stream));
+        else HIPCHK(c, hb::launch_resample_splat(dd, 1, s, c->stream));
+        for (int k = 0; k < c->P.box_passes; ++k) HIPCHK(c, hb::launch_box_pass(dd, 1, s, W, k, c->stream));
+        HIPCHK(c, hb::launch_density_grad(dd, 1, s, B, c->stream));
+        HIPCHK(c, hb::launch_advect_smooth(dd, 1, s, c->stream));
+    }
+    c->pending = true;
+    c->pend_start = c->iter;
+    c->pend_T = T;
+    c->pend_flags = flags;
+    // bookkeeping as if the run completes; finish_pending corrects it on overflow
+    c->ss = last_ss;
+    c->so = last_so;
+    c->ps = ps;
+    c->os = os;
+    c->iter += T;
+    return HB_OK;
+}
+
+// Wait for an enqueued run; on a point-buffer overflow grow the buffers and run the
+// remaining iterations again from the last complete state.
+static hb_status finish_pending(hb_ctx *c) {
+    while (c->pending) {
+        c->pending = false;
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        int32_t status = 0;
+        HIPCHK(c, hipMemcpy(&status, c->d_status, sizeof status, hipMemcpyDeviceToHost));
+        const int T = c->pend_T;
+        std::vector<int64_t> tot((size_t)T);
+        HIPCHK(c, hipMemcpy(tot.data(), c->d_totals, sizeof(int64_t) * T, hipMemcpyDeviceToHost));
+        const bool given0 = (c->pend_flags & HB_RUN_SAMPLES_GIVEN) != 0;
+        if (given0) tot[0] = c->n_state;
+        if (status == 0) {
+            c->last_counts.insert(c->last_counts.end(), tot.begin(), tot.end());
+            c->n_state = tot[T - 1];
+            c->n_samples = tot[T - 1];
+            c->have_samples = true;
+            c->have_maps = true;
+            c->have_jacc = (c->pend_flags & HB_RUN_RECORD_DECISIONS) != 0;
+            return HB_OK;
+        }
+        // first iteration that stopped
+        int f = 0;
+        while (f < T && !(tot[f] < 0 || tot[f] > c->cap)) ++f;
+        if (f >= T) f = T - 1;
+        const int64_t need = tot[f] > 0 ? tot[f] : c->cap;
+        c->last_counts.insert(c->last_counts.end(), tot.begin(), tot.begin() + f);
+        c->ps = c->pend_ps[f];
+        c->os = c->pend_os[f];
+        c->iter = c->pend_start + f;
+        if (f > 0) c->n_state = tot[f - 1];
+        c->have_samples = false;
+        int32_t zero = 0;
+        HIPCHK(c, hipMemcpy(c->d_status, &zero, sizeof zero, hipMemcpyHostToDevice));
+        if (status & hb::ST_HIST_OVERFLOW)
+            return fail(c, HB_EOVERFLOW,
+                        "sample count too large for int32 histograms or int64 box sums");
+        CHKST(ensure_capacity(c, need + need / 4 + 64));
+        uint32_t flags = c->pend_flags;
+        if (f > 0) flags &= ~(uint32_t)HB_RUN_SAMPLES_GIVEN;
+        CHKST(enqueue_run(c, T - f, flags & ~(uint32_t)HB_RUN_ASYNC));
+    }
+    return HB_OK;
+}
+
+HB_API hb_status hb_sync(hb_ctx *c) {
+    ENTER(c);
+    return finish_pending(c);
+}
+
+// ------------------------------------------------------------------ data movement
+
+static hb_status copy_out(hb_ctx *c, void *dst, const void *src, size_t bytes, uint32_t flags) {
+    if (bytes == 0) return HB_OK;
+    HIPCHK(c, hipMemcpyAsync(dst, src, bytes,
+                             (flags & HB_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                             c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return HB_OK;
+}
+
+HB_API hb_status hb_get_num_points(hb_ctx *c, int32_t which, int64_t *n) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    if (!n) return fail(c, HB_EINVAL, "n_points is NULL");
+    if (!c->have_graph) return fail(c, HB_ESTATE, "no graph");
+    if (which == HB_POINTS_STATE) *n = c->n_state;
+    else if (which == HB_POINTS_SAMPLES) {
+        if (!c->have_samples) return fail(c, HB_ESTATE, "no samples: run an iteration first");
+        *n = c->n_samples;
+    } else return fail(c, HB_EINVAL, "unknown point set");
+    return HB_OK;
+}
+
+HB_API hb_status hb_get_points(hb_ctx *c, int32_t which, int64_t *offsets, float *xy,
+                               int64_t cap_points, uint32_t flags) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    if (!c->have_graph) return fail(c, HB_ESTATE, "no graph");
+    int pi, oi;
+    int64_t n;
+    if (which == HB_POINTS_STATE) {
+        pi = c->ps; oi = c->os; n = c->n_state;
+    } else if (which == HB_POINTS_SAMPLES) {
+        if (!c->have_samples) return fail(c, HB_ESTATE, "no samples: run an iteration first");
+        pi = c->ss; oi = c->so; n = c->n_samples;
+    } else return fail(c, HB_EINVAL, "unknown point set");
+    if (cap_points < n) return fail(c, HB_EINVAL, "xy buffer too small");
+    if (!offsets || (n > 0 && !xy)) return fail(c, HB_EINVAL, "offsets and xy are required");
+    CHKST(copy_out(c, offsets, c->off[oi], sizeof(int64_t) * (size_t)(c->E + 1), flags));
+    CHKST(copy_out(c, xy, c->pts[pi], sizeof(float2) * (size_t)n, flags));
+    return HB_OK;
+}
+
+HB_API hb_status hb_set_points(hb_ctx *c, const int64_t *offsets, const float *xy, int64_t n_points,
+                               uint32_t flags) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    if (!c->have_graph) return fail(c, HB_ESTATE, "hb_set_graph must come first");
+    if (!offsets || (n_points > 0 && !xy)) return fail(c, HB_EINVAL, "offsets and xy are required");
+    std::vector<int64_t> ho;
+    CHKST(to_host(c, ho, offsets, (size_t)c->E + 1, flags));
+    if (ho[0] != 0 || ho[c->E] != n_points) return fail(c, HB_EINVAL, "offsets must run from 0 to n_points");
+    for (int64_t e = 0; e < c->E; ++e)
+        if (ho[e + 1] - ho[e] < 2) return fail(c, HB_EINVAL, "every polyline needs at least two points");
+    std::vector<float> hx;
+    CHKST(to_host(c, hx, xy, (size_t)n_points * 2, flags));
+    for (float v : hx)
+        if (!std::isfinite(v)) return fail(c, HB_EINVAL, "point coordinates must be finite");
+    c->have_samples = false;
+    c->have_jacc = false;
+    c->n_state = 0;
+    CHKST(ensure_capacity(c, n_points));
+    c->ps = 0;
+    c->os = 0;
+    CHKST(upload(c, c->off[0], ho));
+    if (n_points > 0)
+        HIPCHK(c, hipMemcpy(c->pts[0], hx.data(), hx.size() * sizeof(float), hipMemcpyHostToDevice));
+    c->n_state = n_points;
+    CHKST(ensure_desc(c, 1));
+    CHKST(wait_desc(c));
+    GDesc d = base_desc(c);
+    set_iter_scalars(c, d, c->iter);
+    d.pin = c->pts[0];
+    d.off_in = c->off[0];
+    c->h_desc[0] = d;
+    CHKST(upload_desc(c, 1));
+    const Shape s = hb::shape_of(c->E, d.B, d.W, d.H);
+    HIPCHK(c, hb::launch_lengths(c->d_desc, 1, s, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return HB_OK;
+}
+
+HB_API hb_status hb_get_map(hb_ctx *c, int32_t kind, int32_t group, int32_t pass, void *out,
+                            int64_t bytes, uint32_t flags) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    if (!c->have_maps) return fail(c, HB_ESTATE, "no maps: run an iteration first");
+    if (!out) return fail(c, HB_EINVAL, "out is NULL");
+    if (group < 0 || group >= c->map_B) return fail(c, HB_EINVAL, "group index out of range");
+    const size_t plane = (size_t)c->map_W * c->map_H;
+    const size_t gofs = (size_t)group * plane;
+    const void *src;
+    size_t need;
+    switch (kind) {
+        case HB_MAP_HIST: src = c->d_hist + gofs; need = plane * sizeof(int32_t); break;
+        case HB_MAP_BOX:
+            if (pass < 1 || pass > c->map_P) return fail(c, HB_EINVAL, "pass out of range [1, P]");
+            src = c->d_box + (size_t)(pass - 1) * c->map_B * plane + gofs;
+            need = plane * sizeof(int64_t);
+            break;
+        case HB_MAP_DENSITY: src = c->d_rho + gofs; need = plane * sizeof(float); break;
+        case HB_MAP_GRAD: src = c->d_grad + gofs; need = plane * sizeof(float2); break;
+        default: return fail(c, HB_EINVAL, "unknown map kind");
+    }
+    if (bytes < (int64_t)need) return fail(c, HB_EINVAL, "output buffer too small");
+    return copy_out(c, out, src, need, flags);
+}
+
+HB_API hb_status hb_get_decisions(hb_ctx *c, int8_t *jacc, int64_t cap_points, uint32_t flags) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    if (!c->have_jacc || !c->have_samples)
+        return fail(c, HB_ESTATE, "no decisions: run with HB_RUN_RECORD_DECISIONS");
+    if (!jacc || cap_points < c->n_samples) return fail(c, HB_EINVAL, "buffer too small");
+    return copy_out(c, jacc, c->d_jacc, (size_t)c->n_samples, flags);
+}
+
+HB_API hb_status hb_get_iter_counts(hb_ctx *c, int64_t *counts, int32_t cap) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    if (!counts || cap < (int32_t)c->last_counts.size()) return fail(c, HB_EINVAL, "buffer too small");
+    std::copy(c->last_counts.begin(), c->last_counts.end(), counts);
+    return HB_OK;
+}
+
+HB_API hb_status hb_get_ink(hb_ctx *c, double *ink) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    if (!ink) return fail(c, HB_EINVAL, "ink is NULL");
+    if (!c->have_graph) return fail(c, HB_ESTATE, "no graph");
+    std::vector<double> L((size_t)c->E);
+    if (c->E > 0) CHKST(copy_out(c, L.data(), c->d_lens, sizeof(double) * (size_t)c->E, 0));
+    double s = 0.0;
+    for (double v : L) s += v;
+    *ink = s;
+    return HB_OK;
+}
+
+HB_API hb_status hb_get_iteration(hb_ctx *c, int32_t *iter) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    if (!iter) return fail(c, HB_EINVAL, "iter is NULL");
+    *iter = c->iter;
+    return HB_OK;
+}
+
+HB_API hb_status hb_set_iteration(hb_ctx *c, int32_t iter) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    if (iter < 0) return fail(c, HB_EINVAL, "iteration must be >= 0");
+    c->iter = iter;
+    return HB_OK;
+}
