@@ -184,6 +184,27 @@ const char *hb_last_error(const hb_ctx *ctx);
 /* Library version string. */
 const char *hb_version(void);
 
+/* Stages of one iteration, for hb_get_stage_times. */
+enum {
+    HB_STAGE_SCAN = 0,            /* sample-count scan -> offsets */
+    HB_STAGE_CLEAR = 1,           /* histogram clear */
+    HB_STAGE_RESAMPLE_SPLAT = 2,  /* resampling + splatting (or splatting given samples) */
+    HB_STAGE_BOX = 3,             /* one box pass (row + column kernels) */
+    HB_STAGE_DENSITY_GRAD = 4,    /* density stack + gradient */
+    HB_STAGE_ADVECT_SMOOTH = 5,   /* advection + Laplacian smoothing + next counts */
+    HB_NUM_STAGES = 6
+};
+
+/* Enable (1) or disable (0) per-stage timing with HIP events on the context's stream.
+ * While enabled, every stage launch of hb_run is bracketed by two events. */
+hb_status hb_set_profiling(hb_ctx *ctx, int32_t enable);
+
+/* Accumulated stage times (milliseconds) and launch counts since profiling was enabled or
+ * last reset; ms and launches are arrays of n_stages (<= HB_NUM_STAGES). reset != 0 clears
+ * the accumulators after reading. */
+hb_status hb_get_stage_times(hb_ctx *ctx, double *ms, int64_t *launches, int32_t n_stages,
+                             int32_t reset);
+
 #ifdef __cplusplus
 }
 #endif

@@ -84,7 +84,12 @@ _SIGS = {
     "hb_set_iteration": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "hb_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "hb_version": (ctypes.c_char_p, []),
+    "hb_set_profiling": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "hb_get_stage_times": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                            ctypes.c_int32, ctypes.c_int32]),
 }
+
+STAGES = ["scan", "clear", "resample_splat", "box", "density_grad", "advect_smooth"]
 
 
 def load():
@@ -275,6 +280,19 @@ def hb_version() -> str:
     return load().hb_version().decode()
 
 
+def hb_set_profiling(ctx, enable: bool) -> None:
+    _check(ctx, load().hb_set_profiling(ctx, 1 if enable else 0))
+
+
+def hb_get_stage_times(ctx, reset: bool = False):
+    """{stage: (total ms, launches)} accumulated while profiling was enabled."""
+    n = len(STAGES)
+    ms = np.zeros(n, np.float64)
+    cnt = np.zeros(n, np.int64)
+    _check(ctx, load().hb_get_stage_times(ctx, ms.ctypes.data, cnt.ctypes.data, n, 1 if reset else 0))
+    return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(STAGES)}
+
+
 # ------------------------------------------------------------------ convenience
 
 def make_params(grid_w: int, grid_h: int, radii: Sequence[int], *, delta: float = 1.0,
@@ -373,6 +391,12 @@ class Bundler:
 
     def ink(self):
         return hb_get_ink(self.ctx)
+
+    def profiling(self, enable=True):
+        hb_set_profiling(self.ctx, enable)
+
+    def stage_times(self, reset=False):
+        return hb_get_stage_times(self.ctx, reset)
 
     @property
     def iteration(self):

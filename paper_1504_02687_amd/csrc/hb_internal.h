@@ -42,6 +42,7 @@ struct GDesc {
     double a[HB_MAX_PASSES];    // density weight of each pass
     double ck[HB_MAX_PASSES];   // (2r+1)^(2k), k = 1..P
 
+    const int32_t *perm;        // visiting order of the edges (nullptr: 0..E-1)
     const int32_t *group;
     const int32_t *weight;      // nullptr: unit weights
     const float *M;             // B x B, M[l * B + b]
@@ -57,7 +58,9 @@ struct GDesc {
     int64_t *tsum;              // per scan tile partial sums
     int64_t *total;             // sample count of this iteration (device scalar)
 
-    int32_t *hist;              // [B][H][W]
+    int32_t *hist;              // [B][H][W] histogram (sum of the per-XCD copies)
+    int32_t *histx;             // [nx][B][H][W] per-XCD copies the splat kernels add into
+    int32_t nx;                 // number of copies (XCDs of the device)
     int64_t *box;               // [P][B][H][W]
     int64_t *tmp;               // [B][H][W] row-pass output
     float *rho;                 // [B][H][W]
@@ -65,6 +68,9 @@ struct GDesc {
     int8_t *jacc;               // [cap] accepted halving per sample (record != 0)
     int32_t *status;
 };
+
+// Work per trip of the point kernels (chunks of 64 segments / 62 points), set at load.
+extern int g_resample_u, g_advect_u;
 
 // Launch-shape block counts of one graph (host side).
 struct Shape {

@@ -67,6 +67,22 @@ __device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t *total) {
     return pre + incl - v;
 }
 
+// Edge handled by wave `wid` of block `blk_local` of a graph. Blocks are dealt to the XCDs
+// round-robin, so block b is mapped to chunk c of the visiting order with consecutive
+// chunks on the same XCD: each XCD walks one contiguous range of the order (edges sorted
+// by group and position), which keeps its share of the density maps small enough for its
+// L2. Returns -1 past the last edge.
+__device__ __forceinline__ int64_t edge_of(const GDesc &d, int64_t blk_local, int wid) {
+    const int64_t nblk = (d.n_edges + kWavesPerBlock - 1) / kWavesPerBlock;
+    const int64_t nx = d.nx;
+    const int64_t x = blk_local % nx, i = blk_local / nx;
+    const int64_t q = nblk / nx, r = nblk % nx;
+    const int64_t c = x * q + (x < r ? x : r) + i;
+    const int64_t idx = c * kWavesPerBlock + wid;
+    if (idx >= d.n_edges) return -1;
+    return d.perm ? (int64_t)d.perm[idx] : idx;
+}
+
 __device__ __forceinline__ int64_t sample_count(double L, double delta) {
     double q = ceil(L / delta);
     if (!(q >= 1.0)) q = 1.0;          // also catches NaN
@@ -181,7 +197,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_top(const GDesc *__restrict__ g
         double wsum = (double)carry * (double)d.wmax;
         double grow = 1.0;
         for (int k = 1; k < d.P; ++k) grow *= (double)(2 * d.r + 1) * (double)(2 * d.r + 1);
-        if (wsum >= 2147483647.0 || wsum * grow >= 9.2e18) st |= ST_HIST_OVERFLOW;
+        // int32 counts: no pixel can reach 2^32 while N w < 2^32, so a pixel that passes 2^31
+        // shows up as a negative count in the first row pass; int64 box sums stay below
+        // N w (2r+1)^(2(P-1)).
+        if (wsum >= 4294967295.0 || wsum * grow >= 9.2e18) st |= ST_HIST_OVERFLOW;
         if (st) atomicOr(d.status, st);
     }
 }
@@ -212,22 +231,35 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const GDesc *__restrict__
 
 // ---------------------------------------------------------------- resample + splat
 
-// One wave per edge. The polyline (pin) is streamed in chunks of 64 segments; lane j of a
-// chunk holds segment j, its FP64 length and the arclength at its start (wave scan). The
-// samples whose arclength s_k = k L / (n-1) falls in the chunk are produced 64 at a time:
-// each lane finds its segment by binary search in LDS and interpolates in FP64. Every
-// sample is stored (coalesced, float2) and splatted into the group's histogram.
+// XCD (accelerator complex die) that runs the calling wave. Histogram updates go to a
+// per-XCD copy of the histogram stack, which spreads the atomics on hot bundle pixels over
+// nx addresses; the first box pass sums the copies.
+__device__ __forceinline__ int xcc_id(int nx) {
+    unsigned v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+    const int x = (int)(v & 0xfu);
+    return x < nx ? x : nx - 1;
+}
+
+// One wave per edge. The polyline (pin) is streamed U chunks of 64 segments at a time;
+// lane j of a chunk holds segment j, its FP64 length and the arclength at its start (wave
+// scans, U independent chains in flight). The samples whose arclength s_k = k L / (n-1)
+// falls in those segments are produced 64 at a time: each lane finds its segment by
+// binary search in LDS and interpolates in FP64. Every sample is stored (coalesced,
+// float2) and splatted into this XCD's copy of its group's histogram.
+template <int U>
 __global__ __launch_bounds__(kBlock) void k_resample_splat(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_edge);
     if (stopped(d)) return;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int64_t e = (blk - d.blk_edge) * kWavesPerBlock + wid;
-    if (e >= d.n_edges) return;
+    const int64_t e = edge_of(d, blk - d.blk_edge, wid);
+    if (e < 0) return;
 
-    __shared__ double sC[kWavesPerBlock][64];
-    __shared__ float2 sP[kWavesPerBlock][65];
+    __shared__ double sC[kWavesPerBlock][64 * U];
+    __shared__ double sR[kWavesPerBlock][64 * U];
+    __shared__ float2 sP[kWavesPerBlock][64 * U + 1];
 
     const int64_t i0 = d.off_in[e], m = d.off_in[e + 1] - i0;
     const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
@@ -235,43 +267,65 @@ __global__ __launch_bounds__(kBlock) void k_resample_splat(const GDesc *__restri
     const float2 *p = d.pin + i0;
     float2 *q = d.samples + o0;
     const int W = d.W, H = d.H;
-    int32_t *hist = d.hist + (int64_t)d.group[e] * W * H;
+    const int64_t plane = (int64_t)W * H;
+    int32_t *hist = d.histx + ((int64_t)xcc_id(d.nx) * d.B + d.group[e]) * plane;
     const int w = d.weight ? d.weight[e] : 1;
     const double nm1 = (double)(n - 1);
+    const double ds = L / nm1;          // arclength between consecutive samples
 
     double Cbase = 0.0;
     int64_t knext = 0;
-    for (int64_t j0 = 0; j0 < m - 1; j0 += 64) {
-        const int nseg = (int)((m - 1 - j0) < 64 ? (m - 1 - j0) : 64);
-        float2 a = make_float2(0.0f, 0.0f);
-        if (lane <= nseg && lane < 64) a = p[j0 + lane];
-        float2 b;
-        b.x = __shfl_down(a.x, 1, 64);
-        b.y = __shfl_down(a.y, 1, 64);
-        if (lane == 63 && nseg == 64) b = p[j0 + 64];
-        const double ell = lane < nseg ? seg_len(a, b) : 0.0;
-        const double incl = wave_incl_scan<double>(ell, lane);
-        double excl = __shfl_up(incl, 1, 64);
-        if (lane == 0) excl = 0.0;
-        if (lane < nseg) {
-            sC[wid][lane] = Cbase + excl;
-            sP[wid][lane] = a;
+    for (int64_t j0 = 0; j0 < m - 1; j0 += 64 * U) {
+        const int64_t rem = m - 1 - j0;
+        const int nsegT = (int)(rem < 64 * U ? rem : 64 * U);
+        float2 a[U], b[U];
+        double incl[U];
+        int ns[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t r = rem - 64 * u;
+            ns[u] = (int)(r <= 0 ? 0 : (r < 64 ? r : 64));
+            a[u] = make_float2(0.0f, 0.0f);
+            if (lane <= ns[u] && ns[u] > 0) a[u] = p[j0 + 64 * u + lane];
         }
-        if (lane == nseg - 1) sP[wid][nseg] = b;
-        const double Cend = Cbase + __shfl(incl, nseg - 1, 64);
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            b[u].x = __shfl_down(a[u].x, 1, 64);
+            b[u].y = __shfl_down(a[u].y, 1, 64);
+            if (lane == 63 && ns[u] == 64) b[u] = p[j0 + 64 * u + 64];
+        }
+        double ell[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) ell[u] = lane < ns[u] ? seg_len(a[u], b[u]) : 0.0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) incl[u] = wave_incl_scan<double>(ell[u], lane);
+        double cb = Cbase;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            double excl = __shfl_up(incl[u], 1, 64);
+            if (lane == 0) excl = 0.0;
+            if (lane < ns[u]) {
+                sC[wid][64 * u + lane] = cb + excl;
+                sR[wid][64 * u + lane] = ell[u] > 0.0 ? 1.0 / ell[u] : 0.0;
+                sP[wid][64 * u + lane] = a[u];
+            }
+            if (lane == ns[u] - 1) sP[wid][64 * u + ns[u]] = b[u];
+            cb = cb + __shfl(incl[u], 63, 64);
+        }
+        const double Cend = cb;
         __builtin_amdgcn_wave_barrier();
 
-        const bool last = (j0 + 64 >= m - 1);
+        const bool last = (j0 + 64 * U >= m - 1);
         int64_t kend;
         if (last) {
             kend = n;
         } else if (!(L > 0.0)) {
             kend = knext;
         } else {
-            double kf = ceil(Cend * nm1 / L);
+            double kf = ceil(Cend / ds);
             int64_t kk = kf < (double)knext ? knext : (kf > nm1 ? n - 1 : (int64_t)kf);
-            while (kk > knext && (double)(kk - 1) * L / nm1 >= Cend) --kk;
-            while (kk < n - 1 && (double)kk * L / nm1 < Cend) ++kk;
+            while (kk > knext && (double)(kk - 1) * ds >= Cend) --kk;
+            while (kk < n - 1 && (double)kk * ds < Cend) ++kk;
             kend = kk;
         }
         for (int64_t kb = knext; kb < kend; kb += 64) {
@@ -283,16 +337,15 @@ __global__ __launch_bounds__(kBlock) void k_resample_splat(const GDesc *__restri
                 } else if (k == n - 1) {
                     out = p[m - 1];
                 } else {
-                    const double s = (double)k * L / nm1;
-                    int lo = 0, hi = nseg - 1;
+                    const double s = (double)k * ds;
+                    int lo = 0, hi = nsegT - 1;
                     while (lo < hi) {
                         int mid = (lo + hi + 1) >> 1;
                         if (sC[wid][mid] <= s) lo = mid; else hi = mid - 1;
                     }
                     const float2 pa = sP[wid][lo], pb = sP[wid][lo + 1];
                     const double ex = (double)pb.x - (double)pa.x, ey = (double)pb.y - (double)pa.y;
-                    const double el = sqrt(ex * ex + ey * ey);
-                    double t = el > 0.0 ? (s - sC[wid][lo]) / el : 0.0;
+                    double t = (s - sC[wid][lo]) * sR[wid][lo];
                     t = fmin(fmax(t, 0.0), 1.0);
                     out.x = (float)((double)pa.x + t * ex);
                     out.y = (float)((double)pa.y + t * ey);
@@ -314,26 +367,31 @@ __global__ __launch_bounds__(kBlock) void k_splat_given(const GDesc *__restrict_
     if (stopped(d)) return;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int64_t e = (blk - d.blk_edge) * kWavesPerBlock + wid;
-    if (e >= d.n_edges) return;
+    const int64_t e = edge_of(d, blk - d.blk_edge, wid);
+    if (e < 0) return;
     const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
-    int32_t *hist = d.hist + (int64_t)d.group[e] * d.W * d.H;
+    const int64_t plane = (int64_t)d.W * d.H;
+    int32_t *hist = d.histx + ((int64_t)xcc_id(d.nx) * d.B + d.group[e]) * plane;
     const int w = d.weight ? d.weight[e] : 1;
     for (int64_t j = lane; j < n; j += 64) splat_point(hist, d.W, d.H, d.samples[o0 + j], w);
 }
 
 // ---------------------------------------------------------------- maps
 
+// Clear every per-XCD histogram copy. One thread per layer pixel.
 __global__ __launch_bounds__(kBlock) void k_clear_hist(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_pxb);
     if (stopped(d)) return;
+    const int64_t n = (int64_t)d.B * d.W * d.H;
     const int64_t i = (blk - d.blk_pxb) * kBlock + threadIdx.x;
-    if (i < (int64_t)d.B * d.W * d.H) d.hist[i] = 0;
+    if (i >= n) return;
+    for (int c = 0; c < d.nx; ++c) d.histx[c * n + i] = 0;
 }
 
 // Row pass of one box filter: out(u) = sum of in(u') over |u'-u| <= r inside the row,
-// from the row's prefix sums in LDS. One block per row of one group.
+// from the row's prefix sums in LDS. One block per row of one group. The first pass sums
+// the per-XCD histogram copies, stores the histogram row and flags int32 overflow.
 template <typename Tin>
 __global__ __launch_bounds__(kBlock) void k_box_rows(const GDesc *__restrict__ gd, int ng,
                                                      int pass) {
@@ -344,9 +402,24 @@ __global__ __launch_bounds__(kBlock) void k_box_rows(const GDesc *__restrict__ g
     const int64_t row = blk - d.blk_row;
     const int W = d.W, r = d.r;
     const int64_t plane = (int64_t)d.B * d.W * d.H;
-    const Tin *in = (pass == 0 ? (const Tin *)d.hist : (const Tin *)(d.box + (pass - 1) * plane)) +
-                    row * W;
-    for (int u = threadIdx.x; u < W; u += kBlock) srow[u] = (int64_t)in[u];
+    if (pass == 0) {
+        bool bad = false;
+        for (int u = threadIdx.x; u < W; u += kBlock) {
+            int64_t x = 0;
+            for (int c = 0; c < d.nx; ++c) {
+                const int32_t v = d.histx[c * plane + row * W + u];
+                bad |= v < 0;
+                x += v;
+            }
+            bad |= x > 2147483647;
+            srow[u] = x;
+            d.hist[row * W + u] = (int32_t)x;
+        }
+        if (bad) atomicOr(d.status, ST_HIST_OVERFLOW);
+    } else {
+        const Tin *in = (const Tin *)(d.box + (pass - 1) * plane) + row * W;
+        for (int u = threadIdx.x; u < W; u += kBlock) srow[u] = (int64_t)in[u];
+    }
     __syncthreads();
     const int items = (W + kBlock - 1) / kBlock;
     const int beg = threadIdx.x * items;
@@ -484,7 +557,25 @@ __device__ __forceinline__ Bilin bilin_taps(double x, double y, int W, int H) {
     return b;
 }
 
-// Density sample for the acceptance test, in FP32 (the precision of the stored map).
+// FP32 taps and density sample for the acceptance tests (the precision of the stored map).
+__device__ __forceinline__ float bilin1f(const float *__restrict__ m, float x, float y, int W,
+                                         int H) {
+    const float fx = fminf(fmaxf(x - 0.5f, -1.0f), (float)W);
+    const float fy = fminf(fmaxf(y - 0.5f, -1.0f), (float)H);
+    const float u0f = floorf(fx), v0f = floorf(fy);
+    const float tx = fx - u0f, ty = fy - v0f;
+    int u0 = (int)u0f, v0 = (int)v0f;
+    int u1 = u0 + 1, v1 = v0 + 1;
+    u0 = u0 < 0 ? 0 : (u0 > W - 1 ? W - 1 : u0);
+    u1 = u1 < 0 ? 0 : (u1 > W - 1 ? W - 1 : u1);
+    v0 = v0 < 0 ? 0 : (v0 > H - 1 ? H - 1 : v0);
+    v1 = v1 < 0 ? 0 : (v1 > H - 1 ? H - 1 : v1);
+    const float *r0 = m + v0 * W, *r1 = m + v1 * W;
+    return (1.0f - tx) * (1.0f - ty) * r0[u0] + tx * (1.0f - ty) * r0[u1] +
+           (1.0f - tx) * ty * r1[u0] + tx * ty * r1[u1];
+}
+
+// Density sample with the FP64 taps of the gradient sample.
 __device__ __forceinline__ float bilin1(const float *__restrict__ m, const Bilin &b) {
     const float tx = (float)b.tx, ty = (float)b.ty;
     return (1.0f - tx) * (1.0f - ty) * m[b.i00] + tx * (1.0f - ty) * m[b.i10] +
@@ -503,18 +594,20 @@ __device__ __forceinline__ void bilin2(const float2 *__restrict__ m, const Bilin
     gy = w00 * f00.y + w10 * f10.y + w01 * f01.y + w11 * f11.y;
 }
 
-// One wave per edge, chunks of 62 output points with a one-point halo on each side: lane
-// l of a chunk advects point j0 - 1 + l (end points stay), neighbours come from lanes l-1
-// and l+1, and lanes 1..62 write the Laplacian-smoothed point. The FP64 polyline length
-// of the smoothed edge gives the next sample count.
+// One wave per edge. Each trip handles U sub-chunks of 62 output points with a one-point
+// halo on each side (U independent gather chains in flight): lane l of sub-chunk u
+// advects point j0 + 62u - 1 + l (end points stay), neighbours come from lanes l-1 and l+1,
+// and lanes 1..62 write the Laplacian-smoothed point. The FP64 length of the smoothed
+// polyline gives the next sample count.
+template <int U>
 __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_edge);
     if (stopped(d)) return;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int64_t e = (blk - d.blk_edge) * kWavesPerBlock + wid;
-    if (e >= d.n_edges) return;
+    const int64_t e = edge_of(d, blk - d.blk_edge, wid);
+    if (e < 0) return;
 
     const int W = d.W, H = d.H;
     const int64_t plane = (int64_t)W * H;
@@ -525,62 +618,106 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
     const float2 *__restrict__ xs = d.samples + o0;
     float2 *__restrict__ ys = d.pnew + o0;
     const double h = d.h, s = d.s;
-    const double eps = d.eps;
+    const float eps = (float)d.eps;
     const int K = d.K;
     const double xmax = (double)W - 1.0 / 256.0, ymax = (double)H - 1.0 / 256.0;
+    const float xmaxf = (float)xmax, ymaxf = (float)ymax;
 
     double L = 0.0;
     float2 yprev = make_float2(0.0f, 0.0f);
-    for (int64_t j0 = 0; j0 < n; j0 += 62) {
-        const int64_t j = j0 - 1 + lane;
-        const bool inr = j >= 0 && j < n;
-        float2 x = make_float2(0.0f, 0.0f);
-        if (inr) x = xs[j];
-        double ax = x.x, ay = x.y;
-        int jj = -2;
-        if (inr && j > 0 && j < n - 1) {
-            const Bilin t0 = bilin_taps(ax, ay, W, H);
-            double gx, gy;
-            bilin2(grad, t0, gx, gy);
-            const double nrm = sqrt(gx * gx + gy * gy);
-            const double den = nrm > eps ? nrm : eps;
-            const double dx = gx / den, dy = gy / den;
-            const float r0 = bilin1(rho, t0);
-            double m = h;
-            jj = -1;
-            for (int k = 0; k <= K; ++k) {
-                const double cx = fmin(fmax((double)x.x + m * dx, 0.0), xmax);
-                const double cy = fmin(fmax((double)x.y + m * dy, 0.0), ymax);
-                const float r1 = bilin1(rho, bilin_taps(cx, cy, W, H));
-                if (r1 >= r0) {
-                    ax = cx;
-                    ay = cy;
-                    jj = k;
-                    break;
-                }
-                m *= 0.5;
+    for (int64_t j0 = 0; j0 < n; j0 += 62 * U) {
+        float2 x[U];
+        double ax[U], ay[U];
+        float dx[U], dy[U], r0[U];
+        int jj[U];
+        bool act[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t j = j0 + 62 * u - 1 + lane;
+            const bool inr = j >= 0 && j < n;
+            x[u] = make_float2(0.0f, 0.0f);
+            if (inr) x[u] = xs[j];
+            ax[u] = x[u].x;
+            ay[u] = x[u].y;
+            act[u] = inr && j > 0 && j < n - 1;
+            jj[u] = act[u] ? -1 : -2;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            dx[u] = dy[u] = 0.0f;
+            r0[u] = 0.0f;
+            if (act[u]) {
+                // the interpolated gradient in FP64 keeps its direction where the taps
+                // nearly cancel; its normalisation only needs FP32
+                const Bilin t0 = bilin_taps(ax[u], ay[u], W, H);
+                double gx, gy;
+                bilin2(grad, t0, gx, gy);
+                const float fx = (float)gx, fy = (float)gy;
+                const float nrm = sqrtf(fx * fx + fy * fy);
+                const float den = nrm > eps ? nrm : eps;
+                dx[u] = fx / den;
+                dy[u] = fy / den;
+                r0[u] = bilin1(rho, t0);
             }
         }
-        const double lx = __shfl_up(ax, 1, 64), ly = __shfl_up(ay, 1, 64);
-        const double rx = __shfl_down(ax, 1, 64), ry = __shfl_down(ay, 1, 64);
-        const bool out = lane >= 1 && lane <= 62 && j < n;
-        float2 y = x;
-        if (out && j > 0 && j < n - 1) {
-            y.x = (float)((1.0 - s) * ax + 0.5 * s * (lx + rx));
-            y.y = (float)((1.0 - s) * ay + 0.5 * s * (ly + ry));
+        // acceptance tests in FP32; the accepted point is recomputed in FP64
+        float mf = (float)h;
+        for (int k = 0; k <= K; ++k) {
+            bool any = false;
+#pragma unroll
+            for (int u = 0; u < U; ++u) any |= act[u];
+            if (!__any(any)) break;
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (act[u]) {
+                    const float cx = fminf(fmaxf(x[u].x + mf * dx[u], 0.0f), xmaxf);
+                    const float cy = fminf(fmaxf(x[u].y + mf * dy[u], 0.0f), ymaxf);
+                    if (bilin1f(rho, cx, cy, W, H) >= r0[u]) {
+                        jj[u] = k;
+                        act[u] = false;
+                    }
+                }
+            }
+            mf *= 0.5f;
         }
-        if (out) {
-            ys[j] = y;
-            if (d.record) d.jacc[o0 + j] = (int8_t)jj;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (jj[u] >= 0) {
+                const double m = ldexp(h, -jj[u]);
+                ax[u] = fmin(fmax((double)x[u].x + m * (double)dx[u], 0.0), xmax);
+                ay[u] = fmin(fmax((double)x[u].y + m * (double)dy[u], 0.0), ymax);
+            }
         }
-        float2 yl;
-        yl.x = __shfl_up(y.x, 1, 64);
-        yl.y = __shfl_up(y.y, 1, 64);
-        if (lane == 1) yl = yprev;
-        const double sl = (out && j >= 1) ? seg_len(yl, y) : 0.0;
-        L += wave_sum(sl);
-        yprev.x = __shfl(y.x, 62, 64);
-        yprev.y = __shfl(y.y, 62, 64);
+        float2 y[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t j = j0 + 62 * u - 1 + lane;
+            const double lx = __shfl_up(ax[u], 1, 64), ly = __shfl_up(ay[u], 1, 64);
+            const double rx = __shfl_down(ax[u], 1, 64), ry = __shfl_down(ay[u], 1, 64);
+            const bool out = lane >= 1 && lane <= 62 && j < n;
+            y[u] = x[u];
+            if (out && j > 0 && j < n - 1) {
+                y[u].x = (float)((1.0 - s) * ax[u] + 0.5 * s * (lx + rx));
+                y[u].y = (float)((1.0 - s) * ay[u] + 0.5 * s * (ly + ry));
+            }
+            if (out) {
+                ys[j] = y[u];
+                if (d.record) d.jacc[o0 + j] = (int8_t)jj[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t j = j0 + 62 * u - 1 + lane;
+            const bool out = lane >= 1 && lane <= 62 && j < n;
+            float2 yl;
+            yl.x = __shfl_up(y[u].x, 1, 64);
+            yl.y = __shfl_up(y[u].y, 1, 64);
+            if (lane == 1) yl = yprev;
+            const double sl = (out && j >= 1) ? seg_len(yl, y[u]) : 0.0;
+            L += wave_sum(sl);
+            yprev.x = __shfl(y[u].x, 62, 64);
+            yprev.y = __shfl(y[u].y, 62, 64);
+        }
     }
     if (lane == 0) {
         d.lens[e] = L;
@@ -630,9 +767,16 @@ hipError_t launch_scan(const GDesc *desc, int ng, const Shape &tot, hipStream_t 
     return hipGetLastError();
 }
 
+int g_resample_u = 1, g_advect_u = 2;
+
 hipError_t launch_resample_splat(const GDesc *desc, int ng, const Shape &tot, hipStream_t st) {
     if (tot.edge <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_resample_splat, grid_of(tot.edge), dim3(kBlock), 0, st, desc, ng);
+    const dim3 gr = grid_of(tot.edge), bl(kBlock);
+    switch (g_resample_u) {
+        case 1: hipLaunchKernelGGL(k_resample_splat<1>, gr, bl, 0, st, desc, ng); break;
+        case 4: hipLaunchKernelGGL(k_resample_splat<4>, gr, bl, 0, st, desc, ng); break;
+        default: hipLaunchKernelGGL(k_resample_splat<2>, gr, bl, 0, st, desc, ng); break;
+    }
     return hipGetLastError();
 }
 
@@ -674,7 +818,12 @@ hipError_t launch_density_grad(const GDesc *desc, int ng, const Shape &tot, int 
 
 hipError_t launch_advect_smooth(const GDesc *desc, int ng, const Shape &tot, hipStream_t st) {
     if (tot.edge <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_advect_smooth, grid_of(tot.edge), dim3(kBlock), 0, st, desc, ng);
+    const dim3 gr = grid_of(tot.edge), bl(kBlock);
+    switch (g_advect_u) {
+        case 1: hipLaunchKernelGGL(k_advect_smooth<1>, gr, bl, 0, st, desc, ng); break;
+        case 4: hipLaunchKernelGGL(k_advect_smooth<4>, gr, bl, 0, st, desc, ng); break;
+        default: hipLaunchKernelGGL(k_advect_smooth<2>, gr, bl, 0, st, desc, ng); break;
+    }
     return hipGetLastError();
 }
 

@@ -39,7 +39,8 @@ struct hb_ctx {
     bool have_graph = false;
     int32_t B = 0;
     bool have_groups = false;
-    int32_t *d_group = nullptr, *d_weight = nullptr;
+    int32_t *d_group = nullptr, *d_weight = nullptr, *d_perm = nullptr;
+    std::vector<uint32_t> h_morton;     // Morton code of each straight edge's midpoint
     float *d_M = nullptr;
 
     // points: state = (pts[ps], off[os]); last samples = (pts[ss], off[so])
@@ -56,7 +57,8 @@ struct hb_ctx {
     int totals_cap = 0;
 
     // maps of the last iteration
-    int32_t *d_hist = nullptr;
+    int32_t *d_hist = nullptr, *d_histx = nullptr;
+    int32_t nx = 1;
     int64_t *d_box = nullptr, *d_tmp = nullptr;
     float *d_rho = nullptr;
     float2 *d_grad = nullptr;
@@ -74,6 +76,14 @@ struct hb_ctx {
 
     int32_t iter = 0;
     std::vector<int64_t> last_counts;
+
+    // per-stage timing
+    bool profiling = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<int> ev_stage;           // stage of each recorded pair
+    double stage_ms[HB_NUM_STAGES] = {0};
+    int64_t stage_n[HB_NUM_STAGES] = {0};
 
     // pending asynchronous run
     bool pending = false;
@@ -303,6 +313,7 @@ static hb_status ensure_maps(hb_ctx *c) {
     const size_t plane = (size_t)B * W * H;
     c->have_maps = false;
     CHKST(dalloc(c, &c->d_hist, plane, "histogram"));
+    CHKST(dalloc(c, &c->d_histx, plane * (size_t)c->nx, "per-XCD histograms"));
     CHKST(dalloc(c, &c->d_box, plane * P, "box passes"));
     CHKST(dalloc(c, &c->d_tmp, plane, "row-pass scratch"));
     CHKST(dalloc(c, &c->d_rho, plane, "density"));
@@ -334,6 +345,7 @@ static GDesc base_desc(const hb_ctx *c) {
     for (int k = 0; k < d.P; ++k)
         d.a[k] = c->passw.empty() ? (k == d.P - 1 ? 1.0 : 0.0) : (double)c->passw[k];
     d.group = c->d_group;
+    d.perm = c->d_perm;
     d.weight = c->d_weight;
     d.M = c->d_M;
     d.counts = c->d_counts;
@@ -341,6 +353,8 @@ static GDesc base_desc(const hb_ctx *c) {
     d.tsum = c->d_tsum;
     d.total = c->d_totals;
     d.hist = c->d_hist;
+    d.histx = c->d_histx;
+    d.nx = c->nx;
     d.box = c->d_box;
     d.tmp = c->d_tmp;
     d.rho = c->d_rho;
@@ -380,6 +394,52 @@ static hb_status read_scalar(hb_ctx *c, const int64_t *dptr, int64_t *out) {
     return HB_OK;
 }
 
+// ------------------------------------------------------------------ stage timing
+
+// Record the start event of a stage launch; returns the pair index or -1.
+static hb_status stage_begin(hb_ctx *c, int stage, int *pair) {
+    *pair = -1;
+    if (!c->profiling) return HB_OK;
+    size_t need = c->ev_used + 2;
+    while (c->ev_pool.size() < need) {
+        hipEvent_t e;
+        HIPCHK(c, hipEventCreate(&e));
+        c->ev_pool.push_back(e);
+    }
+    HIPCHK(c, hipEventRecord(c->ev_pool[c->ev_used], c->stream));
+    *pair = (int)(c->ev_used / 2);
+    c->ev_stage.push_back(stage);
+    c->ev_used += 2;
+    return HB_OK;
+}
+
+static hb_status stage_end(hb_ctx *c, int pair) {
+    if (pair < 0) return HB_OK;
+    HIPCHK(c, hipEventRecord(c->ev_pool[(size_t)pair * 2 + 1], c->stream));
+    return HB_OK;
+}
+
+// After the stream has drained: fold the recorded pairs into the accumulators.
+static hb_status stage_collect(hb_ctx *c) {
+    for (size_t i = 0; i < c->ev_stage.size(); ++i) {
+        float ms = 0.0f;
+        HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[2 * i], c->ev_pool[2 * i + 1]));
+        c->stage_ms[c->ev_stage[i]] += (double)ms;
+        c->stage_n[c->ev_stage[i]] += 1;
+    }
+    c->ev_stage.clear();
+    c->ev_used = 0;
+    return HB_OK;
+}
+
+#define STAGE(c, id, launch)                      \
+    do {                                          \
+        int pair_;                                \
+        CHKST(stage_begin(c, id, &pair_));        \
+        HIPCHK(c, launch);                        \
+        CHKST(stage_end(c, pair_));               \
+    } while (0)
+
 // ------------------------------------------------------------------ lifecycle
 
 HB_API hb_status hb_create(hb_ctx **out, int32_t device, void *hip_stream) {
@@ -395,6 +455,16 @@ HB_API hb_status hb_create(hb_ctx **out, int32_t device, void *hip_stream) {
     if (!guard.ok) {
         delete c;
         return fail(nullptr, HB_EDEVICE, "hipSetDevice failed");
+    }
+    {
+        int nx = 1;
+        if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, device) != hipSuccess || nx < 1)
+            nx = 1;
+        c->nx = nx > 16 ? 16 : nx;
+        (void)hipGetLastError();
+        // work per trip of the point kernels (tuning knobs; 1, 2 or 4)
+        if (const char *v = getenv("HB_RESAMPLE_U")) hb::g_resample_u = atoi(v);
+        if (const char *v = getenv("HB_ADVECT_U")) hb::g_advect_u = atoi(v);
     }
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;
@@ -431,6 +501,7 @@ HB_API void hb_destroy(hb_ctx *c) {
         DeviceGuard guard(c->device);
         (void)hipStreamSynchronize(c->stream);
         dfree(&c->d_group);
+        dfree(&c->d_perm);
         dfree(&c->d_weight);
         dfree(&c->d_M);
         for (int i = 0; i < 2; ++i) {
@@ -443,6 +514,7 @@ HB_API void hb_destroy(hb_ctx *c) {
         dfree(&c->d_lens);
         dfree(&c->d_status);
         dfree(&c->d_hist);
+        dfree(&c->d_histx);
         dfree(&c->d_box);
         dfree(&c->d_tmp);
         dfree(&c->d_rho);
@@ -451,6 +523,7 @@ HB_API void hb_destroy(hb_ctx *c) {
         dfree(&c->d_desc);
         if (c->h_desc) (void)hipHostFree(c->h_desc);
         if (c->desc_done) (void)hipEventDestroy(c->desc_done);
+        for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
     }
     delete c;
@@ -550,6 +623,28 @@ HB_API hb_status hb_set_graph(hb_ctx *c, int32_t n_nodes, const float *node_xy, 
         wmax = std::max(wmax, w);
     }
     const int64_t E = n_edges;
+    {
+        // Morton code (16 bits per axis) of each edge's midpoint in the grid, for the
+        // visiting order of the point kernels
+        auto spread = [](uint32_t v) {
+            v &= 0xffff;
+            v = (v | (v << 8)) & 0x00ff00ffu;
+            v = (v | (v << 4)) & 0x0f0f0f0fu;
+            v = (v | (v << 2)) & 0x33333333u;
+            v = (v | (v << 1)) & 0x55555555u;
+            return v;
+        };
+        const double x0 = c->P.bbox[0], y0 = c->P.bbox[1], sx = c->P.bbox[2] - x0, sy = c->P.bbox[3] - y0;
+        c->h_morton.resize((size_t)E);
+        for (int64_t e = 0; e < E; ++e) {
+            const float *a = &hx[2 * (size_t)hs[e]], *b = &hx[2 * (size_t)ht[e]];
+            double mx = (0.5 * ((double)a[0] + b[0]) - x0) / sx, my = (0.5 * ((double)a[1] + b[1]) - y0) / sy;
+            mx = std::min(std::max(mx, 0.0), 1.0);
+            my = std::min(std::max(my, 0.0), 1.0);
+            c->h_morton[e] = spread((uint32_t)(mx * 65535.0)) | (spread((uint32_t)(my * 65535.0)) << 1);
+        }
+        dfree(&c->d_perm);
+    }
     c->have_graph = false;
     c->have_samples = false;
     c->have_jacc = false;
@@ -639,6 +734,21 @@ HB_API hb_status hb_set_groups(hb_ctx *c, int32_t n_groups, const int32_t *group
     CHKST(upload(c, c->d_group, hg));
     CHKST(dalloc(c, &c->d_M, hm.size(), "interaction matrix"));
     CHKST(upload(c, c->d_M, hm));
+    // visiting order of the point kernels: identity by default; HB_EDGE_ORDER=1 visits the
+    // edges by group, then by position (Morton order of the midpoint), which keeps an XCD's
+    // density gathers in its L2 but concentrates the memory-side splat atomics
+    dfree(&c->d_perm);
+    if (const char *ord = getenv("HB_EDGE_ORDER"); ord && atoi(ord) == 1) {
+        std::vector<int32_t> perm((size_t)c->E);
+        for (int64_t e = 0; e < c->E; ++e) perm[e] = (int32_t)e;
+        const std::vector<uint32_t> &mc = c->h_morton;
+        std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
+            if (hg[a] != hg[b]) return hg[a] < hg[b];
+            return mc[a] < mc[b];
+        });
+        CHKST(dalloc(c, &c->d_perm, std::max<size_t>(1, perm.size()), "edge order"));
+        CHKST(upload(c, c->d_perm, perm));
+    }
     c->B = n_groups;
     c->have_groups = true;
     c->have_maps = false;
@@ -660,7 +770,7 @@ HB_API hb_status hb_run(hb_ctx *c, int32_t n_iters, uint32_t flags) {
     c->last_counts.clear();
     if (n_iters == 0) return HB_OK;
     if ((flags & HB_RUN_SAMPLES_GIVEN) &&
-        (double)c->n_state * (double)c->wmax >= 2147483647.0)
+        (double)c->n_state * (double)c->wmax >= 4294967295.0)
         return fail(c, HB_EOVERFLOW, "histogram counts could exceed int32");
     CHKST(enqueue_run(c, n_iters, flags));
     if (flags & HB_RUN_ASYNC) return HB_OK;
@@ -716,13 +826,14 @@ static hb_status enqueue_run(hb_ctx *c, int T, uint32_t flags) {
     for (int it = 0; it < T; ++it) {
         const GDesc *dd = c->d_desc + it;
         const bool given = it == 0 && (flags & HB_RUN_SAMPLES_GIVEN);
-        if (!given) HIPCHK(c, hb::launch_scan(dd, 1, s, c->stream));
-        HIPCHK(c, hb::launch_clear_hist(dd, 1, s, c->stream));
-        if (given) HIPCHK(c, hb::launch_splat_given(dd, 1, s, c->stream));
-        else HIPCHK(c, hb::launch_resample_splat(dd, 1, s, c->stream));
-        for (int k = 0; k < c->P.box_passes; ++k) HIPCHK(c, hb::launch_box_pass(dd, 1, s, W, k, c->stream));
-        HIPCHK(c, hb::launch_density_grad(dd, 1, s, B, c->stream));
-        HIPCHK(c, hb::launch_advect_smooth(dd, 1, s, c->stream));
+        if (!given) STAGE(c, HB_STAGE_SCAN, hb::launch_scan(dd, 1, s, c->stream));
+        STAGE(c, HB_STAGE_CLEAR, hb::launch_clear_hist(dd, 1, s, c->stream));
+        if (given) STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_splat_given(dd, 1, s, c->stream));
+        else STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_resample_splat(dd, 1, s, c->stream));
+        for (int k = 0; k < c->P.box_passes; ++k)
+            STAGE(c, HB_STAGE_BOX, hb::launch_box_pass(dd, 1, s, W, k, c->stream));
+        STAGE(c, HB_STAGE_DENSITY_GRAD, hb::launch_density_grad(dd, 1, s, B, c->stream));
+        STAGE(c, HB_STAGE_ADVECT_SMOOTH, hb::launch_advect_smooth(dd, 1, s, c->stream));
     }
     c->pending = true;
     c->pend_start = c->iter;
@@ -743,6 +854,7 @@ static hb_status finish_pending(hb_ctx *c) {
     while (c->pending) {
         c->pending = false;
         HIPCHK(c, hipStreamSynchronize(c->stream));
+        CHKST(stage_collect(c));
         int32_t status = 0;
         HIPCHK(c, hipMemcpy(&status, c->d_status, sizeof status, hipMemcpyDeviceToHost));
         const int T = c->pend_T;
@@ -775,7 +887,7 @@ static hb_status finish_pending(hb_ctx *c) {
         if (status & hb::ST_HIST_OVERFLOW)
             return fail(c, HB_EOVERFLOW,
                         "sample count too large for int32 histograms or int64 box sums");
-        CHKST(ensure_capacity(c, need + need / 4 + 64));
+        CHKST(ensure_capacity(c, 2 * need + 64));
         uint32_t flags = c->pend_flags;
         if (f > 0) flags &= ~(uint32_t)HB_RUN_SAMPLES_GIVEN;
         CHKST(enqueue_run(c, T - f, flags & ~(uint32_t)HB_RUN_ASYNC));
@@ -940,5 +1052,30 @@ HB_API hb_status hb_set_iteration(hb_ctx *c, int32_t iter) {
     CHKST(finish_pending(c));
     if (iter < 0) return fail(c, HB_EINVAL, "iteration must be >= 0");
     c->iter = iter;
+    return HB_OK;
+}
+
+HB_API hb_status hb_set_profiling(hb_ctx *c, int32_t enable) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    c->profiling = enable != 0;
+    return HB_OK;
+}
+
+HB_API hb_status hb_get_stage_times(hb_ctx *c, double *ms, int64_t *launches, int32_t n_stages,
+                                    int32_t reset) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    if (n_stages < 0 || n_stages > HB_NUM_STAGES) return fail(c, HB_EINVAL, "n_stages out of range");
+    if ((n_stages > 0 && (!ms || !launches))) return fail(c, HB_EINVAL, "ms and launches are required");
+    for (int i = 0; i < n_stages; ++i) {
+        ms[i] = c->stage_ms[i];
+        launches[i] = c->stage_n[i];
+    }
+    if (reset)
+        for (int i = 0; i < HB_NUM_STAGES; ++i) {
+            c->stage_ms[i] = 0.0;
+            c->stage_n[i] = 0;
+        }
     return HB_OK;
 }
