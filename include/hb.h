@@ -61,7 +61,10 @@ enum {
                                       sample points (no resampling in that iteration) */
     HB_RUN_RECORD_DECISIONS = 2u,  /* keep the accepted halving index of every sample point of
                                       the last iteration (hb_get_decisions) */
-    HB_RUN_ASYNC = 4u              /* return without waiting; errors surface at hb_sync */
+    HB_RUN_ASYNC = 4u,             /* return without waiting; errors surface at hb_sync */
+    HB_RUN_GRAPH = 8u              /* capture the n_iters iterations as one hipGraph and replay
+                                      it on later runs with the same layout (graph count, sizes,
+                                      n_iters and flags) */
 };
 
 /* which point set hb_get_num_points / hb_get_points read */
@@ -183,6 +186,27 @@ const char *hb_last_error(const hb_ctx *ctx);
 
 /* Library version string. */
 const char *hb_version(void);
+
+/*
+ * Batched form: many independent graphs (each in its own context, all on one device) advance
+ * together. Every stage of an iteration is one kernel launch for the whole batch, over a
+ * device table of per-graph descriptors; graphs may differ in edge count, group count, grid
+ * size and schedule. Launches go to the stream of ctxs[0] (the streams of the other contexts
+ * are drained first). flags: HB_RUN_ASYNC, HB_RUN_GRAPH. A context whose point buffers
+ * overflow is grown and finished on its own stream. Errors name the first failing context in
+ * hb_last_error(ctxs[0]).
+ */
+hb_status hb_batch_run(hb_ctx *const *ctxs, int32_t n, int32_t n_iters, uint32_t flags);
+
+/* Choose the kernel variants (work chunks per trip of the resampling and advection kernels)
+ * for a batch by timing n_iters iterations of each candidate from the current polylines and
+ * restoring them afterwards. The choice is stored in every context and written to
+ * choice[2] (resample, advect) when choice is not NULL. */
+hb_status hb_autotune(hb_ctx *const *ctxs, int32_t n, int32_t n_iters, int32_t *choice);
+
+/* Set / read the kernel variants directly (chunks 1, 2 or 4). */
+hb_status hb_set_tuning(hb_ctx *ctx, int32_t resample_chunks, int32_t advect_chunks);
+hb_status hb_get_tuning(hb_ctx *ctx, int32_t *resample_chunks, int32_t *advect_chunks);
 
 /* Stages of one iteration, for hb_get_stage_times. */
 enum {

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libhb.so")
 
 HB_OK, HB_EINVAL, HB_ENOMEM, HB_EDEVICE, HB_ESTATE, HB_EOVERFLOW = 0, -1, -2, -3, -4, -5
 HB_DEVICE_PTRS = 1
-HB_RUN_SAMPLES_GIVEN, HB_RUN_RECORD_DECISIONS, HB_RUN_ASYNC = 1, 2, 4
+HB_RUN_SAMPLES_GIVEN, HB_RUN_RECORD_DECISIONS, HB_RUN_ASYNC, HB_RUN_GRAPH = 1, 2, 4, 8
 HB_POINTS_STATE, HB_POINTS_SAMPLES = 0, 1
 HB_MAP_HIST, HB_MAP_BOX, HB_MAP_DENSITY, HB_MAP_GRAD = 0, 1, 2, 3
 HB_MAX_GROUPS, HB_MAX_PASSES = 64, 8
@@ -85,6 +85,11 @@ _SIGS = {
     "hb_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "hb_version": (ctypes.c_char_p, []),
     "hb_set_profiling": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
+    "hb_batch_run": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32]),
+    "hb_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
+    "hb_set_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "hb_get_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32)]),
     "hb_get_stage_times": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                             ctypes.c_int32, ctypes.c_int32]),
 }
@@ -293,6 +298,33 @@ def hb_get_stage_times(ctx, reset: bool = False):
     return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(STAGES)}
 
 
+def _ctx_array(ctxs):
+    arr = (ctypes.c_void_p * len(ctxs))(*[c.value for c in ctxs])
+    return arr
+
+
+def hb_batch_run(ctxs, n_iters: int, flags: int = 0) -> None:
+    arr = _ctx_array(ctxs)
+    _check(ctxs[0], load().hb_batch_run(arr, len(ctxs), n_iters, flags))
+
+
+def hb_autotune(ctxs, n_iters: int = 1):
+    arr = _ctx_array(ctxs)
+    choice = (ctypes.c_int32 * 2)()
+    _check(ctxs[0], load().hb_autotune(arr, len(ctxs), n_iters, choice))
+    return int(choice[0]), int(choice[1])
+
+
+def hb_set_tuning(ctx, resample_chunks: int, advect_chunks: int) -> None:
+    _check(ctx, load().hb_set_tuning(ctx, resample_chunks, advect_chunks))
+
+
+def hb_get_tuning(ctx):
+    a, b = ctypes.c_int32(), ctypes.c_int32()
+    _check(ctx, load().hb_get_tuning(ctx, ctypes.byref(a), ctypes.byref(b)))
+    return int(a.value), int(b.value)
+
+
 # ------------------------------------------------------------------ convenience
 
 def make_params(grid_w: int, grid_h: int, radii: Sequence[int], *, delta: float = 1.0,
@@ -392,6 +424,11 @@ class Bundler:
     def ink(self):
         return hb_get_ink(self.ctx)
 
+    def tuning(self, resample_chunks=None, advect_chunks=None):
+        if resample_chunks is not None:
+            hb_set_tuning(self.ctx, resample_chunks, advect_chunks)
+        return hb_get_tuning(self.ctx)
+
     def profiling(self, enable=True):
         hb_set_profiling(self.ctx, enable)
 
@@ -405,3 +442,12 @@ class Bundler:
     @iteration.setter
     def iteration(self, it):
         hb_set_iteration(self.ctx, it)
+
+
+def batch_run(bundlers, n_iters: int, flags: int = 0) -> None:
+    """Advance several ``Bundler`` contexts together (one launch per stage for all)."""
+    hb_batch_run([b.ctx for b in bundlers], n_iters, flags)
+
+
+def autotune(bundlers, n_iters: int = 1):
+    return hb_autotune([b.ctx for b in bundlers], n_iters)

@@ -69,9 +69,6 @@ struct GDesc {
     int32_t *status;
 };
 
-// Work per trip of the point kernels (chunks of 64 segments / 62 points), set at load.
-extern int g_resample_u, g_advect_u;
-
 // Launch-shape block counts of one graph (host side).
 struct Shape {
     int64_t edge, scan, row, col, px, pxb, edget;
@@ -85,13 +82,17 @@ hipError_t launch_init_state(const GDesc *desc, int ng, const Shape &tot, const 
                              double x1, double y1, hipStream_t st);
 hipError_t launch_lengths(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
 hipError_t launch_scan(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
-hipError_t launch_resample_splat(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
+// u: chunks of 64 segments (resampling) / 62 points (advection) per trip: 1, 2 or 4
+hipError_t launch_resample_splat(const GDesc *desc, int ng, const Shape &tot, int u,
+                                 hipStream_t st);
 hipError_t launch_splat_given(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
 hipError_t launch_clear_hist(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
 hipError_t launch_box_pass(const GDesc *desc, int ng, const Shape &tot, int max_w, int pass,
                            hipStream_t st);
 hipError_t launch_density_grad(const GDesc *desc, int ng, const Shape &tot, int bmax,
                                hipStream_t st);
-hipError_t launch_advect_smooth(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
+hipError_t launch_advect_smooth(const GDesc *desc, int ng, const Shape &tot, int u,
+                                hipStream_t st);
+hipError_t launch_fill_totals(const GDesc *desc, int ng, int T, hipStream_t st);
 
 }  // namespace hb

@@ -90,9 +90,11 @@ __device__ __forceinline__ int64_t sample_count(double L, double delta) {
     return (int64_t)q + 1;
 }
 
+// Explicit roundings (no contraction choices left to the compiler), so that every kernel
+// variant computes the same bits.
 __device__ __forceinline__ double seg_len(float2 a, float2 b) {
-    double dx = (double)b.x - (double)a.x, dy = (double)b.y - (double)a.y;
-    return sqrt(dx * dx + dy * dy);
+    const double dx = (double)b.x - (double)a.x, dy = (double)b.y - (double)a.y;
+    return sqrt(__fma_rn(dx, dx, __dmul_rn(dy, dy)));
 }
 
 __device__ __forceinline__ void splat_point(int32_t *hist, int W, int H, float2 p, int w) {
@@ -337,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void k_resample_splat(const GDesc *__restri
                 } else if (k == n - 1) {
                     out = p[m - 1];
                 } else {
-                    const double s = (double)k * ds;
+                    const double s = __dmul_rn((double)k, ds);
                     int lo = 0, hi = nsegT - 1;
                     while (lo < hi) {
                         int mid = (lo + hi + 1) >> 1;
@@ -345,10 +347,10 @@ __global__ __launch_bounds__(kBlock) void k_resample_splat(const GDesc *__restri
                     }
                     const float2 pa = sP[wid][lo], pb = sP[wid][lo + 1];
                     const double ex = (double)pb.x - (double)pa.x, ey = (double)pb.y - (double)pa.y;
-                    double t = (s - sC[wid][lo]) * sR[wid][lo];
+                    double t = __dmul_rn(__dsub_rn(s, sC[wid][lo]), sR[wid][lo]);
                     t = fmin(fmax(t, 0.0), 1.0);
-                    out.x = (float)((double)pa.x + t * ex);
-                    out.y = (float)((double)pa.y + t * ey);
+                    out.x = (float)__fma_rn(t, ex, (double)pa.x);
+                    out.y = (float)__fma_rn(t, ey, (double)pa.y);
                 }
                 q[k] = out;
                 splat_point(hist, W, H, out, w);
@@ -398,7 +400,7 @@ __global__ __launch_bounds__(kBlock) void k_box_rows(const GDesc *__restrict__ g
     extern __shared__ int64_t srow[];
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_row);
-    if (stopped(d)) return;
+    if (stopped(d) || pass >= d.P) return;
     const int64_t row = blk - d.blk_row;
     const int W = d.W, r = d.r;
     const int64_t plane = (int64_t)d.B * d.W * d.H;
@@ -447,7 +449,7 @@ __global__ __launch_bounds__(kBlock) void k_box_cols(const GDesc *__restrict__ g
                                                      int pass) {
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_col);
-    if (stopped(d)) return;
+    if (stopped(d) || pass >= d.P) return;
     const int W = d.W, H = d.H, r = d.r;
     const int nseg = (H + kColSeg - 1) / kColSeg;
     const int64_t t = (blk - d.blk_col) * kBlock + threadIdx.x;
@@ -684,8 +686,8 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
         for (int u = 0; u < U; ++u) {
             if (jj[u] >= 0) {
                 const double m = ldexp(h, -jj[u]);
-                ax[u] = fmin(fmax((double)x[u].x + m * (double)dx[u], 0.0), xmax);
-                ay[u] = fmin(fmax((double)x[u].y + m * (double)dy[u], 0.0), ymax);
+                ax[u] = fmin(fmax(__fma_rn(m, (double)dx[u], (double)x[u].x), 0.0), xmax);
+                ay[u] = fmin(fmax(__fma_rn(m, (double)dy[u], (double)x[u].y), 0.0), ymax);
             }
         }
         float2 y[U];
@@ -697,8 +699,8 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
             const bool out = lane >= 1 && lane <= 62 && j < n;
             y[u] = x[u];
             if (out && j > 0 && j < n - 1) {
-                y[u].x = (float)((1.0 - s) * ax[u] + 0.5 * s * (lx + rx));
-                y[u].y = (float)((1.0 - s) * ay[u] + 0.5 * s * (ly + ry));
+                y[u].x = (float)__fma_rn(0.5 * s, __dadd_rn(lx, rx), __dmul_rn(1.0 - s, ax[u]));
+                y[u].y = (float)__fma_rn(0.5 * s, __dadd_rn(ly, ry), __dmul_rn(1.0 - s, ay[u]));
             }
             if (out) {
                 ys[j] = y[u];
@@ -723,6 +725,13 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
         d.lens[e] = L;
         d.counts[e] = sample_count(L, d.delta);
     }
+}
+
+// Mark the per-iteration sample totals of every graph as not produced yet (-1). One block
+// per graph; desc[g] is graph g's descriptor of the first iteration.
+__global__ __launch_bounds__(kBlock) void k_fill_totals(const GDesc *__restrict__ gd, int T) {
+    int64_t *t = gd[blockIdx.x].total;
+    for (int i = threadIdx.x; i < T; i += kBlock) t[i] = -1;
 }
 
 // ---------------------------------------------------------------- launchers
@@ -752,6 +761,11 @@ hipError_t launch_init_state(const GDesc *desc, int ng, const Shape &tot, const 
     return hipGetLastError();
 }
 
+hipError_t launch_fill_totals(const GDesc *desc, int ng, int T, hipStream_t st) {
+    hipLaunchKernelGGL(k_fill_totals, dim3(ng), dim3(kBlock), 0, st, desc, T);
+    return hipGetLastError();
+}
+
 hipError_t launch_lengths(const GDesc *desc, int ng, const Shape &tot, hipStream_t st) {
     if (tot.edge <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_lengths, grid_of(tot.edge), dim3(kBlock), 0, st, desc, ng);
@@ -767,12 +781,11 @@ hipError_t launch_scan(const GDesc *desc, int ng, const Shape &tot, hipStream_t 
     return hipGetLastError();
 }
 
-int g_resample_u = 1, g_advect_u = 2;
-
-hipError_t launch_resample_splat(const GDesc *desc, int ng, const Shape &tot, hipStream_t st) {
+hipError_t launch_resample_splat(const GDesc *desc, int ng, const Shape &tot, int u,
+                                 hipStream_t st) {
     if (tot.edge <= 0) return hipSuccess;
     const dim3 gr = grid_of(tot.edge), bl(kBlock);
-    switch (g_resample_u) {
+    switch (u) {
         case 1: hipLaunchKernelGGL(k_resample_splat<1>, gr, bl, 0, st, desc, ng); break;
         case 4: hipLaunchKernelGGL(k_resample_splat<4>, gr, bl, 0, st, desc, ng); break;
         default: hipLaunchKernelGGL(k_resample_splat<2>, gr, bl, 0, st, desc, ng); break;
@@ -816,10 +829,11 @@ hipError_t launch_density_grad(const GDesc *desc, int ng, const Shape &tot, int 
     return hipGetLastError();
 }
 
-hipError_t launch_advect_smooth(const GDesc *desc, int ng, const Shape &tot, hipStream_t st) {
+hipError_t launch_advect_smooth(const GDesc *desc, int ng, const Shape &tot, int u,
+                                hipStream_t st) {
     if (tot.edge <= 0) return hipSuccess;
     const dim3 gr = grid_of(tot.edge), bl(kBlock);
-    switch (g_advect_u) {
+    switch (u) {
         case 1: hipLaunchKernelGGL(k_advect_smooth<1>, gr, bl, 0, st, desc, ng); break;
         case 4: hipLaunchKernelGGL(k_advect_smooth<4>, gr, bl, 0, st, desc, ng); break;
         default: hipLaunchKernelGGL(k_advect_smooth<2>, gr, bl, 0, st, desc, ng); break;

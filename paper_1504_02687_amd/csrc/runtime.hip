@@ -85,7 +85,15 @@ struct hb_ctx {
     double stage_ms[HB_NUM_STAGES] = {0};
     int64_t stage_n[HB_NUM_STAGES] = {0};
 
+    // kernel variants (chunks of 64 per trip in resampling / advection)
+    int tune_ru = 1, tune_au = 2;
+
+    // captured iteration sequence, replayed while the batch layout is unchanged
+    hipGraphExec_t gexec = nullptr;
+    std::vector<int64_t> gkey;
+
     // pending asynchronous run
+    hb_ctx *pend_lead = nullptr;
     bool pending = false;
     int32_t pend_start = 0, pend_T = 0;
     uint32_t pend_flags = 0;
@@ -462,9 +470,13 @@ HB_API hb_status hb_create(hb_ctx **out, int32_t device, void *hip_stream) {
             nx = 1;
         c->nx = nx > 16 ? 16 : nx;
         (void)hipGetLastError();
-        // work per trip of the point kernels (tuning knobs; 1, 2 or 4)
-        if (const char *v = getenv("HB_RESAMPLE_U")) hb::g_resample_u = atoi(v);
-        if (const char *v = getenv("HB_ADVECT_U")) hb::g_advect_u = atoi(v);
+        // work per trip of the point kernels (1, 2 or 4; see hb_autotune)
+        auto pick = [](const char *v, int dflt) {
+            int u = v ? atoi(v) : dflt;
+            return (u == 1 || u == 2 || u == 4) ? u : dflt;
+        };
+        c->tune_ru = pick(getenv("HB_RESAMPLE_U"), 1);
+        c->tune_au = pick(getenv("HB_ADVECT_U"), 2);
     }
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;
@@ -524,6 +536,7 @@ HB_API void hb_destroy(hb_ctx *c) {
         if (c->h_desc) (void)hipHostFree(c->h_desc);
         if (c->desc_done) (void)hipEventDestroy(c->desc_done);
         for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+        if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
     }
     delete c;
@@ -757,7 +770,166 @@ HB_API hb_status hb_set_groups(hb_ctx *c, int32_t n_groups, const int32_t *group
 
 // ------------------------------------------------------------------ the iteration loop
 
-static hb_status enqueue_run(hb_ctx *c, int T, uint32_t flags);
+static hb_status prepare_ctx(hb_ctx *c, int T, uint32_t flags) {
+    CHKST(ensure_maps(c));
+    CHKST(ensure_totals(c, T));
+    if ((flags & HB_RUN_RECORD_DECISIONS) && c->jacc_cap < c->cap) {
+        CHKST(dalloc(c, &c->d_jacc, (size_t)c->cap, "decisions"));
+        c->jacc_cap = c->cap;
+    }
+    return HB_OK;
+}
+
+static void shape_add(Shape &a, const Shape &b) {
+    a.edge += b.edge; a.scan += b.scan; a.row += b.row; a.col += b.col;
+    a.px += b.px; a.pxb += b.pxb; a.edget += b.edget;
+}
+
+// Enqueue T iterations of the graphs cs[0..n) on lead's stream: the descriptor table holds
+// [T][n] entries (iteration-major) and every stage of an iteration is one launch for the
+// whole batch. With use_graph the launches are captured once as a hipGraph and replayed
+// while the batch layout is unchanged (only the descriptor contents change between runs).
+static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, uint32_t flags,
+                               bool use_graph) {
+    for (int g = 0; g < n; ++g) {
+        hb_status st = prepare_ctx(cs[g], T, flags);
+        if (st != HB_OK) {
+            if (cs[g] != lead) lead->err = cs[g]->err;
+            return st;
+        }
+    }
+    CHKST(ensure_desc(lead, (size_t)T * n));
+    CHKST(wait_desc(lead));
+
+    std::vector<Shape> base((size_t)n);
+    Shape tot{};
+    int max_w = 2, bmax = 1, pmax = 1;
+    for (int g = 0; g < n; ++g) {
+        const hb_ctx *c = cs[g];
+        base[g] = tot;
+        shape_add(tot, hb::shape_of(c->E, c->B, c->P.grid_w, c->P.grid_h));
+        max_w = std::max(max_w, c->P.grid_w);
+        bmax = std::max(bmax, c->B);
+        pmax = std::max(pmax, c->P.box_passes);
+    }
+    const bool given0 = (flags & HB_RUN_SAMPLES_GIVEN) != 0;
+    const bool record = (flags & HB_RUN_RECORD_DECISIONS) != 0;
+    for (int g = 0; g < n; ++g) {
+        hb_ctx *c = cs[g];
+        c->pend_ps.assign(T, 0);
+        c->pend_os.assign(T, 0);
+        int ps = c->ps, os = c->os, last_ss = 0, last_so = 0;
+        for (int it = 0; it < T; ++it) {
+            c->pend_ps[it] = ps;
+            c->pend_os[it] = os;
+            const bool given = it == 0 && given0;
+            last_ss = given ? ps : 1 - ps;
+            last_so = given ? os : 1 - os;
+            GDesc d = base_desc(c);
+            set_iter_scalars(c, d, c->iter + it);
+            d.blk_edge = base[g].edge;
+            d.blk_scan = base[g].scan;
+            d.blk_row = base[g].row;
+            d.blk_col = base[g].col;
+            d.blk_px = base[g].px;
+            d.blk_pxb = base[g].pxb;
+            d.blk_edget = base[g].edget;
+            d.record = record && it == T - 1;
+            d.total = c->d_totals + it;
+            if (given) {
+                d.samples = c->pts[ps];
+                d.off_s = c->off[os];
+                d.pnew = c->pts[1 - ps];
+                ps = 1 - ps;
+            } else {
+                d.pin = c->pts[ps];
+                d.off_in = c->off[os];
+                d.samples = c->pts[1 - ps];
+                d.off_s = c->off[1 - os];
+                d.pnew = c->pts[ps];
+                os = 1 - os;
+            }
+            lead->h_desc[(size_t)it * n + g] = d;
+        }
+        c->pending = true;
+        c->pend_start = c->iter;
+        c->pend_T = T;
+        c->pend_flags = flags;
+        c->pend_lead = lead;
+        // bookkeeping as if the run completes; finish_pending corrects it on overflow
+        c->ss = last_ss;
+        c->so = last_so;
+        c->ps = ps;
+        c->os = os;
+        c->iter += T;
+    }
+    CHKST(upload_desc(lead, (size_t)T * n));
+
+    const int ru = lead->tune_ru, au = lead->tune_au;
+    auto launch_all = [&](bool timed) -> hb_status {
+        HIPCHK(lead, hb::launch_fill_totals(lead->d_desc, n, T, lead->stream));
+        for (int it = 0; it < T; ++it) {
+            const GDesc *dd = lead->d_desc + (size_t)it * n;
+            hb_ctx *c = lead;
+            const bool given = it == 0 && given0;
+            if (!timed) {
+                if (!given) HIPCHK(c, hb::launch_scan(dd, n, tot, c->stream));
+                HIPCHK(c, hb::launch_clear_hist(dd, n, tot, c->stream));
+                if (given) HIPCHK(c, hb::launch_splat_given(dd, n, tot, c->stream));
+                else HIPCHK(c, hb::launch_resample_splat(dd, n, tot, ru, c->stream));
+                for (int k = 0; k < pmax; ++k) HIPCHK(c, hb::launch_box_pass(dd, n, tot, max_w, k, c->stream));
+                HIPCHK(c, hb::launch_density_grad(dd, n, tot, bmax, c->stream));
+                HIPCHK(c, hb::launch_advect_smooth(dd, n, tot, au, c->stream));
+                continue;
+            }
+            if (!given) STAGE(c, HB_STAGE_SCAN, hb::launch_scan(dd, n, tot, c->stream));
+            STAGE(c, HB_STAGE_CLEAR, hb::launch_clear_hist(dd, n, tot, c->stream));
+            if (given) STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_splat_given(dd, n, tot, c->stream));
+            else STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_resample_splat(dd, n, tot, ru, c->stream));
+            for (int k = 0; k < pmax; ++k)
+                STAGE(c, HB_STAGE_BOX, hb::launch_box_pass(dd, n, tot, max_w, k, c->stream));
+            STAGE(c, HB_STAGE_DENSITY_GRAD, hb::launch_density_grad(dd, n, tot, bmax, c->stream));
+            STAGE(c, HB_STAGE_ADVECT_SMOOTH, hb::launch_advect_smooth(dd, n, tot, au, c->stream));
+        }
+        return HB_OK;
+    };
+
+    if (!use_graph) return launch_all(lead->profiling);
+
+    std::vector<int64_t> key = {n, T, (int64_t)flags, (int64_t)(intptr_t)lead->d_desc, ru, au,
+                                max_w, bmax, pmax};
+    for (int g = 0; g < n; ++g) {
+        const hb_ctx *c = cs[g];
+        key.insert(key.end(), {(int64_t)(intptr_t)c, c->E, c->B, c->P.grid_w, c->P.grid_h,
+                               c->P.box_passes});
+    }
+    if (!lead->gexec || key != lead->gkey) {
+        if (lead->gexec) {
+            (void)hipGraphExecDestroy(lead->gexec);
+            lead->gexec = nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        HIPCHK(lead, hipStreamBeginCapture(lead->stream, hipStreamCaptureModeThreadLocal));
+        hb_status st = launch_all(false);
+        hipError_t e = hipStreamEndCapture(lead->stream, &graph);
+        if (st != HB_OK) return st;
+        if (e != hipSuccess) return fail_dev(lead, e, "hipStreamEndCapture");
+        e = hipGraphInstantiate(&lead->gexec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return fail_dev(lead, e, "hipGraphInstantiate");
+        lead->gkey = key;
+    }
+    HIPCHK(lead, hipGraphLaunch(lead->gexec, lead->stream));
+    return HB_OK;
+}
+
+static hb_status enqueue_run(hb_ctx *c, int T, uint32_t flags) {
+    hb_ctx *cs[1] = {c};
+    return enqueue_batch(c, cs, 1, T, flags, (flags & HB_RUN_GRAPH) != 0);
+}
+
+static const uint32_t kRunFlags =
+    HB_RUN_SAMPLES_GIVEN | HB_RUN_RECORD_DECISIONS | HB_RUN_ASYNC | HB_RUN_GRAPH;
 
 HB_API hb_status hb_run(hb_ctx *c, int32_t n_iters, uint32_t flags) {
     ENTER(c);
@@ -765,8 +937,7 @@ HB_API hb_status hb_run(hb_ctx *c, int32_t n_iters, uint32_t flags) {
     if (!c->have_params || !c->have_graph || !c->have_groups)
         return fail(c, HB_ESTATE, "hb_run needs parameters, graph and groups");
     if (n_iters < 0) return fail(c, HB_EINVAL, "n_iters must be >= 0");
-    if (flags & ~(uint32_t)(HB_RUN_SAMPLES_GIVEN | HB_RUN_RECORD_DECISIONS | HB_RUN_ASYNC))
-        return fail(c, HB_EINVAL, "unknown run flags");
+    if (flags & ~kRunFlags) return fail(c, HB_EINVAL, "unknown run flags");
     c->last_counts.clear();
     if (n_iters == 0) return HB_OK;
     if ((flags & HB_RUN_SAMPLES_GIVEN) &&
@@ -777,84 +948,15 @@ HB_API hb_status hb_run(hb_ctx *c, int32_t n_iters, uint32_t flags) {
     return finish_pending(c);
 }
 
-static hb_status enqueue_run(hb_ctx *c, int T, uint32_t flags) {
-    CHKST(ensure_maps(c));
-    CHKST(ensure_totals(c, T));
-    const bool record = (flags & HB_RUN_RECORD_DECISIONS) != 0;
-    if (record && c->jacc_cap < c->cap) {
-        CHKST(dalloc(c, &c->d_jacc, (size_t)c->cap, "decisions"));
-        c->jacc_cap = c->cap;
-    }
-    CHKST(ensure_desc(c, (size_t)T));
-    CHKST(wait_desc(c));
-    HIPCHK(c, hipMemsetAsync(c->d_totals, 0xff, sizeof(int64_t) * T, c->stream));
-
-    c->pend_ps.assign(T, 0);
-    c->pend_os.assign(T, 0);
-    int ps = c->ps, os = c->os;
-    int last_ss = 0, last_so = 0;
-    for (int it = 0; it < T; ++it) {
-        c->pend_ps[it] = ps;
-        c->pend_os[it] = os;
-        const bool given = it == 0 && (flags & HB_RUN_SAMPLES_GIVEN);
-        last_ss = given ? ps : 1 - ps;
-        last_so = given ? os : 1 - os;
-        GDesc d = base_desc(c);
-        set_iter_scalars(c, d, c->iter + it);
-        d.record = record && it == T - 1;
-        d.jacc = c->d_jacc;
-        d.total = c->d_totals + it;
-        if (given) {
-            d.samples = c->pts[ps];
-            d.off_s = c->off[os];
-            d.pnew = c->pts[1 - ps];
-            ps = 1 - ps;
-        } else {
-            d.pin = c->pts[ps];
-            d.off_in = c->off[os];
-            d.samples = c->pts[1 - ps];
-            d.off_s = c->off[1 - os];
-            d.pnew = c->pts[ps];
-            os = 1 - os;
-        }
-        c->h_desc[it] = d;
-    }
-    CHKST(upload_desc(c, (size_t)T));
-
-    const int W = c->P.grid_w, H = c->P.grid_h, B = c->B;
-    const Shape s = hb::shape_of(c->E, B, W, H);
-    for (int it = 0; it < T; ++it) {
-        const GDesc *dd = c->d_desc + it;
-        const bool given = it == 0 && (flags & HB_RUN_SAMPLES_GIVEN);
-        if (!given) STAGE(c, HB_STAGE_SCAN, hb::launch_scan(dd, 1, s, c->stream));
-        STAGE(c, HB_STAGE_CLEAR, hb::launch_clear_hist(dd, 1, s, c->stream));
-        if (given) STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_splat_given(dd, 1, s, c->stream));
-        else STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_resample_splat(dd, 1, s, c->stream));
-        for (int k = 0; k < c->P.box_passes; ++k)
-            STAGE(c, HB_STAGE_BOX, hb::launch_box_pass(dd, 1, s, W, k, c->stream));
-        STAGE(c, HB_STAGE_DENSITY_GRAD, hb::launch_density_grad(dd, 1, s, B, c->stream));
-        STAGE(c, HB_STAGE_ADVECT_SMOOTH, hb::launch_advect_smooth(dd, 1, s, c->stream));
-    }
-    c->pending = true;
-    c->pend_start = c->iter;
-    c->pend_T = T;
-    c->pend_flags = flags;
-    // bookkeeping as if the run completes; finish_pending corrects it on overflow
-    c->ss = last_ss;
-    c->so = last_so;
-    c->ps = ps;
-    c->os = os;
-    c->iter += T;
-    return HB_OK;
-}
-
 // Wait for an enqueued run; on a point-buffer overflow grow the buffers and run the
 // remaining iterations again from the last complete state.
 static hb_status finish_pending(hb_ctx *c) {
     while (c->pending) {
         c->pending = false;
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        CHKST(stage_collect(c));
+        hb_ctx *lead = c->pend_lead ? c->pend_lead : c;
+        c->pend_lead = nullptr;
+        HIPCHK(c, hipStreamSynchronize(lead->stream));
+        if (lead == c) CHKST(stage_collect(c));
         int32_t status = 0;
         HIPCHK(c, hipMemcpy(&status, c->d_status, sizeof status, hipMemcpyDeviceToHost));
         const int T = c->pend_T;
@@ -888,9 +990,9 @@ static hb_status finish_pending(hb_ctx *c) {
             return fail(c, HB_EOVERFLOW,
                         "sample count too large for int32 histograms or int64 box sums");
         CHKST(ensure_capacity(c, 2 * need + 64));
-        uint32_t flags = c->pend_flags;
+        uint32_t flags = c->pend_flags & ~(uint32_t)(HB_RUN_ASYNC | HB_RUN_GRAPH);
         if (f > 0) flags &= ~(uint32_t)HB_RUN_SAMPLES_GIVEN;
-        CHKST(enqueue_run(c, T - f, flags & ~(uint32_t)HB_RUN_ASYNC));
+        CHKST(enqueue_run(c, T - f, flags));
     }
     return HB_OK;
 }
@@ -898,6 +1000,163 @@ static hb_status finish_pending(hb_ctx *c) {
 HB_API hb_status hb_sync(hb_ctx *c) {
     ENTER(c);
     return finish_pending(c);
+}
+
+// ------------------------------------------------------------------ batches
+
+static hb_status check_batch(hb_ctx *const *ctxs, int32_t n) {
+    if (!ctxs || n < 1) return fail(nullptr, HB_EINVAL, "need at least one context");
+    if (!ctxs[0]) return fail(nullptr, HB_EINVAL, "null context");
+    for (int g = 0; g < n; ++g) {
+        hb_ctx *c = ctxs[g];
+        if (!c) return fail(ctxs[0], HB_EINVAL, "null context in batch");
+        if (c->sticky) return fail(ctxs[0], HB_EDEVICE, "a context of the batch has a sticky HIP error");
+        if (c->device != ctxs[0]->device) return fail(ctxs[0], HB_EINVAL, "contexts on different devices");
+        for (int h = 0; h < g; ++h)
+            if (ctxs[h] == c) return fail(ctxs[0], HB_EINVAL, "context listed twice");
+        if (!c->have_params || !c->have_graph || !c->have_groups)
+            return fail(ctxs[0], HB_ESTATE, "every context needs parameters, graph and groups");
+    }
+    return HB_OK;
+}
+
+HB_API hb_status hb_batch_run(hb_ctx *const *ctxs, int32_t n, int32_t n_iters, uint32_t flags) {
+    CHKST(check_batch(ctxs, n));
+    hb_ctx *lead = ctxs[0];
+    ENTER(lead);
+    if (n_iters < 0) return fail(lead, HB_EINVAL, "n_iters must be >= 0");
+    if (flags & ~(uint32_t)(HB_RUN_ASYNC | HB_RUN_GRAPH))
+        return fail(lead, HB_EINVAL, "batch runs take HB_RUN_ASYNC and HB_RUN_GRAPH only");
+    for (int g = 0; g < n; ++g) {
+        hb_status st = finish_pending(ctxs[g]);
+        if (st != HB_OK) return fail(lead, st, ctxs[g]->err);
+        HIPCHK(lead, hipStreamSynchronize(ctxs[g]->stream));
+        ctxs[g]->last_counts.clear();
+    }
+    if (n_iters == 0) return HB_OK;
+    CHKST(enqueue_batch(lead, ctxs, n, n_iters, flags, (flags & HB_RUN_GRAPH) != 0));
+    if (flags & HB_RUN_ASYNC) return HB_OK;
+    hb_status first = HB_OK;
+    for (int g = 0; g < n; ++g) {
+        hb_status st = finish_pending(ctxs[g]);
+        if (st != HB_OK && first == HB_OK) {
+            first = st;
+            lead->err = ctxs[g]->err;
+        }
+    }
+    return first;
+}
+
+// Snapshot of the polylines and counts of a context (for trial runs of the autotuner).
+struct Snapshot {
+    float2 *pts = nullptr;
+    int64_t *off = nullptr, *counts = nullptr;
+    double *lens = nullptr;
+    int64_t n = 0;
+    int ps = 0, os = 0, iter = 0;
+};
+
+static hb_status take_snapshot(hb_ctx *c, Snapshot &s) {
+    s.n = c->n_state;
+    s.ps = c->ps;
+    s.os = c->os;
+    s.iter = c->iter;
+    CHKST(dalloc(c, &s.pts, (size_t)std::max<int64_t>(1, s.n), "snapshot"));
+    CHKST(dalloc(c, &s.off, (size_t)c->E + 1, "snapshot"));
+    CHKST(dalloc(c, &s.counts, (size_t)std::max<int64_t>(1, c->E), "snapshot"));
+    CHKST(dalloc(c, &s.lens, (size_t)std::max<int64_t>(1, c->E), "snapshot"));
+    HIPCHK(c, hipMemcpyAsync(s.pts, c->pts[c->ps], sizeof(float2) * s.n, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(s.off, c->off[c->os], sizeof(int64_t) * (c->E + 1), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(s.counts, c->d_counts, sizeof(int64_t) * c->E, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(s.lens, c->d_lens, sizeof(double) * c->E, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return HB_OK;
+}
+
+static hb_status restore_snapshot(hb_ctx *c, Snapshot &s) {
+    c->ps = s.ps;
+    c->os = s.os;
+    c->iter = s.iter;
+    c->n_state = s.n;
+    c->have_samples = false;
+    c->have_jacc = false;
+    HIPCHK(c, hipMemcpyAsync(c->pts[c->ps], s.pts, sizeof(float2) * s.n, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->off[c->os], s.off, sizeof(int64_t) * (c->E + 1), hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_counts, s.counts, sizeof(int64_t) * c->E, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_lens, s.lens, sizeof(double) * c->E, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    dfree(&s.pts);
+    dfree(&s.off);
+    dfree(&s.counts);
+    dfree(&s.lens);
+    return HB_OK;
+}
+
+HB_API hb_status hb_autotune(hb_ctx *const *ctxs, int32_t n, int32_t n_iters, int32_t *choice) {
+    CHKST(check_batch(ctxs, n));
+    hb_ctx *lead = ctxs[0];
+    ENTER(lead);
+    if (n_iters < 1) return fail(lead, HB_EINVAL, "n_iters must be >= 1");
+    for (int g = 0; g < n; ++g) CHKST(finish_pending(ctxs[g]));
+    static const int cand[][2] = {{1, 1}, {1, 2}, {2, 2}, {1, 4}, {2, 4}, {4, 4}};
+    const int ncand = (int)(sizeof cand / sizeof cand[0]);
+    hipEvent_t e0, e1;
+    HIPCHK(lead, hipEventCreate(&e0));
+    HIPCHK(lead, hipEventCreate(&e1));
+    float best = 0.0f;
+    int bi = -1;
+    const bool prof = lead->profiling;
+    lead->profiling = false;
+    hb_status st = HB_OK;
+    for (int i = 0; i < ncand && st == HB_OK; ++i) {
+        std::vector<Snapshot> snap((size_t)n);
+        for (int g = 0; g < n && st == HB_OK; ++g) st = take_snapshot(ctxs[g], snap[g]);
+        if (st != HB_OK) break;
+        lead->tune_ru = cand[i][0];
+        lead->tune_au = cand[i][1];
+        if (hipEventRecord(e0, lead->stream) != hipSuccess) st = fail_dev(lead, hipGetLastError(), "event");
+        if (st == HB_OK) st = enqueue_batch(lead, ctxs, n, n_iters, 0, false);
+        if (st == HB_OK && hipEventRecord(e1, lead->stream) != hipSuccess) st = fail_dev(lead, hipGetLastError(), "event");
+        for (int g = 0; g < n && st == HB_OK; ++g) st = finish_pending(ctxs[g]);
+        float ms = 0.0f;
+        if (st == HB_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = fail_dev(lead, hipGetLastError(), "event");
+        for (int g = 0; g < n && st == HB_OK; ++g) st = restore_snapshot(ctxs[g], snap[g]);
+        if (st == HB_OK && (bi < 0 || ms < best)) {
+            best = ms;
+            bi = i;
+        }
+    }
+    lead->profiling = prof;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != HB_OK) return st;
+    for (int g = 0; g < n; ++g) {
+        ctxs[g]->tune_ru = cand[bi][0];
+        ctxs[g]->tune_au = cand[bi][1];
+        ctxs[g]->last_counts.clear();
+    }
+    if (choice) {
+        choice[0] = cand[bi][0];
+        choice[1] = cand[bi][1];
+    }
+    return HB_OK;
+}
+
+HB_API hb_status hb_set_tuning(hb_ctx *c, int32_t resample_chunks, int32_t advect_chunks) {
+    ENTER(c);
+    auto ok = [](int v) { return v == 1 || v == 2 || v == 4; };
+    if (!ok(resample_chunks) || !ok(advect_chunks)) return fail(c, HB_EINVAL, "chunk counts are 1, 2 or 4");
+    c->tune_ru = resample_chunks;
+    c->tune_au = advect_chunks;
+    return HB_OK;
+}
+
+HB_API hb_status hb_get_tuning(hb_ctx *c, int32_t *resample_chunks, int32_t *advect_chunks) {
+    ENTER(c);
+    if (!resample_chunks || !advect_chunks) return fail(c, HB_EINVAL, "null output");
+    *resample_chunks = c->tune_ru;
+    *advect_chunks = c->tune_au;
+    return HB_OK;
 }
 
 // ------------------------------------------------------------------ data movement
