@@ -208,6 +208,34 @@ hb_status hb_autotune(hb_ctx *const *ctxs, int32_t n, int32_t n_iters, int32_t *
 hb_status hb_set_tuning(hb_ctx *ctx, int32_t resample_chunks, int32_t advect_chunks);
 hb_status hb_get_tuning(hb_ctx *ctx, int32_t *resample_chunks, int32_t *advect_chunks);
 
+/*
+ * Differentiable form. With the discrete choices of a forward run held fixed (sample counts
+ * and interpolation segments of every resampling, the histograms -- so the integer box sums
+ * are constants -- and the accepted halving of every point), T iterations of Section 3 are a
+ * piecewise smooth function of the polylines that entered them, of the interaction matrix M
+ * (Eq. 3-4) and of the pass weights a of the density. hb_backward applies the transpose of
+ * its Jacobian to the gradient of the loss L = total length of the final polylines ("ink").
+ *
+ * hb_forward_ckpt runs n_iters iterations like hb_run and keeps, for every iteration, the
+ * polylines entering it (with their lengths and next sample counts) on the device; it needs
+ * B <= 16. Any later call that changes the polylines, the parameters, the groups or the
+ * iteration counter discards the checkpoints.
+ */
+hb_status hb_forward_ckpt(hb_ctx *ctx, int32_t n_iters, uint32_t flags);
+
+/* After hb_forward_ckpt: loss (may be NULL) = L; dL_dM[B*B] (row-major, may be NULL);
+ * dL_da[P] (may be NULL); dL_dxy0[N0][2] (may be NULL) = gradient with respect to the
+ * points of the polylines that entered the checkpointed run (N0 of them, same layout as
+ * hb_get_points; cap_points is the capacity of dL_dxy0 in points). Each iteration is
+ * recomputed from its checkpoint; all reductions run in a fixed order (bit-reproducible).
+ * flags: HB_DEVICE_PTRS for dL_dxy0 only. */
+hb_status hb_backward(hb_ctx *ctx, double *loss, float *dL_dM, float *dL_da, float *dL_dxy0,
+                      int64_t cap_points, uint32_t flags);
+
+/* Polylines that entered checkpointed iteration t (0 = the start of the run). */
+hb_status hb_get_ckpt_points(hb_ctx *ctx, int32_t t, int64_t *offsets, float *xy,
+                             int64_t cap_points, uint32_t flags);
+
 /* Stages of one iteration, for hb_get_stage_times. */
 enum {
     HB_STAGE_SCAN = 0,            /* sample-count scan -> offsets */

@@ -54,7 +54,9 @@ def lib():
             "orc_polyline_length": (f64, [P, i64]),
             "orc_sample_count": (i64, [f64, f64]),
             "orc_resample_counts": (i64, [i64, P, P, f64, P, P]),
-            "orc_resample": (None, [i64, P, P, P, P, P]),
+            "orc_resample": (None, [i64, P, P, P, P, P, P]),
+            "orc_resample_frozen": (None, [i64, P, P, P, P, P]),
+            "orc_advect_frozen": (None, [i64, P, P, P, i32, i32, P, f64, P, f64, P]),
             "orc_splat": (None, [i64, P, P, P, P, i32, i32, i32, P]),
             "orc_box_brute": (None, [i32, i32, P, i32, P]),
             "orc_integral_image": (None, [i32, i32, P, P]),
@@ -160,8 +162,9 @@ def sample_count(L: float, delta: float) -> int:
     return int(lib().orc_sample_count(L, delta))
 
 
-def resample(off, xy, delta):
-    """Uniform-arclength resampling of every polyline; returns (off_out, xy_out, lens)."""
+def resample(off, xy, delta, want_seg=False):
+    """Uniform-arclength resampling of every polyline; returns (off_out, xy_out, lens) and,
+    with want_seg, the segment index of every sample (-1 at end points)."""
     off = _c(off, np.int64)
     xy = _c(xy, np.float64)
     E = off.shape[0] - 1
@@ -172,7 +175,10 @@ def resample(off, xy, delta):
     np.cumsum(counts, out=off_out[1:])
     assert off_out[-1] == N
     xy_out = np.empty((N, 2), np.float64)
-    lib().orc_resample(E, _p(off), _p(xy), _p(off_out), _p(lens), _p(xy_out))
+    seg = np.empty(N, np.int64) if want_seg else None
+    lib().orc_resample(E, _p(off), _p(xy), _p(off_out), _p(lens), _p(xy_out), _p(seg))
+    if want_seg:
+        return off_out, xy_out, lens, seg
     return off_out, xy_out, lens
 
 
@@ -315,3 +321,65 @@ def run(node_xy, src, dst, group, M, p: Params, n_iters: int, weight=None):
         off, xy = res["off"], res["xy"]
         counts.append(int(off[-1]))
     return off, xy, counts
+
+
+# ----------------------------------------------------------------------- frozen surrogate
+
+def record_run(off, xy, group, M, p: Params, n_iters: int, it0: int = 0, weight=None):
+    """Base run from the polylines (off, xy): per iteration, the discrete choices that the
+    frozen surrogate replays (sample offsets, segment indices, histograms, decisions)."""
+    rec = []
+    off = _c(off, np.int64)
+    xy = _c(xy, np.float64)
+    B = int(np.asarray(M).shape[0])
+    for t in range(n_iters):
+        it = it0 + t
+        s_off, s_xy, _, seg = resample(off, xy, p.delta, want_seg=True)
+        hist = splat(s_off, s_xy, group, B, p.grid_w, p.grid_h, weight)
+        r = p.radius(it)
+        S = box_chain(hist, p.passes, r)
+        g = gradient(density(S, r, p.a(), M))
+        adv = advect(s_off, s_xy, group, density(S, r, p.a(), M), g, p.bandwidth(it),
+                     p.max_halvings, p.eps, p.amb_tol)
+        rec.append({"in_off": off, "s_off": s_off, "seg": seg, "S": S, "jacc": adv["jacc"],
+                    "jfirm": adv["jfirm"], "amb": adv["amb"], "h": p.bandwidth(it), "r": r})
+        off, xy = s_off, laplacian(s_off, adv["xy"], p.smooth_weight, p.smooth_passes)
+    return rec, off, xy
+
+
+def frozen_loss(xy0, M, a, rec, group, p: Params):
+    """Ink of the polylines after the recorded iterations, replayed with the frozen choices,
+    as a function of the starting positions xy0, the interaction matrix M and the pass
+    weights a (all FP64)."""
+    xy = _c(xy0, np.float64)
+    group = _c(group, np.int32)
+    a = _c(a, np.float64)
+    M = _c(M, np.float64)
+    for r in rec:
+        in_off, s_off, seg = r["in_off"], r["s_off"], r["seg"]
+        E = in_off.shape[0] - 1
+        sx = np.empty((s_off[-1], 2), np.float64)
+        lib().orc_resample_frozen(E, _p(in_off), _p(xy), _p(s_off), _p(seg), _p(sx))
+        g = gradient(density(r["S"], r["r"], a, M))
+        B, H, W, _ = g.shape
+        ax = np.empty_like(sx)
+        jacc = _c(r["jacc"], np.int32)
+        lib().orc_advect_frozen(E, _p(s_off), _p(sx), _p(group), W, H, _p(g), r["h"], _p(jacc),
+                                p.eps, _p(ax))
+        xy = laplacian(s_off, ax, p.smooth_weight, p.smooth_passes)
+    return ink(rec[-1]["s_off"], xy)
+
+
+def frozen_fd(xy0, M, a, rec, group, p: Params, which: str, index, step: float):
+    """Central finite difference of frozen_loss in one parameter: which is "M" (index (l, b)),
+    "a" (index k) or "x" (index (point, coordinate))."""
+    def f(delta):
+        x, m, aa = np.array(xy0, np.float64), np.array(M, np.float64), np.array(a, np.float64)
+        if which == "M":
+            m[index] += delta
+        elif which == "a":
+            aa[index] += delta
+        else:
+            x[index] += delta
+        return frozen_loss(x, m, aa, rec, group, p)
+    return (f(step) - f(-step)) / (2.0 * step)

@@ -28,6 +28,9 @@
 
 #define EXPORT __attribute__((visibility("default")))
 
+EXPORT double orc_bilinear(int32_t W, int32_t H, const double *map, int32_t stride, int32_t comp,
+                           double x, double y);
+
 /* ------------------------------------------------------------------ threads */
 
 EXPORT int orc_num_threads(void) {
@@ -104,9 +107,12 @@ EXPORT int64_t orc_resample_counts(int64_t E, const int64_t *off, const double *
     return total;
 }
 
-/* Resample every polyline into off_out/xy_out; lens[] are the lengths from above. */
+/* Resample every polyline into off_out/xy_out; lens[] are the lengths from above. seg (may
+ * be NULL) receives, for every sample, the index within its edge of the segment it was
+ * interpolated on (-1 for the two end points). */
 EXPORT void orc_resample(int64_t E, const int64_t *off_in, const double *xy_in,
-                         const int64_t *off_out, const double *lens, double *xy_out) {
+                         const int64_t *off_out, const double *lens, double *xy_out,
+                         int64_t *seg) {
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t e = 0; e < E; ++e) {
         const double *p = xy_in + 2 * off_in[e];
@@ -118,6 +124,10 @@ EXPORT void orc_resample(int64_t E, const int64_t *off_in, const double *xy_in,
         o[1] = p[1];
         o[2 * (n - 1)] = p[2 * (m - 1)];
         o[2 * (n - 1) + 1] = p[2 * (m - 1) + 1];
+        if (seg) {
+            seg[off_out[e]] = -1;
+            seg[off_out[e] + n - 1] = -1;
+        }
         int64_t j = 0;          /* current segment (p_j, p_j+1) */
         double C = 0.0;         /* arclength at p_j */
         double ell = hypot(p[2] - p[0], p[3] - p[1]);
@@ -134,6 +144,73 @@ EXPORT void orc_resample(int64_t E, const int64_t *off_in, const double *xy_in,
             if (t > 1.0) t = 1.0;
             o[2 * k] = p[2 * j] + t * (p[2 * (j + 1)] - p[2 * j]);
             o[2 * k + 1] = p[2 * j + 1] + t * (p[2 * (j + 1) + 1] - p[2 * j + 1]);
+            if (seg) seg[off_out[e] + k] = j;
+        }
+    }
+}
+
+/* ------------------------------------------------ frozen-decision surrogate (for gradients)
+ * Holding the discrete choices of a base run fixed (sample counts, the segment each sample
+ * is interpolated on, the histograms, the accepted halving of every point) makes one
+ * iteration a piecewise smooth function of the positions, the interaction matrix and the
+ * pass weights; its derivatives are what the adjoint computes.
+ *
+ * Resampling with frozen counts (off_out) and segment indices (seg): the arclengths are
+ * recomputed from the current positions; t is clamped to [0, 1] as in orc_resample.
+ */
+EXPORT void orc_resample_frozen(int64_t E, const int64_t *off_in, const double *xy_in,
+                                const int64_t *off_out, const int64_t *seg, double *xy_out) {
+    for (int64_t e = 0; e < E; ++e) {
+        const double *p = xy_in + 2 * off_in[e];
+        int64_t m = off_in[e + 1] - off_in[e];
+        double *o = xy_out + 2 * off_out[e];
+        int64_t n = off_out[e + 1] - off_out[e];
+        double L = orc_polyline_length(p, m);
+        o[0] = p[0];
+        o[1] = p[1];
+        o[2 * (n - 1)] = p[2 * (m - 1)];
+        o[2 * (n - 1) + 1] = p[2 * (m - 1) + 1];
+        for (int64_t k = 1; k + 1 < n; ++k) {
+            int64_t j = seg[off_out[e] + k];
+            double C = orc_polyline_length(p, j + 1);     /* arclength at p_j */
+            double ell = hypot(p[2 * (j + 1)] - p[2 * j], p[2 * (j + 1) + 1] - p[2 * j + 1]);
+            double s = (double)k * L / (double)(n - 1);
+            double t = ell > 0.0 ? (s - C) / ell : 0.0;
+            if (t < 0.0) t = 0.0;
+            if (t > 1.0) t = 1.0;
+            o[2 * k] = p[2 * j] + t * (p[2 * (j + 1)] - p[2 * j]);
+            o[2 * k + 1] = p[2 * j + 1] + t * (p[2 * (j + 1) + 1] - p[2 * j + 1]);
+        }
+    }
+}
+
+/* Advection with frozen accepted halvings jacc (-1: no move, -2: end point): the direction
+ * is recomputed from the current maps and position (Eq. 5), the step is h / 2^jacc, and the
+ * result is clamped like orc_advect. */
+EXPORT void orc_advect_frozen(int64_t E, const int64_t *off, const double *xy, const int32_t *group,
+                              int32_t W, int32_t H, const double *grad, double h,
+                              const int32_t *jacc, double eps, double *xy_out) {
+    int64_t plane = (int64_t)W * H;
+    double xmax = (double)W - 1.0 / 256.0, ymax = (double)H - 1.0 / 256.0;
+    for (int64_t e = 0; e < E; ++e) {
+        const double *gl = grad + (int64_t)group[e] * plane * 2;
+        for (int64_t i = off[e]; i < off[e + 1]; ++i) {
+            double x = xy[2 * i], y = xy[2 * i + 1];
+            xy_out[2 * i] = x;
+            xy_out[2 * i + 1] = y;
+            if (jacc[i] < 0) continue;
+            double gx = orc_bilinear(W, H, gl, 2, 0, x, y);
+            double gy = orc_bilinear(W, H, gl, 2, 1, x, y);
+            double nrm = sqrt(gx * gx + gy * gy);
+            double den = nrm > eps ? nrm : eps;
+            double m = ldexp(h, -jacc[i]);
+            double cx = x + m * gx / den, cy = y + m * gy / den;
+            if (cx < 0.0) cx = 0.0;
+            if (cx > xmax) cx = xmax;
+            if (cy < 0.0) cy = 0.0;
+            if (cy > ymax) cy = ymax;
+            xy_out[2 * i] = cx;
+            xy_out[2 * i + 1] = cy;
         }
     }
 }

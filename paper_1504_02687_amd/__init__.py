@@ -86,6 +86,11 @@ _SIGS = {
     "hb_version": (ctypes.c_char_p, []),
     "hb_set_profiling": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "hb_batch_run": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32]),
+    "hb_forward_ckpt": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32]),
+    "hb_backward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32]),
+    "hb_get_ckpt_points": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                            ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32]),
     "hb_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
     "hb_set_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
     "hb_get_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
@@ -451,3 +456,72 @@ def batch_run(bundlers, n_iters: int, flags: int = 0) -> None:
 
 def autotune(bundlers, n_iters: int = 1):
     return hb_autotune([b.ctx for b in bundlers], n_iters)
+
+
+# ------------------------------------------------------------------ differentiable form
+
+def hb_forward_ckpt(ctx, n_iters: int) -> None:
+    _check(ctx, load().hb_forward_ckpt(ctx, n_iters, 0))
+
+
+def hb_backward(ctx, n_groups: int, n_passes: int, n_points0: int):
+    """(loss, dL/dM [B, B], dL/da [P], dL/dxy0 [N0, 2]) as numpy arrays."""
+    loss = ctypes.c_double()
+    dM = np.zeros((n_groups, n_groups), np.float32)
+    da = np.zeros(n_passes, np.float32)
+    dx = np.zeros((n_points0, 2), np.float32)
+    _check(ctx, load().hb_backward(ctx, ctypes.byref(loss), dM.ctypes.data, da.ctypes.data,
+                                   dx.ctypes.data, n_points0, 0))
+    return float(loss.value), dM, da, dx
+
+
+def hb_get_ckpt_points(ctx, t: int, n_edges: int, n_points: int):
+    off = np.empty(n_edges + 1, np.int64)
+    xy = np.empty((n_points, 2), np.float32)
+    _check(ctx, load().hb_get_ckpt_points(ctx, t, off.ctypes.data, xy.ctypes.data, n_points, 0))
+    return off, xy
+
+
+def _bundle_function():
+    import torch
+
+    class BundleFn(torch.autograd.Function):
+        """Ink after ``n_iters`` bundling iterations as a differentiable function of the
+        polylines ``xy0`` (N0 x 2, layout ``offsets``), the interaction matrix ``M`` (B x B) and
+        the pass weights ``a`` (P), with the discrete choices of the forward run held fixed.
+        ``bundler`` must already hold the graph, groups and parameters; the forward pass sets
+        M, a and the polylines, runs with per-iteration checkpoints, and the backward pass
+        calls the hand-written adjoint."""
+
+        @staticmethod
+        def forward(ctx, xy0, M, a, bundler, offsets, group, n_iters, params):
+            bundler.set_params(**params, pass_weights=[float(v) for v in a.detach().cpu()])
+            bundler.set_groups(group, M.detach().cpu().numpy())
+            bundler.set_points(offsets, xy0.detach().cpu().numpy())
+            hb_forward_ckpt(bundler.ctx, n_iters)
+            ctx.bundler = bundler
+            ctx.shapes = (M.shape[0], a.shape[0], xy0.shape[0])
+            ctx.devs = (xy0.device, M.device, a.device)
+            return torch.tensor(hb_get_ink(bundler.ctx), dtype=torch.float64, device=xy0.device)
+
+        @staticmethod
+        def backward(ctx, g):
+            _, dM, da, dx = hb_backward(ctx.bundler.ctx, *ctx.shapes)
+            gv = float(g)
+            return (torch.from_numpy(dx).to(ctx.devs[0]) * gv,
+                    torch.from_numpy(dM).to(ctx.devs[1]) * gv,
+                    torch.from_numpy(da).to(ctx.devs[2]) * gv,
+                    None, None, None, None, None)
+
+    return BundleFn
+
+
+_BUNDLE_FN = None
+
+
+def bundle_ink(xy0, M, a, bundler, offsets, group, n_iters, params):
+    """torch entry point of the differentiable form (see BundleFn)."""
+    global _BUNDLE_FN
+    if _BUNDLE_FN is None:
+        _BUNDLE_FN = _bundle_function()
+    return _BUNDLE_FN.apply(xy0, M, a, bundler, offsets, group, n_iters, params)

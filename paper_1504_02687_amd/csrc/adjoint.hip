@@ -1,0 +1,434 @@
+// Adjoint of one bundling iteration with the discrete choices of the forward run held
+// fixed: the sample counts and the segment each sample is interpolated on (resampling), the
+// histograms (so the int64 box sums are constants), and the accepted halving of every point
+// (advection). With those frozen the iteration is a piecewise smooth function of the point
+// positions, of the interaction matrix M and of the pass weights a (density of Section 3.2
+// Eq. 3, advection of Section 3.3 Eq. 5, Laplacian smoothing of Section 3.3); these kernels
+// apply its transposed Jacobian.
+//
+// The density gradient seen by a point of layer l is
+//   g_l(x) = bilinear( sum_b M[l][b] sum_k a_k G_bk , x ),  G_bk = grad(S_b^k) / (2r+1)^(2k),
+// so dL/dM and dL/da follow from gathering the maps G_bk at every moved point; nothing is
+// scattered into map adjoints and every reduction runs in a fixed order (the results are
+// reproducible bit for bit).
+#include <hip/hip_runtime.h>
+
+#include "device_common.h"
+
+namespace hb {
+
+// dL/dp of L = total polyline length: p_bar_j = u_(j-1) - u_j with u the unit vectors of the
+// adjacent segments (zero for zero-length segments). One wave per edge over (pin, off_in).
+__global__ __launch_bounds__(kBlock) void k_ink_grad(const GDesc *__restrict__ gd, int ng) {
+    const int64_t blk = blockIdx.x;
+    HB_FIND(blk_edge);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t e = (blk - d.blk_edge) * kWavesPerBlock + wid;
+    if (e >= d.n_edges) return;
+    const int64_t i0 = d.off_in[e], m = d.off_in[e + 1] - i0;
+    const float2 *p = d.pin + i0;
+    float2 *out = d.adj_out + i0;
+    for (int64_t j = lane; j < m; j += 64) {
+        const float2 c = p[j];
+        double gx = 0.0, gy = 0.0;
+        if (j > 0) {
+            const float2 a = p[j - 1];
+            const double dx = (double)c.x - a.x, dy = (double)c.y - a.y;
+            const double l = sqrt(dx * dx + dy * dy);
+            if (l > 0.0) {
+                gx += dx / l;
+                gy += dy / l;
+            }
+        }
+        if (j + 1 < m) {
+            const float2 b = p[j + 1];
+            const double dx = (double)b.x - c.x, dy = (double)b.y - c.y;
+            const double l = sqrt(dx * dx + dy * dy);
+            if (l > 0.0) {
+                gx -= dx / l;
+                gy -= dy / l;
+            }
+        }
+        out[j] = make_float2((float)gx, (float)gy);
+    }
+}
+
+// G_bk = 1/2 (S_b^k(u+1) - S_b^k(u-1), S_b^k(v+1) - S_b^k(v-1)) / (2r+1)^(2k), from exact
+// int64 differences (zero outside the grid). One thread per (group, pixel).
+__global__ __launch_bounds__(kBlock) void k_adj_maps(const GDesc *__restrict__ gd, int ng) {
+    const int64_t blk = blockIdx.x;
+    HB_FIND(blk_pxb);
+    const int W = d.W, H = d.H, B = d.B, P = d.P;
+    const int64_t plane = (int64_t)W * H;
+    const int64_t i = (blk - d.blk_pxb) * kBlock + threadIdx.x;
+    if (i >= (int64_t)B * plane) return;
+    const int64_t b = i / plane, px = i % plane;
+    const int u = (int)(px % W), v = (int)(px / W);
+    for (int k = 0; k < P; ++k) {
+        const int64_t *S = d.box + ((int64_t)k * B + b) * plane + px;
+        const int64_t xr = u + 1 < W ? S[1] : 0, xl = u > 0 ? S[-1] : 0;
+        const int64_t yu = v + 1 < H ? S[W] : 0, yd = v > 0 ? S[-W] : 0;
+        d.gsk[(b * P + k) * plane + px] = make_float2((float)(0.5 * ((double)(xr - xl) / d.ck[k])),
+                                                      (float)(0.5 * ((double)(yu - yd) / d.ck[k])));
+    }
+}
+
+// Transposed Laplacian smoothing and advection, fused. One wave per edge, chunks of 62
+// points with a one-point halo (like the forward): with y_bar the adjoint of the smoothed
+// points (adj_in), lane l computes the adjoint x'_bar of the advected point j from y_bar of
+// j-1, j, j+1, then the adjoint of the sample x_bar = w + m (dg/dx)^T v, where w is x'_bar
+// without the clamped coordinates, v = (dd/dg)^T w with d = g / max(|g|, eps), and m the
+// frozen step h / 2^j. The same v gives the point's contribution m v . dg/dM and m v . dg/da.
+template <int BMAX>
+__global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__ gd, int ng) {
+    const int64_t blk = blockIdx.x;
+    HB_FIND(blk_edge);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t e = (blk - d.blk_edge) * kWavesPerBlock + wid;
+    if (e >= d.n_edges) return;
+
+    const int W = d.W, H = d.H, B = d.B, P = d.P;
+    const int64_t plane = (int64_t)W * H;
+    const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
+    const int l = d.group[e];
+    const float2 *__restrict__ grad = d.grad + (int64_t)l * plane;
+    const float2 *__restrict__ xs = d.samples + o0;
+    const float2 *__restrict__ yb = d.adj_in + o0;
+    float2 *__restrict__ xb = d.adj_out + o0;
+    const int8_t *__restrict__ jv = d.jacc + o0;
+    const double h = d.h, s = d.s, eps = d.eps;
+    const double xmax = (double)W - 1.0 / 256.0, ymax = (double)H - 1.0 / 256.0;
+
+    double accM[BMAX], accA[HB_MAX_PASSES];
+#pragma unroll
+    for (int b = 0; b < BMAX; ++b) accM[b] = 0.0;
+#pragma unroll
+    for (int k = 0; k < HB_MAX_PASSES; ++k) accA[k] = 0.0;
+
+    for (int64_t j0 = 0; j0 < n; j0 += 62) {
+        const int64_t j = j0 - 1 + lane;
+        const bool inr = j >= 0 && j < n;
+        const bool interior = inr && j > 0 && j < n - 1;
+        float2 ybar = make_float2(0.0f, 0.0f);
+        if (inr) ybar = yb[j];
+        const double qx = interior ? (double)ybar.x : 0.0, qy = interior ? (double)ybar.y : 0.0;
+        const double qlx = __shfl_up(qx, 1, 64), qly = __shfl_up(qy, 1, 64);
+        const double qrx = __shfl_down(qx, 1, 64), qry = __shfl_down(qy, 1, 64);
+        if (!(lane >= 1 && lane <= 62 && j < n)) continue;
+        const double cf = interior ? 1.0 - s : 1.0;
+        double wx = cf * (double)ybar.x + 0.5 * s * (qlx + qrx);
+        double wy = cf * (double)ybar.y + 0.5 * s * (qly + qry);
+        double gxb = wx, gyb = wy;
+        const int jj = interior ? (int)jv[j] : -2;
+        if (jj >= 0) {
+            const float2 x = xs[j];
+            const Bilin t0 = bilin_taps((double)x.x, (double)x.y, W, H);
+            double gx, gy;
+            bilin2(grad, t0, gx, gy);
+            const double nrm = sqrt(gx * gx + gy * gy);
+            const bool big = nrm > eps;
+            const double den = big ? nrm : eps;
+            const double dx = gx / den, dy = gy / den;
+            const double m = ldexp(h, -jj);
+            const double cx = (double)x.x + m * dx, cy = (double)x.y + m * dy;
+            if (cx < 0.0 || cx > xmax) wx = 0.0;
+            if (cy < 0.0 || cy > ymax) wy = 0.0;
+            double vx, vy;
+            if (big) {
+                const double dw = dx * wx + dy * wy;
+                vx = (wx - dx * dw) / nrm;
+                vy = (wy - dy * dw) / nrm;
+            } else {
+                vx = wx / eps;
+                vy = wy / eps;
+            }
+            const float2 g00 = grad[t0.i00], g10 = grad[t0.i10], g01 = grad[t0.i01], g11 = grad[t0.i11];
+            const double v00 = g00.x * vx + g00.y * vy, v10 = g10.x * vx + g10.y * vy;
+            const double v01 = g01.x * vx + g01.y * vy, v11 = g11.x * vx + g11.y * vy;
+            const double tx = t0.tx, ty = t0.ty;
+            gxb = wx + m * ((1.0 - ty) * (v10 - v00) + ty * (v11 - v01));
+            gyb = wy + m * ((1.0 - tx) * (v01 - v00) + tx * (v11 - v10));
+            const double mvx = m * vx, mvy = m * vy;
+#pragma unroll
+            for (int b = 0; b < BMAX; ++b) {
+                if (b >= B) break;
+                const double Mlb = (double)d.M[l * B + b];
+                for (int k = 0; k < P; ++k) {
+                    double sx, sy;
+                    bilin2(d.gsk + ((int64_t)b * P + k) * plane, t0, sx, sy);
+                    const double q = mvx * sx + mvy * sy;
+                    accM[b] += d.a[k] * q;
+                    accA[k] += Mlb * q;
+                }
+            }
+        }
+        xb[j] = make_float2((float)gxb, (float)gyb);
+    }
+    double *out = d.partials + e * (int64_t)(B + P);
+#pragma unroll
+    for (int b = 0; b < BMAX; ++b) {
+        if (b >= B) break;
+        const double v = wave_sum(accM[b]);
+        if (lane == 0) out[b] = v;
+    }
+    for (int k = 0; k < P; ++k) {
+        const double v = wave_sum(accA[k]);
+        if (lane == 0) out[B + k] = v;
+    }
+}
+
+// Transposed resampling. Sample k of an edge is x_k = p_j + t (p_(j+1) - p_j) with
+// t = (k L/(n-1) - C_j) / l_j, C_j the arclength at p_j, l_j the segment length and L the
+// polyline length; the end points are copies. One wave per edge, two passes:
+//  A) chunks of 64 segments as in the forward; the samples of a chunk add (1-t) x_bar and
+//     t x_bar to the segment's end points and -t_bar/l, -t_bar t/l to C_bar_j and l_bar_j
+//     (segmented scans over the lanes, in a fixed order); each point's adjoint is written
+//     from its two segments, with everything except the terms proportional to L_bar and
+//     to the total of C_bar, which are only known at the end of the edge;
+//  B) add (L_bar + sum_j C_bar_j)(u_(i-1) - u_i) to every point (u: unit segment vectors).
+// Point i is always handled by lane i mod 64, so pass B re-reads only its own writes.
+__global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict__ gd, int ng) {
+    const int64_t blk = blockIdx.x;
+    HB_FIND(blk_edge);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t e = (blk - d.blk_edge) * kWavesPerBlock + wid;
+    if (e >= d.n_edges) return;
+
+    __shared__ double sC[kWavesPerBlock][64];
+    __shared__ double sR[kWavesPerBlock][64];
+    __shared__ float2 sP[kWavesPerBlock][65];
+    __shared__ double acc[kWavesPerBlock][6][64];
+
+    const int64_t i0 = d.off_in[e], m = d.off_in[e + 1] - i0;
+    const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
+    const double L = d.lens[e];
+    const float2 *p = d.pin + i0;
+    const float2 *xb = d.adj_in + o0;
+    float2 *pb = d.adj_out + i0;
+    const double nm1 = (double)(n - 1);
+    const double ds = L / nm1;
+
+    double Cbase = 0.0, Lbar = 0.0, carryP = 0.0;
+    double carryBx = 0.0, carryBy = 0.0, carryVx = 0.0, carryVy = 0.0;
+    int64_t knext = 0;
+    for (int64_t j0 = 0; j0 < m - 1; j0 += 64) {
+        const int64_t rem = m - 1 - j0;
+        const int nseg = (int)(rem < 64 ? rem : 64);
+        float2 a = make_float2(0.0f, 0.0f);
+        if (lane <= nseg && lane < 64) a = p[j0 + lane];
+        float2 b;
+        b.x = __shfl_down(a.x, 1, 64);
+        b.y = __shfl_down(a.y, 1, 64);
+        if (lane == 63 && nseg == 64) b = p[j0 + 64];
+        const double ell = lane < nseg ? seg_len(a, b) : 0.0;
+        const double incl = wave_incl_scan<double>(ell, lane);
+        double excl = __shfl_up(incl, 1, 64);
+        if (lane == 0) excl = 0.0;
+        if (lane < nseg) {
+            sC[wid][lane] = Cbase + excl;
+            sR[wid][lane] = ell > 0.0 ? 1.0 / ell : 0.0;
+            sP[wid][lane] = a;
+            for (int c = 0; c < 6; ++c) acc[wid][c][lane] = 0.0;
+        }
+        if (lane == nseg - 1) sP[wid][nseg] = b;
+        const double Cend = Cbase + __shfl(incl, 63, 64);
+        __builtin_amdgcn_wave_barrier();
+
+        const bool last = (j0 + 64 >= m - 1);
+        int64_t kend;
+        if (last) {
+            kend = n;
+        } else if (!(L > 0.0)) {
+            kend = knext;
+        } else {
+            double kf = ceil(Cend / ds);
+            int64_t kk = kf < (double)knext ? knext : (kf > nm1 ? n - 1 : (int64_t)kf);
+            while (kk > knext && (double)(kk - 1) * ds >= Cend) --kk;
+            while (kk < n - 1 && (double)kk * ds < Cend) ++kk;
+            kend = kk;
+        }
+        if (j0 == 0 && kend < 1) kend = 1;   // the first end point belongs to point 0
+        for (int64_t kb = knext; kb < kend; kb += 64) {
+            const int64_t k = kb + lane;
+            const bool valid = k < kend;
+            int jl = 64 + lane;   // distinct keys for idle lanes
+            double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            if (valid) {
+                const float2 xv = xb[k];
+                double t = 0.0, tb = 0.0;
+                if (k == 0) {
+                    jl = 0;
+                } else if (k == n - 1) {
+                    jl = nseg - 1;
+                    t = 1.0;
+                } else {
+                    const double sk = __dmul_rn((double)k, ds);
+                    int lo = 0, hi = nseg - 1;
+                    while (lo < hi) {
+                        int mid = (lo + hi + 1) >> 1;
+                        if (sC[wid][mid] <= sk) lo = mid; else hi = mid - 1;
+                    }
+                    jl = lo;
+                    const double traw = __dmul_rn(__dsub_rn(sk, sC[wid][lo]), sR[wid][lo]);
+                    t = fmin(fmax(traw, 0.0), 1.0);
+                    if (traw > 0.0 && traw < 1.0 && sR[wid][lo] > 0.0) {
+                        const float2 pa = sP[wid][lo], pz = sP[wid][lo + 1];
+                        tb = xv.x * ((double)pz.x - pa.x) + xv.y * ((double)pz.y - pa.y);
+                        Lbar += tb * sR[wid][lo] * ((double)k / nm1);
+                    }
+                }
+                v[0] = (1.0 - t) * xv.x;
+                v[1] = (1.0 - t) * xv.y;
+                v[2] = t * xv.x;
+                v[3] = t * xv.y;
+                v[4] = -tb * sR[wid][jl];
+                v[5] = -tb * t * sR[wid][jl];
+            }
+            // segmented inclusive scan over runs of equal segment index
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int ko = __shfl_up(jl, o, 64);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    const double vo = __shfl_up(v[c], o, 64);
+                    if (lane >= o && ko == jl) v[c] += vo;
+                }
+            }
+            const int knx = __shfl_down(jl, 1, 64);
+            if (valid && (lane == 63 || knx != jl))
+                for (int c = 0; c < 6; ++c) acc[wid][c][jl] += v[c];
+            __builtin_amdgcn_wave_barrier();
+        }
+        // point adjoints of this chunk (all but the L_bar and sum C_bar terms)
+        double Ax = 0.0, Ay = 0.0, Bx = 0.0, By = 0.0, Cb = 0.0, lb = 0.0, ux = 0.0, uy = 0.0;
+        if (lane < nseg) {
+            Ax = acc[wid][0][lane];
+            Ay = acc[wid][1][lane];
+            Bx = acc[wid][2][lane];
+            By = acc[wid][3][lane];
+            Cb = acc[wid][4][lane];
+            lb = acc[wid][5][lane];
+            const double r = sR[wid][lane];
+            ux = ((double)b.x - a.x) * r;
+            uy = ((double)b.y - a.y) * r;
+        }
+        const double Pin = carryP + wave_incl_scan<double>(Cb, lane);
+        const double Vx = lane < nseg ? (lb - Pin) * ux : 0.0;
+        const double Vy = lane < nseg ? (lb - Pin) * uy : 0.0;
+        double Bpx = __shfl_up(Bx, 1, 64), Bpy = __shfl_up(By, 1, 64);
+        double Vpx = __shfl_up(Vx, 1, 64), Vpy = __shfl_up(Vy, 1, 64);
+        if (lane == 0) {
+            Bpx = carryBx;
+            Bpy = carryBy;
+            Vpx = carryVx;
+            Vpy = carryVy;
+        }
+        if (lane < nseg || (last && lane == nseg))
+            pb[j0 + lane] = make_float2((float)(Ax + Bpx - Vx + Vpx), (float)(Ay + Bpy - Vy + Vpy));
+        carryBx = __shfl(Bx, nseg - 1, 64);
+        carryBy = __shfl(By, nseg - 1, 64);
+        carryVx = __shfl(Vx, nseg - 1, 64);
+        carryVy = __shfl(Vy, nseg - 1, 64);
+        carryP = __shfl(Pin, nseg - 1, 64);
+        if (last && nseg == 64 && lane == 0)
+            pb[j0 + 64] = make_float2((float)(carryBx + carryVx), (float)(carryBy + carryVy));
+        __builtin_amdgcn_wave_barrier();
+        knext = kend;
+        Cbase = Cend;
+    }
+    // pass B: L_bar and the total of C_bar enter every segment length alike
+    const double G = wave_sum(Lbar) + carryP;
+    if (G == 0.0) return;
+    for (int64_t i = lane; i < m; i += 64) {
+        double gx = 0.0, gy = 0.0;
+        const float2 c = p[i];
+        if (i > 0) {
+            const float2 q = p[i - 1];
+            const double dx = (double)c.x - q.x, dy = (double)c.y - q.y;
+            const double l = sqrt(__fma_rn(dx, dx, __dmul_rn(dy, dy)));
+            if (l > 0.0) {
+                gx += dx / l;
+                gy += dy / l;
+            }
+        }
+        if (i + 1 < m) {
+            const float2 q = p[i + 1];
+            const double dx = (double)q.x - c.x, dy = (double)q.y - c.y;
+            const double l = sqrt(__fma_rn(dx, dx, __dmul_rn(dy, dy)));
+            if (l > 0.0) {
+                gx -= dx / l;
+                gy -= dy / l;
+            }
+        }
+        const float2 cur = pb[i];
+        pb[i] = make_float2((float)((double)cur.x + G * gx), (float)((double)cur.y + G * gy));
+    }
+}
+
+// dL/dM[l][b] += sum over edges of layer l of partials[e][b]; dL/da_k += sum over all edges
+// of partials[e][B + k]. One block per entry; fixed per-thread order and a fixed tree.
+__global__ __launch_bounds__(kBlock) void k_adj_reduce(const GDesc *__restrict__ gd, int ng) {
+    const GDesc &d = gd[0];
+    const int B = d.B, P = d.P;
+    const int q = blockIdx.x;
+    int l = -1, col;
+    if (q < B * B) {
+        l = q / B;
+        col = q % B;
+    } else {
+        col = B + (q - B * B);
+    }
+    double s = 0.0;
+    for (int64_t e = threadIdx.x; e < d.n_edges; e += kBlock)
+        if (l < 0 || d.group[e] == l) s += d.partials[e * (B + P) + col];
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) d.grad_param[q] += red[0];
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline dim3 grid1(int64_t blocks) { return dim3((unsigned)(blocks > 0 ? blocks : 0)); }
+
+hipError_t launch_ink_grad(const GDesc *desc, const Shape &tot, hipStream_t st) {
+    if (tot.edge <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_ink_grad, grid1(tot.edge), dim3(kBlock), 0, st, desc, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_maps(const GDesc *desc, const Shape &tot, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_maps, grid1(tot.pxb), dim3(kBlock), 0, st, desc, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_advect(const GDesc *desc, const Shape &tot, int bmax, hipStream_t st) {
+    if (tot.edge <= 0) return hipSuccess;
+    const dim3 gr = grid1(tot.edge), bl(kBlock);
+    if (bmax <= 1) hipLaunchKernelGGL(k_adj_advect<1>, gr, bl, 0, st, desc, 1);
+    else if (bmax <= 2) hipLaunchKernelGGL(k_adj_advect<2>, gr, bl, 0, st, desc, 1);
+    else if (bmax <= 4) hipLaunchKernelGGL(k_adj_advect<4>, gr, bl, 0, st, desc, 1);
+    else if (bmax <= 8) hipLaunchKernelGGL(k_adj_advect<8>, gr, bl, 0, st, desc, 1);
+    else hipLaunchKernelGGL(k_adj_advect<16>, gr, bl, 0, st, desc, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_resample(const GDesc *desc, const Shape &tot, hipStream_t st) {
+    if (tot.edge <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_resample, grid1(tot.edge), dim3(kBlock), 0, st, desc, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_reduce(const GDesc *desc, int B, int P, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_reduce, dim3(B * B + P), dim3(kBlock), 0, st, desc, 1);
+    return hipGetLastError();
+}
+
+}  // namespace hb

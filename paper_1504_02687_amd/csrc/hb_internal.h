@@ -67,6 +67,13 @@ struct GDesc {
     float2 *grad;               // [B][H][W]
     int8_t *jacc;               // [cap] accepted halving per sample (record != 0)
     int32_t *status;
+
+    // adjoint of one iteration (frozen decisions)
+    const float2 *adj_in;       // adjoint of this stage's output points
+    float2 *adj_out;            // adjoint of this stage's input points
+    float2 *gsk;                // [B][P][H][W] gradient of pass k of group b / (2r+1)^(2k)
+    double *partials;           // [E][B + P] per-edge parameter partials
+    double *grad_param;         // [B*B + P] accumulated dL/dM (row-major) and dL/da
 };
 
 // Launch-shape block counts of one graph (host side).
@@ -94,5 +101,12 @@ hipError_t launch_density_grad(const GDesc *desc, int ng, const Shape &tot, int 
 hipError_t launch_advect_smooth(const GDesc *desc, int ng, const Shape &tot, int u,
                                 hipStream_t st);
 hipError_t launch_fill_totals(const GDesc *desc, int ng, int T, hipStream_t st);
+
+// Adjoint kernels (one graph per launch).
+hipError_t launch_ink_grad(const GDesc *desc, const Shape &tot, hipStream_t st);
+hipError_t launch_adj_maps(const GDesc *desc, const Shape &tot, hipStream_t st);
+hipError_t launch_adj_advect(const GDesc *desc, const Shape &tot, int bmax, hipStream_t st);
+hipError_t launch_adj_resample(const GDesc *desc, const Shape &tot, hipStream_t st);
+hipError_t launch_adj_reduce(const GDesc *desc, int B, int P, hipStream_t st);
 
 }  // namespace hb

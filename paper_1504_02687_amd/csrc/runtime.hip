@@ -85,6 +85,17 @@ struct hb_ctx {
     double stage_ms[HB_NUM_STAGES] = {0};
     int64_t stage_n[HB_NUM_STAGES] = {0};
 
+    // checkpoints of a differentiable run: the polylines entering each iteration
+    struct Ckpt {
+        float2 *pts = nullptr;
+        int64_t *off = nullptr, *counts = nullptr;
+        double *lens = nullptr;
+        int64_t n = 0;
+        int32_t iter = 0;
+    };
+    std::vector<Ckpt> ckpts;
+    int32_t ckpt_end_iter = -1;
+
     // kernel variants (chunks of 64 per trip in resampling / advection)
     int tune_ru = 1, tune_au = 2;
 
@@ -507,6 +518,8 @@ HB_API hb_status hb_create(hb_ctx **out, int32_t device, void *hip_stream) {
     return HB_OK;
 }
 
+static void free_ckpts(hb_ctx *c);
+
 HB_API void hb_destroy(hb_ctx *c) {
     if (!c) return;
     {
@@ -532,6 +545,7 @@ HB_API void hb_destroy(hb_ctx *c) {
         dfree(&c->d_rho);
         dfree(&c->d_grad);
         dfree(&c->d_jacc);
+        free_ckpts(c);
         dfree(&c->d_desc);
         if (c->h_desc) (void)hipHostFree(c->h_desc);
         if (c->desc_done) (void)hipEventDestroy(c->desc_done);
@@ -562,6 +576,7 @@ HB_API hb_status hb_set_params(hb_ctx *c, const hb_params *p) {
     c->P.pass_weights = nullptr;
     if (c->P.capacity_factor == 0.0f) c->P.capacity_factor = 2.0f;
     c->have_params = true;
+    c->ckpt_end_iter = -1;
     c->have_maps = false;
     return HB_OK;
 }
@@ -725,6 +740,7 @@ HB_API hb_status hb_set_graph(hb_ctx *c, int32_t n_nodes, const float *node_xy, 
     CHKST(setup_scan_total(c, &n0));
     CHKST(ensure_capacity(c, (int64_t)std::ceil((double)n0 * c->P.capacity_factor) + 64));
     c->have_graph = true;
+    c->ckpt_end_iter = -1;
     return HB_OK;
 }
 
@@ -764,6 +780,7 @@ HB_API hb_status hb_set_groups(hb_ctx *c, int32_t n_groups, const int32_t *group
     }
     c->B = n_groups;
     c->have_groups = true;
+    c->ckpt_end_iter = -1;
     c->have_maps = false;
     return HB_OK;
 }
@@ -852,6 +869,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
             lead->h_desc[(size_t)it * n + g] = d;
         }
         c->pending = true;
+        c->ckpt_end_iter = -1;
         c->pend_start = c->iter;
         c->pend_T = T;
         c->pend_flags = flags;
@@ -1228,6 +1246,7 @@ HB_API hb_status hb_set_points(hb_ctx *c, const int64_t *offsets, const float *x
     if (n_points > 0)
         HIPCHK(c, hipMemcpy(c->pts[0], hx.data(), hx.size() * sizeof(float), hipMemcpyHostToDevice));
     c->n_state = n_points;
+    c->ckpt_end_iter = -1;
     CHKST(ensure_desc(c, 1));
     CHKST(wait_desc(c));
     GDesc d = base_desc(c);
@@ -1311,6 +1330,7 @@ HB_API hb_status hb_set_iteration(hb_ctx *c, int32_t iter) {
     CHKST(finish_pending(c));
     if (iter < 0) return fail(c, HB_EINVAL, "iteration must be >= 0");
     c->iter = iter;
+    c->ckpt_end_iter = -1;
     return HB_OK;
 }
 
@@ -1336,5 +1356,201 @@ HB_API hb_status hb_get_stage_times(hb_ctx *c, double *ms, int64_t *launches, in
             c->stage_ms[i] = 0.0;
             c->stage_n[i] = 0;
         }
+    return HB_OK;
+}
+
+// ------------------------------------------------------------------ adjoint
+
+static void free_ckpts(hb_ctx *c) {
+    for (auto &k : c->ckpts) {
+        dfree(&k.pts);
+        dfree(&k.off);
+        dfree(&k.counts);
+        dfree(&k.lens);
+    }
+    c->ckpts.clear();
+    c->ckpt_end_iter = -1;
+}
+
+HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    if (!c->have_params || !c->have_graph || !c->have_groups)
+        return fail(c, HB_ESTATE, "hb_forward_ckpt needs parameters, graph and groups");
+    if (n_iters < 1) return fail(c, HB_EINVAL, "n_iters must be >= 1");
+    if (flags != 0) return fail(c, HB_EINVAL, "hb_forward_ckpt takes no flags");
+    if (c->B > 16) return fail(c, HB_EINVAL, "the adjoint supports at most 16 groups");
+    free_ckpts(c);
+    std::vector<int64_t> counts;
+    for (int t = 0; t < n_iters; ++t) {
+        hb_ctx::Ckpt k;
+        k.n = c->n_state;
+        k.iter = c->iter;
+        hb_status st = dalloc(c, &k.pts, (size_t)std::max<int64_t>(1, k.n), "checkpoint");
+        if (st == HB_OK) st = dalloc(c, &k.off, (size_t)c->E + 1, "checkpoint");
+        if (st == HB_OK) st = dalloc(c, &k.counts, (size_t)std::max<int64_t>(1, c->E), "checkpoint");
+        if (st == HB_OK) st = dalloc(c, &k.lens, (size_t)std::max<int64_t>(1, c->E), "checkpoint");
+        c->ckpts.push_back(k);
+        if (st != HB_OK) {
+            free_ckpts(c);
+            return st;
+        }
+        HIPCHK(c, hipMemcpyAsync(k.pts, c->pts[c->ps], sizeof(float2) * k.n, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(k.off, c->off[c->os], sizeof(int64_t) * (c->E + 1), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(k.counts, c->d_counts, sizeof(int64_t) * c->E, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(k.lens, c->d_lens, sizeof(double) * c->E, hipMemcpyDeviceToDevice, c->stream));
+        c->last_counts.clear();
+        CHKST(enqueue_run(c, 1, 0));
+        CHKST(finish_pending(c));
+        counts.insert(counts.end(), c->last_counts.begin(), c->last_counts.end());
+    }
+    c->last_counts = counts;
+    c->ckpt_end_iter = c->iter;
+    return HB_OK;
+}
+
+// Gradient of the loss L = total length of the polylines after the checkpointed run, with
+// respect to M (B x B), the pass weights a (P) and the polylines that entered the run.
+HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da, float *dL_dxy0,
+                             int64_t cap_points, uint32_t flags) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    if (c->ckpts.empty() || c->iter != c->ckpt_end_iter)
+        return fail(c, HB_ESTATE, "hb_backward needs hb_forward_ckpt just before it");
+    if (flags & ~(uint32_t)HB_DEVICE_PTRS) return fail(c, HB_EINVAL, "unknown flags");
+    const int T = (int)c->ckpts.size();
+    const int B = c->B, P = c->P.box_passes, W = c->P.grid_w, H = c->P.grid_h;
+    const int64_t E = c->E, n0 = c->ckpts[0].n;
+    if (dL_dxy0 && cap_points < n0) return fail(c, HB_EINVAL, "dL_dxy0 buffer too small");
+    int64_t nmax = c->n_state;
+    for (auto &k : c->ckpts) nmax = std::max(nmax, k.n);
+    CHKST(ensure_maps(c));
+    CHKST(ensure_totals(c, 1));
+    CHKST(ensure_desc(c, (size_t)(3 * T + 1)));
+    CHKST(wait_desc(c));
+
+    struct Tmp {
+        float2 *a0 = nullptr, *a1 = nullptr, *xs = nullptr, *xn = nullptr, *gsk = nullptr;
+        int64_t *soff = nullptr, *save_counts = nullptr;
+        double *partials = nullptr, *gparam = nullptr, *save_lens = nullptr;
+        int8_t *jacc = nullptr;
+        ~Tmp() {
+            dfree(&a0); dfree(&a1); dfree(&xs); dfree(&xn); dfree(&gsk); dfree(&soff);
+            dfree(&save_counts); dfree(&partials); dfree(&gparam); dfree(&save_lens); dfree(&jacc);
+        }
+    } tm;
+    const size_t plane = (size_t)W * H;
+    CHKST(dalloc(c, &tm.a0, (size_t)nmax, "adjoint"));
+    CHKST(dalloc(c, &tm.a1, (size_t)nmax, "adjoint"));
+    CHKST(dalloc(c, &tm.xs, (size_t)nmax, "recomputed samples"));
+    CHKST(dalloc(c, &tm.xn, (size_t)nmax, "recomputed polylines"));
+    CHKST(dalloc(c, &tm.jacc, (size_t)nmax, "recomputed decisions"));
+    CHKST(dalloc(c, &tm.gsk, (size_t)B * P * plane, "pass gradient maps"));
+    CHKST(dalloc(c, &tm.soff, (size_t)E + 1, "offsets"));
+    CHKST(dalloc(c, &tm.save_counts, (size_t)std::max<int64_t>(1, E), "counts"));
+    CHKST(dalloc(c, &tm.save_lens, (size_t)std::max<int64_t>(1, E), "lengths"));
+    CHKST(dalloc(c, &tm.partials, (size_t)std::max<int64_t>(1, E) * (B + P), "partials"));
+    CHKST(dalloc(c, &tm.gparam, (size_t)(B * B + P), "parameter gradients"));
+    HIPCHK(c, hipMemsetAsync(tm.gparam, 0, sizeof(double) * (B * B + P), c->stream));
+    HIPCHK(c, hipMemcpyAsync(tm.save_counts, c->d_counts, sizeof(int64_t) * E, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(tm.save_lens, c->d_lens, sizeof(double) * E, hipMemcpyDeviceToDevice, c->stream));
+
+    // loss: total length of the final polylines (the lengths the last advection wrote)
+    std::vector<double> Lh((size_t)E);
+    if (E > 0) HIPCHK(c, hipMemcpy(Lh.data(), c->d_lens, sizeof(double) * E, hipMemcpyDeviceToHost));
+    double ink = 0.0;
+    for (double v : Lh) ink += v;
+
+    const Shape s = hb::shape_of(E, B, W, H);
+    // descriptor 0: adjoint of the loss on the final polylines
+    GDesc d0 = base_desc(c);
+    set_iter_scalars(c, d0, c->iter);
+    d0.pin = c->pts[c->ps];
+    d0.off_in = c->off[c->os];
+    d0.adj_out = tm.a0;
+    c->h_desc[0] = d0;
+    float2 *cur = tm.a0, *other = tm.a1;   // cur: adjoint of the polylines leaving iteration t
+    for (int t = T - 1; t >= 0; --t) {
+        const hb_ctx::Ckpt &k = c->ckpts[t];
+        const size_t slot = 1 + 3 * (size_t)(T - 1 - t);
+        GDesc r = base_desc(c);                 // forward recompute of iteration t
+        set_iter_scalars(c, r, k.iter);
+        r.cap = nmax;
+        r.pin = k.pts;
+        r.off_in = k.off;
+        r.samples = tm.xs;
+        r.off_s = tm.soff;
+        r.pnew = tm.xn;
+        r.record = 1;
+        r.jacc = tm.jacc;
+        r.total = c->d_totals;
+        GDesc a = r;                            // adjoint of smoothing + advection
+        a.gsk = tm.gsk;
+        a.adj_in = cur;
+        a.adj_out = other;
+        a.partials = tm.partials;
+        a.grad_param = tm.gparam;
+        GDesc q = a;                            // adjoint of resampling
+        q.lens = k.lens;
+        q.adj_in = other;
+        q.adj_out = cur;
+        c->h_desc[slot] = r;
+        c->h_desc[slot + 1] = a;
+        c->h_desc[slot + 2] = q;
+    }
+    CHKST(upload_desc(c, (size_t)(3 * T + 1)));
+    HIPCHK(c, hb::launch_ink_grad(c->d_desc, s, c->stream));
+    for (int t = T - 1; t >= 0; --t) {
+        const hb_ctx::Ckpt &k = c->ckpts[t];
+        const GDesc *r = c->d_desc + 1 + 3 * (size_t)(T - 1 - t);
+        HIPCHK(c, hipMemcpyAsync(c->d_counts, k.counts, sizeof(int64_t) * E, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(c->d_lens, k.lens, sizeof(double) * E, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hb::launch_scan(r, 1, s, c->stream));
+        HIPCHK(c, hb::launch_clear_hist(r, 1, s, c->stream));
+        HIPCHK(c, hb::launch_resample_splat(r, 1, s, c->tune_ru, c->stream));
+        for (int kk = 0; kk < P; ++kk) HIPCHK(c, hb::launch_box_pass(r, 1, s, W, kk, c->stream));
+        HIPCHK(c, hb::launch_density_grad(r, 1, s, B, c->stream));
+        HIPCHK(c, hb::launch_advect_smooth(r, 1, s, c->tune_au, c->stream));
+        HIPCHK(c, hb::launch_adj_maps(r + 1, s, c->stream));
+        HIPCHK(c, hb::launch_adj_advect(r + 1, s, B, c->stream));
+        HIPCHK(c, hb::launch_adj_resample(r + 2, s, c->stream));
+        HIPCHK(c, hb::launch_adj_reduce(r + 1, B, P, c->stream));
+    }
+    // leave the state as the forward run left it
+    HIPCHK(c, hipMemcpyAsync(c->d_counts, tm.save_counts, sizeof(int64_t) * E, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_lens, tm.save_lens, sizeof(double) * E, hipMemcpyDeviceToDevice, c->stream));
+    std::vector<double> gp((size_t)(B * B + P));
+    HIPCHK(c, hipMemcpyAsync(gp.data(), tm.gparam, sizeof(double) * gp.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    int32_t status = 0;
+    HIPCHK(c, hipMemcpy(&status, c->d_status, sizeof status, hipMemcpyDeviceToHost));
+    if (status != 0) {
+        int32_t zero = 0;
+        HIPCHK(c, hipMemcpy(c->d_status, &zero, sizeof zero, hipMemcpyHostToDevice));
+        return fail(c, HB_EOVERFLOW, "recomputed iteration exceeded a range check");
+    }
+    if (loss) *loss = ink;
+    if (dL_dM)
+        for (int i = 0; i < B * B; ++i) dL_dM[i] = (float)gp[i];
+    if (dL_da)
+        for (int k = 0; k < P; ++k) dL_da[k] = (float)gp[B * B + k];
+    if (dL_dxy0) {
+        // cur holds the adjoint of the polylines that entered the run
+        HIPCHK(c, hipMemcpyAsync(dL_dxy0, cur, sizeof(float2) * n0,
+                                 (flags & HB_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost,
+                                 c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return HB_OK;
+}
+
+HB_API hb_status hb_get_ckpt_points(hb_ctx *c, int32_t t, int64_t *offsets, float *xy,
+                                    int64_t cap_points, uint32_t flags) {
+    ENTER(c);
+    if (t < 0 || t >= (int32_t)c->ckpts.size()) return fail(c, HB_EINVAL, "no such checkpoint");
+    const hb_ctx::Ckpt &k = c->ckpts[t];
+    if (!offsets || cap_points < k.n || (k.n > 0 && !xy)) return fail(c, HB_EINVAL, "buffer too small");
+    CHKST(copy_out(c, offsets, k.off, sizeof(int64_t) * (size_t)(c->E + 1), flags));
+    CHKST(copy_out(c, xy, k.pts, sizeof(float2) * (size_t)k.n, flags));
     return HB_OK;
 }
