@@ -119,12 +119,21 @@ def main():
                     help="first run a plain 1 GiB device copy (reference for HBM byte counters)")
     ap.add_argument("--cpu-fraction", type=float, default=0.25,
                     help="edge fraction of the workload timed on the CPU oracle (0: skip)")
+    ap.add_argument("--grad-iters", type=int, default=3,
+                    help="iterations of the forward+backward / plain ratio (0: skip)")
+    ap.add_argument("--batched", action="store_true",
+                    help="measure the batched form instead (prints its own JSON line)")
+    ap.add_argument("--batch-graphs", type=int, default=64)
+    ap.add_argument("--batch-emax", type=float, default=1e5)
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the bundling path runs on a single MI355X; "
               "run it with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.batched:
+        batched_main(args)
+        return
 
     import numpy as np
     import torch
@@ -193,6 +202,11 @@ def main():
         if ms > 0:
             per_stage_gbs[k] = round(stage_bytes(k, w, counts, n_state0) / (ms * 1e-3) / 1e9, 1)
 
+    fwd_bwd = None
+    if args.grad_iters > 0:
+        fwd_bwd = grad_ratio(hb, w, args.grad_iters, args.capacity)
+        log(f"fwd+bwd / plain over {args.grad_iters} iterations: {fwd_bwd['ratio']:.2f}")
+
     cpu = None
     if args.cpu_fraction > 0:
         log(f"cpu baseline: oracle on {args.cpu_fraction:.0%} of the edges")
@@ -221,7 +235,104 @@ def main():
         "stage_ms": stage_ms,
         "stage_gbs": per_stage_gbs,
         "ink_final": ink,
-        "fwd_bwd_ratio": None,
+        "fwd_bwd_ratio": None if fwd_bwd is None else fwd_bwd["ratio"],
+        "fwd_bwd": fwd_bwd,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def grad_ratio(hb, w, T, capacity):
+    """Time T plain iterations, then T checkpointed iterations plus the backward pass, both
+    from the straight edges: the forward+backward / plain-forward time ratio."""
+    import torch
+    b = hb.Bundler(0)
+    b.set_workload(w, capacity_factor=capacity)
+    b.run(1)                                       # warm-up (kernels, buffers)
+    b.set_graph(w.node_xy, w.src, w.dst, w.weight)
+    b.set_groups(w.group, w.M)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(T)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    n_pts = int(b.iter_counts(T).sum())
+    b.set_graph(w.node_xy, w.src, w.dst, w.weight)
+    b.set_groups(w.group, w.M)
+    n0 = hb.hb_get_num_points(b.ctx)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hb.hb_forward_ckpt(b.ctx, T)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss, dM, da, dx = hb.hb_backward(b.ctx, w.n_groups, w.passes, n0)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    b.close()
+    return {"iterations": T, "points": n_pts, "plain_ms": t_plain * 1e3,
+            "fwd_ckpt_ms": (t1 - t0) * 1e3, "bwd_ms": (t2 - t1) * 1e3,
+            "ratio": (t2 - t0) / t_plain, "loss": loss,
+            "dL_dM_norm": float((dM.astype("float64") ** 2).sum() ** 0.5)}
+
+
+def batched_main(args):
+    """Batched form: many uneven graphs advanced together (one launch per stage, hipGraph
+    replay) against the same graphs run one at a time."""
+    import numpy as np
+    import torch
+
+    import paper_1504_02687_amd as hb
+    import workloads
+
+    torch.cuda.set_device(0)
+    log(f"generating {args.batch_graphs} graphs, edges log-uniform in [1e3, {args.batch_emax:.0e}]")
+    ws = workloads.batched(n_graphs=args.batch_graphs, e_max=args.batch_emax, n_iters=args.steps)
+    T = args.steps
+    # one at a time
+    per_graph_ms, pts_seq = [], 0
+    t_seq = 0.0
+    for w in ws:
+        b = hb.Bundler(0)
+        b.set_workload(w, capacity_factor=args.capacity)
+        b.run(1)
+        b.set_graph(w.node_xy, w.src, w.dst, w.weight)
+        b.set_groups(w.group, w.M)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run(T)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        t_seq += dt
+        per_graph_ms.append(dt * 1e3 / T)
+        pts_seq += int(b.iter_counts(T).sum())
+        b.close()
+    # together
+    bs = [hb.Bundler(0) for _ in ws]
+    for b, w in zip(bs, ws):
+        b.set_workload(w, capacity_factor=args.capacity)
+    choice = hb.autotune(bs, 1)
+    hb.batch_run(bs, 1, hb.HB_RUN_GRAPH)            # capture
+    for b, w in zip(bs, ws):
+        b.set_graph(w.node_xy, w.src, w.dst, w.weight)
+        b.set_groups(w.group, w.M)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hb.batch_run(bs, T, hb.HB_RUN_GRAPH)
+    torch.cuda.synchronize()
+    t_bat = time.perf_counter() - t0
+    pts_bat = sum(int(b.iter_counts(T).sum()) for b in bs)
+    for b in bs:
+        b.close()
+    out = {
+        "metric": "batched edge-points advected/sec per iteration (64 uneven graphs)",
+        "value": pts_bat / t_bat, "unit": "edge-points/s", "n_gpus": 1, "steps": T,
+        "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": f"batch-{len(ws)}-graphs", "edges_total": int(sum(w.n_edges for w in ws)),
+                   "edges_max": int(max(w.n_edges for w in ws)), "groups": [w.n_groups for w in ws],
+                   "grids": [w.grid_w for w in ws], "autotuned_chunks": list(choice)},
+        "one_at_a_time": {"value": pts_seq / t_seq, "per_graph_iter_ms_p50": float(np.percentile(per_graph_ms, 50)),
+                          "per_graph_iter_ms_p99": float(np.percentile(per_graph_ms, 99))},
+        "batched_iter_ms": t_bat * 1e3 / T,
+        "speedup": (pts_bat / t_bat) / (pts_seq / t_seq),
     }
     print(json.dumps(out), flush=True)
 
