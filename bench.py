@@ -259,6 +259,10 @@ def grad_ratio(hb, w, T, capacity):
     b.set_graph(w.node_xy, w.src, w.dst, w.weight)
     b.set_groups(w.group, w.M)
     n0 = hb.hb_get_num_points(b.ctx)
+    hb.hb_forward_ckpt(b.ctx, T)                   # warm-up: checkpoint and adjoint buffers
+    hb.hb_backward(b.ctx, w.n_groups, w.passes, n0)
+    b.set_graph(w.node_xy, w.src, w.dst, w.weight)
+    b.set_groups(w.group, w.M)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     hb.hb_forward_ckpt(b.ctx, T)

@@ -54,24 +54,48 @@ __global__ __launch_bounds__(kBlock) void k_ink_grad(const GDesc *__restrict__ g
     }
 }
 
-// G_bk = 1/2 (S_b^k(u+1) - S_b^k(u-1), S_b^k(v+1) - S_b^k(v-1)) / (2r+1)^(2k), from exact
-// int64 differences (zero outside the grid). One thread per (group, pixel).
+// Gradient maps the parameter gradients gather, from exact int64 differences of the box
+// sums (zero outside the grid), with D_bk = 1/2 grad(S_b^k) / (2r+1)^(2k):
+//   gb[b]    = sum_k a_k D_bk        dL/dM[l][b] = sum over moved points of layer l of
+//                                    m v . bilinear(gb[b])
+//   gl[l][k] = sum_b M[l][b] D_bk    dL/da_k     = sum over moved points of layer l of
+//                                    m v . bilinear(gl[l][k])
+// Stored interleaved per layer and pixel: record (l, px) holds gb[0..B), then gl[l][0..P),
+// padded to an even number of float2 (16-byte aligned), so a bilinear tap of all B + P maps
+// is a few contiguous 16-byte loads. One thread per (layer, pixel).
 __global__ __launch_bounds__(kBlock) void k_adj_maps(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_pxb);
-    const int W = d.W, H = d.H, B = d.B, P = d.P;
+    const int W = d.W, H = d.H, B = d.B, P = d.P, R = d.rec;
     const int64_t plane = (int64_t)W * H;
     const int64_t i = (blk - d.blk_pxb) * kBlock + threadIdx.x;
     if (i >= (int64_t)B * plane) return;
-    const int64_t b = i / plane, px = i % plane;
+    const int64_t l = i / plane, px = i % plane;
     const int u = (int)(px % W), v = (int)(px / W);
+    const bool hasr = u + 1 < W, hasl = u > 0, hasu = v + 1 < H, hasd = v > 0;
+    float2 *out = d.gsk + i * R;
+    for (int b = 0; b < B; ++b) out[b] = make_float2(0.0f, 0.0f);
     for (int k = 0; k < P; ++k) {
-        const int64_t *S = d.box + ((int64_t)k * B + b) * plane + px;
-        const int64_t xr = u + 1 < W ? S[1] : 0, xl = u > 0 ? S[-1] : 0;
-        const int64_t yu = v + 1 < H ? S[W] : 0, yd = v > 0 ? S[-W] : 0;
-        d.gsk[(b * P + k) * plane + px] = make_float2((float)(0.5 * ((double)(xr - xl) / d.ck[k])),
-                                                      (float)(0.5 * ((double)(yu - yd) / d.ck[k])));
+        double ax = 0.0, ay = 0.0;
+        for (int b = 0; b < B; ++b) {
+            const int64_t *S = d.box + ((int64_t)k * B + b) * plane + px;
+            const int64_t xr = hasr ? S[1] : 0, xl = hasl ? S[-1] : 0;
+            const int64_t yu = hasu ? S[W] : 0, yd = hasd ? S[-W] : 0;
+            const double dx = 0.5 * ((double)(xr - xl) / d.ck[k]);
+            const double dy = 0.5 * ((double)(yu - yd) / d.ck[k]);
+            const double mlb = (double)d.M[l * B + b];
+            ax += mlb * dx;
+            ay += mlb * dy;
+            if (d.a[k] != 0.0) {
+                float2 g = out[b];
+                g.x = (float)((double)g.x + d.a[k] * dx);
+                g.y = (float)((double)g.y + d.a[k] * dy);
+                out[b] = g;
+            }
+        }
+        out[B + k] = make_float2((float)ax, (float)ay);
     }
+    for (int q = B + P; q < R; ++q) out[q] = make_float2(0.0f, 0.0f);
 }
 
 // Transposed Laplacian smoothing and advection, fused. One wave per edge, chunks of 62
@@ -79,7 +103,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_maps(const GDesc *__restrict__ g
 // points (adj_in), lane l computes the adjoint x'_bar of the advected point j from y_bar of
 // j-1, j, j+1, then the adjoint of the sample x_bar = w + m (dg/dx)^T v, where w is x'_bar
 // without the clamped coordinates, v = (dd/dg)^T w with d = g / max(|g|, eps), and m the
-// frozen step h / 2^j. The same v gives the point's contribution m v . dg/dM and m v . dg/da.
+// frozen step h / 2^j. The same v gives the point's contribution m v . dg/dM and m v . dg/da
+// (FP32 gathers of the combined maps, FP64 accumulation).
 template <int BMAX>
 __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
@@ -101,11 +126,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
     const double h = d.h, s = d.s, eps = d.eps;
     const double xmax = (double)W - 1.0 / 256.0, ymax = (double)H - 1.0 / 256.0;
 
-    double accM[BMAX], accA[HB_MAX_PASSES];
+    // record of the interleaved gradient maps of this layer: B + P float2, padded to RMAX2
+    constexpr int RMAX2 = (BMAX + HB_MAX_PASSES + 1) / 2;   // 16-byte pieces per record
+    const int R = d.rec, nq = B + P;
+    const float4 *__restrict__ G = (const float4 *)(d.gsk + (int64_t)l * plane * R);
+    double acc[2 * RMAX2];
 #pragma unroll
-    for (int b = 0; b < BMAX; ++b) accM[b] = 0.0;
-#pragma unroll
-    for (int k = 0; k < HB_MAX_PASSES; ++k) accA[k] = 0.0;
+    for (int q = 0; q < 2 * RMAX2; ++q) acc[q] = 0.0;
 
     for (int64_t j0 = 0; j0 < n; j0 += 62) {
         const int64_t j = j0 - 1 + lane;
@@ -150,32 +177,33 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
             const double tx = t0.tx, ty = t0.ty;
             gxb = wx + m * ((1.0 - ty) * (v10 - v00) + ty * (v11 - v01));
             gyb = wy + m * ((1.0 - tx) * (v01 - v00) + tx * (v11 - v10));
-            const double mvx = m * vx, mvy = m * vy;
+            const float mvx = (float)(m * vx), mvy = (float)(m * vy);
+            const float ftx = (float)t0.tx, fty = (float)t0.ty;
+            const float w00 = (1.0f - ftx) * (1.0f - fty), w10 = ftx * (1.0f - fty);
+            const float w01 = (1.0f - ftx) * fty, w11 = ftx * fty;
+            const int64_t h2 = R / 2;
+            const float4 *r00 = G + t0.i00 * h2, *r10 = G + t0.i10 * h2;
+            const float4 *r01 = G + t0.i01 * h2, *r11 = G + t0.i11 * h2;
 #pragma unroll
-            for (int b = 0; b < BMAX; ++b) {
-                if (b >= B) break;
-                const double Mlb = (double)d.M[l * B + b];
-                for (int k = 0; k < P; ++k) {
-                    double sx, sy;
-                    bilin2(d.gsk + ((int64_t)b * P + k) * plane, t0, sx, sy);
-                    const double q = mvx * sx + mvy * sy;
-                    accM[b] += d.a[k] * q;
-                    accA[k] += Mlb * q;
-                }
+            for (int q2 = 0; q2 < RMAX2; ++q2) {
+                if (2 * q2 >= nq) break;
+                const float4 a00 = r00[q2], a10 = r10[q2], a01 = r01[q2], a11 = r11[q2];
+                const float gx0 = w00 * a00.x + w10 * a10.x + w01 * a01.x + w11 * a11.x;
+                const float gy0 = w00 * a00.y + w10 * a10.y + w01 * a01.y + w11 * a11.y;
+                const float gx1 = w00 * a00.z + w10 * a10.z + w01 * a01.z + w11 * a11.z;
+                const float gy1 = w00 * a00.w + w10 * a10.w + w01 * a01.w + w11 * a11.w;
+                acc[2 * q2] += (double)(mvx * gx0 + mvy * gy0);
+                acc[2 * q2 + 1] += (double)(mvx * gx1 + mvy * gy1);
             }
         }
         xb[j] = make_float2((float)gxb, (float)gyb);
     }
     double *out = d.partials + e * (int64_t)(B + P);
 #pragma unroll
-    for (int b = 0; b < BMAX; ++b) {
-        if (b >= B) break;
-        const double v = wave_sum(accM[b]);
-        if (lane == 0) out[b] = v;
-    }
-    for (int k = 0; k < P; ++k) {
-        const double v = wave_sum(accA[k]);
-        if (lane == 0) out[B + k] = v;
+    for (int q = 0; q < 2 * RMAX2; ++q) {
+        if (q >= nq) break;
+        const double v = wave_sum(acc[q]);
+        if (lane == 0) out[q] = v;
     }
 }
 

@@ -87,14 +87,26 @@ struct hb_ctx {
 
     // checkpoints of a differentiable run: the polylines entering each iteration
     struct Ckpt {
-        float2 *pts = nullptr;
-        int64_t *off = nullptr, *counts = nullptr;
+        float2 *pts = nullptr, *xs = nullptr;      // polylines entering / samples of the iteration
+        int64_t *off = nullptr, *xoff = nullptr;   // their offsets
+        int64_t *counts = nullptr;
         double *lens = nullptr;
-        int64_t n = 0;
+        int8_t *jacc = nullptr;                    // accepted halvings of the samples
+        int32_t *hist = nullptr;                   // [B][H][W] histogram of the samples
+        int64_t n = 0, ns = 0;
         int32_t iter = 0;
+        int64_t cap_n = 0, cap_ns = 0, cap_e = 0, cap_px = 0;   // allocated sizes (reused)
     };
-    std::vector<Ckpt> ckpts;
+    std::vector<Ckpt> ckpts;       // checkpoints of the last hb_forward_ckpt
+    std::vector<Ckpt> ckpt_pool;   // allocated checkpoint buffers for reuse
     int32_t ckpt_end_iter = -1;
+
+    // adjoint work buffers, kept between backward passes
+    struct AdjBufs {
+        float2 *a0 = nullptr, *a1 = nullptr, *gb = nullptr;
+        double *partials = nullptr, *gparam = nullptr;
+        int64_t cap_pts = 0, cap_a1 = 0, cap_gb = 0, cap_part = 0, cap_gp = 0;
+    } adj;
 
     // kernel variants (chunks of 64 per trip in resampling / advection)
     int tune_ru = 1, tune_au = 2;
@@ -317,11 +329,7 @@ static hb_status ensure_capacity(hb_ctx *c, int64_t need) {
         dfree(&c->pts[i]);
         c->pts[i] = np[i];
     }
-    if (c->d_jacc) {
-        dfree(&c->d_jacc);
-        c->jacc_cap = 0;
-        c->have_jacc = false;
-    }
+    c->have_jacc = false;   // the decisions buffer is kept; it grows when a run records
     c->cap = ncap;
     return HB_OK;
 }
@@ -1362,14 +1370,34 @@ HB_API hb_status hb_get_stage_times(hb_ctx *c, double *ms, int64_t *launches, in
 // ------------------------------------------------------------------ adjoint
 
 static void free_ckpts(hb_ctx *c) {
+    for (auto &k : c->ckpt_pool) c->ckpts.push_back(k);
+    c->ckpt_pool.clear();
     for (auto &k : c->ckpts) {
         dfree(&k.pts);
+        dfree(&k.xs);
         dfree(&k.off);
+        dfree(&k.xoff);
         dfree(&k.counts);
         dfree(&k.lens);
+        dfree(&k.jacc);
+        dfree(&k.hist);
     }
     c->ckpts.clear();
     c->ckpt_end_iter = -1;
+    dfree(&c->adj.a0);
+    dfree(&c->adj.a1);
+    dfree(&c->adj.gb);
+    dfree(&c->adj.partials);
+    dfree(&c->adj.gparam);
+    c->adj = hb_ctx::AdjBufs();
+}
+
+template <typename T>
+static hb_status grow(hb_ctx *c, T **p, int64_t &cap, int64_t need, const char *what) {
+    if (need <= cap && *p) return HB_OK;
+    CHKST(dalloc(c, p, (size_t)std::max<int64_t>(1, need), what));
+    cap = need;
+    return HB_OK;
 }
 
 HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
@@ -1380,37 +1408,68 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
     if (n_iters < 1) return fail(c, HB_EINVAL, "n_iters must be >= 1");
     if (flags != 0) return fail(c, HB_EINVAL, "hb_forward_ckpt takes no flags");
     if (c->B > 16) return fail(c, HB_EINVAL, "the adjoint supports at most 16 groups");
-    free_ckpts(c);
+    // earlier checkpoint buffers go back to the pool and are reused when large enough
+    for (auto &k : c->ckpts) c->ckpt_pool.push_back(k);
+    c->ckpts.clear();
+    c->ckpt_end_iter = -1;
+    const int64_t plane = (int64_t)c->B * c->P.grid_w * c->P.grid_h;
+    const size_t E1 = (size_t)c->E + 1;
     std::vector<int64_t> counts;
     for (int t = 0; t < n_iters; ++t) {
         hb_ctx::Ckpt k;
+        if (!c->ckpt_pool.empty()) {
+            k = c->ckpt_pool.front();        // slot t reuses the buffers of the last slot t
+            c->ckpt_pool.erase(c->ckpt_pool.begin());
+        }
         k.n = c->n_state;
         k.iter = c->iter;
-        hb_status st = dalloc(c, &k.pts, (size_t)std::max<int64_t>(1, k.n), "checkpoint");
-        if (st == HB_OK) st = dalloc(c, &k.off, (size_t)c->E + 1, "checkpoint");
-        if (st == HB_OK) st = dalloc(c, &k.counts, (size_t)std::max<int64_t>(1, c->E), "checkpoint");
-        if (st == HB_OK) st = dalloc(c, &k.lens, (size_t)std::max<int64_t>(1, c->E), "checkpoint");
+        hb_status st = grow(c, &k.pts, k.cap_n, k.n, "checkpoint");
+        int64_t cap_e = k.cap_e, cap_e2 = k.cap_e, cap_e3 = k.cap_e, cap_e4 = k.cap_e;
+        if (st == HB_OK) st = grow(c, &k.off, cap_e, c->E + 1, "checkpoint");
+        if (st == HB_OK) st = grow(c, &k.xoff, cap_e2, c->E + 1, "checkpoint");
+        if (st == HB_OK) st = grow(c, &k.counts, cap_e3, c->E + 1, "checkpoint");
+        if (st == HB_OK) st = grow(c, &k.lens, cap_e4, c->E + 1, "checkpoint");
+        k.cap_e = std::min(std::min(cap_e, cap_e2), std::min(cap_e3, cap_e4));
+        if (st == HB_OK) st = grow(c, &k.hist, k.cap_px, plane, "checkpoint");
         c->ckpts.push_back(k);
         if (st != HB_OK) {
             free_ckpts(c);
             return st;
         }
         HIPCHK(c, hipMemcpyAsync(k.pts, c->pts[c->ps], sizeof(float2) * k.n, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(k.off, c->off[c->os], sizeof(int64_t) * (c->E + 1), hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(k.off, c->off[c->os], sizeof(int64_t) * E1, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(k.counts, c->d_counts, sizeof(int64_t) * c->E, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(k.lens, c->d_lens, sizeof(double) * c->E, hipMemcpyDeviceToDevice, c->stream));
         c->last_counts.clear();
-        CHKST(enqueue_run(c, 1, 0));
+        CHKST(enqueue_run(c, 1, HB_RUN_RECORD_DECISIONS));
         CHKST(finish_pending(c));
         counts.insert(counts.end(), c->last_counts.begin(), c->last_counts.end());
+        // the samples, decisions and histogram of this iteration
+        hb_ctx::Ckpt &kk = c->ckpts.back();
+        kk.ns = c->n_samples;
+        int64_t cap_ns2 = kk.cap_ns;
+        st = grow(c, &kk.xs, kk.cap_ns, kk.ns, "checkpoint");
+        if (st == HB_OK) st = grow(c, &kk.jacc, cap_ns2, kk.ns, "checkpoint");
+        kk.cap_ns = std::min(kk.cap_ns, cap_ns2);
+        if (st != HB_OK) {
+            free_ckpts(c);
+            return st;
+        }
+        HIPCHK(c, hipMemcpyAsync(kk.xs, c->pts[c->ss], sizeof(float2) * kk.ns, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(kk.xoff, c->off[c->so], sizeof(int64_t) * E1, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(kk.jacc, c->d_jacc, (size_t)kk.ns, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(kk.hist, c->d_hist, sizeof(int32_t) * plane, hipMemcpyDeviceToDevice, c->stream));
     }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     c->last_counts = counts;
     c->ckpt_end_iter = c->iter;
     return HB_OK;
 }
 
 // Gradient of the loss L = total length of the polylines after the checkpointed run, with
-// respect to M (B x B), the pass weights a (P) and the polylines that entered the run.
+// respect to M (B x B), the pass weights a (P) and the polylines that entered the run. The
+// maps of each iteration are rebuilt from its checkpointed histogram; the samples and the
+// accepted halvings come from the checkpoints, so nothing else is recomputed.
 HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da, float *dL_dxy0,
                              int64_t cap_points, uint32_t flags) {
     ENTER(c);
@@ -1423,37 +1482,19 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
     const int64_t E = c->E, n0 = c->ckpts[0].n;
     if (dL_dxy0 && cap_points < n0) return fail(c, HB_EINVAL, "dL_dxy0 buffer too small");
     int64_t nmax = c->n_state;
-    for (auto &k : c->ckpts) nmax = std::max(nmax, k.n);
+    for (auto &k : c->ckpts) nmax = std::max(nmax, std::max(k.n, k.ns));
     CHKST(ensure_maps(c));
-    CHKST(ensure_totals(c, 1));
-    CHKST(ensure_desc(c, (size_t)(3 * T + 1)));
+    CHKST(ensure_desc(c, (size_t)(2 * T + 1)));
     CHKST(wait_desc(c));
-
-    struct Tmp {
-        float2 *a0 = nullptr, *a1 = nullptr, *xs = nullptr, *xn = nullptr, *gsk = nullptr;
-        int64_t *soff = nullptr, *save_counts = nullptr;
-        double *partials = nullptr, *gparam = nullptr, *save_lens = nullptr;
-        int8_t *jacc = nullptr;
-        ~Tmp() {
-            dfree(&a0); dfree(&a1); dfree(&xs); dfree(&xn); dfree(&gsk); dfree(&soff);
-            dfree(&save_counts); dfree(&partials); dfree(&gparam); dfree(&save_lens); dfree(&jacc);
-        }
-    } tm;
-    const size_t plane = (size_t)W * H;
-    CHKST(dalloc(c, &tm.a0, (size_t)nmax, "adjoint"));
-    CHKST(dalloc(c, &tm.a1, (size_t)nmax, "adjoint"));
-    CHKST(dalloc(c, &tm.xs, (size_t)nmax, "recomputed samples"));
-    CHKST(dalloc(c, &tm.xn, (size_t)nmax, "recomputed polylines"));
-    CHKST(dalloc(c, &tm.jacc, (size_t)nmax, "recomputed decisions"));
-    CHKST(dalloc(c, &tm.gsk, (size_t)B * P * plane, "pass gradient maps"));
-    CHKST(dalloc(c, &tm.soff, (size_t)E + 1, "offsets"));
-    CHKST(dalloc(c, &tm.save_counts, (size_t)std::max<int64_t>(1, E), "counts"));
-    CHKST(dalloc(c, &tm.save_lens, (size_t)std::max<int64_t>(1, E), "lengths"));
-    CHKST(dalloc(c, &tm.partials, (size_t)std::max<int64_t>(1, E) * (B + P), "partials"));
-    CHKST(dalloc(c, &tm.gparam, (size_t)(B * B + P), "parameter gradients"));
-    HIPCHK(c, hipMemsetAsync(tm.gparam, 0, sizeof(double) * (B * B + P), c->stream));
-    HIPCHK(c, hipMemcpyAsync(tm.save_counts, c->d_counts, sizeof(int64_t) * E, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(tm.save_lens, c->d_lens, sizeof(double) * E, hipMemcpyDeviceToDevice, c->stream));
+    const int64_t plane = (int64_t)W * H;
+    hb_ctx::AdjBufs &A = c->adj;
+    CHKST(grow(c, &A.a0, A.cap_pts, nmax, "adjoint"));
+    CHKST(grow(c, &A.a1, A.cap_a1, nmax, "adjoint"));
+    const int rec = (B + P + 1) / 2 * 2;
+    CHKST(grow(c, &A.gb, A.cap_gb, (int64_t)B * plane * rec, "gradient maps"));
+    CHKST(grow(c, &A.partials, A.cap_part, std::max<int64_t>(1, E) * (B + P), "partials"));
+    CHKST(grow(c, &A.gparam, A.cap_gp, (int64_t)(B * B + P), "parameter gradients"));
+    HIPCHK(c, hipMemsetAsync(A.gparam, 0, sizeof(double) * (B * B + P), c->stream));
 
     // loss: total length of the final polylines (the lengths the last advection wrote)
     std::vector<double> Lh((size_t)E);
@@ -1462,72 +1503,58 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
     for (double v : Lh) ink += v;
 
     const Shape s = hb::shape_of(E, B, W, H);
-    // descriptor 0: adjoint of the loss on the final polylines
     GDesc d0 = base_desc(c);
     set_iter_scalars(c, d0, c->iter);
     d0.pin = c->pts[c->ps];
     d0.off_in = c->off[c->os];
-    d0.adj_out = tm.a0;
+    d0.adj_out = A.a0;
     c->h_desc[0] = d0;
-    float2 *cur = tm.a0, *other = tm.a1;   // cur: adjoint of the polylines leaving iteration t
+    float2 *cur = A.a0, *other = A.a1;   // cur: adjoint of the polylines leaving iteration t
     for (int t = T - 1; t >= 0; --t) {
         const hb_ctx::Ckpt &k = c->ckpts[t];
-        const size_t slot = 1 + 3 * (size_t)(T - 1 - t);
-        GDesc r = base_desc(c);                 // forward recompute of iteration t
-        set_iter_scalars(c, r, k.iter);
-        r.cap = nmax;
-        r.pin = k.pts;
-        r.off_in = k.off;
-        r.samples = tm.xs;
-        r.off_s = tm.soff;
-        r.pnew = tm.xn;
-        r.record = 1;
-        r.jacc = tm.jacc;
-        r.total = c->d_totals;
-        GDesc a = r;                            // adjoint of smoothing + advection
-        a.gsk = tm.gsk;
+        const size_t slot = 1 + 2 * (size_t)(T - 1 - t);
+        GDesc a = base_desc(c);                 // maps, smoothing and advection adjoint
+        set_iter_scalars(c, a, k.iter);
+        a.histx = k.hist;                       // one histogram copy: the checkpoint
+        a.nx = 1;
+        a.samples = k.xs;
+        a.off_s = k.xoff;
+        a.jacc = k.jacc;
+        a.gsk = A.gb;
+        a.rec = rec;
         a.adj_in = cur;
         a.adj_out = other;
-        a.partials = tm.partials;
-        a.grad_param = tm.gparam;
-        GDesc q = a;                            // adjoint of resampling
+        a.partials = A.partials;
+        a.grad_param = A.gparam;
+        GDesc q = a;                            // resampling adjoint
+        q.pin = k.pts;
+        q.off_in = k.off;
         q.lens = k.lens;
         q.adj_in = other;
         q.adj_out = cur;
-        c->h_desc[slot] = r;
-        c->h_desc[slot + 1] = a;
-        c->h_desc[slot + 2] = q;
+        c->h_desc[slot] = a;
+        c->h_desc[slot + 1] = q;
     }
-    CHKST(upload_desc(c, (size_t)(3 * T + 1)));
+    CHKST(upload_desc(c, (size_t)(2 * T + 1)));
     HIPCHK(c, hb::launch_ink_grad(c->d_desc, s, c->stream));
     for (int t = T - 1; t >= 0; --t) {
-        const hb_ctx::Ckpt &k = c->ckpts[t];
-        const GDesc *r = c->d_desc + 1 + 3 * (size_t)(T - 1 - t);
-        HIPCHK(c, hipMemcpyAsync(c->d_counts, k.counts, sizeof(int64_t) * E, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(c->d_lens, k.lens, sizeof(double) * E, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hb::launch_scan(r, 1, s, c->stream));
-        HIPCHK(c, hb::launch_clear_hist(r, 1, s, c->stream));
-        HIPCHK(c, hb::launch_resample_splat(r, 1, s, c->tune_ru, c->stream));
-        for (int kk = 0; kk < P; ++kk) HIPCHK(c, hb::launch_box_pass(r, 1, s, W, kk, c->stream));
-        HIPCHK(c, hb::launch_density_grad(r, 1, s, B, c->stream));
-        HIPCHK(c, hb::launch_advect_smooth(r, 1, s, c->tune_au, c->stream));
-        HIPCHK(c, hb::launch_adj_maps(r + 1, s, c->stream));
-        HIPCHK(c, hb::launch_adj_advect(r + 1, s, B, c->stream));
-        HIPCHK(c, hb::launch_adj_resample(r + 2, s, c->stream));
-        HIPCHK(c, hb::launch_adj_reduce(r + 1, B, P, c->stream));
+        const GDesc *a = c->d_desc + 1 + 2 * (size_t)(T - 1 - t);
+        for (int kk = 0; kk < P; ++kk) HIPCHK(c, hb::launch_box_pass(a, 1, s, W, kk, c->stream));
+        HIPCHK(c, hb::launch_density_grad(a, 1, s, B, c->stream));
+        HIPCHK(c, hb::launch_adj_maps(a, s, c->stream));
+        HIPCHK(c, hb::launch_adj_advect(a, s, B, c->stream));
+        HIPCHK(c, hb::launch_adj_resample(a + 1, s, c->stream));
+        HIPCHK(c, hb::launch_adj_reduce(a, B, P, c->stream));
     }
-    // leave the state as the forward run left it
-    HIPCHK(c, hipMemcpyAsync(c->d_counts, tm.save_counts, sizeof(int64_t) * E, hipMemcpyDeviceToDevice, c->stream));
-    HIPCHK(c, hipMemcpyAsync(c->d_lens, tm.save_lens, sizeof(double) * E, hipMemcpyDeviceToDevice, c->stream));
     std::vector<double> gp((size_t)(B * B + P));
-    HIPCHK(c, hipMemcpyAsync(gp.data(), tm.gparam, sizeof(double) * gp.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(gp.data(), A.gparam, sizeof(double) * gp.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     int32_t status = 0;
     HIPCHK(c, hipMemcpy(&status, c->d_status, sizeof status, hipMemcpyDeviceToHost));
     if (status != 0) {
         int32_t zero = 0;
         HIPCHK(c, hipMemcpy(c->d_status, &zero, sizeof zero, hipMemcpyHostToDevice));
-        return fail(c, HB_EOVERFLOW, "recomputed iteration exceeded a range check");
+        return fail(c, HB_EOVERFLOW, "rebuilt maps exceeded a range check");
     }
     if (loss) *loss = ink;
     if (dL_dM)
