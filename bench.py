@@ -26,7 +26,8 @@ sys.path.insert(0, ROOT)
 METRIC = "edge-points advected/sec per iteration, 1M edges x 8 groups; fwd+bwd vs plain fwd"
 HBM_PEAK_GBS = 8000.0
 KERNEL_NAMES = {
-    "resample_splat": "k_resample_splat",
+    "resample_splat": "k_resample_count",
+    "bin": "k_bin_scan/k_bin_samples/k_tile_hist",
     "advect_smooth": "k_advect_smooth",
     "box": "k_box_rows/k_box_cols",
     "density_grad": "k_density_grad",
@@ -59,7 +60,9 @@ def stage_bytes(stage, w, counts, n_state0):
         if stage == "advect_smooth":
             tot += 16 * n + 28 * E             # read samples, write polylines; offsets, group, counts, lengths
         elif stage == "resample_splat":
-            tot += 8 * prev + 8 * n + 28 * E + 4 * px   # read polylines, write samples, final histogram
+            tot += 8 * prev + 8 * n + 28 * E   # read polylines, write samples; offsets, lengths
+        elif stage == "bin":
+            tot += 8 * n + 4 * px              # read samples, write the histogram
         elif stage == "box":
             tot += (28 + 32 * (P - 1)) * px    # row pass read+write, column pass read+write, per pass
         elif stage == "density_grad":

@@ -49,7 +49,8 @@ enum {
     HB_ENOMEM = -2,     /* device allocation failed */
     HB_EDEVICE = -3,    /* HIP error (sticky) */
     HB_ESTATE = -4,     /* call order: e.g. hb_run before graph, groups and parameters */
-    HB_EOVERFLOW = -5   /* integer range of the histogram or the box sums would be exceeded */
+    HB_EOVERFLOW = -5,  /* integer range of the histogram or the box sums would be exceeded */
+    HB_EINTERNAL = -6   /* an internal consistency check of the device code failed */
 };
 
 /* flags of the data-movement calls */
@@ -85,6 +86,7 @@ enum {
 #define HB_MAX_PASSES 8
 #define HB_MAX_GRID 8192
 #define HB_MAX_HALVINGS 30
+#define HB_MAX_EDGE_WEIGHT 1048575   /* 2^20 - 1 */
 
 /*
  * Parameters of the method. Section numbers refer to the paper.
@@ -130,7 +132,8 @@ void hb_destroy(hb_ctx *ctx);
 hb_status hb_set_params(hb_ctx *ctx, const hb_params *p);
 
 /* Set the graph G = {N, E} (Section 3.1): node positions node_xy[n_nodes][2] in user
- * coordinates, edges (src[e], dst[e]) with integer weights weight[e] >= 1 (NULL: all 1).
+ * coordinates, edges (src[e], dst[e]) with integer weights 1 <= weight[e] <=
+ * HB_MAX_EDGE_WEIGHT (NULL: all 1); a sample of edge e adds weight[e] to its pixel.
  * Resets the polylines to the straight segments and the iteration counter to 0.
  * Requires hb_set_params first (the grid and the bounding box). */
 hb_status hb_set_graph(hb_ctx *ctx, int32_t n_nodes, const float *node_xy, int64_t n_edges,
@@ -240,11 +243,13 @@ hb_status hb_get_ckpt_points(hb_ctx *ctx, int32_t t, int64_t *offsets, float *xy
 enum {
     HB_STAGE_SCAN = 0,            /* sample-count scan -> offsets */
     HB_STAGE_CLEAR = 1,           /* histogram clear */
-    HB_STAGE_RESAMPLE_SPLAT = 2,  /* resampling + splatting (or splatting given samples) */
+    HB_STAGE_RESAMPLE_SPLAT = 2,  /* resampling + samples per histogram tile (or counting
+                                     the given samples) */
     HB_STAGE_BOX = 3,             /* one box pass (row + column kernels) */
     HB_STAGE_DENSITY_GRAD = 4,    /* density stack + gradient */
     HB_STAGE_ADVECT_SMOOTH = 5,   /* advection + Laplacian smoothing + next counts */
-    HB_NUM_STAGES = 6
+    HB_STAGE_BIN = 6,             /* splatting: samples binned by tile, tile histograms in LDS */
+    HB_NUM_STAGES = 7
 };
 
 /* Enable (1) or disable (0) per-stage timing with HIP events on the context's stream.

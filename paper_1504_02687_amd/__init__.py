@@ -17,15 +17,17 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libhb.so")
 
-HB_OK, HB_EINVAL, HB_ENOMEM, HB_EDEVICE, HB_ESTATE, HB_EOVERFLOW = 0, -1, -2, -3, -4, -5
+HB_OK, HB_EINVAL, HB_ENOMEM, HB_EDEVICE, HB_ESTATE, HB_EOVERFLOW, HB_EINTERNAL = 0, -1, -2, -3, -4, -5, -6
 HB_DEVICE_PTRS = 1
 HB_RUN_SAMPLES_GIVEN, HB_RUN_RECORD_DECISIONS, HB_RUN_ASYNC, HB_RUN_GRAPH = 1, 2, 4, 8
 HB_POINTS_STATE, HB_POINTS_SAMPLES = 0, 1
 HB_MAP_HIST, HB_MAP_BOX, HB_MAP_DENSITY, HB_MAP_GRAD = 0, 1, 2, 3
 HB_MAX_GROUPS, HB_MAX_PASSES = 64, 8
+HB_MAX_EDGE_WEIGHT = (1 << 20) - 1
 
 STATUS_NAMES = {0: "HB_OK", -1: "HB_EINVAL", -2: "HB_ENOMEM", -3: "HB_EDEVICE",
-                -4: "HB_ESTATE", -5: "HB_EOVERFLOW"}
+                -4: "HB_ESTATE", -5: "HB_EOVERFLOW",
+                -6: "HB_EINTERNAL"}
 
 
 class HBError(RuntimeError):
@@ -99,7 +101,7 @@ _SIGS = {
                                             ctypes.c_int32, ctypes.c_int32]),
 }
 
-STAGES = ["scan", "clear", "resample_splat", "box", "density_grad", "advect_smooth"]
+STAGES = ["scan", "clear", "resample_splat", "box", "density_grad", "advect_smooth", "bin"]
 
 
 def load():

@@ -68,7 +68,7 @@ __device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t *total) {
 // L2. Returns -1 past the last edge.
 __device__ __forceinline__ int64_t edge_of(const GDesc &d, int64_t blk_local, int wid) {
     const int64_t nblk = (d.n_edges + kWavesPerBlock - 1) / kWavesPerBlock;
-    const int64_t nx = d.nx;
+    const int64_t nx = d.nxcd;
     const int64_t x = blk_local % nx, i = blk_local / nx;
     const int64_t q = nblk / nx, r = nblk % nx;
     const int64_t c = x * q + (x < r ? x : r) + i;
@@ -91,13 +91,37 @@ __device__ __forceinline__ double seg_len(float2 a, float2 b) {
     return sqrt(__fma_rn(dx, dx, __dmul_rn(dy, dy)));
 }
 
-__device__ __forceinline__ void splat_point(int32_t *hist, int W, int H, float2 p, int w) {
-    float fu = fminf(fmaxf(floorf(p.x), 0.0f), (float)(W - 1));
-    float fv = fminf(fmaxf(floorf(p.y), 0.0f), (float)(H - 1));
-    int u = (int)fu, v = (int)fv;
-    atomicAdd(hist + (int64_t)v * W + u, w);
+// ---------------------------------------------------------------- spatial binning
+
+// Histogram tile (key) of a sample and its pixel inside the tile: the pixel the sample
+// falls in (floor of its coordinates), clamped to the grid.
+__device__ __forceinline__ void bin_of(const GDesc &d, int layer, float2 p, int &key,
+                                       uint32_t &local) {
+    const float fu = fminf(fmaxf(floorf(p.x), 0.0f), (float)(d.W - 1));
+    const float fv = fminf(fmaxf(floorf(p.y), 0.0f), (float)(d.H - 1));
+    const int u = (int)fu, v = (int)fv;
+    key = (layer * d.tiles_y + (v >> kTileShift)) * d.tiles_x + (u >> kTileShift);
+    local = (uint32_t)(((v & (kTile - 1)) << kTileShift) | (u & (kTile - 1)));
 }
 
+// Runs of equal keys among lanes 0..cnt-1 of a wave, which hold consecutive samples of one
+// edge (about 64 of them share one or two tiles). Ballot of the lanes that start a run.
+__device__ __forceinline__ uint64_t run_heads(int key, int lane, int cnt) {
+    const int prev = __shfl_up(key, 1, 64);
+    return __ballot(lane < cnt && (lane == 0 || prev != key));
+}
+
+// Length of the run that starts at lane `lane`.
+__device__ __forceinline__ int run_length(uint64_t heads, int lane, int cnt) {
+    const uint64_t after = lane == 63 ? 0ull : (heads >> (lane + 1));
+    return (after ? lane + 1 + __builtin_ctzll(after) : cnt) - lane;
+}
+
+// First lane of the run that holds lane `lane` (lane < cnt).
+__device__ __forceinline__ int run_head(uint64_t heads, int lane) {
+    const uint64_t upto = lane == 63 ? heads : (heads & ((2ull << lane) - 1));
+    return 63 - __builtin_clzll(upto | 1ull);
+}
 
 // ---------------------------------------------------------------- bilinear sampling
 

@@ -13,13 +13,25 @@ namespace hb {
 enum : int32_t {
     ST_POINT_OVERFLOW = 1,   // the next sample set does not fit the point buffers
     ST_HIST_OVERFLOW = 2,    // counts could exceed int32 / int64 box sums could overflow
-    ST_STOP = ST_POINT_OVERFLOW | ST_HIST_OVERFLOW,
+    ST_BIN_MISMATCH = 4,     // tile counts and binned samples disagree (internal error)
+    ST_STOP = ST_POINT_OVERFLOW | ST_HIST_OVERFLOW | ST_BIN_MISMATCH,
 };
 
 constexpr int kBlock = 256;            // threads per block of every kernel
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kScanTile = 1024;        // edges per scan tile (4 per thread)
 constexpr int kColSeg = 128;           // rows per thread in the column box pass
+
+// Spatial binning of the samples: the histogram is built tile by tile in LDS.
+constexpr int kTileShift = 6;                       // tiles of 64 x 64 pixels
+constexpr int kTile = 1 << kTileShift;
+constexpr int kTilePx = kTile * kTile;              // LDS counters of one tile
+constexpr int kLocalBits = 2 * kTileShift;          // pixel inside the tile, low bits of an entry
+constexpr int kBinSetsMax = 64;                     // tile-count sets (edge block mod sets)
+constexpr int64_t kBinCounters = 1 << 18;          // counters of all sets, at most (unless 1 set)
+constexpr int64_t kSegEntries = 1 << 16;            // entries per tile-histogram work item
+constexpr int kTileBlocksMax = 2048;                // blocks of one graph in k_tile_hist
+static_assert(HB_MAX_EDGE_WEIGHT < (1u << (32 - kLocalBits)), "weights must fit an entry");
 
 // One graph of one iteration. Every kernel takes an array of these (one per graph of a
 // batch) and finds its graph from blockIdx via the blk_* prefixes, so a single graph is
@@ -33,6 +45,7 @@ struct GDesc {
     int64_t blk_px;      // one thread per pixel (W * H)
     int64_t blk_pxb;     // one thread per layer pixel (B * W * H)
     int64_t blk_edget;   // one thread per edge
+    int64_t blk_tile;    // tile-histogram blocks (tile_blocks per graph)
 
     int64_t n_edges;
     int64_t cap;         // capacity of the point buffers, in points
@@ -61,6 +74,16 @@ struct GDesc {
     int32_t *hist;              // [B][H][W] histogram (sum of the per-XCD copies)
     int32_t *histx;             // [nx][B][H][W] per-XCD copies the splat kernels add into
     int32_t nx;                 // number of copies (XCDs of the device)
+    int32_t nxcd;               // XCDs of the device (block-to-edge mapping)
+
+    // spatial binning: tile t = (layer * tiles_y + ty) * tiles_x + tx
+    int32_t tiles_x, tiles_y, n_tiles, tile_blocks;
+    int32_t n_sets;             // counter sets (power of two): edge block b counts in set b % n_sets
+    int64_t *bin_cnt;           // [n_sets][n_tiles] samples per tile, per set of edge blocks
+    int64_t *bin_cur;           // [n_sets][n_tiles] write cursors of the binning pass
+    int64_t *tile_off;          // [n_tiles + 1] first entry of each tile
+    int64_t *seg_off;           // [n_tiles + 1] first work item (kSegEntries entries) of each tile
+    uint32_t *bins;             // [cap] entries: pixel in tile | edge weight << kLocalBits
     int64_t *box;               // [P][B][H][W]
     int64_t *tmp;               // [B][H][W] row-pass output
     float *rho;                 // [B][H][W]
@@ -81,9 +104,15 @@ struct GDesc {
 
 // Launch-shape block counts of one graph (host side).
 struct Shape {
-    int64_t edge, scan, row, col, px, pxb, edget;
+    int64_t edge, scan, row, col, px, pxb, edget, tile;
 };
 Shape shape_of(int64_t n_edges, int32_t B, int32_t W, int32_t H);
+
+// Tiling of the B histogram layers of a W x H grid.
+struct Tiles {
+    int32_t x, y, n, blocks, sets;
+};
+Tiles tiles_of(int32_t B, int32_t W, int32_t H);
 
 // Launchers (all asynchronous on `st`). desc points to device memory holding ng
 // descriptors; tot is the sum of the per-graph shapes.
@@ -93,9 +122,11 @@ hipError_t launch_init_state(const GDesc *desc, int ng, const Shape &tot, const 
 hipError_t launch_lengths(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
 hipError_t launch_scan(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
 // u: chunks of 64 segments (resampling) / 62 points (advection) per trip: 1, 2 or 4
-hipError_t launch_resample_splat(const GDesc *desc, int ng, const Shape &tot, int u,
+hipError_t launch_resample_count(const GDesc *desc, int ng, const Shape &tot, int u,
                                  hipStream_t st);
-hipError_t launch_splat_given(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
+hipError_t launch_count_given(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
+// tile offsets, binning of the samples and the tile histograms (three kernels)
+hipError_t launch_bin_hist(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
 hipError_t launch_clear_hist(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
 hipError_t launch_box_pass(const GDesc *desc, int ng, const Shape &tot, int max_w, int pass,
                            hipStream_t st);

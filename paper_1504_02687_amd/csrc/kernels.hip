@@ -140,32 +140,24 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const GDesc *__restrict__
     }
 }
 
-// ---------------------------------------------------------------- resample + splat
-
-// XCD (accelerator complex die) that runs the calling wave. Histogram updates go to a
-// per-XCD copy of the histogram stack, which spreads the atomics on hot bundle pixels over
-// nx addresses; the first box pass sums the copies.
-__device__ __forceinline__ int xcc_id(int nx) {
-    unsigned v;
-    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
-    const int x = (int)(v & 0xfu);
-    return x < nx ? x : nx - 1;
-}
+// ---------------------------------------------------------------- resample + bin
 
 // One wave per edge. The polyline (pin) is streamed U chunks of 64 segments at a time;
 // lane j of a chunk holds segment j, its FP64 length and the arclength at its start (wave
 // scans, U independent chains in flight). The samples whose arclength s_k = k L / (n-1)
 // falls in those segments are produced 64 at a time: each lane finds its segment by
 // binary search in LDS and interpolates in FP64. Every sample is stored (coalesced,
-// float2) and splatted into this XCD's copy of its group's histogram.
+// float2) and counted in its histogram tile: one atomic per run of consecutive samples in
+// the same tile, into the counter set of this block (block mod n_sets).
 template <int U>
-__global__ __launch_bounds__(kBlock) void k_resample_splat(const GDesc *__restrict__ gd, int ng) {
+__global__ __launch_bounds__(kBlock) void k_resample_count(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_edge);
     if (stopped(d)) return;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int64_t e = edge_of(d, blk - d.blk_edge, wid);
+    const int64_t bl = blk - d.blk_edge;
+    const int64_t e = edge_of(d, bl, wid);
     if (e < 0) return;
 
     __shared__ double sC[kWavesPerBlock][64 * U];
@@ -177,10 +169,8 @@ __global__ __launch_bounds__(kBlock) void k_resample_splat(const GDesc *__restri
     const double L = d.lens[e];
     const float2 *p = d.pin + i0;
     float2 *q = d.samples + o0;
-    const int W = d.W, H = d.H;
-    const int64_t plane = (int64_t)W * H;
-    int32_t *hist = d.histx + ((int64_t)xcc_id(d.nx) * d.B + d.group[e]) * plane;
-    const int w = d.weight ? d.weight[e] : 1;
+    const int layer = d.group[e];
+    unsigned long long *ctr = (unsigned long long *)d.bin_cnt + (bl & (d.n_sets - 1)) * d.n_tiles;
     const double nm1 = (double)(n - 1);
     const double ds = L / nm1;          // arclength between consecutive samples
 
@@ -241,6 +231,8 @@ __global__ __launch_bounds__(kBlock) void k_resample_splat(const GDesc *__restri
         }
         for (int64_t kb = knext; kb < kend; kb += 64) {
             const int64_t k = kb + lane;
+            int key = 0;
+            uint32_t loc = 0;
             if (k < kend) {
                 float2 out;
                 if (k == 0) {
@@ -262,8 +254,12 @@ __global__ __launch_bounds__(kBlock) void k_resample_splat(const GDesc *__restri
                     out.y = (float)__fma_rn(t, ey, (double)pa.y);
                 }
                 q[k] = out;
-                splat_point(hist, W, H, out, w);
+                bin_of(d, layer, out, key, loc);
             }
+            const int cnt = (int)(kend - kb < 64 ? kend - kb : 64);
+            const uint64_t heads = run_heads(key, lane, cnt);
+            if ((heads >> lane) & 1ull)
+                atomicAdd(ctr + key, (unsigned long long)run_length(heads, lane, cnt));
         }
         __builtin_amdgcn_wave_barrier();
         knext = kend;
@@ -271,25 +267,143 @@ __global__ __launch_bounds__(kBlock) void k_resample_splat(const GDesc *__restri
     }
 }
 
-// Splat the given sample points (no resampling). One wave per edge.
-__global__ __launch_bounds__(kBlock) void k_splat_given(const GDesc *__restrict__ gd, int ng) {
+// Samples of every edge in its histogram tile, one wave per edge, 64 consecutive samples
+// at a time. Counting (SCATTER = false): one atomic per run of samples in the same tile, as
+// k_resample_count does for samples it makes. Binning (SCATTER = true): the run takes its
+// place from the write cursor of its tile and set (returning atomic) and stores one entry
+// per sample. Both passes map an edge to the same block, so to the same counter set.
+template <bool SCATTER>
+__global__ __launch_bounds__(kBlock) void k_bin_samples(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_edge);
     if (stopped(d)) return;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int64_t e = edge_of(d, blk - d.blk_edge, wid);
+    const int64_t bl = blk - d.blk_edge;
+    const int64_t e = edge_of(d, bl, wid);
     if (e < 0) return;
+    unsigned long long *ctr =
+        (unsigned long long *)(SCATTER ? d.bin_cur : d.bin_cnt) + (bl & (d.n_sets - 1)) * d.n_tiles;
     const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
-    const int64_t plane = (int64_t)d.W * d.H;
-    int32_t *hist = d.histx + ((int64_t)xcc_id(d.nx) * d.B + d.group[e]) * plane;
-    const int w = d.weight ? d.weight[e] : 1;
-    for (int64_t j = lane; j < n; j += 64) splat_point(hist, d.W, d.H, d.samples[o0 + j], w);
+    const int layer = d.group[e];
+    const uint32_t wbits = (uint32_t)(d.weight ? d.weight[e] : 1) << kLocalBits;
+    const float2 *__restrict__ xs = d.samples + o0;
+    for (int64_t j0 = 0; j0 < n; j0 += 64) {
+        const int64_t k = j0 + lane;
+        const int cnt = (int)(n - j0 < 64 ? n - j0 : 64);
+        int key = 0;
+        uint32_t loc = 0;
+        if (k < n) bin_of(d, layer, xs[k], key, loc);
+        const uint64_t heads = run_heads(key, lane, cnt);
+        const bool head = (heads >> lane) & 1ull;
+        if (!SCATTER) {
+            if (head) atomicAdd(ctr + key, (unsigned long long)run_length(heads, lane, cnt));
+        } else {
+            unsigned long long base = 0;
+            if (head) base = atomicAdd(ctr + key, (unsigned long long)run_length(heads, lane, cnt));
+            const int h = run_head(heads, lane);
+            base = __shfl(base, h, 64);
+            if (k < n) {
+                const unsigned long long pos = base + (unsigned long long)(lane - h);
+                if (pos < (unsigned long long)d.cap) d.bins[pos] = loc | wbits;
+                else atomicOr(d.status, ST_BIN_MISMATCH);
+            }
+        }
+    }
+}
+
+// Tile offsets of one graph (one block per graph): the entries of tile t start at
+// tile_off[t], those of set s of tile t right after the sets before it (the cursors), and
+// tile t is cut into work items of kSegEntries entries numbered from seg_off[t].
+__global__ __launch_bounds__(kBlock) void k_bin_scan(const GDesc *__restrict__ gd, int ng) {
+    if ((int)blockIdx.x >= ng) return;
+    const GDesc &d = gd[blockIdx.x];
+    if (stopped(d)) return;
+    const int nt = d.n_tiles;
+    int64_t base_off = 0, base_seg = 0;
+    for (int t0 = 0; t0 < nt; t0 += kBlock) {
+        const int t = t0 + (int)threadIdx.x;
+        int64_t tot = 0;
+        if (t < nt)
+            for (int q = 0; q < d.n_sets; ++q) tot += d.bin_cnt[(int64_t)q * nt + t];
+        const int64_t segs = (tot + kSegEntries - 1) / kSegEntries;
+        int64_t sum_tot, sum_seg;
+        const int64_t xo = block_excl_scan(tot, &sum_tot);
+        const int64_t xg = block_excl_scan(segs, &sum_seg);
+        if (t < nt) {
+            int64_t at = base_off + xo;
+            d.tile_off[t] = at;
+            d.seg_off[t] = base_seg + xg;
+            for (int q = 0; q < d.n_sets; ++q) {
+                d.bin_cur[(int64_t)q * nt + t] = at;
+                at += d.bin_cnt[(int64_t)q * nt + t];
+            }
+        }
+        base_off += sum_tot;
+        base_seg += sum_seg;
+    }
+    if (threadIdx.x == 0) {
+        d.tile_off[nt] = base_off;
+        d.seg_off[nt] = base_seg;
+        if (base_off != d.off_s[d.n_edges] || base_off > d.cap) atomicOr(d.status, ST_BIN_MISMATCH);
+    }
+}
+
+// Histogram tiles in LDS. Each block takes work items (up to kSegEntries entries of one
+// tile) round-robin, adds the entries' weights to its LDS copy of the tile with LDS
+// atomics, then adds the non-zero counters to the histogram (first copy of histx).
+__global__ __launch_bounds__(kBlock) void k_tile_hist(const GDesc *__restrict__ gd, int ng) {
+    const int64_t blk = blockIdx.x;
+    HB_FIND(blk_tile);
+    if (stopped(d)) return;
+    __shared__ int32_t lh[kTilePx];
+    const int nt = d.n_tiles;
+    const int64_t nseg = d.seg_off[nt];
+    const int W = d.W, H = d.H;
+    const int64_t plane = (int64_t)W * H;
+    const int per_layer = d.tiles_x * d.tiles_y;
+    const uint32_t *__restrict__ bins = d.bins;
+    for (int64_t sg = blk - d.blk_tile; sg < nseg; sg += d.tile_blocks) {
+        int lo = 0, hi = nt - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (d.seg_off[mid] <= sg) lo = mid; else hi = mid - 1;
+        }
+        const int t = lo;
+        const int64_t beg = d.tile_off[t] + (sg - d.seg_off[t]) * kSegEntries;
+        const int64_t lim = d.tile_off[t + 1];
+        const int64_t end = beg + kSegEntries < lim ? beg + kSegEntries : lim;
+        for (int i = threadIdx.x; i < kTilePx; i += kBlock) lh[i] = 0;
+        __syncthreads();
+        int64_t i = beg + threadIdx.x;
+        for (; i + 3 * kBlock < end; i += 4 * kBlock) {
+            const uint32_t a0 = bins[i], a1 = bins[i + kBlock];
+            const uint32_t a2 = bins[i + 2 * kBlock], a3 = bins[i + 3 * kBlock];
+            atomicAdd(&lh[a0 & (kTilePx - 1)], (int32_t)(a0 >> kLocalBits));
+            atomicAdd(&lh[a1 & (kTilePx - 1)], (int32_t)(a1 >> kLocalBits));
+            atomicAdd(&lh[a2 & (kTilePx - 1)], (int32_t)(a2 >> kLocalBits));
+            atomicAdd(&lh[a3 & (kTilePx - 1)], (int32_t)(a3 >> kLocalBits));
+        }
+        for (; i < end; i += kBlock) {
+            const uint32_t a0 = bins[i];
+            atomicAdd(&lh[a0 & (kTilePx - 1)], (int32_t)(a0 >> kLocalBits));
+        }
+        __syncthreads();
+        const int layer = t / per_layer, rem = t - layer * per_layer;
+        const int ty = rem / d.tiles_x, tx = rem - ty * d.tiles_x;
+        int32_t *hist = d.histx + (int64_t)layer * plane;
+        for (int p = threadIdx.x; p < kTilePx; p += kBlock) {
+            const int32_t v = lh[p];
+            const int y = ty * kTile + (p >> kTileShift), x = tx * kTile + (p & (kTile - 1));
+            if (v != 0 && x < W && y < H) atomicAdd(hist + (int64_t)y * W + x, v);
+        }
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------- maps
 
-// Clear every per-XCD histogram copy. One thread per layer pixel.
+// Clear the histogram accumulator and the tile counters. One thread per layer pixel.
 __global__ __launch_bounds__(kBlock) void k_clear_hist(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_pxb);
@@ -298,6 +412,7 @@ __global__ __launch_bounds__(kBlock) void k_clear_hist(const GDesc *__restrict__
     const int64_t i = (blk - d.blk_pxb) * kBlock + threadIdx.x;
     if (i >= n) return;
     for (int c = 0; c < d.nx; ++c) d.histx[c * n + i] = 0;
+    for (int64_t j = i; j < (int64_t)d.n_sets * d.n_tiles; j += n) d.bin_cnt[j] = 0;
 }
 
 // Row pass of one box filter: out(u) = sum of in(u') over |u'-u| <= r inside the row,
@@ -593,7 +708,19 @@ Shape shape_of(int64_t n_edges, int32_t B, int32_t W, int32_t H) {
     s.px = (plane + kBlock - 1) / kBlock;
     s.pxb = ((int64_t)B * plane + kBlock - 1) / kBlock;
     s.edget = (n_edges + 1 + kBlock - 1) / kBlock;
+    s.tile = tiles_of(B, W, H).blocks;
     return s;
+}
+
+Tiles tiles_of(int32_t B, int32_t W, int32_t H) {
+    Tiles t;
+    t.x = (W + kTile - 1) / kTile;
+    t.y = (H + kTile - 1) / kTile;
+    t.n = B * t.x * t.y;
+    t.blocks = t.n < kTileBlocksMax ? t.n : kTileBlocksMax;
+    t.sets = 1;
+    while (t.sets < kBinSetsMax && (int64_t)t.sets * 2 * t.n <= kBinCounters) t.sets *= 2;
+    return t;
 }
 
 static inline dim3 grid_of(int64_t blocks) { return dim3((unsigned)(blocks > 0 ? blocks : 0)); }
@@ -627,21 +754,32 @@ hipError_t launch_scan(const GDesc *desc, int ng, const Shape &tot, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_resample_splat(const GDesc *desc, int ng, const Shape &tot, int u,
+hipError_t launch_resample_count(const GDesc *desc, int ng, const Shape &tot, int u,
                                  hipStream_t st) {
     if (tot.edge <= 0) return hipSuccess;
     const dim3 gr = grid_of(tot.edge), bl(kBlock);
     switch (u) {
-        case 1: hipLaunchKernelGGL(k_resample_splat<1>, gr, bl, 0, st, desc, ng); break;
-        case 4: hipLaunchKernelGGL(k_resample_splat<4>, gr, bl, 0, st, desc, ng); break;
-        default: hipLaunchKernelGGL(k_resample_splat<2>, gr, bl, 0, st, desc, ng); break;
+        case 1: hipLaunchKernelGGL(k_resample_count<1>, gr, bl, 0, st, desc, ng); break;
+        case 4: hipLaunchKernelGGL(k_resample_count<4>, gr, bl, 0, st, desc, ng); break;
+        default: hipLaunchKernelGGL(k_resample_count<2>, gr, bl, 0, st, desc, ng); break;
     }
     return hipGetLastError();
 }
 
-hipError_t launch_splat_given(const GDesc *desc, int ng, const Shape &tot, hipStream_t st) {
+hipError_t launch_count_given(const GDesc *desc, int ng, const Shape &tot, hipStream_t st) {
     if (tot.edge <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_splat_given, grid_of(tot.edge), dim3(kBlock), 0, st, desc, ng);
+    hipLaunchKernelGGL(k_bin_samples<false>, grid_of(tot.edge), dim3(kBlock), 0, st, desc, ng);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_hist(const GDesc *desc, int ng, const Shape &tot, hipStream_t st) {
+    if (ng <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bin_scan, dim3((unsigned)ng), dim3(kBlock), 0, st, desc, ng);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || tot.edge <= 0) return e;
+    hipLaunchKernelGGL(k_bin_samples<true>, grid_of(tot.edge), dim3(kBlock), 0, st, desc, ng);
+    if ((e = hipGetLastError()) != hipSuccess || tot.tile <= 0) return e;
+    hipLaunchKernelGGL(k_tile_hist, grid_of(tot.tile), dim3(kBlock), 0, st, desc, ng);
     return hipGetLastError();
 }
 

@@ -40,6 +40,7 @@ struct hb_ctx {
     int32_t B = 0;
     bool have_groups = false;
     int32_t *d_group = nullptr, *d_weight = nullptr, *d_perm = nullptr;
+    std::vector<int32_t> h_group;
     std::vector<uint32_t> h_morton;     // Morton code of each straight edge's midpoint
     float *d_M = nullptr;
 
@@ -47,6 +48,7 @@ struct hb_ctx {
     float2 *pts[2] = {nullptr, nullptr};
     int64_t *off[2] = {nullptr, nullptr};
     int64_t cap = 0;
+    uint32_t *d_bins = nullptr;          // [cap] binned samples of the splat
     int ps = 0, os = 0, ss = 0, so = 0;
     int64_t n_state = 0, n_samples = 0;
     bool have_samples = false;
@@ -58,7 +60,8 @@ struct hb_ctx {
 
     // maps of the last iteration
     int32_t *d_hist = nullptr, *d_histx = nullptr;
-    int32_t nx = 1;
+    int32_t nx = 1;                      // XCDs of the device
+    int64_t *d_bin_cnt = nullptr, *d_bin_cur = nullptr, *d_tile_off = nullptr, *d_seg_off = nullptr;
     int64_t *d_box = nullptr, *d_tmp = nullptr;
     float *d_rho = nullptr;
     float2 *d_grad = nullptr;
@@ -318,6 +321,15 @@ static hb_status ensure_capacity(hb_ctx *c, int64_t need) {
             return s;
         }
     }
+    uint32_t *nb = nullptr;
+    {
+        hb_status s = dalloc(c, &nb, (size_t)ncap, "binned samples");
+        if (s != HB_OK) {
+            dfree(&np[0]);
+            dfree(&np[1]);
+            return s;
+        }
+    }
     if (c->pts[c->ps] && c->n_state > 0)
         HIPCHK(c, hipMemcpyAsync(np[c->ps], c->pts[c->ps], sizeof(float2) * c->n_state,
                                  hipMemcpyDeviceToDevice, c->stream));
@@ -329,6 +341,8 @@ static hb_status ensure_capacity(hb_ctx *c, int64_t need) {
         dfree(&c->pts[i]);
         c->pts[i] = np[i];
     }
+    dfree(&c->d_bins);
+    c->d_bins = nb;
     c->have_jacc = false;   // the decisions buffer is kept; it grows when a run records
     c->cap = ncap;
     return HB_OK;
@@ -340,7 +354,12 @@ static hb_status ensure_maps(hb_ctx *c) {
     const size_t plane = (size_t)B * W * H;
     c->have_maps = false;
     CHKST(dalloc(c, &c->d_hist, plane, "histogram"));
-    CHKST(dalloc(c, &c->d_histx, plane * (size_t)c->nx, "per-XCD histograms"));
+    CHKST(dalloc(c, &c->d_histx, plane, "histogram accumulator"));
+    const hb::Tiles tl = hb::tiles_of(B, W, H);
+    CHKST(dalloc(c, &c->d_bin_cnt, (size_t)tl.sets * tl.n, "tile counts"));
+    CHKST(dalloc(c, &c->d_bin_cur, (size_t)tl.sets * tl.n, "tile cursors"));
+    CHKST(dalloc(c, &c->d_tile_off, (size_t)tl.n + 1, "tile offsets"));
+    CHKST(dalloc(c, &c->d_seg_off, (size_t)tl.n + 1, "tile work items"));
     CHKST(dalloc(c, &c->d_box, plane * P, "box passes"));
     CHKST(dalloc(c, &c->d_tmp, plane, "row-pass scratch"));
     CHKST(dalloc(c, &c->d_rho, plane, "density"));
@@ -381,7 +400,19 @@ static GDesc base_desc(const hb_ctx *c) {
     d.total = c->d_totals;
     d.hist = c->d_hist;
     d.histx = c->d_histx;
-    d.nx = c->nx;
+    d.nx = 1;
+    d.nxcd = c->nx;
+    const hb::Tiles tl = hb::tiles_of(d.B, d.W, d.H);
+    d.tiles_x = tl.x;
+    d.tiles_y = tl.y;
+    d.n_tiles = tl.n;
+    d.tile_blocks = tl.blocks;
+    d.n_sets = tl.sets;
+    d.bin_cnt = c->d_bin_cnt;
+    d.bin_cur = c->d_bin_cur;
+    d.tile_off = c->d_tile_off;
+    d.seg_off = c->d_seg_off;
+    d.bins = c->d_bins;
     d.box = c->d_box;
     d.tmp = c->d_tmp;
     d.rho = c->d_rho;
@@ -548,6 +579,11 @@ HB_API void hb_destroy(hb_ctx *c) {
         dfree(&c->d_status);
         dfree(&c->d_hist);
         dfree(&c->d_histx);
+        dfree(&c->d_bins);
+        dfree(&c->d_bin_cnt);
+        dfree(&c->d_bin_cur);
+        dfree(&c->d_tile_off);
+        dfree(&c->d_seg_off);
         dfree(&c->d_box);
         dfree(&c->d_tmp);
         dfree(&c->d_rho);
@@ -655,7 +691,8 @@ HB_API hb_status hb_set_graph(hb_ctx *c, int32_t n_nodes, const float *node_xy, 
             return fail(c, HB_EINVAL, "edge end point out of range");
     int32_t wmax = 1;
     for (int32_t w : hw) {
-        if (w < 1) return fail(c, HB_EINVAL, "edge weights must be >= 1");
+        if (w < 1 || w > HB_MAX_EDGE_WEIGHT)
+            return fail(c, HB_EINVAL, "edge weights must be in [1, HB_MAX_EDGE_WEIGHT]");
         wmax = std::max(wmax, w);
     }
     const int64_t E = n_edges;
@@ -752,6 +789,20 @@ HB_API hb_status hb_set_graph(hb_ctx *c, int32_t n_nodes, const float *node_xy, 
     return HB_OK;
 }
 
+// Edges sorted by group, then by the Morton code of their straight midpoint.
+static std::vector<int32_t> spatial_order(const hb_ctx *c) {
+    std::vector<int32_t> perm((size_t)c->E);
+    for (int64_t e = 0; e < c->E; ++e) perm[e] = (int32_t)e;
+    const std::vector<uint32_t> &mc = c->h_morton;
+    const std::vector<int32_t> &g = c->h_group;
+    const bool by_group = (int64_t)g.size() == c->E;
+    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
+        if (by_group && g[a] != g[b]) return g[a] < g[b];
+        return mc[a] < mc[b];
+    });
+    return perm;
+}
+
 HB_API hb_status hb_set_groups(hb_ctx *c, int32_t n_groups, const int32_t *group, const float *M,
                                uint32_t flags) {
     ENTER(c);
@@ -772,17 +823,12 @@ HB_API hb_status hb_set_groups(hb_ctx *c, int32_t n_groups, const int32_t *group
     CHKST(dalloc(c, &c->d_M, hm.size(), "interaction matrix"));
     CHKST(upload(c, c->d_M, hm));
     // visiting order of the point kernels: identity by default; HB_EDGE_ORDER=1 visits the
-    // edges by group, then by position (Morton order of the midpoint), which keeps an XCD's
-    // density gathers in its L2 but concentrates the memory-side splat atomics
+    // edges by group, then by position, which keeps an XCD's density gathers in its L2 but
+    // concentrates the memory-side splat atomics
     dfree(&c->d_perm);
+    c->h_group = hg;
     if (const char *ord = getenv("HB_EDGE_ORDER"); ord && atoi(ord) == 1) {
-        std::vector<int32_t> perm((size_t)c->E);
-        for (int64_t e = 0; e < c->E; ++e) perm[e] = (int32_t)e;
-        const std::vector<uint32_t> &mc = c->h_morton;
-        std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
-            if (hg[a] != hg[b]) return hg[a] < hg[b];
-            return mc[a] < mc[b];
-        });
+        const std::vector<int32_t> perm = spatial_order(c);
         CHKST(dalloc(c, &c->d_perm, std::max<size_t>(1, perm.size()), "edge order"));
         CHKST(upload(c, c->d_perm, perm));
     }
@@ -807,7 +853,7 @@ static hb_status prepare_ctx(hb_ctx *c, int T, uint32_t flags) {
 
 static void shape_add(Shape &a, const Shape &b) {
     a.edge += b.edge; a.scan += b.scan; a.row += b.row; a.col += b.col;
-    a.px += b.px; a.pxb += b.pxb; a.edget += b.edget;
+    a.px += b.px; a.pxb += b.pxb; a.edget += b.edget; a.tile += b.tile;
 }
 
 // Enqueue T iterations of the graphs cs[0..n) on lead's stream: the descriptor table holds
@@ -859,6 +905,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
             d.blk_px = base[g].px;
             d.blk_pxb = base[g].pxb;
             d.blk_edget = base[g].edget;
+            d.blk_tile = base[g].tile;
             d.record = record && it == T - 1;
             d.total = c->d_totals + it;
             if (given) {
@@ -901,8 +948,9 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
             if (!timed) {
                 if (!given) HIPCHK(c, hb::launch_scan(dd, n, tot, c->stream));
                 HIPCHK(c, hb::launch_clear_hist(dd, n, tot, c->stream));
-                if (given) HIPCHK(c, hb::launch_splat_given(dd, n, tot, c->stream));
-                else HIPCHK(c, hb::launch_resample_splat(dd, n, tot, ru, c->stream));
+                if (given) HIPCHK(c, hb::launch_count_given(dd, n, tot, c->stream));
+                else HIPCHK(c, hb::launch_resample_count(dd, n, tot, ru, c->stream));
+                HIPCHK(c, hb::launch_bin_hist(dd, n, tot, c->stream));
                 for (int k = 0; k < pmax; ++k) HIPCHK(c, hb::launch_box_pass(dd, n, tot, max_w, k, c->stream));
                 HIPCHK(c, hb::launch_density_grad(dd, n, tot, bmax, c->stream));
                 HIPCHK(c, hb::launch_advect_smooth(dd, n, tot, au, c->stream));
@@ -910,8 +958,9 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
             }
             if (!given) STAGE(c, HB_STAGE_SCAN, hb::launch_scan(dd, n, tot, c->stream));
             STAGE(c, HB_STAGE_CLEAR, hb::launch_clear_hist(dd, n, tot, c->stream));
-            if (given) STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_splat_given(dd, n, tot, c->stream));
-            else STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_resample_splat(dd, n, tot, ru, c->stream));
+            if (given) STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_count_given(dd, n, tot, c->stream));
+            else STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_resample_count(dd, n, tot, ru, c->stream));
+            STAGE(c, HB_STAGE_BIN, hb::launch_bin_hist(dd, n, tot, c->stream));
             for (int k = 0; k < pmax; ++k)
                 STAGE(c, HB_STAGE_BOX, hb::launch_box_pass(dd, n, tot, max_w, k, c->stream));
             STAGE(c, HB_STAGE_DENSITY_GRAD, hb::launch_density_grad(dd, n, tot, bmax, c->stream));
@@ -1012,6 +1061,8 @@ static hb_status finish_pending(hb_ctx *c) {
         c->have_samples = false;
         int32_t zero = 0;
         HIPCHK(c, hipMemcpy(c->d_status, &zero, sizeof zero, hipMemcpyHostToDevice));
+        if (status & hb::ST_BIN_MISMATCH)
+            return fail(c, HB_EINTERNAL, "binned samples disagree with the tile counts");
         if (status & hb::ST_HIST_OVERFLOW)
             return fail(c, HB_EOVERFLOW,
                         "sample count too large for int32 histograms or int64 box sums");

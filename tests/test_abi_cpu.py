@@ -78,3 +78,12 @@ def test_create_without_device_reports_error():
     st = hb.load().hb_create(ctypes.byref(ctx), 0, None)
     assert st == hb.HB_EDEVICE
     assert "device" in hb.hb_last_error().lower()
+
+
+def test_header_constants_match_binding():
+    text = open(os.path.join(ROOT, "include", "hb.h")).read()
+    assert int(re.search(r"#define HB_MAX_EDGE_WEIGHT (\d+)", text).group(1)) == hb.HB_MAX_EDGE_WEIGHT
+    assert int(re.search(r"HB_NUM_STAGES = (\d+)", text).group(1)) == len(hb.STAGES)
+    for name in ("HB_EINVAL", "HB_ENOMEM", "HB_EDEVICE", "HB_ESTATE", "HB_EOVERFLOW", "HB_EINTERNAL"):
+        v = int(re.search(name + r" = (-\d+)", text).group(1))
+        assert getattr(hb, name) == v and hb.STATUS_NAMES[v] == name

@@ -117,6 +117,74 @@ def test_stage_parity_given_samples(hb, E, W, H, B, r, a, seed):
     np.testing.assert_array_equal(xy_n[ends], xy[ends])
 
 
+def _given_hist(hb, W, H, off, xy, group, B, weight=None, seed=0):
+    """Histogram the GPU builds from given samples (one iteration with HB_RUN_SAMPLES_GIVEN)."""
+    E = len(off) - 1
+    rng = np.random.default_rng(seed)
+    with hb.Bundler(0) as b:
+        b.set_params(W, H, [2])
+        nodes = rng.random((16, 2)).astype(np.float32)
+        src = rng.integers(0, 16, E).astype(np.int32)
+        b.set_graph(nodes, src, ((src + 1) % 16).astype(np.int32), weight)
+        b.set_groups(group, np.eye(B, dtype=np.float32))
+        b.set_points(off, xy)
+        b.run(1, hb.HB_RUN_SAMPLES_GIVEN)
+        return np.stack([b.map(hb.HB_MAP_HIST, g) for g in range(B)]).astype(np.int64)
+
+
+@pytest.mark.parametrize("W,H,B,E,heavy,seed", [
+    (200, 130, 3, 700, 30000, 21), (64, 64, 1, 700, 30000, 22), (1000, 65, 2, 12, 1 << 20, 23)])
+def test_weighted_histogram_parity(hb, W, H, B, E, heavy, seed):
+    """Edge weights: each sample adds its edge's weight; ragged tiles at the right and
+    bottom borders; weights up to the largest accepted one (the int32 range check bounds
+    the sample count times the largest weight)."""
+    rng = np.random.default_rng(seed)
+    off, xy = PT.random_polylines(rng, E, W, H, step=3.0)
+    group = rng.integers(0, B, E).astype(np.int32)
+    weight = rng.integers(1, 9, E).astype(np.int32)
+    if E < 50:
+        weight[:] = np.minimum(heavy - 1 - np.arange(E), hb.HB_MAX_EDGE_WEIGHT)
+    else:
+        weight[::97] = heavy
+    assert int(np.diff(off).sum()) * int(weight.max()) < 2 ** 31
+    hist = _given_hist(hb, W, H, off, xy, group, B, weight, seed)
+    ref = O.splat(off, xy.astype(np.float64), group, B, W, H, weight)
+    np.testing.assert_array_equal(hist, ref)
+    assert hist.sum() == int((np.diff(off) * weight.astype(np.int64)).sum())
+
+
+def test_histogram_hot_tile(hb):
+    """About 240 000 samples in one 64 x 64 tile (several LDS work items of one tile) plus
+    a sparse background: bit-exact against the oracle's splat."""
+    rng = np.random.default_rng(24)
+    W = H = 256
+    E_hot, E_bg = 4000, 500
+    c = rng.integers(60, 64, E_hot)
+    off_h = np.concatenate([[0], np.cumsum(c)]).astype(np.int64)
+    xy_h = rng.uniform([128.0, 64.0], [191.99, 127.99], (int(off_h[-1]), 2))
+    off_b, xy_b = PT.random_polylines(rng, E_bg, W, H)
+    off = np.concatenate([off_h, off_b[1:] + off_h[-1]])
+    xy = np.concatenate([xy_h, xy_b]).astype(np.float32)
+    E = E_hot + E_bg
+    group = np.zeros(E, np.int32)
+    hist = _given_hist(hb, W, H, off, xy, group, 1)
+    ref = O.splat(off, xy.astype(np.float64), group, 1, W, H)
+    np.testing.assert_array_equal(hist, ref)
+    assert hist[0, 64:128, 128:192].sum() >= 240000
+
+
+def test_edge_weight_limits(hb):
+    nodes = np.random.default_rng(0).random((4, 2)).astype(np.float32)
+    src, dst = np.array([0, 1], np.int32), np.array([1, 2], np.int32)
+    with hb.Bundler(0) as b:
+        b.set_params(32, 32, [2])
+        for bad in (0, -3, hb.HB_MAX_EDGE_WEIGHT + 1):
+            with pytest.raises(hb.HBError) as ei:
+                b.set_graph(nodes, src, dst, np.array([1, bad], np.int32))
+            assert ei.value.status == hb.HB_EINVAL
+        b.set_graph(nodes, src, dst, np.array([1, hb.HB_MAX_EDGE_WEIGHT], np.int32))
+
+
 @pytest.mark.parametrize("E,W,H,delta,seed", [(800, 128, 96, 1.0, 5), (300, 512, 512, 4.0, 6)])
 def test_resample_parity(hb, E, W, H, delta, seed):
     rng = np.random.default_rng(seed)
