@@ -42,7 +42,7 @@ def log(*a):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("kernels.hip", "hb_internal.h"):
+    for f in ("kernels.hip", "device_common.h", "hb_internal.h"):
         with open(os.path.join(ROOT, "paper_1504_02687_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -90,6 +90,50 @@ def traffic_for(stage):
     return None if ent is None else ent.get("bytes_per_launch")
 
 
+def _counter_rows(path):
+    import csv
+    rows = []
+    for r in csv.DictReader(open(path)):
+        name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("hb::", "").split("<")[0]
+        rows.append((int(r["Dispatch_Id"]), name, r["Counter_Name"], float(r["Counter_Value"])))
+    return rows
+
+
+def write_traffic(fetch_csv, write_csv, last, out_path):
+    """HBM bytes per launch of every kernel from two rocprofv3 --pmc runs of the same
+    command (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by what the counter
+    reads for the 1 GiB device copies of --calibrate-copy. Averages the last `last`
+    dispatches of each kernel (the timed iterations)."""
+    res = {}
+    for which, path in (("fetch", fetch_csv), ("write", write_csv)):
+        per = {}
+        for did, name, cname, v in _counter_rows(path):
+            per.setdefault(name, {}).setdefault(did, 0.0)
+            per[name][did] += v
+        copies = [v for v in per.get("__amd_rocclr_copyBuffer", {}).values() if v * 1024 >= (1 << 29)]
+        if not copies:
+            raise SystemExit(f"no 1 GiB copy dispatch in {path}")
+        factor = (1 << 30) / (1024.0 * sum(copies) / len(copies))
+        res[which] = {"factor": factor, "copy_kib": sum(copies) / len(copies), "per": per}
+    kernels = {}
+    for name in res["fetch"]["per"]:
+        if not name.startswith("k_"):
+            continue
+        f = [v for _, v in sorted(res["fetch"]["per"][name].items())][-last:]
+        wv = [v for _, v in sorted(res["write"]["per"].get(name, {}).items())][-last:]
+        fb = 1024.0 * res["fetch"]["factor"] * sum(f) / len(f)
+        wb = 1024.0 * res["write"]["factor"] * sum(wv) / max(1, len(wv))
+        kernels[name] = {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
+                         "launches_averaged": len(f)}
+    data = {"kernel_source_hash": kernel_source_hash(),
+            "calibration": {k: {"factor": res[k]["factor"], "copy_counter_kib": res[k]["copy_kib"]}
+                            for k in ("fetch", "write")},
+            "kernels": kernels}
+    with open(out_path, "w") as fh:
+        json.dump(data, fh, indent=1)
+    return data
+
+
 def cpu_baseline(w, fraction):
     import numpy as np
     import oracle as O
@@ -128,7 +172,16 @@ def main():
                     help="measure the batched form instead (prints its own JSON line)")
     ap.add_argument("--batch-graphs", type=int, default=64)
     ap.add_argument("--batch-emax", type=float, default=1e5)
+    ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write profiles/hbm_traffic.json from two rocprofv3 --pmc runs "
+                         "(FETCH_SIZE, WRITE_SIZE) of a --calibrate-copy bench; averages the "
+                         "last --steps launches of each kernel")
     args = ap.parse_args()
+    if args.write_traffic:
+        d = write_traffic(args.write_traffic[0], args.write_traffic[1], args.steps,
+                          os.path.join(ROOT, "profiles", "hbm_traffic.json"))
+        print(json.dumps({k: round(v["bytes_per_launch"] / 1e9, 3) for k, v in d["kernels"].items()}))
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the bundling path runs on a single MI355X; "

@@ -25,22 +25,102 @@ __device__ __forceinline__ bool stopped(const GDesc &d) {
     return (*(volatile const int32_t *)d.status & ST_STOP) != 0;
 }
 
+// Pointers into device memory (global address space): loads and stores through them are
+// global (not flat) instructions, which take an SGPR base and wait only on the vector
+// memory counter.
+#define HB_G __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ HB_G T *glb(T *p) {
+    return (HB_G T *)p;
+}
+
+// float2 through global pointers (one 8-byte access; the vector type's operators only
+// take generic references).
+__device__ __forceinline__ float2 ld2(const HB_G float2 *p) {
+    const uint64_t v = *(const HB_G uint64_t *)p;
+    return make_float2(__uint_as_float((uint32_t)v), __uint_as_float((uint32_t)(v >> 32)));
+}
+__device__ __forceinline__ float2 ld2(const float2 *p) { return *p; }
+__device__ __forceinline__ void st2(HB_G float2 *p, float2 v) {
+    *(HB_G uint64_t *)p = (uint64_t)__float_as_uint(v.x) | ((uint64_t)__float_as_uint(v.y) << 32);
+}
+
+// ---------------------------------------------------------------- cross-lane moves (DPP)
+
+// DPP controls of gfx9 wave64: whole-wave shifts by one lane, row (16-lane) shifts, and the
+// broadcasts of lane 15 / lane 31 into the following rows.
+enum : int {
+    kDppWaveShl1 = 0x130,   // lane l reads lane l + 1
+    kDppWaveShr1 = 0x138,   // lane l reads lane l - 1
+    kDppRowShr = 0x110,     // + n: lane l reads lane l - n of its row
+    kDppRowBcast15 = 0x142,
+    kDppRowBcast31 = 0x143,
+};
+
+// v of the lane selected by CTRL; lanes without a source, or outside the row mask, get old.
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ int dpp(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, CTRL, ROWS, 0xf, false);
+}
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ float dpp(float old, float v) {
+    return __int_as_float(dpp<CTRL, ROWS>(__float_as_int(old), __float_as_int(v)));
+}
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ int64_t dpp(int64_t old, int64_t v) {
+    const int lo = dpp<CTRL, ROWS>((int)(uint32_t)old, (int)(uint32_t)v);
+    const int hi = dpp<CTRL, ROWS>((int)(old >> 32), (int)(v >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <int CTRL, int ROWS = 0xf>
+__device__ __forceinline__ double dpp(double old, double v) {
+    return __longlong_as_double(dpp<CTRL, ROWS>((int64_t)__double_as_longlong(old),
+                                                (int64_t)__double_as_longlong(v)));
+}
+
+// Value of lane l - 1 (lane 0 gets fill) and of lane l + 1 (lane 63 gets fill). Every lane
+// of the wave must be active.
+template <typename T>
+__device__ __forceinline__ T lane_prev(T v, T fill) {
+    return dpp<kDppWaveShr1>(fill, v);
+}
+template <typename T>
+__device__ __forceinline__ T lane_next(T v, T fill) {
+    return dpp<kDppWaveShl1>(fill, v);
+}
+
+// Value of lane 63, in every lane.
+__device__ __forceinline__ double last_lane(double v) {
+    const int64_t b = __double_as_longlong(v);
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)b, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+    return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+__device__ __forceinline__ int64_t last_lane(int64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readlane((int)(uint32_t)v, 63);
+    const uint32_t hi = __builtin_amdgcn_readlane((int)(v >> 32), 63);
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
+
+// Inclusive sum over lanes 0..l (every lane active): shifts by 1, 2, 4, 8 inside each row
+// of 16 lanes, then the row totals through the lane 15 and lane 31 broadcasts. The order of
+// the additions is fixed, so the result is reproducible.
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v, int lane) {
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-        T t = __shfl_up(v, o, 64);
-        if (lane >= o) v += t;
-    }
+    (void)lane;
+    v += dpp<kDppRowShr + 1>((T)0, v);
+    v += dpp<kDppRowShr + 2>((T)0, v);
+    v += dpp<kDppRowShr + 4>((T)0, v);
+    v += dpp<kDppRowShr + 8>((T)0, v);
+    v += dpp<kDppRowBcast15, 0xa>((T)0, v);
+    v += dpp<kDppRowBcast31, 0xc>((T)0, v);
     return v;
 }
 
-// Butterfly sum: every lane ends with the same value (IEEE addition is commutative).
+// Sum over the wave, the same value in every lane (every lane active).
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+    return last_lane(wave_incl_scan<T>(v, 0));
 }
 
 // Exclusive block scan of one int64 per thread (kBlock threads); *total gets the sum.
@@ -107,7 +187,7 @@ __device__ __forceinline__ void bin_of(const GDesc &d, int layer, float2 p, int 
 // Runs of equal keys among lanes 0..cnt-1 of a wave, which hold consecutive samples of one
 // edge (about 64 of them share one or two tiles). Ballot of the lanes that start a run.
 __device__ __forceinline__ uint64_t run_heads(int key, int lane, int cnt) {
-    const int prev = __shfl_up(key, 1, 64);
+    const int prev = lane_prev(key, -1);
     return __ballot(lane < cnt && (lane == 0 || prev != key));
 }
 
@@ -152,8 +232,8 @@ __device__ __forceinline__ Bilin bilin_taps(double x, double y, int W, int H) {
 }
 
 // FP32 taps and density sample for the acceptance tests (the precision of the stored map).
-__device__ __forceinline__ float bilin1f(const float *__restrict__ m, float x, float y, int W,
-                                         int H) {
+template <typename PF>
+__device__ __forceinline__ float bilin1f(PF m, float x, float y, int W, int H) {
     const float fx = fminf(fmaxf(x - 0.5f, -1.0f), (float)W);
     const float fy = fminf(fmaxf(y - 0.5f, -1.0f), (float)H);
     const float u0f = floorf(fx), v0f = floorf(fy);
@@ -164,13 +244,14 @@ __device__ __forceinline__ float bilin1f(const float *__restrict__ m, float x, f
     u1 = u1 < 0 ? 0 : (u1 > W - 1 ? W - 1 : u1);
     v0 = v0 < 0 ? 0 : (v0 > H - 1 ? H - 1 : v0);
     v1 = v1 < 0 ? 0 : (v1 > H - 1 ? H - 1 : v1);
-    const float *r0 = m + v0 * W, *r1 = m + v1 * W;
+    const PF r0 = m + v0 * W, r1 = m + v1 * W;
     return (1.0f - tx) * (1.0f - ty) * r0[u0] + tx * (1.0f - ty) * r0[u1] +
            (1.0f - tx) * ty * r1[u0] + tx * ty * r1[u1];
 }
 
 // Density sample with the FP64 taps of the gradient sample.
-__device__ __forceinline__ float bilin1(const float *__restrict__ m, const Bilin &b) {
+template <typename PF>
+__device__ __forceinline__ float bilin1(PF m, const Bilin &b) {
     const float tx = (float)b.tx, ty = (float)b.ty;
     return (1.0f - tx) * (1.0f - ty) * m[b.i00] + tx * (1.0f - ty) * m[b.i10] +
            (1.0f - tx) * ty * m[b.i01] + tx * ty * m[b.i11];
@@ -178,12 +259,12 @@ __device__ __forceinline__ float bilin1(const float *__restrict__ m, const Bilin
 
 // Gradient sample in FP64: the direction of a small gradient between taps of opposite
 // sign keeps the precision of the stored taps.
-__device__ __forceinline__ void bilin2(const float2 *__restrict__ m, const Bilin &b, double &gx,
-                                       double &gy) {
+template <typename PF2>
+__device__ __forceinline__ void bilin2(PF2 m, const Bilin &b, double &gx, double &gy) {
     const double tx = b.tx, ty = b.ty;
     const double w00 = (1.0 - tx) * (1.0 - ty), w10 = tx * (1.0 - ty);
     const double w01 = (1.0 - tx) * ty, w11 = tx * ty;
-    const float2 f00 = m[b.i00], f10 = m[b.i10], f01 = m[b.i01], f11 = m[b.i11];
+    const float2 f00 = ld2(m + b.i00), f10 = ld2(m + b.i10), f01 = ld2(m + b.i01), f11 = ld2(m + b.i11);
     gx = w00 * f00.x + w10 * f10.x + w01 * f01.x + w11 * f11.x;
     gy = w00 * f00.y + w10 * f10.y + w01 * f01.y + w11 * f11.y;
 }

@@ -167,10 +167,11 @@ __global__ __launch_bounds__(kBlock) void k_resample_count(const GDesc *__restri
     const int64_t i0 = d.off_in[e], m = d.off_in[e + 1] - i0;
     const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
     const double L = d.lens[e];
-    const float2 *p = d.pin + i0;
-    float2 *q = d.samples + o0;
+    const HB_G float2 *p = glb(d.pin + i0);
+    HB_G float2 *q = glb(d.samples + o0);
     const int layer = d.group[e];
-    unsigned long long *ctr = (unsigned long long *)d.bin_cnt + (bl & (d.n_sets - 1)) * d.n_tiles;
+    HB_G unsigned long long *ctr =
+        glb((unsigned long long *)d.bin_cnt) + (bl & (d.n_sets - 1)) * d.n_tiles;
     const double nm1 = (double)(n - 1);
     const double ds = L / nm1;          // arclength between consecutive samples
 
@@ -187,13 +188,13 @@ __global__ __launch_bounds__(kBlock) void k_resample_count(const GDesc *__restri
             const int64_t r = rem - 64 * u;
             ns[u] = (int)(r <= 0 ? 0 : (r < 64 ? r : 64));
             a[u] = make_float2(0.0f, 0.0f);
-            if (lane <= ns[u] && ns[u] > 0) a[u] = p[j0 + 64 * u + lane];
+            if (lane <= ns[u] && ns[u] > 0) a[u] = ld2(p + (j0 + 64 * u + lane));
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            b[u].x = __shfl_down(a[u].x, 1, 64);
-            b[u].y = __shfl_down(a[u].y, 1, 64);
-            if (lane == 63 && ns[u] == 64) b[u] = p[j0 + 64 * u + 64];
+            b[u].x = lane_next(a[u].x, 0.0f);
+            b[u].y = lane_next(a[u].y, 0.0f);
+            if (lane == 63 && ns[u] == 64) b[u] = ld2(p + (j0 + 64 * u + 64));
         }
         double ell[U];
 #pragma unroll
@@ -203,15 +204,14 @@ __global__ __launch_bounds__(kBlock) void k_resample_count(const GDesc *__restri
         double cb = Cbase;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            double excl = __shfl_up(incl[u], 1, 64);
-            if (lane == 0) excl = 0.0;
+            const double excl = lane_prev(incl[u], 0.0);
             if (lane < ns[u]) {
                 sC[wid][64 * u + lane] = cb + excl;
                 sR[wid][64 * u + lane] = ell[u] > 0.0 ? 1.0 / ell[u] : 0.0;
                 sP[wid][64 * u + lane] = a[u];
             }
             if (lane == ns[u] - 1) sP[wid][64 * u + ns[u]] = b[u];
-            cb = cb + __shfl(incl[u], 63, 64);
+            cb = cb + last_lane(incl[u]);
         }
         const double Cend = cb;
         __builtin_amdgcn_wave_barrier();
@@ -236,9 +236,9 @@ __global__ __launch_bounds__(kBlock) void k_resample_count(const GDesc *__restri
             if (k < kend) {
                 float2 out;
                 if (k == 0) {
-                    out = p[0];
+                    out = ld2(p);
                 } else if (k == n - 1) {
-                    out = p[m - 1];
+                    out = ld2(p + (m - 1));
                 } else {
                     const double s = __dmul_rn((double)k, ds);
                     int lo = 0, hi = nsegT - 1;
@@ -253,13 +253,13 @@ __global__ __launch_bounds__(kBlock) void k_resample_count(const GDesc *__restri
                     out.x = (float)__fma_rn(t, ex, (double)pa.x);
                     out.y = (float)__fma_rn(t, ey, (double)pa.y);
                 }
-                q[k] = out;
+                st2(q + k, out);
                 bin_of(d, layer, out, key, loc);
             }
             const int cnt = (int)(kend - kb < 64 ? kend - kb : 64);
             const uint64_t heads = run_heads(key, lane, cnt);
             if ((heads >> lane) & 1ull)
-                atomicAdd(ctr + key, (unsigned long long)run_length(heads, lane, cnt));
+                atomicAdd((unsigned long long *)(ctr + key), (unsigned long long)run_length(heads, lane, cnt));
         }
         __builtin_amdgcn_wave_barrier();
         knext = kend;
@@ -282,30 +282,32 @@ __global__ __launch_bounds__(kBlock) void k_bin_samples(const GDesc *__restrict_
     const int64_t bl = blk - d.blk_edge;
     const int64_t e = edge_of(d, bl, wid);
     if (e < 0) return;
-    unsigned long long *ctr =
-        (unsigned long long *)(SCATTER ? d.bin_cur : d.bin_cnt) + (bl & (d.n_sets - 1)) * d.n_tiles;
+    HB_G unsigned long long *ctr =
+        glb((unsigned long long *)(SCATTER ? d.bin_cur : d.bin_cnt)) + (bl & (d.n_sets - 1)) * d.n_tiles;
     const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
     const int layer = d.group[e];
     const uint32_t wbits = (uint32_t)(d.weight ? d.weight[e] : 1) << kLocalBits;
-    const float2 *__restrict__ xs = d.samples + o0;
+    const HB_G float2 *__restrict__ xs = glb(d.samples + o0);
+    HB_G uint32_t *bins = glb(d.bins);
     for (int64_t j0 = 0; j0 < n; j0 += 64) {
         const int64_t k = j0 + lane;
         const int cnt = (int)(n - j0 < 64 ? n - j0 : 64);
         int key = 0;
         uint32_t loc = 0;
-        if (k < n) bin_of(d, layer, xs[k], key, loc);
+        if (k < n) bin_of(d, layer, ld2(xs + k), key, loc);
         const uint64_t heads = run_heads(key, lane, cnt);
         const bool head = (heads >> lane) & 1ull;
         if (!SCATTER) {
-            if (head) atomicAdd(ctr + key, (unsigned long long)run_length(heads, lane, cnt));
+            if (head) atomicAdd((unsigned long long *)(ctr + key), (unsigned long long)run_length(heads, lane, cnt));
         } else {
             unsigned long long base = 0;
-            if (head) base = atomicAdd(ctr + key, (unsigned long long)run_length(heads, lane, cnt));
+            if (head)
+                base = atomicAdd((unsigned long long *)(ctr + key), (unsigned long long)run_length(heads, lane, cnt));
             const int h = run_head(heads, lane);
             base = __shfl(base, h, 64);
             if (k < n) {
                 const unsigned long long pos = base + (unsigned long long)(lane - h);
-                if (pos < (unsigned long long)d.cap) d.bins[pos] = loc | wbits;
+                if (pos < (unsigned long long)d.cap) bins[pos] = loc | wbits;
                 else atomicOr(d.status, ST_BIN_MISMATCH);
             }
         }
@@ -362,7 +364,7 @@ __global__ __launch_bounds__(kBlock) void k_tile_hist(const GDesc *__restrict__ 
     const int W = d.W, H = d.H;
     const int64_t plane = (int64_t)W * H;
     const int per_layer = d.tiles_x * d.tiles_y;
-    const uint32_t *__restrict__ bins = d.bins;
+    const HB_G uint32_t *__restrict__ bins = glb(d.bins);
     for (int64_t sg = blk - d.blk_tile; sg < nseg; sg += d.tile_blocks) {
         int lo = 0, hi = nt - 1;
         while (lo < hi) {
@@ -391,11 +393,11 @@ __global__ __launch_bounds__(kBlock) void k_tile_hist(const GDesc *__restrict__ 
         __syncthreads();
         const int layer = t / per_layer, rem = t - layer * per_layer;
         const int ty = rem / d.tiles_x, tx = rem - ty * d.tiles_x;
-        int32_t *hist = d.histx + (int64_t)layer * plane;
+        HB_G int32_t *hist = glb(d.histx) + (int64_t)layer * plane;
         for (int p = threadIdx.x; p < kTilePx; p += kBlock) {
             const int32_t v = lh[p];
             const int y = ty * kTile + (p >> kTileShift), x = tx * kTile + (p & (kTile - 1));
-            if (v != 0 && x < W && y < H) atomicAdd(hist + (int64_t)y * W + x, v);
+            if (v != 0 && x < W && y < H) atomicAdd((int32_t *)(hist + (int64_t)y * W + x), v);
         }
         __syncthreads();
     }
@@ -576,10 +578,11 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
     const int64_t plane = (int64_t)W * H;
     const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
     const int64_t lay = (int64_t)d.group[e] * plane;
-    const float *__restrict__ rho = d.rho + lay;
-    const float2 *__restrict__ grad = d.grad + lay;
-    const float2 *__restrict__ xs = d.samples + o0;
-    float2 *__restrict__ ys = d.pnew + o0;
+    const HB_G float *__restrict__ rho = glb(d.rho + lay);
+    const HB_G float2 *__restrict__ grad = glb(d.grad + lay);
+    const HB_G float2 *__restrict__ xs = glb(d.samples + o0);
+    HB_G float2 *__restrict__ ys = glb(d.pnew + o0);
+    HB_G int8_t *__restrict__ jrec = glb(d.jacc + o0);
     const double h = d.h, s = d.s;
     const float eps = (float)d.eps;
     const int K = d.K;
@@ -599,7 +602,7 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
             const int64_t j = j0 + 62 * u - 1 + lane;
             const bool inr = j >= 0 && j < n;
             x[u] = make_float2(0.0f, 0.0f);
-            if (inr) x[u] = xs[j];
+            if (inr) x[u] = ld2(xs + j);
             ax[u] = x[u].x;
             ay[u] = x[u].y;
             act[u] = inr && j > 0 && j < n - 1;
@@ -655,8 +658,8 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t j = j0 + 62 * u - 1 + lane;
-            const double lx = __shfl_up(ax[u], 1, 64), ly = __shfl_up(ay[u], 1, 64);
-            const double rx = __shfl_down(ax[u], 1, 64), ry = __shfl_down(ay[u], 1, 64);
+            const double lx = lane_prev(ax[u], 0.0), ly = lane_prev(ay[u], 0.0);
+            const double rx = lane_next(ax[u], 0.0), ry = lane_next(ay[u], 0.0);
             const bool out = lane >= 1 && lane <= 62 && j < n;
             y[u] = x[u];
             if (out && j > 0 && j < n - 1) {
@@ -664,8 +667,8 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
                 y[u].y = (float)__fma_rn(0.5 * s, __dadd_rn(ly, ry), __dmul_rn(1.0 - s, ay[u]));
             }
             if (out) {
-                ys[j] = y[u];
-                if (d.record) d.jacc[o0 + j] = (int8_t)jj[u];
+                st2(ys + j, y[u]);
+                if (d.record) jrec[j] = (int8_t)jj[u];
             }
         }
 #pragma unroll
@@ -673,13 +676,13 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
             const int64_t j = j0 + 62 * u - 1 + lane;
             const bool out = lane >= 1 && lane <= 62 && j < n;
             float2 yl;
-            yl.x = __shfl_up(y[u].x, 1, 64);
-            yl.y = __shfl_up(y[u].y, 1, 64);
+            yl.x = lane_prev(y[u].x, 0.0f);
+            yl.y = lane_prev(y[u].y, 0.0f);
             if (lane == 1) yl = yprev;
             const double sl = (out && j >= 1) ? seg_len(yl, y[u]) : 0.0;
             L += wave_sum(sl);
-            yprev.x = __shfl(y[u].x, 62, 64);
-            yprev.y = __shfl(y[u].y, 62, 64);
+            yprev.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y[u].x), 62));
+            yprev.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y[u].y), 62));
         }
     }
     if (lane == 0) {
