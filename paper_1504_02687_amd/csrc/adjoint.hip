@@ -151,7 +151,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
         const int jj = interior ? (int)jv[j] : -2;
         if (jj >= 0) {
             const float2 x = xs[j];
-            const Bilin t0 = bilin_taps((double)x.x, (double)x.y, W, H);
+            const Taps t0 = taps_of(x.x, x.y, W, H);
             double gx, gy;
             bilin2(grad, t0, gx, gy);
             const double nrm = sqrt(gx * gx + gy * gy);
@@ -171,19 +171,19 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
                 vx = wx / eps;
                 vy = wy / eps;
             }
-            const float2 g00 = grad[t0.i00], g10 = grad[t0.i10], g01 = grad[t0.i01], g11 = grad[t0.i11];
+            const float2 g00 = grad[t0.o00], g10 = grad[t0.o10], g01 = grad[t0.o01], g11 = grad[t0.o11];
             const double v00 = g00.x * vx + g00.y * vy, v10 = g10.x * vx + g10.y * vy;
             const double v01 = g01.x * vx + g01.y * vy, v11 = g11.x * vx + g11.y * vy;
             const double tx = t0.tx, ty = t0.ty;
             gxb = wx + m * ((1.0 - ty) * (v10 - v00) + ty * (v11 - v01));
             gyb = wy + m * ((1.0 - tx) * (v01 - v00) + tx * (v11 - v10));
             const float mvx = (float)(m * vx), mvy = (float)(m * vy);
-            const float ftx = (float)t0.tx, fty = (float)t0.ty;
+            const float ftx = t0.tx, fty = t0.ty;
             const float w00 = (1.0f - ftx) * (1.0f - fty), w10 = ftx * (1.0f - fty);
             const float w01 = (1.0f - ftx) * fty, w11 = ftx * fty;
             const int64_t h2 = R / 2;
-            const float4 *r00 = G + t0.i00 * h2, *r10 = G + t0.i10 * h2;
-            const float4 *r01 = G + t0.i01 * h2, *r11 = G + t0.i11 * h2;
+            const float4 *r00 = G + (int64_t)t0.o00 * h2, *r10 = G + (int64_t)t0.o10 * h2;
+            const float4 *r01 = G + (int64_t)t0.o01 * h2, *r11 = G + (int64_t)t0.o11 * h2;
 #pragma unroll
             for (int q2 = 0; q2 < RMAX2; ++q2) {
                 if (2 * q2 >= nq) break;

@@ -205,66 +205,60 @@ __device__ __forceinline__ int run_head(uint64_t heads, int lane) {
 
 // ---------------------------------------------------------------- bilinear sampling
 
-struct Bilin {
-    int64_t i00, i10, i01, i11;
-    double tx, ty;
+// Taps of a bilinear sample at (x - 1/2, y - 1/2), clamped into the grid: 32-bit offsets
+// into one map layer and the FP32 fractions between the taps. For x >= 1/2 the FP32
+// subtraction and the fraction are exact; below 1/2 (and at the far border) both taps of the
+// axis are the same column or row, so the fraction has no effect.
+struct Taps {
+    uint32_t o00, o10, o01, o11;   // (u0, v0), (u1, v0), (u0, v1), (u1, v1)
+    float tx, ty;
 };
 
-// Taps of a bilinear sample at (x - 1/2, y - 1/2), clamped into the grid.
-__device__ __forceinline__ Bilin bilin_taps(double x, double y, int W, int H) {
-    double fx = fmin(fmax(x - 0.5, -1.0), (double)W);
-    double fy = fmin(fmax(y - 0.5, -1.0), (double)H);
-    double u0f = floor(fx), v0f = floor(fy);
-    Bilin b;
-    b.tx = fx - u0f;
-    b.ty = fy - v0f;
-    int u0 = (int)u0f, v0 = (int)v0f;
-    int u1 = u0 + 1, v1 = v0 + 1;
-    u0 = u0 < 0 ? 0 : (u0 > W - 1 ? W - 1 : u0);
-    u1 = u1 < 0 ? 0 : (u1 > W - 1 ? W - 1 : u1);
-    v0 = v0 < 0 ? 0 : (v0 > H - 1 ? H - 1 : v0);
-    v1 = v1 < 0 ? 0 : (v1 > H - 1 ? H - 1 : v1);
-    b.i00 = (int64_t)v0 * W + u0;
-    b.i10 = (int64_t)v0 * W + u1;
-    b.i01 = (int64_t)v1 * W + u0;
-    b.i11 = (int64_t)v1 * W + u1;
-    return b;
-}
-
-// FP32 taps and density sample for the acceptance tests (the precision of the stored map).
-template <typename PF>
-__device__ __forceinline__ float bilin1f(PF m, float x, float y, int W, int H) {
-    const float fx = fminf(fmaxf(x - 0.5f, -1.0f), (float)W);
-    const float fy = fminf(fmaxf(y - 0.5f, -1.0f), (float)H);
+__device__ __forceinline__ Taps taps_of(float x, float y, int W, int H) {
+    const float fx = __builtin_amdgcn_fmed3f(x - 0.5f, -1.0f, (float)W);
+    const float fy = __builtin_amdgcn_fmed3f(y - 0.5f, -1.0f, (float)H);
     const float u0f = floorf(fx), v0f = floorf(fy);
-    const float tx = fx - u0f, ty = fy - v0f;
-    int u0 = (int)u0f, v0 = (int)v0f;
-    int u1 = u0 + 1, v1 = v0 + 1;
-    u0 = u0 < 0 ? 0 : (u0 > W - 1 ? W - 1 : u0);
-    u1 = u1 < 0 ? 0 : (u1 > W - 1 ? W - 1 : u1);
-    v0 = v0 < 0 ? 0 : (v0 > H - 1 ? H - 1 : v0);
-    v1 = v1 < 0 ? 0 : (v1 > H - 1 ? H - 1 : v1);
-    const PF r0 = m + v0 * W, r1 = m + v1 * W;
-    return (1.0f - tx) * (1.0f - ty) * r0[u0] + tx * (1.0f - ty) * r0[u1] +
-           (1.0f - tx) * ty * r1[u0] + tx * ty * r1[u1];
+    Taps t;
+    t.tx = fx - u0f;
+    t.ty = fy - v0f;
+    const int u0 = (int)u0f, v0 = (int)v0f;
+    const int ua = min(max(u0, 0), W - 1), ub = min(max(u0 + 1, 0), W - 1);
+    const int va = min(max(v0, 0), H - 1), vb = min(max(v0 + 1, 0), H - 1);
+    // grid sides are at most 8192, so the row products fit the 24-bit multiplier
+    const uint32_t ra = __umul24((uint32_t)va, (uint32_t)W), rb = __umul24((uint32_t)vb, (uint32_t)W);
+    t.o00 = ra + (uint32_t)ua;
+    t.o10 = ra + (uint32_t)ub;
+    t.o01 = rb + (uint32_t)ua;
+    t.o11 = rb + (uint32_t)ub;
+    return t;
 }
 
-// Density sample with the FP64 taps of the gradient sample.
+// Map element at a 32-bit offset (global pointers: base in SGPRs, 32-bit byte offset).
+__device__ __forceinline__ float ldo(const HB_G float *m, uint32_t i) {
+    return *(const HB_G float *)((const HB_G char *)m + (i << 2));
+}
+__device__ __forceinline__ float2 ldo(const HB_G float2 *m, uint32_t i) {
+    return ld2((const HB_G float2 *)((const HB_G char *)m + (i << 3)));
+}
+__device__ __forceinline__ float ldo(const float *m, uint32_t i) { return m[i]; }
+__device__ __forceinline__ float2 ldo(const float2 *m, uint32_t i) { return m[i]; }
+
+// Density sample in FP32 (the precision of the stored map; the acceptance tests).
 template <typename PF>
-__device__ __forceinline__ float bilin1(PF m, const Bilin &b) {
-    const float tx = (float)b.tx, ty = (float)b.ty;
-    return (1.0f - tx) * (1.0f - ty) * m[b.i00] + tx * (1.0f - ty) * m[b.i10] +
-           (1.0f - tx) * ty * m[b.i01] + tx * ty * m[b.i11];
+__device__ __forceinline__ float sample1(PF m, const Taps &t) {
+    const float tx = t.tx, ty = t.ty;
+    return (1.0f - tx) * (1.0f - ty) * ldo(m, t.o00) + tx * (1.0f - ty) * ldo(m, t.o10) +
+           (1.0f - tx) * ty * ldo(m, t.o01) + tx * ty * ldo(m, t.o11);
 }
 
 // Gradient sample in FP64: the direction of a small gradient between taps of opposite
 // sign keeps the precision of the stored taps.
 template <typename PF2>
-__device__ __forceinline__ void bilin2(PF2 m, const Bilin &b, double &gx, double &gy) {
-    const double tx = b.tx, ty = b.ty;
+__device__ __forceinline__ void bilin2(PF2 m, const Taps &t, double &gx, double &gy) {
+    const double tx = t.tx, ty = t.ty;
     const double w00 = (1.0 - tx) * (1.0 - ty), w10 = tx * (1.0 - ty);
     const double w01 = (1.0 - tx) * ty, w11 = tx * ty;
-    const float2 f00 = ld2(m + b.i00), f10 = ld2(m + b.i10), f01 = ld2(m + b.i01), f11 = ld2(m + b.i11);
+    const float2 f00 = ldo(m, t.o00), f10 = ldo(m, t.o10), f01 = ldo(m, t.o01), f11 = ldo(m, t.o11);
     gx = w00 * f00.x + w10 * f10.x + w01 * f01.x + w11 * f11.x;
     gy = w00 * f00.y + w10 * f10.y + w01 * f01.y + w11 * f11.y;
 }

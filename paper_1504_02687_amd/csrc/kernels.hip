@@ -150,7 +150,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const GDesc *__restrict__
 // float2) and counted in its histogram tile: one atomic per run of consecutive samples in
 // the same tile, into the counter set of this block (block mod n_sets).
 template <int U>
-__global__ __launch_bounds__(kBlock) void k_resample_count(const GDesc *__restrict__ gd, int ng) {
+__global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_edge);
     if (stopped(d)) return;
@@ -584,7 +584,7 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
     HB_G float2 *__restrict__ ys = glb(d.pnew + o0);
     HB_G int8_t *__restrict__ jrec = glb(d.jacc + o0);
     const double h = d.h, s = d.s;
-    const float eps = (float)d.eps;
+    const float eps2 = (float)(d.eps * d.eps), inv_eps = (float)(1.0 / d.eps);
     const int K = d.K;
     const double xmax = (double)W - 1.0 / 256.0, ymax = (double)H - 1.0 / 256.0;
     const float xmaxf = (float)xmax, ymaxf = (float)ymax;
@@ -615,15 +615,16 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
             if (act[u]) {
                 // the interpolated gradient in FP64 keeps its direction where the taps
                 // nearly cancel; its normalisation only needs FP32
-                const Bilin t0 = bilin_taps(ax[u], ay[u], W, H);
+                const Taps t0 = taps_of(x[u].x, x[u].y, W, H);
                 double gx, gy;
                 bilin2(grad, t0, gx, gy);
                 const float fx = (float)gx, fy = (float)gy;
-                const float nrm = sqrtf(fx * fx + fy * fy);
-                const float den = nrm > eps ? nrm : eps;
-                dx[u] = fx / den;
-                dy[u] = fy / den;
-                r0[u] = bilin1(rho, t0);
+                // d = g / max(|g|, eps), through one reciprocal square root (about 1 ulp)
+                const float n2 = fx * fx + fy * fy;
+                const float inv = n2 > eps2 ? __builtin_amdgcn_rsqf(n2) : inv_eps;
+                dx[u] = fx * inv;
+                dy[u] = fy * inv;
+                r0[u] = sample1(rho, t0);
             }
         }
         // acceptance tests in FP32; the accepted point is recomputed in FP64
@@ -636,9 +637,9 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 if (act[u]) {
-                    const float cx = fminf(fmaxf(x[u].x + mf * dx[u], 0.0f), xmaxf);
-                    const float cy = fminf(fmaxf(x[u].y + mf * dy[u], 0.0f), ymaxf);
-                    if (bilin1f(rho, cx, cy, W, H) >= r0[u]) {
+                    const float cx = __builtin_amdgcn_fmed3f(x[u].x + mf * dx[u], 0.0f, xmaxf);
+                    const float cy = __builtin_amdgcn_fmed3f(x[u].y + mf * dy[u], 0.0f, ymaxf);
+                    if (sample1(rho, taps_of(cx, cy, W, H)) >= r0[u]) {
                         jj[u] = k;
                         act[u] = false;
                     }

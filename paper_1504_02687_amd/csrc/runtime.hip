@@ -112,7 +112,7 @@ struct hb_ctx {
     } adj;
 
     // kernel variants (chunks of 64 per trip in resampling / advection)
-    int tune_ru = 1, tune_au = 2;
+    int tune_ru = 2, tune_au = 1;
 
     // captured iteration sequence, replayed while the batch layout is unchanged
     hipGraphExec_t gexec = nullptr;
@@ -525,8 +525,8 @@ HB_API hb_status hb_create(hb_ctx **out, int32_t device, void *hip_stream) {
             int u = v ? atoi(v) : dflt;
             return (u == 1 || u == 2 || u == 4) ? u : dflt;
         };
-        c->tune_ru = pick(getenv("HB_RESAMPLE_U"), 1);
-        c->tune_au = pick(getenv("HB_ADVECT_U"), 2);
+        c->tune_ru = pick(getenv("HB_RESAMPLE_U"), 2);
+        c->tune_au = pick(getenv("HB_ADVECT_U"), 1);
     }
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;
