@@ -241,10 +241,14 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
                     out = ld2(p + (m - 1));
                 } else {
                     const double s = __dmul_rn((double)k, ds);
-                    int lo = 0, hi = nsegT - 1;
-                    while (lo < hi) {
-                        int mid = (lo + hi + 1) >> 1;
-                        if (sC[wid][mid] <= s) lo = mid; else hi = mid - 1;
+                    // last segment of the chunk that starts at or before s (branch-free
+                    // binary search over the LDS arclengths)
+                    int lo = 0;
+#pragma unroll
+                    for (int step = 32 * U; step >= 1; step >>= 1) {
+                        const int c = lo + step;
+                        const int cc = c < nsegT ? c : nsegT - 1;
+                        if (c < nsegT && sC[wid][cc] <= s) lo = c;
                     }
                     const float2 pa = sP[wid][lo], pb = sP[wid][lo + 1];
                     const double ex = (double)pb.x - (double)pa.x, ey = (double)pb.y - (double)pa.y;
@@ -289,26 +293,43 @@ __global__ __launch_bounds__(kBlock) void k_bin_samples(const GDesc *__restrict_
     const uint32_t wbits = (uint32_t)(d.weight ? d.weight[e] : 1) << kLocalBits;
     const HB_G float2 *__restrict__ xs = glb(d.samples + o0);
     HB_G uint32_t *bins = glb(d.bins);
-    for (int64_t j0 = 0; j0 < n; j0 += 64) {
-        const int64_t k = j0 + lane;
-        const int cnt = (int)(n - j0 < 64 ? n - j0 : 64);
-        int key = 0;
-        uint32_t loc = 0;
-        if (k < n) bin_of(d, layer, ld2(xs + k), key, loc);
-        const uint64_t heads = run_heads(key, lane, cnt);
-        const bool head = (heads >> lane) & 1ull;
-        if (!SCATTER) {
-            if (head) atomicAdd((unsigned long long *)(ctr + key), (unsigned long long)run_length(heads, lane, cnt));
-        } else {
-            unsigned long long base = 0;
-            if (head)
-                base = atomicAdd((unsigned long long *)(ctr + key), (unsigned long long)run_length(heads, lane, cnt));
-            const int h = run_head(heads, lane);
-            base = __shfl(base, h, 64);
-            if (k < n) {
-                const unsigned long long pos = base + (unsigned long long)(lane - h);
-                if (pos < (unsigned long long)d.cap) bins[pos] = loc | wbits;
-                else atomicOr(d.status, ST_BIN_MISMATCH);
+    // four chunks per trip: their atomics are in flight together
+    constexpr int U = 4;
+    for (int64_t j0 = 0; j0 < n; j0 += 64 * U) {
+        int key[U], cnt[U];
+        uint32_t loc[U];
+        uint64_t heads[U];
+        unsigned long long base[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t k = j0 + 64 * u + lane;
+            const int64_t r = n - j0 - 64 * u;
+            cnt[u] = (int)(r <= 0 ? 0 : (r < 64 ? r : 64));
+            key[u] = 0;
+            loc[u] = 0;
+            if (k < n) bin_of(d, layer, ld2(xs + k), key[u], loc[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            heads[u] = run_heads(key[u], lane, cnt[u]);
+            base[u] = 0;
+            if ((heads[u] >> lane) & 1ull) {
+                unsigned long long *c = (unsigned long long *)(ctr + key[u]);
+                const unsigned long long len = (unsigned long long)run_length(heads[u], lane, cnt[u]);
+                if (SCATTER) base[u] = atomicAdd(c, len);
+                else atomicAdd(c, len);
+            }
+        }
+        if (SCATTER) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int h = run_head(heads[u], lane);
+                const unsigned long long b0 = __shfl(base[u], h, 64);
+                if (lane < cnt[u]) {
+                    const unsigned long long pos = b0 + (unsigned long long)(lane - h);
+                    if (pos < (unsigned long long)d.cap) bins[pos] = loc[u] | wbits;
+                    else atomicOr(d.status, ST_BIN_MISMATCH);
+                }
             }
         }
     }
