@@ -111,8 +111,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
     HB_FIND(blk_edge);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int64_t e = (blk - d.blk_edge) * kWavesPerBlock + wid;
-    if (e >= d.n_edges) return;
+    // edges in the given order (by group, then position), dealt round-robin: the blocks in
+    // flight work on one or two layers, whose gradient-map records then stay in the caches
+    const int64_t idx = (blk - d.blk_edge) * kWavesPerBlock + wid;
+    if (idx >= d.n_edges) return;
+    const int64_t e = d.perm ? (int64_t)d.perm[idx] : idx;
 
     const int W = d.W, H = d.H, B = d.B, P = d.P;
     const int64_t plane = (int64_t)W * H;

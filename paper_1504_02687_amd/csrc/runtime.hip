@@ -40,6 +40,7 @@ struct hb_ctx {
     int32_t B = 0;
     bool have_groups = false;
     int32_t *d_group = nullptr, *d_weight = nullptr, *d_perm = nullptr;
+    int32_t *d_perm_adj = nullptr;       // edge order of the advection adjoint (built on use)
     std::vector<int32_t> h_group;
     std::vector<uint32_t> h_morton;     // Morton code of each straight edge's midpoint
     float *d_M = nullptr;
@@ -566,6 +567,7 @@ HB_API void hb_destroy(hb_ctx *c) {
         (void)hipStreamSynchronize(c->stream);
         dfree(&c->d_group);
         dfree(&c->d_perm);
+        dfree(&c->d_perm_adj);
         dfree(&c->d_weight);
         dfree(&c->d_M);
         for (int i = 0; i < 2; ++i) {
@@ -717,6 +719,7 @@ HB_API hb_status hb_set_graph(hb_ctx *c, int32_t n_nodes, const float *node_xy, 
             c->h_morton[e] = spread((uint32_t)(mx * 65535.0)) | (spread((uint32_t)(my * 65535.0)) << 1);
         }
         dfree(&c->d_perm);
+        dfree(&c->d_perm_adj);
     }
     c->have_graph = false;
     c->have_samples = false;
@@ -789,17 +792,25 @@ HB_API hb_status hb_set_graph(hb_ctx *c, int32_t n_nodes, const float *node_xy, 
     return HB_OK;
 }
 
-// Edges sorted by group, then by the Morton code of their straight midpoint.
+// Edges sorted by group, then by the Morton code of their straight midpoint on a 256 x 256
+// grid of cells (a stable counting sort, linear in the edge count).
 static std::vector<int32_t> spatial_order(const hb_ctx *c) {
-    std::vector<int32_t> perm((size_t)c->E);
-    for (int64_t e = 0; e < c->E; ++e) perm[e] = (int32_t)e;
+    const int64_t E = c->E;
     const std::vector<uint32_t> &mc = c->h_morton;
     const std::vector<int32_t> &g = c->h_group;
-    const bool by_group = (int64_t)g.size() == c->E;
-    std::stable_sort(perm.begin(), perm.end(), [&](int32_t a, int32_t b) {
-        if (by_group && g[a] != g[b]) return g[a] < g[b];
-        return mc[a] < mc[b];
-    });
+    const bool by_group = (int64_t)g.size() == E;
+    int32_t B = 1;
+    if (by_group)
+        for (int32_t v : g) B = std::max(B, v + 1);
+    const int64_t nkey = (int64_t)B << 16;
+    auto key = [&](int64_t e) -> int64_t {
+        return ((int64_t)(by_group ? g[e] : 0) << 16) | (int64_t)(mc[e] >> 16);
+    };
+    std::vector<int64_t> start((size_t)nkey + 1, 0);
+    for (int64_t e = 0; e < E; ++e) ++start[(size_t)key(e) + 1];
+    for (int64_t k = 0; k < nkey; ++k) start[(size_t)k + 1] += start[(size_t)k];
+    std::vector<int32_t> perm((size_t)E);
+    for (int64_t e = 0; e < E; ++e) perm[(size_t)start[(size_t)key(e)]++] = (int32_t)e;
     return perm;
 }
 
@@ -826,6 +837,7 @@ HB_API hb_status hb_set_groups(hb_ctx *c, int32_t n_groups, const int32_t *group
     // edges by group, then by position, which keeps an XCD's density gathers in its L2 but
     // concentrates the memory-side splat atomics
     dfree(&c->d_perm);
+    dfree(&c->d_perm_adj);
     c->h_group = hg;
     if (const char *ord = getenv("HB_EDGE_ORDER"); ord && atoi(ord) == 1) {
         const std::vector<int32_t> perm = spatial_order(c);
@@ -1545,6 +1557,11 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
     CHKST(grow(c, &A.gb, A.cap_gb, (int64_t)B * plane * rec, "gradient maps"));
     CHKST(grow(c, &A.partials, A.cap_part, std::max<int64_t>(1, E) * (B + P), "partials"));
     CHKST(grow(c, &A.gparam, A.cap_gp, (int64_t)(B * B + P), "parameter gradients"));
+    if (!c->d_perm_adj && E > 0) {
+        const std::vector<int32_t> perm = spatial_order(c);
+        CHKST(dalloc(c, &c->d_perm_adj, perm.size(), "adjoint edge order"));
+        CHKST(upload(c, c->d_perm_adj, perm));
+    }
     HIPCHK(c, hipMemsetAsync(A.gparam, 0, sizeof(double) * (B * B + P), c->stream));
 
     // loss: total length of the final polylines (the lengths the last advection wrote)
@@ -1578,6 +1595,7 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
         a.partials = A.partials;
         a.grad_param = A.gparam;
         GDesc q = a;                            // resampling adjoint
+        a.perm = c->d_perm_adj;
         q.pin = k.pts;
         q.off_in = k.off;
         q.lens = k.lens;
