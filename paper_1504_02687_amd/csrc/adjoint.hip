@@ -144,8 +144,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
         float2 ybar = make_float2(0.0f, 0.0f);
         if (inr) ybar = yb[j];
         const double qx = interior ? (double)ybar.x : 0.0, qy = interior ? (double)ybar.y : 0.0;
-        const double qlx = __shfl_up(qx, 1, 64), qly = __shfl_up(qy, 1, 64);
-        const double qrx = __shfl_down(qx, 1, 64), qry = __shfl_down(qy, 1, 64);
+        const double qlx = lane_prev(qx, 0.0), qly = lane_prev(qy, 0.0);
+        const double qrx = lane_next(qx, 0.0), qry = lane_next(qy, 0.0);
         if (!(lane >= 1 && lane <= 62 && j < n)) continue;
         const double cf = interior ? 1.0 - s : 1.0;
         double wx = cf * (double)ybar.x + 0.5 * s * (qlx + qrx);
@@ -251,13 +251,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
         float2 a = make_float2(0.0f, 0.0f);
         if (lane <= nseg && lane < 64) a = p[j0 + lane];
         float2 b;
-        b.x = __shfl_down(a.x, 1, 64);
-        b.y = __shfl_down(a.y, 1, 64);
+        b.x = lane_next(a.x, 0.0f);
+        b.y = lane_next(a.y, 0.0f);
         if (lane == 63 && nseg == 64) b = p[j0 + 64];
         const double ell = lane < nseg ? seg_len(a, b) : 0.0;
         const double incl = wave_incl_scan<double>(ell, lane);
-        double excl = __shfl_up(incl, 1, 64);
-        if (lane == 0) excl = 0.0;
+        const double excl = lane_prev(incl, 0.0);
         if (lane < nseg) {
             sC[wid][lane] = Cbase + excl;
             sR[wid][lane] = ell > 0.0 ? 1.0 / ell : 0.0;
@@ -265,7 +264,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
             for (int c = 0; c < 6; ++c) acc[wid][c][lane] = 0.0;
         }
         if (lane == nseg - 1) sP[wid][nseg] = b;
-        const double Cend = Cbase + __shfl(incl, 63, 64);
+        const double Cend = Cbase + last_lane(incl);
         __builtin_amdgcn_wave_barrier();
 
         const bool last = (j0 + 64 >= m - 1);
@@ -318,17 +317,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
                 v[4] = -tb * sR[wid][jl];
                 v[5] = -tb * t * sR[wid][jl];
             }
-            // segmented inclusive scan over runs of equal segment index
-#pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int ko = __shfl_up(jl, o, 64);
-#pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    const double vo = __shfl_up(v[c], o, 64);
-                    if (lane >= o && ko == jl) v[c] += vo;
-                }
-            }
-            const int knx = __shfl_down(jl, 1, 64);
+            // segmented inclusive scan over runs of equal segment index (the segment index
+            // grows with the sample; idle lanes carry larger, distinct keys)
+            wave_seg_scan<6>(v, jl);
+            const int knx = lane_next(jl, -1);
             if (valid && (lane == 63 || knx != jl))
                 for (int c = 0; c < 6; ++c) acc[wid][c][jl] += v[c];
             __builtin_amdgcn_wave_barrier();
@@ -349,8 +341,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
         const double Pin = carryP + wave_incl_scan<double>(Cb, lane);
         const double Vx = lane < nseg ? (lb - Pin) * ux : 0.0;
         const double Vy = lane < nseg ? (lb - Pin) * uy : 0.0;
-        double Bpx = __shfl_up(Bx, 1, 64), Bpy = __shfl_up(By, 1, 64);
-        double Vpx = __shfl_up(Vx, 1, 64), Vpy = __shfl_up(Vy, 1, 64);
+        double Bpx = lane_prev(Bx, 0.0), Bpy = lane_prev(By, 0.0);
+        double Vpx = lane_prev(Vx, 0.0), Vpy = lane_prev(Vy, 0.0);
         if (lane == 0) {
             Bpx = carryBx;
             Bpy = carryBy;
@@ -359,11 +351,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
         }
         if (lane < nseg || (last && lane == nseg))
             pb[j0 + lane] = make_float2((float)(Ax + Bpx - Vx + Vpx), (float)(Ay + Bpy - Vy + Vpy));
-        carryBx = __shfl(Bx, nseg - 1, 64);
-        carryBy = __shfl(By, nseg - 1, 64);
-        carryVx = __shfl(Vx, nseg - 1, 64);
-        carryVy = __shfl(Vy, nseg - 1, 64);
-        carryP = __shfl(Pin, nseg - 1, 64);
+        carryBx = read_lane(Bx, nseg - 1);
+        carryBy = read_lane(By, nseg - 1);
+        carryVx = read_lane(Vx, nseg - 1);
+        carryVy = read_lane(Vy, nseg - 1);
+        carryP = read_lane(Pin, nseg - 1);
         if (last && nseg == 64 && lane == 0)
             pb[j0 + 64] = make_float2((float)(carryBx + carryVx), (float)(carryBy + carryVy));
         __builtin_amdgcn_wave_barrier();
