@@ -60,42 +60,51 @@ __global__ __launch_bounds__(kBlock) void k_ink_grad(const GDesc *__restrict__ g
 //                                    m v . bilinear(gb[b])
 //   gl[l][k] = sum_b M[l][b] D_bk    dL/da_k     = sum over moved points of layer l of
 //                                    m v . bilinear(gl[l][k])
-// Stored interleaved per layer and pixel: record (l, px) holds gb[0..B), then gl[l][0..P),
-// padded to an even number of float2 (16-byte aligned), so a bilinear tap of all B + P maps
-// is a few contiguous 16-byte loads. One thread per (layer, pixel).
+// gb does not depend on the layer: one record of B float2 per pixel serves every layer, and
+// layer l has its own record of P float2 per pixel (records padded to 16-byte multiples, so a
+// bilinear tap is a few 16-byte loads). One thread per pixel, all layers.
 __global__ __launch_bounds__(kBlock) void k_adj_maps(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
-    HB_FIND(blk_pxb);
-    const int W = d.W, H = d.H, B = d.B, P = d.P, R = d.rec;
+    HB_FIND(blk_px);
+    const int W = d.W, H = d.H, B = d.B, P = d.P, bp = d.bp, pp = d.pp;
     const int64_t plane = (int64_t)W * H;
-    const int64_t i = (blk - d.blk_pxb) * kBlock + threadIdx.x;
-    if (i >= (int64_t)B * plane) return;
-    const int64_t l = i / plane, px = i % plane;
+    const int64_t px = (blk - d.blk_px) * kBlock + threadIdx.x;
+    if (px >= plane) return;
     const int u = (int)(px % W), v = (int)(px / W);
     const bool hasr = u + 1 < W, hasl = u > 0, hasu = v + 1 < H, hasd = v > 0;
-    float2 *out = d.gsk + i * R;
-    for (int b = 0; b < B; ++b) out[b] = make_float2(0.0f, 0.0f);
+    float2 *gb = d.gbm + px * bp;
+    for (int b = 0; b < bp; ++b) gb[b] = make_float2(0.0f, 0.0f);
+    for (int l = 0; l < B; ++l)
+        for (int k = P; k < pp; ++k) d.gkm[((int64_t)l * plane + px) * pp + k] = make_float2(0.0f, 0.0f);
     for (int k = 0; k < P; ++k) {
-        double ax = 0.0, ay = 0.0;
         for (int b = 0; b < B; ++b) {
             const int64_t *S = d.box + ((int64_t)k * B + b) * plane + px;
             const int64_t xr = hasr ? S[1] : 0, xl = hasl ? S[-1] : 0;
             const int64_t yu = hasu ? S[W] : 0, yd = hasd ? S[-W] : 0;
             const double dx = 0.5 * ((double)(xr - xl) / d.ck[k]);
             const double dy = 0.5 * ((double)(yu - yd) / d.ck[k]);
-            const double mlb = (double)d.M[l * B + b];
-            ax += mlb * dx;
-            ay += mlb * dy;
             if (d.a[k] != 0.0) {
-                float2 g = out[b];
+                float2 g = gb[b];
                 g.x = (float)((double)g.x + d.a[k] * dx);
                 g.y = (float)((double)g.y + d.a[k] * dy);
-                out[b] = g;
+                gb[b] = g;
             }
         }
-        out[B + k] = make_float2((float)ax, (float)ay);
+        for (int l = 0; l < B; ++l) {
+            double ax = 0.0, ay = 0.0;
+            for (int b = 0; b < B; ++b) {
+                const int64_t *S = d.box + ((int64_t)k * B + b) * plane + px;
+                const int64_t xr = hasr ? S[1] : 0, xl = hasl ? S[-1] : 0;
+                const int64_t yu = hasu ? S[W] : 0, yd = hasd ? S[-W] : 0;
+                const double dx = 0.5 * ((double)(xr - xl) / d.ck[k]);
+                const double dy = 0.5 * ((double)(yu - yd) / d.ck[k]);
+                const double mlb = (double)d.M[l * B + b];
+                ax += mlb * dx;
+                ay += mlb * dy;
+            }
+            d.gkm[((int64_t)l * plane + px) * pp + k] = make_float2((float)ax, (float)ay);
+        }
     }
-    for (int q = B + P; q < R; ++q) out[q] = make_float2(0.0f, 0.0f);
 }
 
 // Transposed Laplacian smoothing and advection, fused. One wave per edge, chunks of 62
@@ -129,13 +138,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
     const double h = d.h, s = d.s, eps = d.eps;
     const double xmax = (double)W - 1.0 / 256.0, ymax = (double)H - 1.0 / 256.0;
 
-    // record of the interleaved gradient maps of this layer: B + P float2, padded to RMAX2
-    constexpr int RMAX2 = (BMAX + HB_MAX_PASSES + 1) / 2;   // 16-byte pieces per record
-    const int R = d.rec, nq = B + P;
-    const float4 *__restrict__ G = (const float4 *)(d.gsk + (int64_t)l * plane * R);
-    double acc[2 * RMAX2];
+    // gradient-map records: the groups' record (shared by every layer) and this layer's
+    // record of the passes
+    constexpr int BH = (BMAX + 1) / 2, PH = HB_MAX_PASSES / 2;   // 16-byte pieces, at most
+    const int bh = d.bp / 2, ph = d.pp / 2;
+    const float4 *__restrict__ GB = (const float4 *)d.gbm;
+    const float4 *__restrict__ GK = (const float4 *)(d.gkm + (int64_t)l * plane * d.pp);
+    double accb[2 * BH], acck[2 * PH];
 #pragma unroll
-    for (int q = 0; q < 2 * RMAX2; ++q) acc[q] = 0.0;
+    for (int q = 0; q < 2 * BH; ++q) accb[q] = 0.0;
+#pragma unroll
+    for (int q = 0; q < 2 * PH; ++q) acck[q] = 0.0;
 
     for (int64_t j0 = 0; j0 < n; j0 += 62) {
         const int64_t j = j0 - 1 + lane;
@@ -184,29 +197,47 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
             const float ftx = t0.tx, fty = t0.ty;
             const float w00 = (1.0f - ftx) * (1.0f - fty), w10 = ftx * (1.0f - fty);
             const float w01 = (1.0f - ftx) * fty, w11 = ftx * fty;
-            const int64_t h2 = R / 2;
-            const float4 *r00 = G + (int64_t)t0.o00 * h2, *r10 = G + (int64_t)t0.o10 * h2;
-            const float4 *r01 = G + (int64_t)t0.o01 * h2, *r11 = G + (int64_t)t0.o11 * h2;
+            const float4 *b00 = GB + (int64_t)t0.o00 * bh, *b10 = GB + (int64_t)t0.o10 * bh;
+            const float4 *b01 = GB + (int64_t)t0.o01 * bh, *b11 = GB + (int64_t)t0.o11 * bh;
 #pragma unroll
-            for (int q2 = 0; q2 < RMAX2; ++q2) {
-                if (2 * q2 >= nq) break;
-                const float4 a00 = r00[q2], a10 = r10[q2], a01 = r01[q2], a11 = r11[q2];
+            for (int q2 = 0; q2 < BH; ++q2) {
+                if (q2 >= bh) break;
+                const float4 a00 = b00[q2], a10 = b10[q2], a01 = b01[q2], a11 = b11[q2];
                 const float gx0 = w00 * a00.x + w10 * a10.x + w01 * a01.x + w11 * a11.x;
                 const float gy0 = w00 * a00.y + w10 * a10.y + w01 * a01.y + w11 * a11.y;
                 const float gx1 = w00 * a00.z + w10 * a10.z + w01 * a01.z + w11 * a11.z;
                 const float gy1 = w00 * a00.w + w10 * a10.w + w01 * a01.w + w11 * a11.w;
-                acc[2 * q2] += (double)(mvx * gx0 + mvy * gy0);
-                acc[2 * q2 + 1] += (double)(mvx * gx1 + mvy * gy1);
+                accb[2 * q2] += (double)(mvx * gx0 + mvy * gy0);
+                accb[2 * q2 + 1] += (double)(mvx * gx1 + mvy * gy1);
+            }
+            const float4 *k00 = GK + (int64_t)t0.o00 * ph, *k10 = GK + (int64_t)t0.o10 * ph;
+            const float4 *k01 = GK + (int64_t)t0.o01 * ph, *k11 = GK + (int64_t)t0.o11 * ph;
+#pragma unroll
+            for (int q2 = 0; q2 < PH; ++q2) {
+                if (q2 >= ph) break;
+                const float4 a00 = k00[q2], a10 = k10[q2], a01 = k01[q2], a11 = k11[q2];
+                const float gx0 = w00 * a00.x + w10 * a10.x + w01 * a01.x + w11 * a11.x;
+                const float gy0 = w00 * a00.y + w10 * a10.y + w01 * a01.y + w11 * a11.y;
+                const float gx1 = w00 * a00.z + w10 * a10.z + w01 * a01.z + w11 * a11.z;
+                const float gy1 = w00 * a00.w + w10 * a10.w + w01 * a01.w + w11 * a11.w;
+                acck[2 * q2] += (double)(mvx * gx0 + mvy * gy0);
+                acck[2 * q2 + 1] += (double)(mvx * gx1 + mvy * gy1);
             }
         }
         xb[j] = make_float2((float)gxb, (float)gyb);
     }
     double *out = d.partials + e * (int64_t)(B + P);
 #pragma unroll
-    for (int q = 0; q < 2 * RMAX2; ++q) {
-        if (q >= nq) break;
-        const double v = wave_sum(acc[q]);
+    for (int q = 0; q < 2 * BH; ++q) {
+        if (q >= B) break;
+        const double v = wave_sum(accb[q]);
         if (lane == 0) out[q] = v;
+    }
+#pragma unroll
+    for (int q = 0; q < 2 * PH; ++q) {
+        if (q >= P) break;
+        const double v = wave_sum(acck[q]);
+        if (lane == 0) out[B + q] = v;
     }
 }
 
@@ -319,7 +350,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
             }
             // segmented inclusive scan over runs of equal segment index (the segment index
             // grows with the sample; idle lanes carry larger, distinct keys)
-            wave_seg_scan<6>(v, jl);
+#pragma unroll
+            for (int o = 1; o < 64; o <<= 1) {
+                const int ko = __shfl_up(jl, o, 64);
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    const double vo = __shfl_up(v[c], o, 64);
+                    if (lane >= o && ko == jl) v[c] += vo;
+                }
+            }
             const int knx = lane_next(jl, -1);
             if (valid && (lane == 63 || knx != jl))
                 for (int c = 0; c < 6; ++c) acc[wid][c][jl] += v[c];
@@ -428,7 +467,7 @@ hipError_t launch_ink_grad(const GDesc *desc, const Shape &tot, hipStream_t st) 
 }
 
 hipError_t launch_adj_maps(const GDesc *desc, const Shape &tot, hipStream_t st) {
-    hipLaunchKernelGGL(k_adj_maps, grid1(tot.pxb), dim3(kBlock), 0, st, desc, 1);
+    hipLaunchKernelGGL(k_adj_maps, grid1(tot.px), dim3(kBlock), 0, st, desc, 1);
     return hipGetLastError();
 }
 

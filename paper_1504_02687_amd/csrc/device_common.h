@@ -110,31 +110,6 @@ __device__ __forceinline__ double read_lane(double v, int l) {
     return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// One step of a segmented scan: add the values of the lane selected by CTRL when it has the
-// same key.
-template <int CTRL, int ROWS, int N>
-__device__ __forceinline__ void seg_step(double (&v)[N], int key) {
-    const bool same = dpp<CTRL, ROWS>(-1, key) == key;
-#pragma unroll
-    for (int c = 0; c < N; ++c) {
-        const double t = dpp<CTRL, ROWS>(0.0, v[c]);
-        if (same) v[c] += t;
-    }
-}
-
-// Segmented inclusive sums of N values over the lanes (every lane active). Lanes with
-// equal keys form a segment; keys must be non-negative and non-decreasing along the lanes,
-// so a lane with the key of lane l - o belongs to the segment of every lane in between.
-template <int N>
-__device__ __forceinline__ void wave_seg_scan(double (&v)[N], int key) {
-    seg_step<kDppRowShr + 1, 0xf>(v, key);
-    seg_step<kDppRowShr + 2, 0xf>(v, key);
-    seg_step<kDppRowShr + 4, 0xf>(v, key);
-    seg_step<kDppRowShr + 8, 0xf>(v, key);
-    seg_step<kDppRowBcast15, 0xa>(v, key);
-    seg_step<kDppRowBcast31, 0xc>(v, key);
-}
-
 // Inclusive sum over lanes 0..l (every lane active): shifts by 1, 2, 4, 8 inside each row
 // of 16 lanes, then the row totals through the lane 15 and lane 31 broadcasts. The order of
 // the additions is fixed, so the result is reproducible.

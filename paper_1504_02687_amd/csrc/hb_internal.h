@@ -94,10 +94,10 @@ struct GDesc {
     // adjoint of one iteration (frozen decisions)
     const float2 *adj_in;       // adjoint of this stage's output points
     float2 *adj_out;            // adjoint of this stage's input points
-    float2 *gsk;                // [B][H][W][rec] per layer l and pixel: sum_k a_k D_bk for
-                                // b < B, then sum_b M[l][b] D_bk for k < P, zero padding;
-                                // D_bk = grad(pass k of group b) / (2r+1)^(2k)
-    int32_t rec;                // record length in float2 (B + P rounded up to even)
+    // D_bk = grad(pass k of group b) / (2r+1)^(2k); records padded to an even float2 count
+    float2 *gbm;                // [H][W][bp]: sum_k a_k D_bk for every group b (all layers)
+    float2 *gkm;                // [B][H][W][pp]: sum_b M[l][b] D_bk for every pass k, layer l
+    int32_t bp, pp;             // record lengths in float2 (B and P rounded up to even)
     double *partials;           // [E][B + P] per-edge parameter partials
     double *grad_param;         // [B*B + P] accumulated dL/dM (row-major) and dL/da
 };

@@ -1553,8 +1553,8 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
     hb_ctx::AdjBufs &A = c->adj;
     CHKST(grow(c, &A.a0, A.cap_pts, nmax, "adjoint"));
     CHKST(grow(c, &A.a1, A.cap_a1, nmax, "adjoint"));
-    const int rec = (B + P + 1) / 2 * 2;
-    CHKST(grow(c, &A.gb, A.cap_gb, (int64_t)B * plane * rec, "gradient maps"));
+    const int bp = (B + 1) / 2 * 2, pp = (P + 1) / 2 * 2;
+    CHKST(grow(c, &A.gb, A.cap_gb, plane * (bp + (int64_t)B * pp), "gradient maps"));
     CHKST(grow(c, &A.partials, A.cap_part, std::max<int64_t>(1, E) * (B + P), "partials"));
     CHKST(grow(c, &A.gparam, A.cap_gp, (int64_t)(B * B + P), "parameter gradients"));
     if (!c->d_perm_adj && E > 0) {
@@ -1588,8 +1588,10 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
         a.samples = k.xs;
         a.off_s = k.xoff;
         a.jacc = k.jacc;
-        a.gsk = A.gb;
-        a.rec = rec;
+        a.gbm = A.gb;
+        a.gkm = A.gb + plane * bp;
+        a.bp = bp;
+        a.pp = pp;
         a.adj_in = cur;
         a.adj_out = other;
         a.partials = A.partials;
