@@ -226,18 +226,19 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
         }
         xb[j] = make_float2((float)gxb, (float)gyb);
     }
-    double *out = d.partials + e * (int64_t)(B + P);
+    double *out = d.partials + idx;
+    const int64_t E = d.n_edges;
 #pragma unroll
     for (int q = 0; q < 2 * BH; ++q) {
         if (q >= B) break;
         const double v = wave_sum(accb[q]);
-        if (lane == 0) out[q] = v;
+        if (lane == 0) out[q * E] = v;
     }
 #pragma unroll
     for (int q = 0; q < 2 * PH; ++q) {
         if (q >= P) break;
         const double v = wave_sum(acck[q]);
-        if (lane == 0) out[B + q] = v;
+        if (lane == 0) out[(B + q) * E] = v;
     }
 }
 
@@ -430,22 +431,29 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
     }
 }
 
-// dL/dM[l][b] += sum over edges of layer l of partials[e][b]; dL/da_k += sum over all edges
-// of partials[e][B + k]. One block per entry; fixed per-thread order and a fixed tree.
+// dL/dM[l][b] += sum over the edges of layer l of their partial b; dL/da_k += sum over all
+// edges of their partial B + k. Two fixed-order stages: block (q, slice) sums one slice of
+// parameter q's contiguous range of the column-major partials (fixed per-thread order and
+// a fixed tree), then one thread per parameter adds its slice sums in order.
 __global__ __launch_bounds__(kBlock) void k_adj_reduce(const GDesc *__restrict__ gd, int ng) {
     const GDesc &d = gd[0];
-    const int B = d.B, P = d.P;
-    const int q = blockIdx.x;
-    int l = -1, col;
+    const int B = d.B;
+    const int q = (int)blockIdx.x / kRedSlices, sl = (int)blockIdx.x % kRedSlices;
+    int64_t lo = 0, hi = d.n_edges;
+    int col;
     if (q < B * B) {
-        l = q / B;
+        const int l = q / B;
         col = q % B;
+        lo = d.gstart[l];
+        hi = d.gstart[l + 1];
     } else {
         col = B + (q - B * B);
     }
+    const int64_t per = (hi - lo + kRedSlices - 1) / kRedSlices;
+    const int64_t a = lo + sl * per, b = a + per < hi ? a + per : hi;
+    const double *p = d.partials + (int64_t)col * d.n_edges;
     double s = 0.0;
-    for (int64_t e = threadIdx.x; e < d.n_edges; e += kBlock)
-        if (l < 0 || d.group[e] == l) s += d.partials[e * (B + P) + col];
+    for (int64_t i = a + threadIdx.x; i < b; i += kBlock) s += p[i];
     __shared__ double red[kBlock];
     red[threadIdx.x] = s;
     __syncthreads();
@@ -453,7 +461,17 @@ __global__ __launch_bounds__(kBlock) void k_adj_reduce(const GDesc *__restrict__
         if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
         __syncthreads();
     }
-    if (threadIdx.x == 0) d.grad_param[q] += red[0];
+    if (threadIdx.x == 0) d.red[(int64_t)q * kRedSlices + sl] = red[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_adj_reduce_sum(const GDesc *__restrict__ gd, int ng) {
+    const GDesc &d = gd[0];
+    const int nq = d.B * d.B + d.P;
+    for (int q = threadIdx.x; q < nq; q += kBlock) {
+        double s = 0.0;
+        for (int sl = 0; sl < kRedSlices; ++sl) s += d.red[(int64_t)q * kRedSlices + sl];
+        d.grad_param[q] += s;
+    }
 }
 
 // ---------------------------------------------------------------- launchers
@@ -489,7 +507,10 @@ hipError_t launch_adj_resample(const GDesc *desc, const Shape &tot, hipStream_t 
 }
 
 hipError_t launch_adj_reduce(const GDesc *desc, int B, int P, hipStream_t st) {
-    hipLaunchKernelGGL(k_adj_reduce, dim3(B * B + P), dim3(kBlock), 0, st, desc, 1);
+    hipLaunchKernelGGL(k_adj_reduce, dim3((B * B + P) * kRedSlices), dim3(kBlock), 0, st, desc, 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_adj_reduce_sum, dim3(1), dim3(kBlock), 0, st, desc, 1);
     return hipGetLastError();
 }
 

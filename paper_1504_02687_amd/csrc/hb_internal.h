@@ -31,6 +31,7 @@ constexpr int kBinSetsMax = 64;                     // tile-count sets (edge blo
 constexpr int64_t kBinCounters = 1 << 18;          // counters of all sets, at most (unless 1 set)
 constexpr int64_t kSegEntries = 1 << 16;            // entries per tile-histogram work item
 constexpr int kTileBlocksMax = 2048;                // blocks of one graph in k_tile_hist
+constexpr int kRedSlices = 32;                      // slices per parameter in k_adj_reduce
 static_assert(HB_MAX_EDGE_WEIGHT < (1u << (32 - kLocalBits)), "weights must fit an entry");
 
 // One graph of one iteration. Every kernel takes an array of these (one per graph of a
@@ -98,7 +99,10 @@ struct GDesc {
     float2 *gbm;                // [H][W][bp]: sum_k a_k D_bk for every group b (all layers)
     float2 *gkm;                // [B][H][W][pp]: sum_b M[l][b] D_bk for every pass k, layer l
     int32_t bp, pp;             // record lengths in float2 (B and P rounded up to even)
-    double *partials;           // [E][B + P] per-edge parameter partials
+    double *partials;           // [B + P][E] parameter partials, column-major, edges in the
+                                // advection adjoint's order (by group)
+    const int64_t *gstart;      // [B + 1] first position of each group in that order
+    double *red;                // [B*B + P][kRedSlices] slice sums of the reduction
     double *grad_param;         // [B*B + P] accumulated dL/dM (row-major) and dL/da
 };
 

@@ -41,6 +41,7 @@ struct hb_ctx {
     bool have_groups = false;
     int32_t *d_group = nullptr, *d_weight = nullptr, *d_perm = nullptr;
     int32_t *d_perm_adj = nullptr;       // edge order of the advection adjoint (built on use)
+    int64_t *d_gstart_adj = nullptr;     // first position of each group in that order
     std::vector<int32_t> h_group;
     std::vector<uint32_t> h_morton;     // Morton code of each straight edge's midpoint
     float *d_M = nullptr;
@@ -108,8 +109,8 @@ struct hb_ctx {
     // adjoint work buffers, kept between backward passes
     struct AdjBufs {
         float2 *a0 = nullptr, *a1 = nullptr, *gb = nullptr;
-        double *partials = nullptr, *gparam = nullptr;
-        int64_t cap_pts = 0, cap_a1 = 0, cap_gb = 0, cap_part = 0, cap_gp = 0;
+        double *partials = nullptr, *gparam = nullptr, *red = nullptr;
+        int64_t cap_pts = 0, cap_a1 = 0, cap_gb = 0, cap_part = 0, cap_gp = 0, cap_red = 0;
     } adj;
 
     // kernel variants (chunks of 64 per trip in resampling / advection)
@@ -568,6 +569,7 @@ HB_API void hb_destroy(hb_ctx *c) {
         dfree(&c->d_group);
         dfree(&c->d_perm);
         dfree(&c->d_perm_adj);
+        dfree(&c->d_gstart_adj);
         dfree(&c->d_weight);
         dfree(&c->d_M);
         for (int i = 0; i < 2; ++i) {
@@ -720,6 +722,7 @@ HB_API hb_status hb_set_graph(hb_ctx *c, int32_t n_nodes, const float *node_xy, 
         }
         dfree(&c->d_perm);
         dfree(&c->d_perm_adj);
+        dfree(&c->d_gstart_adj);
     }
     c->have_graph = false;
     c->have_samples = false;
@@ -838,6 +841,7 @@ HB_API hb_status hb_set_groups(hb_ctx *c, int32_t n_groups, const int32_t *group
     // concentrates the memory-side splat atomics
     dfree(&c->d_perm);
     dfree(&c->d_perm_adj);
+    dfree(&c->d_gstart_adj);
     c->h_group = hg;
     if (const char *ord = getenv("HB_EDGE_ORDER"); ord && atoi(ord) == 1) {
         const std::vector<int32_t> perm = spatial_order(c);
@@ -1452,6 +1456,7 @@ static void free_ckpts(hb_ctx *c) {
     dfree(&c->adj.gb);
     dfree(&c->adj.partials);
     dfree(&c->adj.gparam);
+    dfree(&c->adj.red);
     c->adj = hb_ctx::AdjBufs();
 }
 
@@ -1557,10 +1562,16 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
     CHKST(grow(c, &A.gb, A.cap_gb, plane * (bp + (int64_t)B * pp), "gradient maps"));
     CHKST(grow(c, &A.partials, A.cap_part, std::max<int64_t>(1, E) * (B + P), "partials"));
     CHKST(grow(c, &A.gparam, A.cap_gp, (int64_t)(B * B + P), "parameter gradients"));
-    if (!c->d_perm_adj && E > 0) {
+    CHKST(grow(c, &A.red, A.cap_red, (int64_t)(B * B + P) * hb::kRedSlices, "reduction"));
+    if (!c->d_perm_adj) {
         const std::vector<int32_t> perm = spatial_order(c);
-        CHKST(dalloc(c, &c->d_perm_adj, perm.size(), "adjoint edge order"));
+        std::vector<int64_t> gstart((size_t)B + 1, 0);
+        for (int32_t g : c->h_group) ++gstart[(size_t)g + 1];
+        for (int b = 0; b < B; ++b) gstart[(size_t)b + 1] += gstart[(size_t)b];
+        CHKST(dalloc(c, &c->d_perm_adj, std::max<size_t>(1, perm.size()), "adjoint edge order"));
         CHKST(upload(c, c->d_perm_adj, perm));
+        CHKST(dalloc(c, &c->d_gstart_adj, gstart.size(), "adjoint group starts"));
+        CHKST(upload(c, c->d_gstart_adj, gstart));
     }
     HIPCHK(c, hipMemsetAsync(A.gparam, 0, sizeof(double) * (B * B + P), c->stream));
 
@@ -1595,6 +1606,8 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
         a.adj_in = cur;
         a.adj_out = other;
         a.partials = A.partials;
+        a.gstart = c->d_gstart_adj;
+        a.red = A.red;
         a.grad_param = A.gparam;
         GDesc q = a;                            // resampling adjoint
         a.perm = c->d_perm_adj;
