@@ -124,7 +124,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
     // flight work on one or two layers, whose gradient-map records then stay in the caches
     const int64_t idx = (blk - d.blk_edge) * kWavesPerBlock + wid;
     if (idx >= d.n_edges) return;
-    const int64_t e = d.perm ? (int64_t)d.perm[idx] : idx;
+    const int64_t e = d.order ? (int64_t)d.order[idx] : idx;
 
     const int W = d.W, H = d.H, B = d.B, P = d.P;
     const int64_t plane = (int64_t)W * H;

@@ -57,6 +57,8 @@ struct GDesc {
     double ck[HB_MAX_PASSES];   // (2r+1)^(2k), k = 1..P
 
     const int32_t *perm;        // visiting order of the edges (nullptr: 0..E-1)
+    const int32_t *order;       // edge order of the advection kernels (by group, then position;
+                                // dealt round-robin; nullptr: 0..E-1)
     const int32_t *group;
     const int32_t *weight;      // nullptr: unit weights
     const float *M;             // B x B, M[l * B + b]

@@ -592,8 +592,11 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
     if (stopped(d)) return;
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int64_t e = edge_of(d, blk - d.blk_edge, wid);
-    if (e < 0) return;
+    // edges by group, then position, dealt round-robin: the blocks in flight read one or
+    // two layers of the maps, around nearby edges
+    const int64_t idx = (blk - d.blk_edge) * kWavesPerBlock + wid;
+    if (idx >= d.n_edges) return;
+    const int64_t e = d.order ? (int64_t)d.order[idx] : idx;
 
     const int W = d.W, H = d.H;
     const int64_t plane = (int64_t)W * H;

@@ -40,7 +40,7 @@ struct hb_ctx {
     int32_t B = 0;
     bool have_groups = false;
     int32_t *d_group = nullptr, *d_weight = nullptr, *d_perm = nullptr;
-    int32_t *d_perm_adj = nullptr;       // edge order of the advection adjoint (built on use)
+    int32_t *d_perm_adj = nullptr;       // edge order of the advection kernels (built on use)
     int64_t *d_gstart_adj = nullptr;     // first position of each group in that order
     std::vector<int32_t> h_group;
     std::vector<uint32_t> h_morton;     // Morton code of each straight edge's midpoint
@@ -394,6 +394,7 @@ static GDesc base_desc(const hb_ctx *c) {
         d.a[k] = c->passw.empty() ? (k == d.P - 1 ? 1.0 : 0.0) : (double)c->passw[k];
     d.group = c->d_group;
     d.perm = c->d_perm;
+    d.order = c->d_perm_adj;
     d.weight = c->d_weight;
     d.M = c->d_M;
     d.counts = c->d_counts;
@@ -857,7 +858,27 @@ HB_API hb_status hb_set_groups(hb_ctx *c, int32_t n_groups, const int32_t *group
 
 // ------------------------------------------------------------------ the iteration loop
 
+// Edge order of the advection kernels (by group, then position) and the first position of
+// each group in it; rebuilt after the graph or the groups change.
+static hb_status ensure_order(hb_ctx *c) {
+    if (c->d_perm_adj && c->d_gstart_adj) return HB_OK;
+    const int32_t B = std::max(1, c->B);
+    const std::vector<int32_t> order = spatial_order(c);
+    std::vector<int64_t> gstart((size_t)B + 1, 0);
+    if ((int64_t)c->h_group.size() == c->E)
+        for (int32_t g : c->h_group) ++gstart[(size_t)g + 1];
+    else
+        gstart[1] = c->E;
+    for (int b = 0; b < B; ++b) gstart[(size_t)b + 1] += gstart[(size_t)b];
+    CHKST(dalloc(c, &c->d_perm_adj, std::max<size_t>(1, order.size()), "advection edge order"));
+    CHKST(upload(c, c->d_perm_adj, order));
+    CHKST(dalloc(c, &c->d_gstart_adj, gstart.size(), "group starts"));
+    CHKST(upload(c, c->d_gstart_adj, gstart));
+    return HB_OK;
+}
+
 static hb_status prepare_ctx(hb_ctx *c, int T, uint32_t flags) {
+    CHKST(ensure_order(c));
     CHKST(ensure_maps(c));
     CHKST(ensure_totals(c, T));
     if ((flags & HB_RUN_RECORD_DECISIONS) && c->jacc_cap < c->cap) {
@@ -1563,16 +1584,7 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
     CHKST(grow(c, &A.partials, A.cap_part, std::max<int64_t>(1, E) * (B + P), "partials"));
     CHKST(grow(c, &A.gparam, A.cap_gp, (int64_t)(B * B + P), "parameter gradients"));
     CHKST(grow(c, &A.red, A.cap_red, (int64_t)(B * B + P) * hb::kRedSlices, "reduction"));
-    if (!c->d_perm_adj) {
-        const std::vector<int32_t> perm = spatial_order(c);
-        std::vector<int64_t> gstart((size_t)B + 1, 0);
-        for (int32_t g : c->h_group) ++gstart[(size_t)g + 1];
-        for (int b = 0; b < B; ++b) gstart[(size_t)b + 1] += gstart[(size_t)b];
-        CHKST(dalloc(c, &c->d_perm_adj, std::max<size_t>(1, perm.size()), "adjoint edge order"));
-        CHKST(upload(c, c->d_perm_adj, perm));
-        CHKST(dalloc(c, &c->d_gstart_adj, gstart.size(), "adjoint group starts"));
-        CHKST(upload(c, c->d_gstart_adj, gstart));
-    }
+    CHKST(ensure_order(c));
     HIPCHK(c, hipMemsetAsync(A.gparam, 0, sizeof(double) * (B * B + P), c->stream));
 
     // loss: total length of the final polylines (the lengths the last advection wrote)
@@ -1610,7 +1622,6 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
         a.red = A.red;
         a.grad_param = A.gparam;
         GDesc q = a;                            // resampling adjoint
-        a.perm = c->d_perm_adj;
         q.pin = k.pts;
         q.off_in = k.off;
         q.lens = k.lens;
