@@ -251,6 +251,55 @@ __device__ __forceinline__ float2 ldo(const HB_G float2 *m, uint32_t i) {
 __device__ __forceinline__ float ldo(const float *m, uint32_t i) { return m[i]; }
 __device__ __forceinline__ float2 ldo(const float2 *m, uint32_t i) { return m[i]; }
 
+// Bilinear cell of a sample and the fractions between its taps (the same taps and
+// fractions as taps_of).
+struct Cell {
+    uint32_t c;
+    float tx, ty;
+};
+
+__device__ __forceinline__ Cell cell_of(float x, float y, int W, int H) {
+    const float fx = __builtin_amdgcn_fmed3f(x - 0.5f, -1.0f, (float)W);
+    const float fy = __builtin_amdgcn_fmed3f(y - 0.5f, -1.0f, (float)H);
+    const float u0f = floorf(fx), v0f = floorf(fy);
+    Cell t;
+    t.tx = fx - u0f;
+    t.ty = fy - v0f;
+    const int u0 = min((int)u0f, W - 1), v0 = min((int)v0f, H - 1);
+    t.c = __umul24((uint32_t)(v0 + 1), (uint32_t)(W + 1)) + (uint32_t)(u0 + 1);
+    return t;
+}
+
+__device__ __forceinline__ Quad ldq(const HB_G Quad *m, uint32_t i) {
+    typedef float f4v __attribute__((ext_vector_type(4)));
+    const f4v v = *(const HB_G f4v *)((const HB_G char *)m + ((uint64_t)i << 4));
+    Quad q;
+    q.a = v.x;
+    q.b = v.y;
+    q.c = v.z;
+    q.d = v.w;
+    return q;
+}
+
+// Density sample from a cell, in FP32 (same arithmetic as sample1).
+__device__ __forceinline__ float sample1q(const HB_G Quad *m, const Cell &t) {
+    const float tx = t.tx, ty = t.ty;
+    const Quad q = ldq(m, t.c);
+    return (1.0f - tx) * (1.0f - ty) * q.a + tx * (1.0f - ty) * q.b +
+           (1.0f - tx) * ty * q.c + tx * ty * q.d;
+}
+
+// Gradient sample from a cell in FP64 (same arithmetic as bilin2).
+__device__ __forceinline__ void bilin2q(const HB_G Quad *m, const Cell &t, double &gx,
+                                        double &gy) {
+    const double tx = t.tx, ty = t.ty;
+    const double w00 = (1.0 - tx) * (1.0 - ty), w10 = tx * (1.0 - ty);
+    const double w01 = (1.0 - tx) * ty, w11 = tx * ty;
+    const Quad q0 = ldq(m, 2 * t.c), q1 = ldq(m, 2 * t.c + 1);
+    gx = w00 * q0.a + w10 * q0.c + w01 * q1.a + w11 * q1.c;
+    gy = w00 * q0.b + w10 * q0.d + w01 * q1.b + w11 * q1.d;
+}
+
 // Density sample in FP32 (the precision of the stored map; the acceptance tests).
 template <typename PF>
 __device__ __forceinline__ float sample1(PF m, const Taps &t) {

@@ -34,6 +34,11 @@ constexpr int kTileBlocksMax = 2048;                // blocks of one graph in k_
 constexpr int kRedSlices = 32;                      // slices per parameter in k_adj_reduce
 static_assert(HB_MAX_EDGE_WEIGHT < (1u << (32 - kLocalBits)), "weights must fit an entry");
 
+// Four map values of one bilinear cell (16 bytes, one load).
+struct alignas(16) Quad {
+    float a, b, c, d;
+};
+
 // One graph of one iteration. Every kernel takes an array of these (one per graph of a
 // batch) and finds its graph from blockIdx via the blk_* prefixes, so a single graph is
 // a batch of one.
@@ -47,6 +52,7 @@ struct GDesc {
     int64_t blk_pxb;     // one thread per layer pixel (B * W * H)
     int64_t blk_edget;   // one thread per edge
     int64_t blk_tile;    // tile-histogram blocks (tile_blocks per graph)
+    int64_t blk_cell;    // one thread per bilinear cell of a layer (B * (W+1) * (H+1))
 
     int64_t n_edges;
     int64_t cap;         // capacity of the point buffers, in points
@@ -91,6 +97,10 @@ struct GDesc {
     int64_t *tmp;               // [B][H][W] row-pass output
     float *rho;                 // [B][H][W]
     float2 *grad;               // [B][H][W]
+    // bilinear cells: cell (u0, v0), u0 in [-1, W-1], v0 in [-1, H-1], at (v0+1)(W+1) + u0+1,
+    // holds the taps (u0,v0), (u0+1,v0), (u0,v0+1), (u0+1,v0+1), clamped into the grid
+    Quad *rhoq;                 // [B][H+1][W+1] density taps
+    Quad *gradq;                // [B][H+1][W+1][2] gradient taps: (x, y) of the first two, last two
     int8_t *jacc;               // [cap] accepted halving per sample (record != 0)
     int32_t *status;
 
@@ -110,7 +120,7 @@ struct GDesc {
 
 // Launch-shape block counts of one graph (host side).
 struct Shape {
-    int64_t edge, scan, row, col, px, pxb, edget, tile;
+    int64_t edge, scan, row, col, px, pxb, edget, tile, cell;
 };
 Shape shape_of(int64_t n_edges, int32_t B, int32_t W, int32_t H);
 
@@ -138,6 +148,9 @@ hipError_t launch_box_pass(const GDesc *desc, int ng, const Shape &tot, int max_
                            hipStream_t st);
 hipError_t launch_density_grad(const GDesc *desc, int ng, const Shape &tot, int bmax,
                                hipStream_t st);
+// density and gradient, then their bilinear cells (what the advection reads)
+hipError_t launch_density_cells(const GDesc *desc, int ng, const Shape &tot, int bmax,
+                                hipStream_t st);
 hipError_t launch_advect_smooth(const GDesc *desc, int ng, const Shape &tot, int u,
                                 hipStream_t st);
 hipError_t launch_fill_totals(const GDesc *desc, int ng, int T, hipStream_t st);

@@ -578,6 +578,44 @@ __global__ __launch_bounds__(kBlock) void k_density_grad(const GDesc *__restrict
     }
 }
 
+// Bilinear cells of the density and gradient maps (one thread per cell of a layer): the
+// four clamped taps of every sample whose first tap is (u0, v0), so that the advection reads
+// a density sample with one 16-byte load and a gradient sample with two.
+__global__ __launch_bounds__(kBlock) void k_cells(const GDesc *__restrict__ gd, int ng) {
+    const int64_t blk = blockIdx.x;
+    HB_FIND(blk_cell);
+    if (stopped(d)) return;
+    const int W = d.W, H = d.H, qw = W + 1;
+    const int64_t nq = (int64_t)qw * (H + 1), plane = (int64_t)W * H;
+    const int64_t i = (blk - d.blk_cell) * kBlock + threadIdx.x;
+    if (i >= (int64_t)d.B * nq) return;
+    const int64_t l = i / nq, c = i - l * nq;
+    const int v0 = (int)(c / qw) - 1, u0 = (int)(c - (c / qw) * qw) - 1;
+    const int ua = min(max(u0, 0), W - 1), ub = min(max(u0 + 1, 0), W - 1);
+    const int va = min(max(v0, 0), H - 1), vb = min(max(v0 + 1, 0), H - 1);
+    const float *rho = d.rho + l * plane;
+    const float2 *grad = d.grad + l * plane;
+    const int64_t a = (int64_t)va * W, b = (int64_t)vb * W;
+    Quad r;
+    r.a = rho[a + ua];
+    r.b = rho[a + ub];
+    r.c = rho[b + ua];
+    r.d = rho[b + ub];
+    d.rhoq[i] = r;
+    const float2 g00 = grad[a + ua], g10 = grad[a + ub], g01 = grad[b + ua], g11 = grad[b + ub];
+    Quad q0, q1;
+    q0.a = g00.x;
+    q0.b = g00.y;
+    q0.c = g10.x;
+    q0.d = g10.y;
+    q1.a = g01.x;
+    q1.b = g01.y;
+    q1.c = g11.x;
+    q1.d = g11.y;
+    d.gradq[2 * i] = q0;
+    d.gradq[2 * i + 1] = q1;
+}
+
 // ---------------------------------------------------------------- advection + smoothing
 
 // One wave per edge. Each trip handles U sub-chunks of 62 output points with a one-point
@@ -601,9 +639,10 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
     const int W = d.W, H = d.H;
     const int64_t plane = (int64_t)W * H;
     const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
-    const int64_t lay = (int64_t)d.group[e] * plane;
-    const HB_G float *__restrict__ rho = glb(d.rho + lay);
-    const HB_G float2 *__restrict__ grad = glb(d.grad + lay);
+    (void)plane;
+    const int64_t cells = (int64_t)d.group[e] * (W + 1) * (H + 1);
+    const HB_G Quad *__restrict__ rho = glb(d.rhoq + cells);
+    const HB_G Quad *__restrict__ grad = glb(d.gradq + 2 * cells);
     const HB_G float2 *__restrict__ xs = glb(d.samples + o0);
     HB_G float2 *__restrict__ ys = glb(d.pnew + o0);
     HB_G int8_t *__restrict__ jrec = glb(d.jacc + o0);
@@ -639,16 +678,16 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
             if (act[u]) {
                 // the interpolated gradient in FP64 keeps its direction where the taps
                 // nearly cancel; its normalisation only needs FP32
-                const Taps t0 = taps_of(x[u].x, x[u].y, W, H);
+                const Cell t0 = cell_of(x[u].x, x[u].y, W, H);
                 double gx, gy;
-                bilin2(grad, t0, gx, gy);
+                bilin2q(grad, t0, gx, gy);
                 const float fx = (float)gx, fy = (float)gy;
                 // d = g / max(|g|, eps), through one reciprocal square root (about 1 ulp)
                 const float n2 = fx * fx + fy * fy;
                 const float inv = n2 > eps2 ? __builtin_amdgcn_rsqf(n2) : inv_eps;
                 dx[u] = fx * inv;
                 dy[u] = fy * inv;
-                r0[u] = sample1(rho, t0);
+                r0[u] = sample1q(rho, t0);
             }
         }
         // acceptance tests in FP32; the accepted point is recomputed in FP64
@@ -663,7 +702,7 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
                 if (act[u]) {
                     const float cx = __builtin_amdgcn_fmed3f(x[u].x + mf * dx[u], 0.0f, xmaxf);
                     const float cy = __builtin_amdgcn_fmed3f(x[u].y + mf * dy[u], 0.0f, ymaxf);
-                    if (sample1(rho, taps_of(cx, cy, W, H)) >= r0[u]) {
+                    if (sample1q(rho, cell_of(cx, cy, W, H)) >= r0[u]) {
                         jj[u] = k;
                         act[u] = false;
                     }
@@ -737,6 +776,7 @@ Shape shape_of(int64_t n_edges, int32_t B, int32_t W, int32_t H) {
     s.pxb = ((int64_t)B * plane + kBlock - 1) / kBlock;
     s.edget = (n_edges + 1 + kBlock - 1) / kBlock;
     s.tile = tiles_of(B, W, H).blocks;
+    s.cell = ((int64_t)B * (W + 1) * (H + 1) + kBlock - 1) / kBlock;
     return s;
 }
 
@@ -838,6 +878,14 @@ hipError_t launch_density_grad(const GDesc *desc, int ng, const Shape &tot, int 
     else if (bmax <= 4) hipLaunchKernelGGL(k_density_grad<4>, gr, bl, 0, st, desc, ng);
     else if (bmax <= 8) hipLaunchKernelGGL(k_density_grad<8>, gr, bl, 0, st, desc, ng);
     else hipLaunchKernelGGL(k_density_grad<16>, gr, bl, 0, st, desc, ng);
+    return hipGetLastError();
+}
+
+hipError_t launch_density_cells(const GDesc *desc, int ng, const Shape &tot, int bmax,
+                                hipStream_t st) {
+    hipError_t e = launch_density_grad(desc, ng, tot, bmax, st);
+    if (e != hipSuccess || tot.cell <= 0) return e;
+    hipLaunchKernelGGL(k_cells, grid_of(tot.cell), dim3(kBlock), 0, st, desc, ng);
     return hipGetLastError();
 }
 

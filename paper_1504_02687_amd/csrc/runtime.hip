@@ -67,6 +67,7 @@ struct hb_ctx {
     int64_t *d_box = nullptr, *d_tmp = nullptr;
     float *d_rho = nullptr;
     float2 *d_grad = nullptr;
+    hb::Quad *d_rhoq = nullptr, *d_gradq = nullptr;
     int32_t map_B = 0, map_W = 0, map_H = 0, map_P = 0;
     bool have_maps = false;
 
@@ -366,6 +367,9 @@ static hb_status ensure_maps(hb_ctx *c) {
     CHKST(dalloc(c, &c->d_tmp, plane, "row-pass scratch"));
     CHKST(dalloc(c, &c->d_rho, plane, "density"));
     CHKST(dalloc(c, &c->d_grad, plane, "gradient"));
+    const size_t cells = (size_t)B * (W + 1) * (H + 1);
+    CHKST(dalloc(c, &c->d_rhoq, cells, "density cells"));
+    CHKST(dalloc(c, &c->d_gradq, 2 * cells, "gradient cells"));
     c->map_B = B;
     c->map_W = W;
     c->map_H = H;
@@ -420,6 +424,8 @@ static GDesc base_desc(const hb_ctx *c) {
     d.tmp = c->d_tmp;
     d.rho = c->d_rho;
     d.grad = c->d_grad;
+    d.rhoq = c->d_rhoq;
+    d.gradq = c->d_gradq;
     d.jacc = c->d_jacc;
     d.status = c->d_status;
     return d;
@@ -593,6 +599,8 @@ HB_API void hb_destroy(hb_ctx *c) {
         dfree(&c->d_tmp);
         dfree(&c->d_rho);
         dfree(&c->d_grad);
+        dfree(&c->d_rhoq);
+        dfree(&c->d_gradq);
         dfree(&c->d_jacc);
         free_ckpts(c);
         dfree(&c->d_desc);
@@ -890,7 +898,7 @@ static hb_status prepare_ctx(hb_ctx *c, int T, uint32_t flags) {
 
 static void shape_add(Shape &a, const Shape &b) {
     a.edge += b.edge; a.scan += b.scan; a.row += b.row; a.col += b.col;
-    a.px += b.px; a.pxb += b.pxb; a.edget += b.edget; a.tile += b.tile;
+    a.px += b.px; a.pxb += b.pxb; a.edget += b.edget; a.tile += b.tile; a.cell += b.cell;
 }
 
 // Enqueue T iterations of the graphs cs[0..n) on lead's stream: the descriptor table holds
@@ -943,6 +951,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
             d.blk_pxb = base[g].pxb;
             d.blk_edget = base[g].edget;
             d.blk_tile = base[g].tile;
+            d.blk_cell = base[g].cell;
             d.record = record && it == T - 1;
             d.total = c->d_totals + it;
             if (given) {
@@ -989,7 +998,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
                 else HIPCHK(c, hb::launch_resample_count(dd, n, tot, ru, c->stream));
                 HIPCHK(c, hb::launch_bin_hist(dd, n, tot, c->stream));
                 for (int k = 0; k < pmax; ++k) HIPCHK(c, hb::launch_box_pass(dd, n, tot, max_w, k, c->stream));
-                HIPCHK(c, hb::launch_density_grad(dd, n, tot, bmax, c->stream));
+                HIPCHK(c, hb::launch_density_cells(dd, n, tot, bmax, c->stream));
                 HIPCHK(c, hb::launch_advect_smooth(dd, n, tot, au, c->stream));
                 continue;
             }
@@ -1000,7 +1009,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
             STAGE(c, HB_STAGE_BIN, hb::launch_bin_hist(dd, n, tot, c->stream));
             for (int k = 0; k < pmax; ++k)
                 STAGE(c, HB_STAGE_BOX, hb::launch_box_pass(dd, n, tot, max_w, k, c->stream));
-            STAGE(c, HB_STAGE_DENSITY_GRAD, hb::launch_density_grad(dd, n, tot, bmax, c->stream));
+            STAGE(c, HB_STAGE_DENSITY_GRAD, hb::launch_density_cells(dd, n, tot, bmax, c->stream));
             STAGE(c, HB_STAGE_ADVECT_SMOOTH, hb::launch_advect_smooth(dd, n, tot, au, c->stream));
         }
         return HB_OK;
