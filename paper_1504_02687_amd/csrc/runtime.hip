@@ -115,7 +115,7 @@ struct hb_ctx {
     } adj;
 
     // kernel variants (chunks of 64 per trip in resampling / advection)
-    int tune_ru = 2, tune_au = 1;
+    int tune_ru = 2, tune_au = 2;
 
     // captured iteration sequence, replayed while the batch layout is unchanged
     hipGraphExec_t gexec = nullptr;
@@ -535,7 +535,7 @@ HB_API hb_status hb_create(hb_ctx **out, int32_t device, void *hip_stream) {
             return (u == 1 || u == 2 || u == 4) ? u : dflt;
         };
         c->tune_ru = pick(getenv("HB_RESAMPLE_U"), 2);
-        c->tune_au = pick(getenv("HB_ADVECT_U"), 1);
+        c->tune_au = pick(getenv("HB_ADVECT_U"), 2);
     }
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;
