@@ -112,21 +112,21 @@ __global__ __launch_bounds__(kBlock) void k_adj_maps(const GDesc *__restrict__ g
 // points (adj_in), lane l computes the adjoint x'_bar of the advected point j from y_bar of
 // j-1, j, j+1, then the adjoint of the sample x_bar = w + m (dg/dx)^T v, where w is x'_bar
 // without the clamped coordinates, v = (dd/dg)^T w with d = g / max(|g|, eps), and m the
-// frozen step h / 2^j. The same v gives the point's contribution m v . dg/dM and m v . dg/da
-// (FP32 gathers of the combined maps, FP64 accumulation).
-template <int BMAX>
+// frozen step h / 2^j. m v is stored for every sample (zero where the sample did not move):
+// the parameter gradients are its contractions with the gradient maps (k_adj_params); mvmax
+// gets its largest component.
 __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_edge);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     // edges in the given order (by group, then position), dealt round-robin: the blocks in
-    // flight work on one or two layers, whose gradient-map records then stay in the caches
+    // flight work on one or two layers of the maps
     const int64_t idx = (blk - d.blk_edge) * kWavesPerBlock + wid;
     if (idx >= d.n_edges) return;
     const int64_t e = d.order ? (int64_t)d.order[idx] : idx;
 
-    const int W = d.W, H = d.H, B = d.B, P = d.P;
+    const int W = d.W, H = d.H;
     const int64_t plane = (int64_t)W * H;
     const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
     const int l = d.group[e];
@@ -134,22 +134,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
     const float2 *__restrict__ xs = d.samples + o0;
     const float2 *__restrict__ yb = d.adj_in + o0;
     float2 *__restrict__ xb = d.adj_out + o0;
+    float2 *__restrict__ mvp = d.mv + o0;
     const int8_t *__restrict__ jv = d.jacc + o0;
     const double h = d.h, s = d.s, eps = d.eps;
     const double xmax = (double)W - 1.0 / 256.0, ymax = (double)H - 1.0 / 256.0;
 
-    // gradient-map records: the groups' record (shared by every layer) and this layer's
-    // record of the passes
-    constexpr int BH = (BMAX + 1) / 2, PH = HB_MAX_PASSES / 2;   // 16-byte pieces, at most
-    const int bh = d.bp / 2, ph = d.pp / 2;
-    const float4 *__restrict__ GB = (const float4 *)d.gbm;
-    const float4 *__restrict__ GK = (const float4 *)(d.gkm + (int64_t)l * plane * d.pp);
-    double accb[2 * BH], acck[2 * PH];
-#pragma unroll
-    for (int q = 0; q < 2 * BH; ++q) accb[q] = 0.0;
-#pragma unroll
-    for (int q = 0; q < 2 * PH; ++q) acck[q] = 0.0;
-
+    float mbig = 0.0f;
     for (int64_t j0 = 0; j0 < n; j0 += 62) {
         const int64_t j = j0 - 1 + lane;
         const bool inr = j >= 0 && j < n;
@@ -164,6 +154,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
         double wx = cf * (double)ybar.x + 0.5 * s * (qlx + qrx);
         double wy = cf * (double)ybar.y + 0.5 * s * (qly + qry);
         double gxb = wx, gyb = wy;
+        float2 mvv = make_float2(0.0f, 0.0f);
         const int jj = interior ? (int)jv[j] : -2;
         if (jj >= 0) {
             const float2 x = xs[j];
@@ -193,52 +184,116 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
             const double tx = t0.tx, ty = t0.ty;
             gxb = wx + m * ((1.0 - ty) * (v10 - v00) + ty * (v11 - v01));
             gyb = wy + m * ((1.0 - tx) * (v01 - v00) + tx * (v11 - v10));
-            const float mvx = (float)(m * vx), mvy = (float)(m * vy);
-            const float ftx = t0.tx, fty = t0.ty;
-            const float w00 = (1.0f - ftx) * (1.0f - fty), w10 = ftx * (1.0f - fty);
-            const float w01 = (1.0f - ftx) * fty, w11 = ftx * fty;
-            const float4 *b00 = GB + (int64_t)t0.o00 * bh, *b10 = GB + (int64_t)t0.o10 * bh;
-            const float4 *b01 = GB + (int64_t)t0.o01 * bh, *b11 = GB + (int64_t)t0.o11 * bh;
-#pragma unroll
-            for (int q2 = 0; q2 < BH; ++q2) {
-                if (q2 >= bh) break;
-                const float4 a00 = b00[q2], a10 = b10[q2], a01 = b01[q2], a11 = b11[q2];
-                const float gx0 = w00 * a00.x + w10 * a10.x + w01 * a01.x + w11 * a11.x;
-                const float gy0 = w00 * a00.y + w10 * a10.y + w01 * a01.y + w11 * a11.y;
-                const float gx1 = w00 * a00.z + w10 * a10.z + w01 * a01.z + w11 * a11.z;
-                const float gy1 = w00 * a00.w + w10 * a10.w + w01 * a01.w + w11 * a11.w;
-                accb[2 * q2] += (double)(mvx * gx0 + mvy * gy0);
-                accb[2 * q2 + 1] += (double)(mvx * gx1 + mvy * gy1);
-            }
-            const float4 *k00 = GK + (int64_t)t0.o00 * ph, *k10 = GK + (int64_t)t0.o10 * ph;
-            const float4 *k01 = GK + (int64_t)t0.o01 * ph, *k11 = GK + (int64_t)t0.o11 * ph;
-#pragma unroll
-            for (int q2 = 0; q2 < PH; ++q2) {
-                if (q2 >= ph) break;
-                const float4 a00 = k00[q2], a10 = k10[q2], a01 = k01[q2], a11 = k11[q2];
-                const float gx0 = w00 * a00.x + w10 * a10.x + w01 * a01.x + w11 * a11.x;
-                const float gy0 = w00 * a00.y + w10 * a10.y + w01 * a01.y + w11 * a11.y;
-                const float gx1 = w00 * a00.z + w10 * a10.z + w01 * a01.z + w11 * a11.z;
-                const float gy1 = w00 * a00.w + w10 * a10.w + w01 * a01.w + w11 * a11.w;
-                acck[2 * q2] += (double)(mvx * gx0 + mvy * gy0);
-                acck[2 * q2 + 1] += (double)(mvx * gx1 + mvy * gy1);
-            }
+            mvv = make_float2((float)(m * vx), (float)(m * vy));
+            mbig = fmaxf(mbig, fmaxf(fabsf(mvv.x), fabsf(mvv.y)));
         }
         xb[j] = make_float2((float)gxb, (float)gyb);
-    }
-    double *out = d.partials + idx;
-    const int64_t E = d.n_edges;
-#pragma unroll
-    for (int q = 0; q < 2 * BH; ++q) {
-        if (q >= B) break;
-        const double v = wave_sum(accb[q]);
-        if (lane == 0) out[q * E] = v;
+        mvp[j] = mvv;
     }
 #pragma unroll
-    for (int q = 0; q < 2 * PH; ++q) {
-        if (q >= P) break;
-        const double v = wave_sum(acck[q]);
-        if (lane == 0) out[(B + q) * E] = v;
+    for (int o = 32; o >= 1; o >>= 1) mbig = fmaxf(mbig, __shfl_xor(mbig, o, 64));
+    if (lane == 0 && mbig > 0.0f) atomicMax(d.mvmax, __float_as_uint(mbig));
+}
+
+// Parameter gradients, tile by tile. A moved sample p contributes m v_p . g(x_p), g the
+// bilinear sample of a gradient-map record (Eq. 3 differentiated with respect to M and a);
+// summed by pixel instead, that is the sum over pixels of A(px) . record(px), with
+// A(px) = sum over samples of w_px(x_p) m v_p. A block takes work items of the iteration's
+// checkpointed tile bins (up to kSegEntries samples of one tile), adds w m v into a
+// (64 + 2)^2 LDS grid (the tile and a one-pixel border, where the taps of its samples fall)
+// as 64-bit fixed point with unit 2^-S, max |m v| 2^S < 2^40 (exact sums in any order), then
+// contracts the grid with the records in FP64 and writes the item's B + P partial sums; all
+// reductions run in a fixed order, so the gradients are bit-reproducible.
+template <int BMAX>
+__global__ __launch_bounds__(kBlock) void k_adj_params(const GDesc *__restrict__ gd, int ng) {
+    const GDesc &d = gd[0];
+    constexpr int GW = kTile + 2, GN = GW * GW, NQ = BMAX + HB_MAX_PASSES;
+    __shared__ unsigned long long sA[2][GN];
+    __shared__ double sred[kWavesPerBlock][NQ];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int nt = d.n_tiles, B = d.B, P = d.P, W = d.W, H = d.H, bp = d.bp, pp = d.pp;
+    const int64_t nitems = d.aseg_off[nt];
+    const int64_t plane = (int64_t)W * H;
+    const int per_layer = d.tiles_x * d.tiles_y;
+    const float mmax = __uint_as_float(*d.mvmax);
+    int ex = 0;
+    if (mmax > 0.0f) (void)frexpf(mmax, &ex);
+    const float scale = ldexpf(1.0f, 40 - ex);
+    const double unit = ldexp(1.0, ex - 40);
+    for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        int lo = 0, hi = nt - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (d.aseg_off[mid] <= it) lo = mid; else hi = mid - 1;
+        }
+        const int t = lo;
+        const int64_t beg = d.atile_off[t] + (it - d.aseg_off[t]) * kSegEntries;
+        const int64_t lim = d.atile_off[t + 1];
+        const int64_t end = beg + kSegEntries < lim ? beg + kSegEntries : lim;
+        const int layer = t / per_layer, rem = t - layer * per_layer;
+        const int ty = rem / d.tiles_x, tx = rem - ty * d.tiles_x;
+        const int X0 = tx * kTile - 1, Y0 = ty * kTile - 1;   // grid cell (0, 0)
+        for (int c = threadIdx.x; c < 2 * GN; c += kBlock) (&sA[0][0])[c] = 0ull;
+        __syncthreads();
+        for (int64_t i = beg + threadIdx.x; i < end; i += kBlock) {
+            const uint32_t p = d.abin_src[i];
+            const float2 m = d.mv[p];
+            if (m.x == 0.0f && m.y == 0.0f) continue;
+            const float2 x = d.samples[p];
+            const Taps tp = taps_of(x.x, x.y, W, H);
+            const float ftx = tp.tx, fty = tp.ty;
+            const float w[4] = {(1.0f - ftx) * (1.0f - fty), ftx * (1.0f - fty),
+                                (1.0f - ftx) * fty, ftx * fty};
+            const uint32_t o[4] = {tp.o00, tp.o10, tp.o01, tp.o11};
+            const float mx = m.x * scale, my = m.y * scale;
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int v = (int)(o[q] / (uint32_t)W), u = (int)(o[q] - (uint32_t)v * (uint32_t)W);
+                const int c = (v - Y0) * GW + (u - X0);
+                atomicAdd(&sA[0][c], (unsigned long long)(long long)rintf(w[q] * mx));
+                atomicAdd(&sA[1][c], (unsigned long long)(long long)rintf(w[q] * my));
+            }
+        }
+        __syncthreads();
+        double acc[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+        for (int c = threadIdx.x; c < GN; c += kBlock) {
+            const long long ax = (long long)sA[0][c], ay = (long long)sA[1][c];
+            if (ax == 0 && ay == 0) continue;
+            const int v = Y0 + c / GW, u = X0 + c % GW;
+            const int64_t px = (int64_t)v * W + u;
+            const double fx = (double)ax * unit, fy = (double)ay * unit;
+            const float2 *gb = d.gbm + px * bp;
+            const float2 *gk = d.gkm + ((int64_t)layer * plane + px) * pp;
+#pragma unroll
+            for (int b = 0; b < BMAX; ++b) {
+                if (b >= B) break;
+                const float2 g = gb[b];
+                acc[b] += fx * g.x + fy * g.y;
+            }
+#pragma unroll
+            for (int k = 0; k < HB_MAX_PASSES; ++k) {
+                if (k >= P) break;
+                const float2 g = gk[k];
+                acc[BMAX + k] += fx * g.x + fy * g.y;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            const bool used = q < BMAX ? q < B : q - BMAX < P;
+            if (!used) continue;
+            const double v = wave_sum(acc[q]);
+            if (lane == 0) sred[wid][q] = v;
+        }
+        __syncthreads();
+        if ((int)threadIdx.x < B + P) {
+            const int q = (int)threadIdx.x < B ? (int)threadIdx.x : BMAX + ((int)threadIdx.x - B);
+            double sum = 0.0;
+            for (int w2 = 0; w2 < kWavesPerBlock; ++w2) sum += sred[w2][q];
+            d.partials[(int64_t)threadIdx.x * d.max_items + it] = sum;
+        }
+        __syncthreads();
     }
 }
 
@@ -431,27 +486,29 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
     }
 }
 
-// dL/dM[l][b] += sum over the edges of layer l of their partial b; dL/da_k += sum over all
-// edges of their partial B + k. Two fixed-order stages: block (q, slice) sums one slice of
-// parameter q's contiguous range of the column-major partials (fixed per-thread order and
-// a fixed tree), then one thread per parameter adds its slice sums in order.
+// dL/dM[l][b] += sum over the work items of layer l of their partial b; dL/da_k += sum over
+// all work items of their partial B + k (items are in tile order, so a layer's items are
+// contiguous). Two fixed-order stages: block (q, slice) sums one slice of parameter q's
+// range (fixed per-thread order and a fixed tree), then one thread per parameter adds its
+// slice sums in order.
 __global__ __launch_bounds__(kBlock) void k_adj_reduce(const GDesc *__restrict__ gd, int ng) {
     const GDesc &d = gd[0];
     const int B = d.B;
     const int q = (int)blockIdx.x / kRedSlices, sl = (int)blockIdx.x % kRedSlices;
-    int64_t lo = 0, hi = d.n_edges;
+    const int per_layer = d.tiles_x * d.tiles_y;
+    int64_t lo = 0, hi = d.aseg_off[d.n_tiles];
     int col;
     if (q < B * B) {
         const int l = q / B;
         col = q % B;
-        lo = d.gstart[l];
-        hi = d.gstart[l + 1];
+        lo = d.aseg_off[l * per_layer];
+        hi = d.aseg_off[(l + 1) * per_layer];
     } else {
         col = B + (q - B * B);
     }
     const int64_t per = (hi - lo + kRedSlices - 1) / kRedSlices;
     const int64_t a = lo + sl * per, b = a + per < hi ? a + per : hi;
-    const double *p = d.partials + (int64_t)col * d.n_edges;
+    const double *p = d.partials + (int64_t)col * d.max_items;
     double s = 0.0;
     for (int64_t i = a + threadIdx.x; i < b; i += kBlock) s += p[i];
     __shared__ double red[kBlock];
@@ -489,14 +546,17 @@ hipError_t launch_adj_maps(const GDesc *desc, const Shape &tot, hipStream_t st) 
     return hipGetLastError();
 }
 
-hipError_t launch_adj_advect(const GDesc *desc, const Shape &tot, int bmax, hipStream_t st) {
+hipError_t launch_adj_advect(const GDesc *desc, const Shape &tot, hipStream_t st) {
     if (tot.edge <= 0) return hipSuccess;
-    const dim3 gr = grid1(tot.edge), bl(kBlock);
-    if (bmax <= 1) hipLaunchKernelGGL(k_adj_advect<1>, gr, bl, 0, st, desc, 1);
-    else if (bmax <= 2) hipLaunchKernelGGL(k_adj_advect<2>, gr, bl, 0, st, desc, 1);
-    else if (bmax <= 4) hipLaunchKernelGGL(k_adj_advect<4>, gr, bl, 0, st, desc, 1);
-    else if (bmax <= 8) hipLaunchKernelGGL(k_adj_advect<8>, gr, bl, 0, st, desc, 1);
-    else hipLaunchKernelGGL(k_adj_advect<16>, gr, bl, 0, st, desc, 1);
+    hipLaunchKernelGGL(k_adj_advect, grid1(tot.edge), dim3(kBlock), 0, st, desc, 1);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_params(const GDesc *desc, const Shape &tot, int bmax, hipStream_t st) {
+    if (tot.tile <= 0) return hipSuccess;
+    const dim3 gr = grid1(tot.tile), bl(kBlock);
+    if (bmax <= 8) hipLaunchKernelGGL(k_adj_params<8>, gr, bl, 0, st, desc, 1);
+    else hipLaunchKernelGGL(k_adj_params<16>, gr, bl, 0, st, desc, 1);
     return hipGetLastError();
 }
 

@@ -93,6 +93,7 @@ struct GDesc {
     int64_t *tile_off;          // [n_tiles + 1] first entry of each tile
     int64_t *seg_off;           // [n_tiles + 1] first work item (kSegEntries entries) of each tile
     uint32_t *bins;             // [cap] entries: pixel in tile | edge weight << kLocalBits
+    uint32_t *bin_src;          // [cap] sample of each entry (runs that record it; else null)
     int64_t *box;               // [P][B][H][W]
     int64_t *tmp;               // [B][H][W] row-pass output
     float *rho;                 // [B][H][W]
@@ -111,9 +112,16 @@ struct GDesc {
     float2 *gbm;                // [H][W][bp]: sum_k a_k D_bk for every group b (all layers)
     float2 *gkm;                // [B][H][W][pp]: sum_b M[l][b] D_bk for every pass k, layer l
     int32_t bp, pp;             // record lengths in float2 (B and P rounded up to even)
-    double *partials;           // [B + P][E] parameter partials, column-major, edges in the
-                                // advection adjoint's order (by group)
-    const int64_t *gstart;      // [B + 1] first position of each group in that order
+    // parameter gradients, tile by tile: the samples of the iteration binned by histogram
+    // tile (checkpointed bins), m v of every sample from the advection adjoint, a fixed-point
+    // splat of w m v per tile in LDS and its contraction with the gradient-map records
+    const uint32_t *abin_src;   // [N] checkpointed sample of each entry, in tile order
+    const int64_t *atile_off;   // [n_tiles + 1] checkpointed first entry of each tile
+    const int64_t *aseg_off;    // [n_tiles + 1] checkpointed first work item of each tile
+    float2 *mv;                 // [N] m v of every sample (zero where it does not move)
+    uint32_t *mvmax;            // largest |component| of m v (bits of a non-negative float)
+    double *partials;           // [B + P][n_items] parameter partials of each work item
+    int64_t max_items;          // capacity of partials per parameter
     double *red;                // [B*B + P][kRedSlices] slice sums of the reduction
     double *grad_param;         // [B*B + P] accumulated dL/dM (row-major) and dL/da
 };
@@ -158,7 +166,8 @@ hipError_t launch_fill_totals(const GDesc *desc, int ng, int T, hipStream_t st);
 // Adjoint kernels (one graph per launch).
 hipError_t launch_ink_grad(const GDesc *desc, const Shape &tot, hipStream_t st);
 hipError_t launch_adj_maps(const GDesc *desc, const Shape &tot, hipStream_t st);
-hipError_t launch_adj_advect(const GDesc *desc, const Shape &tot, int bmax, hipStream_t st);
+hipError_t launch_adj_advect(const GDesc *desc, const Shape &tot, hipStream_t st);
+hipError_t launch_adj_params(const GDesc *desc, const Shape &tot, int bmax, hipStream_t st);
 hipError_t launch_adj_resample(const GDesc *desc, const Shape &tot, hipStream_t st);
 hipError_t launch_adj_reduce(const GDesc *desc, int B, int P, hipStream_t st);
 

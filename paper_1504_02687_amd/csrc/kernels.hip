@@ -327,8 +327,12 @@ __global__ __launch_bounds__(kBlock) void k_bin_samples(const GDesc *__restrict_
                 const unsigned long long b0 = __shfl(base[u], h, 64);
                 if (lane < cnt[u]) {
                     const unsigned long long pos = b0 + (unsigned long long)(lane - h);
-                    if (pos < (unsigned long long)d.cap) bins[pos] = loc[u] | wbits;
-                    else atomicOr(d.status, ST_BIN_MISMATCH);
+                    if (pos < (unsigned long long)d.cap) {
+                        bins[pos] = loc[u] | wbits;
+                        if (d.bin_src) d.bin_src[pos] = (uint32_t)(o0 + j0 + 64 * u + lane);
+                    } else {
+                        atomicOr(d.status, ST_BIN_MISMATCH);
+                    }
                 }
             }
         }

@@ -41,7 +41,6 @@ struct hb_ctx {
     bool have_groups = false;
     int32_t *d_group = nullptr, *d_weight = nullptr, *d_perm = nullptr;
     int32_t *d_perm_adj = nullptr;       // edge order of the advection kernels (built on use)
-    int64_t *d_gstart_adj = nullptr;     // first position of each group in that order
     std::vector<int32_t> h_group;
     std::vector<uint32_t> h_morton;     // Morton code of each straight edge's midpoint
     float *d_M = nullptr;
@@ -51,6 +50,8 @@ struct hb_ctx {
     int64_t *off[2] = {nullptr, nullptr};
     int64_t cap = 0;
     uint32_t *d_bins = nullptr;          // [cap] binned samples of the splat
+    uint32_t *d_binsrc = nullptr;        // [cap] sample of each binned entry (checkpointed runs)
+    int64_t binsrc_cap = 0;
     int ps = 0, os = 0, ss = 0, so = 0;
     int64_t n_state = 0, n_samples = 0;
     bool have_samples = false;
@@ -99,9 +100,12 @@ struct hb_ctx {
         double *lens = nullptr;
         int8_t *jacc = nullptr;                    // accepted halvings of the samples
         int32_t *hist = nullptr;                   // [B][H][W] histogram of the samples
+        uint32_t *bsrc = nullptr;                  // samples binned by histogram tile
+        int64_t *toff = nullptr, *soff = nullptr;  // tile offsets and work-item offsets
         int64_t n = 0, ns = 0;
         int32_t iter = 0;
         int64_t cap_n = 0, cap_ns = 0, cap_e = 0, cap_px = 0;   // allocated sizes (reused)
+        int64_t cap_bs = 0, cap_t = 0;
     };
     std::vector<Ckpt> ckpts;       // checkpoints of the last hb_forward_ckpt
     std::vector<Ckpt> ckpt_pool;   // allocated checkpoint buffers for reuse
@@ -111,7 +115,10 @@ struct hb_ctx {
     struct AdjBufs {
         float2 *a0 = nullptr, *a1 = nullptr, *gb = nullptr;
         double *partials = nullptr, *gparam = nullptr, *red = nullptr;
+        float2 *mv = nullptr;
+        uint32_t *mvmax = nullptr;
         int64_t cap_pts = 0, cap_a1 = 0, cap_gb = 0, cap_part = 0, cap_gp = 0, cap_red = 0;
+        int64_t cap_mv = 0, cap_mm = 0;
     } adj;
 
     // kernel variants (chunks of 64 per trip in resampling / advection)
@@ -576,7 +583,6 @@ HB_API void hb_destroy(hb_ctx *c) {
         dfree(&c->d_group);
         dfree(&c->d_perm);
         dfree(&c->d_perm_adj);
-        dfree(&c->d_gstart_adj);
         dfree(&c->d_weight);
         dfree(&c->d_M);
         for (int i = 0; i < 2; ++i) {
@@ -591,6 +597,7 @@ HB_API void hb_destroy(hb_ctx *c) {
         dfree(&c->d_hist);
         dfree(&c->d_histx);
         dfree(&c->d_bins);
+        dfree(&c->d_binsrc);
         dfree(&c->d_bin_cnt);
         dfree(&c->d_bin_cur);
         dfree(&c->d_tile_off);
@@ -731,7 +738,6 @@ HB_API hb_status hb_set_graph(hb_ctx *c, int32_t n_nodes, const float *node_xy, 
         }
         dfree(&c->d_perm);
         dfree(&c->d_perm_adj);
-        dfree(&c->d_gstart_adj);
     }
     c->have_graph = false;
     c->have_samples = false;
@@ -850,7 +856,6 @@ HB_API hb_status hb_set_groups(hb_ctx *c, int32_t n_groups, const int32_t *group
     // concentrates the memory-side splat atomics
     dfree(&c->d_perm);
     dfree(&c->d_perm_adj);
-    dfree(&c->d_gstart_adj);
     c->h_group = hg;
     if (const char *ord = getenv("HB_EDGE_ORDER"); ord && atoi(ord) == 1) {
         const std::vector<int32_t> perm = spatial_order(c);
@@ -866,24 +871,18 @@ HB_API hb_status hb_set_groups(hb_ctx *c, int32_t n_groups, const int32_t *group
 
 // ------------------------------------------------------------------ the iteration loop
 
-// Edge order of the advection kernels (by group, then position) and the first position of
-// each group in it; rebuilt after the graph or the groups change.
+// Edge order of the advection kernels (by group, then position); rebuilt after the graph or
+// the groups change.
 static hb_status ensure_order(hb_ctx *c) {
-    if (c->d_perm_adj && c->d_gstart_adj) return HB_OK;
-    const int32_t B = std::max(1, c->B);
+    if (c->d_perm_adj) return HB_OK;
     const std::vector<int32_t> order = spatial_order(c);
-    std::vector<int64_t> gstart((size_t)B + 1, 0);
-    if ((int64_t)c->h_group.size() == c->E)
-        for (int32_t g : c->h_group) ++gstart[(size_t)g + 1];
-    else
-        gstart[1] = c->E;
-    for (int b = 0; b < B; ++b) gstart[(size_t)b + 1] += gstart[(size_t)b];
     CHKST(dalloc(c, &c->d_perm_adj, std::max<size_t>(1, order.size()), "advection edge order"));
     CHKST(upload(c, c->d_perm_adj, order));
-    CHKST(dalloc(c, &c->d_gstart_adj, gstart.size(), "group starts"));
-    CHKST(upload(c, c->d_gstart_adj, gstart));
     return HB_OK;
 }
+
+// Internal run flag of hb_forward_ckpt: record the sample of every splat entry.
+static const uint32_t kRunRecordBins = 1u << 30;
 
 static hb_status prepare_ctx(hb_ctx *c, int T, uint32_t flags) {
     CHKST(ensure_order(c));
@@ -892,6 +891,10 @@ static hb_status prepare_ctx(hb_ctx *c, int T, uint32_t flags) {
     if ((flags & HB_RUN_RECORD_DECISIONS) && c->jacc_cap < c->cap) {
         CHKST(dalloc(c, &c->d_jacc, (size_t)c->cap, "decisions"));
         c->jacc_cap = c->cap;
+    }
+    if ((flags & kRunRecordBins) && c->binsrc_cap < c->cap) {
+        CHKST(dalloc(c, &c->d_binsrc, (size_t)c->cap, "binned samples"));
+        c->binsrc_cap = c->cap;
     }
     return HB_OK;
 }
@@ -953,6 +956,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
             d.blk_tile = base[g].tile;
             d.blk_cell = base[g].cell;
             d.record = record && it == T - 1;
+            d.bin_src = (d.record && (flags & kRunRecordBins)) ? c->d_binsrc : nullptr;
             d.total = c->d_totals + it;
             if (given) {
                 d.samples = c->pts[ps];
@@ -1478,6 +1482,9 @@ static void free_ckpts(hb_ctx *c) {
         dfree(&k.lens);
         dfree(&k.jacc);
         dfree(&k.hist);
+        dfree(&k.bsrc);
+        dfree(&k.toff);
+        dfree(&k.soff);
     }
     c->ckpts.clear();
     c->ckpt_end_iter = -1;
@@ -1487,6 +1494,8 @@ static void free_ckpts(hb_ctx *c) {
     dfree(&c->adj.partials);
     dfree(&c->adj.gparam);
     dfree(&c->adj.red);
+    dfree(&c->adj.mv);
+    dfree(&c->adj.mvmax);
     c->adj = hb_ctx::AdjBufs();
 }
 
@@ -1539,16 +1548,22 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
         HIPCHK(c, hipMemcpyAsync(k.counts, c->d_counts, sizeof(int64_t) * c->E, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(k.lens, c->d_lens, sizeof(double) * c->E, hipMemcpyDeviceToDevice, c->stream));
         c->last_counts.clear();
-        CHKST(enqueue_run(c, 1, HB_RUN_RECORD_DECISIONS));
+        CHKST(enqueue_run(c, 1, HB_RUN_RECORD_DECISIONS | kRunRecordBins));
         CHKST(finish_pending(c));
         counts.insert(counts.end(), c->last_counts.begin(), c->last_counts.end());
         // the samples, decisions and histogram of this iteration
         hb_ctx::Ckpt &kk = c->ckpts.back();
         kk.ns = c->n_samples;
         int64_t cap_ns2 = kk.cap_ns;
+        const int64_t nt1 = (int64_t)hb::tiles_of(std::max(1, c->B), c->P.grid_w, c->P.grid_h).n + 1;
+        int64_t cap_t2 = kk.cap_t;
         st = grow(c, &kk.xs, kk.cap_ns, kk.ns, "checkpoint");
         if (st == HB_OK) st = grow(c, &kk.jacc, cap_ns2, kk.ns, "checkpoint");
+        if (st == HB_OK) st = grow(c, &kk.bsrc, kk.cap_bs, kk.ns, "checkpoint");
+        if (st == HB_OK) st = grow(c, &kk.toff, kk.cap_t, nt1, "checkpoint");
+        if (st == HB_OK) st = grow(c, &kk.soff, cap_t2, nt1, "checkpoint");
         kk.cap_ns = std::min(kk.cap_ns, cap_ns2);
+        kk.cap_t = std::min(kk.cap_t, cap_t2);
         if (st != HB_OK) {
             free_ckpts(c);
             return st;
@@ -1557,6 +1572,9 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
         HIPCHK(c, hipMemcpyAsync(kk.xoff, c->off[c->so], sizeof(int64_t) * E1, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(kk.jacc, c->d_jacc, (size_t)kk.ns, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(kk.hist, c->d_hist, sizeof(int32_t) * plane, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(kk.bsrc, c->d_binsrc, sizeof(uint32_t) * kk.ns, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(kk.toff, c->d_tile_off, sizeof(int64_t) * nt1, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(kk.soff, c->d_seg_off, sizeof(int64_t) * nt1, hipMemcpyDeviceToDevice, c->stream));
     }
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->last_counts = counts;
@@ -1590,7 +1608,13 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
     CHKST(grow(c, &A.a1, A.cap_a1, nmax, "adjoint"));
     const int bp = (B + 1) / 2 * 2, pp = (P + 1) / 2 * 2;
     CHKST(grow(c, &A.gb, A.cap_gb, plane * (bp + (int64_t)B * pp), "gradient maps"));
-    CHKST(grow(c, &A.partials, A.cap_part, std::max<int64_t>(1, E) * (B + P), "partials"));
+    // work items of the tile bins: at most one per kSegEntries samples plus one per tile
+    const int64_t nt = hb::tiles_of(B, W, H).n;
+    int64_t max_items = 1;
+    for (auto &k : c->ckpts) max_items = std::max(max_items, k.ns / hb::kSegEntries + nt + 1);
+    CHKST(grow(c, &A.partials, A.cap_part, max_items * (B + P), "partials"));
+    CHKST(grow(c, &A.mv, A.cap_mv, std::max<int64_t>(1, nmax), "adjoint steps"));
+    CHKST(grow(c, &A.mvmax, A.cap_mm, (int64_t)T, "adjoint step scale"));
     CHKST(grow(c, &A.gparam, A.cap_gp, (int64_t)(B * B + P), "parameter gradients"));
     CHKST(grow(c, &A.red, A.cap_red, (int64_t)(B * B + P) * hb::kRedSlices, "reduction"));
     CHKST(ensure_order(c));
@@ -1627,7 +1651,12 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
         a.adj_in = cur;
         a.adj_out = other;
         a.partials = A.partials;
-        a.gstart = c->d_gstart_adj;
+        a.max_items = max_items;
+        a.abin_src = k.bsrc;
+        a.atile_off = k.toff;
+        a.aseg_off = k.soff;
+        a.mv = A.mv;
+        a.mvmax = A.mvmax + t;
         a.red = A.red;
         a.grad_param = A.gparam;
         GDesc q = a;                            // resampling adjoint
@@ -1640,13 +1669,15 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
         c->h_desc[slot + 1] = q;
     }
     CHKST(upload_desc(c, (size_t)(2 * T + 1)));
+    HIPCHK(c, hipMemsetAsync(A.mvmax, 0, sizeof(uint32_t) * T, c->stream));
     HIPCHK(c, hb::launch_ink_grad(c->d_desc, s, c->stream));
     for (int t = T - 1; t >= 0; --t) {
         const GDesc *a = c->d_desc + 1 + 2 * (size_t)(T - 1 - t);
         for (int kk = 0; kk < P; ++kk) HIPCHK(c, hb::launch_box_pass(a, 1, s, W, kk, c->stream));
         HIPCHK(c, hb::launch_density_grad(a, 1, s, B, c->stream));
         HIPCHK(c, hb::launch_adj_maps(a, s, c->stream));
-        HIPCHK(c, hb::launch_adj_advect(a, s, B, c->stream));
+        HIPCHK(c, hb::launch_adj_advect(a, s, c->stream));
+        HIPCHK(c, hb::launch_adj_params(a, s, B, c->stream));
         HIPCHK(c, hb::launch_adj_resample(a + 1, s, c->stream));
         HIPCHK(c, hb::launch_adj_reduce(a, B, P, c->stream));
     }
