@@ -18,7 +18,9 @@
 namespace hb {
 
 // dL/dp of L = total polyline length: p_bar_j = u_(j-1) - u_j with u the unit vectors of the
-// adjacent segments (zero for zero-length segments). One wave per edge over (pin, off_in).
+// adjacent segments (zero for zero-length segments). One wave per edge over (pin, off_in),
+// 63 points per trip: lane l takes segment (j, j+1) from its neighbour lane, u_(j-1) comes
+// from lane l-1 (or from the previous trip for lane 0).
 __global__ __launch_bounds__(kBlock) void k_ink_grad(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_edge);
@@ -29,28 +31,28 @@ __global__ __launch_bounds__(kBlock) void k_ink_grad(const GDesc *__restrict__ g
     const int64_t i0 = d.off_in[e], m = d.off_in[e + 1] - i0;
     const float2 *p = d.pin + i0;
     float2 *out = d.adj_out + i0;
-    for (int64_t j = lane; j < m; j += 64) {
-        const float2 c = p[j];
-        double gx = 0.0, gy = 0.0;
-        if (j > 0) {
-            const float2 a = p[j - 1];
-            const double dx = (double)c.x - a.x, dy = (double)c.y - a.y;
+    double cux = 0.0, cuy = 0.0;   // u of the segment ending at the trip's first point
+    for (int64_t j0 = 0; j0 < m; j0 += 63) {
+        const int64_t j = j0 + lane;
+        const float2 c = j < m ? p[j] : make_float2(0.0f, 0.0f);
+        const float nxx = lane_next(c.x, 0.0f), nxy = lane_next(c.y, 0.0f);
+        double ux = 0.0, uy = 0.0;
+        if (lane < 63 && j + 1 < m) {
+            const double dx = (double)nxx - c.x, dy = (double)nxy - c.y;
             const double l = sqrt(dx * dx + dy * dy);
             if (l > 0.0) {
-                gx += dx / l;
-                gy += dy / l;
+                ux = dx / l;
+                uy = dy / l;
             }
         }
-        if (j + 1 < m) {
-            const float2 b = p[j + 1];
-            const double dx = (double)b.x - c.x, dy = (double)b.y - c.y;
-            const double l = sqrt(dx * dx + dy * dy);
-            if (l > 0.0) {
-                gx -= dx / l;
-                gy -= dy / l;
-            }
+        double px = lane_prev(ux, 0.0), py = lane_prev(uy, 0.0);
+        if (lane == 0) {
+            px = cux;
+            py = cuy;
         }
-        out[j] = make_float2((float)gx, (float)gy);
+        if (lane < 63 && j < m) out[j] = make_float2((float)(px - ux), (float)(py - uy));
+        cux = read_lane(ux, 62);
+        cuy = read_lane(uy, 62);
     }
 }
 
@@ -383,10 +385,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
                     t = 1.0;
                 } else {
                     const double sk = __dmul_rn((double)k, ds);
-                    int lo = 0, hi = nseg - 1;
-                    while (lo < hi) {
-                        int mid = (lo + hi + 1) >> 1;
-                        if (sC[wid][mid] <= sk) lo = mid; else hi = mid - 1;
+                    // last segment that starts at or before sk (branch-free binary search)
+                    int lo = 0;
+#pragma unroll
+                    for (int step = 32; step >= 1; step >>= 1) {
+                        const int c = lo + step;
+                        const int cc = c < nseg ? c : nseg - 1;
+                        if (c < nseg && sC[wid][cc] <= sk) lo = c;
                     }
                     jl = lo;
                     const double traw = __dmul_rn(__dsub_rn(sk, sC[wid][lo]), sR[wid][lo]);
