@@ -409,19 +409,24 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
                 v[4] = -tb * sR[wid][jl];
                 v[5] = -tb * t * sR[wid][jl];
             }
-            // segmented inclusive scan over runs of equal segment index (the segment index
-            // grows with the sample; idle lanes carry larger, distinct keys)
+            // per-segment sums: runs of equal segment index are contiguous lanes (the index
+            // grows with the sample; idle lanes carry larger, distinct keys), so a run's sum is
+            // the difference of plain inclusive wave sums at its last lane and before its first
+            // (the lane moves run on every lane: a DPP read from a disabled lane is not defined)
+            const int jprev = lane_prev(jl, -1), jnext = lane_next(jl, -1);
+            const uint64_t heads = __ballot(lane == 0 || jprev != jl);
+            const int hd = run_head(heads, lane);
+            const bool tail = lane == 63 || jnext != jl;
+            const int src = (hd > 0 ? hd - 1 : 0) * 4;
 #pragma unroll
-            for (int o = 1; o < 64; o <<= 1) {
-                const int ko = __shfl_up(jl, o, 64);
-#pragma unroll
-                for (int c = 0; c < 6; ++c) {
-                    const double vo = __shfl_up(v[c], o, 64);
-                    if (lane >= o && ko == jl) v[c] += vo;
-                }
+            for (int c = 0; c < 6; ++c) {
+                const double pc = wave_incl_scan<double>(v[c], lane);
+                const int64_t pb = __builtin_amdgcn_ds_bpermute(src, (int)__double_as_longlong(pc)) & 0xffffffffll;
+                const int64_t pt = __builtin_amdgcn_ds_bpermute(src, (int)(__double_as_longlong(pc) >> 32));
+                const double before = hd > 0 ? __longlong_as_double((long long)(((uint64_t)pt << 32) | (uint64_t)pb)) : 0.0;
+                v[c] = pc - before;
             }
-            const int knx = lane_next(jl, -1);
-            if (valid && (lane == 63 || knx != jl))
+            if (valid && tail)
                 for (int c = 0; c < 6; ++c) acc[wid][c][jl] += v[c];
             __builtin_amdgcn_wave_barrier();
         }
