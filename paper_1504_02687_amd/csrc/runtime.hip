@@ -1507,6 +1507,35 @@ static hb_status grow(hb_ctx *c, T **p, int64_t &cap, int64_t need, const char *
     return HB_OK;
 }
 
+// One descriptor of a checkpointed iteration, on explicit buffers.
+static GDesc ckpt_desc(hb_ctx *c, const float2 *pin, const int64_t *off_in, float2 *xs, int64_t *xoff,
+                       int64_t cap) {
+    GDesc d = base_desc(c);
+    set_iter_scalars(c, d, c->iter);
+    d.pin = pin;
+    d.off_in = off_in;
+    d.samples = xs;
+    d.off_s = xoff;
+    d.cap = cap;
+    d.total = c->d_totals;
+    return d;
+}
+
+static hb_status read_status(hb_ctx *c) {
+    int32_t status = 0;
+    HIPCHK(c, hipMemcpy(&status, c->d_status, sizeof status, hipMemcpyDeviceToHost));
+    if (status == 0) return HB_OK;
+    int32_t zero = 0;
+    HIPCHK(c, hipMemcpy(c->d_status, &zero, sizeof zero, hipMemcpyHostToDevice));
+    if (status & hb::ST_BIN_MISMATCH)
+        return fail(c, HB_EINTERNAL, "binned samples disagree with the tile counts");
+    return fail(c, HB_EOVERFLOW, "sample count too large for int32 histograms or int64 box sums");
+}
+
+// The iterations write straight into the checkpoints: iteration t reads the polylines of
+// checkpoint t, writes its samples, decisions and splat bins into checkpoint t and its new
+// polylines into checkpoint t + 1 (the last one into the context's state buffer). Each
+// iteration first scans the sample counts alone, so every buffer is sized exactly.
 HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
     ENTER(c);
     CHKST(finish_pending(c));
@@ -1519,64 +1548,115 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
     for (auto &k : c->ckpts) c->ckpt_pool.push_back(k);
     c->ckpts.clear();
     c->ckpt_end_iter = -1;
+    CHKST(prepare_ctx(c, 1, 0));
+    CHKST(ensure_desc(c, 1));
+    CHKST(wait_desc(c));
+    const int T = n_iters;
+    const int64_t E = c->E;
     const int64_t plane = (int64_t)c->B * c->P.grid_w * c->P.grid_h;
-    const size_t E1 = (size_t)c->E + 1;
-    std::vector<int64_t> counts;
-    for (int t = 0; t < n_iters; ++t) {
+    const size_t E1 = (size_t)E + 1;
+    const int64_t nt1 = (int64_t)hb::tiles_of(std::max(1, c->B), c->P.grid_w, c->P.grid_h).n + 1;
+    const Shape sh = hb::shape_of(E, std::max(1, c->B), c->P.grid_w, c->P.grid_h);
+    auto take = [&]() {
         hb_ctx::Ckpt k;
         if (!c->ckpt_pool.empty()) {
             k = c->ckpt_pool.front();        // slot t reuses the buffers of the last slot t
             c->ckpt_pool.erase(c->ckpt_pool.begin());
         }
+        return k;
+    };
+    auto fail_free = [&](hb_status st) {
+        free_ckpts(c);
+        return st;
+    };
+    // checkpoint 0: the polylines that enter the run
+    {
+        hb_ctx::Ckpt k = take();
         k.n = c->n_state;
+        hb_status st = grow(c, &k.pts, k.cap_n, std::max<int64_t>(1, k.n), "checkpoint");
+        c->ckpts.push_back(k);
+        if (st != HB_OK) return fail_free(st);
+        HIPCHK(c, hipMemcpyAsync(k.pts, c->pts[c->ps], sizeof(float2) * k.n, hipMemcpyDeviceToDevice, c->stream));
+    }
+    std::vector<int64_t> counts;
+    for (int t = 0; t < T; ++t) {
+        hb_ctx::Ckpt &k = c->ckpts[t];
         k.iter = c->iter;
-        hb_status st = grow(c, &k.pts, k.cap_n, k.n, "checkpoint");
         int64_t cap_e = k.cap_e, cap_e2 = k.cap_e, cap_e3 = k.cap_e, cap_e4 = k.cap_e;
-        if (st == HB_OK) st = grow(c, &k.off, cap_e, c->E + 1, "checkpoint");
-        if (st == HB_OK) st = grow(c, &k.xoff, cap_e2, c->E + 1, "checkpoint");
-        if (st == HB_OK) st = grow(c, &k.counts, cap_e3, c->E + 1, "checkpoint");
-        if (st == HB_OK) st = grow(c, &k.lens, cap_e4, c->E + 1, "checkpoint");
+        hb_status st = grow(c, &k.off, cap_e, E + 1, "checkpoint");
+        if (st == HB_OK) st = grow(c, &k.xoff, cap_e2, E + 1, "checkpoint");
+        if (st == HB_OK) st = grow(c, &k.counts, cap_e3, E + 1, "checkpoint");
+        if (st == HB_OK) st = grow(c, &k.lens, cap_e4, E + 1, "checkpoint");
         k.cap_e = std::min(std::min(cap_e, cap_e2), std::min(cap_e3, cap_e4));
         if (st == HB_OK) st = grow(c, &k.hist, k.cap_px, plane, "checkpoint");
-        c->ckpts.push_back(k);
-        if (st != HB_OK) {
-            free_ckpts(c);
-            return st;
+        if (st != HB_OK) return fail_free(st);
+        // offsets, sample counts and lengths of the polylines entering iteration t
+        const int64_t *off_in = t == 0 ? c->off[c->os] : c->ckpts[t - 1].xoff;
+        HIPCHK(c, hipMemcpyAsync(k.off, off_in, sizeof(int64_t) * E1, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(k.counts, c->d_counts, sizeof(int64_t) * E, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipMemcpyAsync(k.lens, c->d_lens, sizeof(double) * E, hipMemcpyDeviceToDevice, c->stream));
+        // the sample offsets, and the sample count that sizes this iteration's buffers
+        GDesc d = ckpt_desc(c, k.pts, k.off, nullptr, k.xoff, INT64_MAX);
+        c->h_desc[0] = d;
+        CHKST(upload_desc(c, 1));
+        HIPCHK(c, hb::launch_scan(c->d_desc, 1, sh, c->stream));
+        int64_t ns = 0;
+        CHKST(read_scalar(c, c->d_totals, &ns));
+        CHKST(read_status(c));
+        k.ns = ns;
+        int64_t cap_ns2 = k.cap_ns, cap_t2 = k.cap_t;
+        st = grow(c, &k.xs, k.cap_ns, std::max<int64_t>(1, ns), "checkpoint");
+        if (st == HB_OK) st = grow(c, &k.jacc, cap_ns2, std::max<int64_t>(1, ns), "checkpoint");
+        if (st == HB_OK) st = grow(c, &k.bsrc, k.cap_bs, std::max<int64_t>(1, ns), "checkpoint");
+        if (st == HB_OK) st = grow(c, &k.toff, k.cap_t, nt1, "checkpoint");
+        if (st == HB_OK) st = grow(c, &k.soff, cap_t2, nt1, "checkpoint");
+        k.cap_ns = std::min(k.cap_ns, cap_ns2);
+        k.cap_t = std::min(k.cap_t, cap_t2);
+        if (st == HB_OK) st = ensure_capacity(c, ns + 64);   // splat bins and the final state
+        if (st != HB_OK) return fail_free(st);
+        float2 *pnew = c->pts[c->ps];
+        if (t + 1 < T) {
+            hb_ctx::Ckpt kn = take();
+            kn.n = ns;
+            st = grow(c, &kn.pts, kn.cap_n, std::max<int64_t>(1, ns), "checkpoint");
+            c->ckpts.push_back(kn);
+            if (st != HB_OK) return fail_free(st);
+            pnew = kn.pts;
         }
-        HIPCHK(c, hipMemcpyAsync(k.pts, c->pts[c->ps], sizeof(float2) * k.n, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(k.off, c->off[c->os], sizeof(int64_t) * E1, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(k.counts, c->d_counts, sizeof(int64_t) * c->E, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(k.lens, c->d_lens, sizeof(double) * c->E, hipMemcpyDeviceToDevice, c->stream));
-        c->last_counts.clear();
-        CHKST(enqueue_run(c, 1, HB_RUN_RECORD_DECISIONS | kRunRecordBins));
-        CHKST(finish_pending(c));
-        counts.insert(counts.end(), c->last_counts.begin(), c->last_counts.end());
-        // the samples, decisions and histogram of this iteration
-        hb_ctx::Ckpt &kk = c->ckpts.back();
-        kk.ns = c->n_samples;
-        int64_t cap_ns2 = kk.cap_ns;
-        const int64_t nt1 = (int64_t)hb::tiles_of(std::max(1, c->B), c->P.grid_w, c->P.grid_h).n + 1;
-        int64_t cap_t2 = kk.cap_t;
-        st = grow(c, &kk.xs, kk.cap_ns, kk.ns, "checkpoint");
-        if (st == HB_OK) st = grow(c, &kk.jacc, cap_ns2, kk.ns, "checkpoint");
-        if (st == HB_OK) st = grow(c, &kk.bsrc, kk.cap_bs, kk.ns, "checkpoint");
-        if (st == HB_OK) st = grow(c, &kk.toff, kk.cap_t, nt1, "checkpoint");
-        if (st == HB_OK) st = grow(c, &kk.soff, cap_t2, nt1, "checkpoint");
-        kk.cap_ns = std::min(kk.cap_ns, cap_ns2);
-        kk.cap_t = std::min(kk.cap_t, cap_t2);
-        if (st != HB_OK) {
-            free_ckpts(c);
-            return st;
-        }
-        HIPCHK(c, hipMemcpyAsync(kk.xs, c->pts[c->ss], sizeof(float2) * kk.ns, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(kk.xoff, c->off[c->so], sizeof(int64_t) * E1, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(kk.jacc, c->d_jacc, (size_t)kk.ns, hipMemcpyDeviceToDevice, c->stream));
+        hb_ctx::Ckpt &kk = c->ckpts[t];
+        // the iteration, on the checkpoint buffers
+        d = ckpt_desc(c, kk.pts, kk.off, kk.xs, kk.xoff, ns);
+        d.pnew = pnew;
+        d.jacc = kk.jacc;
+        d.bin_src = kk.bsrc;
+        d.record = 1;
+        c->h_desc[0] = d;
+        CHKST(wait_desc(c));
+        CHKST(upload_desc(c, 1));
+        const GDesc *dd = c->d_desc;
+        HIPCHK(c, hb::launch_clear_hist(dd, 1, sh, c->stream));
+        HIPCHK(c, hb::launch_resample_count(dd, 1, sh, c->tune_ru, c->stream));
+        HIPCHK(c, hb::launch_bin_hist(dd, 1, sh, c->stream));
+        for (int kp = 0; kp < c->P.box_passes; ++kp)
+            HIPCHK(c, hb::launch_box_pass(dd, 1, sh, c->P.grid_w, kp, c->stream));
+        HIPCHK(c, hb::launch_density_cells(dd, 1, sh, std::max(1, c->B), c->stream));
+        HIPCHK(c, hb::launch_advect_smooth(dd, 1, sh, c->tune_au, c->stream));
         HIPCHK(c, hipMemcpyAsync(kk.hist, c->d_hist, sizeof(int32_t) * plane, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipMemcpyAsync(kk.bsrc, c->d_binsrc, sizeof(uint32_t) * kk.ns, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(kk.toff, c->d_tile_off, sizeof(int64_t) * nt1, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(kk.soff, c->d_seg_off, sizeof(int64_t) * nt1, hipMemcpyDeviceToDevice, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        CHKST(read_status(c));
+        counts.push_back(ns);
+        c->iter += 1;
     }
+    // the state after the run: polylines in pts[ps] with the last sample offsets
+    const hb_ctx::Ckpt &kl = c->ckpts[T - 1];
+    HIPCHK(c, hipMemcpyAsync(c->off[c->os], kl.xoff, sizeof(int64_t) * E1, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->n_state = kl.ns;
+    c->have_samples = false;   // the samples stay in the checkpoints
+    c->have_jacc = false;
+    c->have_maps = true;
     c->last_counts = counts;
     c->ckpt_end_iter = c->iter;
     return HB_OK;

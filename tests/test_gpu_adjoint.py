@@ -130,3 +130,23 @@ def test_backward_needs_fresh_checkpoints(hb):
         b.run(1)
         with pytest.raises(hb.HBError):
             hb.hb_backward(b.ctx, 1, 3, 80)
+
+
+def test_checkpointed_forward_matches_plain_run(hb):
+    """The checkpointed forward writes straight into its checkpoints; its polylines, sample
+    counts and ink equal a plain run's bit for bit."""
+    w = workloads.scaled("zipf", n_edges=3000, grid=256, groups=4, n_iters=3, seed=21)
+    res = []
+    for ckpt in (False, True):
+        with _setup(hb, w) as b:
+            if ckpt:
+                hb.hb_forward_ckpt(b.ctx, 3)
+            else:
+                b.run(3)
+            res.append((b.points(), b.iter_counts(3), b.ink(), b.iteration))
+    (o1, x1), c1, i1, t1 = res[0]
+    (o2, x2), c2, i2, t2 = res[1]
+    np.testing.assert_array_equal(o1, o2)
+    np.testing.assert_array_equal(x1, x2)
+    np.testing.assert_array_equal(c1, c2)
+    assert i1 == i2 and t1 == t2 == 3
