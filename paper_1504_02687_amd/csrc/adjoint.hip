@@ -132,7 +132,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
     const int64_t plane = (int64_t)W * H;
     const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
     const int l = d.group[e];
-    const float2 *__restrict__ grad = d.grad + (int64_t)l * plane;
+    (void)plane;
+    const HB_G Quad *__restrict__ grad = glb(d.gradq + 2 * (int64_t)l * (W + 1) * (H + 1));
     const float2 *__restrict__ xs = d.samples + o0;
     const float2 *__restrict__ yb = d.adj_in + o0;
     float2 *__restrict__ xb = d.adj_out + o0;
@@ -160,13 +161,23 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
         const int jj = interior ? (int)jv[j] : -2;
         if (jj >= 0) {
             const float2 x = xs[j];
-            const Taps t0 = taps_of(x.x, x.y, W, H);
+            const Cell t0 = cell_of(x.x, x.y, W, H);
+            const Quad q0 = ldq(grad, 2 * t0.c), q1 = ldq(grad, 2 * t0.c + 1);
+            const float2 g00 = make_float2(q0.a, q0.b), g10 = make_float2(q0.c, q0.d);
+            const float2 g01 = make_float2(q1.a, q1.b), g11 = make_float2(q1.c, q1.d);
             double gx, gy;
-            bilin2(grad, t0, gx, gy);
+            {
+                // the forward's bilinear gradient sample (same arithmetic)
+                const double tx = t0.tx, ty = t0.ty;
+                const double w00 = (1.0 - tx) * (1.0 - ty), w10 = tx * (1.0 - ty);
+                const double w01 = (1.0 - tx) * ty, w11 = tx * ty;
+                gx = w00 * g00.x + w10 * g10.x + w01 * g01.x + w11 * g11.x;
+                gy = w00 * g00.y + w10 * g10.y + w01 * g01.y + w11 * g11.y;
+            }
             const double nrm = sqrt(gx * gx + gy * gy);
             const bool big = nrm > eps;
-            const double den = big ? nrm : eps;
-            const double dx = gx / den, dy = gy / den;
+            const double inv = 1.0 / (big ? nrm : eps);   // one division for d and v
+            const double dx = gx * inv, dy = gy * inv;
             const double m = ldexp(h, -jj);
             const double cx = (double)x.x + m * dx, cy = (double)x.y + m * dy;
             if (cx < 0.0 || cx > xmax) wx = 0.0;
@@ -174,13 +185,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
             double vx, vy;
             if (big) {
                 const double dw = dx * wx + dy * wy;
-                vx = (wx - dx * dw) / nrm;
-                vy = (wy - dy * dw) / nrm;
+                vx = (wx - dx * dw) * inv;
+                vy = (wy - dy * dw) * inv;
             } else {
-                vx = wx / eps;
-                vy = wy / eps;
+                vx = wx * inv;
+                vy = wy * inv;
             }
-            const float2 g00 = grad[t0.o00], g10 = grad[t0.o10], g01 = grad[t0.o01], g11 = grad[t0.o11];
             const double v00 = g00.x * vx + g00.y * vy, v10 = g10.x * vx + g10.y * vy;
             const double v01 = g01.x * vx + g01.y * vy, v11 = g11.x * vx + g11.y * vy;
             const double tx = t0.tx, ty = t0.ty;
@@ -237,23 +247,42 @@ __global__ __launch_bounds__(kBlock) void k_adj_params(const GDesc *__restrict__
         const int X0 = tx * kTile - 1, Y0 = ty * kTile - 1;   // grid cell (0, 0)
         for (int c = threadIdx.x; c < 2 * GN; c += kBlock) (&sA[0][0])[c] = 0ull;
         __syncthreads();
-        for (int64_t i = beg + threadIdx.x; i < end; i += kBlock) {
-            const uint32_t p = d.abin_src[i];
-            const float2 m = d.mv[p];
-            if (m.x == 0.0f && m.y == 0.0f) continue;
-            const float2 x = d.samples[p];
-            const Taps tp = taps_of(x.x, x.y, W, H);
-            const float ftx = tp.tx, fty = tp.ty;
-            const float w[4] = {(1.0f - ftx) * (1.0f - fty), ftx * (1.0f - fty),
-                                (1.0f - ftx) * fty, ftx * fty};
-            const uint32_t o[4] = {tp.o00, tp.o10, tp.o01, tp.o11};
-            const float mx = m.x * scale, my = m.y * scale;
+        // four entries per thread in flight (the gathers of m v and x depend on the entry)
+        for (int64_t i0 = beg + threadIdx.x; i0 < end; i0 += 4 * kBlock) {
+            uint32_t pe[4];
+            float2 me[4], xe[4];
 #pragma unroll
-            for (int q = 0; q < 4; ++q) {
-                const int v = (int)(o[q] / (uint32_t)W), u = (int)(o[q] - (uint32_t)v * (uint32_t)W);
-                const int c = (v - Y0) * GW + (u - X0);
-                atomicAdd(&sA[0][c], (unsigned long long)(long long)rintf(w[q] * mx));
-                atomicAdd(&sA[1][c], (unsigned long long)(long long)rintf(w[q] * my));
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i0 + r * kBlock;
+                pe[r] = i < end ? d.abin_src[i] : 0u;
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i0 + r * kBlock;
+                me[r] = make_float2(0.0f, 0.0f);
+                xe[r] = make_float2(0.0f, 0.0f);
+                if (i < end) {
+                    me[r] = d.mv[pe[r]];
+                    xe[r] = d.samples[pe[r]];
+                }
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const float2 m = me[r], x = xe[r];
+                if (m.x == 0.0f && m.y == 0.0f) continue;
+                const Taps tp = taps_of(x.x, x.y, W, H);
+                const float ftx = tp.tx, fty = tp.ty;
+                const float w[4] = {(1.0f - ftx) * (1.0f - fty), ftx * (1.0f - fty),
+                                    (1.0f - ftx) * fty, ftx * fty};
+                const uint32_t o[4] = {tp.o00, tp.o10, tp.o01, tp.o11};
+                const float mx = m.x * scale, my = m.y * scale;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int v = (int)(o[q] / (uint32_t)W), u = (int)(o[q] - (uint32_t)v * (uint32_t)W);
+                    const int c = (v - Y0) * GW + (u - X0);
+                    atomicAdd(&sA[0][c], (unsigned long long)(long long)rintf(w[q] * mx));
+                    atomicAdd(&sA[1][c], (unsigned long long)(long long)rintf(w[q] * my));
+                }
             }
         }
         __syncthreads();

@@ -1754,7 +1754,7 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
     for (int t = T - 1; t >= 0; --t) {
         const GDesc *a = c->d_desc + 1 + 2 * (size_t)(T - 1 - t);
         for (int kk = 0; kk < P; ++kk) HIPCHK(c, hb::launch_box_pass(a, 1, s, W, kk, c->stream));
-        HIPCHK(c, hb::launch_density_grad(a, 1, s, B, c->stream));
+        HIPCHK(c, hb::launch_density_cells(a, 1, s, B, c->stream));
         HIPCHK(c, hb::launch_adj_maps(a, s, c->stream));
         HIPCHK(c, hb::launch_adj_advect(a, s, c->stream));
         HIPCHK(c, hb::launch_adj_params(a, s, B, c->stream));
@@ -1771,6 +1771,7 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
         HIPCHK(c, hipMemcpy(c->d_status, &zero, sizeof zero, hipMemcpyHostToDevice));
         return fail(c, HB_EOVERFLOW, "rebuilt maps exceeded a range check");
     }
+    c->have_maps = false;   // the maps buffers now hold the rebuilt maps of the first iteration
     if (loss) *loss = ink;
     if (dL_dM)
         for (int i = 0; i < B * B; ++i) dL_dM[i] = (float)gp[i];
