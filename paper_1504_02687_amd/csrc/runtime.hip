@@ -24,6 +24,8 @@ struct hb_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    hipStream_t side = nullptr;          // second stream of the backward (parameter gradients)
+    std::vector<hipEvent_t> adj_ev;      // events ordering the two streams of the backward
     bool sticky = false;
     std::string err;
 
@@ -615,6 +617,8 @@ HB_API void hb_destroy(hb_ctx *c) {
         if (c->desc_done) (void)hipEventDestroy(c->desc_done);
         for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
         if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+        for (hipEvent_t e : c->adj_ev) (void)hipEventDestroy(e);
+        if (c->side) (void)hipStreamDestroy(c->side);
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
     }
     delete c;
@@ -1750,17 +1754,34 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
     }
     CHKST(upload_desc(c, (size_t)(2 * T + 1)));
     HIPCHK(c, hipMemsetAsync(A.mvmax, 0, sizeof(uint32_t) * T, c->stream));
+    // The parameter gradients of iteration t (tile splat + reduction) run on a second stream,
+    // beside the resampling adjoint of t and the map rebuild of t - 1; iteration t - 1 waits
+    // for them before it overwrites the gradient maps and m v.
+    if (!c->side) HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    while (c->adj_ev.size() < (size_t)(2 * T)) {
+        hipEvent_t ev;
+        HIPCHK(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
+        c->adj_ev.push_back(ev);
+    }
     HIPCHK(c, hb::launch_ink_grad(c->d_desc, s, c->stream));
+    hipEvent_t params_done = nullptr;
     for (int t = T - 1; t >= 0; --t) {
         const GDesc *a = c->d_desc + 1 + 2 * (size_t)(T - 1 - t);
+        hipEvent_t adv_done = c->adj_ev[2 * (size_t)t], par_done = c->adj_ev[2 * (size_t)t + 1];
         for (int kk = 0; kk < P; ++kk) HIPCHK(c, hb::launch_box_pass(a, 1, s, W, kk, c->stream));
         HIPCHK(c, hb::launch_density_cells(a, 1, s, B, c->stream));
+        if (params_done) HIPCHK(c, hipStreamWaitEvent(c->stream, params_done, 0));
         HIPCHK(c, hb::launch_adj_maps(a, s, c->stream));
         HIPCHK(c, hb::launch_adj_advect(a, s, c->stream));
-        HIPCHK(c, hb::launch_adj_params(a, s, B, c->stream));
+        HIPCHK(c, hipEventRecord(adv_done, c->stream));
+        HIPCHK(c, hipStreamWaitEvent(c->side, adv_done, 0));
+        HIPCHK(c, hb::launch_adj_params(a, s, B, c->side));
+        HIPCHK(c, hb::launch_adj_reduce(a, B, P, c->side));
+        HIPCHK(c, hipEventRecord(par_done, c->side));
+        params_done = par_done;
         HIPCHK(c, hb::launch_adj_resample(a + 1, s, c->stream));
-        HIPCHK(c, hb::launch_adj_reduce(a, B, P, c->stream));
     }
+    if (params_done) HIPCHK(c, hipStreamWaitEvent(c->stream, params_done, 0));
     std::vector<double> gp((size_t)(B * B + P));
     HIPCHK(c, hipMemcpyAsync(gp.data(), A.gparam, sizeof(double) * gp.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
