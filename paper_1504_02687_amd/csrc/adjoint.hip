@@ -439,21 +439,32 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
                 v[5] = -tb * t * sR[wid][jl];
             }
             // per-segment sums: runs of equal segment index are contiguous lanes (the index
-            // grows with the sample; idle lanes carry larger, distinct keys), so a run's sum is
-            // the difference of plain inclusive wave sums at its last lane and before its first
-            // (the lane moves run on every lane: a DPP read from a disabled lane is not defined)
+            // grows with the sample; idle lanes carry larger, distinct keys). Runs of one or two
+            // samples (segments about as long as the sampling step) take one lane shift;
+            // longer runs the difference of plain inclusive wave sums at the run's last lane
+            // and before its first. (Lane moves run on every lane: a DPP read from a disabled
+            // lane is not defined.)
             const int jprev = lane_prev(jl, -1), jnext = lane_next(jl, -1);
             const uint64_t heads = __ballot(lane == 0 || jprev != jl);
-            const int hd = run_head(heads, lane);
             const bool tail = lane == 63 || jnext != jl;
-            const int src = (hd > 0 ? hd - 1 : 0) * 4;
+            if ((heads | (heads << 1) | 1ull) == ~0ull) {
+                // every lane is a head or directly follows one: runs of length <= 2
 #pragma unroll
-            for (int c = 0; c < 6; ++c) {
-                const double pc = wave_incl_scan<double>(v[c], lane);
-                const int64_t pb = __builtin_amdgcn_ds_bpermute(src, (int)__double_as_longlong(pc)) & 0xffffffffll;
-                const int64_t pt = __builtin_amdgcn_ds_bpermute(src, (int)(__double_as_longlong(pc) >> 32));
-                const double before = hd > 0 ? __longlong_as_double((long long)(((uint64_t)pt << 32) | (uint64_t)pb)) : 0.0;
-                v[c] = pc - before;
+                for (int c = 0; c < 6; ++c) {
+                    const double pv = lane_prev(v[c], 0.0);
+                    if (jprev == jl) v[c] += pv;
+                }
+            } else {
+                const int hd = run_head(heads, lane);
+                const int src = (hd > 0 ? hd - 1 : 0) * 4;
+#pragma unroll
+                for (int c = 0; c < 6; ++c) {
+                    const double pc = wave_incl_scan<double>(v[c], lane);
+                    const int64_t pb = __builtin_amdgcn_ds_bpermute(src, (int)__double_as_longlong(pc)) & 0xffffffffll;
+                    const int64_t pt = __builtin_amdgcn_ds_bpermute(src, (int)(__double_as_longlong(pc) >> 32));
+                    const double before = hd > 0 ? __longlong_as_double((long long)(((uint64_t)pt << 32) | (uint64_t)pb)) : 0.0;
+                    v[c] = pc - before;
+                }
             }
             if (valid && tail)
                 for (int c = 0; c < 6; ++c) acc[wid][c][jl] += v[c];

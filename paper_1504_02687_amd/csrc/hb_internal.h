@@ -32,6 +32,7 @@ constexpr int64_t kBinCounters = 1 << 18;          // counters of all sets, at m
 constexpr int64_t kSegEntries = 1 << 16;            // entries per tile-histogram work item
 constexpr int kTileBlocksMax = 2048;                // blocks of one graph in k_tile_hist
 constexpr int kRedSlices = 32;                      // slices per parameter in k_adj_reduce
+constexpr int kInkSlices = 256;                     // slices of the ink sum
 static_assert(HB_MAX_EDGE_WEIGHT < (1u << (32 - kLocalBits)), "weights must fit an entry");
 
 // Four map values of one bilinear cell (16 bytes, one load).
@@ -162,6 +163,8 @@ hipError_t launch_density_cells(const GDesc *desc, int ng, const Shape &tot, int
 hipError_t launch_advect_smooth(const GDesc *desc, int ng, const Shape &tot, int u,
                                 hipStream_t st);
 hipError_t launch_fill_totals(const GDesc *desc, int ng, int T, hipStream_t st);
+// ink = sum of n polyline lengths, fixed order; part[kInkSlices] receives it (device)
+hipError_t launch_ink(const double *lens, int64_t n, double *part, hipStream_t st);
 
 // Adjoint kernels (one graph per launch).
 hipError_t launch_ink_grad(const GDesc *desc, const Shape &tot, hipStream_t st);

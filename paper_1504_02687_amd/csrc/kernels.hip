@@ -759,6 +759,32 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
     }
 }
 
+// Total length of the polylines (the ink): sum of the per-edge lengths in a fixed order.
+// Stage 1: block j sums its contiguous slice (fixed per-thread order, fixed tree) into
+// part[j]; stage 2: one block sums the kInkSlices slice sums in order into part[kInkSlices].
+__global__ __launch_bounds__(kBlock) void k_ink_slices(const double *__restrict__ lens,
+                                                       int64_t n, double *part) {
+    const int64_t per = (n + kInkSlices - 1) / kInkSlices;
+    const int64_t a = (int64_t)blockIdx.x * per, b = a + per < n ? a + per : n;
+    double s = 0.0;
+    for (int64_t i = a + threadIdx.x; i < b; i += kBlock) s += lens[i];
+    __shared__ double red[kBlock];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = kBlock / 2; w > 0; w >>= 1) {
+        if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(kBlock) void k_ink_total(double *part) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int j = 0; j < kInkSlices; ++j) s += part[j];
+    part[kInkSlices] = s;
+}
+
 // Mark the per-iteration sample totals of every graph as not produced yet (-1). One block
 // per graph; desc[g] is graph g's descriptor of the first iteration.
 __global__ __launch_bounds__(kBlock) void k_fill_totals(const GDesc *__restrict__ gd, int T) {
@@ -890,6 +916,14 @@ hipError_t launch_density_cells(const GDesc *desc, int ng, const Shape &tot, int
     hipError_t e = launch_density_grad(desc, ng, tot, bmax, st);
     if (e != hipSuccess || tot.cell <= 0) return e;
     hipLaunchKernelGGL(k_cells, grid_of(tot.cell), dim3(kBlock), 0, st, desc, ng);
+    return hipGetLastError();
+}
+
+hipError_t launch_ink(const double *lens, int64_t n, double *part, hipStream_t st) {
+    hipLaunchKernelGGL(k_ink_slices, dim3(kInkSlices), dim3(kBlock), 0, st, lens, n, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_ink_total, dim3(1), dim3(64), 0, st, part);
     return hipGetLastError();
 }
 

@@ -61,6 +61,7 @@ struct hb_ctx {
     int64_t *d_counts = nullptr, *d_tsum = nullptr, *d_totals = nullptr;
     double *d_lens = nullptr;
     int32_t *d_status = nullptr;
+    double *d_ink = nullptr;             // [kInkSlices + 1] ink slice sums and total
     int totals_cap = 0;
 
     // maps of the last iteration
@@ -596,6 +597,7 @@ HB_API void hb_destroy(hb_ctx *c) {
         dfree(&c->d_totals);
         dfree(&c->d_lens);
         dfree(&c->d_status);
+        dfree(&c->d_ink);
         dfree(&c->d_hist);
         dfree(&c->d_histx);
         dfree(&c->d_bins);
@@ -1422,11 +1424,10 @@ HB_API hb_status hb_get_ink(hb_ctx *c, double *ink) {
     CHKST(finish_pending(c));
     if (!ink) return fail(c, HB_EINVAL, "ink is NULL");
     if (!c->have_graph) return fail(c, HB_ESTATE, "no graph");
-    std::vector<double> L((size_t)c->E);
-    if (c->E > 0) CHKST(copy_out(c, L.data(), c->d_lens, sizeof(double) * (size_t)c->E, 0));
-    double s = 0.0;
-    for (double v : L) s += v;
-    *ink = s;
+    if (!c->d_ink) CHKST(dalloc(c, &c->d_ink, (size_t)hb::kInkSlices + 1, "ink"));
+    HIPCHK(c, hb::launch_ink(c->d_lens, c->E, c->d_ink, c->stream));
+    HIPCHK(c, hipMemcpyAsync(ink, c->d_ink + hb::kInkSlices, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
     return HB_OK;
 }
 
@@ -1705,10 +1706,10 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
     HIPCHK(c, hipMemsetAsync(A.gparam, 0, sizeof(double) * (B * B + P), c->stream));
 
     // loss: total length of the final polylines (the lengths the last advection wrote)
-    std::vector<double> Lh((size_t)E);
-    if (E > 0) HIPCHK(c, hipMemcpy(Lh.data(), c->d_lens, sizeof(double) * E, hipMemcpyDeviceToHost));
+    if (!c->d_ink) CHKST(dalloc(c, &c->d_ink, (size_t)hb::kInkSlices + 1, "ink"));
+    HIPCHK(c, hb::launch_ink(c->d_lens, E, c->d_ink, c->stream));
     double ink = 0.0;
-    for (double v : Lh) ink += v;
+    HIPCHK(c, hipMemcpyAsync(&ink, c->d_ink + hb::kInkSlices, sizeof(double), hipMemcpyDeviceToHost, c->stream));
 
     const Shape s = hb::shape_of(E, B, W, H);
     GDesc d0 = base_desc(c);
