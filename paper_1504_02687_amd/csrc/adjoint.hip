@@ -8,53 +8,16 @@
 //
 // The density gradient seen by a point of layer l is
 //   g_l(x) = bilinear( sum_b M[l][b] sum_k a_k G_bk , x ),  G_bk = grad(S_b^k) / (2r+1)^(2k),
-// so dL/dM and dL/da follow from gathering the maps G_bk at every moved point; nothing is
-// scattered into map adjoints and every reduction runs in a fixed order (the results are
-// reproducible bit for bit).
+// so dL/dM and dL/da are contractions of m v (step times direction adjoint) at the moved
+// points with bilinear samples of the maps G_bk. They are summed tile by tile: m v is splatted
+// with the bilinear weights into LDS as 64-bit fixed point (exact in any order) and the
+// splat is contracted with the maps; every floating-point reduction runs in a fixed order,
+// so the results are reproducible bit for bit.
 #include <hip/hip_runtime.h>
 
 #include "device_common.h"
 
 namespace hb {
-
-// dL/dp of L = total polyline length: p_bar_j = u_(j-1) - u_j with u the unit vectors of the
-// adjacent segments (zero for zero-length segments). One wave per edge over (pin, off_in),
-// 63 points per trip: lane l takes segment (j, j+1) from its neighbour lane, u_(j-1) comes
-// from lane l-1 (or from the previous trip for lane 0).
-__global__ __launch_bounds__(kBlock) void k_ink_grad(const GDesc *__restrict__ gd, int ng) {
-    const int64_t blk = blockIdx.x;
-    HB_FIND(blk_edge);
-    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    const int64_t e = (blk - d.blk_edge) * kWavesPerBlock + wid;
-    if (e >= d.n_edges) return;
-    const int64_t i0 = d.off_in[e], m = d.off_in[e + 1] - i0;
-    const float2 *p = d.pin + i0;
-    float2 *out = d.adj_out + i0;
-    double cux = 0.0, cuy = 0.0;   // u of the segment ending at the trip's first point
-    for (int64_t j0 = 0; j0 < m; j0 += 63) {
-        const int64_t j = j0 + lane;
-        const float2 c = j < m ? p[j] : make_float2(0.0f, 0.0f);
-        const float nxx = lane_next(c.x, 0.0f), nxy = lane_next(c.y, 0.0f);
-        double ux = 0.0, uy = 0.0;
-        if (lane < 63 && j + 1 < m) {
-            const double dx = (double)nxx - c.x, dy = (double)nxy - c.y;
-            const double l = sqrt(dx * dx + dy * dy);
-            if (l > 0.0) {
-                ux = dx / l;
-                uy = dy / l;
-            }
-        }
-        double px = lane_prev(ux, 0.0), py = lane_prev(uy, 0.0);
-        if (lane == 0) {
-            px = cux;
-            py = cuy;
-        }
-        if (lane < 63 && j < m) out[j] = make_float2((float)(px - ux), (float)(py - uy));
-        cux = read_lane(ux, 62);
-        cuy = read_lane(uy, 62);
-    }
-}
 
 // Gradient maps the parameter gradients gather, from exact int64 differences of the box
 // sums (zero outside the grid), with D_bk = 1/2 grad(S_b^k) / (2r+1)^(2k):
@@ -65,6 +28,7 @@ __global__ __launch_bounds__(kBlock) void k_ink_grad(const GDesc *__restrict__ g
 // gb does not depend on the layer: one record of B float2 per pixel serves every layer, and
 // layer l has its own record of P float2 per pixel (records padded to 16-byte multiples, so a
 // bilinear tap is a few 16-byte loads). One thread per pixel, all layers.
+template <int BMAX>
 __global__ __launch_bounds__(kBlock) void k_adj_maps(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_px);
@@ -75,38 +39,45 @@ __global__ __launch_bounds__(kBlock) void k_adj_maps(const GDesc *__restrict__ g
     const int u = (int)(px % W), v = (int)(px / W);
     const bool hasr = u + 1 < W, hasl = u > 0, hasu = v + 1 < H, hasd = v > 0;
     float2 *gb = d.gbm + px * bp;
-    for (int b = 0; b < bp; ++b) gb[b] = make_float2(0.0f, 0.0f);
+    float gbx[BMAX], gby[BMAX];
+#pragma unroll
+    for (int b = 0; b < BMAX; ++b) gbx[b] = gby[b] = 0.0f;
     for (int l = 0; l < B; ++l)
         for (int k = P; k < pp; ++k) d.gkm[((int64_t)l * plane + px) * pp + k] = make_float2(0.0f, 0.0f);
     for (int k = 0; k < P; ++k) {
-        for (int b = 0; b < B; ++b) {
-            const int64_t *S = d.box + ((int64_t)k * B + b) * plane + px;
-            const int64_t xr = hasr ? S[1] : 0, xl = hasl ? S[-1] : 0;
-            const int64_t yu = hasu ? S[W] : 0, yd = hasd ? S[-W] : 0;
-            const double dx = 0.5 * ((double)(xr - xl) / d.ck[k]);
-            const double dy = 0.5 * ((double)(yu - yd) / d.ck[k]);
-            if (d.a[k] != 0.0) {
-                float2 g = gb[b];
-                g.x = (float)((double)g.x + d.a[k] * dx);
-                g.y = (float)((double)g.y + d.a[k] * dy);
-                gb[b] = g;
+        // D_bk of every group at this pixel, read once per pass
+        double dxs[BMAX], dys[BMAX];
+#pragma unroll
+        for (int b = 0; b < BMAX; ++b) {
+            dxs[b] = dys[b] = 0.0;
+            if (b < B) {
+                const int64_t *S = d.box + ((int64_t)k * B + b) * plane + px;
+                const int64_t xr = hasr ? S[1] : 0, xl = hasl ? S[-1] : 0;
+                const int64_t yu = hasu ? S[W] : 0, yd = hasd ? S[-W] : 0;
+                dxs[b] = 0.5 * ((double)(xr - xl) / d.ck[k]);
+                dys[b] = 0.5 * ((double)(yu - yd) / d.ck[k]);
+                if (d.a[k] != 0.0) {
+                    gbx[b] = (float)((double)gbx[b] + d.a[k] * dxs[b]);
+                    gby[b] = (float)((double)gby[b] + d.a[k] * dys[b]);
+                }
             }
         }
         for (int l = 0; l < B; ++l) {
             double ax = 0.0, ay = 0.0;
-            for (int b = 0; b < B; ++b) {
-                const int64_t *S = d.box + ((int64_t)k * B + b) * plane + px;
-                const int64_t xr = hasr ? S[1] : 0, xl = hasl ? S[-1] : 0;
-                const int64_t yu = hasu ? S[W] : 0, yd = hasd ? S[-W] : 0;
-                const double dx = 0.5 * ((double)(xr - xl) / d.ck[k]);
-                const double dy = 0.5 * ((double)(yu - yd) / d.ck[k]);
-                const double mlb = (double)d.M[l * B + b];
-                ax += mlb * dx;
-                ay += mlb * dy;
+#pragma unroll
+            for (int b = 0; b < BMAX; ++b) {
+                if (b < B) {
+                    const double mlb = (double)d.M[l * B + b];
+                    ax += mlb * dxs[b];
+                    ay += mlb * dys[b];
+                }
             }
             d.gkm[((int64_t)l * plane + px) * pp + k] = make_float2((float)ax, (float)ay);
         }
     }
+#pragma unroll
+    for (int b = 0; b < BMAX; ++b)
+        if (b < bp) gb[b] = make_float2(b < B ? gbx[b] : 0.0f, b < B ? gby[b] : 0.0f);
 }
 
 // Transposed Laplacian smoothing and advection, fused. One wave per edge, chunks of 62
@@ -148,7 +119,42 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
         const bool inr = j >= 0 && j < n;
         const bool interior = inr && j > 0 && j < n - 1;
         float2 ybar = make_float2(0.0f, 0.0f);
-        if (inr) ybar = yb[j];
+        if (d.ink_pts) {
+            // the output polylines are the final ones: y_bar_j = u_(j-1) - u_j, u the unit
+            // vectors of the adjacent segments (the gradient of the ink)
+            const float2 *pp = d.ink_pts + o0;
+            const float2 c = inr ? pp[j] : make_float2(0.0f, 0.0f);
+            float nxx = lane_next(c.x, 0.0f), nxy = lane_next(c.y, 0.0f);
+            if (lane == 63 && j + 1 < n) {
+                nxx = pp[j + 1].x;
+                nxy = pp[j + 1].y;
+            }
+            double ux = 0.0, uy = 0.0;
+            if (inr && j + 1 < n) {
+                const double dx = (double)nxx - c.x, dy = (double)nxy - c.y;
+                const double l = sqrt(dx * dx + dy * dy);
+                if (l > 0.0) {
+                    ux = dx / l;
+                    uy = dy / l;
+                }
+            }
+            double pux = lane_prev(ux, 0.0), puy = lane_prev(uy, 0.0);
+            if (lane == 0) {
+                pux = puy = 0.0;
+                if (inr && j >= 1) {
+                    const float2 a = pp[j - 1];
+                    const double dx = (double)c.x - a.x, dy = (double)c.y - a.y;
+                    const double l = sqrt(dx * dx + dy * dy);
+                    if (l > 0.0) {
+                        pux = dx / l;
+                        puy = dy / l;
+                    }
+                }
+            }
+            if (inr) ybar = make_float2((float)(pux - ux), (float)(puy - uy));
+        } else if (inr) {
+            ybar = yb[j];
+        }
         const double qx = interior ? (double)ybar.x : 0.0, qy = interior ? (double)ybar.y : 0.0;
         const double qlx = lane_prev(qx, 0.0), qly = lane_prev(qy, 0.0);
         const double qrx = lane_next(qx, 0.0), qry = lane_next(qy, 0.0);
@@ -585,14 +591,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_reduce_sum(const GDesc *__restri
 
 static inline dim3 grid1(int64_t blocks) { return dim3((unsigned)(blocks > 0 ? blocks : 0)); }
 
-hipError_t launch_ink_grad(const GDesc *desc, const Shape &tot, hipStream_t st) {
-    if (tot.edge <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_ink_grad, grid1(tot.edge), dim3(kBlock), 0, st, desc, 1);
-    return hipGetLastError();
-}
-
-hipError_t launch_adj_maps(const GDesc *desc, const Shape &tot, hipStream_t st) {
-    hipLaunchKernelGGL(k_adj_maps, grid1(tot.px), dim3(kBlock), 0, st, desc, 1);
+hipError_t launch_adj_maps(const GDesc *desc, const Shape &tot, int bmax, hipStream_t st) {
+    if (bmax <= 8) hipLaunchKernelGGL(k_adj_maps<8>, grid1(tot.px), dim3(kBlock), 0, st, desc, 1);
+    else hipLaunchKernelGGL(k_adj_maps<16>, grid1(tot.px), dim3(kBlock), 0, st, desc, 1);
     return hipGetLastError();
 }
 

@@ -108,6 +108,8 @@ struct GDesc {
 
     // adjoint of one iteration (frozen decisions)
     const float2 *adj_in;       // adjoint of this stage's output points
+    const float2 *ink_pts;      // if set: the output points are the final polylines and their
+                                // adjoint is the gradient of the ink, computed in place
     float2 *adj_out;            // adjoint of this stage's input points
     // D_bk = grad(pass k of group b) / (2r+1)^(2k); records padded to an even float2 count
     float2 *gbm;                // [H][W][bp]: sum_k a_k D_bk for every group b (all layers)
@@ -167,8 +169,7 @@ hipError_t launch_fill_totals(const GDesc *desc, int ng, int T, hipStream_t st);
 hipError_t launch_ink(const double *lens, int64_t n, double *part, hipStream_t st);
 
 // Adjoint kernels (one graph per launch).
-hipError_t launch_ink_grad(const GDesc *desc, const Shape &tot, hipStream_t st);
-hipError_t launch_adj_maps(const GDesc *desc, const Shape &tot, hipStream_t st);
+hipError_t launch_adj_maps(const GDesc *desc, const Shape &tot, int bmax, hipStream_t st);
 hipError_t launch_adj_advect(const GDesc *desc, const Shape &tot, hipStream_t st);
 hipError_t launch_adj_params(const GDesc *desc, const Shape &tot, int bmax, hipStream_t st);
 hipError_t launch_adj_resample(const GDesc *desc, const Shape &tot, hipStream_t st);

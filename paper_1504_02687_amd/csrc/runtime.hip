@@ -1602,9 +1602,12 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
         HIPCHK(c, hipMemcpyAsync(k.lens, c->d_lens, sizeof(double) * E, hipMemcpyDeviceToDevice, c->stream));
         // the sample offsets, and the sample count that sizes this iteration's buffers
         GDesc d = ckpt_desc(c, k.pts, k.off, nullptr, k.xoff, INT64_MAX);
+        CHKST(wait_desc(c));   // the staging copy of the last upload has been consumed
         c->h_desc[0] = d;
         CHKST(upload_desc(c, 1));
         HIPCHK(c, hb::launch_scan(c->d_desc, 1, sh, c->stream));
+        // one synchronisation per iteration: the sample count, and the status of the previous
+        // iteration's kernels and of this scan
         int64_t ns = 0;
         CHKST(read_scalar(c, c->d_totals, &ns));
         CHKST(read_status(c));
@@ -1635,8 +1638,8 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
         d.jacc = kk.jacc;
         d.bin_src = kk.bsrc;
         d.record = 1;
-        c->h_desc[0] = d;
         CHKST(wait_desc(c));
+        c->h_desc[0] = d;
         CHKST(upload_desc(c, 1));
         const GDesc *dd = c->d_desc;
         HIPCHK(c, hb::launch_clear_hist(dd, 1, sh, c->stream));
@@ -1649,8 +1652,6 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
         HIPCHK(c, hipMemcpyAsync(kk.hist, c->d_hist, sizeof(int32_t) * plane, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(kk.toff, c->d_tile_off, sizeof(int64_t) * nt1, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(kk.soff, c->d_seg_off, sizeof(int64_t) * nt1, hipMemcpyDeviceToDevice, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        CHKST(read_status(c));
         counts.push_back(ns);
         c->iter += 1;
     }
@@ -1658,6 +1659,7 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
     const hb_ctx::Ckpt &kl = c->ckpts[T - 1];
     HIPCHK(c, hipMemcpyAsync(c->off[c->os], kl.xoff, sizeof(int64_t) * E1, hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    CHKST(read_status(c));
     c->n_state = kl.ns;
     c->have_samples = false;   // the samples stay in the checkpoints
     c->have_jacc = false;
@@ -1685,7 +1687,7 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
     int64_t nmax = c->n_state;
     for (auto &k : c->ckpts) nmax = std::max(nmax, std::max(k.n, k.ns));
     CHKST(ensure_maps(c));
-    CHKST(ensure_desc(c, (size_t)(2 * T + 1)));
+    CHKST(ensure_desc(c, (size_t)(2 * T)));
     CHKST(wait_desc(c));
     const int64_t plane = (int64_t)W * H;
     hb_ctx::AdjBufs &A = c->adj;
@@ -1712,16 +1714,10 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
     HIPCHK(c, hipMemcpyAsync(&ink, c->d_ink + hb::kInkSlices, sizeof(double), hipMemcpyDeviceToHost, c->stream));
 
     const Shape s = hb::shape_of(E, B, W, H);
-    GDesc d0 = base_desc(c);
-    set_iter_scalars(c, d0, c->iter);
-    d0.pin = c->pts[c->ps];
-    d0.off_in = c->off[c->os];
-    d0.adj_out = A.a0;
-    c->h_desc[0] = d0;
     float2 *cur = A.a0, *other = A.a1;   // cur: adjoint of the polylines leaving iteration t
     for (int t = T - 1; t >= 0; --t) {
         const hb_ctx::Ckpt &k = c->ckpts[t];
-        const size_t slot = 1 + 2 * (size_t)(T - 1 - t);
+        const size_t slot = 2 * (size_t)(T - 1 - t);
         GDesc a = base_desc(c);                 // maps, smoothing and advection adjoint
         set_iter_scalars(c, a, k.iter);
         a.histx = k.hist;                       // one histogram copy: the checkpoint
@@ -1735,6 +1731,7 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
         a.pp = pp;
         a.adj_in = cur;
         a.adj_out = other;
+        if (t == T - 1) a.ink_pts = c->pts[c->ps];   // the loss gradient, computed in place
         a.partials = A.partials;
         a.max_items = max_items;
         a.abin_src = k.bsrc;
@@ -1753,7 +1750,7 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
         c->h_desc[slot] = a;
         c->h_desc[slot + 1] = q;
     }
-    CHKST(upload_desc(c, (size_t)(2 * T + 1)));
+    CHKST(upload_desc(c, (size_t)(2 * T)));
     HIPCHK(c, hipMemsetAsync(A.mvmax, 0, sizeof(uint32_t) * T, c->stream));
     // The parameter gradients of iteration t (tile splat + reduction) run on a second stream,
     // beside the resampling adjoint of t and the map rebuild of t - 1; iteration t - 1 waits
@@ -1764,15 +1761,14 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
         HIPCHK(c, hipEventCreateWithFlags(&ev, hipEventDisableTiming));
         c->adj_ev.push_back(ev);
     }
-    HIPCHK(c, hb::launch_ink_grad(c->d_desc, s, c->stream));
     hipEvent_t params_done = nullptr;
     for (int t = T - 1; t >= 0; --t) {
-        const GDesc *a = c->d_desc + 1 + 2 * (size_t)(T - 1 - t);
+        const GDesc *a = c->d_desc + 2 * (size_t)(T - 1 - t);
         hipEvent_t adv_done = c->adj_ev[2 * (size_t)t], par_done = c->adj_ev[2 * (size_t)t + 1];
         for (int kk = 0; kk < P; ++kk) HIPCHK(c, hb::launch_box_pass(a, 1, s, W, kk, c->stream));
         HIPCHK(c, hb::launch_density_cells(a, 1, s, B, c->stream));
         if (params_done) HIPCHK(c, hipStreamWaitEvent(c->stream, params_done, 0));
-        HIPCHK(c, hb::launch_adj_maps(a, s, c->stream));
+        HIPCHK(c, hb::launch_adj_maps(a, s, B, c->stream));
         HIPCHK(c, hb::launch_adj_advect(a, s, c->stream));
         HIPCHK(c, hipEventRecord(adv_done, c->stream));
         HIPCHK(c, hipStreamWaitEvent(c->side, adv_done, 0));
