@@ -118,6 +118,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
         const int64_t j = j0 - 1 + lane;
         const bool inr = j >= 0 && j < n;
         const bool interior = inr && j > 0 && j < n - 1;
+        // loads of this trip issued together: decisions and samples do not depend on y_bar
+        int8_t jraw = -2;
+        float2 xsj = make_float2(0.0f, 0.0f);
+        if (inr) {
+            jraw = jv[j];
+            xsj = xs[j];
+        }
         float2 ybar = make_float2(0.0f, 0.0f);
         if (d.ink_pts) {
             // the output polylines are the final ones: y_bar_j = u_(j-1) - u_j, u the unit
@@ -164,9 +171,9 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
         double wy = cf * (double)ybar.y + 0.5 * s * (qly + qry);
         double gxb = wx, gyb = wy;
         float2 mvv = make_float2(0.0f, 0.0f);
-        const int jj = interior ? (int)jv[j] : -2;
+        const int jj = interior ? (int)jraw : -2;
         if (jj >= 0) {
-            const float2 x = xs[j];
+            const float2 x = xsj;
             const Cell t0 = cell_of(x.x, x.y, W, H);
             const Quad q0 = ldq(grad, 2 * t0.c), q1 = ldq(grad, 2 * t0.c + 1);
             const float2 g00 = make_float2(q0.a, q0.b), g10 = make_float2(q0.c, q0.d);
