@@ -523,29 +523,37 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
     // pass B: L_bar and the total of C_bar enter every segment length alike
     const double G = wave_sum(Lbar) + carryP;
     if (G == 0.0) return;
-    for (int64_t i = lane; i < m; i += 64) {
-        double gx = 0.0, gy = 0.0;
-        const float2 c = p[i];
-        if (i > 0) {
-            const float2 q = p[i - 1];
-            const double dx = (double)c.x - q.x, dy = (double)c.y - q.y;
+    // G (u_(i-1) - u_i) with u the unit vectors of the segments: one segment per lane, 63
+    // points per trip, u_(i-1) from lane l-1 (lane 0: from the previous trip)
+    double cux = 0.0, cuy = 0.0;
+    for (int64_t i0 = 0; i0 < m; i0 += 63) {
+        const int64_t i = i0 + lane;
+        const float2 c = i < m ? p[i] : make_float2(0.0f, 0.0f);
+        float nxx = lane_next(c.x, 0.0f), nxy = lane_next(c.y, 0.0f);
+        if (lane == 63 && i + 1 < m) {
+            nxx = p[i + 1].x;
+            nxy = p[i + 1].y;
+        }
+        double ux = 0.0, uy = 0.0;
+        if (lane < 63 && i + 1 < m) {
+            const double dx = (double)nxx - c.x, dy = (double)nxy - c.y;
             const double l = sqrt(__fma_rn(dx, dx, __dmul_rn(dy, dy)));
             if (l > 0.0) {
-                gx += dx / l;
-                gy += dy / l;
+                ux = dx / l;
+                uy = dy / l;
             }
         }
-        if (i + 1 < m) {
-            const float2 q = p[i + 1];
-            const double dx = (double)q.x - c.x, dy = (double)q.y - c.y;
-            const double l = sqrt(__fma_rn(dx, dx, __dmul_rn(dy, dy)));
-            if (l > 0.0) {
-                gx -= dx / l;
-                gy -= dy / l;
-            }
+        double pux = lane_prev(ux, 0.0), puy = lane_prev(uy, 0.0);
+        if (lane == 0) {
+            pux = cux;
+            puy = cuy;
         }
-        const float2 cur = pb[i];
-        pb[i] = make_float2((float)((double)cur.x + G * gx), (float)((double)cur.y + G * gy));
+        if (lane < 63 && i < m) {
+            const float2 cur = pb[i];
+            pb[i] = make_float2((float)((double)cur.x + G * (pux - ux)), (float)((double)cur.y + G * (puy - uy)));
+        }
+        cux = read_lane(ux, 62);
+        cuy = read_lane(uy, 62);
     }
 }
 
