@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
     const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
     const int l = d.group[e];
     (void)plane;
-    const HB_G Quad *__restrict__ grad = glb(d.gradq + 2 * (int64_t)l * (W + 1) * (H + 1));
+    const HB_G Quad *__restrict__ grad = glb(d.gradq + 2 * (int64_t)l * cell_plane(W, H));
     const float2 *__restrict__ xs = d.samples + o0;
     const float2 *__restrict__ yb = d.adj_in + o0;
     float2 *__restrict__ xb = d.adj_out + o0;
@@ -175,18 +175,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
         if (jj >= 0) {
             const float2 x = xsj;
             const Cell t0 = cell_of(x.x, x.y, W, H);
-            const Quad q0 = ldq(grad, 2 * t0.c), q1 = ldq(grad, 2 * t0.c + 1);
+            const Quad q0 = ldq(grad, 2 * t0.g), q1 = ldq(grad, 2 * t0.g + 1);
             const float2 g00 = make_float2(q0.a, q0.b), g10 = make_float2(q0.c, q0.d);
             const float2 g01 = make_float2(q1.a, q1.b), g11 = make_float2(q1.c, q1.d);
             double gx, gy;
-            {
-                // the forward's bilinear gradient sample (same arithmetic)
-                const double tx = t0.tx, ty = t0.ty;
-                const double w00 = (1.0 - tx) * (1.0 - ty), w10 = tx * (1.0 - ty);
-                const double w01 = (1.0 - tx) * ty, w11 = tx * ty;
-                gx = w00 * g00.x + w10 * g10.x + w01 * g01.x + w11 * g11.x;
-                gy = w00 * g00.y + w10 * g10.y + w01 * g01.y + w11 * g11.y;
-            }
+            interp2q(q0, q1, t0, gx, gy);   // the forward's bilinear gradient sample
             const double nrm = sqrt(gx * gx + gy * gy);
             const bool big = nrm > eps;
             const double inv = 1.0 / (big ? nrm : eps);   // one division for d and v

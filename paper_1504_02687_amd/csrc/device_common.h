@@ -241,20 +241,36 @@ __device__ __forceinline__ Taps taps_of(float x, float y, int W, int H) {
     return t;
 }
 
-// Map element at a 32-bit offset (global pointers: base in SGPRs, 32-bit byte offset).
-__device__ __forceinline__ float ldo(const HB_G float *m, uint32_t i) {
-    return *(const HB_G float *)((const HB_G char *)m + (i << 2));
+// Wait for every outstanding vector-memory load of the wave (s_waitcnt vmcnt(0); the
+// export and LDS/scalar counters are left alone).
+__device__ __forceinline__ void vm_wait_all() { __builtin_amdgcn_s_waitcnt(0x0F70); }
+
+// Bilinear interpolation of four taps a (u0,v0), b (u0+1,v0), c (u0,v0+1), d (u0+1,v0+1)
+// at fractions (tx, ty), with one fixed rounding order (products of the weights rounded,
+// the four terms summed a, b, c, d with fused multiply-adds; no contraction left to the
+// compiler), so every kernel and every unrolled variant computes the same bits.
+__device__ __forceinline__ float bilerp(float a, float b, float c, float d, float tx, float ty) {
+#pragma clang fp contract(off)
+    const float sx = 1.0f - tx, sy = 1.0f - ty;
+    float r = (sx * sy) * a;
+    r = __builtin_fmaf(tx * sy, b, r);
+    r = __builtin_fmaf(sx * ty, c, r);
+    return __builtin_fmaf(tx * ty, d, r);
 }
-__device__ __forceinline__ float2 ldo(const HB_G float2 *m, uint32_t i) {
-    return ld2((const HB_G float2 *)((const HB_G char *)m + (i << 3)));
+__device__ __forceinline__ double bilerp(double a, double b, double c, double d, double tx,
+                                         double ty) {
+#pragma clang fp contract(off)
+    const double sx = 1.0 - tx, sy = 1.0 - ty;
+    double r = (sx * sy) * a;
+    r = __builtin_fma(tx * sy, b, r);
+    r = __builtin_fma(sx * ty, c, r);
+    return __builtin_fma(tx * ty, d, r);
 }
-__device__ __forceinline__ float ldo(const float *m, uint32_t i) { return m[i]; }
-__device__ __forceinline__ float2 ldo(const float2 *m, uint32_t i) { return m[i]; }
 
 // Bilinear cell of a sample and the fractions between its taps (the same taps and
-// fractions as taps_of).
+// fractions as taps_of): c indexes its density record, g its gradient record (tiled layout).
 struct Cell {
-    uint32_t c;
+    uint32_t c, g;
     float tx, ty;
 };
 
@@ -265,8 +281,10 @@ __device__ __forceinline__ Cell cell_of(float x, float y, int W, int H) {
     Cell t;
     t.tx = fx - u0f;
     t.ty = fy - v0f;
-    const int u0 = min((int)u0f, W - 1), v0 = min((int)v0f, H - 1);
-    t.c = __umul24((uint32_t)(v0 + 1), (uint32_t)(W + 1)) + (uint32_t)(u0 + 1);
+    const uint32_t cu = (uint32_t)(min((int)u0f, W - 1) + 1), cv = (uint32_t)(min((int)v0f, H - 1) + 1);
+    const uint32_t base = (__umul24(cv >> 1, (uint32_t)cell_tiles_x(W)) + (cu >> 2)) << 3;
+    t.c = base + ((cv & 1u) << 2) + (cu & 3u);
+    t.g = base + ((cu & 2u) << 1) + ((cv & 1u) << 1) + (cu & 1u);
     return t;
 }
 
@@ -281,43 +299,20 @@ __device__ __forceinline__ Quad ldq(const HB_G Quad *m, uint32_t i) {
     return q;
 }
 
-// Density sample from a cell, in FP32 (same arithmetic as sample1).
-__device__ __forceinline__ float sample1q(const HB_G Quad *m, const Cell &t) {
-    const float tx = t.tx, ty = t.ty;
-    const Quad q = ldq(m, t.c);
-    return (1.0f - tx) * (1.0f - ty) * q.a + tx * (1.0f - ty) * q.b +
-           (1.0f - tx) * ty * q.c + tx * ty * q.d;
+// Density sample from the loaded taps of a cell, in FP32 (the precision of the stored map;
+// the acceptance tests).
+__device__ __forceinline__ float interp1q(const Quad &q, const Cell &t) {
+    return bilerp(q.a, q.b, q.c, q.d, t.tx, t.ty);
 }
 
-// Gradient sample from a cell in FP64 (same arithmetic as bilin2).
-__device__ __forceinline__ void bilin2q(const HB_G Quad *m, const Cell &t, double &gx,
-                                        double &gy) {
+// Gradient sample from the loaded taps of a cell (q0: x, y of the first two taps, q1: of
+// the last two), in FP64: the direction of a small gradient between taps of opposite sign
+// keeps the precision of the stored taps.
+__device__ __forceinline__ void interp2q(const Quad &q0, const Quad &q1, const Cell &t,
+                                         double &gx, double &gy) {
     const double tx = t.tx, ty = t.ty;
-    const double w00 = (1.0 - tx) * (1.0 - ty), w10 = tx * (1.0 - ty);
-    const double w01 = (1.0 - tx) * ty, w11 = tx * ty;
-    const Quad q0 = ldq(m, 2 * t.c), q1 = ldq(m, 2 * t.c + 1);
-    gx = w00 * q0.a + w10 * q0.c + w01 * q1.a + w11 * q1.c;
-    gy = w00 * q0.b + w10 * q0.d + w01 * q1.b + w11 * q1.d;
-}
-
-// Density sample in FP32 (the precision of the stored map; the acceptance tests).
-template <typename PF>
-__device__ __forceinline__ float sample1(PF m, const Taps &t) {
-    const float tx = t.tx, ty = t.ty;
-    return (1.0f - tx) * (1.0f - ty) * ldo(m, t.o00) + tx * (1.0f - ty) * ldo(m, t.o10) +
-           (1.0f - tx) * ty * ldo(m, t.o01) + tx * ty * ldo(m, t.o11);
-}
-
-// Gradient sample in FP64: the direction of a small gradient between taps of opposite
-// sign keeps the precision of the stored taps.
-template <typename PF2>
-__device__ __forceinline__ void bilin2(PF2 m, const Taps &t, double &gx, double &gy) {
-    const double tx = t.tx, ty = t.ty;
-    const double w00 = (1.0 - tx) * (1.0 - ty), w10 = tx * (1.0 - ty);
-    const double w01 = (1.0 - tx) * ty, w11 = tx * ty;
-    const float2 f00 = ldo(m, t.o00), f10 = ldo(m, t.o10), f01 = ldo(m, t.o01), f11 = ldo(m, t.o11);
-    gx = w00 * f00.x + w10 * f10.x + w01 * f01.x + w11 * f11.x;
-    gy = w00 * f00.y + w10 * f10.y + w01 * f01.y + w11 * f11.y;
+    gx = bilerp((double)q0.a, (double)q0.c, (double)q1.a, (double)q1.c, tx, ty);
+    gy = bilerp((double)q0.b, (double)q0.d, (double)q1.b, (double)q1.d, tx, ty);
 }
 
 }  // namespace hb

@@ -40,6 +40,17 @@ struct alignas(16) Quad {
     float a, b, c, d;
 };
 
+// Bilinear cells (cu, cv) = (u0 + 1, v0 + 1), cu in [0, W], cv in [0, H], are stored by tiles
+// of 4 x 2 cells, tile (cu / 4, cv / 2) at (cv / 2) * cell_tiles_x(W) + cu / 4, eight records
+// per tile: the density record of a cell at tile * 8 + (cv % 2) * 4 + cu % 4 (a tile is one
+// 128-byte line), its 32-byte gradient record at tile * 8 + ((cu / 2) % 2) * 4 + (cv % 2) * 2
+// + cu % 2 (2 x 2 cells per line). Samples that are close in the plane then share lines
+// whatever the direction of their edge.
+__host__ __device__ inline int32_t cell_tiles_x(int32_t W) { return (W + 4) >> 2; }
+__host__ __device__ inline int64_t cell_plane(int32_t W, int32_t H) {
+    return (int64_t)cell_tiles_x(W) * ((H + 2) >> 1) * 8;
+}
+
 // One graph of one iteration. Every kernel takes an array of these (one per graph of a
 // batch) and finds its graph from blockIdx via the blk_* prefixes, so a single graph is
 // a batch of one.
@@ -53,7 +64,7 @@ struct GDesc {
     int64_t blk_pxb;     // one thread per layer pixel (B * W * H)
     int64_t blk_edget;   // one thread per edge
     int64_t blk_tile;    // tile-histogram blocks (tile_blocks per graph)
-    int64_t blk_cell;    // one thread per bilinear cell of a layer (B * (W+1) * (H+1))
+    int64_t blk_cell;    // one thread per cell record of a layer (B * cell_plane(W, H))
 
     int64_t n_edges;
     int64_t cap;         // capacity of the point buffers, in points
@@ -99,10 +110,10 @@ struct GDesc {
     int64_t *tmp;               // [B][H][W] row-pass output
     float *rho;                 // [B][H][W]
     float2 *grad;               // [B][H][W]
-    // bilinear cells: cell (u0, v0), u0 in [-1, W-1], v0 in [-1, H-1], at (v0+1)(W+1) + u0+1,
-    // holds the taps (u0,v0), (u0+1,v0), (u0,v0+1), (u0+1,v0+1), clamped into the grid
-    Quad *rhoq;                 // [B][H+1][W+1] density taps
-    Quad *gradq;                // [B][H+1][W+1][2] gradient taps: (x, y) of the first two, last two
+    // bilinear cells: cell (u0, v0), u0 in [-1, W-1], v0 in [-1, H-1], holds the taps
+    // (u0,v0), (u0+1,v0), (u0,v0+1), (u0+1,v0+1), clamped into the grid (tiled, see Quad)
+    Quad *rhoq;                 // [B][cell_plane] density taps
+    Quad *gradq;                // [B][cell_plane][2] gradient taps: (x, y) of the first two, last two
     int8_t *jacc;               // [cap] accepted halving per sample (record != 0)
     int32_t *status;
 

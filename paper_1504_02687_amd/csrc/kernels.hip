@@ -582,42 +582,60 @@ __global__ __launch_bounds__(kBlock) void k_density_grad(const GDesc *__restrict
     }
 }
 
-// Bilinear cells of the density and gradient maps (one thread per cell of a layer): the
-// four clamped taps of every sample whose first tap is (u0, v0), so that the advection reads
-// a density sample with one 16-byte load and a gradient sample with two.
+// Bilinear cells of the density and gradient maps in their tiled layout (one thread per
+// record slot of a layer: the density record and the gradient record stored at that slot,
+// which belong to different cells of the same tile): the four clamped taps of every sample
+// whose first tap is (u0, v0), so that the advection reads a density sample with one
+// 16-byte load and a gradient sample with two.
 __global__ __launch_bounds__(kBlock) void k_cells(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_cell);
     if (stopped(d)) return;
-    const int W = d.W, H = d.H, qw = W + 1;
-    const int64_t nq = (int64_t)qw * (H + 1), plane = (int64_t)W * H;
+    const int W = d.W, H = d.H, ntx = cell_tiles_x(W);
+    const int64_t nq = cell_plane(W, H), plane = (int64_t)W * H;
     const int64_t i = (blk - d.blk_cell) * kBlock + threadIdx.x;
     if (i >= (int64_t)d.B * nq) return;
-    const int64_t l = i / nq, c = i - l * nq;
-    const int v0 = (int)(c / qw) - 1, u0 = (int)(c - (c / qw) * qw) - 1;
-    const int ua = min(max(u0, 0), W - 1), ub = min(max(u0 + 1, 0), W - 1);
-    const int va = min(max(v0, 0), H - 1), vb = min(max(v0 + 1, 0), H - 1);
+    const int64_t l = i / nq, r = i - l * nq;
+    const int tile = (int)(r >> 3), p = (int)(r & 7);
+    const int tyi = tile / ntx, txi = tile - tyi * ntx;
     const float *rho = d.rho + l * plane;
     const float2 *grad = d.grad + l * plane;
-    const int64_t a = (int64_t)va * W, b = (int64_t)vb * W;
-    Quad r;
-    r.a = rho[a + ua];
-    r.b = rho[a + ub];
-    r.c = rho[b + ua];
-    r.d = rho[b + ub];
-    d.rhoq[i] = r;
-    const float2 g00 = grad[a + ua], g10 = grad[a + ub], g01 = grad[b + ua], g11 = grad[b + ub];
-    Quad q0, q1;
-    q0.a = g00.x;
-    q0.b = g00.y;
-    q0.c = g10.x;
-    q0.d = g10.y;
-    q1.a = g01.x;
-    q1.b = g01.y;
-    q1.c = g11.x;
-    q1.d = g11.y;
-    d.gradq[2 * i] = q0;
-    d.gradq[2 * i + 1] = q1;
+    {
+        // density record: cell (4 txi + p % 4, 2 tyi + p / 4)
+        const int u0 = 4 * txi + (p & 3) - 1, v0 = 2 * tyi + (p >> 2) - 1;
+        if (u0 < W && v0 < H) {
+            const int ua = min(max(u0, 0), W - 1), ub = min(max(u0 + 1, 0), W - 1);
+            const int va = min(max(v0, 0), H - 1), vb = min(max(v0 + 1, 0), H - 1);
+            const int64_t a = (int64_t)va * W, b = (int64_t)vb * W;
+            Quad q;
+            q.a = rho[a + ua];
+            q.b = rho[a + ub];
+            q.c = rho[b + ua];
+            q.d = rho[b + ub];
+            d.rhoq[i] = q;
+        }
+    }
+    {
+        // gradient record: cell (4 txi + 2 ((p / 4) % 2) + p % 2, 2 tyi + (p / 2) % 2)
+        const int u0 = 4 * txi + 2 * (p >> 2) + (p & 1) - 1, v0 = 2 * tyi + ((p >> 1) & 1) - 1;
+        if (u0 < W && v0 < H) {
+            const int ua = min(max(u0, 0), W - 1), ub = min(max(u0 + 1, 0), W - 1);
+            const int va = min(max(v0, 0), H - 1), vb = min(max(v0 + 1, 0), H - 1);
+            const int64_t a = (int64_t)va * W, b = (int64_t)vb * W;
+            const float2 g00 = grad[a + ua], g10 = grad[a + ub], g01 = grad[b + ua], g11 = grad[b + ub];
+            Quad q0, q1;
+            q0.a = g00.x;
+            q0.b = g00.y;
+            q0.c = g10.x;
+            q0.d = g10.y;
+            q1.a = g01.x;
+            q1.b = g01.y;
+            q1.c = g11.x;
+            q1.d = g11.y;
+            d.gradq[2 * i] = q0;
+            d.gradq[2 * i + 1] = q1;
+        }
+    }
 }
 
 // ---------------------------------------------------------------- advection + smoothing
@@ -644,7 +662,7 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
     const int64_t plane = (int64_t)W * H;
     const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
     (void)plane;
-    const int64_t cells = (int64_t)d.group[e] * (W + 1) * (H + 1);
+    const int64_t cells = (int64_t)d.group[e] * cell_plane(W, H);
     const HB_G Quad *__restrict__ rho = glb(d.rhoq + cells);
     const HB_G Quad *__restrict__ grad = glb(d.gradq + 2 * cells);
     const HB_G float2 *__restrict__ xs = glb(d.samples + o0);
@@ -656,7 +674,7 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
     const double xmax = (double)W - 1.0 / 256.0, ymax = (double)H - 1.0 / 256.0;
     const float xmaxf = (float)xmax, ymaxf = (float)ymax;
 
-    double L = 0.0;
+    double Lp = 0.0;
     float2 yprev = make_float2(0.0f, 0.0f);
     for (int64_t j0 = 0; j0 < n; j0 += 62 * U) {
         float2 x[U];
@@ -675,43 +693,61 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
             act[u] = inr && j > 0 && j < n - 1;
             jj[u] = act[u] ? -1 : -2;
         }
+        // every sub-chunk's cells first, then all their loads, then the arithmetic, so the
+        // U gather chains are in flight together (inactive lanes read a valid cell)
+        Cell t0[U];
+        Quad g0[U], g1[U], rq[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) t0[u] = cell_of(x[u].x, x[u].y, W, H);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            dx[u] = dy[u] = 0.0f;
-            r0[u] = 0.0f;
-            if (act[u]) {
-                // the interpolated gradient in FP64 keeps its direction where the taps
-                // nearly cancel; its normalisation only needs FP32
-                const Cell t0 = cell_of(x[u].x, x[u].y, W, H);
-                double gx, gy;
-                bilin2q(grad, t0, gx, gy);
-                const float fx = (float)gx, fy = (float)gy;
-                // d = g / max(|g|, eps), through one reciprocal square root (about 1 ulp)
-                const float n2 = fx * fx + fy * fy;
-                const float inv = n2 > eps2 ? __builtin_amdgcn_rsqf(n2) : inv_eps;
-                dx[u] = fx * inv;
-                dy[u] = fy * inv;
-                r0[u] = sample1q(rho, t0);
-            }
+            g0[u] = ldq(grad, 2 * t0[u].g);
+            g1[u] = ldq(grad, 2 * t0[u].g + 1);
+            rq[u] = ldq(rho, t0[u].c);
         }
-        // acceptance tests in FP32; the accepted point is recomputed in FP64
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            // the interpolated gradient in FP64 keeps its direction where the taps nearly
+            // cancel; its normalisation only needs FP32
+            double gx, gy;
+            interp2q(g0[u], g1[u], t0[u], gx, gy);
+            const float fx = (float)gx, fy = (float)gy;
+            // d = g / max(|g|, eps), through one reciprocal square root (about 1 ulp)
+            const float n2 = __builtin_fmaf(fy, fy, fx * fx);
+            const float inv = n2 > eps2 ? __builtin_amdgcn_rsqf(n2) : inv_eps;
+            dx[u] = act[u] ? fx * inv : 0.0f;
+            dy[u] = act[u] ? fy * inv : 0.0f;
+            r0[u] = act[u] ? interp1q(rq[u], t0[u]) : 0.0f;
+        }
+        // acceptance tests in FP32 (the loads of all sub-chunks issued before any test);
+        // the accepted point is recomputed in FP64
         float mf = (float)h;
         for (int k = 0; k <= K; ++k) {
             bool any = false;
 #pragma unroll
             for (int u = 0; u < U; ++u) any |= act[u];
             if (!__any(any)) break;
+            Cell c[U];
+            Quad q[U];
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                if (act[u]) {
-                    const float cx = __builtin_amdgcn_fmed3f(x[u].x + mf * dx[u], 0.0f, xmaxf);
-                    const float cy = __builtin_amdgcn_fmed3f(x[u].y + mf * dy[u], 0.0f, ymaxf);
-                    if (sample1q(rho, cell_of(cx, cy, W, H)) >= r0[u]) {
-                        jj[u] = k;
-                        act[u] = false;
-                    }
+                const float cx = __builtin_amdgcn_fmed3f(__builtin_fmaf(mf, dx[u], x[u].x), 0.0f, xmaxf);
+                const float cy = __builtin_amdgcn_fmed3f(__builtin_fmaf(mf, dy[u], x[u].y), 0.0f, ymaxf);
+                c[u] = cell_of(cx, cy, W, H);
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (act[u]) q[u] = ldq(rho, c[u].c);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (act[u] && interp1q(q[u], c[u]) >= r0[u]) {
+                    jj[u] = k;
+                    act[u] = false;
                 }
             }
+            // no load of this trip is left in flight (a lane that skipped its test skipped
+            // the wait as well): the next trip's loads then go out without waiting
+            vm_wait_all();
             mf *= 0.5f;
         }
 #pragma unroll
@@ -747,12 +783,14 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
             yl.x = lane_prev(y[u].x, 0.0f);
             yl.y = lane_prev(y[u].y, 0.0f);
             if (lane == 1) yl = yprev;
-            const double sl = (out && j >= 1) ? seg_len(yl, y[u]) : 0.0;
-            L += wave_sum(sl);
+            // each lane sums its own segments, in the same order whatever U; one wave sum at
+            // the end of the edge
+            if (out && j >= 1) Lp += seg_len(yl, y[u]);
             yprev.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y[u].x), 62));
             yprev.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y[u].y), 62));
         }
     }
+    const double L = wave_sum(Lp);
     if (lane == 0) {
         d.lens[e] = L;
         d.counts[e] = sample_count(L, d.delta);
@@ -806,7 +844,7 @@ Shape shape_of(int64_t n_edges, int32_t B, int32_t W, int32_t H) {
     s.pxb = ((int64_t)B * plane + kBlock - 1) / kBlock;
     s.edget = (n_edges + 1 + kBlock - 1) / kBlock;
     s.tile = tiles_of(B, W, H).blocks;
-    s.cell = ((int64_t)B * (W + 1) * (H + 1) + kBlock - 1) / kBlock;
+    s.cell = ((int64_t)B * cell_plane(W, H) + kBlock - 1) / kBlock;
     return s;
 }
 

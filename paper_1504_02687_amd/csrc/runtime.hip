@@ -377,7 +377,7 @@ static hb_status ensure_maps(hb_ctx *c) {
     CHKST(dalloc(c, &c->d_tmp, plane, "row-pass scratch"));
     CHKST(dalloc(c, &c->d_rho, plane, "density"));
     CHKST(dalloc(c, &c->d_grad, plane, "gradient"));
-    const size_t cells = (size_t)B * (W + 1) * (H + 1);
+    const size_t cells = (size_t)B * hb::cell_plane(W, H);
     CHKST(dalloc(c, &c->d_rhoq, cells, "density cells"));
     CHKST(dalloc(c, &c->d_gradq, 2 * cells, "gradient cells"));
     c->map_B = B;
