@@ -49,7 +49,8 @@ enum {
     HB_ENOMEM = -2,     /* device allocation failed */
     HB_EDEVICE = -3,    /* HIP error (sticky) */
     HB_ESTATE = -4,     /* call order: e.g. hb_run before graph, groups and parameters */
-    HB_EOVERFLOW = -5,  /* integer range of the histogram or the box sums would be exceeded */
+    HB_EOVERFLOW = -5,  /* integer range of the histogram or the box sums would be exceeded,
+                           or one edge would get 2^31 samples or more */
     HB_EINTERNAL = -6   /* an internal consistency check of the device code failed */
 };
 

@@ -419,7 +419,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
                     jl = nseg - 1;
                     t = 1.0;
                 } else {
-                    const double sk = __dmul_rn((double)k, ds);
+                    const double sk = mul_rn((double)k, ds);
                     // last segment that starts at or before sk (branch-free binary search)
                     int lo = 0;
 #pragma unroll
@@ -429,7 +429,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
                         if (c < nseg && sC[wid][cc] <= sk) lo = c;
                     }
                     jl = lo;
-                    const double traw = __dmul_rn(__dsub_rn(sk, sC[wid][lo]), sR[wid][lo]);
+                    const double traw = mul_rn(sub_rn(sk, sC[wid][lo]), sR[wid][lo]);
                     t = fmin(fmax(traw, 0.0), 1.0);
                     if (traw > 0.0 && traw < 1.0 && sR[wid][lo] > 0.0) {
                         const float2 pa = sP[wid][lo], pz = sP[wid][lo + 1];
@@ -530,7 +530,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
         double ux = 0.0, uy = 0.0;
         if (lane < 63 && i + 1 < m) {
             const double dx = (double)nxx - c.x, dy = (double)nxy - c.y;
-            const double l = sqrt(__fma_rn(dx, dx, __dmul_rn(dy, dy)));
+            const double l = sqrt(__builtin_fma(dx, dx, mul_rn(dy, dy)));
             if (l > 0.0) {
                 ux = dx / l;
                 uy = dy / l;

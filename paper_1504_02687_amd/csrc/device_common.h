@@ -172,11 +172,26 @@ __device__ __forceinline__ int64_t sample_count(double L, double delta) {
     return (int64_t)q + 1;
 }
 
+// FP64 operations rounded on their own: compiled with contraction off, so the compiler
+// cannot fuse them with a neighbouring add or multiply, whatever the surrounding code.
+__device__ __forceinline__ double mul_rn(double a, double b) {
+#pragma clang fp contract(off)
+    return a * b;
+}
+__device__ __forceinline__ double add_rn(double a, double b) {
+#pragma clang fp contract(off)
+    return a + b;
+}
+__device__ __forceinline__ double sub_rn(double a, double b) {
+#pragma clang fp contract(off)
+    return a - b;
+}
+
 // Explicit roundings (no contraction choices left to the compiler), so that every kernel
 // variant computes the same bits.
 __device__ __forceinline__ double seg_len(float2 a, float2 b) {
-    const double dx = (double)b.x - (double)a.x, dy = (double)b.y - (double)a.y;
-    return sqrt(__fma_rn(dx, dx, __dmul_rn(dy, dy)));
+    const double dx = sub_rn((double)b.x, (double)a.x), dy = sub_rn((double)b.y, (double)a.y);
+    return sqrt(__builtin_fma(dx, dx, mul_rn(dy, dy)));
 }
 
 // ---------------------------------------------------------------- spatial binning

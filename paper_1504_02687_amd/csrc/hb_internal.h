@@ -33,6 +33,7 @@ constexpr int64_t kSegEntries = 1 << 16;            // entries per tile-histogra
 constexpr int kTileBlocksMax = 2048;                // blocks of one graph in k_tile_hist
 constexpr int kRedSlices = 32;                      // slices per parameter in k_adj_reduce
 constexpr int kInkSlices = 256;                     // slices of the ink sum
+constexpr int64_t kMaxEdgeSamples = int64_t(1) << 31;  // samples of one edge, exclusive bound
 static_assert(HB_MAX_EDGE_WEIGHT < (1u << (32 - kLocalBits)), "weights must fit an entry");
 
 // Four map values of one bilinear cell (16 bytes, one load).

@@ -77,12 +77,19 @@ __global__ __launch_bounds__(kBlock) void k_scan_tiles(const GDesc *__restrict__
     const int64_t tile = blk - d.blk_scan;
     const int64_t base = tile * kScanTile;
     int64_t s = 0;
+    int big = 0;
     for (int i = threadIdx.x; i < kScanTile; i += kBlock) {
         int64_t e = base + i;
-        if (e < d.n_edges) s += d.counts[e];
+        if (e < d.n_edges) {
+            const int64_t c = d.counts[e];
+            s += c;
+            big |= c >= kMaxEdgeSamples;
+        }
     }
     int64_t tot;
     (void)block_excl_scan(s, &tot);
+    // the point kernels index the samples of one edge with 32-bit integers
+    if (__syncthreads_or(big) && threadIdx.x == 0) atomicOr(d.status, (int32_t)ST_HIST_OVERFLOW);
     if (threadIdx.x == 0) d.tsum[tile] = tot;
 }
 
@@ -164,8 +171,9 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
     __shared__ double sR[kWavesPerBlock][64 * U];
     __shared__ float2 sP[kWavesPerBlock][64 * U + 1];
 
-    const int64_t i0 = d.off_in[e], m = d.off_in[e + 1] - i0;
-    const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
+    // per-edge point and sample counts are below 2^31 (checked by the count scan)
+    const int64_t i0 = d.off_in[e], o0 = d.off_s[e];
+    const int m = (int)(d.off_in[e + 1] - i0), n = (int)(d.off_s[e + 1] - o0);
     const double L = d.lens[e];
     const HB_G float2 *p = glb(d.pin + i0);
     HB_G float2 *q = glb(d.samples + o0);
@@ -176,17 +184,17 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
     const double ds = L / nm1;          // arclength between consecutive samples
 
     double Cbase = 0.0;
-    int64_t knext = 0;
-    for (int64_t j0 = 0; j0 < m - 1; j0 += 64 * U) {
-        const int64_t rem = m - 1 - j0;
-        const int nsegT = (int)(rem < 64 * U ? rem : 64 * U);
+    int knext = 0;
+    for (int j0 = 0; j0 < m - 1; j0 += 64 * U) {
+        const int rem = m - 1 - j0;
+        const int nsegT = rem < 64 * U ? rem : 64 * U;
         float2 a[U], b[U];
         double incl[U];
         int ns[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t r = rem - 64 * u;
-            ns[u] = (int)(r <= 0 ? 0 : (r < 64 ? r : 64));
+            const int r = rem - 64 * u;
+            ns[u] = r <= 0 ? 0 : (r < 64 ? r : 64);
             a[u] = make_float2(0.0f, 0.0f);
             if (lane <= ns[u] && ns[u] > 0) a[u] = ld2(p + (j0 + 64 * u + lane));
         }
@@ -205,8 +213,10 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const double excl = lane_prev(incl[u], 0.0);
+            // arclengths past the chunk's last segment read as +inf: the search needs no
+            // bound check
+            sC[wid][64 * u + lane] = lane < ns[u] ? cb + excl : __builtin_huge_val();
             if (lane < ns[u]) {
-                sC[wid][64 * u + lane] = cb + excl;
                 sR[wid][64 * u + lane] = ell[u] > 0.0 ? 1.0 / ell[u] : 0.0;
                 sP[wid][64 * u + lane] = a[u];
             }
@@ -217,20 +227,20 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
         __builtin_amdgcn_wave_barrier();
 
         const bool last = (j0 + 64 * U >= m - 1);
-        int64_t kend;
+        int kend;
         if (last) {
             kend = n;
         } else if (!(L > 0.0)) {
             kend = knext;
         } else {
-            double kf = ceil(Cend / ds);
-            int64_t kk = kf < (double)knext ? knext : (kf > nm1 ? n - 1 : (int64_t)kf);
+            const double kf = ceil(Cend / ds);
+            int kk = kf < (double)knext ? knext : (kf > nm1 ? n - 1 : (int)kf);
             while (kk > knext && (double)(kk - 1) * ds >= Cend) --kk;
             while (kk < n - 1 && (double)kk * ds < Cend) ++kk;
             kend = kk;
         }
-        for (int64_t kb = knext; kb < kend; kb += 64) {
-            const int64_t k = kb + lane;
+        for (int kb = knext; kb < kend; kb += 64) {
+            const int k = kb + lane;
             int key = 0;
             uint32_t loc = 0;
             if (k < kend) {
@@ -240,27 +250,24 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
                 } else if (k == n - 1) {
                     out = ld2(p + (m - 1));
                 } else {
-                    const double s = __dmul_rn((double)k, ds);
-                    // last segment of the chunk that starts at or before s (branch-free
-                    // binary search over the LDS arclengths)
+                    const double s = mul_rn((double)k, ds);
+                    // last segment of the chunk that starts at or before s (binary search
+                    // over the LDS arclengths; lo + step < 64 U always)
                     int lo = 0;
 #pragma unroll
-                    for (int step = 32 * U; step >= 1; step >>= 1) {
-                        const int c = lo + step;
-                        const int cc = c < nsegT ? c : nsegT - 1;
-                        if (c < nsegT && sC[wid][cc] <= s) lo = c;
-                    }
+                    for (int step = 32 * U; step >= 1; step >>= 1)
+                        lo = sC[wid][lo + step] <= s ? lo + step : lo;
                     const float2 pa = sP[wid][lo], pb = sP[wid][lo + 1];
                     const double ex = (double)pb.x - (double)pa.x, ey = (double)pb.y - (double)pa.y;
-                    double t = __dmul_rn(__dsub_rn(s, sC[wid][lo]), sR[wid][lo]);
+                    double t = mul_rn(sub_rn(s, sC[wid][lo]), sR[wid][lo]);
                     t = fmin(fmax(t, 0.0), 1.0);
-                    out.x = (float)__fma_rn(t, ex, (double)pa.x);
-                    out.y = (float)__fma_rn(t, ey, (double)pa.y);
+                    out.x = (float)__builtin_fma(t, ex, (double)pa.x);
+                    out.y = (float)__builtin_fma(t, ey, (double)pa.y);
                 }
                 st2(q + k, out);
                 bin_of(d, layer, out, key, loc);
             }
-            const int cnt = (int)(kend - kb < 64 ? kend - kb : 64);
+            const int cnt = kend - kb < 64 ? kend - kb : 64;
             const uint64_t heads = run_heads(key, lane, cnt);
             if ((heads >> lane) & 1ull)
                 atomicAdd((unsigned long long *)(ctr + key), (unsigned long long)run_length(heads, lane, cnt));
@@ -754,8 +761,8 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
         for (int u = 0; u < U; ++u) {
             if (jj[u] >= 0) {
                 const double m = ldexp(h, -jj[u]);
-                ax[u] = fmin(fmax(__fma_rn(m, (double)dx[u], (double)x[u].x), 0.0), xmax);
-                ay[u] = fmin(fmax(__fma_rn(m, (double)dy[u], (double)x[u].y), 0.0), ymax);
+                ax[u] = fmin(fmax(__builtin_fma(m, (double)dx[u], (double)x[u].x), 0.0), xmax);
+                ay[u] = fmin(fmax(__builtin_fma(m, (double)dy[u], (double)x[u].y), 0.0), ymax);
             }
         }
         float2 y[U];
@@ -767,8 +774,8 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
             const bool out = lane >= 1 && lane <= 62 && j < n;
             y[u] = x[u];
             if (out && j > 0 && j < n - 1) {
-                y[u].x = (float)__fma_rn(0.5 * s, __dadd_rn(lx, rx), __dmul_rn(1.0 - s, ax[u]));
-                y[u].y = (float)__fma_rn(0.5 * s, __dadd_rn(ly, ry), __dmul_rn(1.0 - s, ay[u]));
+                y[u].x = (float)__builtin_fma(0.5 * s, add_rn(lx, rx), mul_rn(1.0 - s, ax[u]));
+                y[u].y = (float)__builtin_fma(0.5 * s, add_rn(ly, ry), mul_rn(1.0 - s, ay[u]));
             }
             if (out) {
                 st2(ys + j, y[u]);

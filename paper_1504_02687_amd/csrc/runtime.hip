@@ -674,6 +674,22 @@ static hb_status upload(hb_ctx *c, T *dst, const std::vector<T> &src) {
 }
 
 // Lay out the descriptor of a setup kernel on the state (pin/off_in) in slot 0.
+static const char *const kOverflowMsg =
+    "sample count too large for int32 histograms or int64 box sums, or 2^31 samples or more "
+    "on one edge";
+
+// Error of a non-zero device status word (cleared on the device).
+static hb_status read_status(hb_ctx *c) {
+    int32_t status = 0;
+    HIPCHK(c, hipMemcpy(&status, c->d_status, sizeof status, hipMemcpyDeviceToHost));
+    if (status == 0) return HB_OK;
+    int32_t zero = 0;
+    HIPCHK(c, hipMemcpy(c->d_status, &zero, sizeof zero, hipMemcpyHostToDevice));
+    if (status & hb::ST_BIN_MISMATCH)
+        return fail(c, HB_EINTERNAL, "binned samples disagree with the tile counts");
+    return fail(c, HB_EOVERFLOW, kOverflowMsg);
+}
+
 static hb_status setup_scan_total(hb_ctx *c, int64_t *total_out) {
     // Scan the counts of the current state into off[1 - os] to learn the next sample count.
     CHKST(ensure_desc(c, 1));
@@ -691,6 +707,7 @@ static hb_status setup_scan_total(hb_ctx *c, int64_t *total_out) {
     const Shape s = hb::shape_of(c->E, d.B, d.W, d.H);
     HIPCHK(c, hb::launch_scan(c->d_desc, 1, s, c->stream));
     CHKST(read_scalar(c, c->d_totals, total_out));
+    CHKST(read_status(c));   // an edge with 2^31 samples or more
     return HB_OK;
 }
 
@@ -1120,8 +1137,7 @@ static hb_status finish_pending(hb_ctx *c) {
         if (status & hb::ST_BIN_MISMATCH)
             return fail(c, HB_EINTERNAL, "binned samples disagree with the tile counts");
         if (status & hb::ST_HIST_OVERFLOW)
-            return fail(c, HB_EOVERFLOW,
-                        "sample count too large for int32 histograms or int64 box sums");
+            return fail(c, HB_EOVERFLOW, kOverflowMsg);
         CHKST(ensure_capacity(c, 2 * need + 64));
         uint32_t flags = c->pend_flags & ~(uint32_t)(HB_RUN_ASYNC | HB_RUN_GRAPH);
         if (f > 0) flags &= ~(uint32_t)HB_RUN_SAMPLES_GIVEN;
@@ -1524,17 +1540,6 @@ static GDesc ckpt_desc(hb_ctx *c, const float2 *pin, const int64_t *off_in, floa
     d.cap = cap;
     d.total = c->d_totals;
     return d;
-}
-
-static hb_status read_status(hb_ctx *c) {
-    int32_t status = 0;
-    HIPCHK(c, hipMemcpy(&status, c->d_status, sizeof status, hipMemcpyDeviceToHost));
-    if (status == 0) return HB_OK;
-    int32_t zero = 0;
-    HIPCHK(c, hipMemcpy(c->d_status, &zero, sizeof zero, hipMemcpyHostToDevice));
-    if (status & hb::ST_BIN_MISMATCH)
-        return fail(c, HB_EINTERNAL, "binned samples disagree with the tile counts");
-    return fail(c, HB_EOVERFLOW, "sample count too large for int32 histograms or int64 box sums");
 }
 
 // The iterations write straight into the checkpoints: iteration t reads the polylines of

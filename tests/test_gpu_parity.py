@@ -185,6 +185,23 @@ def test_edge_weight_limits(hb):
         b.set_graph(nodes, src, dst, np.array([1, hb.HB_MAX_EDGE_WEIGHT], np.int32))
 
 
+def test_edge_sample_limit(hb):
+    """An edge that would get 2^31 samples or more is refused with HB_EOVERFLOW before any
+    point work (the point kernels index the samples of one edge with 32-bit integers)."""
+    nodes = np.array([[0.05, 0.5], [0.95, 0.5]], np.float32)
+    with hb.Bundler(0) as b:
+        b.set_params(1024, 1024, [2], delta=4e-7)   # 921.6 px / 4e-7 px > 2^31 samples
+        with pytest.raises(hb.HBError) as ei:
+            b.set_graph(nodes, np.array([0], np.int32), np.array([1], np.int32))
+        assert ei.value.status == hb.HB_EOVERFLOW
+        # the context stays usable: the same edge at a sane spacing runs
+        b.set_params(1024, 1024, [2], delta=1.0)
+        b.set_graph(nodes, np.array([0], np.int32), np.array([1], np.int32))
+        b.set_groups(np.zeros(1, np.int32), np.ones((1, 1), np.float32))
+        b.run(1)
+        assert 900 < b.points()[0][-1] < 950   # about 922 samples of the 921.6 px edge
+
+
 @pytest.mark.parametrize("E,W,H,delta,seed", [(800, 128, 96, 1.0, 5), (300, 512, 512, 4.0, 6)])
 def test_resample_parity(hb, E, W, H, delta, seed):
     rng = np.random.default_rng(seed)
