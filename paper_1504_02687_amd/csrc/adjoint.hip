@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
             // vectors of the adjacent segments (the gradient of the ink)
             const float2 *pp = d.ink_pts + o0;
             const float2 c = inr ? pp[j] : make_float2(0.0f, 0.0f);
-            float nxx = lane_next(c.x, 0.0f), nxy = lane_next(c.y, 0.0f);
+            float nxx = lane_next(c.x), nxy = lane_next(c.y);
             if (lane == 63 && j + 1 < n) {
                 nxx = pp[j + 1].x;
                 nxy = pp[j + 1].y;
@@ -145,7 +145,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
                     uy = dy / l;
                 }
             }
-            double pux = lane_prev(ux, 0.0), puy = lane_prev(uy, 0.0);
+            double pux = lane_prev(ux), puy = lane_prev(uy);
             if (lane == 0) {
                 pux = puy = 0.0;
                 if (inr && j >= 1) {
@@ -163,8 +163,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
             ybar = yb[j];
         }
         const double qx = interior ? (double)ybar.x : 0.0, qy = interior ? (double)ybar.y : 0.0;
-        const double qlx = lane_prev(qx, 0.0), qly = lane_prev(qy, 0.0);
-        const double qrx = lane_next(qx, 0.0), qry = lane_next(qy, 0.0);
+        const double qlx = lane_prev(qx), qly = lane_prev(qy);
+        const double qrx = lane_next(qx), qry = lane_next(qy);
         if (!(lane >= 1 && lane <= 62 && j < n)) continue;
         const double cf = interior ? 1.0 - s : 1.0;
         double wx = cf * (double)ybar.x + 0.5 * s * (qlx + qrx);
@@ -375,12 +375,12 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
         float2 a = make_float2(0.0f, 0.0f);
         if (lane <= nseg && lane < 64) a = p[j0 + lane];
         float2 b;
-        b.x = lane_next(a.x, 0.0f);
-        b.y = lane_next(a.y, 0.0f);
+        b.x = lane_next(a.x);
+        b.y = lane_next(a.y);
         if (lane == 63 && nseg == 64) b = p[j0 + 64];
         const double ell = lane < nseg ? seg_len(a, b) : 0.0;
         const double incl = wave_incl_scan<double>(ell, lane);
-        const double excl = lane_prev(incl, 0.0);
+        const double excl = lane_prev(incl);
         if (lane < nseg) {
             sC[wid][lane] = Cbase + excl;
             sR[wid][lane] = ell > 0.0 ? 1.0 / ell : 0.0;
@@ -457,7 +457,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
                 // every lane is a head or directly follows one: runs of length <= 2
 #pragma unroll
                 for (int c = 0; c < 6; ++c) {
-                    const double pv = lane_prev(v[c], 0.0);
+                    const double pv = lane_prev(v[c]);
                     if (jprev == jl) v[c] += pv;
                 }
             } else {
@@ -492,8 +492,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
         const double Pin = carryP + wave_incl_scan<double>(Cb, lane);
         const double Vx = lane < nseg ? (lb - Pin) * ux : 0.0;
         const double Vy = lane < nseg ? (lb - Pin) * uy : 0.0;
-        double Bpx = lane_prev(Bx, 0.0), Bpy = lane_prev(By, 0.0);
-        double Vpx = lane_prev(Vx, 0.0), Vpy = lane_prev(Vy, 0.0);
+        double Bpx = lane_prev(Bx), Bpy = lane_prev(By);
+        double Vpx = lane_prev(Vx), Vpy = lane_prev(Vy);
         if (lane == 0) {
             Bpx = carryBx;
             Bpy = carryBy;
@@ -522,7 +522,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
     for (int64_t i0 = 0; i0 < m; i0 += 63) {
         const int64_t i = i0 + lane;
         const float2 c = i < m ? p[i] : make_float2(0.0f, 0.0f);
-        float nxx = lane_next(c.x, 0.0f), nxy = lane_next(c.y, 0.0f);
+        float nxx = lane_next(c.x), nxy = lane_next(c.y);
         if (lane == 63 && i + 1 < m) {
             nxx = p[i + 1].x;
             nxy = p[i + 1].y;
@@ -536,7 +536,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
                 uy = dy / l;
             }
         }
-        double pux = lane_prev(ux, 0.0), puy = lane_prev(uy, 0.0);
+        double pux = lane_prev(ux), puy = lane_prev(uy);
         if (lane == 0) {
             pux = cux;
             puy = cuy;

@@ -78,8 +78,28 @@ __device__ __forceinline__ double dpp(double old, double v) {
                                                 (int64_t)__double_as_longlong(v)));
 }
 
-// Value of lane l - 1 (lane 0 gets fill) and of lane l + 1 (lane 63 gets fill). Every lane
-// of the wave must be active.
+// v of the lane selected by CTRL in every row; lanes without a source read 0 (the hardware
+// bound control: no copy of an old value is needed).
+template <int CTRL>
+__device__ __forceinline__ int dpp0(int v) {
+    return __builtin_amdgcn_mov_dpp(v, CTRL, 0xf, 0xf, true);
+}
+template <int CTRL>
+__device__ __forceinline__ float dpp0(float v) {
+    return __int_as_float(dpp0<CTRL>(__float_as_int(v)));
+}
+template <int CTRL>
+__device__ __forceinline__ int64_t dpp0(int64_t v) {
+    const int lo = dpp0<CTRL>((int)(uint32_t)v), hi = dpp0<CTRL>((int)(v >> 32));
+    return (int64_t)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+template <int CTRL>
+__device__ __forceinline__ double dpp0(double v) {
+    return __longlong_as_double(dpp0<CTRL>((int64_t)__double_as_longlong(v)));
+}
+
+// Value of lane l - 1 (lane 0 gets fill, or 0) and of lane l + 1 (lane 63 gets fill, or 0).
+// Every lane of the wave must be active.
 template <typename T>
 __device__ __forceinline__ T lane_prev(T v, T fill) {
     return dpp<kDppWaveShr1>(fill, v);
@@ -87,6 +107,14 @@ __device__ __forceinline__ T lane_prev(T v, T fill) {
 template <typename T>
 __device__ __forceinline__ T lane_next(T v, T fill) {
     return dpp<kDppWaveShl1>(fill, v);
+}
+template <typename T>
+__device__ __forceinline__ T lane_prev(T v) {
+    return dpp0<kDppWaveShr1>(v);
+}
+template <typename T>
+__device__ __forceinline__ T lane_next(T v) {
+    return dpp0<kDppWaveShl1>(v);
 }
 
 // Value of lane 63, in every lane.
@@ -116,10 +144,10 @@ __device__ __forceinline__ double read_lane(double v, int l) {
 template <typename T>
 __device__ __forceinline__ T wave_incl_scan(T v, int lane) {
     (void)lane;
-    v += dpp<kDppRowShr + 1>((T)0, v);
-    v += dpp<kDppRowShr + 2>((T)0, v);
-    v += dpp<kDppRowShr + 4>((T)0, v);
-    v += dpp<kDppRowShr + 8>((T)0, v);
+    v += dpp0<kDppRowShr + 1>(v);
+    v += dpp0<kDppRowShr + 2>(v);
+    v += dpp0<kDppRowShr + 4>(v);
+    v += dpp0<kDppRowShr + 8>(v);
     v += dpp<kDppRowBcast15, 0xa>((T)0, v);
     v += dpp<kDppRowBcast31, 0xc>((T)0, v);
     return v;

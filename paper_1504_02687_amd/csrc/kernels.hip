@@ -200,8 +200,8 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            b[u].x = lane_next(a[u].x, 0.0f);
-            b[u].y = lane_next(a[u].y, 0.0f);
+            b[u].x = lane_next(a[u].x);
+            b[u].y = lane_next(a[u].y);
             if (lane == 63 && ns[u] == 64) b[u] = ld2(p + (j0 + 64 * u + 64));
         }
         double ell[U];
@@ -212,7 +212,7 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
         double cb = Cbase;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const double excl = lane_prev(incl[u], 0.0);
+            const double excl = lane_prev(incl[u]);
             // arclengths past the chunk's last segment read as +inf: the search needs no
             // bound check
             sC[wid][64 * u + lane] = lane < ns[u] ? cb + excl : __builtin_huge_val();
@@ -769,8 +769,8 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t j = j0 + 62 * u - 1 + lane;
-            const double lx = lane_prev(ax[u], 0.0), ly = lane_prev(ay[u], 0.0);
-            const double rx = lane_next(ax[u], 0.0), ry = lane_next(ay[u], 0.0);
+            const double lx = lane_prev(ax[u]), ly = lane_prev(ay[u]);
+            const double rx = lane_next(ax[u]), ry = lane_next(ay[u]);
             const bool out = lane >= 1 && lane <= 62 && j < n;
             y[u] = x[u];
             if (out && j > 0 && j < n - 1) {
@@ -787,8 +787,8 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
             const int64_t j = j0 + 62 * u - 1 + lane;
             const bool out = lane >= 1 && lane <= 62 && j < n;
             float2 yl;
-            yl.x = lane_prev(y[u].x, 0.0f);
-            yl.y = lane_prev(y[u].y, 0.0f);
+            yl.x = lane_prev(y[u].x);
+            yl.y = lane_prev(y[u].y);
             if (lane == 1) yl = yprev;
             // each lane sums its own segments, in the same order whatever U; one wave sum at
             // the end of the edge
