@@ -170,6 +170,10 @@ def main():
                     help="iterations of the forward+backward / plain ratio (0: skip)")
     ap.add_argument("--batched", action="store_true",
                     help="measure the batched form instead (prints its own JSON line)")
+    ap.add_argument("--convergence", type=int, default=0, metavar="T",
+                    help="instead of the throughput run: T iterations with the step-halving "
+                         "advection and T with the original fixed step, per-iteration ink and "
+                         "histogram concentration of both (one JSON line)")
     ap.add_argument("--batch-graphs", type=int, default=64)
     ap.add_argument("--batch-emax", type=float, default=1e5)
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -190,6 +194,9 @@ def main():
     if args.batched:
         batched_main(args)
         return
+    if args.convergence > 0:
+        convergence_main(args)
+        return
 
     import numpy as np
     import torch
@@ -209,6 +216,8 @@ def main():
         torch.cuda.synchronize()
         log("calibration copy: 3 x 1 GiB read + 1 GiB write")
         del src, dst
+    copy_gbs = measure_copy_gbs()
+    log(f"device copy: {copy_gbs:.0f} GB/s (read + write of 1 GiB, best of 5)")
     log(f"generating workload ({args.edges} edges, {args.grid}^2 x {args.groups})")
     t = time.time()
     w = workloads.stack3d(n_edges=args.edges, grid=args.grid, groups=args.groups)
@@ -252,7 +261,8 @@ def main():
     roofline = {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": tr, "algorithmic_bytes_per_launch": int(bytes_dom / max(1, n_dom)),
-                "avg_launch_ms": round(ms_dom / max(1, n_dom), 4)}
+                "avg_launch_ms": round(ms_dom / max(1, n_dom), 4),
+                "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(achieved / copy_gbs, 4)}
     per_stage_gbs = {}
     for k, (ms, n) in stages.items():
         if ms > 0:
@@ -295,6 +305,76 @@ def main():
         "fwd_bwd": fwd_bwd,
     }
     print(json.dumps(out), flush=True)
+
+
+def convergence_main(args):
+    """The step-halving advection against the original fixed step (every point moved by h,
+    no density test) on the same workload and schedule: after each iteration the ink (total
+    polyline length) and, from the histogram of that iteration's samples, the fraction of
+    occupied pixels and the mean count of the pixel a sample falls in (sum H^2 / sum H). A
+    bundling that converges concentrates the samples: fewer occupied pixels, higher counts."""
+    import numpy as np
+    import torch
+
+    import paper_1504_02687_amd as hb
+    import workloads
+
+    torch.cuda.set_device(0)
+    w = workloads.stack3d(n_edges=args.edges, grid=args.grid, groups=args.groups)
+    log(f"convergence: {w.describe()}, {args.convergence} iterations per mode")
+    res = {}
+    for name, K in (("halving", 8), ("fixed_step", -1)):
+        b = hb.Bundler(0)
+        b.set_workload(w, capacity_factor=args.capacity, max_halvings=K)
+        ink, occ, conc, ms, pts = [], [], [], [], []
+        stopped = None
+        for i in range(args.convergence):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            try:
+                b.run(1)
+            except hb.HBError as e:
+                # the sample count outgrew the integer histogram (edges that keep lengthening)
+                stopped = {"iteration": i, "error": str(e)}
+                log(f"  {name}: stopped at iteration {i}: {e}")
+                break
+            torch.cuda.synchronize()
+            ms.append((time.perf_counter() - t0) * 1e3)
+            pts.append(int(b.iter_counts(1)[0]))
+            H = np.stack([b.map(hb.HB_MAP_HIST, g) for g in range(w.n_groups)]).astype(np.float64)
+            occ.append(float((H > 0).mean()))
+            conc.append(float((H * H).sum() / max(1.0, H.sum())))
+            ink.append(b.ink())
+        b.close()
+        res[name] = {"ink": ink, "occupied_frac": occ, "samples_per_pixel": conc, "points": pts,
+                     "iteration_ms": [round(v, 2) for v in ms], "stopped": stopped}
+        if ink:
+            log(f"  {name}: ink {ink[0]:.4g} -> {ink[-1]:.4g}, occupied {occ[0]:.4f} -> "
+                f"{occ[-1]:.4f}, sum H^2 / sum H {conc[0]:.1f} -> {conc[-1]:.1f}")
+    print(json.dumps({"metric": "convergence: step halving vs original fixed step",
+                      "config": {"workload": w.name, "edges": w.n_edges, "groups": w.n_groups,
+                                 "grid": [w.grid_w, w.grid_h], "iterations": args.convergence},
+                      "data": "synthetic", **res}), flush=True)
+
+
+def measure_copy_gbs():
+    """Measured device bandwidth: a plain 1 GiB device-to-device copy (1 GiB read + 1 GiB
+    written), best of 5, timed with events on the current stream."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    best = float("inf")
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        e1.synchronize()
+        best = min(best, e0.elapsed_time(e1) * 1e-3)
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2.0 * (1 << 30) / best / 1e9
 
 
 def grad_ratio(hb, w, T, capacity):

@@ -105,7 +105,10 @@ typedef struct hb_params {
                                    sigma(r)^2 = P r (r+1) / 3 (Section 3.3, Fig. 2) */
     float lambda;               /* bandwidth decay h_i = lambda^i h_max (Section 2.1: 0.5..0.9) */
     float eps;                  /* epsilon of Eq. 5 (density units per pixel) */
-    int32_t max_halvings;       /* K: step halvings tried before a point stays (Section 3.3) */
+    int32_t max_halvings;       /* K: step halvings tried before a point stays (Section 3.3),
+                                   in [0, HB_MAX_HALVINGS]; -1: the original fixed step of
+                                   Section 2 (every interior point moves by h, no density
+                                   test), the baseline Section 3.3 compares against */
     float smooth_weight;        /* Laplacian weight s in y = (1-s) x + s (x- + x+)/2 */
     int32_t smooth_passes;      /* Jacobi passes of the Laplacian smoothing (1) */
     const float *pass_weights;  /* a[P]: density = sum_k a_k * pass_k / (2r+1)^(2k);

@@ -398,6 +398,10 @@ EXPORT double orc_bilinear(int32_t W, int32_t H, const double *map, int32_t stri
  * Pins: every accepted move satisfies rho(x') >= rho(x); zero gradient gives no move; a
  * point near an isolated smoothed impulse moves radially in closed form; a straight edge
  * on a pixel-centre row of a symmetric map never leaves the row.
+ *
+ * K < 0 selects the original advection step that Section 2 describes for KDEEB and Section
+ * 3.3 compares against: every interior point moves by m = h along d with no density test
+ * (then clamped); jacc = jfirm = 0 and no try is ambiguous.
  */
 EXPORT void orc_advect(int64_t E, const int64_t *off, const double *xy, const int32_t *group,
                        int32_t B, int32_t W, int32_t H, const double *rho, const double *grad,
@@ -429,6 +433,18 @@ EXPORT void orc_advect(int64_t E, const int64_t *off, const double *xy, const in
             double dx = gx / den, dy = gy / den;
             dir[2 * i] = dx;
             dir[2 * i + 1] = dy;
+            if (K < 0) {
+                double cx = x + h * dx, cy = y + h * dy;
+                if (cx < 0.0) cx = 0.0;
+                if (cx > xmax) cx = xmax;
+                if (cy < 0.0) cy = 0.0;
+                if (cy > ymax) cy = ymax;
+                xy_out[2 * i] = cx;
+                xy_out[2 * i + 1] = cy;
+                jacc[i] = 0;
+                jfirm[i] = 0;
+                continue;
+            }
             double r0 = orc_bilinear(W, H, rl, 1, 0, x, y);
             int32_t acc = -1, firm = -1;
             uint32_t mask = 0;

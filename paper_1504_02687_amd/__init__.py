@@ -120,11 +120,6 @@ def load():
     return _lib
 
 
-def build(verbose: bool = False) -> str:
-    from . import build as _b
-    return _b.build(verbose)
-
-
 def exported_symbols() -> Sequence[str]:
     return list(_SIGS)
 

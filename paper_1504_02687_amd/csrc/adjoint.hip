@@ -357,32 +357,34 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
     __shared__ float2 sP[kWavesPerBlock][65];
     __shared__ double acc[kWavesPerBlock][6][64];
 
-    const int64_t i0 = d.off_in[e], m = d.off_in[e + 1] - i0;
-    const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
+    // per-edge point and sample counts are below 2^31 (checked by the count scan)
+    const int64_t i0 = d.off_in[e], o0 = d.off_s[e];
+    const int m = (int)(d.off_in[e + 1] - i0), n = (int)(d.off_s[e + 1] - o0);
     const double L = d.lens[e];
-    const float2 *p = d.pin + i0;
-    const float2 *xb = d.adj_in + o0;
-    float2 *pb = d.adj_out + i0;
+    const HB_G float2 *p = glb(d.pin + i0);
+    const HB_G float2 *xb = glb(d.adj_in + o0);
+    HB_G float2 *pb = glb(d.adj_out + i0);
     const double nm1 = (double)(n - 1);
     const double ds = L / nm1;
 
     double Cbase = 0.0, Lbar = 0.0, carryP = 0.0;
     double carryBx = 0.0, carryBy = 0.0, carryVx = 0.0, carryVy = 0.0;
-    int64_t knext = 0;
-    for (int64_t j0 = 0; j0 < m - 1; j0 += 64) {
-        const int64_t rem = m - 1 - j0;
-        const int nseg = (int)(rem < 64 ? rem : 64);
+    int knext = 0;
+    for (int j0 = 0; j0 < m - 1; j0 += 64) {
+        const int rem = m - 1 - j0;
+        const int nseg = rem < 64 ? rem : 64;
         float2 a = make_float2(0.0f, 0.0f);
-        if (lane <= nseg && lane < 64) a = p[j0 + lane];
+        if (lane <= nseg && lane < 64) a = ld2(p + (j0 + lane));
         float2 b;
         b.x = lane_next(a.x);
         b.y = lane_next(a.y);
-        if (lane == 63 && nseg == 64) b = p[j0 + 64];
+        if (lane == 63 && nseg == 64) b = ld2(p + (j0 + 64));
         const double ell = lane < nseg ? seg_len(a, b) : 0.0;
         const double incl = wave_incl_scan<double>(ell, lane);
         const double excl = lane_prev(incl);
+        // arclengths past the chunk's last segment read as +inf (no bound check in the search)
+        sC[wid][lane] = lane < nseg ? Cbase + excl : __builtin_huge_val();
         if (lane < nseg) {
-            sC[wid][lane] = Cbase + excl;
             sR[wid][lane] = ell > 0.0 ? 1.0 / ell : 0.0;
             sP[wid][lane] = a;
             for (int c = 0; c < 6; ++c) acc[wid][c][lane] = 0.0;
@@ -392,26 +394,26 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
         __builtin_amdgcn_wave_barrier();
 
         const bool last = (j0 + 64 >= m - 1);
-        int64_t kend;
+        int kend;
         if (last) {
             kend = n;
         } else if (!(L > 0.0)) {
             kend = knext;
         } else {
-            double kf = ceil(Cend / ds);
-            int64_t kk = kf < (double)knext ? knext : (kf > nm1 ? n - 1 : (int64_t)kf);
+            const double kf = ceil(Cend / ds);
+            int kk = kf < (double)knext ? knext : (kf > nm1 ? n - 1 : (int)kf);
             while (kk > knext && (double)(kk - 1) * ds >= Cend) --kk;
             while (kk < n - 1 && (double)kk * ds < Cend) ++kk;
             kend = kk;
         }
         if (j0 == 0 && kend < 1) kend = 1;   // the first end point belongs to point 0
-        for (int64_t kb = knext; kb < kend; kb += 64) {
-            const int64_t k = kb + lane;
+        for (int kb = knext; kb < kend; kb += 64) {
+            const int k = kb + lane;
             const bool valid = k < kend;
             int jl = 64 + lane;   // distinct keys for idle lanes
             double v[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             if (valid) {
-                const float2 xv = xb[k];
+                const float2 xv = ld2(xb + k);
                 double t = 0.0, tb = 0.0;
                 if (k == 0) {
                     jl = 0;
@@ -420,14 +422,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
                     t = 1.0;
                 } else {
                     const double sk = mul_rn((double)k, ds);
-                    // last segment that starts at or before sk (branch-free binary search)
+                    // last segment that starts at or before sk (binary search; lo + step < 64)
                     int lo = 0;
 #pragma unroll
-                    for (int step = 32; step >= 1; step >>= 1) {
-                        const int c = lo + step;
-                        const int cc = c < nseg ? c : nseg - 1;
-                        if (c < nseg && sC[wid][cc] <= sk) lo = c;
-                    }
+                    for (int step = 32; step >= 1; step >>= 1)
+                        lo = sC[wid][lo + step] <= sk ? lo + step : lo;
                     jl = lo;
                     const double traw = mul_rn(sub_rn(sk, sC[wid][lo]), sR[wid][lo]);
                     t = fmin(fmax(traw, 0.0), 1.0);
@@ -501,14 +500,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
             Vpy = carryVy;
         }
         if (lane < nseg || (last && lane == nseg))
-            pb[j0 + lane] = make_float2((float)(Ax + Bpx - Vx + Vpx), (float)(Ay + Bpy - Vy + Vpy));
+            st2(pb + (j0 + lane), make_float2((float)(Ax + Bpx - Vx + Vpx), (float)(Ay + Bpy - Vy + Vpy)));
         carryBx = read_lane(Bx, nseg - 1);
         carryBy = read_lane(By, nseg - 1);
         carryVx = read_lane(Vx, nseg - 1);
         carryVy = read_lane(Vy, nseg - 1);
         carryP = read_lane(Pin, nseg - 1);
         if (last && nseg == 64 && lane == 0)
-            pb[j0 + 64] = make_float2((float)(carryBx + carryVx), (float)(carryBy + carryVy));
+            st2(pb + (j0 + 64), make_float2((float)(carryBx + carryVx), (float)(carryBy + carryVy)));
         __builtin_amdgcn_wave_barrier();
         knext = kend;
         Cbase = Cend;
@@ -519,13 +518,14 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
     // G (u_(i-1) - u_i) with u the unit vectors of the segments: one segment per lane, 63
     // points per trip, u_(i-1) from lane l-1 (lane 0: from the previous trip)
     double cux = 0.0, cuy = 0.0;
-    for (int64_t i0 = 0; i0 < m; i0 += 63) {
-        const int64_t i = i0 + lane;
-        const float2 c = i < m ? p[i] : make_float2(0.0f, 0.0f);
+    for (int q0 = 0; q0 < m; q0 += 63) {
+        const int i = q0 + lane;
+        const float2 c = i < m ? ld2(p + i) : make_float2(0.0f, 0.0f);
         float nxx = lane_next(c.x), nxy = lane_next(c.y);
         if (lane == 63 && i + 1 < m) {
-            nxx = p[i + 1].x;
-            nxy = p[i + 1].y;
+            const float2 nx = ld2(p + (i + 1));
+            nxx = nx.x;
+            nxy = nx.y;
         }
         double ux = 0.0, uy = 0.0;
         if (lane < 63 && i + 1 < m) {
@@ -542,8 +542,8 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
             puy = cuy;
         }
         if (lane < 63 && i < m) {
-            const float2 cur = pb[i];
-            pb[i] = make_float2((float)((double)cur.x + G * (pux - ux)), (float)((double)cur.y + G * (puy - uy)));
+            const float2 cur = ld2(pb + i);
+            st2(pb + i, make_float2((float)((double)cur.x + G * (pux - ux)), (float)((double)cur.y + G * (puy - uy))));
         }
         cux = read_lane(ux, 62);
         cuy = read_lane(uy, 62);

@@ -726,6 +726,14 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
             dy[u] = act[u] ? fy * inv : 0.0f;
             r0[u] = act[u] ? interp1q(rq[u], t0[u]) : 0.0f;
         }
+        // K < 0: the original fixed step (every interior point moves by h, no test)
+        if (K < 0) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (act[u]) jj[u] = 0;
+                act[u] = false;
+            }
+        }
         // acceptance tests in FP32 (the loads of all sub-chunks issued before any test);
         // the accepted point is recomputed in FP64
         float mf = (float)h;

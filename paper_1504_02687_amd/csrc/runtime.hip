@@ -116,12 +116,13 @@ struct hb_ctx {
 
     // adjoint work buffers, kept between backward passes
     struct AdjBufs {
-        float2 *a0 = nullptr, *a1 = nullptr, *gb = nullptr;
+        float2 *a0 = nullptr, *a1 = nullptr;
+        float2 *gb[2] = {nullptr, nullptr};   // gradient-map records, by iteration parity
         double *partials = nullptr, *gparam = nullptr, *red = nullptr;
-        float2 *mv = nullptr;
+        float2 *mv[2] = {nullptr, nullptr};   // m v of every sample, by iteration parity
         uint32_t *mvmax = nullptr;
-        int64_t cap_pts = 0, cap_a1 = 0, cap_gb = 0, cap_part = 0, cap_gp = 0, cap_red = 0;
-        int64_t cap_mv = 0, cap_mm = 0;
+        int64_t cap_pts = 0, cap_a1 = 0, cap_gb[2] = {0, 0}, cap_part = 0, cap_gp = 0, cap_red = 0;
+        int64_t cap_mv[2] = {0, 0}, cap_mm = 0;
     } adj;
 
     // kernel variants (chunks of 64 per trip in resampling / advection)
@@ -270,8 +271,8 @@ static hb_status validate(hb_ctx *c, const hb_params *p) {
     if (!std::isfinite(p->h_max_px)) return fail(c, HB_EINVAL, "h_max_px is not finite");
     if (!(p->lambda > 0.0f) || p->lambda > 1.0f) return fail(c, HB_EINVAL, "lambda must be in (0, 1]");
     if (!(p->eps > 0.0f) || !std::isfinite(p->eps)) return fail(c, HB_EINVAL, "eps must be positive");
-    if (p->max_halvings < 0 || p->max_halvings > HB_MAX_HALVINGS)
-        return fail(c, HB_EINVAL, "max_halvings out of range [0, 30]");
+    if (p->max_halvings < -1 || p->max_halvings > HB_MAX_HALVINGS)
+        return fail(c, HB_EINVAL, "max_halvings out of range [-1, 30]");
     if (!(p->smooth_weight >= 0.0f) || p->smooth_weight > 1.0f)
         return fail(c, HB_EINVAL, "smooth_weight must be in [0, 1]");
     if (p->smooth_passes != 1) return fail(c, HB_EINVAL, "smooth_passes must be 1");
@@ -1511,11 +1512,13 @@ static void free_ckpts(hb_ctx *c) {
     c->ckpt_end_iter = -1;
     dfree(&c->adj.a0);
     dfree(&c->adj.a1);
-    dfree(&c->adj.gb);
+    for (int i = 0; i < 2; ++i) {
+        dfree(&c->adj.gb[i]);
+        dfree(&c->adj.mv[i]);
+    }
     dfree(&c->adj.partials);
     dfree(&c->adj.gparam);
     dfree(&c->adj.red);
-    dfree(&c->adj.mv);
     dfree(&c->adj.mvmax);
     c->adj = hb_ctx::AdjBufs();
 }
@@ -1699,13 +1702,15 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
     CHKST(grow(c, &A.a0, A.cap_pts, nmax, "adjoint"));
     CHKST(grow(c, &A.a1, A.cap_a1, nmax, "adjoint"));
     const int bp = (B + 1) / 2 * 2, pp = (P + 1) / 2 * 2;
-    CHKST(grow(c, &A.gb, A.cap_gb, plane * (bp + (int64_t)B * pp), "gradient maps"));
+    for (int i = 0; i < 2 && i < T; ++i)
+        CHKST(grow(c, &A.gb[i], A.cap_gb[i], plane * (bp + (int64_t)B * pp), "gradient maps"));
     // work items of the tile bins: at most one per kSegEntries samples plus one per tile
     const int64_t nt = hb::tiles_of(B, W, H).n;
     int64_t max_items = 1;
     for (auto &k : c->ckpts) max_items = std::max(max_items, k.ns / hb::kSegEntries + nt + 1);
     CHKST(grow(c, &A.partials, A.cap_part, max_items * (B + P), "partials"));
-    CHKST(grow(c, &A.mv, A.cap_mv, std::max<int64_t>(1, nmax), "adjoint steps"));
+    for (int i = 0; i < 2 && i < T; ++i)
+        CHKST(grow(c, &A.mv[i], A.cap_mv[i], std::max<int64_t>(1, nmax), "adjoint steps"));
     CHKST(grow(c, &A.mvmax, A.cap_mm, (int64_t)T, "adjoint step scale"));
     CHKST(grow(c, &A.gparam, A.cap_gp, (int64_t)(B * B + P), "parameter gradients"));
     CHKST(grow(c, &A.red, A.cap_red, (int64_t)(B * B + P) * hb::kRedSlices, "reduction"));
@@ -1730,8 +1735,8 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
         a.samples = k.xs;
         a.off_s = k.xoff;
         a.jacc = k.jacc;
-        a.gbm = A.gb;
-        a.gkm = A.gb + plane * bp;
+        a.gbm = A.gb[t & 1];
+        a.gkm = A.gb[t & 1] + plane * bp;
         a.bp = bp;
         a.pp = pp;
         a.adj_in = cur;
@@ -1742,7 +1747,7 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
         a.abin_src = k.bsrc;
         a.atile_off = k.toff;
         a.aseg_off = k.soff;
-        a.mv = A.mv;
+        a.mv = A.mv[t & 1];
         a.mvmax = A.mvmax + t;
         a.red = A.red;
         a.grad_param = A.gparam;
@@ -1758,8 +1763,9 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
     CHKST(upload_desc(c, (size_t)(2 * T)));
     HIPCHK(c, hipMemsetAsync(A.mvmax, 0, sizeof(uint32_t) * T, c->stream));
     // The parameter gradients of iteration t (tile splat + reduction) run on a second stream,
-    // beside the resampling adjoint of t and the map rebuild of t - 1; iteration t - 1 waits
-    // for them before it overwrites the gradient maps and m v.
+    // beside the resampling adjoint of t and iteration t - 1; the gradient-map records and m v
+    // are double-buffered by iteration parity, so only iteration t - 2 waits for them before
+    // it overwrites their buffers.
     if (!c->side) HIPCHK(c, hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
     while (c->adj_ev.size() < (size_t)(2 * T)) {
         hipEvent_t ev;
@@ -1772,7 +1778,7 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
         hipEvent_t adv_done = c->adj_ev[2 * (size_t)t], par_done = c->adj_ev[2 * (size_t)t + 1];
         for (int kk = 0; kk < P; ++kk) HIPCHK(c, hb::launch_box_pass(a, 1, s, W, kk, c->stream));
         HIPCHK(c, hb::launch_density_cells(a, 1, s, B, c->stream));
-        if (params_done) HIPCHK(c, hipStreamWaitEvent(c->stream, params_done, 0));
+        if (t + 2 < T) HIPCHK(c, hipStreamWaitEvent(c->stream, c->adj_ev[2 * (size_t)(t + 2) + 1], 0));
         HIPCHK(c, hb::launch_adj_maps(a, s, B, c->stream));
         HIPCHK(c, hb::launch_adj_advect(a, s, c->stream));
         HIPCHK(c, hipEventRecord(adv_done, c->stream));

@@ -39,7 +39,7 @@ def test_default_params_are_the_papers():
 @pytest.mark.parametrize("field,value", [
     ("grid_w", 1), ("grid_h", 9000), ("delta_px", 0.0), ("delta_px", float("nan")),
     ("box_passes", 0), ("box_passes", 9), ("lambda_", 0.0), ("lambda_", 1.5), ("eps", 0.0),
-    ("max_halvings", -1), ("max_halvings", 31), ("smooth_weight", 1.5), ("smooth_passes", 2),
+    ("max_halvings", -2), ("max_halvings", 31), ("smooth_weight", 1.5), ("smooth_passes", 2),
     ("capacity_factor", 1.05), ("h_max_px", float("inf")), ("struct_size", 4), ("n_radii", 0),
 ])
 def test_invalid_params_rejected(field, value):
@@ -47,6 +47,20 @@ def test_invalid_params_rejected(field, value):
     setattr(p, field, value)
     assert hb.hb_validate_params(p) == hb.HB_EINVAL
     assert hb.hb_last_error() != ""
+
+
+def test_build_module_is_reachable():
+    """The build step the entry point calls is the submodule, not a package attribute."""
+    import importlib
+    m = importlib.import_module("paper_1504_02687_amd.build")
+    assert callable(m.build) and m.LIB.endswith("libhb.so")
+    import __graft_entry__
+    assert callable(__graft_entry__.build) and callable(__graft_entry__.smoke)
+
+
+def test_fixed_step_mode_accepted():
+    p, keep = hb.make_params(64, 64, [3], max_halvings=-1)
+    assert hb.hb_validate_params(p) == hb.HB_OK
 
 
 def test_radius_and_bbox_checks():

@@ -117,6 +117,39 @@ def test_stage_parity_given_samples(hb, E, W, H, B, r, a, seed):
     np.testing.assert_array_equal(xy_n[ends], xy[ends])
 
 
+@pytest.mark.parametrize("E,W,H,B,r,a,seed", [STAGE_CASES[0], STAGE_CASES[2]])
+def test_fixed_step_parity_given_samples(hb, E, W, H, B, r, a, seed):
+    """The original fixed step (max_halvings = -1): every interior point moves by h along
+    the normalised gradient, no decisions, against the oracle's fixed step."""
+    rng = np.random.default_rng(seed)
+    off, xy = PT.random_polylines(rng, E, W, H)
+    group = rng.integers(0, B, E).astype(np.int32)
+    M = workloads.interaction_eq4(B, 0.25) if B > 1 else np.ones((1, 1), np.float32)
+    with _bundler(hb, W, H, [r], E, group, M, seed, pass_weights=a, max_halvings=-1) as b:
+        b.set_points(off, xy)
+        b.run(1, hb.HB_RUN_SAMPLES_GIVEN | hb.HB_RUN_RECORD_DECISIONS)
+        off_n, xy_n = b.points(hb.HB_POINTS_STATE)
+        jacc = b.decisions().astype(np.int64)
+    p = O.Params(grid_w=W, grid_h=H, radii=[r], pass_weights=a, max_halvings=-1)
+    x64 = xy.astype(np.float64)
+    ref = O.iterate(off, x64, group, M.astype(np.float64), p, 0, skip_resample=True)
+    ends = np.zeros(len(xy), bool)
+    ends[off[:-1]] = ends[off[1:] - 1] = True
+    np.testing.assert_array_equal(jacc[ends], -2)
+    np.testing.assert_array_equal(jacc[~ends], 0)
+    np.testing.assert_array_equal(ref["adv"]["jacc"][~ends], 0)
+    h = p.bandwidth(0)
+    cond = PT.interp_condition(ref["grad"], group, off, x64)
+    tdir = np.where(np.isfinite(cond), h * 1e-6 * cond, 0.0)
+    tpt = 1e-4 + tdir + 2 * PT.F32_ULP_AT(xy_n).max(1)
+    ty = tpt.copy()
+    ty[1:-1] = 0.5 * tpt[1:-1] + 0.25 * (tpt[:-2] + tpt[2:])
+    err = np.abs(xy_n.astype(np.float64) - ref["xy"]).max(1)
+    assert (err <= ty + 1e-4).all(), f"max err {err.max()} px"
+    assert np.percentile(err, 99) <= 1e-4
+    np.testing.assert_array_equal(xy_n[ends], xy[ends])
+
+
 def _given_hist(hb, W, H, off, xy, group, B, weight=None, seed=0):
     """Histogram the GPU builds from given samples (one iteration with HB_RUN_SAMPLES_GIVEN)."""
     E = len(off) - 1

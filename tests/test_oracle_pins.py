@@ -351,6 +351,53 @@ def test_advect_toward_isolated_bump_closed_form(x, h):
     assert res["dir"][1, 0] == pytest.approx(sgn) and res["dir"][1, 1] == 0.0
 
 
+@pytest.mark.parametrize("x,h", [(26.5, 2.0), (26.5, 12.0), (36.0, 9.0), (31.0, 5.0), (40.0, 45.0)])
+def test_fixed_step_moves_by_h_closed_form(x, h):
+    """The original step (K = -1) moves every interior point by exactly h toward the peak of
+    a symmetric bump, overshooting it where h is larger than the distance, clamped only at
+    the grid border; end points stay."""
+    W, c, P, r = 64, 32, 3, 3
+    rho, grad = _bump(W, c, P, r)
+    y = c + 0.5
+    off = np.array([0, 3], np.int64)
+    xy = np.array([[1.0, 1.0], [x, y], [60.0, 60.0]])
+    res = O.advect(off, xy, np.zeros(1, np.int32), rho, grad, h=h, K=-1)
+    sgn = 1.0 if c + 0.5 > x else -1.0
+    expect = min(max(x + sgn * h, 0.0), W - 1 / 256)
+    assert abs(res["xy"][1, 0] - expect) < 1e-12 and res["xy"][1, 1] == y
+    assert res["jacc"][1] == 0
+    np.testing.assert_array_equal(res["xy"][[0, 2]], xy[[0, 2]])
+
+
+def test_fixed_step_displacement_is_h_times_direction():
+    """On random maps every interior point moves by h d with d the unit direction of the
+    scipy-interpolated gradient (where no clamp applies), and the halving version agrees
+    wherever its first try is accepted."""
+    g = rng(12)
+    W, B = 48, 2
+    hist = g.integers(0, 5, (B, W, W)).astype(np.int64)
+    rho = O.density(O.box_chain(hist, 3, 3), 3, np.array([0, 0, 1.0]), np.eye(B))
+    grad = O.gradient(rho)
+    off, xy = _random_points(g, 40, W, W, B)[:2]
+    group = g.integers(0, B, 40).astype(np.int32)
+    xy = np.clip(xy, 8, W - 8)
+    h = 3.0
+    res = O.advect(off, xy, group, rho, grad, h=h, K=-1)
+    hal = O.advect(off, xy, group, rho, grad, h=h, K=8)
+    ends = np.zeros(len(xy), bool)
+    ends[off[:-1]] = ends[off[1:] - 1] = True
+    for i in np.nonzero(~ends)[0]:
+        e = np.searchsorted(off, i, side="right") - 1
+        gx = scipy.ndimage.map_coordinates(grad[group[e], :, :, 0], [[xy[i, 1] - .5], [xy[i, 0] - .5]], order=1, mode="nearest")[0]
+        gy = scipy.ndimage.map_coordinates(grad[group[e], :, :, 1], [[xy[i, 1] - .5], [xy[i, 0] - .5]], order=1, mode="nearest")[0]
+        n = math.hypot(gx, gy)
+        d = np.array([gx, gy]) / max(n, 1e-6)
+        np.testing.assert_allclose(res["xy"][i], xy[i] + h * d, atol=1e-9)
+        if hal["jacc"][i] == 0:
+            np.testing.assert_allclose(hal["xy"][i], res["xy"][i], atol=1e-12)
+    np.testing.assert_array_equal(res["xy"][ends], xy[ends])
+
+
 # ------------------------------------------------------------------ Laplacian
 
 def test_laplacian_fixed_points_and_zigzag():
