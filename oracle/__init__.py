@@ -55,6 +55,8 @@ def lib():
             "orc_sample_count": (i64, [f64, f64]),
             "orc_resample_counts": (i64, [i64, P, P, f64, P, P]),
             "orc_resample": (None, [i64, P, P, P, P, P, P]),
+            "orc_directed_offset": (None, [i64, P, P, P, P, f64, P]),
+            "orc_orientation": (None, [i64, P, P]),
             "orc_resample_frozen": (None, [i64, P, P, P, P, P]),
             "orc_advect_frozen": (None, [i64, P, P, P, i32, i32, P, f64, P, f64, P]),
             "orc_splat": (None, [i64, P, P, P, P, i32, i32, i32, P]),
@@ -106,6 +108,7 @@ class Params:
     pass_weights: Optional[List[float]] = None   # a_k; None: only the last pass
     amb_tol: float = 1e-5       # decision margin treated as ambiguous in parity checks
     bbox: tuple = (0.0, 0.0, 1.0, 1.0)
+    directed_offset: float = 0.0    # push of interior samples along the left normal (px)
 
     def radius(self, it: int) -> int:
         return int(self.radii[min(it, len(self.radii) - 1)])
@@ -180,6 +183,28 @@ def resample(off, xy, delta, want_seg=False):
     if want_seg:
         return off_out, xy_out, lens, seg
     return off_out, xy_out, lens
+
+
+def directed_offset(off_in, xy_in, off_out, seg, xy, d):
+    """Samples xy (from resample with want_seg) pushed by d px along the left normal of the
+    input segment each lies on; end points unchanged (Section 3, the pipeline)."""
+    off_in = _c(off_in, np.int64)
+    xy_in = _c(xy_in, np.float64)
+    off_out = _c(off_out, np.int64)
+    seg = _c(seg, np.int64)
+    out = np.array(xy, dtype=np.float64, copy=True, order="C")
+    lib().orc_directed_offset(off_in.shape[0] - 1, _p(off_in), _p(xy_in), _p(off_out), _p(seg),
+                              float(d), _p(out))
+    return out
+
+
+def orientation(dxy):
+    """Orientation slice in [0, 4) of every direction (dx, dy): slice k holds the angles in
+    [90k - 45, 90k + 45) degrees (Section 5)."""
+    dxy = _c(np.reshape(dxy, (-1, 2)), np.float64)
+    out = np.empty(dxy.shape[0], np.int32)
+    lib().orc_orientation(dxy.shape[0], _p(dxy), _p(out))
+    return out
 
 
 def splat(off, xy, group, B, W, H, weight=None):
@@ -297,6 +322,9 @@ def iterate(off, xy, group, M, p: Params, it: int, weight=None, skip_resample=Fa
     r = p.radius(it)
     if skip_resample:
         s_off, s_xy = _c(off, np.int64), _c(xy, np.float64)
+    elif p.directed_offset != 0.0:
+        s_off, s_xy, _, seg = resample(off, xy, p.delta, want_seg=True)
+        s_xy = directed_offset(off, xy, s_off, seg, s_xy, p.directed_offset)
     else:
         s_off, s_xy, _ = resample(off, xy, p.delta)
     hist = splat(s_off, s_xy, group, B, W, H, weight)
@@ -328,6 +356,8 @@ def run(node_xy, src, dst, group, M, p: Params, n_iters: int, weight=None):
 def record_run(off, xy, group, M, p: Params, n_iters: int, it0: int = 0, weight=None):
     """Base run from the polylines (off, xy): per iteration, the discrete choices that the
     frozen surrogate replays (sample offsets, segment indices, histograms, decisions)."""
+    if p.directed_offset != 0.0:
+        raise ValueError("the frozen surrogate does not include the directed offset")
     rec = []
     off = _c(off, np.int64)
     xy = _c(xy, np.float64)

@@ -483,3 +483,109 @@ def test_schedule_values():
     assert abs(p.hmax() - 2 * math.sqrt(3 * 8 * 9 / 3)) < 1e-12
     h = [p.bandwidth(i) for i in range(10)]
     np.testing.assert_allclose(h, [16.97056 * 0.9 ** i for i in range(10)], rtol=1e-6)
+
+
+# ------------------------------------------------------------------ directed graphs (Sec. 3)
+
+def _pushed(off, xy, delta, d):
+    o, s, _, seg = O.resample(off, xy, delta, want_seg=True)
+    return o, s, seg, O.directed_offset(off, xy, o, seg, s, d)
+
+
+def test_directed_offset_straight_edges_closed_form():
+    # the same horizontal edge in both directions: the interior samples of the rightward
+    # edge move to y + d (left normal of +x is +y), those of the leftward one to y - d
+    off = np.array([0, 2, 4], np.int64)
+    xy = np.array([[10.25, 20.5], [110.25, 20.5], [110.25, 20.5], [10.25, 20.5]])
+    d = 2.5
+    o, s, seg, out = _pushed(off, xy, 1.0, d)
+    assert o[1] == 101 and o[2] == 202
+    a, b = out[:101], out[101:]
+    np.testing.assert_array_equal(a[1:-1, 1], 20.5 + d)
+    np.testing.assert_array_equal(b[1:-1, 1], 20.5 - d)
+    np.testing.assert_allclose(a[:, 0], 10.25 + np.arange(101), atol=1e-12)
+    np.testing.assert_allclose(b[:, 0], 110.25 - np.arange(101), atol=1e-12)
+    # the two directions part by 2|d|; end points stay
+    assert np.all(a[1:-1, 1] - b[::-1][1:-1, 1] == 2 * d)
+    np.testing.assert_array_equal(out[[0, 100, 101, 201]], xy[[0, 1, 2, 3]])
+
+
+def test_directed_offset_distance_side_and_identity_on_random_polylines():
+    g = rng(21)
+    polys = [np.cumsum(g.normal(0, 3, (int(m), 2)), 0) + 100 for m in g.integers(2, 40, 60)]
+    off = np.concatenate([[0], np.cumsum([len(p) for p in polys])]).astype(np.int64)
+    xy = np.concatenate(polys)
+    d = -1.75
+    o, s, seg, out = _pushed(off, xy, 1.0, d)
+    np.testing.assert_array_equal(O.directed_offset(off, xy, o, seg, s, 0.0), s)
+    interior = np.ones(len(s), bool)
+    interior[o[:-1]] = False
+    interior[o[1:] - 1] = False
+    np.testing.assert_array_equal(out[~interior], s[~interior])
+    # every interior sample moved by |d|, perpendicular to its segment, on the side given
+    # by the sign of d (cross product of the segment direction and the move)
+    eid = np.repeat(np.arange(len(polys)), np.diff(o))[interior]
+    j = seg[interior]
+    p0 = xy[off[eid] + j]
+    p1 = xy[off[eid] + j + 1]
+    e = p1 - p0
+    mv = out[interior] - s[interior]
+    np.testing.assert_allclose(np.hypot(mv[:, 0], mv[:, 1]), abs(d), atol=1e-12)
+    ln = np.hypot(e[:, 0], e[:, 1])
+    np.testing.assert_allclose((e[:, 0] * mv[:, 1] - e[:, 1] * mv[:, 0]) / ln, d, atol=1e-12)
+    np.testing.assert_allclose((e[:, 0] * mv[:, 0] + e[:, 1] * mv[:, 1]) / ln, 0.0, atol=1e-12)
+
+
+def test_directed_offset_commutes_with_quarter_turn():
+    g = rng(22)
+    polys = [np.cumsum(g.normal(0, 4, (int(m), 2)), 0) for m in g.integers(2, 20, 30)]
+    off = np.concatenate([[0], np.cumsum([len(p) for p in polys])]).astype(np.int64)
+    xy = np.concatenate(polys)
+    turn = lambda a: np.stack([-a[:, 1], a[:, 0]], 1)     # exact 90-degree rotation
+    o, s, seg, out = _pushed(off, xy, 1.0, 0.8)
+    o2, s2, seg2, out2 = _pushed(off, turn(xy), 1.0, 0.8)
+    np.testing.assert_array_equal(o, o2)
+    np.testing.assert_allclose(out2, turn(out), atol=1e-9)
+
+
+def test_directed_run_keeps_opposite_edges_mirrored():
+    # two copies of one edge in opposite directions: pushed to opposite sides, then
+    # advected in a density that is symmetric about their common line, so the two final
+    # polylines are mirror images of each other about that line
+    W = 64
+    p = _params(W, [4], directed_offset=1.25)   # pushed rows stay off pixel borders
+    node = np.array([[10.25 / W, 30.5 / W], [50.75 / W, 30.5 / W]], np.float32)
+    off, xy, _ = O.run(node, np.array([0, 1]), np.array([1, 0]), np.zeros(2, np.int32),
+                       np.ones((1, 1)), p, 3)
+    a, b = xy[off[0]:off[1]], xy[off[1]:off[2]][::-1]
+    assert len(a) == len(b)
+    np.testing.assert_allclose(a[:, 0], b[:, 0], atol=1e-9)
+    np.testing.assert_allclose(a[:, 1] + b[:, 1], 61.0, atol=1e-9)
+    assert (a[1:-1, 1] != 30.5).any()
+    # with no push the two copies coincide and stay on the row
+    off0, xy0, _ = O.run(node, np.array([0, 1]), np.array([1, 0]), np.zeros(2, np.int32),
+                         np.ones((1, 1)), _params(W, [4]), 3)
+    np.testing.assert_array_equal(xy0[:, 1], 30.5)
+
+
+# ------------------------------------------------------------------ orientation bins (Sec. 5)
+
+def test_orientation_axes_diagonals_and_zero():
+    dirs = np.array([[1, 0], [1, 1], [0, 1], [-1, 1], [-1, 0], [-1, -1], [0, -1], [1, -1],
+                     [0, 0], [3.5, 0], [0, 0.25]], np.float64)
+    # slices [90k - 45, 90k + 45): 45 -> 1, 135 -> 2, 225 -> 3, 315 -> 0
+    np.testing.assert_array_equal(O.orientation(dirs), [0, 1, 1, 2, 2, 3, 3, 0, 0, 0, 1])
+
+
+def test_orientation_matches_atan2_and_quarter_turns():
+    g = rng(23)
+    v = g.normal(0, 1, (20000, 2)) * g.choice([1e-3, 1.0, 1e3], (20000, 1))
+    ang = np.degrees(np.arctan2(v[:, 1], v[:, 0])) % 360.0
+    away = np.abs(((ang + 45.0) % 90.0) - 45.0) > 1e-6      # not within 1e-6 deg of a border
+    ref = (np.floor((ang + 45.0) / 90.0).astype(np.int64) % 4)
+    got = O.orientation(v)
+    np.testing.assert_array_equal(got[away], ref[away])
+    assert away.mean() > 0.999
+    turn = np.stack([-v[:, 1], v[:, 0]], 1)                  # +90 degrees, exact
+    np.testing.assert_array_equal(O.orientation(turn), (got + 1) % 4)
+    np.testing.assert_array_equal(O.orientation(-v), (got + 2) % 4)
