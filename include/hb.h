@@ -115,6 +115,17 @@ typedef struct hb_params {
                                    NULL selects the last pass only. Copied. */
     float capacity_factor;      /* point-buffer capacity relative to the first sample count
                                    (>= 1.1; grown automatically when exceeded) */
+    float directed_offset_px;   /* directed graphs (Section 3, the pipeline of Fig. 1): in every
+                                   iteration, right after resampling and before the histogram,
+                                   each sample except the two end points is moved by this
+                                   signed distance (px) along the left normal (-t_y, t_x) of
+                                   the polyline segment it was interpolated on, t the unit
+                                   direction of that segment from source towards target (a
+                                   zero-length segment moves nothing); 0 (default) disables
+                                   it. |value| <= max(W, H) / 16 (the paper uses 0.1 % to
+                                   0.5 % of the drawing). Not applied to samples given with
+                                   HB_RUN_SAMPLES_GIVEN; not differentiated (hb_forward_ckpt
+                                   requires 0). */
 } hb_params;
 
 /* Fill p with the paper's defaults for a W x H grid: bbox [0,0,1,1], delta 1 px, P = 3,
@@ -143,6 +154,17 @@ hb_status hb_set_params(hb_ctx *ctx, const hb_params *p);
 hb_status hb_set_graph(hb_ctx *ctx, int32_t n_nodes, const float *node_xy, int64_t n_edges,
                        const int32_t *src, const int32_t *dst, const int32_t *weight,
                        uint32_t flags);
+
+/* Orientation bins of the edges (Section 5): the angle of the direction (dx, dy) from the
+ * first to the last point of each current polyline (source to target; the end points never
+ * move), in grid (pixel) coordinates measured from +x towards +y, discretised into 4 slices of
+ * 90 degrees centred on 0, 90, 180 and 270 degrees: slice k holds the angles in
+ * [90k - 45, 90k + 45), so an angle of exactly 45, 135, 225 or 315 degrees goes to the slice
+ * above it; an edge whose end points coincide is in slice 0. Writes E int32 values in [0, 4)
+ * to group (host memory, or device memory with HB_DEVICE_PTRS; caller-owned, E = the edge
+ * count of hb_set_graph), ready for hb_set_groups with B = 4. Synchronous. Requires
+ * hb_set_graph (HB_ESTATE otherwise); NULL group with E > 0 gives HB_EINVAL. */
+hb_status hb_orientation_groups(hb_ctx *ctx, int32_t *group, uint32_t flags);
 
 /* Set the edge groups b_e in [0, B) and the B x B interaction matrix M (Section 3.2 Eq. 3):
  * M[l * B + b] is the weight of bin b on layer l. B in [1, 64]. */

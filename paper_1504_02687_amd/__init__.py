@@ -54,6 +54,7 @@ class hb_params(ctypes.Structure):
         ("smooth_passes", ctypes.c_int32),
         ("pass_weights", ctypes.POINTER(ctypes.c_float)),
         ("capacity_factor", ctypes.c_float),
+        ("directed_offset_px", ctypes.c_float),
     ]
 
 
@@ -70,6 +71,7 @@ _SIGS = {
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
     "hb_set_groups": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_uint32]),
+    "hb_orientation_groups": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
     "hb_run": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32]),
     "hb_sync": (ctypes.c_int32, [ctypes.c_void_p]),
     "hb_get_num_points": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
@@ -111,6 +113,13 @@ def load():
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
                                "(run __graft_entry__.build() or python -m paper_1504_02687_amd.build)")
+        # torch ships its own HIP runtime: load it first, so that libhb binds to that same
+        # runtime and torch's device tensors and streams are valid in libhb's calls (a second
+        # runtime loaded beside an initialised one leaves torch without devices)
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in _SIGS.items():
             fn = getattr(L, name)
@@ -200,6 +209,19 @@ def hb_set_groups(ctx, group, M) -> None:
     pm, km, dm = _arr(M, np.float32)
     B = int(km.shape[0])
     _check(ctx, load().hb_set_groups(ctx, B, pg, pm, _flags(dg, dm)))
+
+
+def hb_orientation_groups(ctx, n_edges: int, device=None):
+    """Orientation slice in [0, 4) of every edge (int32 numpy array, or a torch tensor on
+    ``device``)."""
+    if device is not None:
+        import torch
+        out = torch.empty(n_edges, dtype=torch.int32, device=device)
+        _check(ctx, load().hb_orientation_groups(ctx, ctypes.c_void_p(out.data_ptr()), HB_DEVICE_PTRS))
+        return out
+    out = np.empty(n_edges, np.int32)
+    _check(ctx, load().hb_orientation_groups(ctx, out.ctypes.data, 0))
+    return out
 
 
 def hb_run(ctx, n_iters: int, flags: int = 0) -> None:
@@ -333,7 +355,7 @@ def make_params(grid_w: int, grid_h: int, radii: Sequence[int], *, delta: float 
                 passes: int = 3, h_max: float = 0.0, lam: float = 0.9, eps: float = 1e-6,
                 max_halvings: int = 8, smooth_weight: float = 0.5,
                 pass_weights: Optional[Sequence[float]] = None, bbox=(0.0, 0.0, 1.0, 1.0),
-                capacity_factor: float = 2.0):
+                capacity_factor: float = 2.0, directed_offset: float = 0.0):
     """hb_params plus the arrays it points to (keep both alive until hb_set_params)."""
     p = hb_default_params(grid_w, grid_h)
     r = (ctypes.c_int32 * len(radii))(*[int(v) for v in radii])
@@ -349,6 +371,7 @@ def make_params(grid_w: int, grid_h: int, radii: Sequence[int], *, delta: float 
     for i in range(4):
         p.bbox[i] = bbox[i]
     p.capacity_factor = capacity_factor
+    p.directed_offset_px = directed_offset
     keep = [r]
     if pass_weights is not None:
         a = (ctypes.c_float * passes)(*[float(v) for v in pass_weights])
@@ -394,6 +417,9 @@ class Bundler:
 
     def set_groups(self, group, M):
         hb_set_groups(self.ctx, group, M)
+
+    def orientation_groups(self, device=None):
+        return hb_orientation_groups(self.ctx, self.n_edges, device)
 
     def set_workload(self, w, **kw):
         """Parameters, graph and groups of a ``workloads.Workload``."""

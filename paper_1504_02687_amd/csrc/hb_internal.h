@@ -72,6 +72,7 @@ struct GDesc {
     int32_t B, W, H, P;
     int32_t r, K, record, wmax;
     double h, eps, s, delta;
+    double doff;                // directed offset of interior samples along the left normal
     double a[HB_MAX_PASSES];    // density weight of each pass
     double ck[HB_MAX_PASSES];   // (2r+1)^(2k), k = 1..P
 
@@ -177,6 +178,8 @@ hipError_t launch_density_cells(const GDesc *desc, int ng, const Shape &tot, int
 hipError_t launch_advect_smooth(const GDesc *desc, int ng, const Shape &tot, int u,
                                 hipStream_t st);
 hipError_t launch_fill_totals(const GDesc *desc, int ng, int T, hipStream_t st);
+// orientation slice in [0, 4) of every edge, from the end points of its polyline
+hipError_t launch_orientation(const GDesc *desc, const Shape &tot, int32_t *group, hipStream_t st);
 // ink = sum of n polyline lengths, fixed order; part[kInkSlices] receives it (device)
 hipError_t launch_ink(const double *lens, int64_t n, double *part, hipStream_t st);
 

@@ -182,6 +182,7 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
         glb((unsigned long long *)d.bin_cnt) + (bl & (d.n_sets - 1)) * d.n_tiles;
     const double nm1 = (double)(n - 1);
     const double ds = L / nm1;          // arclength between consecutive samples
+    const double doff = d.doff;
 
     double Cbase = 0.0;
     int knext = 0;
@@ -261,8 +262,17 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
                     const double ex = (double)pb.x - (double)pa.x, ey = (double)pb.y - (double)pa.y;
                     double t = mul_rn(sub_rn(s, sC[wid][lo]), sR[wid][lo]);
                     t = fmin(fmax(t, 0.0), 1.0);
-                    out.x = (float)__builtin_fma(t, ex, (double)pa.x);
-                    out.y = (float)__builtin_fma(t, ey, (double)pa.y);
+                    double ox = __builtin_fma(t, ex, (double)pa.x);
+                    double oy = __builtin_fma(t, ey, (double)pa.y);
+                    if (doff != 0.0) {
+                        // directed graphs: along the left normal of the segment, doff / |e|
+                        // (-ey, ex) with 1 / |e| the segment's stored reciprocal length
+                        const double f = mul_rn(doff, sR[wid][lo]);
+                        ox = __builtin_fma(-f, ey, ox);
+                        oy = __builtin_fma(f, ex, oy);
+                    }
+                    out.x = (float)ox;
+                    out.y = (float)oy;
                 }
                 st2(q + k, out);
                 bin_of(d, layer, out, key, loc);
@@ -812,6 +822,24 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
     }
 }
 
+// Orientation slice of every edge (one thread per edge): the direction (dx, dy) from the
+// first to the last point of its polyline, slice k for angles in [90k - 45, 90k + 45)
+// degrees, decided by exact comparisons of dx and dy; coincident end points give slice 0.
+__global__ __launch_bounds__(kBlock) void k_orientation(const GDesc *__restrict__ gd, int ng,
+                                                        int32_t *group) {
+    const int64_t blk = blockIdx.x;
+    HB_FIND(blk_edget);
+    const int64_t e = (blk - d.blk_edget) * kBlock + threadIdx.x;
+    if (e >= d.n_edges) return;
+    const float2 a = d.pin[d.off_in[e]], b = d.pin[d.off_in[e + 1] - 1];
+    const double dx = (double)b.x - (double)a.x, dy = (double)b.y - (double)a.y;
+    int k = 0;
+    if (dy > 0.0 && -dy < dx && dx <= dy) k = 1;           // [45, 135)
+    else if (dx < 0.0 && dx < dy && dy <= -dx) k = 2;      // [135, 225)
+    else if (dy < 0.0 && dy <= dx && dx < -dy) k = 3;      // [225, 315)
+    group[e] = k;
+}
+
 // Total length of the polylines (the ink): sum of the per-edge lengths in a fixed order.
 // Stage 1: block j sums its contiguous slice (fixed per-thread order, fixed tree) into
 // part[j]; stage 2: one block sums the kInkSlices slice sums in order into part[kInkSlices].
@@ -969,6 +997,12 @@ hipError_t launch_density_cells(const GDesc *desc, int ng, const Shape &tot, int
     hipError_t e = launch_density_grad(desc, ng, tot, bmax, st);
     if (e != hipSuccess || tot.cell <= 0) return e;
     hipLaunchKernelGGL(k_cells, grid_of(tot.cell), dim3(kBlock), 0, st, desc, ng);
+    return hipGetLastError();
+}
+
+hipError_t launch_orientation(const GDesc *desc, const Shape &tot, int32_t *group, hipStream_t st) {
+    if (tot.edget <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_orientation, grid_of(tot.edget), dim3(kBlock), 0, st, desc, 1, group);
     return hipGetLastError();
 }
 

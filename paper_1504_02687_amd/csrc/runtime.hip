@@ -244,6 +244,7 @@ HB_API void hb_default_params(hb_params *p, int32_t grid_w, int32_t grid_h) {
     p->smooth_passes = 1;
     p->pass_weights = nullptr;
     p->capacity_factor = 2.0f;
+    p->directed_offset_px = 0.0f;
 }
 
 static hb_status validate(hb_ctx *c, const hb_params *p) {
@@ -281,6 +282,9 @@ static hb_status validate(hb_ctx *c, const hb_params *p) {
             if (!std::isfinite(p->pass_weights[k])) return fail(c, HB_EINVAL, "pass_weights not finite");
     if (!(p->capacity_factor == 0.0f || (p->capacity_factor >= 1.1f && p->capacity_factor <= 64.0f)))
         return fail(c, HB_EINVAL, "capacity_factor must be 0 (default) or in [1.1, 64]");
+    if (!std::isfinite(p->directed_offset_px) ||
+        std::fabs(p->directed_offset_px) > (float)std::max(p->grid_w, p->grid_h) / 16.0f)
+        return fail(c, HB_EINVAL, "directed_offset_px must be finite with |value| <= max(W, H) / 16");
     return HB_OK;
 }
 
@@ -405,6 +409,7 @@ static GDesc base_desc(const hb_ctx *c) {
     d.eps = (double)c->P.eps;
     d.s = (double)c->P.smooth_weight;
     d.delta = (double)c->P.delta_px;
+    d.doff = (double)c->P.directed_offset_px;
     for (int k = 0; k < d.P; ++k)
         d.a[k] = c->passw.empty() ? (k == d.P - 1 ? 1.0 : 0.0) : (double)c->passw[k];
     d.group = c->d_group;
@@ -1448,6 +1453,35 @@ HB_API hb_status hb_get_ink(hb_ctx *c, double *ink) {
     return HB_OK;
 }
 
+HB_API hb_status hb_orientation_groups(hb_ctx *c, int32_t *group, uint32_t flags) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    if (flags & ~(uint32_t)HB_DEVICE_PTRS) return fail(c, HB_EINVAL, "unknown flags");
+    if (!c->have_graph) return fail(c, HB_ESTATE, "hb_orientation_groups needs hb_set_graph");
+    if (c->E == 0) return HB_OK;
+    if (!group) return fail(c, HB_EINVAL, "group is NULL");
+    CHKST(ensure_desc(c, 1));
+    CHKST(wait_desc(c));
+    GDesc d = base_desc(c);
+    d.pin = c->pts[c->ps];       // the end points never move: any iteration's polylines
+    d.off_in = c->off[c->os];
+    c->h_desc[0] = d;
+    CHKST(upload_desc(c, 1));
+    int32_t *out = group, *tmp = nullptr;
+    if (!(flags & HB_DEVICE_PTRS)) {
+        CHKST(dalloc(c, &tmp, (size_t)c->E, "orientation bins"));
+        out = tmp;
+    }
+    const Shape s = hb::shape_of(c->E, d.B, d.W, d.H);
+    hipError_t e = hb::launch_orientation(c->d_desc, s, out, c->stream);
+    if (e == hipSuccess && tmp)
+        e = hipMemcpyAsync(group, tmp, sizeof(int32_t) * (size_t)c->E, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dfree(&tmp);
+    if (e != hipSuccess) return fail_dev(c, e, "orientation bins");
+    return HB_OK;
+}
+
 HB_API hb_status hb_get_iteration(hb_ctx *c, int32_t *iter) {
     ENTER(c);
     CHKST(finish_pending(c));
@@ -1557,6 +1591,8 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
     if (n_iters < 1) return fail(c, HB_EINVAL, "n_iters must be >= 1");
     if (flags != 0) return fail(c, HB_EINVAL, "hb_forward_ckpt takes no flags");
     if (c->B > 16) return fail(c, HB_EINVAL, "the adjoint supports at most 16 groups");
+    if (c->P.directed_offset_px != 0.0f)
+        return fail(c, HB_EINVAL, "the adjoint does not differentiate directed_offset_px (set it to 0)");
     // earlier checkpoint buffers go back to the pool and are reused when large enough
     for (auto &k : c->ckpts) c->ckpt_pool.push_back(k);
     c->ckpts.clear();

@@ -3,6 +3,13 @@ import sys
 
 import pytest
 
+# torch first: libhb then binds to the HIP runtime that torch ships, so torch's device
+# tensors and streams are valid in the library's calls within one test process
+try:
+    import torch  # noqa: F401
+except ImportError:
+    pass
+
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)

@@ -41,6 +41,7 @@ def test_default_params_are_the_papers():
     ("box_passes", 0), ("box_passes", 9), ("lambda_", 0.0), ("lambda_", 1.5), ("eps", 0.0),
     ("max_halvings", -2), ("max_halvings", 31), ("smooth_weight", 1.5), ("smooth_passes", 2),
     ("capacity_factor", 1.05), ("h_max_px", float("inf")), ("struct_size", 4), ("n_radii", 0),
+    ("directed_offset_px", 4.5), ("directed_offset_px", -4.5), ("directed_offset_px", float("nan")),
 ])
 def test_invalid_params_rejected(field, value):
     p, keep = hb.make_params(64, 64, [3])
@@ -61,6 +62,14 @@ def test_build_module_is_reachable():
 def test_fixed_step_mode_accepted():
     p, keep = hb.make_params(64, 64, [3], max_halvings=-1)
     assert hb.hb_validate_params(p) == hb.HB_OK
+
+
+def test_directed_offset_range():
+    # |offset| <= max(W, H) / 16: 4 px on a 64 x 32 grid
+    for v in (0.0, 0.5, -4.0, 4.0):
+        p, keep = hb.make_params(64, 32, [3], directed_offset=v)
+        assert hb.hb_validate_params(p) == hb.HB_OK, v
+    assert hb.hb_default_params(64, 64).directed_offset_px == 0.0
 
 
 def test_radius_and_bbox_checks():
