@@ -60,6 +60,7 @@ def lib():
             "orc_resample_frozen": (None, [i64, P, P, P, P, P]),
             "orc_advect_frozen": (None, [i64, P, P, P, i32, i32, P, f64, P, f64, P]),
             "orc_splat": (None, [i64, P, P, P, P, i32, i32, i32, P]),
+            "orc_splat_strip": (None, [i64, P, P, P, P, i32, i32, i32, P]),
             "orc_box_brute": (None, [i32, i32, P, i32, P]),
             "orc_integral_image": (None, [i32, i32, P, P]),
             "orc_box_integral": (None, [i32, i32, P, i32, P]),
@@ -109,6 +110,7 @@ class Params:
     amb_tol: float = 1e-5       # decision margin treated as ambiguous in parity checks
     bbox: tuple = (0.0, 0.0, 1.0, 1.0)
     directed_offset: float = 0.0    # push of interior samples along the left normal (px)
+    strip_splat: bool = False       # histogram of the drawn line strips instead of the points
 
     def radius(self, it: int) -> int:
         return int(self.radii[min(it, len(self.radii) - 1)])
@@ -214,6 +216,19 @@ def splat(off, xy, group, B, W, H, weight=None):
     weight = None if weight is None else _c(weight, np.int32)
     hist = np.empty((B, H, W), np.int64)
     lib().orc_splat(off.shape[0] - 1, _p(off), _p(xy), _p(group), _p(weight), B, W, H, _p(hist))
+    return hist
+
+
+def splat_strip(off, xy, group, B, W, H, weight=None):
+    """Line-strip (rasterised) histogram: each polyline drawn through the pixels of its
+    points, every drawn pixel adding the edge weight (the paper's Bresenham drawing)."""
+    off = _c(off, np.int64)
+    xy = _c(xy, np.float64)
+    group = _c(group, np.int32)
+    weight = None if weight is None else _c(weight, np.int32)
+    hist = np.empty((B, H, W), np.int64)
+    lib().orc_splat_strip(off.shape[0] - 1, _p(off), _p(xy), _p(group), _p(weight), B, W, H,
+                          _p(hist))
     return hist
 
 
@@ -327,7 +342,10 @@ def iterate(off, xy, group, M, p: Params, it: int, weight=None, skip_resample=Fa
         s_xy = directed_offset(off, xy, s_off, seg, s_xy, p.directed_offset)
     else:
         s_off, s_xy, _ = resample(off, xy, p.delta)
-    hist = splat(s_off, s_xy, group, B, W, H, weight)
+    if p.strip_splat:
+        hist = splat_strip(s_off, s_xy, group, B, W, H, weight)
+    else:
+        hist = splat(s_off, s_xy, group, B, W, H, weight)
     S = box_chain(hist, p.passes, r)
     rho = density(S, r, p.a(), M)
     g = gradient(rho)
@@ -356,8 +374,8 @@ def run(node_xy, src, dst, group, M, p: Params, n_iters: int, weight=None):
 def record_run(off, xy, group, M, p: Params, n_iters: int, it0: int = 0, weight=None):
     """Base run from the polylines (off, xy): per iteration, the discrete choices that the
     frozen surrogate replays (sample offsets, segment indices, histograms, decisions)."""
-    if p.directed_offset != 0.0:
-        raise ValueError("the frozen surrogate does not include the directed offset")
+    if p.directed_offset != 0.0 or p.strip_splat:
+        raise ValueError("the frozen surrogate covers the point splat without a directed offset")
     rec = []
     off = _c(off, np.int64)
     xy = _c(xy, np.float64)

@@ -589,3 +589,106 @@ def test_orientation_matches_atan2_and_quarter_turns():
     turn = np.stack([-v[:, 1], v[:, 0]], 1)                  # +90 degrees, exact
     np.testing.assert_array_equal(O.orientation(turn), (got + 1) % 4)
     np.testing.assert_array_equal(O.orientation(-v), (got + 2) % 4)
+
+
+# ------------------------------------------------------------------ line-strip splat (Eq. 1 drawn)
+
+def _textbook_bresenham(x0, y0, x1, y1):
+    """All-octant integer Bresenham (error accumulator), both end pixels included."""
+    dx, dy = abs(x1 - x0), -abs(y1 - y0)
+    sx, sy = (1 if x0 < x1 else -1), (1 if y0 < y1 else -1)
+    err = dx + dy
+    pts = []
+    while True:
+        pts.append((x0, y0))
+        if x0 == x1 and y0 == y1:
+            return pts
+        e2 = 2 * err
+        if e2 >= dy:
+            err += dy
+            x0 += sx
+        if e2 <= dx:
+            err += dx
+            y0 += sy
+
+
+def _strip_pixels(p0, p1, W=64, H=64):
+    off = np.array([0, 2], np.int64)
+    xy = np.array([p0, p1], np.float64) + 0.5          # pixel centres
+    h = O.splat_strip(off, xy, np.zeros(1, np.int32), 1, W, H)[0]
+    v, u = np.nonzero(h)
+    return h, set(zip(u.tolist(), v.tolist()))
+
+
+def test_strip_segments_match_textbook_bresenham_without_ties():
+    g = rng(31)
+    checked = 0
+    for _ in range(400):
+        x0, y0, x1, y1 = (int(c) for c in g.integers(0, 64, 4))
+        n = max(abs(x1 - x0), abs(y1 - y0))
+        minor = abs(y1 - y0) if abs(x1 - x0) >= abs(y1 - y0) else abs(x1 - x0)
+        # a rounding tie: t * minor / n at exactly half an integer for some t
+        if n and any((2 * t * minor) % (2 * n) == n for t in range(n)):
+            continue
+        h, got = _strip_pixels((x0, y0), (x1, y1))
+        ref = _textbook_bresenham(x0, y0, x1, y1)
+        assert got == set(ref)
+        assert h.sum() == len(ref) == n + 1 and h.max() == 1
+        checked += 1
+    assert checked > 200
+
+
+def test_strip_is_connected_and_counts_each_drawn_pixel():
+    g = rng(32)
+    for _ in range(100):
+        x0, y0, x1, y1 = (int(c) for c in g.integers(0, 64, 4))
+        h, got = _strip_pixels((x0, y0), (x1, y1))
+        n = max(abs(x1 - x0), abs(y1 - y0))
+        assert h.sum() == n + 1 and (x0, y0) in got and (x1, y1) in got
+        # 8-connected digital line: one pixel per step of the major coordinate
+        major = 0 if abs(x1 - x0) >= abs(y1 - y0) else 1
+        coords = sorted(got, key=lambda q: q[major] * (1 if (x1 - x0, y1 - y0)[major] >= 0 else -1))
+        for a, b in zip(coords, coords[1:]):
+            assert abs(a[0] - b[0]) <= 1 and abs(a[1] - b[1]) <= 1 and abs(a[major] - b[major]) == 1
+
+
+def test_strip_mass_and_dominates_point_splat():
+    g = rng(33)
+    W, H, B, E = 48, 40, 3, 120
+    off, xy, group = _random_points(g, E, W, H, B)
+    weight = g.integers(1, 5, E).astype(np.int32)
+    hs = O.splat_strip(off, xy, group, B, W, H, weight)
+    hp = O.splat(off, xy, group, B, W, H, weight)
+    u = np.clip(np.floor(xy[:, 0]), 0, W - 1).astype(np.int64)
+    v = np.clip(np.floor(xy[:, 1]), 0, H - 1).astype(np.int64)
+    mass = 0
+    for e in range(E):
+        du, dv = np.diff(u[off[e]:off[e + 1]]), np.diff(v[off[e]:off[e + 1]])
+        mass += int(weight[e]) * (1 + int(np.maximum(np.abs(du), np.abs(dv)).sum()))
+    assert hs.sum() == mass
+    # every point's pixel is drawn (segments start on it, the strip ends on the last one);
+    # points sharing a pixel with their predecessor draw it once
+    E_ids = np.repeat(np.arange(E), np.diff(off))
+    first = np.ones(len(xy), bool)
+    same = (u[1:] == u[:-1]) & (v[1:] == v[:-1]) & (E_ids[1:] == E_ids[:-1])
+    first[1:] = ~same
+    hp_runs = np.zeros_like(hp)
+    np.add.at(hp_runs, (group[E_ids[first]], v[first], u[first]), weight[E_ids[first]])
+    assert (hs >= hp_runs).all()
+
+
+def test_strip_straight_row_closed_form():
+    off = np.array([0, 3], np.int64)
+    xy = np.array([[2.5, 7.25], [9.75, 7.5], [20.1, 7.9]])
+    h = O.splat_strip(off, xy, np.zeros(1, np.int32), 1, 32, 16)[0]
+    ref = np.zeros((16, 32), np.int64)
+    ref[7, 2:21] = 1
+    np.testing.assert_array_equal(h, ref)
+    # a fold: the strip goes right and back, so pixels between the turns count twice
+    xy2 = np.array([[2.5, 3.5], [10.5, 3.5], [5.5, 3.5]])
+    h2 = O.splat_strip(off, xy2, np.zeros(1, np.int32), 1, 32, 16)[0]
+    ref2 = np.zeros((16, 32), np.int64)
+    ref2[3, 2:11] += 1          # 2..9 from the first segment, 10 starts the second
+    ref2[3, 6:10] += 1          # 10 -> 6 drawn by the second segment (10 already counted)
+    ref2[3, 5] += 1             # the last point
+    np.testing.assert_array_equal(h2, ref2)
