@@ -83,6 +83,9 @@ enum {
     HB_MAP_GRAD = 3         /* float32 [H][W][2]: central-difference gradient of layer l */
 };
 
+/* splat modes (hb_params.splat_mode) */
+enum { HB_SPLAT_POINTS = 0, HB_SPLAT_STRIP = 1 };
+
 #define HB_MAX_GROUPS 64
 #define HB_MAX_PASSES 8
 #define HB_MAX_GRID 8192
@@ -126,6 +129,20 @@ typedef struct hb_params {
                                    0.5 % of the drawing). Not applied to samples given with
                                    HB_RUN_SAMPLES_GIVEN; not differentiated (hb_forward_ckpt
                                    requires 0). */
+    int32_t splat_mode;         /* what the histogram H of Eq. 1 counts. HB_SPLAT_POINTS
+                                   (default): every sample point adds the edge weight to the
+                                   pixel it falls in. HB_SPLAT_STRIP: the polyline is drawn as a
+                                   line strip through the pixels of its samples, as the paper's
+                                   implementation draws edges with Bresenham's algorithm
+                                   (Section 4): segment (x_j, x_j+1) draws the n = max(|du|,
+                                   |dv|) pixels (u0 + round(t du / n), v0 + round(t dv / n)),
+                                   t = 0..n-1, halves rounded up, the last sample its own pixel;
+                                   every drawn pixel adds the edge weight. The strip needs an
+                                   entry buffer of (ceil(delta_px + 2 |directed_offset_px|) + 2)
+                                   x 4 bytes per point of capacity; given polylines
+                                   (HB_RUN_SAMPLES_GIVEN) with much longer segments can exceed it
+                                   (HB_EOVERFLOW). Not differentiated (hb_forward_ckpt requires
+                                   HB_SPLAT_POINTS). */
 } hb_params;
 
 /* Fill p with the paper's defaults for a W x H grid: bbox [0,0,1,1], delta 1 px, P = 3,

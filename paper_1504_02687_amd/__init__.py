@@ -22,6 +22,7 @@ HB_DEVICE_PTRS = 1
 HB_RUN_SAMPLES_GIVEN, HB_RUN_RECORD_DECISIONS, HB_RUN_ASYNC, HB_RUN_GRAPH = 1, 2, 4, 8
 HB_POINTS_STATE, HB_POINTS_SAMPLES = 0, 1
 HB_MAP_HIST, HB_MAP_BOX, HB_MAP_DENSITY, HB_MAP_GRAD = 0, 1, 2, 3
+HB_SPLAT_POINTS, HB_SPLAT_STRIP = 0, 1
 HB_MAX_GROUPS, HB_MAX_PASSES = 64, 8
 HB_MAX_EDGE_WEIGHT = (1 << 20) - 1
 
@@ -55,6 +56,7 @@ class hb_params(ctypes.Structure):
         ("pass_weights", ctypes.POINTER(ctypes.c_float)),
         ("capacity_factor", ctypes.c_float),
         ("directed_offset_px", ctypes.c_float),
+        ("splat_mode", ctypes.c_int32),
     ]
 
 
@@ -355,7 +357,8 @@ def make_params(grid_w: int, grid_h: int, radii: Sequence[int], *, delta: float 
                 passes: int = 3, h_max: float = 0.0, lam: float = 0.9, eps: float = 1e-6,
                 max_halvings: int = 8, smooth_weight: float = 0.5,
                 pass_weights: Optional[Sequence[float]] = None, bbox=(0.0, 0.0, 1.0, 1.0),
-                capacity_factor: float = 2.0, directed_offset: float = 0.0):
+                capacity_factor: float = 2.0, directed_offset: float = 0.0,
+                splat_mode: int = 0):
     """hb_params plus the arrays it points to (keep both alive until hb_set_params)."""
     p = hb_default_params(grid_w, grid_h)
     r = (ctypes.c_int32 * len(radii))(*[int(v) for v in radii])
@@ -372,6 +375,7 @@ def make_params(grid_w: int, grid_h: int, radii: Sequence[int], *, delta: float 
         p.bbox[i] = bbox[i]
     p.capacity_factor = capacity_factor
     p.directed_offset_px = directed_offset
+    p.splat_mode = splat_mode
     keep = [r]
     if pass_weights is not None:
         a = (ctypes.c_float * passes)(*[float(v) for v in pass_weights])

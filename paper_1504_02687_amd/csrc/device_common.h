@@ -226,13 +226,23 @@ __device__ __forceinline__ double seg_len(float2 a, float2 b) {
 
 // Histogram tile (key) of a sample and its pixel inside the tile: the pixel the sample
 // falls in (floor of its coordinates), clamped to the grid.
-__device__ __forceinline__ void bin_of(const GDesc &d, int layer, float2 p, int &key,
-                                       uint32_t &local) {
-    const float fu = fminf(fmaxf(floorf(p.x), 0.0f), (float)(d.W - 1));
-    const float fv = fminf(fmaxf(floorf(p.y), 0.0f), (float)(d.H - 1));
-    const int u = (int)fu, v = (int)fv;
+__device__ __forceinline__ void pixel_of(float2 p, int W, int H, int &u, int &v) {
+    u = (int)fminf(fmaxf(floorf(p.x), 0.0f), (float)(W - 1));
+    v = (int)fminf(fmaxf(floorf(p.y), 0.0f), (float)(H - 1));
+}
+
+// Tile (key) of pixel (u, v) of a layer and the pixel's place inside the tile.
+__device__ __forceinline__ void tile_of(const GDesc &d, int layer, int u, int v, int &key,
+                                        uint32_t &local) {
     key = (layer * d.tiles_y + (v >> kTileShift)) * d.tiles_x + (u >> kTileShift);
     local = (uint32_t)(((v & (kTile - 1)) << kTileShift) | (u & (kTile - 1)));
+}
+
+__device__ __forceinline__ void bin_of(const GDesc &d, int layer, float2 p, int &key,
+                                       uint32_t &local) {
+    int u, v;
+    pixel_of(p, d.W, d.H, u, v);
+    tile_of(d, layer, u, v, key, local);
 }
 
 // Runs of equal keys among lanes 0..cnt-1 of a wave, which hold consecutive samples of one

@@ -14,7 +14,8 @@ enum : int32_t {
     ST_POINT_OVERFLOW = 1,   // the next sample set does not fit the point buffers
     ST_HIST_OVERFLOW = 2,    // counts could exceed int32 / int64 box sums could overflow
     ST_BIN_MISMATCH = 4,     // tile counts and binned samples disagree (internal error)
-    ST_STOP = ST_POINT_OVERFLOW | ST_HIST_OVERFLOW | ST_BIN_MISMATCH,
+    ST_ENTRY_OVERFLOW = 8,   // the drawn line strips need more entries than the entry buffer
+    ST_STOP = ST_POINT_OVERFLOW | ST_HIST_OVERFLOW | ST_BIN_MISMATCH | ST_ENTRY_OVERFLOW,
 };
 
 constexpr int kBlock = 256;            // threads per block of every kernel
@@ -73,6 +74,8 @@ struct GDesc {
     int32_t r, K, record, wmax;
     double h, eps, s, delta;
     double doff;                // directed offset of interior samples along the left normal
+    int32_t strip;              // 1: histogram of the drawn line strips (entries per pixel drawn)
+    int64_t ent_cap;            // capacity of bins, in entries (cap for the point splat)
     double a[HB_MAX_PASSES];    // density weight of each pass
     double ck[HB_MAX_PASSES];   // (2r+1)^(2k), k = 1..P
 
@@ -106,7 +109,7 @@ struct GDesc {
     int64_t *bin_cur;           // [n_sets][n_tiles] write cursors of the binning pass
     int64_t *tile_off;          // [n_tiles + 1] first entry of each tile
     int64_t *seg_off;           // [n_tiles + 1] first work item (kSegEntries entries) of each tile
-    uint32_t *bins;             // [cap] entries: pixel in tile | edge weight << kLocalBits
+    uint32_t *bins;             // [ent_cap] entries: pixel in tile | edge weight << kLocalBits
     uint32_t *bin_src;          // [cap] sample of each entry (runs that record it; else null)
     int64_t *box;               // [P][B][H][W]
     int64_t *tmp;               // [B][H][W] row-pass output
@@ -165,8 +168,11 @@ hipError_t launch_scan(const GDesc *desc, int ng, const Shape &tot, hipStream_t 
 hipError_t launch_resample_count(const GDesc *desc, int ng, const Shape &tot, int u,
                                  hipStream_t st);
 hipError_t launch_count_given(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
+// tile counts (scatter = false) or entries (scatter = true) of the drawn line strips
+hipError_t launch_strip_bins(const GDesc *desc, int ng, const Shape &tot, bool scatter,
+                             hipStream_t st);
 // tile offsets, binning of the samples and the tile histograms (three kernels)
-hipError_t launch_bin_hist(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
+hipError_t launch_bin_hist(const GDesc *desc, int ng, const Shape &tot, bool strip, hipStream_t st);
 hipError_t launch_clear_hist(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
 hipError_t launch_box_pass(const GDesc *desc, int ng, const Shape &tot, int max_w, int pass,
                            hipStream_t st);

@@ -188,7 +188,6 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
     int knext = 0;
     for (int j0 = 0; j0 < m - 1; j0 += 64 * U) {
         const int rem = m - 1 - j0;
-        const int nsegT = rem < 64 * U ? rem : 64 * U;
         float2 a[U], b[U];
         double incl[U];
         int ns[U];
@@ -277,10 +276,14 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
                 st2(q + k, out);
                 bin_of(d, layer, out, key, loc);
             }
-            const int cnt = kend - kb < 64 ? kend - kb : 64;
-            const uint64_t heads = run_heads(key, lane, cnt);
-            if ((heads >> lane) & 1ull)
-                atomicAdd((unsigned long long *)(ctr + key), (unsigned long long)run_length(heads, lane, cnt));
+            if (!d.strip) {
+                // the samples are counted in their tiles here; line strips are counted by
+                // k_strip_bins once every sample is known
+                const int cnt = kend - kb < 64 ? kend - kb : 64;
+                const uint64_t heads = run_heads(key, lane, cnt);
+                if ((heads >> lane) & 1ull)
+                    atomicAdd((unsigned long long *)(ctr + key), (unsigned long long)run_length(heads, lane, cnt));
+            }
         }
         __builtin_amdgcn_wave_barrier();
         knext = kend;
@@ -302,7 +305,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_samples(const GDesc *__restrict_
     const int lane = threadIdx.x & 63;
     const int64_t bl = blk - d.blk_edge;
     const int64_t e = edge_of(d, bl, wid);
-    if (e < 0) return;
+    if (e < 0 || d.strip) return;
     HB_G unsigned long long *ctr =
         glb((unsigned long long *)(SCATTER ? d.bin_cur : d.bin_cnt)) + (bl & (d.n_sets - 1)) * d.n_tiles;
     const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
@@ -344,12 +347,98 @@ __global__ __launch_bounds__(kBlock) void k_bin_samples(const GDesc *__restrict_
                 const unsigned long long b0 = __shfl(base[u], h, 64);
                 if (lane < cnt[u]) {
                     const unsigned long long pos = b0 + (unsigned long long)(lane - h);
-                    if (pos < (unsigned long long)d.cap) {
+                    if (pos < (unsigned long long)d.ent_cap) {
                         bins[pos] = loc[u] | wbits;
                         if (d.bin_src) d.bin_src[pos] = (uint32_t)(o0 + j0 + 64 * u + lane);
                     } else {
                         atomicOr(d.status, ST_BIN_MISMATCH);
                     }
+                }
+            }
+        }
+    }
+}
+
+// Line-strip splat (the rasterised drawing of Eq. 1): the polyline of each edge drawn
+// through the pixels of its samples, one wave per edge, 64 segments at a time. Lane k draws
+// segment (k, k+1): the n = max(|du|, |dv|) pixels (u0 + round(t du / n), v0 + round(t dv /
+// n)), t = 0 .. n-1, halves rounded up in exact integer arithmetic, and not its end pixel,
+// which starts the next segment; the last sample of the edge draws its own pixel. At each
+// step t the drawn pixels of the wave are counted in their tiles (SCATTER = false) or
+// written as entries (SCATTER = true) with one atomic per run of drawing lanes in one tile,
+// into the counter set of this block, as k_bin_samples does for samples.
+template <bool SCATTER>
+__global__ __launch_bounds__(kBlock) void k_strip_bins(const GDesc *__restrict__ gd, int ng) {
+    const int64_t blk = blockIdx.x;
+    HB_FIND(blk_edge);
+    if (stopped(d)) return;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t bl = blk - d.blk_edge;
+    const int64_t e = edge_of(d, bl, wid);
+    if (e < 0 || !d.strip) return;
+    HB_G unsigned long long *ctr =
+        glb((unsigned long long *)(SCATTER ? d.bin_cur : d.bin_cnt)) + (bl & (d.n_sets - 1)) * d.n_tiles;
+    const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
+    const int layer = d.group[e];
+    const uint32_t wbits = (uint32_t)(d.weight ? d.weight[e] : 1) << kLocalBits;
+    const HB_G float2 *__restrict__ xs = glb(d.samples + o0);
+    HB_G uint32_t *bins = glb(d.bins);
+    const int W = d.W, H = d.H;
+    const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));    // lanes < lane
+    for (int64_t j0 = 0; j0 < n; j0 += 64) {
+        const int64_t k = j0 + lane;
+        int u0 = 0, v0 = 0;
+        if (k < n) pixel_of(ld2(xs + k), W, H, u0, v0);
+        int u1 = lane_next(u0), v1 = lane_next(v0);
+        if (lane == 63 && k + 1 < n) pixel_of(ld2(xs + k + 1), W, H, u1, v1);
+        const int du = u1 - u0, dv = v1 - v0;
+        const int adu = du < 0 ? -du : du, adv = dv < 0 ? -dv : dv;
+        const int steps = adu > adv ? adu : adv;
+        const int npx = k + 1 < n ? steps : (k + 1 == n ? 1 : 0);
+        const int twon = 2 * steps;
+        for (int t = 0; __any(t < npx); ++t) {
+            const bool act = t < npx;
+            int key = -1;
+            uint32_t loc = 0;
+            if (act) {
+                int u = u0, v = v0;
+                if (k + 1 < n) {
+                    // floor((2 t du + n) / 2n) with a floor for negative numerators
+                    const int a = 2 * t * du + steps, b = 2 * t * dv + steps;
+                    const int qa = a >= 0 ? a / twon : -((-a + twon - 1) / twon);
+                    const int qb = b >= 0 ? b / twon : -((-b + twon - 1) / twon);
+                    u = u0 + qa;
+                    v = v0 + qb;
+                }
+                tile_of(d, layer, u, v, key, loc);
+            }
+            const uint64_t am = __ballot(act);
+            const uint64_t prev_m = am & below;
+            const int pl = prev_m ? 63 - __builtin_clzll(prev_m) : lane;
+            const int pkey = __shfl(key, pl, 64);
+            const bool head = act && (prev_m == 0 || pkey != key);
+            const uint64_t hm = __ballot(head);
+            // this lane's run: from the last head at or below it to the next head above it
+            const uint64_t upto = hm & (below | (1ull << lane));
+            const int h = upto ? 63 - __builtin_clzll(upto) : lane;
+            const uint64_t above = lane == 63 ? 0ull : (hm >> (lane + 1));
+            const int nxt = above ? lane + 1 + __builtin_ctzll(above) : 64;
+            unsigned long long base = 0;
+            if (head) {
+                const uint64_t span = (nxt >= 64 ? ~0ull : ((1ull << nxt) - 1)) & ~below;
+                const unsigned long long len = (unsigned long long)__builtin_popcountll(am & span);
+                unsigned long long *c = (unsigned long long *)(ctr + key);
+                if (SCATTER) base = atomicAdd(c, len);
+                else atomicAdd(c, len);
+            }
+            if (SCATTER) {
+                const unsigned long long b0 = __shfl(base, h, 64);
+                if (act) {
+                    const uint64_t before = am & below & ~(h == 0 ? 0ull : (~0ull >> (64 - h)));
+                    const unsigned long long pos = b0 + (unsigned long long)__builtin_popcountll(before);
+                    if (pos < (unsigned long long)d.ent_cap) bins[pos] = loc | wbits;
+                    else atomicOr(d.status, ST_BIN_MISMATCH);
                 }
             }
         }
@@ -389,7 +478,19 @@ __global__ __launch_bounds__(kBlock) void k_bin_scan(const GDesc *__restrict__ g
     if (threadIdx.x == 0) {
         d.tile_off[nt] = base_off;
         d.seg_off[nt] = base_seg;
-        if (base_off != d.off_s[d.n_edges] || base_off > d.cap) atomicOr(d.status, ST_BIN_MISMATCH);
+        if (d.strip) {
+            // one entry per drawn pixel: the buffer bound and the histogram ranges are checked
+            // here, on the actual count
+            int32_t st = 0;
+            if (base_off > d.ent_cap) st |= ST_ENTRY_OVERFLOW;
+            const double wsum = (double)base_off * (double)d.wmax;
+            double grow = 1.0;
+            for (int k = 1; k < d.P; ++k) grow *= (double)(2 * d.r + 1) * (double)(2 * d.r + 1);
+            if (wsum >= 4294967295.0 || wsum * grow >= 9.2e18) st |= ST_HIST_OVERFLOW;
+            if (st) atomicOr(d.status, st);
+        } else if (base_off != d.off_s[d.n_edges] || base_off > d.ent_cap) {
+            atomicOr(d.status, ST_BIN_MISMATCH);
+        }
     }
 }
 
@@ -951,11 +1052,23 @@ hipError_t launch_count_given(const GDesc *desc, int ng, const Shape &tot, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_bin_hist(const GDesc *desc, int ng, const Shape &tot, hipStream_t st) {
+hipError_t launch_strip_bins(const GDesc *desc, int ng, const Shape &tot, bool scatter,
+                             hipStream_t st) {
+    if (tot.edge <= 0) return hipSuccess;
+    if (scatter) hipLaunchKernelGGL(k_strip_bins<true>, grid_of(tot.edge), dim3(kBlock), 0, st, desc, ng);
+    else hipLaunchKernelGGL(k_strip_bins<false>, grid_of(tot.edge), dim3(kBlock), 0, st, desc, ng);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_hist(const GDesc *desc, int ng, const Shape &tot, bool strip, hipStream_t st) {
     if (ng <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_bin_scan, dim3((unsigned)ng), dim3(kBlock), 0, st, desc, ng);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || tot.edge <= 0) return e;
+    if (strip) {
+        hipLaunchKernelGGL(k_strip_bins<true>, grid_of(tot.edge), dim3(kBlock), 0, st, desc, ng);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
     hipLaunchKernelGGL(k_bin_samples<true>, grid_of(tot.edge), dim3(kBlock), 0, st, desc, ng);
     if ((e = hipGetLastError()) != hipSuccess || tot.tile <= 0) return e;
     hipLaunchKernelGGL(k_tile_hist, grid_of(tot.tile), dim3(kBlock), 0, st, desc, ng);

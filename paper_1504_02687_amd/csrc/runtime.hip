@@ -51,7 +51,8 @@ struct hb_ctx {
     float2 *pts[2] = {nullptr, nullptr};
     int64_t *off[2] = {nullptr, nullptr};
     int64_t cap = 0;
-    uint32_t *d_bins = nullptr;          // [cap] binned samples of the splat
+    uint32_t *d_bins = nullptr;          // [ent_cap] entries of the splat (samples or drawn pixels)
+    int64_t ent_cap = 0;
     uint32_t *d_binsrc = nullptr;        // [cap] sample of each binned entry (checkpointed runs)
     int64_t binsrc_cap = 0;
     int ps = 0, os = 0, ss = 0, so = 0;
@@ -245,6 +246,7 @@ HB_API void hb_default_params(hb_params *p, int32_t grid_w, int32_t grid_h) {
     p->pass_weights = nullptr;
     p->capacity_factor = 2.0f;
     p->directed_offset_px = 0.0f;
+    p->splat_mode = HB_SPLAT_POINTS;
 }
 
 static hb_status validate(hb_ctx *c, const hb_params *p) {
@@ -285,6 +287,8 @@ static hb_status validate(hb_ctx *c, const hb_params *p) {
     if (!std::isfinite(p->directed_offset_px) ||
         std::fabs(p->directed_offset_px) > (float)std::max(p->grid_w, p->grid_h) / 16.0f)
         return fail(c, HB_EINVAL, "directed_offset_px must be finite with |value| <= max(W, H) / 16");
+    if (p->splat_mode != HB_SPLAT_POINTS && p->splat_mode != HB_SPLAT_STRIP)
+        return fail(c, HB_EINVAL, "splat_mode must be HB_SPLAT_POINTS or HB_SPLAT_STRIP");
     return HB_OK;
 }
 
@@ -326,6 +330,24 @@ static hb_status ensure_desc(hb_ctx *c, size_t n) {
 }
 
 // Grow both point buffers to hold at least `need` points, keeping the state and samples.
+// Splat entries per point of capacity: 1 for the point splat; for the line strips, the
+// pixels a segment between consecutive samples can draw (its chord is at most the sample
+// spacing delta plus twice the directed offset, and at most one more pixel comes from the
+// pixel grid) plus one of margin.
+static int64_t entry_factor(const hb_ctx *c) {
+    if (c->P.splat_mode != HB_SPLAT_STRIP) return 1;
+    const double reach = (double)c->P.delta_px + 2.0 * std::fabs((double)c->P.directed_offset_px);
+    return (int64_t)std::ceil(reach) + 2;
+}
+
+static hb_status ensure_bins(hb_ctx *c) {
+    const int64_t need = c->cap * entry_factor(c);
+    if (need <= c->ent_cap && c->d_bins) return HB_OK;
+    CHKST(dalloc(c, &c->d_bins, (size_t)need, "splat entries"));
+    c->ent_cap = need;
+    return HB_OK;
+}
+
 static hb_status ensure_capacity(hb_ctx *c, int64_t need) {
     if (need <= c->cap) return HB_OK;
     int64_t ncap = std::max<int64_t>(need, c->cap + c->cap / 2);
@@ -341,7 +363,7 @@ static hb_status ensure_capacity(hb_ctx *c, int64_t need) {
     }
     uint32_t *nb = nullptr;
     {
-        hb_status s = dalloc(c, &nb, (size_t)ncap, "binned samples");
+        hb_status s = dalloc(c, &nb, (size_t)ncap * (size_t)entry_factor(c), "splat entries");
         if (s != HB_OK) {
             dfree(&np[0]);
             dfree(&np[1]);
@@ -361,6 +383,7 @@ static hb_status ensure_capacity(hb_ctx *c, int64_t need) {
     }
     dfree(&c->d_bins);
     c->d_bins = nb;
+    c->ent_cap = ncap * entry_factor(c);
     c->have_jacc = false;   // the decisions buffer is kept; it grows when a run records
     c->cap = ncap;
     return HB_OK;
@@ -410,6 +433,8 @@ static GDesc base_desc(const hb_ctx *c) {
     d.s = (double)c->P.smooth_weight;
     d.delta = (double)c->P.delta_px;
     d.doff = (double)c->P.directed_offset_px;
+    d.strip = c->P.splat_mode == HB_SPLAT_STRIP ? 1 : 0;
+    d.ent_cap = c->ent_cap;
     for (int k = 0; k < d.P; ++k)
         d.a[k] = c->passw.empty() ? (k == d.P - 1 ? 1.0 : 0.0) : (double)c->passw[k];
     d.group = c->d_group;
@@ -683,6 +708,9 @@ static hb_status upload(hb_ctx *c, T *dst, const std::vector<T> &src) {
 static const char *const kOverflowMsg =
     "sample count too large for int32 histograms or int64 box sums, or 2^31 samples or more "
     "on one edge";
+static const char *const kEntryMsg =
+    "the line strips draw more pixels than the entry buffer holds (given polylines with "
+    "segments much longer than delta_px)";
 
 // Error of a non-zero device status word (cleared on the device).
 static hb_status read_status(hb_ctx *c) {
@@ -693,6 +721,7 @@ static hb_status read_status(hb_ctx *c) {
     HIPCHK(c, hipMemcpy(c->d_status, &zero, sizeof zero, hipMemcpyHostToDevice));
     if (status & hb::ST_BIN_MISMATCH)
         return fail(c, HB_EINTERNAL, "binned samples disagree with the tile counts");
+    if (status & hb::ST_ENTRY_OVERFLOW) return fail(c, HB_EOVERFLOW, kEntryMsg);
     return fail(c, HB_EOVERFLOW, kOverflowMsg);
 }
 
@@ -916,6 +945,7 @@ static const uint32_t kRunRecordBins = 1u << 30;
 static hb_status prepare_ctx(hb_ctx *c, int T, uint32_t flags) {
     CHKST(ensure_order(c));
     CHKST(ensure_maps(c));
+    CHKST(ensure_bins(c));
     CHKST(ensure_totals(c, T));
     if ((flags & HB_RUN_RECORD_DECISIONS) && c->jacc_cap < c->cap) {
         CHKST(dalloc(c, &c->d_jacc, (size_t)c->cap, "decisions"));
@@ -952,6 +982,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
     std::vector<Shape> base((size_t)n);
     Shape tot{};
     int max_w = 2, bmax = 1, pmax = 1;
+    bool strip = false;      // some graph draws line strips: their kernels run too
     for (int g = 0; g < n; ++g) {
         const hb_ctx *c = cs[g];
         base[g] = tot;
@@ -959,6 +990,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
         max_w = std::max(max_w, c->P.grid_w);
         bmax = std::max(bmax, c->B);
         pmax = std::max(pmax, c->P.box_passes);
+        strip = strip || c->P.splat_mode == HB_SPLAT_STRIP;
     }
     const bool given0 = (flags & HB_RUN_SAMPLES_GIVEN) != 0;
     const bool record = (flags & HB_RUN_RECORD_DECISIONS) != 0;
@@ -1029,7 +1061,8 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
                 HIPCHK(c, hb::launch_clear_hist(dd, n, tot, c->stream));
                 if (given) HIPCHK(c, hb::launch_count_given(dd, n, tot, c->stream));
                 else HIPCHK(c, hb::launch_resample_count(dd, n, tot, ru, c->stream));
-                HIPCHK(c, hb::launch_bin_hist(dd, n, tot, c->stream));
+                if (strip) HIPCHK(c, hb::launch_strip_bins(dd, n, tot, false, c->stream));
+                HIPCHK(c, hb::launch_bin_hist(dd, n, tot, strip, c->stream));
                 for (int k = 0; k < pmax; ++k) HIPCHK(c, hb::launch_box_pass(dd, n, tot, max_w, k, c->stream));
                 HIPCHK(c, hb::launch_density_cells(dd, n, tot, bmax, c->stream));
                 HIPCHK(c, hb::launch_advect_smooth(dd, n, tot, au, c->stream));
@@ -1039,7 +1072,8 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
             STAGE(c, HB_STAGE_CLEAR, hb::launch_clear_hist(dd, n, tot, c->stream));
             if (given) STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_count_given(dd, n, tot, c->stream));
             else STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_resample_count(dd, n, tot, ru, c->stream));
-            STAGE(c, HB_STAGE_BIN, hb::launch_bin_hist(dd, n, tot, c->stream));
+            if (strip) STAGE(c, HB_STAGE_BIN, hb::launch_strip_bins(dd, n, tot, false, c->stream));
+            STAGE(c, HB_STAGE_BIN, hb::launch_bin_hist(dd, n, tot, strip, c->stream));
             for (int k = 0; k < pmax; ++k)
                 STAGE(c, HB_STAGE_BOX, hb::launch_box_pass(dd, n, tot, max_w, k, c->stream));
             STAGE(c, HB_STAGE_DENSITY_GRAD, hb::launch_density_cells(dd, n, tot, bmax, c->stream));
@@ -1055,7 +1089,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
     for (int g = 0; g < n; ++g) {
         const hb_ctx *c = cs[g];
         key.insert(key.end(), {(int64_t)(intptr_t)c, c->E, c->B, c->P.grid_w, c->P.grid_h,
-                               c->P.box_passes});
+                               c->P.box_passes, c->P.splat_mode});
     }
     if (!lead->gexec || key != lead->gkey) {
         if (lead->gexec) {
@@ -1144,6 +1178,8 @@ static hb_status finish_pending(hb_ctx *c) {
             return fail(c, HB_EINTERNAL, "binned samples disagree with the tile counts");
         if (status & hb::ST_HIST_OVERFLOW)
             return fail(c, HB_EOVERFLOW, kOverflowMsg);
+        if (status & hb::ST_ENTRY_OVERFLOW)
+            return fail(c, HB_EOVERFLOW, kEntryMsg);
         CHKST(ensure_capacity(c, 2 * need + 64));
         uint32_t flags = c->pend_flags & ~(uint32_t)(HB_RUN_ASYNC | HB_RUN_GRAPH);
         if (f > 0) flags &= ~(uint32_t)HB_RUN_SAMPLES_GIVEN;
@@ -1593,6 +1629,8 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
     if (c->B > 16) return fail(c, HB_EINVAL, "the adjoint supports at most 16 groups");
     if (c->P.directed_offset_px != 0.0f)
         return fail(c, HB_EINVAL, "the adjoint does not differentiate directed_offset_px (set it to 0)");
+    if (c->P.splat_mode != HB_SPLAT_POINTS)
+        return fail(c, HB_EINVAL, "the adjoint needs the point splat (splat_mode HB_SPLAT_POINTS)");
     // earlier checkpoint buffers go back to the pool and are reused when large enough
     for (auto &k : c->ckpts) c->ckpt_pool.push_back(k);
     c->ckpts.clear();
@@ -1688,7 +1726,7 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
         const GDesc *dd = c->d_desc;
         HIPCHK(c, hb::launch_clear_hist(dd, 1, sh, c->stream));
         HIPCHK(c, hb::launch_resample_count(dd, 1, sh, c->tune_ru, c->stream));
-        HIPCHK(c, hb::launch_bin_hist(dd, 1, sh, c->stream));
+        HIPCHK(c, hb::launch_bin_hist(dd, 1, sh, false, c->stream));
         for (int kp = 0; kp < c->P.box_passes; ++kp)
             HIPCHK(c, hb::launch_box_pass(dd, 1, sh, c->P.grid_w, kp, c->stream));
         HIPCHK(c, hb::launch_density_cells(dd, 1, sh, std::max(1, c->B), c->stream));
