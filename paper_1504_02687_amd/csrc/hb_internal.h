@@ -172,7 +172,9 @@ hipError_t launch_count_given(const GDesc *desc, int ng, const Shape &tot, hipSt
 hipError_t launch_strip_bins(const GDesc *desc, int ng, const Shape &tot, bool scatter,
                              hipStream_t st);
 // tile offsets, binning of the samples and the tile histograms (three kernels)
-hipError_t launch_bin_hist(const GDesc *desc, int ng, const Shape &tot, bool strip, hipStream_t st);
+// (strip / points: some graph of the batch uses the line-strip / the point splat)
+hipError_t launch_bin_hist(const GDesc *desc, int ng, const Shape &tot, bool strip, bool points,
+                           hipStream_t st);
 hipError_t launch_clear_hist(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
 hipError_t launch_box_pass(const GDesc *desc, int ng, const Shape &tot, int max_w, int pass,
                            hipStream_t st);

@@ -1060,7 +1060,8 @@ hipError_t launch_strip_bins(const GDesc *desc, int ng, const Shape &tot, bool s
     return hipGetLastError();
 }
 
-hipError_t launch_bin_hist(const GDesc *desc, int ng, const Shape &tot, bool strip, hipStream_t st) {
+hipError_t launch_bin_hist(const GDesc *desc, int ng, const Shape &tot, bool strip, bool points,
+                           hipStream_t st) {
     if (ng <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_bin_scan, dim3((unsigned)ng), dim3(kBlock), 0, st, desc, ng);
     hipError_t e = hipGetLastError();
@@ -1069,7 +1070,8 @@ hipError_t launch_bin_hist(const GDesc *desc, int ng, const Shape &tot, bool str
         hipLaunchKernelGGL(k_strip_bins<true>, grid_of(tot.edge), dim3(kBlock), 0, st, desc, ng);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_bin_samples<true>, grid_of(tot.edge), dim3(kBlock), 0, st, desc, ng);
+    if (points)
+        hipLaunchKernelGGL(k_bin_samples<true>, grid_of(tot.edge), dim3(kBlock), 0, st, desc, ng);
     if ((e = hipGetLastError()) != hipSuccess || tot.tile <= 0) return e;
     hipLaunchKernelGGL(k_tile_hist, grid_of(tot.tile), dim3(kBlock), 0, st, desc, ng);
     return hipGetLastError();

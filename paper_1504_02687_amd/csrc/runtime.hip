@@ -982,7 +982,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
     std::vector<Shape> base((size_t)n);
     Shape tot{};
     int max_w = 2, bmax = 1, pmax = 1;
-    bool strip = false;      // some graph draws line strips: their kernels run too
+    bool strip = false, points = false;   // graphs with line strips / with the point splat
     for (int g = 0; g < n; ++g) {
         const hb_ctx *c = cs[g];
         base[g] = tot;
@@ -991,6 +991,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
         bmax = std::max(bmax, c->B);
         pmax = std::max(pmax, c->P.box_passes);
         strip = strip || c->P.splat_mode == HB_SPLAT_STRIP;
+        points = points || c->P.splat_mode != HB_SPLAT_STRIP;
     }
     const bool given0 = (flags & HB_RUN_SAMPLES_GIVEN) != 0;
     const bool record = (flags & HB_RUN_RECORD_DECISIONS) != 0;
@@ -1062,7 +1063,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
                 if (given) HIPCHK(c, hb::launch_count_given(dd, n, tot, c->stream));
                 else HIPCHK(c, hb::launch_resample_count(dd, n, tot, ru, c->stream));
                 if (strip) HIPCHK(c, hb::launch_strip_bins(dd, n, tot, false, c->stream));
-                HIPCHK(c, hb::launch_bin_hist(dd, n, tot, strip, c->stream));
+                HIPCHK(c, hb::launch_bin_hist(dd, n, tot, strip, points, c->stream));
                 for (int k = 0; k < pmax; ++k) HIPCHK(c, hb::launch_box_pass(dd, n, tot, max_w, k, c->stream));
                 HIPCHK(c, hb::launch_density_cells(dd, n, tot, bmax, c->stream));
                 HIPCHK(c, hb::launch_advect_smooth(dd, n, tot, au, c->stream));
@@ -1073,7 +1074,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
             if (given) STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_count_given(dd, n, tot, c->stream));
             else STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_resample_count(dd, n, tot, ru, c->stream));
             if (strip) STAGE(c, HB_STAGE_BIN, hb::launch_strip_bins(dd, n, tot, false, c->stream));
-            STAGE(c, HB_STAGE_BIN, hb::launch_bin_hist(dd, n, tot, strip, c->stream));
+            STAGE(c, HB_STAGE_BIN, hb::launch_bin_hist(dd, n, tot, strip, points, c->stream));
             for (int k = 0; k < pmax; ++k)
                 STAGE(c, HB_STAGE_BOX, hb::launch_box_pass(dd, n, tot, max_w, k, c->stream));
             STAGE(c, HB_STAGE_DENSITY_GRAD, hb::launch_density_cells(dd, n, tot, bmax, c->stream));
@@ -1726,7 +1727,7 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
         const GDesc *dd = c->d_desc;
         HIPCHK(c, hb::launch_clear_hist(dd, 1, sh, c->stream));
         HIPCHK(c, hb::launch_resample_count(dd, 1, sh, c->tune_ru, c->stream));
-        HIPCHK(c, hb::launch_bin_hist(dd, 1, sh, false, c->stream));
+        HIPCHK(c, hb::launch_bin_hist(dd, 1, sh, false, true, c->stream));
         for (int kp = 0; kp < c->P.box_passes; ++kp)
             HIPCHK(c, hb::launch_box_pass(dd, 1, sh, c->P.grid_w, kp, c->stream));
         HIPCHK(c, hb::launch_density_cells(dd, 1, sh, std::max(1, c->B), c->stream));
