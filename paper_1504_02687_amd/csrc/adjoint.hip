@@ -366,6 +366,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
     HB_G float2 *pb = glb(d.adj_out + i0);
     const double nm1 = (double)(n - 1);
     const double ds = L / nm1;
+    const double inv_ds = 1.0 / ds;
 
     double Cbase = 0.0, Lbar = 0.0, carryP = 0.0;
     double carryBx = 0.0, carryBy = 0.0, carryVx = 0.0, carryVy = 0.0;
@@ -379,13 +380,15 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
         b.x = lane_next(a.x);
         b.y = lane_next(a.y);
         if (lane == 63 && nseg == 64) b = ld2(p + (j0 + 64));
-        const double ell = lane < nseg ? seg_len(a, b) : 0.0;
+        double ell, rcp;
+        seg_len_rcp(a, b, ell, rcp);
+        if (lane >= nseg) ell = 0.0;
         const double incl = wave_incl_scan<double>(ell, lane);
         const double excl = lane_prev(incl);
         // arclengths past the chunk's last segment read as +inf (no bound check in the search)
         sC[wid][lane] = lane < nseg ? Cbase + excl : __builtin_huge_val();
         if (lane < nseg) {
-            sR[wid][lane] = ell > 0.0 ? 1.0 / ell : 0.0;
+            sR[wid][lane] = rcp;
             sP[wid][lane] = a;
             for (int c = 0; c < 6; ++c) acc[wid][c][lane] = 0.0;
         }
@@ -400,7 +403,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict
         } else if (!(L > 0.0)) {
             kend = knext;
         } else {
-            const double kf = ceil(Cend / ds);
+            const double kf = ceil(Cend * inv_ds);     // corrected by the exact tests below
             int kk = kf < (double)knext ? knext : (kf > nm1 ? n - 1 : (int)kf);
             while (kk > knext && (double)(kk - 1) * ds >= Cend) --kk;
             while (kk < n - 1 && (double)kk * ds < Cend) ++kk;

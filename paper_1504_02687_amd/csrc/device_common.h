@@ -183,11 +183,13 @@ __device__ __forceinline__ int64_t block_excl_scan(int64_t v, int64_t *total) {
 // by group and position), which keeps its share of the density maps small enough for its
 // L2. Returns -1 past the last edge.
 __device__ __forceinline__ int64_t edge_of(const GDesc &d, int64_t blk_local, int wid) {
-    const int64_t nblk = (d.n_edges + kWavesPerBlock - 1) / kWavesPerBlock;
-    const int64_t nx = d.nxcd;
-    const int64_t x = blk_local % nx, i = blk_local / nx;
-    const int64_t q = nblk / nx, r = nblk % nx;
-    const int64_t c = x * q + (x < r ? x : r) + i;
+    // at most 2^31 edges (checked when the graph is set): block numbers fit 32 bits, and
+    // 32-bit divisions are far shorter than 64-bit ones
+    const uint32_t nblk = (uint32_t)((d.n_edges + kWavesPerBlock - 1) / kWavesPerBlock);
+    const uint32_t nx = (uint32_t)d.nxcd, b = (uint32_t)blk_local;
+    const uint32_t x = b % nx, i = b / nx;
+    const uint32_t q = nblk / nx, r = nblk % nx;
+    const int64_t c = (int64_t)x * q + (x < r ? x : r) + i;
     const int64_t idx = c * kWavesPerBlock + wid;
     if (idx >= d.n_edges) return -1;
     return d.perm ? (int64_t)d.perm[idx] : idx;
@@ -213,6 +215,21 @@ __device__ __forceinline__ double add_rn(double a, double b) {
 __device__ __forceinline__ double sub_rn(double a, double b) {
 #pragma clang fp contract(off)
     return a - b;
+}
+
+// Length of the segment (a, b) and its reciprocal (both 0 for a zero-length segment) for
+// the arclength walks of the resampling and its adjoint: the hardware reciprocal square root
+// refined by one Newton step in FP64 (relative error of order 1e-15, instead of a correctly
+// rounded square root and division). Sample counts come from seg_len below.
+__device__ __forceinline__ void seg_len_rcp(float2 a, float2 b, double &len, double &rcp) {
+    const double dx = sub_rn((double)b.x, (double)a.x), dy = sub_rn((double)b.y, (double)a.y);
+    const double q = __builtin_fma(dx, dx, mul_rn(dy, dy));
+    const double y0 = __builtin_amdgcn_rsq(q);
+    const double e = __builtin_fma(-mul_rn(q, y0), y0, 1.0);       // 1 - q y0^2
+    const double y1 = __builtin_fma(mul_rn(0.5, y0), e, y0);        // y0 (3 - q y0^2) / 2
+    const bool pos = q > 0.0;
+    len = pos ? mul_rn(q, y1) : 0.0;
+    rcp = pos ? y1 : 0.0;
 }
 
 // Explicit roundings (no contraction choices left to the compiler), so that every kernel

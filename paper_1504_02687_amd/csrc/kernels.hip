@@ -182,6 +182,7 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
         glb((unsigned long long *)d.bin_cnt) + (bl & (d.n_sets - 1)) * d.n_tiles;
     const double nm1 = (double)(n - 1);
     const double ds = L / nm1;          // arclength between consecutive samples
+    const double inv_ds = 1.0 / ds;
     const double doff = d.doff;
 
     double Cbase = 0.0;
@@ -204,9 +205,12 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
             b[u].y = lane_next(a[u].y);
             if (lane == 63 && ns[u] == 64) b[u] = ld2(p + (j0 + 64 * u + 64));
         }
-        double ell[U];
+        double ell[U], rcp[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) ell[u] = lane < ns[u] ? seg_len(a[u], b[u]) : 0.0;
+        for (int u = 0; u < U; ++u) {
+            seg_len_rcp(a[u], b[u], ell[u], rcp[u]);
+            if (lane >= ns[u]) ell[u] = 0.0;
+        }
 #pragma unroll
         for (int u = 0; u < U; ++u) incl[u] = wave_incl_scan<double>(ell[u], lane);
         double cb = Cbase;
@@ -217,7 +221,7 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
             // bound check
             sC[wid][64 * u + lane] = lane < ns[u] ? cb + excl : __builtin_huge_val();
             if (lane < ns[u]) {
-                sR[wid][64 * u + lane] = ell[u] > 0.0 ? 1.0 / ell[u] : 0.0;
+                sR[wid][64 * u + lane] = rcp[u];
                 sP[wid][64 * u + lane] = a[u];
             }
             if (lane == ns[u] - 1) sP[wid][64 * u + ns[u]] = b[u];
@@ -233,7 +237,7 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
         } else if (!(L > 0.0)) {
             kend = knext;
         } else {
-            const double kf = ceil(Cend / ds);
+            const double kf = ceil(Cend * inv_ds);     // corrected by the exact tests below
             int kk = kf < (double)knext ? knext : (kf > nm1 ? n - 1 : (int)kf);
             while (kk > knext && (double)(kk - 1) * ds >= Cend) --kk;
             while (kk < n - 1 && (double)kk * ds < Cend) ++kk;
@@ -758,6 +762,12 @@ __global__ __launch_bounds__(kBlock) void k_cells(const GDesc *__restrict__ gd, 
 
 // ---------------------------------------------------------------- advection + smoothing
 
+// Step halvings tested per round of the advection (candidates loaded together).
+#ifndef HB_TRIES_PER_ROUND
+#define HB_TRIES_PER_ROUND 2
+#endif
+constexpr int kTriesPerRound = HB_TRIES_PER_ROUND;
+
 // One wave per edge. Each trip handles U sub-chunks of 62 output points with a one-point
 // halo on each side (U independent gather chains in flight): lane l of sub-chunk u
 // advects point j0 + 62u - 1 + l (end points stay), neighbours come from lanes l-1 and l+1,
@@ -845,36 +855,48 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
                 act[u] = false;
             }
         }
-        // acceptance tests in FP32 (the loads of all sub-chunks issued before any test);
-        // the accepted point is recomputed in FP64
+        // acceptance tests in FP32, kTriesPerRound halvings per round: the candidates of a
+        // round are loaded together (all sub-chunks too) and the first accepted one in order
+        // wins, so the decisions are those of testing one halving after the other, with
+        // fewer dependent round trips to memory; the accepted point is recomputed in FP64
         float mf = (float)h;
-        for (int k = 0; k <= K; ++k) {
+        for (int k = 0; k <= K; k += kTriesPerRound) {
             bool any = false;
 #pragma unroll
             for (int u = 0; u < U; ++u) any |= act[u];
             if (!__any(any)) break;
-            Cell c[U];
-            Quad q[U];
+            Cell c[kTriesPerRound][U];
+            Quad q[kTriesPerRound][U];
+            float mt = mf;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const float cx = __builtin_amdgcn_fmed3f(__builtin_fmaf(mf, dx[u], x[u].x), 0.0f, xmaxf);
-                const float cy = __builtin_amdgcn_fmed3f(__builtin_fmaf(mf, dy[u], x[u].y), 0.0f, ymaxf);
-                c[u] = cell_of(cx, cy, W, H);
+            for (int i = 0; i < kTriesPerRound; ++i) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const float cx = __builtin_amdgcn_fmed3f(__builtin_fmaf(mt, dx[u], x[u].x), 0.0f, xmaxf);
+                    const float cy = __builtin_amdgcn_fmed3f(__builtin_fmaf(mt, dy[u], x[u].y), 0.0f, ymaxf);
+                    c[i][u] = cell_of(cx, cy, W, H);
+                }
+                mt *= 0.5f;
             }
 #pragma unroll
-            for (int u = 0; u < U; ++u)
-                if (act[u]) q[u] = ldq(rho, c[u].c);
+            for (int i = 0; i < kTriesPerRound; ++i)
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (act[u] && interp1q(q[u], c[u]) >= r0[u]) {
-                    jj[u] = k;
-                    act[u] = false;
+                for (int u = 0; u < U; ++u)
+                    if (act[u] && k + i <= K) q[i][u] = ldq(rho, c[i][u].c);
+#pragma unroll
+            for (int i = 0; i < kTriesPerRound; ++i) {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (act[u] && k + i <= K && interp1q(q[i][u], c[i][u]) >= r0[u]) {
+                        jj[u] = k + i;
+                        act[u] = false;
+                    }
                 }
             }
-            // no load of this trip is left in flight (a lane that skipped its test skipped
-            // the wait as well): the next trip's loads then go out without waiting
+            // no load of this round is left in flight (a lane that skipped its test skipped
+            // the wait as well): the next round's loads then go out without waiting
             vm_wait_all();
-            mf *= 0.5f;
+            mf = mt;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
