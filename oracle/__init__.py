@@ -72,6 +72,12 @@ def lib():
                                   P, P, P, P, P]),
             "orc_laplacian": (None, [i64, P, P, f64, i32, P]),
             "orc_ink": (f64, [i64, P, P]),
+            "orc_sqdist": (f64, [P, P, i32]),
+            "orc_kmeans": (i32, [i64, i32, P, i32, P, i32, P, P]),
+            "orc_davies_bouldin": (f64, [i64, i32, P, i32, P]),
+            "orc_draw": (ctypes.c_uint64, [ctypes.c_uint64, i32, i32, i64]),
+            "orc_init_indices": (None, [ctypes.c_uint64, i32, i32, i64, P]),
+            "orc_choose_groups": (i32, [i64, i32, P, i32, i32, i32, ctypes.c_uint64, i32, P, P]),
         }
         for name, (res, args) in sig.items():
             fn = getattr(L, name)
@@ -321,6 +327,65 @@ def ink(off, xy) -> float:
     off = _c(off, np.int64)
     xy = _c(xy, np.float64)
     return float(lib().orc_ink(off.shape[0] - 1, _p(off), _p(xy)))
+
+
+# ----------------------------------------------------------------------- grouping (Section 5)
+
+def edge_features(node_xy, src, dst, p: "Params", kind: str):
+    """Per-edge features in grid (pixel) units, FP32: "origin" (x_s, y_s), "destination"
+    (x_t, y_t), "od" (x_s, y_s, x_t, y_t) or "length" (|x_t - x_s|)."""
+    _, xy = initial_state(node_xy, src, dst, p)
+    xy = xy.astype(np.float32)
+    a, b = xy[0::2], xy[1::2]
+    if kind == "origin":
+        return np.ascontiguousarray(a)
+    if kind == "destination":
+        return np.ascontiguousarray(b)
+    if kind == "od":
+        return np.ascontiguousarray(np.concatenate([a, b], 1))
+    if kind == "length":
+        d = b.astype(np.float64) - a.astype(np.float64)
+        return np.sqrt(d[:, 0] * d[:, 0] + d[:, 1] * d[:, 1]).astype(np.float32)[:, None]
+    raise ValueError(kind)
+
+
+def kmeans(X, centers, max_iters=100):
+    """Lloyd's k-means from the given centres (FP64); returns labels, centres, inertia, rounds."""
+    X = _c(X, np.float32)
+    n, dim = X.shape
+    cen = np.array(centers, dtype=np.float64, order="C", copy=True)
+    k = cen.shape[0]
+    labels = np.empty(n, np.int32)
+    inertia = ctypes.c_double()
+    rounds = lib().orc_kmeans(n, dim, _p(X), k, _p(cen), max_iters, _p(labels), ctypes.byref(inertia))
+    return labels, cen, float(inertia.value), int(rounds)
+
+
+def davies_bouldin(X, labels, k):
+    X = _c(X, np.float32)
+    labels = _c(labels, np.int32)
+    return float(lib().orc_davies_bouldin(X.shape[0], X.shape[1], _p(X), int(k), _p(labels)))
+
+
+def draw(seed, B, r, t):
+    return int(lib().orc_draw(seed, B, r, t))
+
+
+def init_indices(seed, k, r, n):
+    idx = np.empty(k, np.int64)
+    lib().orc_init_indices(seed, k, r, n, _p(idx))
+    return idx
+
+
+def choose_groups(X, kmin=4, kmax=16, restarts=100, seed=0, max_iters=100):
+    """B in [kmin, kmax] of the lowest Davies-Bouldin index (Section 5); returns (B, labels,
+    db per B)."""
+    X = _c(X, np.float32)
+    n, dim = X.shape
+    labels = np.empty(n, np.int32)
+    db = np.empty(kmax - kmin + 1, np.float64)
+    B = lib().orc_choose_groups(n, dim, _p(X), kmin, kmax, restarts, seed, max_iters, _p(labels), _p(db))
+    return int(B), labels, db
 
 
 # ----------------------------------------------------------------------- iteration

@@ -609,3 +609,179 @@ EXPORT double orc_ink(int64_t E, const int64_t *off, const double *xy) {
     for (int64_t e = 0; e < E; ++e) total += orc_polyline_length(xy + 2 * off[e], off[e + 1] - off[e]);
     return total;
 }
+
+/* ------------------------------------------------ grouping (Sec. 5)
+ * Bins can be found by k-means clustering of an edge property (origin, destination, both,
+ * or the origin-destination distance) with the Euclidean distance, the number of bins B
+ * being the one between 4 and 16 with the lowest Davies-Bouldin index, with k-means run
+ * from several random initialisations for every B.
+ * Reading: Lloyd's algorithm from k given centres. A point goes to its nearest centre by
+ * the squared distance sum_j (x_j - c_j)^2, summed over the coordinates in order in FP64
+ * (ties to the lower index); each centre moves to the mean of its points (a centre left
+ * without points stays); this repeats until no label changes, or for max_iters rounds.
+ * Inertia = sum of the squared distances to the assigned centres. Of the restarts of one B
+ * the run of lowest inertia is kept (the first one on a tie). The random initialisations
+ * take k distinct points, drawn with a counter-based SplitMix64 stream (orc_draw).
+ * Davies-Bouldin index: with s_i the mean distance of the points of cluster i to its
+ * centroid (the mean of its points) and d_ij the distance between centroids, the mean over
+ * the non-empty clusters i of max over j != i of (s_i + s_j) / d_ij (a pair of coincident
+ * centroids counts 0); one cluster or none gives 0.
+ * Pins: scikit-learn's Lloyd k-means from the same centres (labels, centres, inertia) and
+ * its Davies-Bouldin score, brute force on tiny inputs, invariance under point order.
+ */
+EXPORT double orc_sqdist(const float *x, const double *c, int32_t dim) {
+    double s = 0.0;
+    for (int32_t j = 0; j < dim; ++j) {
+        double t = (double)x[j] - c[j];
+        s += t * t;
+    }
+    return s;
+}
+
+/* Lloyd iterations; centers [k][dim] are the starting centres on entry and the final ones on
+ * exit. Returns the number of assignment rounds made. */
+EXPORT int32_t orc_kmeans(int64_t n, int32_t dim, const float *X, int32_t k, double *centers,
+                          int32_t max_iters, int32_t *labels, double *inertia) {
+    double *sum = (double *)calloc((size_t)k * (size_t)dim, sizeof(double));
+    int64_t *cnt = (int64_t *)calloc((size_t)k, sizeof(int64_t));
+    int32_t rounds = 0;
+    for (int64_t i = 0; i < n; ++i) labels[i] = -1;
+    for (int32_t it = 0; it < max_iters; ++it) {
+        int64_t changed = 0;
+        double in = 0.0;
+        for (int64_t i = 0; i < n; ++i) {
+            int32_t best = 0;
+            double bd = orc_sqdist(X + i * dim, centers, dim);
+            for (int32_t c = 1; c < k; ++c) {
+                double dd = orc_sqdist(X + i * dim, centers + (int64_t)c * dim, dim);
+                if (dd < bd) {
+                    bd = dd;
+                    best = c;
+                }
+            }
+            if (labels[i] != best) ++changed;
+            labels[i] = best;
+            in += bd;
+        }
+        rounds = it + 1;
+        *inertia = in;
+        if (changed == 0) break;
+        memset(sum, 0, sizeof(double) * (size_t)k * (size_t)dim);
+        memset(cnt, 0, sizeof(int64_t) * (size_t)k);
+        for (int64_t i = 0; i < n; ++i) {
+            for (int32_t j = 0; j < dim; ++j) sum[(int64_t)labels[i] * dim + j] += (double)X[i * dim + j];
+            cnt[labels[i]] += 1;
+        }
+        for (int32_t c = 0; c < k; ++c)
+            if (cnt[c] > 0)
+                for (int32_t j = 0; j < dim; ++j) centers[(int64_t)c * dim + j] = sum[(int64_t)c * dim + j] / (double)cnt[c];
+        if (it + 1 == max_iters) {
+            /* the inertia of the final centres */
+            in = 0.0;
+            for (int64_t i = 0; i < n; ++i) in += orc_sqdist(X + i * dim, centers + (int64_t)labels[i] * dim, dim);
+            *inertia = in;
+        }
+    }
+    free(sum);
+    free(cnt);
+    return rounds;
+}
+
+EXPORT double orc_davies_bouldin(int64_t n, int32_t dim, const float *X, int32_t k, const int32_t *labels) {
+    double *cen = (double *)calloc((size_t)k * (size_t)dim, sizeof(double));
+    double *s = (double *)calloc((size_t)k, sizeof(double));
+    int64_t *cnt = (int64_t *)calloc((size_t)k, sizeof(int64_t));
+    for (int64_t i = 0; i < n; ++i) {
+        for (int32_t j = 0; j < dim; ++j) cen[(int64_t)labels[i] * dim + j] += (double)X[i * dim + j];
+        cnt[labels[i]] += 1;
+    }
+    for (int32_t c = 0; c < k; ++c)
+        if (cnt[c] > 0)
+            for (int32_t j = 0; j < dim; ++j) cen[(int64_t)c * dim + j] /= (double)cnt[c];
+    for (int64_t i = 0; i < n; ++i) s[labels[i]] += sqrt(orc_sqdist(X + i * dim, cen + (int64_t)labels[i] * dim, dim));
+    int32_t used = 0;
+    double total = 0.0;
+    for (int32_t a = 0; a < k; ++a) {
+        if (cnt[a] == 0) continue;
+        ++used;
+        double worst = 0.0;
+        for (int32_t b = 0; b < k; ++b) {
+            if (b == a || cnt[b] == 0) continue;
+            double d2 = 0.0;
+            for (int32_t j = 0; j < dim; ++j) {
+                double t = cen[(int64_t)a * dim + j] - cen[(int64_t)b * dim + j];
+                d2 += t * t;
+            }
+            double d = sqrt(d2);
+            double r = d > 0.0 ? (s[a] / (double)cnt[a] + s[b] / (double)cnt[b]) / d : 0.0;
+            if (r > worst) worst = r;
+        }
+        total += worst;
+    }
+    free(cen);
+    free(s);
+    free(cnt);
+    return used > 1 ? total / (double)used : 0.0;
+}
+
+/* SplitMix64 (Steele, Lea and Flood, 2014) as a counter-based stream: value t of stream
+ * (seed, B, r) is the SplitMix64 output mix of seed + gamma * (1 + t + 4096 (r + 1024 B)),
+ * gamma = 0x9E3779B97F4A7C15. */
+EXPORT uint64_t orc_draw(uint64_t seed, int32_t B, int32_t r, int64_t t) {
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(1 + t + 4096 * ((int64_t)r + 1024 * (int64_t)B));
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+/* k distinct point indices of restart r for B = k: the values t = 0, 1, ... of stream
+ * (seed, k, r) taken modulo n, skipping repeats (n >= k). */
+EXPORT void orc_init_indices(uint64_t seed, int32_t k, int32_t r, int64_t n, int64_t *idx) {
+    int32_t got = 0;
+    for (int64_t t = 0; got < k; ++t) {
+        int64_t v = (int64_t)(orc_draw(seed, k, r, t) % (uint64_t)n);
+        int32_t dup = 0;
+        for (int32_t q = 0; q < got; ++q) dup |= idx[q] == v;
+        if (!dup) idx[got++] = v;
+    }
+}
+
+/* For every B in [kmin, kmax]: `restarts` k-means runs from orc_init_indices, the lowest
+ * inertia kept, its Davies-Bouldin index in db[B - kmin]; returns the B of the lowest index
+ * (the smallest B on a tie) and its labels. */
+EXPORT int32_t orc_choose_groups(int64_t n, int32_t dim, const float *X, int32_t kmin, int32_t kmax,
+                                 int32_t restarts, uint64_t seed, int32_t max_iters,
+                                 int32_t *labels, double *db) {
+    int32_t *lab = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    int32_t *best_lab = (int32_t *)malloc(sizeof(int32_t) * (size_t)n);
+    double *cen = (double *)malloc(sizeof(double) * (size_t)kmax * (size_t)dim);
+    int64_t *idx = (int64_t *)malloc(sizeof(int64_t) * (size_t)kmax);
+    int32_t chosen = kmin;
+    double chosen_db = 0.0;
+    for (int32_t k = kmin; k <= kmax; ++k) {
+        double best_in = 0.0;
+        for (int32_t r = 0; r < restarts; ++r) {
+            orc_init_indices(seed, k, r, n, idx);
+            for (int32_t c = 0; c < k; ++c)
+                for (int32_t j = 0; j < dim; ++j) cen[(int64_t)c * dim + j] = (double)X[idx[c] * dim + j];
+            double in = 0.0;
+            orc_kmeans(n, dim, X, k, cen, max_iters, lab, &in);
+            if (r == 0 || in < best_in) {
+                best_in = in;
+                memcpy(best_lab, lab, sizeof(int32_t) * (size_t)n);
+            }
+        }
+        double d = orc_davies_bouldin(n, dim, X, k, best_lab);
+        db[k - kmin] = d;
+        if (k == kmin || d < chosen_db) {
+            chosen_db = d;
+            chosen = k;
+            memcpy(labels, best_lab, sizeof(int32_t) * (size_t)n);
+        }
+    }
+    free(lab);
+    free(best_lab);
+    free(cen);
+    free(idx);
+    return chosen;
+}

@@ -692,3 +692,70 @@ def test_strip_straight_row_closed_form():
     ref2[3, 6:10] += 1          # 10 -> 6 drawn by the second segment (10 already counted)
     ref2[3, 5] += 1             # the last point
     np.testing.assert_array_equal(h2, ref2)
+
+
+# ------------------------------------------------------------------ grouping (Sec. 5)
+
+def _blobs(seed, k, n_per, dim, spread=0.02):
+    g = rng(seed)
+    centres = g.uniform(0.1, 0.9, (k, dim))
+    X = np.concatenate([c + spread * g.normal(size=(n_per, dim)) for c in centres])
+    return X[g.permutation(len(X))].astype(np.float32)
+
+
+@pytest.mark.parametrize("k,dim,seed", [(4, 2, 41), (8, 4, 42), (5, 1, 43)])
+def test_kmeans_matches_sklearn_lloyd(k, dim, seed):
+    import sklearn.cluster
+    X = _blobs(seed, k + 2, 300, dim, spread=0.05)
+    init = X[O.init_indices(seed, k, 0, len(X))].astype(np.float64)
+    labels, cen, inertia, rounds = O.kmeans(X, init, max_iters=300)
+    km = sklearn.cluster.KMeans(n_clusters=k, init=init, n_init=1, algorithm="lloyd",
+                                max_iter=300, tol=0.0).fit(X.astype(np.float64))
+    assert rounds < 300
+    np.testing.assert_array_equal(labels, km.labels_)
+    np.testing.assert_allclose(cen, km.cluster_centers_, rtol=1e-10, atol=1e-12)
+    assert abs(inertia - km.inertia_) <= 1e-9 * km.inertia_
+
+
+def test_kmeans_fixed_point_and_permutation():
+    X = _blobs(44, 6, 120, 2, spread=0.08)
+    init = X[:6].astype(np.float64)
+    labels, cen, inertia, _ = O.kmeans(X, init, max_iters=500)
+    # a converged Lloyd run: every point is nearest to its own centre, every centre the mean
+    d = ((X[:, None, :].astype(np.float64) - cen[None]) ** 2).sum(2)
+    np.testing.assert_array_equal(labels, d.argmin(1))
+    for c in range(6):
+        np.testing.assert_allclose(cen[c], X[labels == c].astype(np.float64).mean(0), rtol=1e-12)
+    assert abs(inertia - d.min(1).sum()) <= 1e-12 * inertia
+    perm = rng(45).permutation(len(X))
+    l2, c2, i2, _ = O.kmeans(X[perm], init, max_iters=500)
+    np.testing.assert_array_equal(l2, labels[perm])
+    np.testing.assert_allclose(c2, cen, rtol=1e-12)
+
+
+@pytest.mark.parametrize("k,dim,seed", [(3, 2, 46), (7, 4, 47)])
+def test_davies_bouldin_matches_sklearn(k, dim, seed):
+    import sklearn.metrics
+    X = _blobs(seed, k, 200, dim, spread=0.07)
+    labels = rng(seed).integers(0, k, len(X)).astype(np.int32)
+    ref = sklearn.metrics.davies_bouldin_score(X.astype(np.float64), labels)
+    assert abs(O.davies_bouldin(X, labels, k) - ref) <= 1e-10 * ref
+    l, _, _, _ = O.kmeans(X, X[O.init_indices(seed, k, 0, len(X))], max_iters=300)
+    ref = sklearn.metrics.davies_bouldin_score(X.astype(np.float64), l)
+    assert abs(O.davies_bouldin(X, l, k) - ref) <= 1e-10 * ref
+
+
+def test_draw_is_splitmix64_and_init_indices_distinct():
+    # SplitMix64 reference values: the published generator seeded with 0 (state advanced by
+    # the golden gamma before each output) produces these first outputs
+    ref = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
+    assert [O.draw(0, 0, -1, 4096 + t) for t in range(3)] == ref
+    idx = O.init_indices(123, 16, 7, 20)
+    assert len(set(idx.tolist())) == 16 and idx.min() >= 0 and idx.max() < 20
+
+
+def test_choose_groups_finds_separated_blobs():
+    X = _blobs(48, 6, 150, 2, spread=0.01)
+    B, labels, db = O.choose_groups(X, kmin=4, kmax=9, restarts=100, seed=3, max_iters=200)
+    assert B == 6
+    assert db.argmin() == 6 - 4 and len(np.unique(labels)) == 6
