@@ -177,6 +177,10 @@ def main():
                          "histogram concentration of both (one JSON line)")
     ap.add_argument("--splat", choices=("points", "strip"), default="points",
                     help="histogram of the sample points (default) or of the drawn line strips")
+    ap.add_argument("--grouping", action="store_true",
+                    help="measure the grouping step instead: k-means on the origin-destination "
+                         "features of the edges and the choice of B (one JSON line)")
+    ap.add_argument("--restarts", type=int, default=10, help="k-means restarts per B (--grouping)")
     ap.add_argument("--batch-graphs", type=int, default=64)
     ap.add_argument("--batch-emax", type=float, default=1e5)
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -199,6 +203,9 @@ def main():
         return
     if args.convergence > 0:
         convergence_main(args)
+        return
+    if args.grouping:
+        grouping_main(args)
         return
 
     import numpy as np
@@ -310,6 +317,64 @@ def main():
         "fwd_bwd": fwd_bwd,
     }
     print(json.dumps(out), flush=True)
+
+
+def grouping_main(args):
+    """Grouping (Section 5) on the origin-destination features of the measured workload:
+    Lloyd rounds per second for k = 8 from one SplitMix64 start, HBM roofline of a round
+    (algorithmic bytes: the points read, the labels read and written: 4 dim + 8 bytes per
+    point), then the whole choice of B in [4, 16] with --restarts starts per B; the oracle's
+    Lloyd rounds timed on a sample of the points beside it."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    import paper_1504_02687_amd as hb
+    import workloads
+
+    torch.cuda.set_device(0)
+    w = workloads.stack3d(n_edges=args.edges, grid=args.grid, groups=args.groups)
+    b = hb.Bundler(0)
+    b.set_workload(w, capacity_factor=1.1)
+    X = b.edge_features(hb.HB_FEAT_ORIGIN_DESTINATION)
+    Xd = torch.from_numpy(X).cuda()
+    n, dim = X.shape
+    k = 8
+    init = X[O.init_indices(1, k, 0, n)].astype(np.float64)
+    b.kmeans(Xd, init, max_iters=3)                      # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lab, cen, inertia, rounds = b.kmeans(Xd, init, max_iters=60)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    rate = n * rounds / dt
+    gbs = (4 * dim + 8) * n * rounds / dt / 1e9
+    log(f"k-means k={k}: {rounds} rounds in {dt * 1e3:.1f} ms, {rate / 1e9:.2f} G point-rounds/s, {gbs:.0f} GB/s")
+    t0 = time.perf_counter()
+    B, labels, db = b.choose_groups(Xd, 4, 16, args.restarts, 1, 60)
+    torch.cuda.synchronize()
+    dt_choose = time.perf_counter() - t0
+    log(f"choice of B in [4, 16], {args.restarts} starts each: B = {B} in {dt_choose:.2f} s")
+    b.close()
+    step = 20
+    Xs = np.ascontiguousarray(X[::step])
+    t0 = time.perf_counter()
+    _, _, _, r_cpu = O.kmeans(Xs, init, max_iters=min(rounds, 20))
+    dt_cpu = time.perf_counter() - t0
+    cpu = {"value": len(Xs) * r_cpu / dt_cpu, "unit": "point-rounds/s", "cores": 1, "kind": "oracle",
+           "sample": f"every {step}th point ({len(Xs)} points), {r_cpu} Lloyd rounds, {dt_cpu:.2f} s"}
+    print(json.dumps({
+        "metric": "k-means point-rounds/sec (grouping by origin-destination, k = 8)",
+        "value": rate, "unit": "point-rounds/s", "n_gpus": 1, "higher_is_better": True,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w.name + "-od-features", "points": n, "dim": dim, "k": k,
+                   "rounds": rounds, "round_ms": dt * 1e3 / rounds},
+        "roofline": {"bound": "hbm", "kernel": "k_km_assign+k_km_reduce", "achieved": round(gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+        "choose_groups": {"kmin": 4, "kmax": 16, "restarts": args.restarts, "B": B,
+                          "seconds": dt_choose, "db": [round(v, 6) for v in db.tolist()]},
+        "cpu_baseline": cpu}), flush=True)
 
 
 def convergence_main(args):

@@ -183,6 +183,58 @@ hb_status hb_set_graph(hb_ctx *ctx, int32_t n_nodes, const float *node_xy, int64
  * hb_set_graph (HB_ESTATE otherwise); NULL group with E > 0 gives HB_EINVAL. */
 hb_status hb_orientation_groups(hb_ctx *ctx, int32_t *group, uint32_t flags);
 
+/* ---- grouping (Section 5): bins found by k-means on an edge property with the Euclidean
+ * distance; the number of bins B chosen between 4 and 16 by the lowest Davies-Bouldin index,
+ * k-means being run from many random initialisations for every B. */
+
+/* edge properties of hb_edge_features (grid / pixel units, from the end points) */
+enum {
+    HB_FEAT_ORIGIN = 0,              /* (x_s, y_s): 2 floats per edge */
+    HB_FEAT_DESTINATION = 1,         /* (x_t, y_t): 2 floats per edge */
+    HB_FEAT_ORIGIN_DESTINATION = 2,  /* (x_s, y_s, x_t, y_t): 4 floats per edge */
+    HB_FEAT_LENGTH = 3               /* |x_t - x_s| (FP64, rounded): 1 float per edge */
+};
+#define HB_KMEANS_MAX_K 64
+#define HB_KMEANS_MAX_DIM 8
+
+/* Write the property `kind` of every edge, E x dim floats row-major (dim 2, 2, 4 or 1), to out
+ * (host memory, or device memory with HB_DEVICE_PTRS; caller-owned). cap_floats < E dim gives
+ * HB_EINVAL. Requires hb_set_graph. Synchronous. */
+hb_status hb_edge_features(hb_ctx *ctx, int32_t kind, float *out, int64_t cap_floats, uint32_t flags);
+
+/* Lloyd's k-means of the n points X[n][dim] (float32 row-major; dim in [1, HB_KMEANS_MAX_DIM],
+ * k in [1, HB_KMEANS_MAX_K], n >= k): each round assigns every point to its nearest centre
+ * (squared Euclidean distance summed over the coordinates in order in FP64, ties to the lower
+ * index), then moves every centre with points to their mean (a centre without points stays);
+ * it stops when no label changes, or after max_iters rounds (then the labels are those of the
+ * last round and the centres their means). centers[k][dim] (host, FP64) holds the starting
+ * centres on entry and the final ones on return; labels[n] (int32) receives the clusters;
+ * *inertia the sum of squared distances to the assigned centres, *rounds the rounds made
+ * (either may be NULL). X and labels are host memory, or device memory with HB_DEVICE_PTRS.
+ * Uses the context's device and stream (hb_set_graph not needed). Synchronous. */
+hb_status hb_kmeans(hb_ctx *ctx, const float *X, int64_t n, int32_t dim, int32_t k, double *centers,
+                    int32_t max_iters, int32_t *labels, double *inertia, int32_t *rounds,
+                    uint32_t flags);
+
+/* Davies-Bouldin index of the labelling labels[n] in [0, k) of X[n][dim]: with s_i the mean
+ * distance of the points of cluster i to its centroid and d_ij the distance between centroids,
+ * the mean over the non-empty clusters of max over j != i of (s_i + s_j) / d_ij (coincident
+ * centroids count 0; fewer than two clusters give 0). Memory as in hb_kmeans. */
+hb_status hb_davies_bouldin(hb_ctx *ctx, const float *X, int64_t n, int32_t dim, int32_t k,
+                            const int32_t *labels, double *db, uint32_t flags);
+
+/* The choice of B (Section 5): for every B in [kmin, kmax] (1 <= kmin <= kmax <=
+ * HB_KMEANS_MAX_K, n >= kmax), `restarts` k-means runs of at most max_iters rounds, run r
+ * starting from the B distinct points whose indices are the values t = 0, 1, ... of the
+ * counter-based SplitMix64 stream value(seed, B, r, t) = mix(seed + 0x9E3779B97F4A7C15
+ * (1 + t + 4096 (r + 1024 B))) taken modulo n (repeats skipped; mix is SplitMix64's output
+ * function); the run of lowest inertia is kept (the first on a tie) and db[B - kmin] receives
+ * its Davies-Bouldin index. *n_groups gets the B of the lowest index (the smallest on a tie)
+ * and labels[n] its clusters. X and labels as in hb_kmeans; db is host memory. */
+hb_status hb_choose_groups(hb_ctx *ctx, const float *X, int64_t n, int32_t dim, int32_t kmin,
+                           int32_t kmax, int32_t restarts, uint64_t seed, int32_t max_iters,
+                           int32_t *labels, int32_t *n_groups, double *db, uint32_t flags);
+
 /* Set the edge groups b_e in [0, B) and the B x B interaction matrix M (Section 3.2 Eq. 3):
  * M[l * B + b] is the weight of bin b on layer l. B in [1, 64]. */
 hb_status hb_set_groups(hb_ctx *ctx, int32_t n_groups, const int32_t *group, const float *M,

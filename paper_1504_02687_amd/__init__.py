@@ -23,6 +23,9 @@ HB_RUN_SAMPLES_GIVEN, HB_RUN_RECORD_DECISIONS, HB_RUN_ASYNC, HB_RUN_GRAPH = 1, 2
 HB_POINTS_STATE, HB_POINTS_SAMPLES = 0, 1
 HB_MAP_HIST, HB_MAP_BOX, HB_MAP_DENSITY, HB_MAP_GRAD = 0, 1, 2, 3
 HB_SPLAT_POINTS, HB_SPLAT_STRIP = 0, 1
+HB_FEAT_ORIGIN, HB_FEAT_DESTINATION, HB_FEAT_ORIGIN_DESTINATION, HB_FEAT_LENGTH = 0, 1, 2, 3
+HB_KMEANS_MAX_K, HB_KMEANS_MAX_DIM = 64, 8
+_FEAT_DIM = {0: 2, 1: 2, 2: 4, 3: 1}
 HB_MAX_GROUPS, HB_MAX_PASSES = 64, 8
 HB_MAX_EDGE_WEIGHT = (1 << 20) - 1
 
@@ -74,6 +77,19 @@ _SIGS = {
     "hb_set_groups": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_uint32]),
     "hb_orientation_groups": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_uint32]),
+    "hb_edge_features": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64,
+                                          ctypes.c_uint32]),
+    "hb_kmeans": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                   ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                   ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
+                                   ctypes.c_uint32]),
+    "hb_davies_bouldin": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                           ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.c_uint32]),
+    "hb_choose_groups": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                          ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
+                                          ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.c_void_p, ctypes.c_uint32]),
     "hb_run": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32]),
     "hb_sync": (ctypes.c_int32, [ctypes.c_void_p]),
     "hb_get_num_points": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
@@ -224,6 +240,66 @@ def hb_orientation_groups(ctx, n_edges: int, device=None):
     out = np.empty(n_edges, np.int32)
     _check(ctx, load().hb_orientation_groups(ctx, out.ctypes.data, 0))
     return out
+
+
+def hb_edge_features(ctx, kind: int, n_edges: int) -> np.ndarray:
+    """Edge property `kind` (HB_FEAT_*) of every edge, float32 [E, dim]."""
+    dim = _FEAT_DIM[int(kind)]
+    out = np.empty((n_edges, dim), np.float32)
+    _check(ctx, load().hb_edge_features(ctx, int(kind), out.ctypes.data, out.size, 0))
+    return out
+
+
+def _points(X):
+    px, kx, dx = _arr(X, np.float32)
+    n, dim = (int(kx.shape[0]), int(kx.shape[1])) if kx.ndim == 2 else (int(kx.shape[0]), 1)
+    return px, kx, dx, n, dim
+
+
+def hb_kmeans(ctx, X, centers, max_iters: int = 100):
+    """Lloyd's k-means from `centers` [k, dim]; returns (labels int32 [n], centres float64,
+    inertia, rounds). X may be a numpy array or a CUDA tensor (labels then on the device)."""
+    px, kx, dx, n, dim = _points(X)
+    cen = np.array(centers, dtype=np.float64, order="C", copy=True).reshape(-1, dim)
+    k = int(cen.shape[0])
+    if dx:
+        import torch
+        labels = torch.empty(n, dtype=torch.int32, device=kx.device)
+        pl = labels.data_ptr()
+    else:
+        labels = np.empty(n, np.int32)
+        pl = labels.ctypes.data
+    inertia, rounds = ctypes.c_double(), ctypes.c_int32()
+    _check(ctx, load().hb_kmeans(ctx, px, n, dim, k, cen.ctypes.data, int(max_iters), pl,
+                                 ctypes.byref(inertia), ctypes.byref(rounds), _flags(dx)))
+    return labels, cen, float(inertia.value), int(rounds.value)
+
+
+def hb_davies_bouldin(ctx, X, labels, k: int) -> float:
+    px, kx, dx, n, dim = _points(X)
+    pl, kl, dl = _arr(labels, np.int32)
+    out = ctypes.c_double()
+    _check(ctx, load().hb_davies_bouldin(ctx, px, n, dim, int(k), pl, ctypes.byref(out), _flags(dx, dl)))
+    return float(out.value)
+
+
+def hb_choose_groups(ctx, X, kmin: int = 4, kmax: int = 16, restarts: int = 100, seed: int = 0,
+                     max_iters: int = 100):
+    """B in [kmin, kmax] of the lowest Davies-Bouldin index; returns (B, labels, db per B)."""
+    px, kx, dx, n, dim = _points(X)
+    if dx:
+        import torch
+        labels = torch.empty(n, dtype=torch.int32, device=kx.device)
+        pl = labels.data_ptr()
+    else:
+        labels = np.empty(n, np.int32)
+        pl = labels.ctypes.data
+    db = np.empty(kmax - kmin + 1, np.float64)
+    B = ctypes.c_int32()
+    _check(ctx, load().hb_choose_groups(ctx, px, n, dim, int(kmin), int(kmax), int(restarts),
+                                        ctypes.c_uint64(int(seed)), int(max_iters), pl,
+                                        ctypes.byref(B), db.ctypes.data, _flags(dx)))
+    return int(B.value), labels, db
 
 
 def hb_run(ctx, n_iters: int, flags: int = 0) -> None:
@@ -424,6 +500,18 @@ class Bundler:
 
     def orientation_groups(self, device=None):
         return hb_orientation_groups(self.ctx, self.n_edges, device)
+
+    def edge_features(self, kind):
+        return hb_edge_features(self.ctx, kind, self.n_edges)
+
+    def kmeans(self, X, centers, max_iters=100):
+        return hb_kmeans(self.ctx, X, centers, max_iters)
+
+    def davies_bouldin(self, X, labels, k):
+        return hb_davies_bouldin(self.ctx, X, labels, k)
+
+    def choose_groups(self, X, kmin=4, kmax=16, restarts=100, seed=0, max_iters=100):
+        return hb_choose_groups(self.ctx, X, kmin, kmax, restarts, seed, max_iters)
 
     def set_workload(self, w, **kw):
         """Parameters, graph and groups of a ``workloads.Workload``."""

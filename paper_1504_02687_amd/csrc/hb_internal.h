@@ -36,6 +36,9 @@ constexpr int kRedSlices = 32;                      // slices per parameter in k
 constexpr int kInkSlices = 256;                     // slices of the ink sum
 constexpr int64_t kMaxEdgeSamples = int64_t(1) << 31;  // samples of one edge, exclusive bound
 static_assert(HB_MAX_EDGE_WEIGHT < (1u << (32 - kLocalBits)), "weights must fit an entry");
+constexpr int kKmMaxK = HB_KMEANS_MAX_K;            // clusters of the grouping k-means
+constexpr int kKmMaxDim = HB_KMEANS_MAX_DIM;        // coordinates per point
+static_assert(kKmMaxK <= kBlock, "one thread per cluster in k_km_db");
 
 // Four map values of one bilinear cell (16 bytes, one load).
 struct alignas(16) Quad {
@@ -188,6 +191,19 @@ hipError_t launch_advect_smooth(const GDesc *desc, int ng, const Shape &tot, int
 hipError_t launch_fill_totals(const GDesc *desc, int ng, int T, hipStream_t st);
 // orientation slice in [0, 4) of every edge, from the end points of its polyline
 hipError_t launch_orientation(const GDesc *desc, const Shape &tot, int32_t *group, hipStream_t st);
+// grouping (k-means on edge features, Davies-Bouldin index)
+hipError_t launch_edge_features(const GDesc *desc, int64_t E, int kind, float *out, hipStream_t st);
+hipError_t launch_km_gather(const float *X, int dim, int k, const int64_t *idx, double *centers,
+                            hipStream_t st);
+// one assignment round (mode 0), or the sums of the given labels (mode 1: coordinates and
+// squared distances, mode 2: distances); tot receives k (dim+1) + 1 block-ordered sums
+hipError_t launch_km_round(const float *X, int64_t n, int dim, int k, const double *centers,
+                           int32_t *labels, int mode, double *part, double *tot,
+                           unsigned long long *changed, hipStream_t st);
+hipError_t launch_km_means(const double *tot, int dim, int k, int keep, double *centers,
+                           hipStream_t st);
+hipError_t launch_km_db(const double *tot, const double *centers, int dim, int k, double *db,
+                        hipStream_t st);
 // ink = sum of n polyline lengths, fixed order; part[kInkSlices] receives it (device)
 hipError_t launch_ink(const double *lens, int64_t n, double *part, hipStream_t st);
 

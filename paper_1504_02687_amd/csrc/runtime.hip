@@ -1490,6 +1490,250 @@ HB_API hb_status hb_get_ink(hb_ctx *c, double *ink) {
     return HB_OK;
 }
 
+// ------------------------------------------------------------------ grouping (Section 5)
+
+HB_API hb_status hb_edge_features(hb_ctx *c, int32_t kind, float *out, int64_t cap_floats,
+                                  uint32_t flags) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    if (flags & ~(uint32_t)HB_DEVICE_PTRS) return fail(c, HB_EINVAL, "unknown flags");
+    if (!c->have_graph) return fail(c, HB_ESTATE, "hb_edge_features needs hb_set_graph");
+    static const int kDim[4] = {2, 2, 4, 1};
+    if (kind < 0 || kind > 3) return fail(c, HB_EINVAL, "unknown edge feature kind");
+    const int64_t need = c->E * kDim[kind];
+    if (!out || cap_floats < need) return fail(c, HB_EINVAL, "output buffer missing or too small");
+    if (c->E == 0) return HB_OK;
+    CHKST(ensure_desc(c, 1));
+    CHKST(wait_desc(c));
+    GDesc d = base_desc(c);
+    d.pin = c->pts[c->ps];       // the end points never move
+    d.off_in = c->off[c->os];
+    c->h_desc[0] = d;
+    CHKST(upload_desc(c, 1));
+    float *dst = out, *tmp = nullptr;
+    if (!(flags & HB_DEVICE_PTRS)) {
+        CHKST(dalloc(c, &tmp, (size_t)need, "edge features"));
+        dst = tmp;
+    }
+    hipError_t e = hb::launch_edge_features(c->d_desc, c->E, kind, dst, c->stream);
+    if (e == hipSuccess && tmp)
+        e = hipMemcpyAsync(out, tmp, sizeof(float) * (size_t)need, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    dfree(&tmp);
+    if (e != hipSuccess) return fail_dev(c, e, "edge features");
+    return HB_OK;
+}
+
+// Device buffers of one grouping call, freed on return.
+struct KmBufs {
+    float *X = nullptr;
+    int32_t *lab = nullptr, *best = nullptr, *chosen = nullptr;
+    double *part = nullptr, *tot = nullptr, *cen = nullptr, *db = nullptr;
+    unsigned long long *cnt = nullptr;
+    int64_t *idx = nullptr;
+    ~KmBufs() {
+        dfree(&X);
+        dfree(&lab);
+        dfree(&best);
+        dfree(&chosen);
+        dfree(&part);
+        dfree(&tot);
+        dfree(&cen);
+        dfree(&db);
+        dfree(&cnt);
+        dfree(&idx);
+    }
+};
+
+static hb_status km_check(hb_ctx *c, const float *X, int64_t n, int32_t dim, int32_t kmax,
+                          uint32_t flags) {
+    if (flags & ~(uint32_t)HB_DEVICE_PTRS) return fail(c, HB_EINVAL, "unknown flags");
+    if (!X) return fail(c, HB_EINVAL, "X is NULL");
+    if (dim < 1 || dim > HB_KMEANS_MAX_DIM) return fail(c, HB_EINVAL, "dim must be in [1, HB_KMEANS_MAX_DIM]");
+    if (kmax < 1 || kmax > HB_KMEANS_MAX_K) return fail(c, HB_EINVAL, "k must be in [1, HB_KMEANS_MAX_K]");
+    if (n < kmax) return fail(c, HB_EINVAL, "need at least k points");
+    if (n > ((int64_t)1 << 31)) return fail(c, HB_EINVAL, "at most 2^31 points");
+    return HB_OK;
+}
+
+// Points on the device (copied when given in host memory) and the work buffers for up to
+// kmax clusters.
+static hb_status km_setup(hb_ctx *c, KmBufs &b, const float *X, int64_t n, int32_t dim, int32_t kmax,
+                          uint32_t flags, const float **dX) {
+    if (flags & HB_DEVICE_PTRS) {
+        *dX = X;
+    } else {
+        CHKST(dalloc(c, &b.X, (size_t)(n * dim), "k-means points"));
+        HIPCHK(c, hipMemcpyAsync(b.X, X, sizeof(float) * (size_t)(n * dim), hipMemcpyHostToDevice, c->stream));
+        *dX = b.X;
+    }
+    const int64_t nblk = (n + hb::kBlock - 1) / hb::kBlock;
+    const int64_t w = (int64_t)kmax * (dim + 1) + 1;
+    CHKST(dalloc(c, &b.part, (size_t)(nblk * w), "k-means partial sums"));
+    CHKST(dalloc(c, &b.tot, (size_t)w, "k-means sums"));
+    CHKST(dalloc(c, &b.cen, (size_t)kmax * dim, "k-means centres"));
+    CHKST(dalloc(c, &b.cnt, 1, "k-means counter"));
+    CHKST(dalloc(c, &b.db, 1, "Davies-Bouldin index"));
+    CHKST(dalloc(c, &b.idx, (size_t)kmax, "k-means start indices"));
+    return HB_OK;
+}
+
+// Lloyd rounds from the centres in b.cen; labels in dlab (device).
+static hb_status km_run(hb_ctx *c, KmBufs &b, const float *dX, int64_t n, int32_t dim, int32_t k,
+                        int32_t max_iters, int32_t *dlab, double *inertia, int32_t *rounds) {
+    HIPCHK(c, hipMemsetAsync(dlab, 0xff, sizeof(int32_t) * (size_t)n, c->stream));   // -1: none yet
+    const int w = k * (dim + 1) + 1;
+    int32_t r = 0;
+    for (int32_t it = 0; it < max_iters; ++it) {
+        HIPCHK(c, hipMemsetAsync(b.cnt, 0, sizeof(unsigned long long), c->stream));
+        HIPCHK(c, hb::launch_km_round(dX, n, dim, k, b.cen, dlab, 0, b.part, b.tot, b.cnt, c->stream));
+        unsigned long long changed = 0;
+        HIPCHK(c, hipMemcpyAsync(&changed, b.cnt, sizeof changed, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        r = it + 1;
+        if (changed == 0) break;
+        HIPCHK(c, hb::launch_km_means(b.tot, dim, k, 1, b.cen, c->stream));
+        if (it + 1 == max_iters)   // the sums of squared distances to the final centres
+            HIPCHK(c, hb::launch_km_round(dX, n, dim, k, b.cen, dlab, 1, b.part, b.tot, b.cnt, c->stream));
+    }
+    double in = 0.0;
+    HIPCHK(c, hipMemcpyAsync(&in, b.tot + (w - 1), sizeof in, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (inertia) *inertia = in;
+    if (rounds) *rounds = r;
+    return HB_OK;
+}
+
+// Davies-Bouldin index of the labels dlab (device); invalid labels give HB_EINVAL.
+static hb_status km_db(hb_ctx *c, KmBufs &b, const float *dX, int64_t n, int32_t dim, int32_t k,
+                       int32_t *dlab, double *db) {
+    HIPCHK(c, hipMemsetAsync(b.cnt, 0, sizeof(unsigned long long), c->stream));
+    HIPCHK(c, hipMemsetAsync(b.cen, 0, sizeof(double) * (size_t)k * dim, c->stream));
+    HIPCHK(c, hb::launch_km_round(dX, n, dim, k, b.cen, dlab, 1, b.part, b.tot, b.cnt, c->stream));
+    HIPCHK(c, hb::launch_km_means(b.tot, dim, k, 0, b.cen, c->stream));       // centroids
+    HIPCHK(c, hb::launch_km_round(dX, n, dim, k, b.cen, dlab, 2, b.part, b.tot, b.cnt, c->stream));
+    HIPCHK(c, hb::launch_km_db(b.tot, b.cen, dim, k, b.db, c->stream));
+    unsigned long long bad = 0;
+    HIPCHK(c, hipMemcpyAsync(&bad, b.cnt, sizeof bad, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(db, b.db, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (bad) return fail(c, HB_EINVAL, "labels outside [0, k)");
+    return HB_OK;
+}
+
+HB_API hb_status hb_kmeans(hb_ctx *c, const float *X, int64_t n, int32_t dim, int32_t k,
+                           double *centers, int32_t max_iters, int32_t *labels, double *inertia,
+                           int32_t *rounds, uint32_t flags) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    CHKST(km_check(c, X, n, dim, k, flags));
+    if (!centers || !labels) return fail(c, HB_EINVAL, "centers or labels is NULL");
+    if (max_iters < 1) return fail(c, HB_EINVAL, "max_iters must be >= 1");
+    for (int64_t i = 0; i < (int64_t)k * dim; ++i)
+        if (!std::isfinite(centers[i])) return fail(c, HB_EINVAL, "starting centres not finite");
+    KmBufs b;
+    const float *dX = nullptr;
+    CHKST(km_setup(c, b, X, n, dim, k, flags, &dX));
+    int32_t *dlab = labels;
+    if (!(flags & HB_DEVICE_PTRS)) {
+        CHKST(dalloc(c, &b.lab, (size_t)n, "k-means labels"));
+        dlab = b.lab;
+    }
+    HIPCHK(c, hipMemcpyAsync(b.cen, centers, sizeof(double) * (size_t)k * dim, hipMemcpyHostToDevice, c->stream));
+    CHKST(km_run(c, b, dX, n, dim, k, max_iters, dlab, inertia, rounds));
+    HIPCHK(c, hipMemcpyAsync(centers, b.cen, sizeof(double) * (size_t)k * dim, hipMemcpyDeviceToHost, c->stream));
+    if (b.lab)
+        HIPCHK(c, hipMemcpyAsync(labels, b.lab, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return HB_OK;
+}
+
+HB_API hb_status hb_davies_bouldin(hb_ctx *c, const float *X, int64_t n, int32_t dim, int32_t k,
+                                   const int32_t *labels, double *db, uint32_t flags) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    if (!labels || !db) return fail(c, HB_EINVAL, "labels or db is NULL");
+    if (n < 1) return fail(c, HB_EINVAL, "no points");
+    CHKST(km_check(c, X, n, dim, 1, flags));
+    if (k < 1 || k > HB_KMEANS_MAX_K) return fail(c, HB_EINVAL, "k must be in [1, HB_KMEANS_MAX_K]");
+    KmBufs b;
+    const float *dX = nullptr;
+    CHKST(km_setup(c, b, X, n, dim, k, flags, &dX));
+    int32_t *dlab = const_cast<int32_t *>(labels);
+    if (!(flags & HB_DEVICE_PTRS)) {
+        CHKST(dalloc(c, &b.lab, (size_t)n, "labels"));
+        HIPCHK(c, hipMemcpyAsync(b.lab, labels, sizeof(int32_t) * (size_t)n, hipMemcpyHostToDevice, c->stream));
+        dlab = b.lab;
+    }
+    return km_db(c, b, dX, n, dim, k, dlab, db);
+}
+
+// SplitMix64 (Steele, Lea and Flood 2014) as a counter-based stream: value t of stream
+// (seed, B, r) is the output function applied to seed + gamma (1 + t + 4096 (r + 1024 B)).
+static uint64_t km_draw(uint64_t seed, int32_t B, int32_t r, int64_t t) {
+    uint64_t z = seed + 0x9E3779B97F4A7C15ull * (uint64_t)(1 + t + 4096 * ((int64_t)r + 1024 * (int64_t)B));
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+HB_API hb_status hb_choose_groups(hb_ctx *c, const float *X, int64_t n, int32_t dim, int32_t kmin,
+                                  int32_t kmax, int32_t restarts, uint64_t seed, int32_t max_iters,
+                                  int32_t *labels, int32_t *n_groups, double *db, uint32_t flags) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    CHKST(km_check(c, X, n, dim, kmax, flags));
+    if (kmin < 1 || kmin > kmax) return fail(c, HB_EINVAL, "need 1 <= kmin <= kmax");
+    if (restarts < 1 || max_iters < 1) return fail(c, HB_EINVAL, "restarts and max_iters must be >= 1");
+    if (!labels || !n_groups || !db) return fail(c, HB_EINVAL, "labels, n_groups or db is NULL");
+    KmBufs b;
+    const float *dX = nullptr;
+    CHKST(km_setup(c, b, X, n, dim, kmax, flags, &dX));
+    CHKST(dalloc(c, &b.lab, (size_t)n, "k-means labels"));
+    CHKST(dalloc(c, &b.best, (size_t)n, "k-means best labels"));
+    int32_t *dchosen = labels;
+    if (!(flags & HB_DEVICE_PTRS)) {
+        CHKST(dalloc(c, &b.chosen, (size_t)n, "chosen labels"));
+        dchosen = b.chosen;
+    }
+    std::vector<int64_t> idx((size_t)kmax);
+    int32_t chosen = kmin;
+    double chosen_db = 0.0;
+    for (int32_t k = kmin; k <= kmax; ++k) {
+        double best_in = 0.0;
+        for (int32_t r = 0; r < restarts; ++r) {
+            int32_t got = 0;
+            for (int64_t t = 0; got < k; ++t) {
+                const int64_t v = (int64_t)(km_draw(seed, k, r, t) % (uint64_t)n);
+                bool dup = false;
+                for (int32_t q = 0; q < got; ++q) dup = dup || idx[(size_t)q] == v;
+                if (!dup) idx[(size_t)got++] = v;
+            }
+            HIPCHK(c, hipMemcpyAsync(b.idx, idx.data(), sizeof(int64_t) * (size_t)k, hipMemcpyHostToDevice, c->stream));
+            HIPCHK(c, hb::launch_km_gather(dX, dim, k, b.idx, b.cen, c->stream));
+            double in = 0.0;
+            CHKST(km_run(c, b, dX, n, dim, k, max_iters, b.lab, &in, nullptr));
+            if (r == 0 || in < best_in) {
+                best_in = in;
+                HIPCHK(c, hipMemcpyAsync(b.best, b.lab, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, c->stream));
+            }
+        }
+        double d = 0.0;
+        CHKST(km_db(c, b, dX, n, dim, k, b.best, &d));
+        db[k - kmin] = d;
+        if (k == kmin || d < chosen_db) {
+            chosen_db = d;
+            chosen = k;
+            HIPCHK(c, hipMemcpyAsync(dchosen, b.best, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToDevice, c->stream));
+        }
+    }
+    if (b.chosen)
+        HIPCHK(c, hipMemcpyAsync(labels, b.chosen, sizeof(int32_t) * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    *n_groups = chosen;
+    return HB_OK;
+}
+
 HB_API hb_status hb_orientation_groups(hb_ctx *c, int32_t *group, uint32_t flags) {
     ENTER(c);
     CHKST(finish_pending(c));
