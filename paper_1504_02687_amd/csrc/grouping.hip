@@ -35,6 +35,11 @@ __device__ __forceinline__ double block_sum_d(double v) {
     return s;
 }
 
+// Sum over the wave of one double per lane (fixed DPP order), in every lane.
+__device__ __forceinline__ double wave_sum_d(double v) {
+    return last_lane(wave_incl_scan<double>(v, (int)(threadIdx.x & 63)));
+}
+
 // Edge features from the end points of the current polylines (pixel units): kind 0 origin
 // (x_s, y_s), 1 destination (x_t, y_t), 2 both (x_s, y_s, x_t, y_t), 3 the distance from
 // origin to destination (FP64, rounded to FP32). One thread per edge.
@@ -68,17 +73,17 @@ __global__ __launch_bounds__(kBlock) void k_km_gather(const float *X, int dim, i
 }
 
 // One Lloyd assignment over the points (mode 0): each point to its nearest centre (ties to
-// the lower index), label changes counted in *changed; or (mode 1) the given labels kept,
-// labels outside [0, k) counted in *changed and left out. Per block, in
-// part[blockIdx][c][0..dim) the coordinate sums of cluster c, part[..][c][dim] its count and
-// part[..][k (dim+1)] the sum of the squared distances to the assigned centres; with mode 2,
-// part[..][c][0] is instead the sum of the distances (square roots) of the points of c.
+// the lower index); or (mode 1) the given labels kept, labels outside [0, k) left out. Per
+// wave (64 points, row blockIdx * 4 + wave of part): part[row][c][0..dim) the coordinate
+// sums of cluster c, part[row][c][dim] its count, part[row][k (dim+1)] the sum of the squared
+// distances to the assigned centres and part[row][k (dim+1) + 1] the number of labels that
+// changed (mode 0) or were out of range (modes 1, 2); with mode 2, part[row][c][0] is
+// instead the sum of the distances (square roots) of the points of c.
 __global__ __launch_bounds__(kBlock) void k_km_assign(const float *__restrict__ X, int64_t n,
                                                       int dim, int k,
                                                       const double *__restrict__ centers,
                                                       int32_t *__restrict__ labels, int mode,
-                                                      double *__restrict__ part,
-                                                      unsigned long long *changed) {
+                                                      double *__restrict__ part) {
     __shared__ double cen[kKmMaxK * kKmMaxDim];
     for (int i = threadIdx.x; i < k * dim; i += kBlock) cen[i] = centers[i];
     __syncthreads();
@@ -117,39 +122,52 @@ __global__ __launch_bounds__(kBlock) void k_km_assign(const float *__restrict__ 
         flag = in && (lab < 0 || lab >= k);
         if (flag) lab = -1;
     }
-    const uint64_t m = __ballot(flag);
-    if ((threadIdx.x & 63) == 0 && m) atomicAdd(changed, (unsigned long long)__builtin_popcountll(m));
-    const int w = k * (dim + 1) + 1;
-    double *out = part + (int64_t)blockIdx.x * w;
-    for (int c = 0; c < k; ++c) {
-        const bool mine = lab == c;
-        if (mode == 2) {
-            const double s = block_sum_d(mine ? bd : 0.0);
-            if (threadIdx.x == 0) {
-                out[c * (dim + 1)] = s;
-                for (int j = 1; j < dim; ++j) out[c * (dim + 1) + j] = 0.0;
-            }
+    const double nflag = (double)__builtin_popcountll(__ballot(flag));
+    // the wave's sums: its points, labels and distances through LDS; lane t adds value t
+    // (cluster t / (dim+1), coordinate t % (dim+1), the count at dim; the last value the
+    // squared distances) over the 64 points in order
+    __shared__ float sx[kWavesPerBlock][64][kKmMaxDim];
+    __shared__ int32_t sl[kWavesPerBlock][64];
+    __shared__ double sd[kWavesPerBlock][64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int j = 0; j < kKmMaxDim; ++j) sx[wid][lane][j] = x[j];
+    sl[wid][lane] = lab;
+    sd[wid][lane] = bd;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_s_waitcnt(0xc07f);   // LDS writes of the wave done before the reads
+    const int w = k * (dim + 1) + 2;
+    double *out = part + ((int64_t)blockIdx.x * kWavesPerBlock + wid) * w;
+    if (lane == 0) out[w - 1] = nflag;
+    for (int t = lane; t < w - 1; t += 64) {
+        double s = 0.0;
+        if (t == w - 2) {
+            if (mode != 2)
+                for (int p = 0; p < 64; ++p) s += sd[wid][p];
         } else {
-            for (int j = 0; j < dim; ++j) {
-                const double s = block_sum_d(mine ? (double)x[j] : 0.0);
-                if (threadIdx.x == 0) out[c * (dim + 1) + j] = s;
+            const int c = t / (dim + 1), j = t - c * (dim + 1);
+            for (int p = 0; p < 64; ++p) {
+                if (sl[wid][p] != c) continue;
+                if (j == dim) s += 1.0;
+                else if (mode == 2) s += j == 0 ? sd[wid][p] : 0.0;
+                else s += (double)sx[wid][p][j];
             }
         }
-        const double cnt = block_sum_d(mine ? 1.0 : 0.0);
-        if (threadIdx.x == 0) out[c * (dim + 1) + dim] = cnt;
+        out[t] = s;
     }
-    const double s = block_sum_d(mode == 2 ? 0.0 : bd);
-    if (threadIdx.x == 0) out[k * (dim + 1)] = s;
 }
 
-// Sum of the per-block partials over the blocks, in block order: one thread per value.
-__global__ __launch_bounds__(kBlock) void k_km_reduce(const double *__restrict__ part, int64_t nblk,
+// Sum of the per-wave partials over the rows, in a fixed order: one block per value t;
+// thread i adds rows [i S, (i+1) S) in order, then the block adds the 256 thread sums.
+__global__ __launch_bounds__(kBlock) void k_km_reduce(const double *__restrict__ part, int64_t rows,
                                                       int w, double *__restrict__ tot) {
-    const int t = blockIdx.x * kBlock + threadIdx.x;
-    if (t >= w) return;
+    const int t = blockIdx.x;
+    const int64_t S = (rows + kBlock - 1) / kBlock;
+    const int64_t r0 = (int64_t)threadIdx.x * S, r1 = r0 + S < rows ? r0 + S : rows;
     double s = 0.0;
-    for (int64_t b = 0; b < nblk; ++b) s += part[b * w + t];
-    tot[t] = s;
+    for (int64_t r = r0; r < r1; ++r) s += part[r * w + t];
+    s = block_sum_d(s);
+    if (threadIdx.x == 0) tot[t] = s;
 }
 
 // New centres: the mean of every cluster with points; a cluster without points keeps its
@@ -224,17 +242,16 @@ hipError_t launch_km_gather(const float *X, int dim, int k, const int64_t *idx, 
 }
 
 hipError_t launch_km_round(const float *X, int64_t n, int dim, int k, const double *centers,
-                           int32_t *labels, int mode, double *part, double *tot,
-                           unsigned long long *changed, hipStream_t st) {
+                           int32_t *labels, int mode, double *part, double *tot, hipStream_t st) {
     const int64_t nblk = (n + kBlock - 1) / kBlock;
     if (nblk <= 0) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_km_assign, dim3((unsigned)nblk), dim3(kBlock), 0, st, X, n, dim, k, centers,
-                       labels, mode, part, changed);
+                       labels, mode, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const int w = k * (dim + 1) + 1;
-    hipLaunchKernelGGL(k_km_reduce, dim3((unsigned)((w + kBlock - 1) / kBlock)), dim3(kBlock), 0, st,
-                       part, nblk, w, tot);
+    const int w = k * (dim + 1) + 2;
+    hipLaunchKernelGGL(k_km_reduce, dim3((unsigned)w), dim3(kBlock), 0, st, part,
+                       nblk * kWavesPerBlock, w, tot);
     return hipGetLastError();
 }
 

@@ -196,10 +196,10 @@ hipError_t launch_edge_features(const GDesc *desc, int64_t E, int kind, float *o
 hipError_t launch_km_gather(const float *X, int dim, int k, const int64_t *idx, double *centers,
                             hipStream_t st);
 // one assignment round (mode 0), or the sums of the given labels (mode 1: coordinates and
-// squared distances, mode 2: distances); tot receives k (dim+1) + 1 block-ordered sums
+// squared distances, mode 2: distances); tot receives k (dim+1) + 2 fixed-order sums (the
+// clusters, the squared distances, the changed or out-of-range labels)
 hipError_t launch_km_round(const float *X, int64_t n, int dim, int k, const double *centers,
-                           int32_t *labels, int mode, double *part, double *tot,
-                           unsigned long long *changed, hipStream_t st);
+                           int32_t *labels, int mode, double *part, double *tot, hipStream_t st);
 hipError_t launch_km_means(const double *tot, int dim, int k, int keep, double *centers,
                            hipStream_t st);
 hipError_t launch_km_db(const double *tot, const double *centers, int dim, int k, double *db,

@@ -1529,7 +1529,6 @@ struct KmBufs {
     float *X = nullptr;
     int32_t *lab = nullptr, *best = nullptr, *chosen = nullptr;
     double *part = nullptr, *tot = nullptr, *cen = nullptr, *db = nullptr;
-    unsigned long long *cnt = nullptr;
     int64_t *idx = nullptr;
     ~KmBufs() {
         dfree(&X);
@@ -1540,7 +1539,6 @@ struct KmBufs {
         dfree(&tot);
         dfree(&cen);
         dfree(&db);
-        dfree(&cnt);
         dfree(&idx);
     }
 };
@@ -1568,11 +1566,10 @@ static hb_status km_setup(hb_ctx *c, KmBufs &b, const float *X, int64_t n, int32
         *dX = b.X;
     }
     const int64_t nblk = (n + hb::kBlock - 1) / hb::kBlock;
-    const int64_t w = (int64_t)kmax * (dim + 1) + 1;
-    CHKST(dalloc(c, &b.part, (size_t)(nblk * w), "k-means partial sums"));
+    const int64_t w = (int64_t)kmax * (dim + 1) + 2;
+    CHKST(dalloc(c, &b.part, (size_t)(nblk * hb::kWavesPerBlock * w), "k-means partial sums"));
     CHKST(dalloc(c, &b.tot, (size_t)w, "k-means sums"));
     CHKST(dalloc(c, &b.cen, (size_t)kmax * dim, "k-means centres"));
-    CHKST(dalloc(c, &b.cnt, 1, "k-means counter"));
     CHKST(dalloc(c, &b.db, 1, "Davies-Bouldin index"));
     CHKST(dalloc(c, &b.idx, (size_t)kmax, "k-means start indices"));
     return HB_OK;
@@ -1582,22 +1579,21 @@ static hb_status km_setup(hb_ctx *c, KmBufs &b, const float *X, int64_t n, int32
 static hb_status km_run(hb_ctx *c, KmBufs &b, const float *dX, int64_t n, int32_t dim, int32_t k,
                         int32_t max_iters, int32_t *dlab, double *inertia, int32_t *rounds) {
     HIPCHK(c, hipMemsetAsync(dlab, 0xff, sizeof(int32_t) * (size_t)n, c->stream));   // -1: none yet
-    const int w = k * (dim + 1) + 1;
+    const int w = k * (dim + 1) + 2;
     int32_t r = 0;
     for (int32_t it = 0; it < max_iters; ++it) {
-        HIPCHK(c, hipMemsetAsync(b.cnt, 0, sizeof(unsigned long long), c->stream));
-        HIPCHK(c, hb::launch_km_round(dX, n, dim, k, b.cen, dlab, 0, b.part, b.tot, b.cnt, c->stream));
-        unsigned long long changed = 0;
-        HIPCHK(c, hipMemcpyAsync(&changed, b.cnt, sizeof changed, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hb::launch_km_round(dX, n, dim, k, b.cen, dlab, 0, b.part, b.tot, c->stream));
+        double changed = 0.0;
+        HIPCHK(c, hipMemcpyAsync(&changed, b.tot + (w - 1), sizeof changed, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
         r = it + 1;
-        if (changed == 0) break;
+        if (changed == 0.0) break;
         HIPCHK(c, hb::launch_km_means(b.tot, dim, k, 1, b.cen, c->stream));
         if (it + 1 == max_iters)   // the sums of squared distances to the final centres
-            HIPCHK(c, hb::launch_km_round(dX, n, dim, k, b.cen, dlab, 1, b.part, b.tot, b.cnt, c->stream));
+            HIPCHK(c, hb::launch_km_round(dX, n, dim, k, b.cen, dlab, 1, b.part, b.tot, c->stream));
     }
     double in = 0.0;
-    HIPCHK(c, hipMemcpyAsync(&in, b.tot + (w - 1), sizeof in, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&in, b.tot + (w - 2), sizeof in, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (inertia) *inertia = in;
     if (rounds) *rounds = r;
@@ -1607,17 +1603,17 @@ static hb_status km_run(hb_ctx *c, KmBufs &b, const float *dX, int64_t n, int32_
 // Davies-Bouldin index of the labels dlab (device); invalid labels give HB_EINVAL.
 static hb_status km_db(hb_ctx *c, KmBufs &b, const float *dX, int64_t n, int32_t dim, int32_t k,
                        int32_t *dlab, double *db) {
-    HIPCHK(c, hipMemsetAsync(b.cnt, 0, sizeof(unsigned long long), c->stream));
+    const int w = k * (dim + 1) + 2;
     HIPCHK(c, hipMemsetAsync(b.cen, 0, sizeof(double) * (size_t)k * dim, c->stream));
-    HIPCHK(c, hb::launch_km_round(dX, n, dim, k, b.cen, dlab, 1, b.part, b.tot, b.cnt, c->stream));
+    HIPCHK(c, hb::launch_km_round(dX, n, dim, k, b.cen, dlab, 1, b.part, b.tot, c->stream));
     HIPCHK(c, hb::launch_km_means(b.tot, dim, k, 0, b.cen, c->stream));       // centroids
-    HIPCHK(c, hb::launch_km_round(dX, n, dim, k, b.cen, dlab, 2, b.part, b.tot, b.cnt, c->stream));
+    HIPCHK(c, hb::launch_km_round(dX, n, dim, k, b.cen, dlab, 2, b.part, b.tot, c->stream));
     HIPCHK(c, hb::launch_km_db(b.tot, b.cen, dim, k, b.db, c->stream));
-    unsigned long long bad = 0;
-    HIPCHK(c, hipMemcpyAsync(&bad, b.cnt, sizeof bad, hipMemcpyDeviceToHost, c->stream));
+    double bad = 0.0;
+    HIPCHK(c, hipMemcpyAsync(&bad, b.tot + (w - 1), sizeof bad, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(db, b.db, sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    if (bad) return fail(c, HB_EINVAL, "labels outside [0, k)");
+    if (bad != 0.0) return fail(c, HB_EINVAL, "labels outside [0, k)");
     return HB_OK;
 }
 
