@@ -56,6 +56,8 @@ def lib():
             "orc_resample_counts": (i64, [i64, P, P, f64, P, P]),
             "orc_resample": (None, [i64, P, P, P, P, P, P]),
             "orc_directed_offset": (None, [i64, P, P, P, P, f64, P]),
+            "orc_insdel_counts": (i64, [i64, P, P, f64, f64, P]),
+            "orc_insdel": (None, [i64, P, P, f64, f64, P, P]),
             "orc_orientation": (None, [i64, P, P]),
             "orc_resample_frozen": (None, [i64, P, P, P, P, P]),
             "orc_advect_frozen": (None, [i64, P, P, P, i32, i32, P, f64, P, f64, P]),
@@ -117,6 +119,8 @@ class Params:
     bbox: tuple = (0.0, 0.0, 1.0, 1.0)
     directed_offset: float = 0.0    # push of interior samples along the left normal (px)
     strip_splat: bool = False       # histogram of the drawn line strips instead of the points
+    insert_delete: bool = False     # insert/delete resampling instead of the uniform one
+    delta_min: Optional[float] = None   # removal spacing of insert/delete (None: delta / 2)
 
     def radius(self, it: int) -> int:
         return int(self.radii[min(it, len(self.radii) - 1)])
@@ -191,6 +195,22 @@ def resample(off, xy, delta, want_seg=False):
     if want_seg:
         return off_out, xy_out, lens, seg
     return off_out, xy_out, lens
+
+
+def resample_insdel(off, xy, dmin, dmax):
+    """Insert/delete resampling: interior points closer than dmin to their input predecessor
+    removed, gaps between kept points cut into parts of at most dmax. Returns (off, xy)."""
+    off = _c(off, np.int64)
+    xy = _c(xy, np.float64)
+    E = off.shape[0] - 1
+    counts = np.empty(E, np.int64)
+    N = lib().orc_insdel_counts(E, _p(off), _p(xy), float(dmin), float(dmax), _p(counts))
+    off_out = np.zeros(E + 1, np.int64)
+    np.cumsum(counts, out=off_out[1:])
+    assert off_out[-1] == N
+    out = np.empty((N, 2), np.float64)
+    lib().orc_insdel(E, _p(off), _p(xy), float(dmin), float(dmax), _p(off_out), _p(out))
+    return off_out, out
 
 
 def directed_offset(off_in, xy_in, off_out, seg, xy, d):
@@ -402,6 +422,9 @@ def iterate(off, xy, group, M, p: Params, it: int, weight=None, skip_resample=Fa
     r = p.radius(it)
     if skip_resample:
         s_off, s_xy = _c(off, np.int64), _c(xy, np.float64)
+    elif p.insert_delete:
+        dmin = p.delta_min if p.delta_min is not None else 0.5 * p.delta
+        s_off, s_xy = resample_insdel(off, xy, dmin, p.delta)
     elif p.directed_offset != 0.0:
         s_off, s_xy, _, seg = resample(off, xy, p.delta, want_seg=True)
         s_xy = directed_offset(off, xy, s_off, seg, s_xy, p.directed_offset)
@@ -439,7 +462,7 @@ def run(node_xy, src, dst, group, M, p: Params, n_iters: int, weight=None):
 def record_run(off, xy, group, M, p: Params, n_iters: int, it0: int = 0, weight=None):
     """Base run from the polylines (off, xy): per iteration, the discrete choices that the
     frozen surrogate replays (sample offsets, segment indices, histograms, decisions)."""
-    if p.directed_offset != 0.0 or p.strip_splat:
+    if p.directed_offset != 0.0 or p.strip_splat or p.insert_delete:
         raise ValueError("the frozen surrogate covers the point splat without a directed offset")
     rec = []
     off = _c(off, np.int64)

@@ -759,3 +759,59 @@ def test_choose_groups_finds_separated_blobs():
     B, labels, db = O.choose_groups(X, kmin=4, kmax=9, restarts=100, seed=3, max_iters=200)
     assert B == 6
     assert db.argmin() == 6 - 4 and len(np.unique(labels)) == 6
+
+
+# ------------------------------------------------------------------ insert/delete resampling
+
+def test_insdel_closed_forms():
+    off = np.array([0, 4, 8], np.int64)
+    xy = np.array([[0, 0], [0.2, 0], [0.5, 0], [3.0, 0],       # 0.2 and 0.5 too close: removed
+                   [0, 1], [0.7, 1], [2.9, 1], [3.0, 1]], np.float64)   # 2.9 -> 3.0 too close
+    o, s = O.resample_insdel(off, xy, 0.5, 1.0)
+    np.testing.assert_array_equal(o, [0, 4, 10])
+    np.testing.assert_allclose(s[:4], [[0, 0], [1, 0], [2, 0], [3, 0]], atol=1e-15)
+    # kept 0, 0.7, 3.0 (2.9 is 2.2 from 0.7: kept too), gaps 0.7 (1 part), 2.2 (3 parts), 0.1
+    o2, s2 = O.resample_insdel(np.array([0, 4], np.int64), xy[4:], 0.5, 1.0)
+    exp = [0.0, 0.7, 0.7 + 2.2 / 3, 0.7 + 4.4 / 3, 2.9, 3.0]
+    np.testing.assert_allclose(s2[:, 0], exp, atol=1e-12)
+    np.testing.assert_array_equal(s2[:, 1], 1.0)
+
+
+def test_insdel_invariants_on_random_polylines():
+    g = rng(51)
+    polys = [np.cumsum(g.normal(0, 1.2, (int(m), 2)), 0) + 50 for m in g.integers(2, 60, 80)]
+    off = np.concatenate([[0], np.cumsum([len(p) for p in polys])]).astype(np.int64)
+    xy = np.concatenate(polys)
+    dmin, dmax = 0.5, 1.0
+    o, s = O.resample_insdel(off, xy, dmin, dmax)
+    for e, p in enumerate(polys):
+        q = s[o[e]:o[e + 1]]
+        np.testing.assert_array_equal(q[0], p[0])
+        np.testing.assert_array_equal(q[-1], p[-1])
+        gaps = np.hypot(*np.diff(q, axis=0).T)
+        assert (gaps <= dmax * (1 + 1e-12)).all()
+        # kept points: the interior input points at least dmin from their predecessor
+        dpred = np.hypot(*np.diff(p, axis=0).T)
+        kept = set(map(tuple, p[1:-1][dpred[:-1] >= dmin].tolist()))
+        out = set(map(tuple, q.tolist()))
+        assert kept <= out
+        removed = p[1:-1][dpred[:-1] < dmin]
+        for r in removed:
+            assert tuple(r.tolist()) not in out or tuple(r.tolist()) in kept
+
+
+def test_insdel_fixed_point_and_two_point_edges():
+    # a uniform polyline with spacing in [dmin, dmax] is unchanged
+    t = np.arange(0, 41) * 0.8
+    p = np.stack([10 + 0.6 * t, 20 + 0.8 * t], 1)
+    o, s = O.resample_insdel(np.array([0, 41], np.int64), p, 0.5, 1.0)
+    np.testing.assert_array_equal(s, p)
+    # straight two-point edges: the uniform resampling with delta = dmax
+    g = rng(52)
+    ends = g.uniform(0, 200, (30, 2, 2))
+    off = np.arange(0, 61, 2).astype(np.int64)
+    xy = ends.reshape(-1, 2)
+    o1, s1 = O.resample_insdel(off, xy, 0.5, 1.0)
+    o2, s2, _ = O.resample(off, xy, 1.0)
+    np.testing.assert_array_equal(o1, o2)
+    np.testing.assert_allclose(s1, s2, atol=1e-9)
