@@ -134,11 +134,12 @@ def write_traffic(fetch_csv, write_csv, last, out_path):
     return data
 
 
-def cpu_baseline(w, fraction, strip=False):
+def cpu_baseline(w, fraction, strip=False, insdel=False):
     import numpy as np
     import oracle as O
     p = O.params_for(w)
     p.strip_splat = strip
+    p.insert_delete = insdel
     step = max(1, int(round(1.0 / fraction)))
     sel = np.arange(0, w.n_edges, step)
     off, xy = O.initial_state(w.node_xy, w.src[sel], w.dst[sel], p)
@@ -177,6 +178,8 @@ def main():
                          "histogram concentration of both (one JSON line)")
     ap.add_argument("--splat", choices=("points", "strip"), default="points",
                     help="histogram of the sample points (default) or of the drawn line strips")
+    ap.add_argument("--resample", choices=("uniform", "insdel"), default="uniform",
+                    help="uniform resampling (default) or the insert/delete variant")
     ap.add_argument("--grouping", action="store_true",
                     help="measure the grouping step instead: k-means on the origin-destination "
                          "features of the edges and the choice of B (one JSON line)")
@@ -237,7 +240,8 @@ def main():
     # the sample count grows about 7x over the first iterations of this workload: size the
     # point buffers up front so no buffer growth (and iteration replay) lands in the timed run
     splat_mode = hb.HB_SPLAT_STRIP if args.splat == "strip" else hb.HB_SPLAT_POINTS
-    b.set_workload(w, capacity_factor=args.capacity, splat_mode=splat_mode)
+    resample_mode = hb.HB_RESAMPLE_INSERT_DELETE if args.resample == "insdel" else hb.HB_RESAMPLE_UNIFORM
+    b.set_workload(w, capacity_factor=args.capacity, splat_mode=splat_mode, resample_mode=resample_mode)
     log(f"warmup: {args.warmup} iterations")
     if args.warmup:
         b.run(args.warmup)
@@ -280,14 +284,14 @@ def main():
             per_stage_gbs[k] = round(stage_bytes(k, w, counts, n_state0) / (ms * 1e-3) / 1e9, 1)
 
     fwd_bwd = None
-    if args.grad_iters > 0 and args.splat == "points":
+    if args.grad_iters > 0 and args.splat == "points" and args.resample == "uniform":
         fwd_bwd = grad_ratio(hb, w, args.grad_iters, args.capacity)
         log(f"fwd+bwd / plain over {args.grad_iters} iterations: {fwd_bwd['ratio']:.2f}")
 
     cpu = None
     if args.cpu_fraction > 0:
         log(f"cpu baseline: oracle on {args.cpu_fraction:.0%} of the edges")
-        cpu = cpu_baseline(w, args.cpu_fraction, args.splat == "strip")
+        cpu = cpu_baseline(w, args.cpu_fraction, args.splat == "strip", args.resample == "insdel")
         log(f"  {cpu['value'] / 1e6:.2f} M edge-points/s on {cpu['cores']} threads")
 
     out = {
@@ -303,8 +307,9 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": w.name + ("-strip" if args.splat == "strip" else ""),
-                   "splat": args.splat, "edges": w.n_edges, "groups": w.n_groups,
+        "config": {"workload": w.name + ("-strip" if args.splat == "strip" else "")
+                   + ("-insdel" if args.resample == "insdel" else ""),
+                   "splat": args.splat, "resample": args.resample, "edges": w.n_edges, "groups": w.n_groups,
                    "grid": [w.grid_w, w.grid_h], "delta_px": w.delta, "box_passes": w.passes,
                    "radius_first": w.radii[0], "iterations_timed": args.steps,
                    "points_per_iteration_mean": total_pts / args.steps},

@@ -85,6 +85,8 @@ enum {
 
 /* splat modes (hb_params.splat_mode) */
 enum { HB_SPLAT_POINTS = 0, HB_SPLAT_STRIP = 1 };
+/* resampling modes (hb_params.resample_mode) */
+enum { HB_RESAMPLE_UNIFORM = 0, HB_RESAMPLE_INSERT_DELETE = 1 };
 
 #define HB_MAX_GROUPS 64
 #define HB_MAX_PASSES 8
@@ -143,6 +145,17 @@ typedef struct hb_params {
                                    (HB_RUN_SAMPLES_GIVEN) with much longer segments can exceed it
                                    (HB_EOVERFLOW). Not differentiated (hb_forward_ckpt requires
                                    HB_SPLAT_POINTS). */
+    int32_t resample_mode;      /* how each iteration resamples the polylines (Section 3, the
+                                   pipeline). HB_RESAMPLE_UNIFORM (default): n = max(1,
+                                   ceil(L / delta_px)) + 1 points at equal arclength.
+                                   HB_RESAMPLE_INSERT_DELETE: points are removed where they are
+                                   too close and created where they are too far apart: an
+                                   interior point closer than delta_min_px to its predecessor
+                                   in the polyline is removed, and the gap g between consecutive
+                                   kept points is cut into max(1, ceil(g / delta_px)) equal parts
+                                   (FP64). Needs directed_offset_px = 0; not differentiated. */
+    float delta_min_px;         /* removal spacing of HB_RESAMPLE_INSERT_DELETE; 0 (default):
+                                   delta_px / 2; else in (0, delta_px) */
 } hb_params;
 
 /* Fill p with the paper's defaults for a W x H grid: bbox [0,0,1,1], delta 1 px, P = 3,

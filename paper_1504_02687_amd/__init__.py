@@ -23,6 +23,7 @@ HB_RUN_SAMPLES_GIVEN, HB_RUN_RECORD_DECISIONS, HB_RUN_ASYNC, HB_RUN_GRAPH = 1, 2
 HB_POINTS_STATE, HB_POINTS_SAMPLES = 0, 1
 HB_MAP_HIST, HB_MAP_BOX, HB_MAP_DENSITY, HB_MAP_GRAD = 0, 1, 2, 3
 HB_SPLAT_POINTS, HB_SPLAT_STRIP = 0, 1
+HB_RESAMPLE_UNIFORM, HB_RESAMPLE_INSERT_DELETE = 0, 1
 HB_FEAT_ORIGIN, HB_FEAT_DESTINATION, HB_FEAT_ORIGIN_DESTINATION, HB_FEAT_LENGTH = 0, 1, 2, 3
 HB_KMEANS_MAX_K, HB_KMEANS_MAX_DIM = 64, 8
 _FEAT_DIM = {0: 2, 1: 2, 2: 4, 3: 1}
@@ -60,6 +61,8 @@ class hb_params(ctypes.Structure):
         ("capacity_factor", ctypes.c_float),
         ("directed_offset_px", ctypes.c_float),
         ("splat_mode", ctypes.c_int32),
+        ("resample_mode", ctypes.c_int32),
+        ("delta_min_px", ctypes.c_float),
     ]
 
 
@@ -434,7 +437,7 @@ def make_params(grid_w: int, grid_h: int, radii: Sequence[int], *, delta: float 
                 max_halvings: int = 8, smooth_weight: float = 0.5,
                 pass_weights: Optional[Sequence[float]] = None, bbox=(0.0, 0.0, 1.0, 1.0),
                 capacity_factor: float = 2.0, directed_offset: float = 0.0,
-                splat_mode: int = 0):
+                splat_mode: int = 0, resample_mode: int = 0, delta_min: float = 0.0):
     """hb_params plus the arrays it points to (keep both alive until hb_set_params)."""
     p = hb_default_params(grid_w, grid_h)
     r = (ctypes.c_int32 * len(radii))(*[int(v) for v in radii])
@@ -452,6 +455,8 @@ def make_params(grid_w: int, grid_h: int, radii: Sequence[int], *, delta: float 
     p.capacity_factor = capacity_factor
     p.directed_offset_px = directed_offset
     p.splat_mode = splat_mode
+    p.resample_mode = resample_mode
+    p.delta_min_px = delta_min
     keep = [r]
     if pass_weights is not None:
         a = (ctypes.c_float * passes)(*[float(v) for v in pass_weights])

@@ -78,6 +78,9 @@ struct GDesc {
     double h, eps, s, delta;
     double doff;                // directed offset of interior samples along the left normal
     int32_t strip;              // 1: histogram of the drawn line strips (entries per pixel drawn)
+    int32_t insdel;             // 1: insert/delete resampling (k_insdel) instead of the uniform one
+    int32_t count_given;        // 1: k_bin_samples<false> counts this graph's samples in tiles
+    double dmin;                // removal spacing of the insert/delete resampling
     int64_t ent_cap;            // capacity of bins, in entries (cap for the point splat)
     double a[HB_MAX_PASSES];    // density weight of each pass
     double ck[HB_MAX_PASSES];   // (2r+1)^(2k), k = 1..P
@@ -171,6 +174,9 @@ hipError_t launch_scan(const GDesc *desc, int ng, const Shape &tot, hipStream_t 
 hipError_t launch_resample_count(const GDesc *desc, int ng, const Shape &tot, int u,
                                  hipStream_t st);
 hipError_t launch_count_given(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
+// insert/delete resampling: sample counts of the current polylines (write = false, into
+// counts) or the samples (write = true, at off_s)
+hipError_t launch_insdel(const GDesc *desc, int ng, const Shape &tot, bool write, hipStream_t st);
 // tile counts (scatter = false) or entries (scatter = true) of the drawn line strips
 hipError_t launch_strip_bins(const GDesc *desc, int ng, const Shape &tot, bool scatter,
                              hipStream_t st);

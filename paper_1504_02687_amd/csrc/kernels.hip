@@ -165,7 +165,7 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
     const int lane = threadIdx.x & 63;
     const int64_t bl = blk - d.blk_edge;
     const int64_t e = edge_of(d, bl, wid);
-    if (e < 0) return;
+    if (e < 0 || d.insdel) return;
 
     __shared__ double sC[kWavesPerBlock][64 * U];
     __shared__ double sR[kWavesPerBlock][64 * U];
@@ -295,6 +295,100 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
     }
 }
 
+// Insert/delete resampling (the pipeline of Section 3: points are created where consecutive
+// points are too far apart and removed where they are too close). One wave per edge, the
+// input polyline 64 points at a time. An interior point is kept when its squared distance to
+// its input predecessor is at least dmin^2; the gap g between consecutive kept points a, b is
+// cut into c = max(1, ceil(g / delta)) equal parts: a, then a + (t / c)(b - a), t = 1..c-1.
+// A kept lane owns the gap to the next kept point of its chunk; the last kept point of a
+// chunk is carried into the next one, whose first kept lane also owns the carried gap; the
+// edge's last point closes it. WRITE = false: the point count of each edge (into counts);
+// WRITE = true: the points, at the edge's sample offset. FP64 throughout, every operation
+// rounded on its own.
+__device__ __forceinline__ int64_t insdel_parts(float2 a, float2 b, double dmax) {
+    const double dx = sub_rn((double)b.x, (double)a.x), dy = sub_rn((double)b.y, (double)a.y);
+    const double c = ceil(sqrt(add_rn(mul_rn(dx, dx), mul_rn(dy, dy))) / dmax);
+    return c < 1.0 ? 1 : (int64_t)c;
+}
+
+__device__ __forceinline__ float2 insdel_point(float2 a, float2 b, int64_t t, int64_t c) {
+    const double f = (double)t / (double)c;
+    float2 o;
+    o.x = (float)add_rn((double)a.x, mul_rn(f, sub_rn((double)b.x, (double)a.x)));
+    o.y = (float)add_rn((double)a.y, mul_rn(f, sub_rn((double)b.y, (double)a.y)));
+    return o;
+}
+
+template <bool WRITE>
+__global__ __launch_bounds__(kBlock) void k_insdel(const GDesc *__restrict__ gd, int ng) {
+    const int64_t blk = blockIdx.x;
+    HB_FIND(blk_edge);
+    if (stopped(d)) return;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    const int64_t bl = blk - d.blk_edge;
+    const int64_t e = edge_of(d, bl, wid);
+    if (e < 0 || !d.insdel) return;
+    const int64_t i0 = d.off_in[e], m = d.off_in[e + 1] - i0;
+    const HB_G float2 *p = glb(d.pin + i0);
+    HB_G float2 *q = glb(d.samples + (WRITE ? d.off_s[e] : 0));
+    const double dmin2 = mul_rn(d.dmin, d.dmin), dmax = d.delta;
+    bool carried = false;          // a kept point is carried from the previous chunk
+    float2 cp = make_float2(0.0f, 0.0f);
+    int64_t base = 0;              // points of the edge before this chunk
+    for (int64_t j0 = 0; j0 < m; j0 += 64) {
+        const int64_t j = j0 + lane;
+        const bool inr = j < m;
+        const float2 a = inr ? ld2(p + j) : make_float2(0.0f, 0.0f);
+        float2 pr;
+        pr.x = lane_prev(a.x);
+        pr.y = lane_prev(a.y);
+        if (lane == 0 && j0 > 0) pr = ld2(p + (j0 - 1));
+        bool keep = false;
+        if (inr) {
+            if (j == 0 || j == m - 1) {
+                keep = true;
+            } else {
+                const double dx = sub_rn((double)a.x, (double)pr.x), dy = sub_rn((double)a.y, (double)pr.y);
+                keep = add_rn(mul_rn(dx, dx), mul_rn(dy, dy)) >= dmin2;
+            }
+        }
+        const uint64_t K = __ballot(keep);
+        const uint64_t above = lane == 63 ? 0ull : (K >> (lane + 1));
+        const int nxt = above ? lane + 1 + __builtin_ctzll(above) : lane;
+        float2 b;
+        b.x = __shfl(a.x, nxt, 64);
+        b.y = __shfl(a.y, nxt, 64);
+        const int first = K ? __builtin_ctzll(K) : 64;
+        const int lastk = K ? 63 - __builtin_clzll(K) : 0;
+        const bool final_chunk = j0 + 64 >= m;
+        int64_t c0 = 0, c1 = 0;
+        if (keep) {
+            if (lane == first && carried) c0 = insdel_parts(cp, a, dmax);
+            if (above) c1 = insdel_parts(a, b, dmax);
+            else if (final_chunk) c1 = 1;      // the edge's last point
+        }
+        const int64_t cnt = c0 + c1;
+        const int64_t incl = wave_incl_scan<int64_t>(cnt, lane);
+        if (WRITE) {
+            int64_t o = base + incl - cnt;
+            for (int64_t t = 0; t < c0; ++t) st2(q + o++, insdel_point(cp, a, t, c0));
+            if (above) {
+                for (int64_t t = 0; t < c1; ++t) st2(q + o++, insdel_point(a, b, t, c1));
+            } else if (c1) {
+                st2(q + o, a);
+            }
+        }
+        base += last_lane(incl);
+        if (K) {
+            carried = true;
+            cp.x = __shfl(a.x, lastk, 64);
+            cp.y = __shfl(a.y, lastk, 64);
+        }
+    }
+    if (!WRITE && lane == 0) d.counts[e] = base;
+}
+
 // Samples of every edge in its histogram tile, one wave per edge, 64 consecutive samples
 // at a time. Counting (SCATTER = false): one atomic per run of samples in the same tile, as
 // k_resample_count does for samples it makes. Binning (SCATTER = true): the run takes its
@@ -309,7 +403,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_samples(const GDesc *__restrict_
     const int lane = threadIdx.x & 63;
     const int64_t bl = blk - d.blk_edge;
     const int64_t e = edge_of(d, bl, wid);
-    if (e < 0 || d.strip) return;
+    if (e < 0 || d.strip || (!SCATTER && !d.count_given)) return;
     HB_G unsigned long long *ctr =
         glb((unsigned long long *)(SCATTER ? d.bin_cur : d.bin_cnt)) + (bl & (d.n_sets - 1)) * d.n_tiles;
     const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
@@ -1071,6 +1165,13 @@ hipError_t launch_resample_count(const GDesc *desc, int ng, const Shape &tot, in
 hipError_t launch_count_given(const GDesc *desc, int ng, const Shape &tot, hipStream_t st) {
     if (tot.edge <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_bin_samples<false>, grid_of(tot.edge), dim3(kBlock), 0, st, desc, ng);
+    return hipGetLastError();
+}
+
+hipError_t launch_insdel(const GDesc *desc, int ng, const Shape &tot, bool write, hipStream_t st) {
+    if (tot.edge <= 0) return hipSuccess;
+    if (write) hipLaunchKernelGGL(k_insdel<true>, grid_of(tot.edge), dim3(kBlock), 0, st, desc, ng);
+    else hipLaunchKernelGGL(k_insdel<false>, grid_of(tot.edge), dim3(kBlock), 0, st, desc, ng);
     return hipGetLastError();
 }
 

@@ -247,6 +247,8 @@ HB_API void hb_default_params(hb_params *p, int32_t grid_w, int32_t grid_h) {
     p->capacity_factor = 2.0f;
     p->directed_offset_px = 0.0f;
     p->splat_mode = HB_SPLAT_POINTS;
+    p->resample_mode = HB_RESAMPLE_UNIFORM;
+    p->delta_min_px = 0.0f;
 }
 
 static hb_status validate(hb_ctx *c, const hb_params *p) {
@@ -289,6 +291,12 @@ static hb_status validate(hb_ctx *c, const hb_params *p) {
         return fail(c, HB_EINVAL, "directed_offset_px must be finite with |value| <= max(W, H) / 16");
     if (p->splat_mode != HB_SPLAT_POINTS && p->splat_mode != HB_SPLAT_STRIP)
         return fail(c, HB_EINVAL, "splat_mode must be HB_SPLAT_POINTS or HB_SPLAT_STRIP");
+    if (p->resample_mode != HB_RESAMPLE_UNIFORM && p->resample_mode != HB_RESAMPLE_INSERT_DELETE)
+        return fail(c, HB_EINVAL, "resample_mode must be HB_RESAMPLE_UNIFORM or HB_RESAMPLE_INSERT_DELETE");
+    if (!std::isfinite(p->delta_min_px) || p->delta_min_px < 0.0f || p->delta_min_px >= p->delta_px)
+        return fail(c, HB_EINVAL, "delta_min_px must be 0 (delta_px / 2) or in (0, delta_px)");
+    if (p->resample_mode == HB_RESAMPLE_INSERT_DELETE && p->directed_offset_px != 0.0f)
+        return fail(c, HB_EINVAL, "the directed offset needs the uniform resampling");
     return HB_OK;
 }
 
@@ -435,6 +443,9 @@ static GDesc base_desc(const hb_ctx *c) {
     d.doff = (double)c->P.directed_offset_px;
     d.strip = c->P.splat_mode == HB_SPLAT_STRIP ? 1 : 0;
     d.ent_cap = c->ent_cap;
+    d.insdel = c->P.resample_mode == HB_RESAMPLE_INSERT_DELETE ? 1 : 0;
+    d.dmin = c->P.delta_min_px > 0.0f ? (double)c->P.delta_min_px : 0.5 * (double)c->P.delta_px;
+    d.count_given = 0;
     for (int k = 0; k < d.P; ++k)
         d.a[k] = c->passw.empty() ? (k == d.P - 1 ? 1.0 : 0.0) : (double)c->passw[k];
     d.group = c->d_group;
@@ -983,6 +994,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
     Shape tot{};
     int max_w = 2, bmax = 1, pmax = 1;
     bool strip = false, points = false;   // graphs with line strips / with the point splat
+    bool insdel = false;                  // graphs with the insert/delete resampling
     for (int g = 0; g < n; ++g) {
         const hb_ctx *c = cs[g];
         base[g] = tot;
@@ -992,6 +1004,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
         pmax = std::max(pmax, c->P.box_passes);
         strip = strip || c->P.splat_mode == HB_SPLAT_STRIP;
         points = points || c->P.splat_mode != HB_SPLAT_STRIP;
+        insdel = insdel || c->P.resample_mode == HB_RESAMPLE_INSERT_DELETE;
     }
     const bool given0 = (flags & HB_RUN_SAMPLES_GIVEN) != 0;
     const bool record = (flags & HB_RUN_RECORD_DECISIONS) != 0;
@@ -1019,6 +1032,8 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
             d.blk_cell = base[g].cell;
             d.record = record && it == T - 1;
             d.bin_src = (d.record && (flags & kRunRecordBins)) ? c->d_binsrc : nullptr;
+            // samples not made by the uniform resampling are counted in tiles afterwards
+            d.count_given = !d.strip && (given || d.insdel);
             d.total = c->d_totals + it;
             if (given) {
                 d.samples = c->pts[ps];
@@ -1058,10 +1073,15 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
             hb_ctx *c = lead;
             const bool given = it == 0 && given0;
             if (!timed) {
+                if (!given && insdel) HIPCHK(c, hb::launch_insdel(dd, n, tot, false, c->stream));
                 if (!given) HIPCHK(c, hb::launch_scan(dd, n, tot, c->stream));
                 HIPCHK(c, hb::launch_clear_hist(dd, n, tot, c->stream));
                 if (given) HIPCHK(c, hb::launch_count_given(dd, n, tot, c->stream));
                 else HIPCHK(c, hb::launch_resample_count(dd, n, tot, ru, c->stream));
+                if (!given && insdel) {
+                    HIPCHK(c, hb::launch_insdel(dd, n, tot, true, c->stream));
+                    HIPCHK(c, hb::launch_count_given(dd, n, tot, c->stream));
+                }
                 if (strip) HIPCHK(c, hb::launch_strip_bins(dd, n, tot, false, c->stream));
                 HIPCHK(c, hb::launch_bin_hist(dd, n, tot, strip, points, c->stream));
                 for (int k = 0; k < pmax; ++k) HIPCHK(c, hb::launch_box_pass(dd, n, tot, max_w, k, c->stream));
@@ -1069,10 +1089,15 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
                 HIPCHK(c, hb::launch_advect_smooth(dd, n, tot, au, c->stream));
                 continue;
             }
+            if (!given && insdel) STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_insdel(dd, n, tot, false, c->stream));
             if (!given) STAGE(c, HB_STAGE_SCAN, hb::launch_scan(dd, n, tot, c->stream));
             STAGE(c, HB_STAGE_CLEAR, hb::launch_clear_hist(dd, n, tot, c->stream));
             if (given) STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_count_given(dd, n, tot, c->stream));
             else STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_resample_count(dd, n, tot, ru, c->stream));
+            if (!given && insdel) {
+                STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_insdel(dd, n, tot, true, c->stream));
+                STAGE(c, HB_STAGE_BIN, hb::launch_count_given(dd, n, tot, c->stream));
+            }
             if (strip) STAGE(c, HB_STAGE_BIN, hb::launch_strip_bins(dd, n, tot, false, c->stream));
             STAGE(c, HB_STAGE_BIN, hb::launch_bin_hist(dd, n, tot, strip, points, c->stream));
             for (int k = 0; k < pmax; ++k)
@@ -1090,7 +1115,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
     for (int g = 0; g < n; ++g) {
         const hb_ctx *c = cs[g];
         key.insert(key.end(), {(int64_t)(intptr_t)c, c->E, c->B, c->P.grid_w, c->P.grid_h,
-                               c->P.box_passes, c->P.splat_mode});
+                               c->P.box_passes, c->P.splat_mode, c->P.resample_mode});
     }
     if (!lead->gexec || key != lead->gkey) {
         if (lead->gexec) {
@@ -1872,6 +1897,8 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
         return fail(c, HB_EINVAL, "the adjoint does not differentiate directed_offset_px (set it to 0)");
     if (c->P.splat_mode != HB_SPLAT_POINTS)
         return fail(c, HB_EINVAL, "the adjoint needs the point splat (splat_mode HB_SPLAT_POINTS)");
+    if (c->P.resample_mode != HB_RESAMPLE_UNIFORM)
+        return fail(c, HB_EINVAL, "the adjoint needs the uniform resampling (resample_mode HB_RESAMPLE_UNIFORM)");
     // earlier checkpoint buffers go back to the pool and are reused when large enough
     for (auto &k : c->ckpts) c->ckpt_pool.push_back(k);
     c->ckpts.clear();

@@ -42,7 +42,8 @@ def test_default_params_are_the_papers():
     ("max_halvings", -2), ("max_halvings", 31), ("smooth_weight", 1.5), ("smooth_passes", 2),
     ("capacity_factor", 1.05), ("h_max_px", float("inf")), ("struct_size", 4), ("n_radii", 0),
     ("directed_offset_px", 4.5), ("directed_offset_px", -4.5), ("directed_offset_px", float("nan")),
-    ("splat_mode", 2), ("splat_mode", -1),
+    ("splat_mode", 2), ("splat_mode", -1), ("resample_mode", 2), ("delta_min_px", 1.0),
+    ("delta_min_px", -0.5),
 ])
 def test_invalid_params_rejected(field, value):
     p, keep = hb.make_params(64, 64, [3])
