@@ -69,6 +69,9 @@ def lib():
             "orc_box_chain": (None, [i32, i32, i32, i32, i32, P, P, i32]),
             "orc_density": (None, [i32, i32, i32, i32, i32, P, P, P, P]),
             "orc_gradient": (None, [i32, i32, i32, P, P]),
+            "orc_kovesi_radii": (None, [f64, i32, P]),
+            "orc_box_chain_radii": (None, [i32, i32, i32, i32, P, P, P, i32]),
+            "orc_density_radii": (None, [i32, i32, i32, i32, P, P, P, P, P]),
             "orc_bilinear": (f64, [i32, i32, P, i32, i32, f64, f64]),
             "orc_advect": (None, [i64, P, P, P, i32, i32, i32, P, P, f64, i32, f64, f64,
                                   P, P, P, P, P]),
@@ -121,9 +124,16 @@ class Params:
     strip_splat: bool = False       # histogram of the drawn line strips instead of the points
     insert_delete: bool = False     # insert/delete resampling instead of the uniform one
     delta_min: Optional[float] = None   # removal spacing of insert/delete (None: delta / 2)
+    sigmas: Optional[List[float]] = None   # sigma per iteration: per-pass radii by Kovesi's rule
 
     def radius(self, it: int) -> int:
         return int(self.radii[min(it, len(self.radii) - 1)])
+
+    def pass_radii(self, it: int) -> List[int]:
+        """Box radius of every pass of iteration it (equal radii, or Kovesi's for a sigma)."""
+        if self.sigmas:
+            return kovesi_radii(self.sigmas[min(it, len(self.sigmas) - 1)], self.passes)
+        return [self.radius(it)] * self.passes
 
     def a(self) -> np.ndarray:
         if self.pass_weights is None:
@@ -135,6 +145,8 @@ class Params:
     def hmax(self) -> float:
         if self.h_max is not None and self.h_max > 0:
             return float(self.h_max)
+        if self.sigmas:
+            return 2.0 * float(self.sigmas[0])
         return 2.0 * sigma(self.radius(0), self.passes)
 
     def bandwidth(self, it: int) -> float:
@@ -280,6 +292,33 @@ def box_integral(m, r):
     out = np.empty_like(m)
     lib().orc_box_integral(W, H, _p(m), r, _p(out))
     return out
+
+
+def kovesi_radii(sig: float, passes: int) -> List[int]:
+    out = np.empty(passes, np.int32)
+    lib().orc_kovesi_radii(float(sig), passes, _p(out))
+    return out.tolist()
+
+
+def box_chain_radii(hist, radii, brute=False):
+    """S[k, b] = pass k+1 of the box chain with radius radii[k] on group b (int64, exact)."""
+    hist = _c(hist, np.int64)
+    B, H, W = hist.shape
+    rr = _c(radii, np.int32)
+    S = np.empty((len(rr), B, H, W), np.int64)
+    lib().orc_box_chain_radii(B, W, H, len(rr), _p(rr), _p(hist), _p(S), 1 if brute else 0)
+    return S
+
+
+def density_radii(S, radii, a, M):
+    S = _c(S, np.int64)
+    P, B, H, W = S.shape
+    rr = _c(radii, np.int32)
+    a = _c(a, np.float64)
+    M = _c(M, np.float64)
+    rho = np.empty((B, H, W), np.float64)
+    lib().orc_density_radii(B, W, H, P, _p(rr), _p(S), _p(a), _p(M), _p(rho))
+    return rho
 
 
 def box_chain(hist, passes, r, brute=False):
@@ -434,8 +473,13 @@ def iterate(off, xy, group, M, p: Params, it: int, weight=None, skip_resample=Fa
         hist = splat_strip(s_off, s_xy, group, B, W, H, weight)
     else:
         hist = splat(s_off, s_xy, group, B, W, H, weight)
-    S = box_chain(hist, p.passes, r)
-    rho = density(S, r, p.a(), M)
+    if p.sigmas:
+        rr = p.pass_radii(it)
+        S = box_chain_radii(hist, rr)
+        rho = density_radii(S, rr, p.a(), M)
+    else:
+        S = box_chain(hist, p.passes, r)
+        rho = density(S, r, p.a(), M)
     g = gradient(rho)
     h = p.bandwidth(it)
     adv = advect(s_off, s_xy, group, rho, g, h, p.max_halvings, p.eps, p.amb_tol)
@@ -462,7 +506,7 @@ def run(node_xy, src, dst, group, M, p: Params, n_iters: int, weight=None):
 def record_run(off, xy, group, M, p: Params, n_iters: int, it0: int = 0, weight=None):
     """Base run from the polylines (off, xy): per iteration, the discrete choices that the
     frozen surrogate replays (sample offsets, segment indices, histograms, decisions)."""
-    if p.directed_offset != 0.0 or p.strip_splat or p.insert_delete:
+    if p.directed_offset != 0.0 or p.strip_splat or p.insert_delete or p.sigmas:
         raise ValueError("the frozen surrogate covers the point splat without a directed offset")
     rec = []
     off = _c(off, np.int64)

@@ -511,6 +511,69 @@ EXPORT void orc_density(int32_t B, int32_t W, int32_t H, int32_t P, int32_t r, c
     }
 }
 
+/* Box widths for a real sigma (the variant of the box chain for a radius that is not an
+ * integer): the P passes mix two odd widths, following Kovesi's rule for almost-Gaussian
+ * filtering with repeated boxes (P. Kovesi, "Fast almost-Gaussian filtering", 2010): the ideal
+ * width w = sqrt(12 sigma^2 / P + 1), w_l the largest odd integer <= w, w_u = w_l + 2, and
+ * m = round((12 sigma^2 - P w_l^2 - 4 P w_l - 3 P) / (-4 w_l - 4)) passes of w_l first, the
+ * other P - m of w_u; radius = (width - 1) / 2. The variance of the chain is
+ * sum_k r_k (r_k + 1) / 3.
+ * Pins: a sigma that equal radii reach exactly gives those radii; the achieved sigma is close
+ * to the requested one; the impulse response of the chain has the stated variance.
+ */
+EXPORT void orc_kovesi_radii(double sigma, int32_t P, int32_t *radii) {
+    double wi = sqrt(12.0 * sigma * sigma / (double)P + 1.0);
+    int64_t wl = (int64_t)floor(wi);
+    if (wl % 2 == 0) wl -= 1;
+    if (wl < 1) wl = 1;
+    int64_t wu = wl + 2;
+    double mi = (12.0 * sigma * sigma - (double)P * (double)(wl * wl) - 4.0 * (double)P * (double)wl -
+                 3.0 * (double)P) / (-4.0 * (double)wl - 4.0);
+    int64_t m = (int64_t)round(mi);
+    if (m < 0) m = 0;
+    if (m > P) m = P;
+    for (int32_t k = 0; k < P; ++k) radii[k] = (int32_t)(((k < m ? wl : wu) - 1) / 2);
+}
+
+/* The box chain and the density with one radius per pass (pass k of radius radii[k]; the
+ * normalisation of pass k is prod_{q <= k} (2 r_q + 1)^2). */
+EXPORT void orc_box_chain_radii(int32_t B, int32_t W, int32_t H, int32_t P, const int32_t *radii,
+                                const int64_t *hist, int64_t *S, int32_t brute) {
+    int64_t plane = (int64_t)W * H;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t kb = 0; kb < B; ++kb) {
+        const int64_t *src = hist + kb * plane;
+        for (int64_t k = 0; k < P; ++k) {
+            int64_t *dst = S + (k * B + kb) * plane;
+            if (brute)
+                orc_box_brute(W, H, src, radii[k], dst);
+            else
+                orc_box_integral(W, H, src, radii[k], dst);
+            src = dst;
+        }
+    }
+}
+
+EXPORT void orc_density_radii(int32_t B, int32_t W, int32_t H, int32_t P, const int32_t *radii,
+                              const int64_t *S, const double *a, const double *M, double *rho) {
+    int64_t plane = (int64_t)W * H;
+#pragma omp parallel for schedule(static)
+    for (int64_t px = 0; px < plane; ++px) {
+        for (int64_t l = 0; l < B; ++l) {
+            double acc = 0.0;
+            for (int64_t b = 0; b < B; ++b) {
+                double sbar = 0.0, ck = 1.0;
+                for (int64_t k = 0; k < P; ++k) {
+                    ck *= (double)(2 * radii[k] + 1) * (double)(2 * radii[k] + 1);
+                    sbar += a[k] * ((double)S[(k * B + b) * plane + px] / ck);
+                }
+                acc += M[l * B + b] * sbar;
+            }
+            rho[l * plane + px] = acc;
+        }
+    }
+}
+
 /* Gradient of the density (Sec. 3.3 Eq. 5). Reading: central differences at pixel
  * centres with zero density outside the grid; grad has [B][H][W][2] entries (gx, gy).
  * Pins: exact on linear maps in the interior; sign and factor 1/2.

@@ -815,3 +815,51 @@ def test_insdel_fixed_point_and_two_point_edges():
     o2, s2, _ = O.resample(off, xy, 1.0)
     np.testing.assert_array_equal(o1, o2)
     np.testing.assert_allclose(s1, s2, atol=1e-9)
+
+
+# ------------------------------------------------------------------ box widths for a real sigma
+
+@pytest.mark.parametrize("P", [2, 3, 4])
+def test_kovesi_radii_equal_when_sigma_is_reachable(P):
+    for r in range(1, 41):
+        s = math.sqrt(P * r * (r + 1) / 3.0)
+        assert O.kovesi_radii(s, P) == [r] * P
+
+
+@pytest.mark.parametrize("P", [3, 4])
+def test_kovesi_radii_closest_two_width_mix(P):
+    for sig in np.linspace(1.0, 60.0, 237):
+        rr = O.kovesi_radii(sig, P)
+        assert rr == sorted(rr) and max(rr) - min(rr) <= 1
+        ach = sum(r * (r + 1) / 3.0 for r in rr)
+        rl = min(rr)
+        # brute force over the mixes of radius rl and rl + 1 (m passes of rl first)
+        best = min(abs(m * rl * (rl + 1) / 3.0 + (P - m) * (rl + 1) * (rl + 2) / 3.0 - sig * sig)
+                   for m in range(P + 1))
+        assert abs(ach - sig * sig) <= best + 1e-9
+        assert abs(math.sqrt(ach) - sig) <= 0.08 * sig + 0.6
+
+
+def test_box_chain_radii_impulse_variance_and_scipy():
+    W = H = 101
+    h = np.zeros((1, H, W), np.int64)
+    h[0, 50, 50] = 1
+    rr = [3, 4, 4]
+    S = O.box_chain_radii(h, rr)
+    out = S[-1, 0].astype(np.float64)
+    assert out.sum() == np.prod([(2 * r + 1) ** 2 for r in rr])
+    u = np.arange(W) - 50
+    var = (out.sum(0) * u * u).sum() / out.sum()
+    assert abs(var - sum(r * (r + 1) / 3.0 for r in rr)) < 1e-9
+    g = rng(61)
+    m = g.integers(0, 5, (1, 37, 45)).astype(np.int64)
+    S2 = O.box_chain_radii(m, [1, 2, 3])
+    ref = m[0].astype(np.float64)
+    for k, r in enumerate([1, 2, 3]):
+        ref = scipy.signal.convolve2d(ref, np.ones((2 * r + 1, 2 * r + 1)), mode="same")
+        np.testing.assert_array_equal(S2[k, 0], np.rint(ref).astype(np.int64))
+    np.testing.assert_array_equal(O.box_chain_radii(m, [2, 2, 2]), O.box_chain(m, 3, 2))
+    a = np.array([0.2, 0.3, 0.5])
+    M = np.ones((1, 1))
+    np.testing.assert_allclose(O.density_radii(O.box_chain(m, 3, 2), [2, 2, 2], a, M),
+                               O.density(O.box_chain(m, 3, 2), 2, a, M), rtol=1e-15)
