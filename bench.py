@@ -16,6 +16,7 @@ Prints one JSON line on stdout; progress goes to stderr.
 import argparse
 import hashlib
 import json
+import math
 import os
 import sys
 import time
@@ -134,12 +135,13 @@ def write_traffic(fetch_csv, write_csv, last, out_path):
     return data
 
 
-def cpu_baseline(w, fraction, strip=False, insdel=False):
+def cpu_baseline(w, fraction, strip=False, insdel=False, sigmas=None):
     import numpy as np
     import oracle as O
     p = O.params_for(w)
     p.strip_splat = strip
     p.insert_delete = insdel
+    p.sigmas = sigmas
     step = max(1, int(round(1.0 / fraction)))
     sel = np.arange(0, w.n_edges, step)
     off, xy = O.initial_state(w.node_xy, w.src[sel], w.dst[sel], p)
@@ -180,6 +182,9 @@ def main():
                     help="histogram of the sample points (default) or of the drawn line strips")
     ap.add_argument("--resample", choices=("uniform", "insdel"), default="uniform",
                     help="uniform resampling (default) or the insert/delete variant")
+    ap.add_argument("--sigma-offset", type=float, default=0.0,
+                    help="smooth with a real sigma per iteration, sigma(r_i) + this offset in px, "
+                         "by boxes of two widths (Kovesi's rule) instead of equal radii")
     ap.add_argument("--grouping", action="store_true",
                     help="measure the grouping step instead: k-means on the origin-destination "
                          "features of the edges and the choice of B (one JSON line)")
@@ -241,7 +246,11 @@ def main():
     # point buffers up front so no buffer growth (and iteration replay) lands in the timed run
     splat_mode = hb.HB_SPLAT_STRIP if args.splat == "strip" else hb.HB_SPLAT_POINTS
     resample_mode = hb.HB_RESAMPLE_INSERT_DELETE if args.resample == "insdel" else hb.HB_RESAMPLE_UNIFORM
-    b.set_workload(w, capacity_factor=args.capacity, splat_mode=splat_mode, resample_mode=resample_mode)
+    sigmas = None
+    if args.sigma_offset != 0.0:
+        sigmas = [math.sqrt(w.passes * r * (r + 1) / 3.0) + args.sigma_offset for r in w.radii]
+    b.set_workload(w, capacity_factor=args.capacity, splat_mode=splat_mode, resample_mode=resample_mode,
+                   sigmas=sigmas)
     log(f"warmup: {args.warmup} iterations")
     if args.warmup:
         b.run(args.warmup)
@@ -284,14 +293,14 @@ def main():
             per_stage_gbs[k] = round(stage_bytes(k, w, counts, n_state0) / (ms * 1e-3) / 1e9, 1)
 
     fwd_bwd = None
-    if args.grad_iters > 0 and args.splat == "points" and args.resample == "uniform":
+    if args.grad_iters > 0 and args.splat == "points" and args.resample == "uniform" and not sigmas:
         fwd_bwd = grad_ratio(hb, w, args.grad_iters, args.capacity)
         log(f"fwd+bwd / plain over {args.grad_iters} iterations: {fwd_bwd['ratio']:.2f}")
 
     cpu = None
     if args.cpu_fraction > 0:
         log(f"cpu baseline: oracle on {args.cpu_fraction:.0%} of the edges")
-        cpu = cpu_baseline(w, args.cpu_fraction, args.splat == "strip", args.resample == "insdel")
+        cpu = cpu_baseline(w, args.cpu_fraction, args.splat == "strip", args.resample == "insdel", sigmas)
         log(f"  {cpu['value'] / 1e6:.2f} M edge-points/s on {cpu['cores']} threads")
 
     out = {
@@ -308,7 +317,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": w.name + ("-strip" if args.splat == "strip" else "")
-                   + ("-insdel" if args.resample == "insdel" else ""),
+                   + ("-insdel" if args.resample == "insdel" else "")
+                   + ("-sigma" if sigmas else ""),
+                   "sigma_offset_px": args.sigma_offset,
                    "splat": args.splat, "resample": args.resample, "edges": w.n_edges, "groups": w.n_groups,
                    "grid": [w.grid_w, w.grid_h], "delta_px": w.delta, "box_passes": w.passes,
                    "radius_first": w.radii[0], "iterations_timed": args.steps,

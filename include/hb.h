@@ -156,6 +156,17 @@ typedef struct hb_params {
                                    (FP64). Needs directed_offset_px = 0; not differentiated. */
     float delta_min_px;         /* removal spacing of HB_RESAMPLE_INSERT_DELETE; 0 (default):
                                    delta_px / 2; else in (0, delta_px) */
+    int32_t n_sigmas;           /* 0 (default): the box radius of every pass is radius_per_iter.
+                                   > 0: length of sigma_per_iter, which then replaces the radius
+                                   list: iteration i smooths with a real sigma_i (the last value
+                                   repeats) by P boxes of two odd widths w_l and w_l + 2 chosen
+                                   by Kovesi's rule (ideal width w = sqrt(12 sigma^2 / P + 1),
+                                   w_l the largest odd integer <= w, m = round((12 sigma^2 -
+                                   P w_l^2 - 4 P w_l - 3 P) / (-4 w_l - 4)) passes of w_l first);
+                                   pass k is normalised by prod_{q<=k} (2 r_q + 1)^2 and h_max
+                                   defaults to 2 sigma_0. Every width must fit the grid. Not
+                                   differentiated (hb_forward_ckpt requires 0). */
+    const float *sigma_per_iter; /* sigma_i in pixels (finite, > 0); copied by hb_set_params */
 } hb_params;
 
 /* Fill p with the paper's defaults for a W x H grid: bbox [0,0,1,1], delta 1 px, P = 3,

@@ -63,6 +63,8 @@ class hb_params(ctypes.Structure):
         ("splat_mode", ctypes.c_int32),
         ("resample_mode", ctypes.c_int32),
         ("delta_min_px", ctypes.c_float),
+        ("n_sigmas", ctypes.c_int32),
+        ("sigma_per_iter", ctypes.POINTER(ctypes.c_float)),
     ]
 
 
@@ -437,7 +439,8 @@ def make_params(grid_w: int, grid_h: int, radii: Sequence[int], *, delta: float 
                 max_halvings: int = 8, smooth_weight: float = 0.5,
                 pass_weights: Optional[Sequence[float]] = None, bbox=(0.0, 0.0, 1.0, 1.0),
                 capacity_factor: float = 2.0, directed_offset: float = 0.0,
-                splat_mode: int = 0, resample_mode: int = 0, delta_min: float = 0.0):
+                splat_mode: int = 0, resample_mode: int = 0, delta_min: float = 0.0,
+                sigmas: Optional[Sequence[float]] = None):
     """hb_params plus the arrays it points to (keep both alive until hb_set_params)."""
     p = hb_default_params(grid_w, grid_h)
     r = (ctypes.c_int32 * len(radii))(*[int(v) for v in radii])
@@ -458,6 +461,11 @@ def make_params(grid_w: int, grid_h: int, radii: Sequence[int], *, delta: float 
     p.resample_mode = resample_mode
     p.delta_min_px = delta_min
     keep = [r]
+    if sigmas:
+        sg = (ctypes.c_float * len(sigmas))(*[float(v) for v in sigmas])
+        p.sigma_per_iter = ctypes.cast(sg, ctypes.POINTER(ctypes.c_float))
+        p.n_sigmas = len(sigmas)
+        keep.append(sg)
     if pass_weights is not None:
         a = (ctypes.c_float * passes)(*[float(v) for v in pass_weights])
         p.pass_weights = ctypes.cast(a, ctypes.POINTER(ctypes.c_float))

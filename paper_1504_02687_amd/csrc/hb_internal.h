@@ -83,7 +83,8 @@ struct GDesc {
     double dmin;                // removal spacing of the insert/delete resampling
     int64_t ent_cap;            // capacity of bins, in entries (cap for the point splat)
     double a[HB_MAX_PASSES];    // density weight of each pass
-    double ck[HB_MAX_PASSES];   // (2r+1)^(2k), k = 1..P
+    double ck[HB_MAX_PASSES];   // prod_{q<=k} (2 r_q + 1)^2: the normalisation of pass k
+    int32_t rp[HB_MAX_PASSES];  // box radius of every pass
 
     const int32_t *perm;        // visiting order of the edges (nullptr: 0..E-1)
     const int32_t *order;       // edge order of the advection kernels (by group, then position;

@@ -114,10 +114,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_top(const GDesc *__restrict__ g
         if (carry > d.cap) st |= ST_POINT_OVERFLOW;
         double wsum = (double)carry * (double)d.wmax;
         double grow = 1.0;
-        for (int k = 1; k < d.P; ++k) grow *= (double)(2 * d.r + 1) * (double)(2 * d.r + 1);
+        for (int k = 1; k < d.P; ++k) grow *= (double)(2 * d.rp[k] + 1) * (double)(2 * d.rp[k] + 1);
         // int32 counts: no pixel can reach 2^32 while N w < 2^32, so a pixel that passes 2^31
         // shows up as a negative count in the first row pass; int64 box sums stay below
-        // N w (2r+1)^(2(P-1)).
+        // N w prod_{k>=1} (2 r_k + 1)^2 (a first pass never exceeds the total).
         if (wsum >= 4294967295.0 || wsum * grow >= 9.2e18) st |= ST_HIST_OVERFLOW;
         if (st) atomicOr(d.status, st);
     }
@@ -583,7 +583,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_scan(const GDesc *__restrict__ g
             if (base_off > d.ent_cap) st |= ST_ENTRY_OVERFLOW;
             const double wsum = (double)base_off * (double)d.wmax;
             double grow = 1.0;
-            for (int k = 1; k < d.P; ++k) grow *= (double)(2 * d.r + 1) * (double)(2 * d.r + 1);
+            for (int k = 1; k < d.P; ++k) grow *= (double)(2 * d.rp[k] + 1) * (double)(2 * d.rp[k] + 1);
             if (wsum >= 4294967295.0 || wsum * grow >= 9.2e18) st |= ST_HIST_OVERFLOW;
             if (st) atomicOr(d.status, st);
         } else if (base_off != d.off_s[d.n_edges] || base_off > d.ent_cap) {
@@ -669,7 +669,7 @@ __global__ __launch_bounds__(kBlock) void k_box_rows(const GDesc *__restrict__ g
     HB_FIND(blk_row);
     if (stopped(d) || pass >= d.P) return;
     const int64_t row = blk - d.blk_row;
-    const int W = d.W, r = d.r;
+    const int W = d.W, r = d.rp[pass];
     const int64_t plane = (int64_t)d.B * d.W * d.H;
     if (pass == 0) {
         bool bad = false;
@@ -717,7 +717,7 @@ __global__ __launch_bounds__(kBlock) void k_box_cols(const GDesc *__restrict__ g
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_col);
     if (stopped(d) || pass >= d.P) return;
-    const int W = d.W, H = d.H, r = d.r;
+    const int W = d.W, H = d.H, r = d.rp[pass];
     const int nseg = (H + kColSeg - 1) / kColSeg;
     const int64_t t = (blk - d.blk_col) * kBlock + threadIdx.x;
     if (t >= (int64_t)d.B * nseg * W) return;

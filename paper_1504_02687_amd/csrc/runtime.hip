@@ -32,6 +32,7 @@ struct hb_ctx {
     // parameters
     hb_params P{};
     std::vector<int32_t> radii;
+    std::vector<float> sigmas;           // sigma per iteration (Kovesi widths), or empty
     std::vector<float> passw;
     bool have_params = false;
 
@@ -249,7 +250,11 @@ HB_API void hb_default_params(hb_params *p, int32_t grid_w, int32_t grid_h) {
     p->splat_mode = HB_SPLAT_POINTS;
     p->resample_mode = HB_RESAMPLE_UNIFORM;
     p->delta_min_px = 0.0f;
+    p->n_sigmas = 0;
+    p->sigma_per_iter = nullptr;
 }
+
+static void kovesi_radii(double sigma, int P, int32_t *radii);
 
 static hb_status validate(hb_ctx *c, const hb_params *p) {
     if (!p) return fail(c, HB_EINVAL, "params is NULL");
@@ -265,13 +270,26 @@ static hb_status validate(hb_ctx *c, const hb_params *p) {
         return fail(c, HB_EINVAL, "delta_px must be positive");
     if (p->box_passes < 1 || p->box_passes > HB_MAX_PASSES)
         return fail(c, HB_EINVAL, "box_passes out of range [1, 8]");
-    if (p->n_radii < 1 || !p->radius_per_iter)
-        return fail(c, HB_EINVAL, "radius_per_iter needs at least one value");
     const int side = std::min(p->grid_w, p->grid_h);
-    for (int i = 0; i < p->n_radii; ++i) {
-        int r = p->radius_per_iter[i];
-        if (r < 0 || 2 * r + 1 > side)
-            return fail(c, HB_EINVAL, "box radius must satisfy 0 <= r and 2r+1 <= min(W, H)");
+    if (p->n_sigmas < 0) return fail(c, HB_EINVAL, "n_sigmas must be >= 0");
+    if (p->n_sigmas > 0) {
+        if (!p->sigma_per_iter) return fail(c, HB_EINVAL, "sigma_per_iter is NULL");
+        for (int i = 0; i < p->n_sigmas; ++i) {
+            const float s = p->sigma_per_iter[i];
+            if (!std::isfinite(s) || !(s > 0.0f)) return fail(c, HB_EINVAL, "sigma_per_iter must be finite and > 0");
+            int32_t rp[HB_MAX_PASSES];
+            kovesi_radii((double)s, std::max(1, std::min(p->box_passes, HB_MAX_PASSES)), rp);
+            for (int k = 0; k < std::max(1, std::min(p->box_passes, HB_MAX_PASSES)); ++k)
+                if (2 * rp[k] + 1 > side) return fail(c, HB_EINVAL, "box width of a sigma exceeds min(W, H)");
+        }
+    } else {
+        if (p->n_radii < 1 || !p->radius_per_iter)
+            return fail(c, HB_EINVAL, "radius_per_iter needs at least one value");
+        for (int i = 0; i < p->n_radii; ++i) {
+            int r = p->radius_per_iter[i];
+            if (r < 0 || 2 * r + 1 > side)
+                return fail(c, HB_EINVAL, "box radius must satisfy 0 <= r and 2r+1 <= min(W, H)");
+        }
     }
     if (!std::isfinite(p->h_max_px)) return fail(c, HB_EINVAL, "h_max_px is not finite");
     if (!(p->lambda > 0.0f) || p->lambda > 1.0f) return fail(c, HB_EINVAL, "lambda must be in (0, 1]");
@@ -306,8 +324,34 @@ static int radius_at(const hb_ctx *c, int it) {
     return c->radii[std::min<size_t>((size_t)it, c->radii.size() - 1)];
 }
 
+// Kovesi's two-width rule (Kovesi, "Fast almost-Gaussian filtering", 2010): P passes of odd
+// widths w_l and w_l + 2 whose variances add up closest to sigma^2; radii = (width - 1) / 2.
+static void kovesi_radii(double sigma, int P, int32_t *radii) {
+    const double wi = std::sqrt(12.0 * sigma * sigma / (double)P + 1.0);
+    int64_t wl = (int64_t)std::floor(wi);
+    if (wl % 2 == 0) wl -= 1;
+    if (wl < 1) wl = 1;
+    const int64_t wu = wl + 2;
+    const double mi = (12.0 * sigma * sigma - (double)P * (double)(wl * wl) - 4.0 * (double)P * (double)wl -
+                       3.0 * (double)P) / (-4.0 * (double)wl - 4.0);
+    int64_t m = (int64_t)std::round(mi);
+    m = std::min<int64_t>(std::max<int64_t>(m, 0), P);
+    for (int k = 0; k < P; ++k) radii[k] = (int32_t)(((k < m ? wl : wu) - 1) / 2);
+}
+
+// Box radius of every pass of iteration it.
+static void pass_radii(const hb_ctx *c, int it, int32_t *rp) {
+    const int P = c->P.box_passes;
+    if (!c->sigmas.empty()) {
+        kovesi_radii((double)c->sigmas[std::min<size_t>((size_t)it, c->sigmas.size() - 1)], P, rp);
+        return;
+    }
+    for (int k = 0; k < P; ++k) rp[k] = radius_at(c, it);
+}
+
 static double hmax_of(const hb_ctx *c) {
     if (c->P.h_max_px > 0.0f) return (double)c->P.h_max_px;
+    if (!c->sigmas.empty()) return 2.0 * (double)c->sigmas[0];
     return 2.0 * sigma_of(radius_at(c, 0), c->P.box_passes);
 }
 
@@ -484,12 +528,12 @@ static GDesc base_desc(const hb_ctx *c) {
 }
 
 static void set_iter_scalars(const hb_ctx *c, GDesc &d, int it) {
-    d.r = radius_at(c, it);
+    pass_radii(c, it, d.rp);
+    d.r = d.rp[d.P - 1];
     d.h = bandwidth_at(c, it);
-    const double w = (double)(2 * d.r + 1) * (double)(2 * d.r + 1);
     double ck = 1.0;
     for (int k = 0; k < d.P; ++k) {
-        ck *= w;
+        ck *= (double)(2 * d.rp[k] + 1) * (double)(2 * d.rp[k] + 1);
         d.ck[k] = ck;
     }
 }
@@ -681,11 +725,20 @@ HB_API hb_status hb_set_params(hb_ctx *c, const hb_params *p) {
     if (c->have_graph && (p->grid_w != c->P.grid_w || p->grid_h != c->P.grid_h))
         c->have_samples = false;
     c->P = *p;
-    c->radii.assign(p->radius_per_iter, p->radius_per_iter + p->n_radii);
+    if (p->n_sigmas > 0) {
+        c->sigmas.assign(p->sigma_per_iter, p->sigma_per_iter + p->n_sigmas);
+        int32_t rp[HB_MAX_PASSES];
+        kovesi_radii((double)c->sigmas[0], p->box_passes, rp);
+        c->radii.assign(1, rp[p->box_passes - 1]);
+    } else {
+        c->sigmas.clear();
+        c->radii.assign(p->radius_per_iter, p->radius_per_iter + p->n_radii);
+    }
     c->passw.clear();
     if (p->pass_weights) c->passw.assign(p->pass_weights, p->pass_weights + p->box_passes);
     c->P.radius_per_iter = nullptr;
     c->P.pass_weights = nullptr;
+    c->P.sigma_per_iter = nullptr;
     if (c->P.capacity_factor == 0.0f) c->P.capacity_factor = 2.0f;
     c->have_params = true;
     c->ckpt_end_iter = -1;
@@ -1899,6 +1952,8 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
         return fail(c, HB_EINVAL, "the adjoint needs the point splat (splat_mode HB_SPLAT_POINTS)");
     if (c->P.resample_mode != HB_RESAMPLE_UNIFORM)
         return fail(c, HB_EINVAL, "the adjoint needs the uniform resampling (resample_mode HB_RESAMPLE_UNIFORM)");
+    if (!c->sigmas.empty())
+        return fail(c, HB_EINVAL, "the adjoint needs one box radius per iteration (n_sigmas = 0)");
     // earlier checkpoint buffers go back to the pool and are reused when large enough
     for (auto &k : c->ckpts) c->ckpt_pool.push_back(k);
     c->ckpts.clear();

@@ -66,6 +66,17 @@ def test_fixed_step_mode_accepted():
     assert hb.hb_validate_params(p) == hb.HB_OK
 
 
+def test_sigma_schedule_checks():
+    p, keep = hb.make_params(64, 64, [3], sigmas=[2.5, 1.0])
+    assert hb.hb_validate_params(p) == hb.HB_OK
+    for bad in ([0.0], [float("nan")], [40.0]):          # 40 px needs boxes wider than 64
+        p, keep = hb.make_params(64, 64, [3], sigmas=bad)
+        assert hb.hb_validate_params(p) == hb.HB_EINVAL, bad
+    p, keep = hb.make_params(64, 64, [3])
+    p.n_sigmas = 1                                      # NULL sigma list
+    assert hb.hb_validate_params(p) == hb.HB_EINVAL
+
+
 def test_directed_offset_range():
     # |offset| <= max(W, H) / 16: 4 px on a 64 x 32 grid
     for v in (0.0, 0.5, -4.0, 4.0):
