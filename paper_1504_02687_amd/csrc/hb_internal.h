@@ -80,6 +80,7 @@ struct GDesc {
     int32_t strip;              // 1: histogram of the drawn line strips (entries per pixel drawn)
     int32_t insdel;             // 1: insert/delete resampling (k_insdel) instead of the uniform one
     int32_t count_given;        // 1: k_bin_samples<false> counts this graph's samples in tiles
+    int32_t narrow;             // 1: unit edge weights, entries are 16-bit (pixel in the tile only)
     double dmin;                // removal spacing of the insert/delete resampling
     int64_t ent_cap;            // capacity of bins, in entries (cap for the point splat)
     double a[HB_MAX_PASSES];    // density weight of each pass
@@ -117,6 +118,7 @@ struct GDesc {
     int64_t *tile_off;          // [n_tiles + 1] first entry of each tile
     int64_t *seg_off;           // [n_tiles + 1] first work item (kSegEntries entries) of each tile
     uint32_t *bins;             // [ent_cap] entries: pixel in tile | edge weight << kLocalBits
+                                // (narrow: [ent_cap] uint16 pixels in tile, weight 1)
     uint32_t *bin_src;          // [cap] sample of each entry (runs that record it; else null)
     int64_t *box;               // [P][B][H][W]
     int64_t *tmp;               // [B][H][W] row-pass output

@@ -446,7 +446,8 @@ __global__ __launch_bounds__(kBlock) void k_bin_samples(const GDesc *__restrict_
                 if (lane < cnt[u]) {
                     const unsigned long long pos = b0 + (unsigned long long)(lane - h);
                     if (pos < (unsigned long long)d.ent_cap) {
-                        bins[pos] = loc[u] | wbits;
+                        if (d.narrow) ((HB_G uint16_t *)bins)[pos] = (uint16_t)loc[u];
+                        else bins[pos] = loc[u] | wbits;
                         if (d.bin_src) d.bin_src[pos] = (uint32_t)(o0 + j0 + 64 * u + lane);
                     } else {
                         atomicOr(d.status, ST_BIN_MISMATCH);
@@ -535,7 +536,10 @@ __global__ __launch_bounds__(kBlock) void k_strip_bins(const GDesc *__restrict__
                 if (act) {
                     const uint64_t before = am & below & ~(h == 0 ? 0ull : (~0ull >> (64 - h)));
                     const unsigned long long pos = b0 + (unsigned long long)__builtin_popcountll(before);
-                    if (pos < (unsigned long long)d.ent_cap) bins[pos] = loc | wbits;
+                    if (pos < (unsigned long long)d.ent_cap) {
+                        if (d.narrow) ((HB_G uint16_t *)bins)[pos] = (uint16_t)loc;
+                        else bins[pos] = loc | wbits;
+                    }
                     else atomicOr(d.status, ST_BIN_MISMATCH);
                 }
             }
@@ -619,17 +623,31 @@ __global__ __launch_bounds__(kBlock) void k_tile_hist(const GDesc *__restrict__ 
         for (int i = threadIdx.x; i < kTilePx; i += kBlock) lh[i] = 0;
         __syncthreads();
         int64_t i = beg + threadIdx.x;
-        for (; i + 3 * kBlock < end; i += 4 * kBlock) {
-            const uint32_t a0 = bins[i], a1 = bins[i + kBlock];
-            const uint32_t a2 = bins[i + 2 * kBlock], a3 = bins[i + 3 * kBlock];
-            atomicAdd(&lh[a0 & (kTilePx - 1)], (int32_t)(a0 >> kLocalBits));
-            atomicAdd(&lh[a1 & (kTilePx - 1)], (int32_t)(a1 >> kLocalBits));
-            atomicAdd(&lh[a2 & (kTilePx - 1)], (int32_t)(a2 >> kLocalBits));
-            atomicAdd(&lh[a3 & (kTilePx - 1)], (int32_t)(a3 >> kLocalBits));
-        }
-        for (; i < end; i += kBlock) {
-            const uint32_t a0 = bins[i];
-            atomicAdd(&lh[a0 & (kTilePx - 1)], (int32_t)(a0 >> kLocalBits));
+        if (d.narrow) {
+            // unit weights: 16-bit entries, one count each
+            const HB_G uint16_t *__restrict__ b16 = (const HB_G uint16_t *)bins;
+            for (; i + 3 * kBlock < end; i += 4 * kBlock) {
+                const uint32_t a0 = b16[i], a1 = b16[i + kBlock];
+                const uint32_t a2 = b16[i + 2 * kBlock], a3 = b16[i + 3 * kBlock];
+                atomicAdd(&lh[a0 & (kTilePx - 1)], 1);
+                atomicAdd(&lh[a1 & (kTilePx - 1)], 1);
+                atomicAdd(&lh[a2 & (kTilePx - 1)], 1);
+                atomicAdd(&lh[a3 & (kTilePx - 1)], 1);
+            }
+            for (; i < end; i += kBlock) atomicAdd(&lh[b16[i] & (kTilePx - 1)], 1);
+        } else {
+            for (; i + 3 * kBlock < end; i += 4 * kBlock) {
+                const uint32_t a0 = bins[i], a1 = bins[i + kBlock];
+                const uint32_t a2 = bins[i + 2 * kBlock], a3 = bins[i + 3 * kBlock];
+                atomicAdd(&lh[a0 & (kTilePx - 1)], (int32_t)(a0 >> kLocalBits));
+                atomicAdd(&lh[a1 & (kTilePx - 1)], (int32_t)(a1 >> kLocalBits));
+                atomicAdd(&lh[a2 & (kTilePx - 1)], (int32_t)(a2 >> kLocalBits));
+                atomicAdd(&lh[a3 & (kTilePx - 1)], (int32_t)(a3 >> kLocalBits));
+            }
+            for (; i < end; i += kBlock) {
+                const uint32_t a0 = bins[i];
+                atomicAdd(&lh[a0 & (kTilePx - 1)], (int32_t)(a0 >> kLocalBits));
+            }
         }
         __syncthreads();
         const int layer = t / per_layer, rem = t - layer * per_layer;

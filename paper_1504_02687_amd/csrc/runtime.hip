@@ -256,6 +256,11 @@ HB_API void hb_default_params(hb_params *p, int32_t grid_w, int32_t grid_h) {
 
 static void kovesi_radii(double sigma, int P, int32_t *radii);
 
+// 16-bit splat entries for graphs whose edges all weigh 1
+#ifndef HB_NARROW_ENTRIES
+#define HB_NARROW_ENTRIES 1
+#endif
+
 static hb_status validate(hb_ctx *c, const hb_params *p) {
     if (!p) return fail(c, HB_EINVAL, "params is NULL");
     if (p->struct_size != sizeof(hb_params))
@@ -488,6 +493,7 @@ static GDesc base_desc(const hb_ctx *c) {
     d.strip = c->P.splat_mode == HB_SPLAT_STRIP ? 1 : 0;
     d.ent_cap = c->ent_cap;
     d.insdel = c->P.resample_mode == HB_RESAMPLE_INSERT_DELETE ? 1 : 0;
+    d.narrow = (HB_NARROW_ENTRIES && c->wmax == 1) ? 1 : 0;
     d.dmin = c->P.delta_min_px > 0.0f ? (double)c->P.delta_min_px : 0.5 * (double)c->P.delta_px;
     d.count_given = 0;
     for (int k = 0; k < d.P; ++k)
