@@ -879,6 +879,48 @@ __global__ __launch_bounds__(kBlock) void k_cells(const GDesc *__restrict__ gd, 
 #define HB_TRIES_PER_ROUND 2
 #endif
 constexpr int kTriesPerRound = HB_TRIES_PER_ROUND;
+constexpr float kRoundScale = 1.0f / (float)(1 << HB_TRIES_PER_ROUND);   // step ratio per round
+
+// One round of step halvings k .. k + kTriesPerRound - 1 (step mf, mf/2, ...) for UU
+// sub-chunks: every candidate of the round is loaded first, then the first candidate whose
+// FP32 bilinear density is not lower than r0 is accepted (jj = its halving, act cleared).
+template <int UU>
+__device__ __forceinline__ void halving_round(const HB_G Quad *__restrict__ rho, const float2 *x,
+                                              const float *dx, const float *dy, const float *r0,
+                                              bool *act, int *jj, int k, int K, float mf,
+                                              float xmaxf, float ymaxf, int W, int H) {
+    Cell c[kTriesPerRound][UU];
+    Quad q[kTriesPerRound][UU];
+    float mt = mf;
+#pragma unroll
+    for (int i = 0; i < kTriesPerRound; ++i) {
+#pragma unroll
+        for (int u = 0; u < UU; ++u) {
+            const float cx = __builtin_amdgcn_fmed3f(__builtin_fmaf(mt, dx[u], x[u].x), 0.0f, xmaxf);
+            const float cy = __builtin_amdgcn_fmed3f(__builtin_fmaf(mt, dy[u], x[u].y), 0.0f, ymaxf);
+            c[i][u] = cell_of(cx, cy, W, H);
+        }
+        mt *= 0.5f;
+    }
+#pragma unroll
+    for (int i = 0; i < kTriesPerRound; ++i)
+#pragma unroll
+        for (int u = 0; u < UU; ++u)
+            if (act[u] && k + i <= K) q[i][u] = ldq(rho, c[i][u].c);
+#pragma unroll
+    for (int i = 0; i < kTriesPerRound; ++i) {
+#pragma unroll
+        for (int u = 0; u < UU; ++u) {
+            if (act[u] && k + i <= K && interp1q(q[i][u], c[i][u]) >= r0[u]) {
+                jj[u] = k + i;
+                act[u] = false;
+            }
+        }
+    }
+    // no load of this round is left in flight (a lane that skipped its test skipped the wait
+    // as well): the next round's loads then go out without waiting
+    vm_wait_all();
+}
 
 // One wave per edge. Each trip handles U sub-chunks of 62 output points with a one-point
 // halo on each side (U independent gather chains in flight): lane l of sub-chunk u
@@ -972,43 +1014,24 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
         // wins, so the decisions are those of testing one halving after the other, with
         // fewer dependent round trips to memory; the accepted point is recomputed in FP64
         float mf = (float)h;
-        for (int k = 0; k <= K; k += kTriesPerRound) {
+        int k = 0;
+        if (K >= 0) {
+            bool any = false;
+#pragma unroll
+            for (int u = 0; u < U; ++u) any |= act[u];
+            if (__any(any)) {
+                halving_round<U>(rho, x, dx, dy, r0, act, jj, 0, K, mf, xmaxf, ymaxf, W, H);
+                k = kTriesPerRound;
+                mf *= kRoundScale;
+            }
+        }
+        for (; k <= K; k += kTriesPerRound) {
             bool any = false;
 #pragma unroll
             for (int u = 0; u < U; ++u) any |= act[u];
             if (!__any(any)) break;
-            Cell c[kTriesPerRound][U];
-            Quad q[kTriesPerRound][U];
-            float mt = mf;
-#pragma unroll
-            for (int i = 0; i < kTriesPerRound; ++i) {
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const float cx = __builtin_amdgcn_fmed3f(__builtin_fmaf(mt, dx[u], x[u].x), 0.0f, xmaxf);
-                    const float cy = __builtin_amdgcn_fmed3f(__builtin_fmaf(mt, dy[u], x[u].y), 0.0f, ymaxf);
-                    c[i][u] = cell_of(cx, cy, W, H);
-                }
-                mt *= 0.5f;
-            }
-#pragma unroll
-            for (int i = 0; i < kTriesPerRound; ++i)
-#pragma unroll
-                for (int u = 0; u < U; ++u)
-                    if (act[u] && k + i <= K) q[i][u] = ldq(rho, c[i][u].c);
-#pragma unroll
-            for (int i = 0; i < kTriesPerRound; ++i) {
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    if (act[u] && k + i <= K && interp1q(q[i][u], c[i][u]) >= r0[u]) {
-                        jj[u] = k + i;
-                        act[u] = false;
-                    }
-                }
-            }
-            // no load of this round is left in flight (a lane that skipped its test skipped
-            // the wait as well): the next round's loads then go out without waiting
-            vm_wait_all();
-            mf = mt;
+            halving_round<U>(rho, x, dx, dy, r0, act, jj, k, K, mf, xmaxf, ymaxf, W, H);
+            mf *= kRoundScale;
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1045,7 +1068,13 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
             if (lane == 1) yl = yprev;
             // each lane sums its own segments, in the same order whatever U; one wave sum at
             // the end of the edge
-            if (out && j >= 1) Lp += seg_len(yl, y[u]);
+            if (out && j >= 1) {
+                // next sample count: a relative error of 1e-15 per segment only matters for
+                // lengths within rounding of a multiple of delta, where either count is valid
+                double len, rcp;
+                seg_len_rcp(yl, y[u], len, rcp);
+                Lp += len;
+            }
             yprev.x = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y[u].x), 62));
             yprev.y = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y[u].y), 62));
         }
