@@ -394,6 +394,11 @@ __global__ __launch_bounds__(kBlock) void k_insdel(const GDesc *__restrict__ gd,
 // k_resample_count does for samples it makes. Binning (SCATTER = true): the run takes its
 // place from the write cursor of its tile and set (returning atomic) and stores one entry
 // per sample. Both passes map an edge to the same block, so to the same counter set.
+#ifndef HB_BIN_CHUNKS
+#define HB_BIN_CHUNKS 8
+#endif
+constexpr int kBinChunks = HB_BIN_CHUNKS;
+
 template <bool SCATTER>
 __global__ __launch_bounds__(kBlock) void k_bin_samples(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
@@ -411,8 +416,8 @@ __global__ __launch_bounds__(kBlock) void k_bin_samples(const GDesc *__restrict_
     const uint32_t wbits = (uint32_t)(d.weight ? d.weight[e] : 1) << kLocalBits;
     const HB_G float2 *__restrict__ xs = glb(d.samples + o0);
     HB_G uint32_t *bins = glb(d.bins);
-    // four chunks per trip: their atomics are in flight together
-    constexpr int U = 4;
+    // kBinChunks chunks per trip: their atomics are in flight together
+    constexpr int U = kBinChunks;
     for (int64_t j0 = 0; j0 < n; j0 += 64 * U) {
         int key[U], cnt[U];
         uint32_t loc[U];
