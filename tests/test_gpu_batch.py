@@ -155,3 +155,24 @@ def test_batch_argument_errors(hb):
         assert ei.value.status == hb.HB_EINVAL
         with pytest.raises(hb.HBError):
             hb.batch_run([a], 1, hb.HB_RUN_SAMPLES_GIVEN)
+
+
+@pytest.mark.parametrize("mode", ["strip", "insdel", "sigma"])
+def test_graph_replay_matches_eager_in_variant_modes(hb, mode):
+    """The captured iteration holds the kernels of the chosen modes (line strips, insert/delete
+    resampling, per-pass radii) and replays them like eager runs, with eager work between."""
+    w = workloads.scaled("clustered", n_edges=3000, grid=256, groups=2, n_iters=3, seed=22)
+    kw = {"strip": dict(splat_mode=hb.HB_SPLAT_STRIP),
+          "insdel": dict(resample_mode=hb.HB_RESAMPLE_INSERT_DELETE),
+          "sigma": dict(sigmas=[3.7, 2.9])}[mode]
+    with hb.Bundler(0) as b:
+        b.set_workload(w, **kw)
+        b.run(2)
+        ref = snapshot(hb, b, w)
+    with hb.Bundler(0) as b, hb.Bundler(0) as other:
+        other.set_workload(w)
+        for rep in range(3):
+            b.set_workload(w, **kw)
+            b.run(2, hb.HB_RUN_GRAPH)
+            assert_same(snapshot(hb, b, w), ref)
+            other.run(1)
