@@ -213,6 +213,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
     if (lane == 0 && mbig > 0.0f) atomicMax(d.mvmax, __float_as_uint(mbig));
 }
 
+// Threads of a k_adj_params block: its (64 + 2)^2 LDS grid of two 64-bit sums (70 KB) allows
+// two blocks per CU, so a block of eight waves keeps sixteen waves per CU in flight.
+constexpr int kParBlock = 512;
+constexpr int kParWaves = kParBlock / 64;
+
 // Parameter gradients, tile by tile. A moved sample p contributes m v_p . g(x_p), g the
 // bilinear sample of a gradient-map record (Eq. 3 differentiated with respect to M and a);
 // summed by pixel instead, that is the sum over pixels of A(px) . record(px), with
@@ -223,11 +228,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
 // contracts the grid with the records in FP64 and writes the item's B + P partial sums; all
 // reductions run in a fixed order, so the gradients are bit-reproducible.
 template <int BMAX>
-__global__ __launch_bounds__(kBlock) void k_adj_params(const GDesc *__restrict__ gd, int ng) {
+__global__ __launch_bounds__(kParBlock) void k_adj_params(const GDesc *__restrict__ gd, int ng) {
     const GDesc &d = gd[0];
     constexpr int GW = kTile + 2, GN = GW * GW, NQ = BMAX + HB_MAX_PASSES;
     __shared__ unsigned long long sA[2][GN];
-    __shared__ double sred[kWavesPerBlock][NQ];
+    __shared__ double sred[kParWaves][NQ];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int nt = d.n_tiles, B = d.B, P = d.P, W = d.W, H = d.H, bp = d.bp, pp = d.pp;
     const int64_t nitems = d.aseg_off[nt];
@@ -251,20 +256,20 @@ __global__ __launch_bounds__(kBlock) void k_adj_params(const GDesc *__restrict__
         const int layer = t / per_layer, rem = t - layer * per_layer;
         const int ty = rem / d.tiles_x, tx = rem - ty * d.tiles_x;
         const int X0 = tx * kTile - 1, Y0 = ty * kTile - 1;   // grid cell (0, 0)
-        for (int c = threadIdx.x; c < 2 * GN; c += kBlock) (&sA[0][0])[c] = 0ull;
+        for (int c = threadIdx.x; c < 2 * GN; c += kParBlock) (&sA[0][0])[c] = 0ull;
         __syncthreads();
         // four entries per thread in flight (the gathers of m v and x depend on the entry)
-        for (int64_t i0 = beg + threadIdx.x; i0 < end; i0 += 4 * kBlock) {
+        for (int64_t i0 = beg + threadIdx.x; i0 < end; i0 += 4 * kParBlock) {
             uint32_t pe[4];
             float2 me[4], xe[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t i = i0 + r * kBlock;
+                const int64_t i = i0 + r * kParBlock;
                 pe[r] = i < end ? d.abin_src[i] : 0u;
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t i = i0 + r * kBlock;
+                const int64_t i = i0 + r * kParBlock;
                 me[r] = make_float2(0.0f, 0.0f);
                 xe[r] = make_float2(0.0f, 0.0f);
                 if (i < end) {
@@ -295,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_params(const GDesc *__restrict__
         double acc[NQ];
 #pragma unroll
         for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-        for (int c = threadIdx.x; c < GN; c += kBlock) {
+        for (int c = threadIdx.x; c < GN; c += kParBlock) {
             const long long ax = (long long)sA[0][c], ay = (long long)sA[1][c];
             if (ax == 0 && ay == 0) continue;
             const int v = Y0 + c / GW, u = X0 + c % GW;
@@ -327,7 +332,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_params(const GDesc *__restrict__
         if ((int)threadIdx.x < B + P) {
             const int q = (int)threadIdx.x < B ? (int)threadIdx.x : BMAX + ((int)threadIdx.x - B);
             double sum = 0.0;
-            for (int w2 = 0; w2 < kWavesPerBlock; ++w2) sum += sred[w2][q];
+            for (int w2 = 0; w2 < kParWaves; ++w2) sum += sred[w2][q];
             d.partials[(int64_t)threadIdx.x * d.max_items + it] = sum;
         }
         __syncthreads();
@@ -344,7 +349,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_params(const GDesc *__restrict__
 //     to the total of C_bar, which are only known at the end of the edge;
 //  B) add (L_bar + sum_j C_bar_j)(u_(i-1) - u_i) to every point (u: unit segment vectors).
 // Point i is always handled by lane i mod 64, so pass B re-reads only its own writes.
-__global__ __launch_bounds__(kBlock) void k_adj_resample(const GDesc *__restrict__ gd, int ng) {
+__global__ __launch_bounds__(kBlock, 6) void k_adj_resample(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_edge);
     const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -616,7 +621,7 @@ hipError_t launch_adj_advect(const GDesc *desc, const Shape &tot, hipStream_t st
 
 hipError_t launch_adj_params(const GDesc *desc, const Shape &tot, int bmax, hipStream_t st) {
     if (tot.tile <= 0) return hipSuccess;
-    const dim3 gr = grid1(tot.tile), bl(kBlock);
+    const dim3 gr = grid1(tot.tile), bl(kParBlock);
     if (bmax <= 8) hipLaunchKernelGGL(k_adj_params<8>, gr, bl, 0, st, desc, 1);
     else hipLaunchKernelGGL(k_adj_params<16>, gr, bl, 0, st, desc, 1);
     return hipGetLastError();
