@@ -78,6 +78,7 @@ def lib():
             "orc_laplacian": (None, [i64, P, P, f64, i32, P]),
             "orc_ink": (f64, [i64, P, P]),
             "orc_sqdist": (f64, [P, P, i32]),
+            "orc_point_widths": (None, [i64, P, P, P, i32, i32, P, f64, f64, i32, P, P]),
             "orc_kmeans": (i32, [i64, i32, P, i32, P, i32, P, P]),
             "orc_davies_bouldin": (f64, [i64, i32, P, i32, P]),
             "orc_draw": (ctypes.c_uint64, [ctypes.c_uint64, i32, i32, i64]),
@@ -386,6 +387,37 @@ def ink(off, xy) -> float:
     off = _c(off, np.int64)
     xy = _c(xy, np.float64)
     return float(lib().orc_ink(off.shape[0] - 1, _p(off), _p(xy)))
+
+
+# ----------------------------------------------------------------------- width encoding (3.4)
+
+def point_widths(off, xy, group, rho, w_min, w_max, log_scale=False):
+    """Per point: the density of its edge's layer at the point (>= 0) and the line width
+    w_min + (w_max - w_min) f(rho) / f(rho_max), f linear or log1p. Returns (dens, widths)."""
+    off = _c(off, np.int64)
+    xy = _c(xy, np.float64)
+    group = _c(group, np.int32)
+    rho = _c(rho, np.float64)
+    B, H, W = rho.shape
+    N = xy.shape[0]
+    dens = np.empty(N, np.float64)
+    widths = np.empty(N, np.float64)
+    lib().orc_point_widths(off.shape[0] - 1, _p(off), _p(xy), _p(group), W, H, _p(rho), float(w_min),
+                           float(w_max), 1 if log_scale else 0, _p(dens), _p(widths))
+    return dens, widths
+
+
+def maps_of(off, xy, group, M, p: "Params", it: int, weight=None):
+    """The density stack of the polylines (off, xy) taken as samples, with the box radii of
+    iteration it (histogram, box passes, density; no advection)."""
+    B = int(np.asarray(M).shape[0])
+    if p.strip_splat:
+        hist = splat_strip(off, xy, group, B, p.grid_w, p.grid_h, weight)
+    else:
+        hist = splat(off, xy, group, B, p.grid_w, p.grid_h, weight)
+    rr = p.pass_radii(it)
+    S = box_chain_radii(hist, rr)
+    return density_radii(S, rr, p.a(), M)
 
 
 # ----------------------------------------------------------------------- grouping (Section 5)

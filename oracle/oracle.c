@@ -916,3 +916,34 @@ EXPORT int32_t orc_choose_groups(int64_t n, int32_t dim, const float *X, int32_t
     free(idx);
     return chosen;
 }
+
+/* ------------------------------------------------ width encoding (Sec. 3.4)
+ * Bundle weight is also encoded by line width: the width of the polyline between
+ * consecutive sample points follows the density map at the sample points, on a linear or a
+ * logarithmic scale. Reading: per point, rho = the density of its edge's layer at the point
+ * (bilinear, as the advection samples it; negative values, possible with repelling
+ * interactions, count as 0), the width w = w_min + (w_max - w_min) f(rho) / f(rho_max) with
+ * f(rho) = rho (linear) or log(1 + rho) (log scale; rho in samples per pixel) and rho_max the
+ * largest rho over all points; all points get w_min when rho_max is 0. A renderer draws the
+ * segment (x_j, x_j+1) with the mean of its two end widths.
+ * Pins: closed form on linear maps, w_max at the densest point and w_min where the density is
+ * 0, monotone in the density, the log scale compresses.
+ */
+EXPORT void orc_point_widths(int64_t E, const int64_t *off, const double *xy, const int32_t *group,
+                             int32_t W, int32_t H, const double *rho, double w_min, double w_max,
+                             int32_t log_scale, double *dens, double *widths) {
+    int64_t plane = (int64_t)W * H;
+    double rmax = 0.0;
+    for (int64_t e = 0; e < E; ++e)
+        for (int64_t i = off[e]; i < off[e + 1]; ++i) {
+            double r = orc_bilinear(W, H, rho + (int64_t)group[e] * plane, 1, 0, xy[2 * i], xy[2 * i + 1]);
+            if (!(r > 0.0)) r = 0.0;
+            dens[i] = r;
+            if (r > rmax) rmax = r;
+        }
+    double fmax = log_scale ? log1p(rmax) : rmax;
+    for (int64_t i = 0; i < off[E]; ++i) {
+        double f = log_scale ? log1p(dens[i]) : dens[i];
+        widths[i] = fmax > 0.0 ? w_min + (w_max - w_min) * (f / fmax) : w_min;
+    }
+}

@@ -863,3 +863,34 @@ def test_box_chain_radii_impulse_variance_and_scipy():
     M = np.ones((1, 1))
     np.testing.assert_allclose(O.density_radii(O.box_chain(m, 3, 2), [2, 2, 2], a, M),
                                O.density(O.box_chain(m, 3, 2), 2, a, M), rtol=1e-15)
+
+
+# ------------------------------------------------------------------ width encoding (Sec. 3.4)
+
+def test_point_widths_closed_form_on_a_linear_map():
+    W, H = 40, 30
+    u = np.arange(W) + 0.5
+    rho = np.broadcast_to(0.25 * u[None, :], (H, W)).astype(np.float64)[None].copy()
+    off = np.array([0, 5], np.int64)
+    xy = np.array([[2.0, 5.0], [10.0, 7.5], [20.25, 9.0], [30.5, 3.0], [39.5, 12.0]])
+    dens, w = O.point_widths(off, xy, np.zeros(1, np.int32), rho, 1.0, 5.0)
+    # bilinear on a linear map is exact inside; the last point clamps to the border column
+    np.testing.assert_allclose(dens, 0.25 * np.minimum(xy[:, 0], W - 0.5), rtol=1e-12)
+    np.testing.assert_allclose(w, 1.0 + 4.0 * dens / dens.max(), rtol=1e-12)
+    assert w.max() == 5.0
+    dl, wl = O.point_widths(off, xy, np.zeros(1, np.int32), rho, 1.0, 5.0, log_scale=True)
+    np.testing.assert_allclose(wl, 1.0 + 4.0 * np.log1p(dens) / np.log1p(dens.max()), rtol=1e-12)
+    # the log scale lifts the small densities, keeps the order and the end values
+    assert (np.diff(wl[np.argsort(dens)]) >= 0).all() and (wl >= w - 1e-12).all()
+
+
+def test_point_widths_zero_and_negative_density():
+    rho = -np.ones((2, 8, 8))
+    rho[1, 4, 4] = 3.0
+    off = np.array([0, 2, 4], np.int64)
+    xy = np.array([[4.5, 4.5], [1.5, 1.5], [4.5, 4.5], [0.5, 7.5]])
+    dens, w = O.point_widths(off, xy, np.array([0, 1], np.int32), rho, 0.5, 2.0)
+    np.testing.assert_array_equal(dens, [0.0, 0.0, 3.0, 0.0])
+    np.testing.assert_array_equal(w, [0.5, 0.5, 2.0, 0.5])
+    d0, w0 = O.point_widths(off, xy, np.array([0, 0], np.int32), rho, 0.5, 2.0)
+    np.testing.assert_array_equal(w0, 0.5)
