@@ -381,6 +381,22 @@ hb_status hb_set_profiling(hb_ctx *ctx, int32_t enable);
 hb_status hb_get_stage_times(hb_ctx *ctx, double *ms, int64_t *launches, int32_t n_stages,
                              int32_t reset);
 
+/* ---- rendering (Section 3.4): the density map sets the width of the drawn bundles. */
+
+/* Width of every point of the current polylines (the state of hb_get_points, in its order)
+ * from the density of the edge's own layer at the point. The maps are rebuilt from the
+ * polylines taken as samples (splat of the current splat_mode, the box radii of iteration
+ * `iter` >= 0, the densities of Eq. 3; no resampling or advection), so the context's maps
+ * then hold these (hb_get_map). Per point: dens = the bilinear density of its edge's layer at
+ * the point (taps as in the advection; negative values count 0) and
+ * width = w_min + (w_max - w_min) f(dens) / f(max dens), f(x) = x (log_scale 0) or
+ * log(1 + x) (log_scale 1); all points get w_min when the largest density is 0. w_min and
+ * w_max finite with 0 <= w_min <= w_max. dens (may be NULL) and widths receive n_state floats
+ * each: host memory, or device memory with HB_DEVICE_PTRS; caller-owned; cap_points < n_state
+ * gives HB_EINVAL. A histogram bin or splat-entry overflow gives HB_EOVERFLOW. Synchronous. */
+hb_status hb_point_widths(hb_ctx *ctx, int32_t iter, float w_min, float w_max, int32_t log_scale,
+                          float *dens, float *widths, int64_t cap_points, uint32_t flags);
+
 #ifdef __cplusplus
 }
 #endif

@@ -95,6 +95,9 @@ _SIGS = {
                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                                           ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                           ctypes.c_void_p, ctypes.c_uint32]),
+    "hb_point_widths": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_float, ctypes.c_float,
+                                         ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                         ctypes.c_uint32]),
     "hb_run": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32]),
     "hb_sync": (ctypes.c_int32, [ctypes.c_void_p]),
     "hb_get_num_points": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.POINTER(ctypes.c_int64)]),
@@ -321,6 +324,24 @@ def hb_get_num_points(ctx, which: int = HB_POINTS_STATE) -> int:
     return int(n.value)
 
 
+def hb_point_widths(ctx, it: int, w_min: float, w_max: float, log_scale: bool = False, device=None):
+    """Density at every point of the current polylines and its line width (Section 3.4);
+    returns (dens, widths), float32 [N] numpy arrays, or torch tensors on ``device``."""
+    n = hb_get_num_points(ctx, HB_POINTS_STATE)
+    args = (int(it), float(w_min), float(w_max), 1 if log_scale else 0)
+    if device is not None:
+        import torch
+        dens = torch.empty(max(n, 1), dtype=torch.float32, device=device)
+        widths = torch.empty(max(n, 1), dtype=torch.float32, device=device)
+        _check(ctx, load().hb_point_widths(ctx, *args, ctypes.c_void_p(dens.data_ptr()),
+                                           ctypes.c_void_p(widths.data_ptr()), n, HB_DEVICE_PTRS))
+        return dens[:n], widths[:n]
+    dens = np.empty(max(n, 1), np.float32)
+    widths = np.empty(max(n, 1), np.float32)
+    _check(ctx, load().hb_point_widths(ctx, *args, dens.ctypes.data, widths.ctypes.data, n, 0))
+    return dens[:n], widths[:n]
+
+
 def hb_get_points(ctx, which: int = HB_POINTS_STATE, n_edges: Optional[int] = None, device=None):
     """Offsets [E+1] (int64) and xy [N, 2] (float32) as numpy arrays, or torch tensors on
     ``device`` when given."""
@@ -525,6 +546,9 @@ class Bundler:
 
     def choose_groups(self, X, kmin=4, kmax=16, restarts=100, seed=0, max_iters=100):
         return hb_choose_groups(self.ctx, X, kmin, kmax, restarts, seed, max_iters)
+
+    def point_widths(self, it, w_min, w_max, log_scale=False, device=None):
+        return hb_point_widths(self.ctx, it, w_min, w_max, log_scale, device)
 
     def set_workload(self, w, **kw):
         """Parameters, graph and groups of a ``workloads.Workload``."""

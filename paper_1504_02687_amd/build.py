@@ -7,7 +7,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libhb.so")
-SOURCES = ["kernels.hip", "adjoint.hip", "grouping.hip", "runtime.hip"]
+SOURCES = ["kernels.hip", "adjoint.hip", "grouping.hip", "render.hip", "runtime.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "hb_internal.h"
+#include "render.h"
 
 using hb::GDesc;
 using hb::Shape;
@@ -78,6 +79,8 @@ struct hb_ctx {
     bool have_maps = false;
 
     int8_t *d_jacc = nullptr;
+    float *d_render = nullptr;     // point densities, widths and the largest density (bits)
+    int64_t render_cap = 0;
     int64_t jacc_cap = 0;
     bool have_jacc = false;
 
@@ -705,6 +708,7 @@ HB_API void hb_destroy(hb_ctx *c) {
         dfree(&c->d_rhoq);
         dfree(&c->d_gradq);
         dfree(&c->d_jacc);
+        dfree(&c->d_render);
         free_ckpts(c);
         dfree(&c->d_desc);
         if (c->h_desc) (void)hipHostFree(c->h_desc);
@@ -1840,6 +1844,64 @@ HB_API hb_status hb_orientation_groups(hb_ctx *c, int32_t *group, uint32_t flags
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     dfree(&tmp);
     if (e != hipSuccess) return fail_dev(c, e, "orientation bins");
+    return HB_OK;
+}
+
+HB_API hb_status hb_point_widths(hb_ctx *c, int32_t iter, float w_min, float w_max, int32_t log_scale,
+                                 float *dens, float *widths, int64_t cap_points, uint32_t flags) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    if (flags & ~(uint32_t)HB_DEVICE_PTRS) return fail(c, HB_EINVAL, "unknown flags");
+    if (!c->have_params || !c->have_graph || !c->have_groups)
+        return fail(c, HB_ESTATE, "hb_point_widths needs parameters, graph and groups");
+    if (iter < 0) return fail(c, HB_EINVAL, "iter must be >= 0");
+    if (!std::isfinite(w_min) || !std::isfinite(w_max) || w_min < 0.0f || w_max < w_min)
+        return fail(c, HB_EINVAL, "widths need finite 0 <= w_min <= w_max");
+    if (log_scale != 0 && log_scale != 1) return fail(c, HB_EINVAL, "log_scale must be 0 or 1");
+    const int64_t N = c->n_state;
+    if (cap_points < N) return fail(c, HB_EINVAL, "output buffers too small");
+    if (N > 0 && !widths) return fail(c, HB_EINVAL, "widths is NULL");
+    CHKST(prepare_ctx(c, 1, 0));
+    if (c->render_cap < 2 * N + 1) {
+        dfree(&c->d_render);
+        c->render_cap = 0;
+        CHKST(dalloc(c, &c->d_render, (size_t)(2 * N + 1), "point widths"));
+        c->render_cap = 2 * N + 1;
+    }
+    CHKST(ensure_desc(c, 1));
+    CHKST(wait_desc(c));
+    GDesc d = base_desc(c);
+    set_iter_scalars(c, d, iter);
+    d.samples = c->pts[c->ps];
+    d.off_s = c->off[c->os];
+    d.count_given = !d.strip;
+    c->h_desc[0] = d;
+    CHKST(upload_desc(c, 1));
+    const GDesc *dd = c->d_desc;
+    const Shape s = hb::shape_of(c->E, d.B, d.W, d.H);
+    const bool strip = d.strip != 0;
+    float *pd = c->d_render, *pw = c->d_render + N;
+    uint32_t *pmax = reinterpret_cast<uint32_t *>(c->d_render + 2 * N);
+    if (flags & HB_DEVICE_PTRS) {
+        if (dens) pd = dens;
+        pw = widths;
+    }
+    HIPCHK(c, hb::launch_clear_hist(dd, 1, s, c->stream));
+    if (!strip) HIPCHK(c, hb::launch_count_given(dd, 1, s, c->stream));
+    else HIPCHK(c, hb::launch_strip_bins(dd, 1, s, false, c->stream));
+    HIPCHK(c, hb::launch_bin_hist(dd, 1, s, strip, !strip, c->stream));
+    for (int k = 0; k < d.P; ++k) HIPCHK(c, hb::launch_box_pass(dd, 1, s, d.W, k, c->stream));
+    HIPCHK(c, hb::launch_density_cells(dd, 1, s, d.B, c->stream));
+    HIPCHK(c, hipMemsetAsync(pmax, 0, sizeof(uint32_t), c->stream));
+    HIPCHK(c, hb::launch_point_density(dd, s, pd, pmax, c->stream));
+    HIPCHK(c, hb::launch_widths(pd, N, pmax, (double)w_min, (double)w_max, log_scale, pw, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    CHKST(read_status(c));
+    c->have_maps = true;
+    if (!(flags & HB_DEVICE_PTRS)) {
+        if (dens) CHKST(copy_out(c, dens, pd, sizeof(float) * (size_t)N, 0));
+        CHKST(copy_out(c, widths, pw, sizeof(float) * (size_t)N, 0));
+    }
     return HB_OK;
 }
 
