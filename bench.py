@@ -189,6 +189,9 @@ def main():
                     help="measure the grouping step instead: k-means on the origin-destination "
                          "features of the edges and the choice of B (one JSON line)")
     ap.add_argument("--restarts", type=int, default=10, help="k-means restarts per B (--grouping)")
+    ap.add_argument("--widths", type=int, default=0, metavar="T",
+                    help="time the density-width encoding (Section 3.4) of the polylines after T "
+                         "iterations instead of the iteration")
     ap.add_argument("--batch-graphs", type=int, default=64)
     ap.add_argument("--batch-emax", type=float, default=1e5)
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
@@ -214,6 +217,9 @@ def main():
         return
     if args.grouping:
         grouping_main(args)
+        return
+    if args.widths > 0:
+        widths_main(args)
         return
 
     import numpy as np
@@ -390,6 +396,78 @@ def grouping_main(args):
                      "traffic": None},
         "choose_groups": {"kmin": 4, "kmax": 16, "restarts": args.restarts, "B": B,
                           "seconds": dt_choose, "db": [round(v, 6) for v in db.tolist()]},
+        "cpu_baseline": cpu}), flush=True)
+
+
+def widths_main(args):
+    """Density-width encoding (Section 3.4) of the bundled polylines of the measured workload
+    after --widths iterations: every call rebuilds the maps from the polylines (clear, point
+    splat, box passes, density) and gives each point its layer's density and a line width on
+    the log scale. Timed with events on the context's stream (torch's current stream).
+    Algorithmic bytes of a call: the map stages as in an iteration with the polylines as the
+    samples, plus the point pass (8 read + 4 write per point, 12 per edge) and the width pass
+    (4 read + 4 write per point); the density taps are gathers from the map just written."""
+    import numpy as np
+    import torch
+
+    import oracle as O
+    import paper_1504_02687_amd as hb
+    import workloads
+
+    torch.cuda.set_device(0)
+    stream = torch.cuda.current_stream()
+    w = workloads.stack3d(n_edges=args.edges, grid=args.grid, groups=args.groups)
+    b = hb.Bundler(0, stream=stream.cuda_stream)
+    b.set_workload(w, capacity_factor=args.capacity)
+    T = args.widths
+    log(f"{T} iterations of {w.describe()}")
+    b.run(T)
+    n = hb.hb_get_num_points(b.ctx)
+    dev = torch.device("cuda:0")
+    for _ in range(max(1, args.warmup)):
+        b.point_widths(T, 1.0, 8.0, True, dev)
+    K = args.steps
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(K):
+        b.point_widths(T, 1.0, 8.0, True, dev)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / K
+    b.close()
+    rate = n / (ms * 1e-3)
+    E, px = w.n_edges, w.n_groups * w.grid_w * w.grid_h
+    byts = sum(stage_bytes(s, w, [n], n) for s in ("clear", "bin", "box", "density_grad"))
+    byts += 12 * n + 12 * E + 8 * n
+    gbs = byts / (ms * 1e-3) / 1e9
+    log(f"{n} points: {ms:.3f} ms per call, {rate / 1e9:.2f} G points/s, {gbs:.0f} GB/s")
+    cpu = None
+    if args.cpu_fraction > 0:
+        # the oracle on a sample: every step-th edge's straight polyline resampled by the oracle
+        p = O.params_for(w)
+        step = max(1, int(round(1.0 / args.cpu_fraction)))
+        sel = np.arange(0, E, step)
+        off0, xy0 = O.initial_state(w.node_xy, w.src[sel], w.dst[sel], p)
+        off1, xy1, _ = O.resample(off0, xy0, w.delta)
+        t0 = time.perf_counter()
+        rho = O.maps_of(off1, xy1, w.group[sel], w.M.astype(np.float64), p, T)
+        O.point_widths(off1, xy1, w.group[sel], rho, 1.0, 8.0, True)
+        dt = time.perf_counter() - t0
+        ncpu = int(off1[-1])
+        cpu = {"value": ncpu / dt, "unit": "points/s", "cores": int(O.lib().orc_num_threads()),
+               "kind": "oracle",
+               "sample": f"every {step}th edge ({len(sel)} edges) resampled straight, {ncpu} points, "
+                         f"full {w.grid_w}x{w.grid_h}x{w.n_groups} maps; {dt:.2f} s"}
+    print(json.dumps({
+        "metric": "density-width encoding points/sec (maps rebuilt from the polylines, log scale)",
+        "value": rate, "unit": "points/s", "n_gpus": 1, "steps": K, "warmup": args.warmup,
+        "ms_per_step": ms, "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name + "-widths", "edges": E, "groups": w.n_groups,
+                   "grid": [w.grid_w, w.grid_h], "iterations_before": T, "points": n},
+        "roofline": {"bound": "hbm", "kernel": "whole call", "achieved": round(gbs, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "traffic": None, "algorithmic_bytes_per_launch": int(byts)},
         "cpu_baseline": cpu}), flush=True)
 
 

@@ -390,7 +390,7 @@ hb_status hb_get_stage_times(hb_ctx *ctx, double *ms, int64_t *launches, int32_t
  * then hold these (hb_get_map). Per point: dens = the bilinear density of its edge's layer at
  * the point (taps as in the advection; negative values count 0) and
  * width = w_min + (w_max - w_min) f(dens) / f(max dens), f(x) = x (log_scale 0) or
- * log(1 + x) (log_scale 1); all points get w_min when the largest density is 0. w_min and
+ * log(1 + x) (log_scale 1), in FP32; all points get w_min when the largest density is 0. w_min and
  * w_max finite with 0 <= w_min <= w_max. dens (may be NULL) and widths receive n_state floats
  * each: host memory, or device memory with HB_DEVICE_PTRS; caller-owned; cap_points < n_state
  * gives HB_EINVAL. A histogram bin or splat-entry overflow gives HB_EOVERFLOW. Synchronous. */

@@ -9,10 +9,12 @@
 
 namespace hb {
 
-// One wave per edge, its points 64 at a time (coalesced): bilinear density at each point in
-// its edge's layer (the taps and fractions of the advection's density samples), clamped at 0;
-// a wave maximum, then one atomic max on the float bits (non-negative floats order as their
-// bits).
+// One wave per edge, its points 64 at a time (coalesced), four such chunks in flight per
+// trip: bilinear density at each point in its edge's layer (the taps and fractions of the
+// advection's density samples), clamped at 0; a wave maximum, then one atomic max on the
+// float bits (non-negative floats order as their bits).
+constexpr int kDensChunks = 4;
+
 __global__ __launch_bounds__(kBlock) void k_point_density(const GDesc *__restrict__ gd, int ng,
                                                           float *__restrict__ dens,
                                                           uint32_t *maxbits) {
@@ -26,32 +28,72 @@ __global__ __launch_bounds__(kBlock) void k_point_density(const GDesc *__restric
     const int W = d.W, H = d.H;
     const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
     const float *rho = d.rho + (int64_t)d.group[e] * ((int64_t)W * H);
+    const float2 *xs = d.samples + o0;
+    float *out = dens + o0;
     float m = 0.0f;
-    for (int64_t j0 = 0; j0 < n; j0 += 64) {
-        const int64_t j = j0 + lane;
-        if (j < n) {
-            const float2 x = d.samples[o0 + j];
-            const Taps t = taps_of(x.x, x.y, W, H);
-            float r = bilerp(rho[t.o00], rho[t.o10], rho[t.o01], rho[t.o11], t.tx, t.ty);
+    for (int64_t j0 = 0; j0 < n; j0 += 64 * kDensChunks) {
+        float2 x[kDensChunks];
+#pragma unroll
+        for (int u = 0; u < kDensChunks; ++u) {
+            const int64_t j = j0 + 64 * u + lane;
+            x[u] = j < n ? xs[j] : make_float2(0.5f, 0.5f);
+        }
+        float v[kDensChunks][4];
+        Taps t[kDensChunks];
+#pragma unroll
+        for (int u = 0; u < kDensChunks; ++u) {
+            t[u] = taps_of(x[u].x, x[u].y, W, H);
+            v[u][0] = rho[t[u].o00];
+            v[u][1] = rho[t[u].o10];
+            v[u][2] = rho[t[u].o01];
+            v[u][3] = rho[t[u].o11];
+        }
+#pragma unroll
+        for (int u = 0; u < kDensChunks; ++u) {
+            const int64_t j = j0 + 64 * u + lane;
+            float r = bilerp(v[u][0], v[u][1], v[u][2], v[u][3], t[u].tx, t[u].ty);
             r = r > 0.0f ? r : 0.0f;
-            dens[o0 + j] = r;
-            m = fmaxf(m, r);
+            if (j < n) {
+                out[j] = r;
+                m = fmaxf(m, r);
+            }
         }
     }
     for (int s = 32; s >= 1; s >>= 1) m = fmaxf(m, __shfl_xor(m, s, 64));
     if (lane == 0 && m > 0.0f) atomicMax(maxbits, __float_as_uint(m));
 }
 
+// Four points per thread, kBlock apart (coalesced, all loads issued before the arithmetic).
+// FP32: t = f(rho) / f(max) (a correctly rounded division, so t = 1 exactly at the largest
+// density, which gets w_max itself), width = w_min + t (w_max - w_min).
+constexpr int kWidthPts = 4;
+
 __global__ __launch_bounds__(kBlock) void k_widths(const float *__restrict__ dens, int64_t n,
-                                                   const uint32_t *__restrict__ maxbits, double w_min,
-                                                   double w_max, int log_scale,
+                                                   const uint32_t *__restrict__ maxbits, float w_min,
+                                                   float w_max, int log_scale,
                                                    float *__restrict__ widths) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= n) return;
-    const double rmax = (double)__uint_as_float(*maxbits), r = (double)dens[i];
-    const double fmax = log_scale ? log1p(rmax) : rmax;
-    const double f = log_scale ? log1p(r) : r;
-    widths[i] = (float)(fmax > 0.0 ? w_min + (w_max - w_min) * (f / fmax) : w_min);
+    const int64_t i0 = (int64_t)blockIdx.x * (kBlock * kWidthPts) + threadIdx.x;
+    const float rmax = __uint_as_float(*maxbits);
+    const float fmax = log_scale ? log1pf(rmax) : rmax;
+    const float range = w_max - w_min;
+    float r[kWidthPts];
+#pragma unroll
+    for (int u = 0; u < kWidthPts; ++u) {
+        const int64_t i = i0 + (int64_t)u * kBlock;
+        r[u] = i < n ? dens[i] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < kWidthPts; ++u) {
+        const int64_t i = i0 + (int64_t)u * kBlock;
+        if (i >= n) continue;
+        float w = w_min;
+        if (fmax > 0.0f) {
+            const float f = log_scale ? log1pf(r[u]) : r[u];
+            const float t = f / fmax;
+            w = t >= 1.0f ? w_max : __builtin_fmaf(t, range, w_min);
+        }
+        widths[i] = w;
+    }
 }
 
 hipError_t launch_point_density(const GDesc *desc, const Shape &tot, float *dens, uint32_t *maxbits,
@@ -65,8 +107,9 @@ hipError_t launch_point_density(const GDesc *desc, const Shape &tot, float *dens
 hipError_t launch_widths(const float *dens, int64_t n, const uint32_t *maxbits, double w_min,
                          double w_max, int log_scale, float *widths, hipStream_t st) {
     if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_widths, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, st, dens,
-                       n, maxbits, w_min, w_max, log_scale, widths);
+    const int64_t per = (int64_t)kBlock * kWidthPts;
+    hipLaunchKernelGGL(k_widths, dim3((unsigned)((n + per - 1) / per)), dim3(kBlock), 0, st, dens, n,
+                       maxbits, (float)w_min, (float)w_max, log_scale, widths);
     return hipGetLastError();
 }
 
