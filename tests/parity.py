@@ -62,11 +62,17 @@ def laplace(off, xa, s=0.5):
 
 
 def interp_condition(grad, group, off, xy):
-    """Condition number of the bilinear gradient direction at each point:
+    """Condition number of the bilinear gradient direction at each point of the polylines
+    (off, xy) in its edge's layer (see direction_condition)."""
+    eid = np.repeat(np.arange(len(off) - 1), np.diff(off))
+    return direction_condition(grad, np.asarray(group)[eid], xy)
+
+
+def direction_condition(grad, lay, xy):
+    """Condition number of the bilinear gradient direction at the points xy of layers lay:
     sum_i w_i |g_i| / |sum_i w_i g_i| (inf where the gradient vanishes)."""
     B, H, W, _ = grad.shape
-    eid = np.repeat(np.arange(len(off) - 1), np.diff(off))
-    lay = grad[group[eid]]
+    xy = np.asarray(xy, np.float64)
     fx = np.clip(xy[:, 0] - 0.5, -1, W)
     fy = np.clip(xy[:, 1] - 0.5, -1, H)
     u0 = np.floor(fx).astype(np.int64)
@@ -74,12 +80,13 @@ def interp_condition(grad, group, off, xy):
     tx, ty = fx - u0, fy - v0
     uu = [np.clip(u0, 0, W - 1), np.clip(u0 + 1, 0, W - 1)]
     vv = [np.clip(v0, 0, H - 1), np.clip(v0 + 1, 0, H - 1)]
-    ws = [((1 - tx) * (1 - ty), 0, 0), (tx * (1 - ty), 1, 0), ((1 - tx) * ty, 0, 1), (tx * ty, 1, 1)]
-    ar = np.arange(len(xy))
+    flat = grad.reshape(-1, 2)
+    base = np.asarray(lay, np.int64) * H
     num = np.zeros(len(xy))
     vec = np.zeros((len(xy), 2))
-    for w, a, b in ws:
-        gv = lay[ar, vv[b], uu[a]]
+    for w, a, b in (((1 - tx) * (1 - ty), 0, 0), (tx * (1 - ty), 1, 0), ((1 - tx) * ty, 0, 1),
+                    (tx * ty, 1, 1)):
+        gv = flat[(base + vv[b]) * W + uu[a]]
         num += w * np.abs(gv).sum(1)
         vec += w[:, None] * gv
     den = np.abs(vec).sum(1)
