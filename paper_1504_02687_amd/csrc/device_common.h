@@ -344,9 +344,8 @@ struct Cell {
     float tx, ty;
 };
 
-__device__ __forceinline__ Cell cell_of(float x, float y, int W, int H) {
-    const float fx = __builtin_amdgcn_fmed3f(x - 0.5f, -1.0f, (float)W);
-    const float fy = __builtin_amdgcn_fmed3f(y - 0.5f, -1.0f, (float)H);
+// The cell of (fx, fy) = (x - 1/2, y - 1/2) already inside [-1, W] x [-1, H].
+__device__ __forceinline__ Cell cell_at(float fx, float fy, int W, int H) {
     const float u0f = floorf(fx), v0f = floorf(fy);
     Cell t;
     t.tx = fx - u0f;
@@ -356,6 +355,17 @@ __device__ __forceinline__ Cell cell_of(float x, float y, int W, int H) {
     t.c = base + ((cv & 1u) << 2) + (cu & 3u);
     t.g = base + ((cu & 2u) << 1) + ((cv & 1u) << 1) + (cu & 1u);
     return t;
+}
+
+__device__ __forceinline__ Cell cell_of(float x, float y, int W, int H) {
+    return cell_at(__builtin_amdgcn_fmed3f(x - 0.5f, -1.0f, (float)W),
+                   __builtin_amdgcn_fmed3f(y - 0.5f, -1.0f, (float)H), W, H);
+}
+
+// The cell of a point already clamped into [0, W) x [0, H) (an advection candidate): the
+// clamp of cell_of is then the identity and is left out.
+__device__ __forceinline__ Cell cell_of_inside(float x, float y, int W, int H) {
+    return cell_at(x - 0.5f, y - 0.5f, W, H);
 }
 
 __device__ __forceinline__ Quad ldq(const HB_G Quad *m, uint32_t i) {

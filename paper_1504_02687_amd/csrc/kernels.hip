@@ -604,6 +604,15 @@ __global__ __launch_bounds__(kBlock) void k_bin_scan(const GDesc *__restrict__ g
 // Histogram tiles in LDS. Each block takes work items (up to kSegEntries entries of one
 // tile) round-robin, adds the entries' weights to its LDS copy of the tile with LDS
 // atomics, then adds the non-zero counters to the histogram (first copy of histx).
+// LDS counter of a pixel inside a 64 x 64 tile (row v, column u; local = 64 v + u): the low
+// five bits of the column are XORed with those of the row, so the pixels of one tile column
+// (polylines running vertically) fall into different LDS banks. An involution within the row:
+// the slot of a slot is the pixel.
+__device__ __forceinline__ uint32_t lds_slot(uint32_t local) {
+    local &= (uint32_t)(kTilePx - 1);
+    return local ^ ((local >> kTileShift) & 31u);
+}
+
 __global__ __launch_bounds__(kBlock) void k_tile_hist(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_tile);
@@ -634,32 +643,33 @@ __global__ __launch_bounds__(kBlock) void k_tile_hist(const GDesc *__restrict__ 
             for (; i + 3 * kBlock < end; i += 4 * kBlock) {
                 const uint32_t a0 = b16[i], a1 = b16[i + kBlock];
                 const uint32_t a2 = b16[i + 2 * kBlock], a3 = b16[i + 3 * kBlock];
-                atomicAdd(&lh[a0 & (kTilePx - 1)], 1);
-                atomicAdd(&lh[a1 & (kTilePx - 1)], 1);
-                atomicAdd(&lh[a2 & (kTilePx - 1)], 1);
-                atomicAdd(&lh[a3 & (kTilePx - 1)], 1);
+                atomicAdd(&lh[lds_slot(a0)], 1);
+                atomicAdd(&lh[lds_slot(a1)], 1);
+                atomicAdd(&lh[lds_slot(a2)], 1);
+                atomicAdd(&lh[lds_slot(a3)], 1);
             }
-            for (; i < end; i += kBlock) atomicAdd(&lh[b16[i] & (kTilePx - 1)], 1);
+            for (; i < end; i += kBlock) atomicAdd(&lh[lds_slot(b16[i])], 1);
         } else {
             for (; i + 3 * kBlock < end; i += 4 * kBlock) {
                 const uint32_t a0 = bins[i], a1 = bins[i + kBlock];
                 const uint32_t a2 = bins[i + 2 * kBlock], a3 = bins[i + 3 * kBlock];
-                atomicAdd(&lh[a0 & (kTilePx - 1)], (int32_t)(a0 >> kLocalBits));
-                atomicAdd(&lh[a1 & (kTilePx - 1)], (int32_t)(a1 >> kLocalBits));
-                atomicAdd(&lh[a2 & (kTilePx - 1)], (int32_t)(a2 >> kLocalBits));
-                atomicAdd(&lh[a3 & (kTilePx - 1)], (int32_t)(a3 >> kLocalBits));
+                atomicAdd(&lh[lds_slot(a0)], (int32_t)(a0 >> kLocalBits));
+                atomicAdd(&lh[lds_slot(a1)], (int32_t)(a1 >> kLocalBits));
+                atomicAdd(&lh[lds_slot(a2)], (int32_t)(a2 >> kLocalBits));
+                atomicAdd(&lh[lds_slot(a3)], (int32_t)(a3 >> kLocalBits));
             }
             for (; i < end; i += kBlock) {
                 const uint32_t a0 = bins[i];
-                atomicAdd(&lh[a0 & (kTilePx - 1)], (int32_t)(a0 >> kLocalBits));
+                atomicAdd(&lh[lds_slot(a0)], (int32_t)(a0 >> kLocalBits));
             }
         }
         __syncthreads();
         const int layer = t / per_layer, rem = t - layer * per_layer;
         const int ty = rem / d.tiles_x, tx = rem - ty * d.tiles_x;
         HB_G int32_t *hist = glb(d.histx) + (int64_t)layer * plane;
-        for (int p = threadIdx.x; p < kTilePx; p += kBlock) {
-            const int32_t v = lh[p];
+        for (int q = threadIdx.x; q < kTilePx; q += kBlock) {
+            const int32_t v = lh[q];
+            const int p = (int)lds_slot((uint32_t)q);
             const int y = ty * kTile + (p >> kTileShift), x = tx * kTile + (p & (kTile - 1));
             if (v != 0 && x < W && y < H) atomicAdd((int32_t *)(hist + (int64_t)y * W + x), v);
         }
@@ -903,7 +913,7 @@ __device__ __forceinline__ void halving_round(const HB_G Quad *__restrict__ rho,
         for (int u = 0; u < UU; ++u) {
             const float cx = __builtin_amdgcn_fmed3f(__builtin_fmaf(mt, dx[u], x[u].x), 0.0f, xmaxf);
             const float cy = __builtin_amdgcn_fmed3f(__builtin_fmaf(mt, dy[u], x[u].y), 0.0f, ymaxf);
-            c[i][u] = cell_of(cx, cy, W, H);
+            c[i][u] = cell_of_inside(cx, cy, W, H);
         }
         mt *= 0.5f;
     }
