@@ -601,9 +601,6 @@ __global__ __launch_bounds__(kBlock) void k_bin_scan(const GDesc *__restrict__ g
     }
 }
 
-// Histogram tiles in LDS. Each block takes work items (up to kSegEntries entries of one
-// tile) round-robin, adds the entries' weights to its LDS copy of the tile with LDS
-// atomics, then adds the non-zero counters to the histogram (first copy of histx).
 // LDS counter of a pixel inside a 64 x 64 tile (row v, column u; local = 64 v + u): the low
 // five bits of the column are XORed with those of the row, so the pixels of one tile column
 // (polylines running vertically) fall into different LDS banks. An involution within the row:
@@ -613,6 +610,9 @@ __device__ __forceinline__ uint32_t lds_slot(uint32_t local) {
     return local ^ ((local >> kTileShift) & 31u);
 }
 
+// Histogram tiles in LDS. Each block takes work items (up to kSegEntries entries of one
+// tile) round-robin, adds the entries' weights to its LDS copy of the tile with LDS
+// atomics, then adds the non-zero counters to the histogram (first copy of histx).
 __global__ __launch_bounds__(kBlock) void k_tile_hist(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_tile);

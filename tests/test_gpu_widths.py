@@ -115,6 +115,15 @@ def test_widths_degenerate(hb):
     assert (widths == np.float32(2.0)).all()
     dens, widths, _ = _run(hb, off, xy, group, np.ones((1, 1), np.float32), W, H, [2], 0, 1.0, 5.0, False)
     assert widths[np.argmax(dens)] == np.float32(5.0)
+    # no edges: nothing to encode, in both splat modes
+    for mode in (hb.HB_SPLAT_POINTS, hb.HB_SPLAT_STRIP):
+        with hb.Bundler(0) as b:
+            b.set_params(32, 32, [2], splat_mode=mode)
+            b.set_graph(np.zeros((1, 2), np.float32), np.zeros(0, np.int32), np.zeros(0, np.int32))
+            b.set_groups(np.zeros(0, np.int32), np.ones((1, 1), np.float32))
+            d0, w0 = b.point_widths(0, 1.0, 2.0)
+            assert d0.shape == (0,) and w0.shape == (0,)
+            assert (b.map(hb.HB_MAP_HIST, 0) == 0).all()
 
 
 def test_widths_invalid(hb):
