@@ -10,9 +10,10 @@
 namespace hb {
 
 // One wave per edge, its points 64 at a time (coalesced), four such chunks in flight per
-// trip: bilinear density at each point in its edge's layer (the taps and fractions of the
-// advection's density samples), clamped at 0; a wave maximum, then one atomic max on the
-// float bits (non-negative floats order as their bits).
+// trip: bilinear density at each point in its edge's layer, from the density record of its
+// bilinear cell (the four clamped taps in one 16-byte load, the same taps, fractions and
+// rounding as the advection's density samples), clamped at 0; a wave maximum, then one
+// atomic max on the float bits (non-negative floats order as their bits).
 constexpr int kDensChunks = 4;
 
 __global__ __launch_bounds__(kBlock) void k_point_density(const GDesc *__restrict__ gd, int ng,
@@ -27,31 +28,29 @@ __global__ __launch_bounds__(kBlock) void k_point_density(const GDesc *__restric
     if (e >= d.n_edges) return;
     const int W = d.W, H = d.H;
     const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
-    const float *rho = d.rho + (int64_t)d.group[e] * ((int64_t)W * H);
-    const float2 *xs = d.samples + o0;
-    float *out = dens + o0;
+    const HB_G Quad *__restrict__ rho = glb(d.rhoq + (int64_t)d.group[e] * cell_plane(W, H));
+    const HB_G float2 *__restrict__ xs = glb(d.samples + o0);
+    HB_G float *__restrict__ out = glb(dens + o0);
     float m = 0.0f;
     for (int64_t j0 = 0; j0 < n; j0 += 64 * kDensChunks) {
         float2 x[kDensChunks];
 #pragma unroll
         for (int u = 0; u < kDensChunks; ++u) {
             const int64_t j = j0 + 64 * u + lane;
-            x[u] = j < n ? xs[j] : make_float2(0.5f, 0.5f);
+            x[u] = make_float2(0.5f, 0.5f);
+            if (j < n) x[u] = ld2(xs + j);
         }
-        float v[kDensChunks][4];
-        Taps t[kDensChunks];
+        Cell c[kDensChunks];
+        Quad q[kDensChunks];
 #pragma unroll
         for (int u = 0; u < kDensChunks; ++u) {
-            t[u] = taps_of(x[u].x, x[u].y, W, H);
-            v[u][0] = rho[t[u].o00];
-            v[u][1] = rho[t[u].o10];
-            v[u][2] = rho[t[u].o01];
-            v[u][3] = rho[t[u].o11];
+            c[u] = cell_of(x[u].x, x[u].y, W, H);
+            q[u] = ldq(rho, c[u].c);
         }
 #pragma unroll
         for (int u = 0; u < kDensChunks; ++u) {
             const int64_t j = j0 + 64 * u + lane;
-            float r = bilerp(v[u][0], v[u][1], v[u][2], v[u][3], t[u].tx, t[u].ty);
+            float r = interp1q(q[u], c[u]);
             r = r > 0.0f ? r : 0.0f;
             if (j < n) {
                 out[j] = r;
@@ -64,8 +63,10 @@ __global__ __launch_bounds__(kBlock) void k_point_density(const GDesc *__restric
 }
 
 // Four points per thread, kBlock apart (coalesced, all loads issued before the arithmetic).
-// FP32: t = f(rho) / f(max) (a correctly rounded division, so t = 1 exactly at the largest
-// density, which gets w_max itself), width = w_min + t (w_max - w_min).
+// FP32: t = f(rho) / f(max) with f the identity or log2(1 + x) by the hardware base-2
+// logarithm (the ratio of two logarithms does not depend on their base), as one product
+// with the reciprocal of f(max); width = w_min + t (w_max - w_min), and the largest density
+// gets w_max itself.
 constexpr int kWidthPts = 4;
 
 __global__ __launch_bounds__(kBlock) void k_widths(const float *__restrict__ dens, int64_t n,
@@ -74,7 +75,8 @@ __global__ __launch_bounds__(kBlock) void k_widths(const float *__restrict__ den
                                                    float *__restrict__ widths) {
     const int64_t i0 = (int64_t)blockIdx.x * (kBlock * kWidthPts) + threadIdx.x;
     const float rmax = __uint_as_float(*maxbits);
-    const float fmax = log_scale ? log1pf(rmax) : rmax;
+    const float fmax = log_scale ? __log2f(1.0f + rmax) : rmax;
+    const float inv = fmax > 0.0f ? 1.0f / fmax : 0.0f;
     const float range = w_max - w_min;
     float r[kWidthPts];
 #pragma unroll
@@ -88,9 +90,8 @@ __global__ __launch_bounds__(kBlock) void k_widths(const float *__restrict__ den
         if (i >= n) continue;
         float w = w_min;
         if (fmax > 0.0f) {
-            const float f = log_scale ? log1pf(r[u]) : r[u];
-            const float t = f / fmax;
-            w = t >= 1.0f ? w_max : __builtin_fmaf(t, range, w_min);
+            const float f = log_scale ? __log2f(1.0f + r[u]) : r[u];
+            w = r[u] >= rmax ? w_max : fminf(__builtin_fmaf(f * inv, range, w_min), w_max);
         }
         widths[i] = w;
     }
