@@ -633,7 +633,9 @@ EXPORT double orc_bilinear(int32_t W, int32_t H, const double *map, int32_t stri
  * to the first unambiguous acceptance, whose index is written to jfirm (-1 if none).
  * Pins: every accepted move satisfies rho(x') >= rho(x); zero gradient gives no move; a
  * point near an isolated smoothed impulse moves radially in closed form; a straight edge
- * on a pixel-centre row of a symmetric map never leaves the row.
+ * on a pixel-centre row of a symmetric map never leaves the row; the decision record
+ * (jacc, jfirm, amb) written out by hand on maps whose tries land on pixel centres of known
+ * value, including margins just inside, just outside and exactly on the band edge.
  *
  * K < 0 selects the original advection step that Section 2 describes for KDEEB and Section
  * 3.3 compares against: every interior point moves by m = h along d with no density test
