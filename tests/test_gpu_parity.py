@@ -105,13 +105,13 @@ def test_stage_parity_given_samples(hb, E, W, H, B, r, a, seed):
     nb[1:] &= agree[:-1]
     nb[:-1] &= agree[1:]
     err = np.abs(xy_n.astype(np.float64) - ref["xy"]).max(1)
-    assert (err[nb] <= ty[nb] + 1e-4).all(), f"max err {err[nb].max()} px"
+    assert (err[nb] <= ty[nb]).all(), f"max err {err[nb].max()} px"
     assert np.percentile(err[nb], 99) <= 1e-4, np.percentile(err[nb], 99)
     # the rest: the GPU's (valid) decisions, replayed on the oracle's directions
     jj = np.where(jacc == -2, -1, jacc)
     yalt = PT.laplace(off, PT.candidate(x64, adv["dir"], h, jj, W, H))
     erra = np.abs(xy_n.astype(np.float64) - yalt).max(1)
-    assert (erra[~nb] <= ty[~nb] + 1e-4).all()
+    assert (erra[~nb] <= ty[~nb]).all(), f"max err {erra[~nb].max()} px"
     # end points bit-exact
     ends = np.concatenate([off[:-1], off[1:] - 1])
     np.testing.assert_array_equal(xy_n[ends], xy[ends])
@@ -145,7 +145,7 @@ def test_fixed_step_parity_given_samples(hb, E, W, H, B, r, a, seed):
     ty = tpt.copy()
     ty[1:-1] = 0.5 * tpt[1:-1] + 0.25 * (tpt[:-2] + tpt[2:])
     err = np.abs(xy_n.astype(np.float64) - ref["xy"]).max(1)
-    assert (err <= ty + 1e-4).all(), f"max err {err.max()} px"
+    assert (err <= ty).all(), f"max err {err.max()} px"
     assert np.percentile(err, 99) <= 1e-4
     np.testing.assert_array_equal(xy_n[ends], xy[ends])
 
@@ -280,7 +280,7 @@ def test_end_to_end_tiny_config(hb):
         assert PT.relclose(a, b_, 0.01)
     ds, dr = PT.drift_stats(off, xy), PT.drift_stats(roff, rxy)
     for k in ("mean", "p50", "p90", "p99"):
-        assert abs(ds[k] - dr[k]) <= 0.01 * dr[k] + 0.02, (k, ds[k], dr[k])
+        assert abs(ds[k] - dr[k]) <= 0.01 * dr[k], (k, ds[k], dr[k])
 
 
 def test_run_is_deterministic(hb):
