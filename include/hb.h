@@ -30,6 +30,8 @@
  *     last points are the edge's end points and never move.
  *   - Maps are [B][H][W] row-major.
  *   - One context per host thread; calls on one context must not overlap.
+ *   - Failure injection for tests: while the environment variable HB_TEST_FAIL_ALLOC is
+ *     set, every device allocation of the library fails and the call returns HB_ENOMEM.
  */
 #ifndef HB_H
 #define HB_H
@@ -87,6 +89,8 @@ enum {
 enum { HB_SPLAT_POINTS = 0, HB_SPLAT_STRIP = 1 };
 /* resampling modes (hb_params.resample_mode) */
 enum { HB_RESAMPLE_UNIFORM = 0, HB_RESAMPLE_INSERT_DELETE = 1 };
+/* when the directed push is applied (hb_params.directed_mode) */
+enum { HB_DIRECTED_ONCE = 0, HB_DIRECTED_EVERY_ITER = 1 };
 
 #define HB_MAX_GROUPS 64
 #define HB_MAX_PASSES 8
@@ -120,17 +124,17 @@ typedef struct hb_params {
                                    NULL selects the last pass only. Copied. */
     float capacity_factor;      /* point-buffer capacity relative to the first sample count
                                    (>= 1.1; grown automatically when exceeded) */
-    float directed_offset_px;   /* directed graphs (Section 3, the pipeline of Fig. 1): in every
-                                   iteration, right after resampling and before the histogram,
-                                   each sample except the two end points is moved by this
-                                   signed distance (px) along the left normal (-t_y, t_x) of
-                                   the polyline segment it was interpolated on, t the unit
-                                   direction of that segment from source towards target (a
-                                   zero-length segment moves nothing); 0 (default) disables
-                                   it. |value| <= max(W, H) / 16 (the paper uses 0.1 % to
-                                   0.5 % of the drawing). Not applied to samples given with
-                                   HB_RUN_SAMPLES_GIVEN; not differentiated (hb_forward_ckpt
-                                   requires 0). */
+    float directed_offset_px;   /* directed graphs (Section 3, the pipeline of Fig. 1): right
+                                   after resampling and before the histogram, each sample
+                                   except the two end points is moved by this signed distance
+                                   (px) along the left normal (-t_y, t_x) of the polyline
+                                   segment it was interpolated on, t the unit direction of that
+                                   segment from source towards target (a zero-length segment
+                                   moves nothing); 0 (default) disables it. When the push is
+                                   applied is set by directed_mode. |value| <= max(W, H) / 16
+                                   (the paper uses 0.1 % to 0.5 % of the drawing). Not applied
+                                   to samples given with HB_RUN_SAMPLES_GIVEN; not
+                                   differentiated (hb_forward_ckpt requires 0). */
     int32_t splat_mode;         /* what the histogram H of Eq. 1 counts. HB_SPLAT_POINTS
                                    (default): every sample point adds the edge weight to the
                                    pixel it falls in. HB_SPLAT_STRIP: the polyline is drawn as a
@@ -167,6 +171,13 @@ typedef struct hb_params {
                                    defaults to 2 sigma_0. Every width must fit the grid. Not
                                    differentiated (hb_forward_ckpt requires 0). */
     const float *sigma_per_iter; /* sigma_i in pixels (finite, > 0); copied by hb_set_params */
+    int32_t directed_mode;      /* HB_DIRECTED_ONCE (default): the push follows the first
+                                   sampling only, i.e. the resampling of iteration 0 of the
+                                   schedule, as the pipeline of Section 3 pushes once and then
+                                   loops from the resampling, which keeps the offset (it
+                                   interpolates along the pushed polyline). HB_DIRECTED_EVERY_ITER:
+                                   the push follows the resampling of every iteration, so the
+                                   offset is renewed against the bundling each time. */
 } hb_params;
 
 /* Fill p with the paper's defaults for a W x H grid: bbox [0,0,1,1], delta 1 px, P = 3,
@@ -336,22 +347,32 @@ hb_status hb_get_tuning(hb_ctx *ctx, int32_t *resample_chunks, int32_t *advect_c
  * are constants -- and the accepted halving of every point), T iterations of Section 3 are a
  * piecewise smooth function of the polylines that entered them, of the interaction matrix M
  * (Eq. 3-4) and of the pass weights a of the density. hb_backward applies the transpose of
- * its Jacobian to the gradient of the loss L = total length of the final polylines ("ink").
+ * its Jacobian to the gradient of a loss of the final polylines: one the caller supplies,
+ * or by default L = total length of the final polylines ("ink").
  *
- * hb_forward_ckpt runs n_iters iterations like hb_run and keeps, for every iteration, the
- * polylines entering it (with their lengths and next sample counts) on the device; it needs
- * B <= 16. Any later call that changes the polylines, the parameters, the groups or the
- * iteration counter discards the checkpoints.
+ * hb_forward_ckpt runs n_iters iterations like hb_run from the context's current iteration
+ * (hb_set_iteration) and keeps, for every iteration, the polylines entering it (with their
+ * lengths and next sample counts) on the device; it needs B <= 16. *generation (may be NULL)
+ * receives a number that identifies these checkpoints: it grows with every call on the
+ * context. Any later call that changes the polylines, the parameters, the groups or the
+ * iteration counter discards the checkpoints. flags: none (0).
  */
-hb_status hb_forward_ckpt(hb_ctx *ctx, int32_t n_iters, uint32_t flags);
+hb_status hb_forward_ckpt(hb_ctx *ctx, int32_t n_iters, uint32_t flags, int64_t *generation);
 
-/* After hb_forward_ckpt: loss (may be NULL) = L; dL_dM[B*B] (row-major, may be NULL);
- * dL_da[P] (may be NULL); dL_dxy0[N0][2] (may be NULL) = gradient with respect to the
- * points of the polylines that entered the checkpointed run (N0 of them, same layout as
- * hb_get_points; cap_points is the capacity of dL_dxy0 in points). Each iteration is
- * recomputed from its checkpoint; all reductions run in a fixed order (bit-reproducible).
- * flags: HB_DEVICE_PTRS for dL_dxy0 only. */
-hb_status hb_backward(hb_ctx *ctx, double *loss, float *dL_dM, float *dL_da, float *dL_dxy0,
+/* After hb_forward_ckpt. generation: the value hb_forward_ckpt returned (HB_ESTATE when the
+ * context's checkpoints are not those any more), or -1 for the current checkpoints.
+ * dL_dxy_T[n_points_T][2] (may be NULL): gradient of the caller's loss with respect to the
+ * final polylines (the state of hb_get_points, in its layout); n_points_T must equal their
+ * point count (HB_EINVAL otherwise). NULL selects the ink loss. loss (may be NULL) receives
+ * the ink of the final polylines. Outputs: dL_dM[B*B] (row-major, may be NULL); dL_da[P] (may
+ * be NULL); dL_dxy0[N0][2] (may be NULL) = gradient with respect to the points of the
+ * polylines that entered the checkpointed run (N0 of them, same layout as hb_get_points;
+ * cap_points is the capacity of dL_dxy0 in points). Each iteration is recomputed from its
+ * checkpoint; all reductions run in a fixed order (bit-reproducible). The checkpoints stay,
+ * so several losses can be differentiated in turn. flags: HB_DEVICE_PTRS for dL_dxy_T and
+ * dL_dxy0 (device memory of the context's device, read and written in stream order). */
+hb_status hb_backward(hb_ctx *ctx, int64_t generation, const float *dL_dxy_T, int64_t n_points_T,
+                      double *loss, float *dL_dM, float *dL_da, float *dL_dxy0,
                       int64_t cap_points, uint32_t flags);
 
 /* Polylines that entered checkpointed iteration t (0 = the start of the run). */

@@ -122,6 +122,7 @@ class Params:
     amb_tol: float = 1e-5       # decision margin treated as ambiguous in parity checks
     bbox: tuple = (0.0, 0.0, 1.0, 1.0)
     directed_offset: float = 0.0    # push of interior samples along the left normal (px)
+    directed_every: bool = False    # push after every resampling instead of the first only
     strip_splat: bool = False       # histogram of the drawn line strips instead of the points
     insert_delete: bool = False     # insert/delete resampling instead of the uniform one
     delta_min: Optional[float] = None   # removal spacing of insert/delete (None: delta / 2)
@@ -496,7 +497,9 @@ def iterate(off, xy, group, M, p: Params, it: int, weight=None, skip_resample=Fa
     elif p.insert_delete:
         dmin = p.delta_min if p.delta_min is not None else 0.5 * p.delta
         s_off, s_xy = resample_insdel(off, xy, dmin, p.delta)
-    elif p.directed_offset != 0.0:
+    elif p.directed_offset != 0.0 and (it == 0 or p.directed_every):
+        # Section 3, the pipeline: the push follows the first sampling (iteration 0); the
+        # loop then restarts from the resampling. The other reading pushes every iteration.
         s_off, s_xy, _, seg = resample(off, xy, p.delta, want_seg=True)
         s_xy = directed_offset(off, xy, s_off, seg, s_xy, p.directed_offset)
     else:
@@ -559,10 +562,20 @@ def record_run(off, xy, group, M, p: Params, n_iters: int, it0: int = 0, weight=
     return rec, off, xy
 
 
-def frozen_loss(xy0, M, a, rec, group, p: Params):
-    """Ink of the polylines after the recorded iterations, replayed with the frozen choices,
+def frozen_loss(xy0, M, a, rec, group, p: Params, cT=None):
+    """Loss of the polylines after the recorded iterations, replayed with the frozen choices,
     as a function of the starting positions xy0, the interaction matrix M and the pass
-    weights a (all FP64)."""
+    weights a (all FP64): their ink, or, with weights cT [N_T, 2], the linear loss
+    sum(cT * xy_T) of the final points."""
+    xy = frozen_state(xy0, M, a, rec, group, p)
+    if cT is not None:
+        return float((np.asarray(cT, np.float64) * xy).sum())
+    return ink(rec[-1]["s_off"], xy)
+
+
+def frozen_state(xy0, M, a, rec, group, p: Params):
+    """Final polylines (layout rec[-1]["s_off"]) of the frozen replay of the recorded
+    iterations from xy0, M and a (FP64)."""
     xy = _c(xy0, np.float64)
     group = _c(group, np.int32)
     a = _c(a, np.float64)
@@ -579,12 +592,13 @@ def frozen_loss(xy0, M, a, rec, group, p: Params):
         lib().orc_advect_frozen(E, _p(s_off), _p(sx), _p(group), W, H, _p(g), r["h"], _p(jacc),
                                 p.eps, _p(ax))
         xy = laplacian(s_off, ax, p.smooth_weight, p.smooth_passes)
-    return ink(rec[-1]["s_off"], xy)
+    return xy
 
 
-def frozen_fd(xy0, M, a, rec, group, p: Params, which: str, index, step: float):
-    """Central finite difference of frozen_loss in one parameter: which is "M" (index (l, b)),
-    "a" (index k) or "x" (index (point, coordinate))."""
+def frozen_fd(xy0, M, a, rec, group, p: Params, which: str, index, step: float, cT=None):
+    """Central finite difference of frozen_loss (ink, or the linear loss of weights cT) in
+    one parameter: which is "M" (index (l, b)), "a" (index k) or "x" (index (point,
+    coordinate))."""
     def f(delta):
         x, m, aa = np.array(xy0, np.float64), np.array(M, np.float64), np.array(a, np.float64)
         if which == "M":
@@ -593,5 +607,5 @@ def frozen_fd(xy0, M, a, rec, group, p: Params, which: str, index, step: float):
             aa[index] += delta
         else:
             x[index] += delta
-        return frozen_loss(x, m, aa, rec, group, p)
+        return frozen_loss(x, m, aa, rec, group, p, cT)
     return (f(step) - f(-step)) / (2.0 * step)

@@ -224,8 +224,11 @@ EXPORT void orc_insdel(int64_t E, const int64_t *off_in, const double *xy_in, do
  * Reading: the normal is that of the polyline segment the sample was interpolated on (the
  * segment index seg from orc_resample, taken in the input polyline), on its left-hand side:
  * (-t_y, t_x) for the unit direction t of the segment, oriented from source to target; the
- * signed distance d is in pixels; the push is applied to the samples of every iteration,
- * straight after resampling and before the histogram.
+ * signed distance d is in pixels; the push is applied to a set of samples straight after
+ * their resampling and before the histogram. The pipeline pushes once, after the first
+ * sampling, and then loops from the resampling, which interpolates along the pushed
+ * polyline and so keeps the offset; the loop (oracle/__init__.py, iterate) applies it in
+ * iteration 0 only, or after every resampling when asked to.
  * Pins: closed form on straight edges (interior samples at signed distance d from the line,
  * the along-edge coordinate unchanged), edges in opposite directions part by 2|d|, d = 0 is
  * the identity, a rotation by 90 degrees commutes with the push.

@@ -24,6 +24,7 @@ HB_POINTS_STATE, HB_POINTS_SAMPLES = 0, 1
 HB_MAP_HIST, HB_MAP_BOX, HB_MAP_DENSITY, HB_MAP_GRAD = 0, 1, 2, 3
 HB_SPLAT_POINTS, HB_SPLAT_STRIP = 0, 1
 HB_RESAMPLE_UNIFORM, HB_RESAMPLE_INSERT_DELETE = 0, 1
+HB_DIRECTED_ONCE, HB_DIRECTED_EVERY_ITER = 0, 1
 HB_FEAT_ORIGIN, HB_FEAT_DESTINATION, HB_FEAT_ORIGIN_DESTINATION, HB_FEAT_LENGTH = 0, 1, 2, 3
 HB_KMEANS_MAX_K, HB_KMEANS_MAX_DIM = 64, 8
 _FEAT_DIM = {0: 2, 1: 2, 2: 4, 3: 1}
@@ -65,6 +66,7 @@ class hb_params(ctypes.Structure):
         ("delta_min_px", ctypes.c_float),
         ("n_sigmas", ctypes.c_int32),
         ("sigma_per_iter", ctypes.POINTER(ctypes.c_float)),
+        ("directed_mode", ctypes.c_int32),
     ]
 
 
@@ -116,9 +118,11 @@ _SIGS = {
     "hb_version": (ctypes.c_char_p, []),
     "hb_set_profiling": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32]),
     "hb_batch_run": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint32]),
-    "hb_forward_ckpt": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32]),
-    "hb_backward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_double), ctypes.c_void_p,
-                                     ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32]),
+    "hb_forward_ckpt": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32,
+                                         ctypes.POINTER(ctypes.c_int64)]),
+    "hb_backward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
+                                     ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_void_p,
+                                     ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32]),
     "hb_get_ckpt_points": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32]),
     "hb_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
@@ -461,7 +465,7 @@ def make_params(grid_w: int, grid_h: int, radii: Sequence[int], *, delta: float 
                 pass_weights: Optional[Sequence[float]] = None, bbox=(0.0, 0.0, 1.0, 1.0),
                 capacity_factor: float = 2.0, directed_offset: float = 0.0,
                 splat_mode: int = 0, resample_mode: int = 0, delta_min: float = 0.0,
-                sigmas: Optional[Sequence[float]] = None):
+                sigmas: Optional[Sequence[float]] = None, directed_mode: int = 0):
     """hb_params plus the arrays it points to (keep both alive until hb_set_params)."""
     p = hb_default_params(grid_w, grid_h)
     r = (ctypes.c_int32 * len(radii))(*[int(v) for v in radii])
@@ -478,6 +482,7 @@ def make_params(grid_w: int, grid_h: int, radii: Sequence[int], *, delta: float 
         p.bbox[i] = bbox[i]
     p.capacity_factor = capacity_factor
     p.directed_offset_px = directed_offset
+    p.directed_mode = directed_mode
     p.splat_mode = splat_mode
     p.resample_mode = resample_mode
     p.delta_min_px = delta_min
@@ -612,18 +617,34 @@ def autotune(bundlers, n_iters: int = 1):
 
 # ------------------------------------------------------------------ differentiable form
 
-def hb_forward_ckpt(ctx, n_iters: int) -> None:
-    _check(ctx, load().hb_forward_ckpt(ctx, n_iters, 0))
+def hb_forward_ckpt(ctx, n_iters: int) -> int:
+    """Checkpointed forward of n_iters iterations; returns the checkpoints' generation."""
+    gen = ctypes.c_int64()
+    _check(ctx, load().hb_forward_ckpt(ctx, n_iters, 0, ctypes.byref(gen)))
+    return int(gen.value)
 
 
-def hb_backward(ctx, n_groups: int, n_passes: int, n_points0: int):
-    """(loss, dL/dM [B, B], dL/da [P], dL/dxy0 [N0, 2]) as numpy arrays."""
+def hb_backward(ctx, n_groups: int, n_passes: int, n_points0: int, dL_dxy_T=None,
+                generation: int = -1, device=None):
+    """(loss, dL/dM [B, B], dL/da [P], dL/dxy0 [N0, 2]). dL_dxy_T: gradient of the caller's
+    loss with respect to the final polylines ([N_T, 2] numpy array or torch tensor; None: the
+    ink loss). dL/dxy0 is a numpy array, or a torch tensor on ``device`` when given (then a
+    given dL_dxy_T must be a tensor on that device too)."""
     loss = ctypes.c_double()
     dM = np.zeros((n_groups, n_groups), np.float32)
     da = np.zeros(n_passes, np.float32)
-    dx = np.zeros((n_points0, 2), np.float32)
-    _check(ctx, load().hb_backward(ctx, ctypes.byref(loss), dM.ctypes.data, da.ctypes.data,
-                                   dx.ctypes.data, n_points0, 0))
+    pg, keep, gdev = _arr(dL_dxy_T, np.float32)
+    n_t = int(keep.shape[0]) if keep is not None else 0
+    if device is not None:
+        import torch
+        dx = torch.zeros((n_points0, 2), dtype=torch.float32, device=device)
+        px, xdev = dx.data_ptr(), True
+    else:
+        dx = np.zeros((n_points0, 2), np.float32)
+        px, xdev = dx.ctypes.data, False
+    flags = _flags(gdev if keep is not None else None, xdev)
+    _check(ctx, load().hb_backward(ctx, generation, pg, n_t, ctypes.byref(loss), dM.ctypes.data,
+                                   da.ctypes.data, px, n_points0, flags))
     return float(loss.value), dM, da, dx
 
 
@@ -638,32 +659,62 @@ def _bundle_function():
     import torch
 
     class BundleFn(torch.autograd.Function):
-        """Ink after ``n_iters`` bundling iterations as a differentiable function of the
-        polylines ``xy0`` (N0 x 2, layout ``offsets``), the interaction matrix ``M`` (B x B) and
-        the pass weights ``a`` (P), with the discrete choices of the forward run held fixed.
-        ``bundler`` must already hold the graph, groups and parameters; the forward pass sets
-        M, a and the polylines, runs with per-iteration checkpoints, and the backward pass
-        calls the hand-written adjoint."""
+        """The final polylines after ``n_iters`` bundling iterations started at iteration
+        ``start_iter``, as a differentiable function of the polylines ``xy0`` (N0 x 2 on the
+        context's device, layout ``offsets``), the interaction matrix ``M`` (B x B) and the pass
+        weights ``a`` (P), with the discrete choices of the forward run held fixed. Returns
+        (xy_T [N_T, 2] float32, offsets_T [E+1] int64, ink float64); the offsets are not
+        differentiable, and a loss may use xy_T, the ink, or both. ``bundler`` must already
+        hold the graph and its parameters; the forward pass sets M, a, the start iteration and
+        the polylines (device to device), runs with per-iteration checkpoints and keeps their
+        generation, and the backward pass calls the hand-written adjoint with the gradient of
+        the loss, failing with HB_ESTATE if the checkpoints were replaced meanwhile."""
 
         @staticmethod
-        def forward(ctx, xy0, M, a, bundler, offsets, group, n_iters, params):
+        def forward(ctx, xy0, M, a, bundler, offsets, group, n_iters, start_iter, params):
+            ctx.set_materialize_grads(False)   # an output the loss does not use gets None
+            dev = xy0.device
+            if dev.type != "cuda":
+                raise ValueError("xy0 must be a tensor on the context's GPU")
             bundler.set_params(**params, pass_weights=[float(v) for v in a.detach().cpu()])
             bundler.set_groups(group, M.detach().cpu().numpy())
-            bundler.set_points(offsets, xy0.detach().cpu().numpy())
-            hb_forward_ckpt(bundler.ctx, n_iters)
+            torch.cuda.current_stream(dev).synchronize()   # xy0 complete before the library reads it
+            off_in = torch.as_tensor(np.asarray(offsets, np.int64), device=dev)
+            bundler.set_points(off_in, xy0.detach().float().contiguous())
+            bundler.iteration = int(start_iter)
+            ctx.gen = hb_forward_ckpt(bundler.ctx, n_iters)
+            off_t, xy_t = bundler.points(HB_POINTS_STATE, device=dev)
+            ink = hb_get_ink(bundler.ctx)
             ctx.bundler = bundler
             ctx.shapes = (M.shape[0], a.shape[0], xy0.shape[0])
-            ctx.devs = (xy0.device, M.device, a.device)
-            return torch.tensor(hb_get_ink(bundler.ctx), dtype=torch.float64, device=xy0.device)
+            ctx.devs = (dev, M.device, a.device)
+            ctx.mark_non_differentiable(off_t)
+            return xy_t, off_t, torch.tensor(ink, dtype=torch.float64, device=dev)
 
         @staticmethod
-        def backward(ctx, g):
-            _, dM, da, dx = hb_backward(ctx.bundler.ctx, *ctx.shapes)
-            gv = float(g)
-            return (torch.from_numpy(dx).to(ctx.devs[0]) * gv,
-                    torch.from_numpy(dM).to(ctx.devs[1]) * gv,
-                    torch.from_numpy(da).to(ctx.devs[2]) * gv,
-                    None, None, None, None, None)
+        def backward(ctx, g_xy, g_off, g_ink):
+            import torch
+            b = ctx.bundler
+            dev = ctx.devs[0]
+            gi = 0.0 if g_ink is None else float(g_ink)
+            outs = []
+            # the ink part through the fused ink gradient, the rest through dL/dxy_T
+            if gi != 0.0:
+                outs.append((gi, hb_backward(b.ctx, *ctx.shapes, generation=ctx.gen, device=dev)))
+            if g_xy is not None:
+                torch.cuda.current_stream(dev).synchronize()
+                gt = g_xy.detach().float().contiguous()
+                outs.append((1.0, hb_backward(b.ctx, *ctx.shapes, dL_dxy_T=gt,
+                                              generation=ctx.gen, device=dev)))
+            dx = torch.zeros(ctx.shapes[2], 2, dtype=torch.float32, device=dev)
+            dM = np.zeros((ctx.shapes[0], ctx.shapes[0]), np.float32)
+            da = np.zeros(ctx.shapes[1], np.float32)
+            for wgt, (_, m, aa, x) in outs:
+                dx += wgt * x
+                dM += wgt * m
+                da += wgt * aa
+            return (dx, torch.from_numpy(dM).to(ctx.devs[1]), torch.from_numpy(da).to(ctx.devs[2]),
+                    None, None, None, None, None, None)
 
     return BundleFn
 
@@ -671,9 +722,15 @@ def _bundle_function():
 _BUNDLE_FN = None
 
 
-def bundle_ink(xy0, M, a, bundler, offsets, group, n_iters, params):
-    """torch entry point of the differentiable form (see BundleFn)."""
+def bundle_polylines(xy0, M, a, bundler, offsets, group, n_iters, params, start_iter=0):
+    """torch entry point of the differentiable form: (xy_T, offsets_T, ink) after n_iters
+    iterations from iteration start_iter (see BundleFn)."""
     global _BUNDLE_FN
     if _BUNDLE_FN is None:
         _BUNDLE_FN = _bundle_function()
-    return _BUNDLE_FN.apply(xy0, M, a, bundler, offsets, group, n_iters, params)
+    return _BUNDLE_FN.apply(xy0, M, a, bundler, offsets, group, n_iters, start_iter, params)
+
+
+def bundle_ink(xy0, M, a, bundler, offsets, group, n_iters, params, start_iter=0):
+    """Ink of the final polylines as a differentiable function of xy0, M and a."""
+    return bundle_polylines(xy0, M, a, bundler, offsets, group, n_iters, params, start_iter)[2]

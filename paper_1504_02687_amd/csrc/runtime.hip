@@ -118,6 +118,7 @@ struct hb_ctx {
     std::vector<Ckpt> ckpts;       // checkpoints of the last hb_forward_ckpt
     std::vector<Ckpt> ckpt_pool;   // allocated checkpoint buffers for reuse
     int32_t ckpt_end_iter = -1;
+    int64_t ckpt_gen = 0;          // generation of the checkpoints (one more per forward)
 
     // adjoint work buffers, kept between backward passes
     struct AdjBufs {
@@ -255,6 +256,7 @@ HB_API void hb_default_params(hb_params *p, int32_t grid_w, int32_t grid_h) {
     p->delta_min_px = 0.0f;
     p->n_sigmas = 0;
     p->sigma_per_iter = nullptr;
+    p->directed_mode = HB_DIRECTED_ONCE;
 }
 
 static void kovesi_radii(double sigma, int P, int32_t *radii);
@@ -323,6 +325,8 @@ static hb_status validate(hb_ctx *c, const hb_params *p) {
         return fail(c, HB_EINVAL, "delta_min_px must be 0 (delta_px / 2) or in (0, delta_px)");
     if (p->resample_mode == HB_RESAMPLE_INSERT_DELETE && p->directed_offset_px != 0.0f)
         return fail(c, HB_EINVAL, "the directed offset needs the uniform resampling");
+    if (p->directed_mode != HB_DIRECTED_ONCE && p->directed_mode != HB_DIRECTED_EVERY_ITER)
+        return fail(c, HB_EINVAL, "directed_mode must be HB_DIRECTED_ONCE or HB_DIRECTED_EVERY_ITER");
     return HB_OK;
 }
 
@@ -492,7 +496,7 @@ static GDesc base_desc(const hb_ctx *c) {
     d.eps = (double)c->P.eps;
     d.s = (double)c->P.smooth_weight;
     d.delta = (double)c->P.delta_px;
-    d.doff = (double)c->P.directed_offset_px;
+    d.doff = 0.0;   // per iteration, set_iter_scalars
     d.strip = c->P.splat_mode == HB_SPLAT_STRIP ? 1 : 0;
     d.ent_cap = c->ent_cap;
     d.insdel = c->P.resample_mode == HB_RESAMPLE_INSERT_DELETE ? 1 : 0;
@@ -537,6 +541,9 @@ static GDesc base_desc(const hb_ctx *c) {
 }
 
 static void set_iter_scalars(const hb_ctx *c, GDesc &d, int it) {
+    // the directed push follows the first sampling (iteration 0), or every resampling
+    const bool push = it == 0 || c->P.directed_mode == HB_DIRECTED_EVERY_ITER;
+    d.doff = push ? (double)c->P.directed_offset_px : 0.0;
     pass_radii(c, it, d.rp);
     d.r = d.rp[d.P - 1];
     d.h = bandwidth_at(c, it);
@@ -2006,7 +2013,7 @@ static GDesc ckpt_desc(hb_ctx *c, const float2 *pin, const int64_t *off_in, floa
 // checkpoint t, writes its samples, decisions and splat bins into checkpoint t and its new
 // polylines into checkpoint t + 1 (the last one into the context's state buffer). Each
 // iteration first scans the sample counts alone, so every buffer is sized exactly.
-HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
+HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags, int64_t *generation) {
     ENTER(c);
     CHKST(finish_pending(c));
     if (!c->have_params || !c->have_graph || !c->have_groups)
@@ -2026,6 +2033,7 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
     for (auto &k : c->ckpts) c->ckpt_pool.push_back(k);
     c->ckpts.clear();
     c->ckpt_end_iter = -1;
+    c->ckpt_gen += 1;
     CHKST(prepare_ctx(c, 1, 0));
     CHKST(ensure_desc(c, 1));
     CHKST(wait_desc(c));
@@ -2139,6 +2147,7 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
     c->have_maps = true;
     c->last_counts = counts;
     c->ckpt_end_iter = c->iter;
+    if (generation) *generation = c->ckpt_gen;
     return HB_OK;
 }
 
@@ -2146,17 +2155,23 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags) {
 // respect to M (B x B), the pass weights a (P) and the polylines that entered the run. The
 // maps of each iteration are rebuilt from its checkpointed histogram; the samples and the
 // accepted halvings come from the checkpoints, so nothing else is recomputed.
-HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da, float *dL_dxy0,
-                             int64_t cap_points, uint32_t flags) {
+HB_API hb_status hb_backward(hb_ctx *c, int64_t generation, const float *dL_dxy_T,
+                             int64_t n_points_T, double *loss, float *dL_dM, float *dL_da,
+                             float *dL_dxy0, int64_t cap_points, uint32_t flags) {
     ENTER(c);
     CHKST(finish_pending(c));
     if (c->ckpts.empty() || c->iter != c->ckpt_end_iter)
         return fail(c, HB_ESTATE, "hb_backward needs hb_forward_ckpt just before it");
+    if (generation >= 0 && generation != c->ckpt_gen)
+        return fail(c, HB_ESTATE, "the checkpoints of that generation have been replaced");
+    if (generation < -1) return fail(c, HB_EINVAL, "generation must be -1 or a generation");
     if (flags & ~(uint32_t)HB_DEVICE_PTRS) return fail(c, HB_EINVAL, "unknown flags");
     const int T = (int)c->ckpts.size();
     const int B = c->B, P = c->P.box_passes, W = c->P.grid_w, H = c->P.grid_h;
     const int64_t E = c->E, n0 = c->ckpts[0].n;
     if (dL_dxy0 && cap_points < n0) return fail(c, HB_EINVAL, "dL_dxy0 buffer too small");
+    if (dL_dxy_T && n_points_T != c->n_state)
+        return fail(c, HB_EINVAL, "n_points_T must equal the point count of the final polylines");
     int64_t nmax = c->n_state;
     for (auto &k : c->ckpts) nmax = std::max(nmax, std::max(k.n, k.ns));
     CHKST(ensure_maps(c));
@@ -2190,6 +2205,10 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
 
     const Shape s = hb::shape_of(E, B, W, H);
     float2 *cur = A.a0, *other = A.a1;   // cur: adjoint of the polylines leaving iteration t
+    if (dL_dxy_T && c->n_state > 0)      // the caller's loss gradient enters the last iteration
+        HIPCHK(c, hipMemcpyAsync(cur, dL_dxy_T, sizeof(float2) * c->n_state,
+                                 (flags & HB_DEVICE_PTRS) ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice,
+                                 c->stream));
     for (int t = T - 1; t >= 0; --t) {
         const hb_ctx::Ckpt &k = c->ckpts[t];
         const size_t slot = 2 * (size_t)(T - 1 - t);
@@ -2206,7 +2225,8 @@ HB_API hb_status hb_backward(hb_ctx *c, double *loss, float *dL_dM, float *dL_da
         a.pp = pp;
         a.adj_in = cur;
         a.adj_out = other;
-        if (t == T - 1) a.ink_pts = c->pts[c->ps];   // the loss gradient, computed in place
+        // the ink gradient is computed in place from the final polylines, unless given
+        if (t == T - 1 && !dL_dxy_T) a.ink_pts = c->pts[c->ps];
         a.partials = A.partials;
         a.max_items = max_items;
         a.abin_src = k.bsrc;

@@ -102,22 +102,130 @@ def test_autograd_function_matches_backward(hb):
     w = workloads.scaled("zipf", n_edges=80, grid=64, groups=2, n_iters=2, seed=8)
     params = dict(grid_w=w.grid_w, grid_h=w.grid_h, radii=w.radii, delta=w.delta, passes=w.passes,
                   lam=w.lam)
+    dev = torch.device("cuda:0")
     with hb.Bundler(0) as b:
         b.set_workload(w)
         off, xy = b.points()
-        xy0 = torch.tensor(xy, dtype=torch.float32, requires_grad=True)
+        xy0 = torch.tensor(xy, dtype=torch.float32, device=dev, requires_grad=True)
         M = torch.tensor(w.M, dtype=torch.float32, requires_grad=True)
         a = torch.tensor([0.0, 0.0, 1.0], dtype=torch.float32, requires_grad=True)
         loss = hb.bundle_ink(xy0, M, a, b, off, w.group, 2, params)
         loss.backward()
+        # the same run through the C calls, from the same start iteration
         b.set_points(off, xy)
         b.iteration = 0
         hb.hb_forward_ckpt(b.ctx, 2)
         l2, dM, da, dx = hb.hb_backward(b.ctx, 2, 3, len(xy))
-    assert float(loss) == l2
+    assert float(loss.detach()) == l2
     np.testing.assert_array_equal(M.grad.numpy(), dM)
     np.testing.assert_array_equal(a.grad.numpy(), da)
-    np.testing.assert_array_equal(xy0.grad.numpy(), dx)
+    np.testing.assert_array_equal(xy0.grad.cpu().numpy(), dx)
+
+
+def test_autograd_twice_same_loss_and_stale_node_rejected(hb):
+    """The forward sets its start iteration itself, so two calls on one context give the same
+    loss and gradients; a graph node whose checkpoints were replaced by a later forward
+    refuses its backward (HB_ESTATE) instead of returning the later run's gradients."""
+    import torch
+    w = workloads.scaled("zipf", n_edges=80, grid=64, groups=2, n_iters=2, seed=8)
+    params = dict(grid_w=w.grid_w, grid_h=w.grid_h, radii=w.radii, delta=w.delta, passes=w.passes,
+                  lam=w.lam)
+    dev = torch.device("cuda:0")
+    with hb.Bundler(0) as b:
+        b.set_workload(w)
+        off, xy = b.points()
+        grads = []
+        losses = []
+        for _ in range(2):
+            xy0 = torch.tensor(xy, dtype=torch.float32, device=dev, requires_grad=True)
+            M = torch.tensor(w.M, dtype=torch.float32, requires_grad=True)
+            a = torch.tensor([0.0, 0.0, 1.0], dtype=torch.float32, requires_grad=True)
+            loss = hb.bundle_ink(xy0, M, a, b, off, w.group, 2, params)
+            loss.backward()
+            losses.append(float(loss.detach()))
+            grads.append((M.grad.numpy().copy(), a.grad.numpy().copy(), xy0.grad.cpu().numpy()))
+        assert losses[0] == losses[1]
+        for g1, g2 in zip(*grads):
+            np.testing.assert_array_equal(g1, g2)
+        # two forwards, then the backward of the first
+        xa = torch.tensor(xy, dtype=torch.float32, device=dev, requires_grad=True)
+        Ma = torch.tensor(w.M, dtype=torch.float32, requires_grad=True)
+        aa = torch.tensor([0.0, 0.0, 1.0], dtype=torch.float32, requires_grad=True)
+        first = hb.bundle_ink(xa, Ma, aa, b, off, w.group, 2, params)
+        second = hb.bundle_ink(xa.detach().clone().requires_grad_(True), Ma.detach().clone(),
+                               aa.detach().clone(), b, off, w.group, 2, params)
+        with pytest.raises(hb.HBError) as ei:
+            first.backward()
+        assert ei.value.status == hb.HB_ESTATE
+        second.backward()                     # the current checkpoints still work
+
+
+def test_caller_loss_gradient_matches_oracle(hb):
+    """A loss of the final polylines other than ink: L = sum(c * xy_T) with fixed random c,
+    its gradient given to hb_backward (host and device forms, and through autograd), against
+    the oracle's central differences of the same loss on its frozen surrogate."""
+    import torch
+    w = workloads.scaled("clustered", n_edges=60, grid=64, groups=3, n_iters=2, seed=5)
+    p = O.params_for(w)
+    T = 2
+    with _setup(hb, w) as b:
+        off0, xy0h = b.points()
+        n0 = len(xy0h)
+        gen = hb.hb_forward_ckpt(b.ctx, T)
+        offT, xyT = b.points()
+        c = np.random.default_rng(3).normal(size=xyT.shape).astype(np.float32)
+        _, dM, da, dx = hb.hb_backward(b.ctx, w.n_groups, w.passes, n0, dL_dxy_T=c, generation=gen)
+        dev = torch.device("cuda:0")
+        _, dMd, dad, dxd = hb.hb_backward(b.ctx, w.n_groups, w.passes, n0,
+                                          dL_dxy_T=torch.from_numpy(c).to(dev), device=dev)
+        with pytest.raises(hb.HBError) as ei:      # wrong length
+            hb.hb_backward(b.ctx, w.n_groups, w.passes, n0, dL_dxy_T=c[:-1])
+        assert ei.value.status == hb.HB_EINVAL
+        with pytest.raises(hb.HBError) as ei:      # an older generation
+            hb.hb_backward(b.ctx, w.n_groups, w.passes, n0, dL_dxy_T=c, generation=gen - 1)
+        assert ei.value.status == hb.HB_ESTATE
+        # autograd: the polylines output with the same linear loss
+        params = dict(grid_w=w.grid_w, grid_h=w.grid_h, radii=w.radii, delta=w.delta,
+                      passes=w.passes, lam=w.lam)
+        xt = torch.tensor(xy0h, dtype=torch.float32, device=dev, requires_grad=True)
+        Mt = torch.tensor(w.M, dtype=torch.float32, requires_grad=True)
+        at = torch.tensor([0.0, 0.0, 1.0], dtype=torch.float32, requires_grad=True)
+        xyt, offt, _ = hb.bundle_polylines(xt, Mt, at, b, off0, w.group, T, params)
+        np.testing.assert_array_equal(offt.cpu().numpy(), offT)
+        (torch.from_numpy(c).to(dev) * xyt).sum().backward()
+    np.testing.assert_array_equal(dMd, dM)
+    np.testing.assert_array_equal(dad, da)
+    np.testing.assert_array_equal(dxd.cpu().numpy(), dx)
+    np.testing.assert_array_equal(Mt.grad.numpy(), dM)
+    np.testing.assert_array_equal(at.grad.numpy(), da)
+    np.testing.assert_array_equal(xt.grad.cpu().numpy(), dx)
+
+    off, xy = O.initial_state(w.node_xy, w.src, w.dst, p)
+    rec, offR, xyR = O.record_run(off, xy, w.group, w.M, p, T)
+    np.testing.assert_array_equal(offR, offT)
+    cT = c.astype(np.float64)
+    M = w.M.astype(np.float64)
+    fd = lambda which, idx, st=1e-6: O.frozen_fd(xy, M, p.a(), rec, w.group, p, which, idx, st, cT)
+    B = w.n_groups
+    gM = np.array([[fd("M", (l, bb)) for bb in range(B)] for l in range(B)])
+    ga = np.array([fd("a", k) for k in range(3)])
+    rng = np.random.default_rng(4)
+    coords = []
+    for i in rng.permutation(len(xy)):
+        for cc in range(2):
+            g6, g5 = fd("x", (i, cc)), fd("x", (i, cc), 1e-5)
+            if abs(g6 - g5) <= 1e-5 * max(abs(g6), 1e-3):      # not on a kink
+                coords.append((i, cc, g6))
+        if len(coords) >= 16:
+            break
+    assert len(coords) >= 16
+    gx = np.array([g for _, _, g in coords])
+    got = np.array([dx[i, cc] for i, cc, _ in coords])
+    scale = max(np.abs(gM).max(), np.abs(ga).max(), np.abs(gx).max())
+    floor = 1e-6 * scale
+    np.testing.assert_allclose(dM, gM, rtol=1e-3, atol=floor)
+    np.testing.assert_allclose(da, ga, rtol=1e-3, atol=floor)
+    np.testing.assert_allclose(got, gx, rtol=1e-3, atol=floor)
 
 
 def test_backward_needs_fresh_checkpoints(hb):

@@ -94,12 +94,42 @@ def test_directed_offset_resample_parity(hb, E, W, H, delta, doff, seed):
     assert np.abs(hist - href).sum() <= 2 * PT.near_pixel_edge(rp).sum()
 
 
-def test_directed_offset_end_to_end_tiny(hb):
+@pytest.mark.parametrize("every", [False, True])
+def test_directed_push_once_or_every_iteration_closed_form(hb, every):
+    """A straight horizontal edge and its reversed copy with the advection made negligible
+    (h = 1e-12 px) and no Laplacian smoothing: after T iterations their middles sit at
+    +-|d| from the line when the push follows the first sampling only, and at +-T|d| when
+    it follows every resampling (the oracle's closed form, here through the library)."""
+    W, T, d = 128, 4, 0.75
+    node = np.array([[8.25 / W, 60.5 / W], [120.25 / W, 60.5 / W]], np.float32)
+    with hb.Bundler(0) as b:
+        b.set_params(W, W, [4], h_max=1e-12, smooth_weight=0.0, directed_offset=d,
+                     directed_mode=hb.HB_DIRECTED_EVERY_ITER if every else hb.HB_DIRECTED_ONCE)
+        b.set_graph(node, np.array([0, 1], np.int32), np.array([1, 0], np.int32))
+        b.set_groups(np.zeros(2, np.int32), np.ones((1, 1), np.float32))
+        b.run(T)
+        off, xy = b.points(hb.HB_POINTS_STATE)
+    p = O.Params(grid_w=W, grid_h=W, radii=[4], directed_offset=d, h_max=1e-12,
+                 smooth_weight=0.0, directed_every=every)
+    roff, rxy, _ = O.run(node, np.array([0, 1]), np.array([1, 0]), np.zeros(2, np.int32),
+                         np.ones((1, 1)), p, T)
+    np.testing.assert_array_equal(off, roff)
+    assert np.abs(xy.astype(np.float64) - rxy).max() <= 1e-4
+    k = T if every else 1
+    a, bb = xy[off[0]:off[1]].astype(np.float64), xy[off[1]:off[2]].astype(np.float64)
+    mid = np.abs(a[:, 0] - 64.0) < 30.0
+    np.testing.assert_allclose(a[mid, 1] - 60.5, k * d, atol=1e-4)
+    mid = np.abs(bb[:, 0] - 64.0) < 30.0
+    np.testing.assert_allclose(bb[mid, 1] - 60.5, -k * d, atol=1e-4)
+
+
+@pytest.mark.parametrize("every", [False, True])
+def test_directed_offset_end_to_end_tiny(hb, every):
     """The tiny workload with a 1 px push (0.4 % of the 256 px drawing), orientation slices
-    as groups and the Eq. 4 interaction, against the oracle over 7 iterations. (Later
-    iterations of this run are chaotic: rounding the oracle's own polylines to FP32 after
-    every iteration moves its ink by 0.14 % at the 9th and 0.5 % at the 10th, against
-    <= 0.02 % up to the 7th.)"""
+    as groups and the Eq. 4 interaction, against the oracle over 7 iterations, with the push
+    after the first sampling only and after every resampling. (Later iterations of this run
+    are chaotic: rounding the oracle's own polylines to FP32 after every iteration moves its
+    ink by 0.14 % at the 9th and 0.5 % at the 10th, against <= 0.02 % up to the 7th.)"""
     w = workloads.tiny()
     n_iters = 7
     doff = 1.0
@@ -108,7 +138,8 @@ def test_directed_offset_end_to_end_tiny(hb):
     M = workloads.interaction_eq4(4, 0.25)
     with hb.Bundler(0) as b:
         b.set_params(w.grid_w, w.grid_h, w.radii, delta=w.delta, passes=w.passes, lam=w.lam,
-                     bbox=w.bbox, directed_offset=doff)
+                     bbox=w.bbox, directed_offset=doff,
+                     directed_mode=hb.HB_DIRECTED_EVERY_ITER if every else hb.HB_DIRECTED_ONCE)
         b.set_graph(w.node_xy, w.src, w.dst, w.weight)
         np.testing.assert_array_equal(b.orientation_groups(), group)
         b.set_groups(group, M)
@@ -120,6 +151,7 @@ def test_directed_offset_end_to_end_tiny(hb):
         ink = b.ink()
     p = O.params_for(w)
     p.directed_offset = doff
+    p.directed_every = every
     o0, x0 = O.initial_state(w.node_xy, w.src, w.dst, p)
     r0 = O.iterate(o0, x0, group, M.astype(np.float64), p, 0, keep_maps=False)
     np.testing.assert_array_equal(off1, r0["off"])
@@ -131,7 +163,7 @@ def test_directed_offset_end_to_end_tiny(hb):
         assert PT.relclose(a, b_, 0.01)
     ds, dr = PT.drift_stats(off, xy), PT.drift_stats(roff, rxy)
     for k in ("mean", "p50", "p90", "p99"):
-        assert abs(ds[k] - dr[k]) <= 0.01 * dr[k] + 0.02, (k, ds[k], dr[k])
+        assert abs(ds[k] - dr[k]) <= 0.01 * dr[k], (k, ds[k], dr[k])
 
 
 def test_directed_offset_rejected_by_checkpointed_forward(hb):

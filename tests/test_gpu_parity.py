@@ -372,3 +372,23 @@ def test_api_errors_on_device(hb):
             b.set_points(np.array([0, 1, 3], np.int64), np.zeros((3, 2), np.float32))
         with pytest.raises(hb.HBError):
             b.decisions()
+
+
+def test_allocation_failure_is_an_error_code(hb, monkeypatch):
+    """A failed device allocation (simulated through HB_TEST_FAIL_ALLOC, which makes every
+    allocation of the library fail) returns HB_ENOMEM without aborting; once allocations
+    succeed again the same context sets the graph and runs."""
+    w = workloads.scaled("uniform", n_edges=200, grid=64, groups=2, n_iters=1, seed=5)
+    with hb.Bundler(0) as b:
+        b.set_params(w.grid_w, w.grid_h, w.radii)
+        monkeypatch.setenv("HB_TEST_FAIL_ALLOC", "1")
+        with pytest.raises(hb.HBError) as ei:
+            b.set_graph(w.node_xy, w.src, w.dst)
+        assert ei.value.status == hb.HB_ENOMEM
+        assert "allocation" in hb.hb_last_error(b.ctx)
+        monkeypatch.delenv("HB_TEST_FAIL_ALLOC")
+        b.set_graph(w.node_xy, w.src, w.dst)
+        b.set_groups(w.group, w.M)
+        b.run(1)
+        off, xy = b.points()
+        assert off[-1] == len(xy) > 0

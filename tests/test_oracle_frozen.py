@@ -49,3 +49,23 @@ def test_central_differences_converge():
         g5 = O.frozen_fd(xy, w.M, p.a(), rec, w.group, p, which, idx, 1e-5)
         g6 = O.frozen_fd(xy, w.M, p.a(), rec, w.group, p, which, idx, 1e-6)
         assert abs(g5 - g6) <= 1e-4 * max(abs(g6), 1e-3), (which, g5, g6)
+
+
+def test_frozen_state_replays_base_run_and_linear_loss():
+    w, p, xy, rec, offT, xyT = _case()
+    xs = O.frozen_state(xy, w.M, p.a(), rec, w.group, p)
+    np.testing.assert_array_equal(offT, rec[-1]["s_off"])
+    assert np.abs(xs - xyT).max() <= 1e-9
+    # the linear loss of weights cT is the weighted sum of the final coordinates
+    c = np.zeros_like(xs)
+    c[7, 0], c[11, 1] = 2.0, -0.5
+    L = O.frozen_loss(xy, w.M, p.a(), rec, w.group, p, c)
+    assert abs(L - (2.0 * xyT[7, 0] - 0.5 * xyT[11, 1])) <= 1e-9 * (1 + abs(L))
+    # end points never move, so the gradient of an end point's final coordinate with
+    # respect to the same end point is 1 beside what it does through the interior
+    end = int(offT[1]) - 1                     # last point of edge 0 in the final layout
+    c = np.zeros_like(xs)
+    c[end, 0] = 1.0
+    start_end = 1                              # edge 0's last point in the two-point start
+    g = O.frozen_fd(xy, w.M, p.a(), rec, w.group, p, "x", (start_end, 0), 1e-6, c)
+    assert abs(g - 1.0) <= 1e-6

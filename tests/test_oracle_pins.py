@@ -568,6 +568,41 @@ def test_directed_run_keeps_opposite_edges_mirrored():
     np.testing.assert_array_equal(xy0[:, 1], 30.5)
 
 
+@pytest.mark.parametrize("every", [False, True])
+def test_directed_push_once_or_every_iteration(every):
+    # Section 3's pipeline pushes once after the first sampling and then loops from the
+    # resampling, which interpolates along the pushed polyline and so keeps the offset.
+    # With the advection made negligible (h = 1e-12 px) and no Laplacian smoothing, the
+    # middle of a straight horizontal edge therefore sits at exactly |d| from its line after
+    # any number of iterations, and its reversed copy at -d: the two part by 2|d|, once.
+    # Pushing after every resampling instead stacks the offsets: T|d| after T iterations.
+    W, T, d = 128, 4, 0.75
+    p = _params(W, [4], directed_offset=d, h_max=1e-12, smooth_weight=0.0,
+                directed_every=every)
+    node = np.array([[8.25 / W, 60.5 / W], [120.25 / W, 60.5 / W]], np.float32)
+    off, xy, _ = O.run(node, np.array([0, 1]), np.array([1, 0]), np.zeros(2, np.int32),
+                       np.ones((1, 1)), p, T)
+    a, b = xy[off[0]:off[1]], xy[off[1]:off[2]]
+    k = T if every else 1
+    mid_a = np.abs(a[:, 0] - 64.0) < 30.0
+    mid_b = np.abs(b[:, 0] - 64.0) < 30.0
+    np.testing.assert_allclose(a[mid_a, 1] - 60.5, k * d, atol=1e-9)
+    np.testing.assert_allclose(b[mid_b, 1] - 60.5, -k * d, atol=1e-9)
+    # the interior never goes past the middle's offset; the end points stay
+    assert np.abs(a[1:-1, 1] - 60.5).max() <= k * d + 1e-9
+    np.testing.assert_array_equal(a[[0, -1], 1], 60.5)
+    np.testing.assert_array_equal(b[[0, -1], 1], 60.5)
+    # one iteration is the same in both readings (the first sampling is pushed)
+    p1 = _params(W, [4], directed_offset=d, h_max=1e-12, smooth_weight=0.0,
+                 directed_every=not every)
+    o1, x1, _ = O.run(node, np.array([0, 1]), np.array([1, 0]), np.zeros(2, np.int32),
+                      np.ones((1, 1)), p1, 1)
+    o2, x2, _ = O.run(node, np.array([0, 1]), np.array([1, 0]), np.zeros(2, np.int32),
+                      np.ones((1, 1)), p, 1)
+    np.testing.assert_array_equal(o1, o2)
+    np.testing.assert_array_equal(x1, x2)
+
+
 # ------------------------------------------------------------------ orientation bins (Sec. 5)
 
 def test_orientation_axes_diagonals_and_zero():
