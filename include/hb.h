@@ -258,6 +258,20 @@ hb_status hb_kmeans(hb_ctx *ctx, const float *X, int64_t n, int32_t dim, int32_t
 hb_status hb_davies_bouldin(hb_ctx *ctx, const float *X, int64_t n, int32_t dim, int32_t k,
                             const int32_t *labels, double *db, uint32_t flags);
 
+/* hb_davies_bouldin for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same index, with X and
+ * labels required in device memory of the context's device (no HB_DEVICE_PTRS flag: device
+ * pointers are the only form) and db in host memory. The call allocates nothing: its work
+ * memory is a fixed array of about 1.2 MB per GPU held by the library until the process ends
+ * (the partial sums of chunks of 16384 points, added chunk by chunk in a fixed order, so the
+ * result can differ from hb_davies_bouldin's in the last bits). k (dim + 1) + 2 <= 578, which
+ * every k <= HB_KMEANS_MAX_K, dim <= HB_KMEANS_MAX_DIM meets. All calls on one GPU share that
+ * array: calls that overlap on one GPU (from several contexts or threads) race. HB_ESTATE
+ * while an asynchronous run of the context is pending; labels outside [0, k) give HB_EINVAL.
+ * Synchronous on the context's stream. */
+hb_status hb_davies_bouldin_noalloc(hb_ctx *ctx, const float *X, int64_t n, int32_t dim,
+                                    int32_t k, const int32_t *labels, double *db);
+
 /* The choice of B (Section 5): for every B in [kmin, kmax] (1 <= kmin <= kmax <=
  * HB_KMEANS_MAX_K, n >= kmax), `restarts` k-means runs of at most max_iters rounds, run r
  * starting from the B distinct points whose indices are the values t = 0, 1, ... of the

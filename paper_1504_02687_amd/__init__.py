@@ -93,6 +93,9 @@ _SIGS = {
     "hb_davies_bouldin": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                            ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_double),
                                            ctypes.c_uint32]),
+    "hb_davies_bouldin_noalloc": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64,
+                                                   ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                                   ctypes.POINTER(ctypes.c_double)]),
     "hb_choose_groups": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_uint64,
                                           ctypes.c_int32, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
@@ -292,6 +295,18 @@ def hb_davies_bouldin(ctx, X, labels, k: int) -> float:
     pl, kl, dl = _arr(labels, np.int32)
     out = ctypes.c_double()
     _check(ctx, load().hb_davies_bouldin(ctx, px, n, dim, int(k), pl, ctypes.byref(out), _flags(dx, dl)))
+    return float(out.value)
+
+
+def hb_davies_bouldin_noalloc(ctx, X, labels, k: int) -> float:
+    """hb_davies_bouldin without device allocation; X [n, dim] float32 and labels [n] int32
+    must be torch tensors on the context's GPU."""
+    px, kx, dx, n, dim = _points(X)
+    pl, kl, dl = _arr(labels, np.int32)
+    if not (dx and dl):
+        raise ValueError("X and labels must be device tensors")
+    out = ctypes.c_double()
+    _check(ctx, load().hb_davies_bouldin_noalloc(ctx, px, n, dim, int(k), pl, ctypes.byref(out)))
     return float(out.value)
 
 

@@ -226,6 +226,17 @@ __global__ __launch_bounds__(kBlock) void k_km_db(const double *__restrict__ tot
     }
 }
 
+// Chunk sums added in chunk order (one thread per value).
+__global__ __launch_bounds__(kBlock) void k_km_accum(double *__restrict__ acc,
+                                                     const double *__restrict__ tot, int w,
+                                                     int first) {
+    for (int t = threadIdx.x; t < w; t += kBlock) acc[t] = first ? tot[t] : acc[t] + tot[t];
+}
+
+__global__ __launch_bounds__(kBlock) void k_zero_d(double *__restrict__ x, int n) {
+    for (int t = threadIdx.x; t < n; t += kBlock) x[t] = 0.0;
+}
+
 // ---------------------------------------------------------------- launchers
 
 hipError_t launch_edge_features(const GDesc *desc, int64_t E, int kind, float *out, hipStream_t st) {
@@ -264,6 +275,16 @@ hipError_t launch_km_means(const double *tot, int dim, int k, int keep, double *
 hipError_t launch_km_db(const double *tot, const double *centers, int dim, int k, double *db,
                         hipStream_t st) {
     hipLaunchKernelGGL(k_km_db, dim3(1), dim3(kBlock), 0, st, tot, centers, dim, k, db);
+    return hipGetLastError();
+}
+
+hipError_t launch_km_accum(double *acc, const double *tot, int w, int first, hipStream_t st) {
+    hipLaunchKernelGGL(k_km_accum, dim3(1), dim3(kBlock), 0, st, acc, tot, w, first);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_d(double *x, int n, hipStream_t st) {
+    hipLaunchKernelGGL(k_zero_d, dim3(1), dim3(kBlock), 0, st, x, n);
     return hipGetLastError();
 }
 

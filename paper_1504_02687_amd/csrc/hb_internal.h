@@ -213,6 +213,10 @@ hipError_t launch_km_means(const double *tot, int dim, int k, int keep, double *
                            hipStream_t st);
 hipError_t launch_km_db(const double *tot, const double *centers, int dim, int k, double *db,
                         hipStream_t st);
+// acc[0..w) = tot (first) or acc + tot: the sums of the point chunks, added in chunk order
+hipError_t launch_km_accum(double *acc, const double *tot, int w, int first, hipStream_t st);
+// x[0..n) = 0
+hipError_t launch_zero_d(double *x, int n, hipStream_t st);
 // ink = sum of n polyline lengths, fixed order; part[kInkSlices] receives it (device)
 hipError_t launch_ink(const double *lens, int64_t n, double *part, hipStream_t st);
 

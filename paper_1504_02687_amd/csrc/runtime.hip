@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -621,6 +622,53 @@ static hb_status stage_collect(hb_ctx *c) {
 
 // ------------------------------------------------------------------ lifecycle
 
+// ------------------------------------------------------------------ allocation-free scratch
+//
+// hb_davies_bouldin_noalloc works in this fixed device array instead of allocating: the
+// partial sums of one chunk of at most kNaChunk points (kNaRows rows of kNaW values: 64
+// blocks of 4 waves), the chunk totals, their running sum over the chunks, the centroids and
+// the index. Every GPU holds its own copy for the life of the process; its address on a
+// device comes from hipGetSymbolAddress, taken once per device by hb_create with that device
+// current, and only that address is handed to kernels and copies.
+static constexpr int kNaRows = 256;
+static constexpr int64_t kNaChunk = (int64_t)kNaRows * 64;
+static constexpr int kNaW = HB_KMEANS_MAX_K * (HB_KMEANS_MAX_DIM + 1) + 2;
+static constexpr size_t kNaDoubles =
+    (size_t)kNaRows * kNaW + 2 * (size_t)kNaW + (size_t)HB_KMEANS_MAX_K * HB_KMEANS_MAX_DIM + 1;
+static __device__ __align__(256) double scratch[kNaDoubles];
+
+static std::mutex g_scratch_mu;
+static std::vector<double *> g_scratch_ptr;      // per device; nullptr until set up
+static std::vector<std::string> g_scratch_err;   // per device: why the address is missing
+
+// Called with `device` current. Takes the array's address on that device once.
+static void scratch_setup(int device, int ndev) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch_ptr.size() < ndev) {
+        g_scratch_ptr.resize((size_t)ndev, nullptr);
+        g_scratch_err.resize((size_t)ndev);
+    }
+    if (g_scratch_ptr[(size_t)device]) return;
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        (void)hipGetLastError();
+        g_scratch_err[(size_t)device] = std::string("hipGetSymbolAddress: ") + hipGetErrorString(e);
+        return;
+    }
+    g_scratch_ptr[(size_t)device] = (double *)ptr;
+}
+
+static double *scratch_of(int device, std::string *why) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (device < 0 || device >= (int)g_scratch_ptr.size()) {
+        *why = "scratch not set up on this device";
+        return nullptr;
+    }
+    if (!g_scratch_ptr[(size_t)device]) *why = g_scratch_err[(size_t)device];
+    return g_scratch_ptr[(size_t)device];
+}
+
 HB_API hb_status hb_create(hb_ctx **out, int32_t device, void *hip_stream) {
     if (!out) return fail(nullptr, HB_EINVAL, "out is NULL");
     *out = nullptr;
@@ -635,6 +683,7 @@ HB_API hb_status hb_create(hb_ctx **out, int32_t device, void *hip_stream) {
         delete c;
         return fail(nullptr, HB_EDEVICE, "hipSetDevice failed");
     }
+    scratch_setup(device, ndev);
     {
         int nx = 1;
         if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, device) != hipSuccess || nx < 1)
@@ -1757,6 +1806,53 @@ HB_API hb_status hb_davies_bouldin(hb_ctx *c, const float *X, int64_t n, int32_t
         dlab = b.lab;
     }
     return km_db(c, b, dX, n, dim, k, dlab, db);
+}
+
+// hb_davies_bouldin on device inputs with the fixed scratch array: the points are taken in
+// chunks of kNaChunk, each chunk's sums reduced in a fixed order and added in chunk order.
+HB_API hb_status hb_davies_bouldin_noalloc(hb_ctx *c, const float *X, int64_t n, int32_t dim,
+                                           int32_t k, const int32_t *labels, double *db) {
+    ENTER(c);
+    if (c->pending) return fail(c, HB_ESTATE, "an asynchronous run is pending (hb_sync first)");
+    if (!labels || !db) return fail(c, HB_EINVAL, "labels or db is NULL");
+    if (n < 1) return fail(c, HB_EINVAL, "no points");
+    CHKST(km_check(c, X, n, dim, 1, HB_DEVICE_PTRS));
+    if (k < 1 || k > HB_KMEANS_MAX_K) return fail(c, HB_EINVAL, "k must be in [1, HB_KMEANS_MAX_K]");
+    const int w = k * (dim + 1) + 2;
+    if (w > kNaW) return fail(c, HB_EINVAL, "k (dim + 1) + 2 exceeds the scratch row (578 values)");
+    std::string why;
+    double *base = scratch_of(c->device, &why);
+    if (!base) return fail(c, HB_EDEVICE, "allocation-free scratch unavailable: " + why);
+    double *part = base;
+    double *tot = part + (size_t)kNaRows * kNaW;
+    double *acc = tot + kNaW;
+    double *cen = acc + kNaW;
+    double *dbd = cen + (size_t)HB_KMEANS_MAX_K * HB_KMEANS_MAX_DIM;
+    int32_t *lab = const_cast<int32_t *>(labels);   // modes 1 and 2 only read the labels
+    // mode 1: centroid sums of the given labels; mode 2: distance sums to the centroids
+    auto pass = [&](int mode) -> hipError_t {
+        for (int64_t c0 = 0; c0 < n; c0 += kNaChunk) {
+            const int64_t nc = std::min<int64_t>(kNaChunk, n - c0);
+            hipError_t e = hb::launch_km_round(X + c0 * dim, nc, dim, k, cen, lab + c0, mode, part,
+                                               tot, c->stream);
+            if (e == hipSuccess) e = hb::launch_km_accum(acc, tot, w, c0 == 0 ? 1 : 0, c->stream);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
+    hipError_t e = hb::launch_zero_d(cen, k * dim, c->stream);
+    if (e == hipSuccess) e = pass(1);
+    if (e == hipSuccess) e = hb::launch_km_means(acc, dim, k, 0, cen, c->stream);   // centroids
+    if (e == hipSuccess) e = pass(2);
+    if (e == hipSuccess) e = hb::launch_km_db(acc, cen, dim, k, dbd, c->stream);
+    double bad = 0.0, val = 0.0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&bad, acc + (w - 1), sizeof bad, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(&val, dbd, sizeof val, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return fail_dev(c, e, "Davies-Bouldin index (allocation-free)");
+    if (bad != 0.0) return fail(c, HB_EINVAL, "labels outside [0, k)");
+    *db = val;
+    return HB_OK;
 }
 
 // SplitMix64 (Steele, Lea and Flood 2014) as a counter-based stream: value t of stream
