@@ -339,7 +339,8 @@ const char *hb_version(void);
  * together. Every stage of an iteration is one kernel launch for the whole batch, over a
  * device table of per-graph descriptors; graphs may differ in edge count, group count, grid
  * size and schedule. Launches go to the stream of ctxs[0] (the streams of the other contexts
- * are drained first). flags: HB_RUN_ASYNC, HB_RUN_GRAPH. A context whose point buffers
+ * are drained first). flags: HB_RUN_ASYNC, HB_RUN_GRAPH, HB_RUN_RECORD_DECISIONS (each
+ * context keeps the decisions of its last iteration). A context whose point buffers
  * overflow is grown and finished on its own stream. Errors name the first failing context in
  * hb_last_error(ctxs[0]).
  */
@@ -392,6 +393,12 @@ hb_status hb_backward(hb_ctx *ctx, int64_t generation, const float *dL_dxy_T, in
 /* Polylines that entered checkpointed iteration t (0 = the start of the run). */
 hb_status hb_get_ckpt_points(hb_ctx *ctx, int32_t t, int64_t *offsets, float *xy,
                              int64_t cap_points, uint32_t flags);
+
+/* Sample offsets [E+1] and accepted halving index of every sample [N_t] of checkpointed
+ * iteration t (the discrete choices the adjoint holds fixed; same codes as
+ * hb_get_decisions). cap_points is the capacity of jacc in samples. */
+hb_status hb_get_ckpt_decisions(hb_ctx *ctx, int32_t t, int64_t *offsets, int8_t *jacc,
+                                int64_t cap_points, uint32_t flags);
 
 /* Stages of one iteration, for hb_get_stage_times. */
 enum {

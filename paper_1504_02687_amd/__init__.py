@@ -126,6 +126,8 @@ _SIGS = {
     "hb_backward": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64,
                                      ctypes.POINTER(ctypes.c_double), ctypes.c_void_p, ctypes.c_void_p,
                                      ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32]),
+    "hb_get_ckpt_decisions": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                               ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32]),
     "hb_get_ckpt_points": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
                                             ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32]),
     "hb_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
@@ -661,6 +663,14 @@ def hb_backward(ctx, n_groups: int, n_passes: int, n_points0: int, dL_dxy_T=None
     _check(ctx, load().hb_backward(ctx, generation, pg, n_t, ctypes.byref(loss), dM.ctypes.data,
                                    da.ctypes.data, px, n_points0, flags))
     return float(loss.value), dM, da, dx
+
+
+def hb_get_ckpt_decisions(ctx, t: int, n_edges: int, n_samples: int):
+    """(sample offsets [E+1], accepted halving per sample [N_t] int8) of checkpoint t."""
+    off = np.empty(n_edges + 1, np.int64)
+    jacc = np.empty(max(1, n_samples), np.int8)
+    _check(ctx, load().hb_get_ckpt_decisions(ctx, t, off.ctypes.data, jacc.ctypes.data, n_samples, 0))
+    return off, jacc[:n_samples]
 
 
 def hb_get_ckpt_points(ctx, t: int, n_edges: int, n_points: int):

@@ -1361,8 +1361,9 @@ HB_API hb_status hb_batch_run(hb_ctx *const *ctxs, int32_t n, int32_t n_iters, u
     hb_ctx *lead = ctxs[0];
     ENTER(lead);
     if (n_iters < 0) return fail(lead, HB_EINVAL, "n_iters must be >= 0");
-    if (flags & ~(uint32_t)(HB_RUN_ASYNC | HB_RUN_GRAPH))
-        return fail(lead, HB_EINVAL, "batch runs take HB_RUN_ASYNC and HB_RUN_GRAPH only");
+    if (flags & ~(uint32_t)(HB_RUN_ASYNC | HB_RUN_GRAPH | HB_RUN_RECORD_DECISIONS))
+        return fail(lead, HB_EINVAL,
+                    "batch runs take HB_RUN_ASYNC, HB_RUN_GRAPH and HB_RUN_RECORD_DECISIONS only");
     for (int g = 0; g < n; ++g) {
         hb_status st = finish_pending(ctxs[g]);
         if (st != HB_OK) return fail(lead, st, ctxs[g]->err);
@@ -2394,6 +2395,17 @@ HB_API hb_status hb_backward(hb_ctx *c, int64_t generation, const float *dL_dxy_
                                  c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
+    return HB_OK;
+}
+
+HB_API hb_status hb_get_ckpt_decisions(hb_ctx *c, int32_t t, int64_t *offsets, int8_t *jacc,
+                                       int64_t cap_points, uint32_t flags) {
+    ENTER(c);
+    if (t < 0 || t >= (int32_t)c->ckpts.size()) return fail(c, HB_EINVAL, "no such checkpoint");
+    const hb_ctx::Ckpt &k = c->ckpts[t];
+    if (!offsets || cap_points < k.ns || (k.ns > 0 && !jacc)) return fail(c, HB_EINVAL, "buffer too small");
+    CHKST(copy_out(c, offsets, k.xoff, sizeof(int64_t) * (size_t)(c->E + 1), flags));
+    CHKST(copy_out(c, jacc, k.jacc, sizeof(int8_t) * (size_t)k.ns, flags));
     return HB_OK;
 }
 

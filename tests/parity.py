@@ -117,3 +117,50 @@ def drift_stats(off, xy, n_ref=32):
 
 def relclose(a, b, rel):
     return abs(a - b) <= rel * max(abs(a), abs(b), 1e-12)
+
+
+def check_stage(ref, p, off, xy, group, M, maps, jacc, xy_n, agree_min=0.99):
+    """One iteration from the samples (off, xy) against the oracle's record ``ref`` of the
+    same iteration (O.iterate with skip_resample): histograms and box sums bit-exact, the
+    density within 1e-5 of sum_b |M[l][b]| Sbar_b, the gradient within 1e-6 of the layer's
+    density scale, halving decisions equal or valid within the ambiguity band, new positions
+    within 1e-4 px + 2 FP32 ulps + the conditioning of the interpolated direction (points
+    whose own and neighbours' decisions agree), the others within the same bound of the
+    oracle replaying the GPU's valid decisions, end points bit-exact."""
+    hist, S, rho, grad = maps
+    W, H = p.grid_w, p.grid_h
+    P = len(S)
+    np.testing.assert_array_equal(hist, ref["hist"])
+    np.testing.assert_array_equal(S, ref["S"])
+    aw = p.a()
+    r = ref["r"]
+    c = float((2 * r + 1) ** 2)
+    Sbar = sum(aw[k] * ref["S"][k].astype(np.float64) / c ** (k + 1) for k in range(P))
+    bound = 1e-5 * np.tensordot(np.abs(np.asarray(M, np.float64)), Sbar, 1) + 1e-300
+    assert (np.abs(rho - ref["rho"]) <= bound).all()
+    scale = np.abs(ref["rho"]).max(axis=(1, 2))[:, None, None, None]
+    assert (np.abs(grad - ref["grad"]) <= 1e-6 * scale + 1e-6 * np.abs(ref["grad"])).all()
+    adv = ref["adv"]
+    ok = acceptable(jacc, adv["jacc"], adv["jfirm"], adv["amb"])
+    assert ok.all(), f"{(~ok).sum()} invalid decisions"
+    agree = jacc == adv["jacc"]
+    assert agree.mean() > agree_min, agree.mean()
+    x64 = xy.astype(np.float64)
+    h = ref["h"]
+    cond = interp_condition(ref["grad"], group, off, x64)
+    tdir = np.where(np.isfinite(cond), h * 1e-6 * cond, 0.0)
+    tpt = 1e-4 + tdir + 2 * F32_ULP_AT(xy_n).max(1)
+    ty = tpt.copy()
+    ty[1:-1] = 0.5 * tpt[1:-1] + 0.25 * (tpt[:-2] + tpt[2:])
+    nb = agree.copy()
+    nb[1:] &= agree[:-1]
+    nb[:-1] &= agree[1:]
+    err = np.abs(xy_n.astype(np.float64) - ref["xy"]).max(1)
+    assert (err[nb] <= ty[nb]).all(), f"max err {err[nb].max()} px"
+    assert np.percentile(err[nb], 99) <= 1e-4, np.percentile(err[nb], 99)
+    jj = np.where(jacc == -2, -1, jacc)
+    yalt = laplace(off, candidate(x64, adv["dir"], h, jj, W, H))
+    erra = np.abs(xy_n.astype(np.float64) - yalt).max(1)
+    assert (erra[~nb] <= ty[~nb]).all()
+    ends = np.concatenate([off[:-1], off[1:] - 1])
+    np.testing.assert_array_equal(xy_n[ends], xy[ends])

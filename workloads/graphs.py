@@ -286,9 +286,11 @@ def stack3d(seed: int = 0, n_edges: int = 1_000_000, grid: int = 1024, groups: i
 
 def differentiation(seed: int = 2, n: int = 20_000, n_edges: int = 5_000_000,
                     grid: int = 2048, groups: int = 8, delta: float = 4.0,
-                    n_iters: int = 5) -> Workload:
-    """Matrix-pattern graph, 8 k-means groups, 2048x2048x8, sampling step 4 px, 5 iterations."""
-    xy, s, t = matrix_pattern_graph(n, n_edges, seed)
+                    n_iters: int = 5, band: int = 100, n_blocks: int = 64, block: int = 150,
+                    fill: float = 0.001) -> Workload:
+    """Matrix-pattern graph, 8 k-means groups, 2048x2048x8, sampling step 4 px, 5 iterations
+    (the pattern's band, blocks and fill can be scaled down with the matrix)."""
+    xy, s, t = matrix_pattern_graph(n, n_edges, seed, band, n_blocks, block, fill)
     g = kmeans_groups(_od_features(xy, s, t), groups, seed=1)
     r0 = grid / 32.0
     return Workload(f"differentiation-{n_edges // 1000}k-{grid}x{groups}", xy, s, t, g,
