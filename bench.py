@@ -632,7 +632,7 @@ def batched_main(args):
         "higher_is_better": True, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"batch-{len(ws)}-graphs", "edges_total": int(sum(w.n_edges for w in ws)),
                    "edges_max": int(max(w.n_edges for w in ws)), "groups": [w.n_groups for w in ws],
-                   "grids": [w.grid_w for w in ws], "autotuned_chunks": list(choice)},
+                   "grids": [w.grid_w for w in ws], "autotuned": dict(zip(("resample_chunks", "advect_chunks", "box_col_rows", "bin_sets", "hist_item_entries_log2"), choice))},
         "one_at_a_time": {"value": pts_seq / t_seq, "per_graph_iter_ms_p50": float(np.percentile(per_graph_ms, 50)),
                           "per_graph_iter_ms_p99": float(np.percentile(per_graph_ms, 99))},
         "batched_iter_ms": t_bat * 1e3 / T,

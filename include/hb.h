@@ -346,15 +346,28 @@ const char *hb_version(void);
  */
 hb_status hb_batch_run(hb_ctx *const *ctxs, int32_t n, int32_t n_iters, uint32_t flags);
 
-/* Choose the kernel variants (work chunks per trip of the resampling and advection kernels)
- * for a batch by timing n_iters iterations of each candidate from the current polylines and
- * restoring them afterwards. The choice is stored in every context and written to
- * choice[2] (resample, advect) when choice is not NULL. */
+/* Choose the launch shapes of a batch by timing n_iters iterations of each candidate from the
+ * current polylines and restoring them afterwards, one shape at a time (each stage keeps the
+ * best of the stages before it): the work chunks per trip of the resampling and advection
+ * kernels (1, 2 or 4 each), the rows per thread of the column box pass (64, 128, 256), the
+ * tile-count sets of the splat, i.e. how many privatised copies of the per-tile counters
+ * the edge blocks spread their atomics over (4, 16, 64; fewer when the counters of all sets
+ * would pass 2^18), and the entries per tile-histogram work item (2^14 .. 2^17). Every
+ * choice gives the same results bit for bit. The choice is stored in every context and,
+ * when choice is not NULL, written to choice[5] = {resample chunks, advect chunks, column
+ * rows, sets, log2 item entries}. */
 hb_status hb_autotune(hb_ctx *const *ctxs, int32_t n, int32_t n_iters, int32_t *choice);
 
 /* Set / read the kernel variants directly (chunks 1, 2 or 4). */
 hb_status hb_set_tuning(hb_ctx *ctx, int32_t resample_chunks, int32_t advect_chunks);
 hb_status hb_get_tuning(hb_ctx *ctx, int32_t *resample_chunks, int32_t *advect_chunks);
+
+/* Set / read the map-stage launch shapes directly: rows per thread of the column box pass (a
+ * power of two in [16, 1024]), the most tile-count sets of the splat (a power of two in
+ * [1, 64]) and log2 of the entries per tile-histogram work item (in [12, 20]). Results do
+ * not depend on them. Setting them discards the checkpoints of hb_forward_ckpt. */
+hb_status hb_set_tiling(hb_ctx *ctx, int32_t col_rows, int32_t sets_max, int32_t item_entries_log2);
+hb_status hb_get_tiling(hb_ctx *ctx, int32_t *col_rows, int32_t *sets_max, int32_t *item_entries_log2);
 
 /*
  * Differentiable form. With the discrete choices of a forward run held fixed (sample counts

@@ -132,6 +132,9 @@ _SIGS = {
                                             ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint32]),
     "hb_autotune": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]),
     "hb_set_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]),
+    "hb_set_tiling": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
+    "hb_get_tiling": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "hb_get_tuning": (ctypes.c_int32, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.POINTER(ctypes.c_int32)]),
     "hb_get_stage_times": (ctypes.c_int32, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
@@ -458,10 +461,11 @@ def hb_batch_run(ctxs, n_iters: int, flags: int = 0) -> None:
 
 
 def hb_autotune(ctxs, n_iters: int = 1):
+    """(resample chunks, advect chunks, column rows, tile-count sets, log2 item entries)."""
     arr = _ctx_array(ctxs)
-    choice = (ctypes.c_int32 * 2)()
+    choice = (ctypes.c_int32 * 5)()
     _check(ctxs[0], load().hb_autotune(arr, len(ctxs), n_iters, choice))
-    return int(choice[0]), int(choice[1])
+    return tuple(int(v) for v in choice)
 
 
 def hb_set_tuning(ctx, resample_chunks: int, advect_chunks: int) -> None:
@@ -472,6 +476,16 @@ def hb_get_tuning(ctx):
     a, b = ctypes.c_int32(), ctypes.c_int32()
     _check(ctx, load().hb_get_tuning(ctx, ctypes.byref(a), ctypes.byref(b)))
     return int(a.value), int(b.value)
+
+
+def hb_set_tiling(ctx, col_rows: int, sets_max: int, item_entries_log2: int) -> None:
+    _check(ctx, load().hb_set_tiling(ctx, col_rows, sets_max, item_entries_log2))
+
+
+def hb_get_tiling(ctx):
+    a, b, c = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    _check(ctx, load().hb_get_tiling(ctx, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+    return int(a.value), int(b.value), int(c.value)
 
 
 # ------------------------------------------------------------------ convenience

@@ -250,9 +250,9 @@ __global__ __launch_bounds__(kParBlock) void k_adj_params(const GDesc *__restric
             if (d.aseg_off[mid] <= it) lo = mid; else hi = mid - 1;
         }
         const int t = lo;
-        const int64_t beg = d.atile_off[t] + (it - d.aseg_off[t]) * kSegEntries;
+        const int64_t beg = d.atile_off[t] + (it - d.aseg_off[t]) * d.item_entries;
         const int64_t lim = d.atile_off[t + 1];
-        const int64_t end = beg + kSegEntries < lim ? beg + kSegEntries : lim;
+        const int64_t end = beg + d.item_entries < lim ? beg + d.item_entries : lim;
         const int layer = t / per_layer, rem = t - layer * per_layer;
         const int ty = rem / d.tiles_x, tx = rem - ty * d.tiles_x;
         const int X0 = tx * kTile - 1, Y0 = ty * kTile - 1;   // grid cell (0, 0)

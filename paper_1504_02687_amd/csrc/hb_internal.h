@@ -21,16 +21,16 @@ enum : int32_t {
 constexpr int kBlock = 256;            // threads per block of every kernel
 constexpr int kWavesPerBlock = kBlock / 64;
 constexpr int kScanTile = 1024;        // edges per scan tile (4 per thread)
-constexpr int kColSeg = 128;           // rows per thread in the column box pass
+constexpr int kColSeg = 128;           // rows per thread in the column box pass (default)
 
 // Spatial binning of the samples: the histogram is built tile by tile in LDS.
 constexpr int kTileShift = 6;                       // tiles of 64 x 64 pixels
 constexpr int kTile = 1 << kTileShift;
 constexpr int kTilePx = kTile * kTile;              // LDS counters of one tile
 constexpr int kLocalBits = 2 * kTileShift;          // pixel inside the tile, low bits of an entry
-constexpr int kBinSetsMax = 64;                     // tile-count sets (edge block mod sets)
+constexpr int kBinSetsMax = 64;                     // tile-count sets (edge block mod sets), default
 constexpr int64_t kBinCounters = 1 << 18;          // counters of all sets, at most (unless 1 set)
-constexpr int64_t kSegEntries = 1 << 16;            // entries per tile-histogram work item
+constexpr int64_t kSegEntries = 1 << 16;            // entries per tile-histogram work item, default
 constexpr int kTileBlocksMax = 2048;                // blocks of one graph in k_tile_hist
 constexpr int kRedSlices = 32;                      // slices per parameter in k_adj_reduce
 constexpr int kInkSlices = 256;                     // slices of the ink sum
@@ -113,6 +113,8 @@ struct GDesc {
     // spatial binning: tile t = (layer * tiles_y + ty) * tiles_x + tx
     int32_t tiles_x, tiles_y, n_tiles, tile_blocks;
     int32_t n_sets;             // counter sets (power of two): edge block b counts in set b % n_sets
+    int32_t col_rows;           // rows per thread of the column box pass
+    int64_t item_entries;       // entries per tile-histogram work item
     int64_t *bin_cnt;           // [n_sets][n_tiles] samples per tile, per set of edge blocks
     int64_t *bin_cur;           // [n_sets][n_tiles] write cursors of the binning pass
     int64_t *tile_off;          // [n_tiles + 1] first entry of each tile
@@ -158,13 +160,21 @@ struct GDesc {
 struct Shape {
     int64_t edge, scan, row, col, px, pxb, edget, tile, cell;
 };
-Shape shape_of(int64_t n_edges, int32_t B, int32_t W, int32_t H);
+// Launch shapes that the autotuner may change, per context: rows per thread of the column
+// box pass, the most tile-count sets (privatised copies of the tile counters) and the
+// entries per tile-histogram work item.
+struct Tiling {
+    int32_t col_rows = kColSeg;
+    int32_t sets_max = kBinSetsMax;
+    int64_t item_entries = kSegEntries;
+};
+Shape shape_of(int64_t n_edges, int32_t B, int32_t W, int32_t H, const Tiling &tg);
 
 // Tiling of the B histogram layers of a W x H grid.
 struct Tiles {
     int32_t x, y, n, blocks, sets;
 };
-Tiles tiles_of(int32_t B, int32_t W, int32_t H);
+Tiles tiles_of(int32_t B, int32_t W, int32_t H, int32_t sets_max);
 
 // Launchers (all asynchronous on `st`). desc points to device memory holding ng
 // descriptors; tot is the sum of the per-graph shapes.

@@ -554,7 +554,7 @@ __global__ __launch_bounds__(kBlock) void k_strip_bins(const GDesc *__restrict__
 
 // Tile offsets of one graph (one block per graph): the entries of tile t start at
 // tile_off[t], those of set s of tile t right after the sets before it (the cursors), and
-// tile t is cut into work items of kSegEntries entries numbered from seg_off[t].
+// tile t is cut into work items of item_entries entries numbered from seg_off[t].
 __global__ __launch_bounds__(kBlock) void k_bin_scan(const GDesc *__restrict__ gd, int ng) {
     if ((int)blockIdx.x >= ng) return;
     const GDesc &d = gd[blockIdx.x];
@@ -566,7 +566,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_scan(const GDesc *__restrict__ g
         int64_t tot = 0;
         if (t < nt)
             for (int q = 0; q < d.n_sets; ++q) tot += d.bin_cnt[(int64_t)q * nt + t];
-        const int64_t segs = (tot + kSegEntries - 1) / kSegEntries;
+        const int64_t segs = (tot + d.item_entries - 1) / d.item_entries;
         int64_t sum_tot, sum_seg;
         const int64_t xo = block_excl_scan(tot, &sum_tot);
         const int64_t xg = block_excl_scan(segs, &sum_seg);
@@ -610,7 +610,7 @@ __device__ __forceinline__ uint32_t lds_slot(uint32_t local) {
     return local ^ ((local >> kTileShift) & 31u);
 }
 
-// Histogram tiles in LDS. Each block takes work items (up to kSegEntries entries of one
+// Histogram tiles in LDS. Each block takes work items (up to item_entries entries of one
 // tile) round-robin, adds the entries' weights to its LDS copy of the tile with LDS
 // atomics, then adds the non-zero counters to the histogram (first copy of histx).
 __global__ __launch_bounds__(kBlock) void k_tile_hist(const GDesc *__restrict__ gd, int ng) {
@@ -631,9 +631,9 @@ __global__ __launch_bounds__(kBlock) void k_tile_hist(const GDesc *__restrict__ 
             if (d.seg_off[mid] <= sg) lo = mid; else hi = mid - 1;
         }
         const int t = lo;
-        const int64_t beg = d.tile_off[t] + (sg - d.seg_off[t]) * kSegEntries;
+        const int64_t beg = d.tile_off[t] + (sg - d.seg_off[t]) * d.item_entries;
         const int64_t lim = d.tile_off[t + 1];
-        const int64_t end = beg + kSegEntries < lim ? beg + kSegEntries : lim;
+        const int64_t end = beg + d.item_entries < lim ? beg + d.item_entries : lim;
         for (int i = threadIdx.x; i < kTilePx; i += kBlock) lh[i] = 0;
         __syncthreads();
         int64_t i = beg + threadIdx.x;
@@ -743,7 +743,7 @@ __global__ __launch_bounds__(kBlock) void k_box_rows(const GDesc *__restrict__ g
     }
 }
 
-// Column pass: sliding window sum down a column segment of kColSeg rows. One thread per
+// Column pass: sliding window sum down a column segment of col_rows rows. One thread per
 // (group, segment, column); neighbouring threads read neighbouring columns.
 __global__ __launch_bounds__(kBlock) void k_box_cols(const GDesc *__restrict__ gd, int ng,
                                                      int pass) {
@@ -751,7 +751,8 @@ __global__ __launch_bounds__(kBlock) void k_box_cols(const GDesc *__restrict__ g
     HB_FIND(blk_col);
     if (stopped(d) || pass >= d.P) return;
     const int W = d.W, H = d.H, r = d.rp[pass];
-    const int nseg = (H + kColSeg - 1) / kColSeg;
+    const int rows = d.col_rows;
+    const int nseg = (H + rows - 1) / rows;
     const int64_t t = (blk - d.blk_col) * kBlock + threadIdx.x;
     if (t >= (int64_t)d.B * nseg * W) return;
     const int u = (int)(t % W);
@@ -761,8 +762,8 @@ __global__ __launch_bounds__(kBlock) void k_box_cols(const GDesc *__restrict__ g
     const int64_t plane = (int64_t)W * H;
     const int64_t *in = d.tmp + b * plane + u;
     int64_t *out = d.box + (int64_t)pass * d.B * plane + b * plane + u;
-    const int v0 = seg * kColSeg;
-    const int v1 = v0 + kColSeg < H ? v0 + kColSeg : H;
+    const int v0 = seg * rows;
+    const int v1 = v0 + rows < H ? v0 + rows : H;
     const int lo = v0 - r > 0 ? v0 - r : 0;
     const int hi = v0 + r < H - 1 ? v0 + r : H - 1;
     int64_t acc = 0;
@@ -1154,10 +1155,10 @@ __global__ __launch_bounds__(kBlock) void k_fill_totals(const GDesc *__restrict_
 
 // ---------------------------------------------------------------- launchers
 
-Shape shape_of(int64_t n_edges, int32_t B, int32_t W, int32_t H) {
+Shape shape_of(int64_t n_edges, int32_t B, int32_t W, int32_t H, const Tiling &tg) {
     Shape s;
     const int64_t plane = (int64_t)W * H;
-    const int64_t nseg = (H + kColSeg - 1) / kColSeg;
+    const int64_t nseg = (H + tg.col_rows - 1) / tg.col_rows;
     s.edge = (n_edges + kWavesPerBlock - 1) / kWavesPerBlock;
     s.scan = (n_edges + kScanTile - 1) / kScanTile;
     s.row = (int64_t)B * H;
@@ -1165,19 +1166,19 @@ Shape shape_of(int64_t n_edges, int32_t B, int32_t W, int32_t H) {
     s.px = (plane + kBlock - 1) / kBlock;
     s.pxb = ((int64_t)B * plane + kBlock - 1) / kBlock;
     s.edget = (n_edges + 1 + kBlock - 1) / kBlock;
-    s.tile = tiles_of(B, W, H).blocks;
+    s.tile = tiles_of(B, W, H, tg.sets_max).blocks;
     s.cell = ((int64_t)B * cell_plane(W, H) + kBlock - 1) / kBlock;
     return s;
 }
 
-Tiles tiles_of(int32_t B, int32_t W, int32_t H) {
+Tiles tiles_of(int32_t B, int32_t W, int32_t H, int32_t sets_max) {
     Tiles t;
     t.x = (W + kTile - 1) / kTile;
     t.y = (H + kTile - 1) / kTile;
     t.n = B * t.x * t.y;
     t.blocks = t.n < kTileBlocksMax ? t.n : kTileBlocksMax;
     t.sets = 1;
-    while (t.sets < kBinSetsMax && (int64_t)t.sets * 2 * t.n <= kBinCounters) t.sets *= 2;
+    while (t.sets < sets_max && (int64_t)t.sets * 2 * t.n <= kBinCounters) t.sets *= 2;
     return t;
 }
 

@@ -134,6 +134,8 @@ struct hb_ctx {
 
     // kernel variants (chunks of 64 per trip in resampling / advection)
     int tune_ru = 2, tune_au = 2;
+    hb::Tiling tiling;             // box column rows, tile-count sets, tile work-item size
+    int map_sets = 0;              // tile-count sets the map buffers were sized for
 
     // captured iteration sequence, replayed while the batch layout is unchanged
     hipGraphExec_t gexec = nullptr;
@@ -456,12 +458,14 @@ static hb_status ensure_capacity(hb_ctx *c, int64_t need) {
 
 static hb_status ensure_maps(hb_ctx *c) {
     const int B = c->B, W = c->P.grid_w, H = c->P.grid_h, P = c->P.box_passes;
-    if (c->d_hist && c->map_B == B && c->map_W == W && c->map_H == H && c->map_P == P) return HB_OK;
+    const hb::Tiles tl = hb::tiles_of(B, W, H, c->tiling.sets_max);
+    if (c->d_hist && c->map_B == B && c->map_W == W && c->map_H == H && c->map_P == P &&
+        c->map_sets == tl.sets)
+        return HB_OK;
     const size_t plane = (size_t)B * W * H;
     c->have_maps = false;
     CHKST(dalloc(c, &c->d_hist, plane, "histogram"));
     CHKST(dalloc(c, &c->d_histx, plane, "histogram accumulator"));
-    const hb::Tiles tl = hb::tiles_of(B, W, H);
     CHKST(dalloc(c, &c->d_bin_cnt, (size_t)tl.sets * tl.n, "tile counts"));
     CHKST(dalloc(c, &c->d_bin_cur, (size_t)tl.sets * tl.n, "tile cursors"));
     CHKST(dalloc(c, &c->d_tile_off, (size_t)tl.n + 1, "tile offsets"));
@@ -477,6 +481,7 @@ static hb_status ensure_maps(hb_ctx *c) {
     c->map_W = W;
     c->map_H = H;
     c->map_P = P;
+    c->map_sets = tl.sets;
     return HB_OK;
 }
 
@@ -484,8 +489,7 @@ static hb_status ensure_maps(hb_ctx *c) {
 static GDesc base_desc(const hb_ctx *c) {
     GDesc d;
     memset(&d, 0, sizeof d);
-    const Shape s = hb::shape_of(c->E, std::max(1, c->B), c->P.grid_w, c->P.grid_h);
-    (void)s;
+
     d.n_edges = c->E;
     d.cap = c->cap;
     d.B = std::max(1, c->B);
@@ -519,12 +523,14 @@ static GDesc base_desc(const hb_ctx *c) {
     d.histx = c->d_histx;
     d.nx = 1;
     d.nxcd = c->nx;
-    const hb::Tiles tl = hb::tiles_of(d.B, d.W, d.H);
+    const hb::Tiles tl = hb::tiles_of(d.B, d.W, d.H, c->tiling.sets_max);
     d.tiles_x = tl.x;
     d.tiles_y = tl.y;
     d.n_tiles = tl.n;
     d.tile_blocks = tl.blocks;
     d.n_sets = tl.sets;
+    d.col_rows = c->tiling.col_rows;
+    d.item_entries = c->tiling.item_entries;
     d.bin_cnt = c->d_bin_cnt;
     d.bin_cur = c->d_bin_cur;
     d.tile_off = c->d_tile_off;
@@ -869,7 +875,7 @@ static hb_status setup_scan_total(hb_ctx *c, int64_t *total_out) {
     d.r = 0;
     c->h_desc[0] = d;
     CHKST(upload_desc(c, 1));
-    const Shape s = hb::shape_of(c->E, d.B, d.W, d.H);
+    const Shape s = hb::shape_of(c->E, d.B, d.W, d.H, c->tiling);
     HIPCHK(c, hb::launch_scan(c->d_desc, 1, s, c->stream));
     CHKST(read_scalar(c, c->d_totals, total_out));
     CHKST(read_status(c));   // an edge with 2^31 samples or more
@@ -974,7 +980,7 @@ HB_API hb_status hb_set_graph(hb_ctx *c, int32_t n_nodes, const float *node_xy, 
         c->h_desc[0] = d;
         st = upload_desc(c, 1);
         if (st == HB_OK) {
-            const Shape s = hb::shape_of(E, d.B, d.W, d.H);
+            const Shape s = hb::shape_of(E, d.B, d.W, d.H, c->tiling);
             hipError_t e = hb::launch_init_state(c->d_desc, 1, s, d_nodes, d_src, d_dst,
                                                  c->P.bbox[0], c->P.bbox[1], c->P.bbox[2],
                                                  c->P.bbox[3], c->stream);
@@ -1117,7 +1123,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
     for (int g = 0; g < n; ++g) {
         const hb_ctx *c = cs[g];
         base[g] = tot;
-        shape_add(tot, hb::shape_of(c->E, c->B, c->P.grid_w, c->P.grid_h));
+        shape_add(tot, hb::shape_of(c->E, c->B, c->P.grid_w, c->P.grid_h, c->tiling));
         max_w = std::max(max_w, c->P.grid_w);
         bmax = std::max(bmax, c->B);
         pmax = std::max(pmax, c->P.box_passes);
@@ -1429,53 +1435,152 @@ static hb_status restore_snapshot(hb_ctx *c, Snapshot &s) {
     return HB_OK;
 }
 
+// Tiling values the autotuner and hb_set_tiling accept.
+static constexpr int kSetsLimit = hb::kBinSetsMax;
+static bool tiling_ok(int32_t col_rows, int32_t sets_max, int64_t item_entries) {
+    auto pow2 = [](int64_t v) { return v > 0 && (v & (v - 1)) == 0; };
+    return pow2(col_rows) && col_rows >= 16 && col_rows <= 1024 && pow2(sets_max) &&
+           sets_max <= kSetsLimit && pow2(item_entries) && item_entries >= (1 << 12) &&
+           item_entries <= (1 << 20);
+}
+
+// One setting of every tunable launch shape of a batch.
+struct TuneSet {
+    int ru, au;
+    hb::Tiling tg;
+};
+
+static void apply_tune(hb_ctx *const *ctxs, int n, const TuneSet &t) {
+    for (int g = 0; g < n; ++g) {
+        ctxs[g]->tune_ru = t.ru;
+        ctxs[g]->tune_au = t.au;
+        ctxs[g]->tiling = t.tg;
+    }
+}
+
+// Chooses the launch shapes of a batch by timing n_iters iterations of each candidate from
+// the current polylines (restored afterwards), one shape at a time: the work chunks per
+// trip of the resampling and advection kernels, then the rows per thread of the column box
+// pass, the tile-count sets of the splat (how many privatised copies of the tile counters
+// the edge blocks spread their atomics over) and the entries per tile-histogram work item.
 HB_API hb_status hb_autotune(hb_ctx *const *ctxs, int32_t n, int32_t n_iters, int32_t *choice) {
     CHKST(check_batch(ctxs, n));
     hb_ctx *lead = ctxs[0];
     ENTER(lead);
     if (n_iters < 1) return fail(lead, HB_EINVAL, "n_iters must be >= 1");
     for (int g = 0; g < n; ++g) CHKST(finish_pending(ctxs[g]));
-    static const int cand[][2] = {{1, 1}, {1, 2}, {2, 2}, {1, 4}, {2, 4}, {4, 4}};
-    const int ncand = (int)(sizeof cand / sizeof cand[0]);
     hipEvent_t e0, e1;
     HIPCHK(lead, hipEventCreate(&e0));
     HIPCHK(lead, hipEventCreate(&e1));
-    float best = 0.0f;
-    int bi = -1;
     const bool prof = lead->profiling;
     lead->profiling = false;
     hb_status st = HB_OK;
-    for (int i = 0; i < ncand && st == HB_OK; ++i) {
+    auto trial = [&](const TuneSet &t, float *ms) -> hb_status {
         std::vector<Snapshot> snap((size_t)n);
-        for (int g = 0; g < n && st == HB_OK; ++g) st = take_snapshot(ctxs[g], snap[g]);
-        if (st != HB_OK) break;
-        lead->tune_ru = cand[i][0];
-        lead->tune_au = cand[i][1];
-        if (hipEventRecord(e0, lead->stream) != hipSuccess) st = fail_dev(lead, hipGetLastError(), "event");
-        if (st == HB_OK) st = enqueue_batch(lead, ctxs, n, n_iters, 0, false);
-        if (st == HB_OK && hipEventRecord(e1, lead->stream) != hipSuccess) st = fail_dev(lead, hipGetLastError(), "event");
-        for (int g = 0; g < n && st == HB_OK; ++g) st = finish_pending(ctxs[g]);
-        float ms = 0.0f;
-        if (st == HB_OK && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) st = fail_dev(lead, hipGetLastError(), "event");
-        for (int g = 0; g < n && st == HB_OK; ++g) st = restore_snapshot(ctxs[g], snap[g]);
-        if (st == HB_OK && (bi < 0 || ms < best)) {
-            best = ms;
-            bi = i;
+        for (int g = 0; g < n; ++g) CHKST(take_snapshot(ctxs[g], snap[g]));
+        apply_tune(ctxs, n, t);
+        for (int g = 0; g < n; ++g) CHKST(ensure_maps(ctxs[g]));
+        if (hipEventRecord(e0, lead->stream) != hipSuccess) return fail_dev(lead, hipGetLastError(), "event");
+        CHKST(enqueue_batch(lead, ctxs, n, n_iters, 0, false));
+        if (hipEventRecord(e1, lead->stream) != hipSuccess) return fail_dev(lead, hipGetLastError(), "event");
+        for (int g = 0; g < n; ++g) CHKST(finish_pending(ctxs[g]));
+        if (hipEventElapsedTime(ms, e0, e1) != hipSuccess) return fail_dev(lead, hipGetLastError(), "event");
+        for (int g = 0; g < n; ++g) CHKST(restore_snapshot(ctxs[g], snap[g]));
+        return HB_OK;
+    };
+    TuneSet best{lead->tune_ru, lead->tune_au, lead->tiling};
+    float best_ms = -1.0f;
+    // stage 1: work chunks per trip
+    static const int cand[][2] = {{1, 1}, {1, 2}, {2, 2}, {1, 4}, {2, 4}, {4, 4}};
+    std::vector<TuneSet> sets;
+    for (const auto &c : cand) sets.push_back(TuneSet{c[0], c[1], best.tg});
+    auto pick = [&](std::vector<TuneSet> cs) -> hb_status {
+        for (const TuneSet &t : cs) {
+            float ms = 0.0f;
+            CHKST(trial(t, &ms));
+            if (best_ms < 0.0f || ms < best_ms) {
+                best_ms = ms;
+                best = t;
+            }
         }
+        return HB_OK;
+    };
+    st = pick(sets);
+    // stage 2: rows per thread of the column box pass
+    if (st == HB_OK) {
+        sets.clear();
+        for (int rows : {64, 256}) {
+            TuneSet t = best;
+            t.tg.col_rows = rows;
+            sets.push_back(t);
+        }
+        st = pick(sets);
+    }
+    // stage 3: tile-count sets (privatised copies of the tile counters)
+    if (st == HB_OK) {
+        sets.clear();
+        for (int k : {4, 16}) {
+            TuneSet t = best;
+            t.tg.sets_max = k;
+            sets.push_back(t);
+        }
+        st = pick(sets);
+    }
+    // stage 4: entries per tile-histogram work item
+    if (st == HB_OK) {
+        sets.clear();
+        for (int64_t v : {int64_t(1) << 14, int64_t(1) << 15, int64_t(1) << 17}) {
+            TuneSet t = best;
+            t.tg.item_entries = v;
+            sets.push_back(t);
+        }
+        st = pick(sets);
     }
     lead->profiling = prof;
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st != HB_OK) return st;
+    apply_tune(ctxs, n, best);
     for (int g = 0; g < n; ++g) {
-        ctxs[g]->tune_ru = cand[bi][0];
-        ctxs[g]->tune_au = cand[bi][1];
+        CHKST(ensure_maps(ctxs[g]));
         ctxs[g]->last_counts.clear();
+        ctxs[g]->ckpt_end_iter = -1;
     }
     if (choice) {
-        choice[0] = cand[bi][0];
-        choice[1] = cand[bi][1];
+        choice[0] = best.ru;
+        choice[1] = best.au;
+        choice[2] = best.tg.col_rows;
+        choice[3] = best.tg.sets_max;
+        int lg = 0;
+        while ((int64_t(1) << lg) < best.tg.item_entries) ++lg;
+        choice[4] = lg;
     }
+    return HB_OK;
+}
+
+HB_API hb_status hb_set_tiling(hb_ctx *c, int32_t col_rows, int32_t sets_max, int32_t item_entries_log2) {
+    ENTER(c);
+    CHKST(finish_pending(c));
+    if (item_entries_log2 < 0 || item_entries_log2 > 30 ||
+        !tiling_ok(col_rows, sets_max, int64_t(1) << item_entries_log2))
+        return fail(c, HB_EINVAL, "tiling: col_rows a power of two in [16, 1024], sets_max a power of "
+                                  "two in [1, 64], item_entries_log2 in [12, 20]");
+    c->tiling.col_rows = col_rows;
+    c->tiling.sets_max = sets_max;
+    c->tiling.item_entries = int64_t(1) << item_entries_log2;
+    c->ckpt_end_iter = -1;
+    if (c->have_graph && c->have_groups) CHKST(ensure_maps(c));
+    return HB_OK;
+}
+
+HB_API hb_status hb_get_tiling(hb_ctx *c, int32_t *col_rows, int32_t *sets_max, int32_t *item_entries_log2) {
+    ENTER(c);
+    if (!col_rows || !sets_max || !item_entries_log2) return fail(c, HB_EINVAL, "null output");
+    *col_rows = c->tiling.col_rows;
+    *sets_max = c->tiling.sets_max;
+    int lg = 0;
+    while ((int64_t(1) << lg) < c->tiling.item_entries) ++lg;
+    *item_entries_log2 = lg;
     return HB_OK;
 }
 
@@ -1574,7 +1679,7 @@ HB_API hb_status hb_set_points(hb_ctx *c, const int64_t *offsets, const float *x
     d.off_in = c->off[0];
     c->h_desc[0] = d;
     CHKST(upload_desc(c, 1));
-    const Shape s = hb::shape_of(c->E, d.B, d.W, d.H);
+    const Shape s = hb::shape_of(c->E, d.B, d.W, d.H, c->tiling);
     HIPCHK(c, hb::launch_lengths(c->d_desc, 1, s, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return HB_OK;
@@ -1941,7 +2046,7 @@ HB_API hb_status hb_orientation_groups(hb_ctx *c, int32_t *group, uint32_t flags
         CHKST(dalloc(c, &tmp, (size_t)c->E, "orientation bins"));
         out = tmp;
     }
-    const Shape s = hb::shape_of(c->E, d.B, d.W, d.H);
+    const Shape s = hb::shape_of(c->E, d.B, d.W, d.H, c->tiling);
     hipError_t e = hb::launch_orientation(c->d_desc, s, out, c->stream);
     if (e == hipSuccess && tmp)
         e = hipMemcpyAsync(group, tmp, sizeof(int32_t) * (size_t)c->E, hipMemcpyDeviceToHost, c->stream);
@@ -1982,7 +2087,7 @@ HB_API hb_status hb_point_widths(hb_ctx *c, int32_t iter, float w_min, float w_m
     c->h_desc[0] = d;
     CHKST(upload_desc(c, 1));
     const GDesc *dd = c->d_desc;
-    const Shape s = hb::shape_of(c->E, d.B, d.W, d.H);
+    const Shape s = hb::shape_of(c->E, d.B, d.W, d.H, c->tiling);
     const bool strip = d.strip != 0;
     float *pd = c->d_render, *pw = c->d_render + N;
     uint32_t *pmax = reinterpret_cast<uint32_t *>(c->d_render + 2 * N);
@@ -2138,8 +2243,8 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags, int
     const int64_t E = c->E;
     const int64_t plane = (int64_t)c->B * c->P.grid_w * c->P.grid_h;
     const size_t E1 = (size_t)E + 1;
-    const int64_t nt1 = (int64_t)hb::tiles_of(std::max(1, c->B), c->P.grid_w, c->P.grid_h).n + 1;
-    const Shape sh = hb::shape_of(E, std::max(1, c->B), c->P.grid_w, c->P.grid_h);
+    const int64_t nt1 = (int64_t)hb::tiles_of(std::max(1, c->B), c->P.grid_w, c->P.grid_h, c->tiling.sets_max).n + 1;
+    const Shape sh = hb::shape_of(E, std::max(1, c->B), c->P.grid_w, c->P.grid_h, c->tiling);
     auto take = [&]() {
         hb_ctx::Ckpt k;
         if (!c->ckpt_pool.empty()) {
@@ -2281,10 +2386,10 @@ HB_API hb_status hb_backward(hb_ctx *c, int64_t generation, const float *dL_dxy_
     const int bp = (B + 1) / 2 * 2, pp = (P + 1) / 2 * 2;
     for (int i = 0; i < 2 && i < T; ++i)
         CHKST(grow(c, &A.gb[i], A.cap_gb[i], plane * (bp + (int64_t)B * pp), "gradient maps"));
-    // work items of the tile bins: at most one per kSegEntries samples plus one per tile
-    const int64_t nt = hb::tiles_of(B, W, H).n;
+    // work items of the tile bins: at most one per item_entries samples plus one per tile
+    const int64_t nt = hb::tiles_of(B, W, H, c->tiling.sets_max).n;
     int64_t max_items = 1;
-    for (auto &k : c->ckpts) max_items = std::max(max_items, k.ns / hb::kSegEntries + nt + 1);
+    for (auto &k : c->ckpts) max_items = std::max(max_items, k.ns / c->tiling.item_entries + nt + 1);
     CHKST(grow(c, &A.partials, A.cap_part, max_items * (B + P), "partials"));
     for (int i = 0; i < 2 && i < T; ++i)
         CHKST(grow(c, &A.mv[i], A.cap_mv[i], std::max<int64_t>(1, nmax), "adjoint steps"));
@@ -2300,7 +2405,7 @@ HB_API hb_status hb_backward(hb_ctx *c, int64_t generation, const float *dL_dxy_
     double ink = 0.0;
     HIPCHK(c, hipMemcpyAsync(&ink, c->d_ink + hb::kInkSlices, sizeof(double), hipMemcpyDeviceToHost, c->stream));
 
-    const Shape s = hb::shape_of(E, B, W, H);
+    const Shape s = hb::shape_of(E, B, W, H, c->tiling);
     float2 *cur = A.a0, *other = A.a1;   // cur: adjoint of the polylines leaving iteration t
     if (dL_dxy_T && c->n_state > 0)      // the caller's loss gradient enters the last iteration
         HIPCHK(c, hipMemcpyAsync(cur, dL_dxy_T, sizeof(float2) * c->n_state,

@@ -121,26 +121,35 @@ def test_autotune_restores_polylines_and_tuning_is_bit_identical(hb):
         before = [b.points() for b in bs]
         choice = hb.autotune(bs, 1)
         assert choice[0] in (1, 2, 4) and choice[1] in (1, 2, 4)
+        assert choice[2] in (64, 128, 256) and choice[3] in (4, 16, 64) and 14 <= choice[4] <= 17
         for b, ref in zip(bs, before):
             off, xy = b.points()
             np.testing.assert_array_equal(off, ref[0])
             np.testing.assert_array_equal(xy, ref[1])
-            assert b.iteration == 1 and b.tuning() == choice
+            assert b.iteration == 1 and b.tuning() == choice[:2]
+            assert hb.hb_get_tiling(b.ctx) == choice[2:]
         hb.batch_run(bs, 2)
         tuned = [b.points() for b in bs]
     finally:
         for b in bs:
             b.close()
-    # every kernel variant computes the same bits
-    for (ru, au) in [(1, 1), (4, 4)]:
+    # every kernel variant and launch shape computes the same bits
+    for (ru, au), tiling in [((1, 1), (16, 1, 12)), ((4, 4), (1024, 64, 20)), ((2, 2), (64, 4, 14))]:
         for w, ref in zip(ws, tuned):
             with hb.Bundler(0) as b:
                 b.set_workload(w)
                 b.tuning(ru, au)
+                hb.hb_set_tiling(b.ctx, *tiling)
+                assert hb.hb_get_tiling(b.ctx) == tiling
                 b.run(3)
                 off, xy = b.points()
                 np.testing.assert_array_equal(off, ref[0])
                 np.testing.assert_array_equal(xy, ref[1])
+    with hb.Bundler(0) as b:
+        for bad in [(100, 4, 16), (128, 128, 16), (128, 4, 11), (2048, 4, 16)]:
+            with pytest.raises(hb.HBError) as ei:
+                hb.hb_set_tiling(b.ctx, *bad)
+            assert ei.value.status == hb.HB_EINVAL
 
 
 def test_batch_argument_errors(hb):
