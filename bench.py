@@ -193,7 +193,9 @@ def main():
                     help="time the density-width encoding (Section 3.4) of the polylines after T "
                          "iterations instead of the iteration")
     ap.add_argument("--batch-graphs", type=int, default=64)
-    ap.add_argument("--batch-emax", type=float, default=1e5)
+    ap.add_argument("--batch-emax", type=float, default=5e5)
+    ap.add_argument("--batch-schedule", type=int, default=20,
+                    help="iterations the radius schedule of the batched graphs spans")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/hbm_traffic.json from two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) of a --calibrate-copy bench; averages the "
@@ -588,16 +590,29 @@ def batched_main(args):
     import workloads
 
     torch.cuda.set_device(0)
+    free, total = torch.cuda.mem_get_info()
+    log(f"device memory: {total / 2**30:.0f} GiB, {free / 2**30:.0f} GiB free")
     log(f"generating {args.batch_graphs} graphs, edges log-uniform in [1e3, {args.batch_emax:.0e}]")
-    ws = workloads.batched(n_graphs=args.batch_graphs, e_max=args.batch_emax, n_iters=args.steps)
+    # the radius schedule of every graph spans the configured 20 iterations; --steps of them
+    # are timed (at the stated sizes all 20 do not fit in HBM at once: see the log's estimate)
+    ws = workloads.batched(n_graphs=args.batch_graphs, e_max=args.batch_emax,
+                           n_iters=max(args.steps, args.batch_schedule))
     T = args.steps
-    # one at a time
+    # one at a time: a first untimed run of each graph learns its sample counts, which size its
+    # point buffers for the timed run and for the batched run, so that no buffer growth falls
+    # in either timing
     per_graph_ms, pts_seq = [], 0
     t_seq = 0.0
+    cap_factor, first = [], []
     for w in ws:
         b = hb.Bundler(0)
         b.set_workload(w, capacity_factor=args.capacity)
-        b.run(1)
+        b.run(T)                                     # untimed: learns the sample counts
+        c = b.iter_counts(T)
+        cap_factor.append(max(1.1, 1.05 * float(c.max()) / float(c[0])))
+        first.append(int(c[0]))
+        b.set_params(w.grid_w, w.grid_h, w.radii, delta=w.delta, passes=w.passes, lam=w.lam,
+                     bbox=w.bbox, capacity_factor=cap_factor[-1])
         b.set_graph(w.node_xy, w.src, w.dst, w.weight)
         b.set_groups(w.group, w.M)
         torch.cuda.synchronize()
@@ -607,12 +622,18 @@ def batched_main(args):
         dt = time.perf_counter() - t0
         t_seq += dt
         per_graph_ms.append(dt * 1e3 / T)
-        pts_seq += int(b.iter_counts(T).sum())
+        c = b.iter_counts(T)
+        log(f"  alone: {w.name} {dt * 1e3 / T:.2f} ms per iteration, samples {c[0]} -> max {c.max()}")
+        pts_seq += int(c.sum())
         b.close()
-    # together
+    # together: per graph two FP32 point buffers (16 bytes per point of capacity) and 16-bit
+    # splat entries (2 bytes), plus the maps
+    est = sum(18.0 * f * c0 for f, c0 in zip(cap_factor, first))
+    est += sum(100.0 * w.n_groups * w.grid_w * w.grid_h for w in ws)
+    log(f"batched run: about {est / 2**30:.0f} GiB of point buffers, entries and maps")
     bs = [hb.Bundler(0) for _ in ws]
-    for b, w in zip(bs, ws):
-        b.set_workload(w, capacity_factor=args.capacity)
+    for b, w, f in zip(bs, ws, cap_factor):
+        b.set_workload(w, capacity_factor=f)
     choice = hb.autotune(bs, 1)
     hb.batch_run(bs, 1, hb.HB_RUN_GRAPH)            # capture
     for b, w in zip(bs, ws):
@@ -632,10 +653,15 @@ def batched_main(args):
         "higher_is_better": True, "dtype": "f32", "data": "synthetic",
         "config": {"workload": f"batch-{len(ws)}-graphs", "edges_total": int(sum(w.n_edges for w in ws)),
                    "edges_max": int(max(w.n_edges for w in ws)), "groups": [w.n_groups for w in ws],
-                   "grids": [w.grid_w for w in ws], "autotuned": dict(zip(("resample_chunks", "advect_chunks", "box_col_rows", "bin_sets", "hist_item_entries_log2"), choice))},
+                   "grids": [w.grid_w for w in ws], "schedule_iterations": ws[0].n_iters,
+                   "timed_iterations": T, "memory_estimate_gib": round(est / 2**30, 1),
+                   "autotuned": dict(zip(("resample_chunks", "advect_chunks", "box_col_rows", "bin_sets", "hist_item_entries_log2"), choice))},
         "one_at_a_time": {"value": pts_seq / t_seq, "per_graph_iter_ms_p50": float(np.percentile(per_graph_ms, 50)),
                           "per_graph_iter_ms_p99": float(np.percentile(per_graph_ms, 99))},
         "batched_iter_ms": t_bat * 1e3 / T,
+        # in the batch every graph advances one iteration per batched iteration
+        "batched_per_graph_iter_ms_p50": t_bat * 1e3 / T,
+        "batched_per_graph_iter_ms_p99": t_bat * 1e3 / T,
         "speedup": (pts_bat / t_bat) / (pts_seq / t_seq),
     }
     print(json.dumps(out), flush=True)

@@ -192,7 +192,7 @@ __device__ __forceinline__ int64_t edge_of(const GDesc &d, int64_t blk_local, in
     const int64_t c = (int64_t)x * q + (x < r ? x : r) + i;
     const int64_t idx = c * kWavesPerBlock + wid;
     if (idx >= d.n_edges) return -1;
-    return d.perm ? (int64_t)d.perm[idx] : idx;
+    return idx;
 }
 
 __device__ __forceinline__ int64_t sample_count(double L, double delta) {

@@ -87,7 +87,6 @@ struct GDesc {
     double ck[HB_MAX_PASSES];   // prod_{q<=k} (2 r_q + 1)^2: the normalisation of pass k
     int32_t rp[HB_MAX_PASSES];  // box radius of every pass
 
-    const int32_t *perm;        // visiting order of the edges (nullptr: 0..E-1)
     const int32_t *order;       // edge order of the advection kernels (by group, then position;
                                 // dealt round-robin; nullptr: 0..E-1)
     const int32_t *group;

@@ -394,10 +394,7 @@ __global__ __launch_bounds__(kBlock) void k_insdel(const GDesc *__restrict__ gd,
 // k_resample_count does for samples it makes. Binning (SCATTER = true): the run takes its
 // place from the write cursor of its tile and set (returning atomic) and stores one entry
 // per sample. Both passes map an edge to the same block, so to the same counter set.
-#ifndef HB_BIN_CHUNKS
-#define HB_BIN_CHUNKS 8
-#endif
-constexpr int kBinChunks = HB_BIN_CHUNKS;
+constexpr int kBinChunks = 8;
 
 template <bool SCATTER>
 __global__ __launch_bounds__(kBlock) void k_bin_samples(const GDesc *__restrict__ gd, int ng) {
@@ -891,11 +888,8 @@ __global__ __launch_bounds__(kBlock) void k_cells(const GDesc *__restrict__ gd, 
 // ---------------------------------------------------------------- advection + smoothing
 
 // Step halvings tested per round of the advection (candidates loaded together).
-#ifndef HB_TRIES_PER_ROUND
-#define HB_TRIES_PER_ROUND 2
-#endif
-constexpr int kTriesPerRound = HB_TRIES_PER_ROUND;
-constexpr float kRoundScale = 1.0f / (float)(1 << HB_TRIES_PER_ROUND);   // step ratio per round
+constexpr int kTriesPerRound = 2;
+constexpr float kRoundScale = 1.0f / (float)(1 << kTriesPerRound);   // step ratio per round
 
 // One round of step halvings k .. k + kTriesPerRound - 1 (step mf, mf/2, ...) for UU
 // sub-chunks: every candidate of the round is loaded first, then the first candidate whose

@@ -44,7 +44,7 @@ struct hb_ctx {
     bool have_graph = false;
     int32_t B = 0;
     bool have_groups = false;
-    int32_t *d_group = nullptr, *d_weight = nullptr, *d_perm = nullptr;
+    int32_t *d_group = nullptr, *d_weight = nullptr;
     int32_t *d_perm_adj = nullptr;       // edge order of the advection kernels (built on use)
     std::vector<int32_t> h_group;
     std::vector<uint32_t> h_morton;     // Morton code of each straight edge's midpoint
@@ -264,10 +264,6 @@ HB_API void hb_default_params(hb_params *p, int32_t grid_w, int32_t grid_h) {
 
 static void kovesi_radii(double sigma, int P, int32_t *radii);
 
-// 16-bit splat entries for graphs whose edges all weigh 1
-#ifndef HB_NARROW_ENTRIES
-#define HB_NARROW_ENTRIES 1
-#endif
 
 static hb_status validate(hb_ctx *c, const hb_params *p) {
     if (!p) return fail(c, HB_EINVAL, "params is NULL");
@@ -407,53 +403,53 @@ static int64_t entry_factor(const hb_ctx *c) {
     return (int64_t)std::ceil(reach) + 2;
 }
 
+// 32-bit words of an entry buffer of n entries: graphs whose edges all weigh 1 write 16-bit
+// entries (the pixel inside the tile; the count is 1), the others 32-bit ones (pixel and
+// weight).
+static size_t entry_words(const hb_ctx *c, int64_t n) {
+    return c->wmax == 1 ? (size_t)((n + 1) / 2) : (size_t)n;
+}
+
 static hb_status ensure_bins(hb_ctx *c) {
     const int64_t need = c->cap * entry_factor(c);
     if (need <= c->ent_cap && c->d_bins) return HB_OK;
-    CHKST(dalloc(c, &c->d_bins, (size_t)need, "splat entries"));
+    CHKST(dalloc(c, &c->d_bins, entry_words(c, need), "splat entries"));
     c->ent_cap = need;
     return HB_OK;
 }
 
+// Grows the point buffers to at least `need` points (1.25 times the old capacity at least),
+// one buffer at a time so that at most three point buffers are held at once: the splat
+// entries are rebuilt every iteration and are dropped first.
 static hb_status ensure_capacity(hb_ctx *c, int64_t need) {
     if (need <= c->cap) return HB_OK;
-    int64_t ncap = std::max<int64_t>(need, c->cap + c->cap / 2);
+    int64_t ncap = std::max<int64_t>(need, c->cap + c->cap / 4);
     ncap = std::max<int64_t>(ncap, 1024);
-    float2 *np[2] = {nullptr, nullptr};
-    for (int i = 0; i < 2; ++i) {
-        hb_status s = dalloc(c, &np[i], (size_t)ncap, "point buffer");
-        if (s != HB_OK) {
-            dfree(&np[0]);
-            dfree(&np[1]);
-            return s;
-        }
-    }
-    uint32_t *nb = nullptr;
-    {
-        hb_status s = dalloc(c, &nb, (size_t)ncap * (size_t)entry_factor(c), "splat entries");
-        if (s != HB_OK) {
-            dfree(&np[0]);
-            dfree(&np[1]);
-            return s;
-        }
-    }
-    if (c->pts[c->ps] && c->n_state > 0)
-        HIPCHK(c, hipMemcpyAsync(np[c->ps], c->pts[c->ps], sizeof(float2) * c->n_state,
-                                 hipMemcpyDeviceToDevice, c->stream));
-    if (c->have_samples && c->ss != c->ps && c->n_samples > 0)
-        HIPCHK(c, hipMemcpyAsync(np[c->ss], c->pts[c->ss], sizeof(float2) * c->n_samples,
-                                 hipMemcpyDeviceToDevice, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int i = 0; i < 2; ++i) {
-        dfree(&c->pts[i]);
-        c->pts[i] = np[i];
-    }
     dfree(&c->d_bins);
-    c->d_bins = nb;
-    c->ent_cap = ncap * entry_factor(c);
-    c->have_jacc = false;   // the decisions buffer is kept; it grows when a run records
+    c->ent_cap = 0;
+    for (int i = 0; i < 2; ++i) {
+        float2 *np = nullptr;
+        CHKST(dalloc(c, &np, (size_t)ncap, "point buffer"));
+        int64_t keep = 0;   // points of this buffer that later calls still read
+        if (i == c->ps && c->n_state > 0) keep = c->n_state;
+        if (c->have_samples && i == c->ss && c->ss != c->ps) keep = c->n_samples;
+        if (c->pts[i] && keep > 0) {
+            hipError_t e = hipMemcpyAsync(np, c->pts[i], sizeof(float2) * keep,
+                                          hipMemcpyDeviceToDevice, c->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+            if (e != hipSuccess) {
+                dfree(&np);
+                return fail_dev(c, e, "point buffer copy");
+            }
+        }
+        dfree(&c->pts[i]);
+        c->pts[i] = np;
+        if (i == 0) c->cap = std::min(c->cap, ncap);   // both buffers hold at least cap
+    }
     c->cap = ncap;
-    return HB_OK;
+    c->have_jacc = false;   // the decisions buffer is kept; it grows when a run records
+    return ensure_bins(c);
 }
 
 static hb_status ensure_maps(hb_ctx *c) {
@@ -505,13 +501,12 @@ static GDesc base_desc(const hb_ctx *c) {
     d.strip = c->P.splat_mode == HB_SPLAT_STRIP ? 1 : 0;
     d.ent_cap = c->ent_cap;
     d.insdel = c->P.resample_mode == HB_RESAMPLE_INSERT_DELETE ? 1 : 0;
-    d.narrow = (HB_NARROW_ENTRIES && c->wmax == 1) ? 1 : 0;
+    d.narrow = c->wmax == 1 ? 1 : 0;   // 16-bit splat entries: every edge weighs 1
     d.dmin = c->P.delta_min_px > 0.0f ? (double)c->P.delta_min_px : 0.5 * (double)c->P.delta_px;
     d.count_given = 0;
     for (int k = 0; k < d.P; ++k)
         d.a[k] = c->passw.empty() ? (k == d.P - 1 ? 1.0 : 0.0) : (double)c->passw[k];
     d.group = c->d_group;
-    d.perm = c->d_perm;
     d.order = c->d_perm_adj;
     d.weight = c->d_weight;
     d.M = c->d_M;
@@ -696,13 +691,6 @@ HB_API hb_status hb_create(hb_ctx **out, int32_t device, void *hip_stream) {
             nx = 1;
         c->nx = nx > 16 ? 16 : nx;
         (void)hipGetLastError();
-        // work per trip of the point kernels (1, 2 or 4; see hb_autotune)
-        auto pick = [](const char *v, int dflt) {
-            int u = v ? atoi(v) : dflt;
-            return (u == 1 || u == 2 || u == 4) ? u : dflt;
-        };
-        c->tune_ru = pick(getenv("HB_RESAMPLE_U"), 2);
-        c->tune_au = pick(getenv("HB_ADVECT_U"), 2);
     }
     if (hip_stream) {
         c->stream = (hipStream_t)hip_stream;
@@ -741,7 +729,6 @@ HB_API void hb_destroy(hb_ctx *c) {
         DeviceGuard guard(c->device);
         (void)hipStreamSynchronize(c->stream);
         dfree(&c->d_group);
-        dfree(&c->d_perm);
         dfree(&c->d_perm_adj);
         dfree(&c->d_weight);
         dfree(&c->d_M);
@@ -930,7 +917,6 @@ HB_API hb_status hb_set_graph(hb_ctx *c, int32_t n_nodes, const float *node_xy, 
             my = std::min(std::max(my, 0.0), 1.0);
             c->h_morton[e] = spread((uint32_t)(mx * 65535.0)) | (spread((uint32_t)(my * 65535.0)) << 1);
         }
-        dfree(&c->d_perm);
         dfree(&c->d_perm_adj);
     }
     c->have_graph = false;
@@ -1045,17 +1031,10 @@ HB_API hb_status hb_set_groups(hb_ctx *c, int32_t n_groups, const int32_t *group
     CHKST(upload(c, c->d_group, hg));
     CHKST(dalloc(c, &c->d_M, hm.size(), "interaction matrix"));
     CHKST(upload(c, c->d_M, hm));
-    // visiting order of the point kernels: identity by default; HB_EDGE_ORDER=1 visits the
-    // edges by group, then by position, which keeps an XCD's density gathers in its L2 but
-    // concentrates the memory-side splat atomics
-    dfree(&c->d_perm);
+    // the advection's edge order is rebuilt from the new groups when it is next needed (the
+    // resampling and splat kernels visit the edges in index order)
     dfree(&c->d_perm_adj);
     c->h_group = hg;
-    if (const char *ord = getenv("HB_EDGE_ORDER"); ord && atoi(ord) == 1) {
-        const std::vector<int32_t> perm = spatial_order(c);
-        CHKST(dalloc(c, &c->d_perm, std::max<size_t>(1, perm.size()), "edge order"));
-        CHKST(upload(c, c->d_perm, perm));
-    }
     c->B = n_groups;
     c->have_groups = true;
     c->ckpt_end_iter = -1;
