@@ -26,6 +26,16 @@ sys.path.insert(0, ROOT)
 
 METRIC = "edge-points advected/sec per iteration, 1M edges x 8 groups; fwd+bwd vs plain fwd"
 HBM_PEAK_GBS = 8000.0
+def kernel_names(splat, resample):
+    """Kernels behind each timed stage in the run's modes."""
+    k = dict(KERNEL_NAMES)
+    if resample == "insdel":
+        k["resample_splat"] = "k_insdel"
+    if splat == "strip":
+        k["bin"] = "k_strip_bins/k_bin_scan/k_tile_hist"
+    return k
+
+
 KERNEL_NAMES = {
     "resample_splat": "k_resample_count",
     "bin": "k_bin_scan/k_bin_samples/k_tile_hist",
@@ -76,8 +86,10 @@ def stage_bytes(stage, w, counts, n_state0):
     return tot
 
 
-def traffic_for(stage):
-    """HBM bytes per launch from committed rocprofv3 counters, if they match these kernels."""
+def traffic_for(stage, names, counts):
+    """Measured HBM bytes per launch of the stage's kernel from committed rocprofv3 counters
+    (if they were taken on these kernel sources and that kernel), scaled from the counter
+    run's mean sample count per launch to this run's."""
     path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
     if not os.path.exists(path):
         return None
@@ -87,8 +99,12 @@ def traffic_for(stage):
         return None
     if data.get("kernel_source_hash") != kernel_source_hash():
         return None
-    ent = data.get("kernels", {}).get(KERNEL_NAMES.get(stage, ""))
-    return None if ent is None else ent.get("bytes_per_launch")
+    ent = data.get("kernels", {}).get(names.get(stage, ""))
+    n_ref = data.get("points_per_launch")
+    if ent is None or not n_ref:
+        return None
+    n_line = float(sum(int(c) for c in counts)) / max(1, len(counts))
+    return ent.get("bytes_per_launch") * n_line / float(n_ref)
 
 
 def _counter_rows(path):
@@ -100,7 +116,7 @@ def _counter_rows(path):
     return rows
 
 
-def write_traffic(fetch_csv, write_csv, last, out_path):
+def write_traffic(fetch_csv, write_csv, last, out_path, points_per_launch):
     """HBM bytes per launch of every kernel from two rocprofv3 --pmc runs of the same
     command (FETCH_SIZE, then WRITE_SIZE; KiB per dispatch), each scaled by what the counter
     reads for the 1 GiB device copies of --calibrate-copy. Averages the last `last`
@@ -127,6 +143,7 @@ def write_traffic(fetch_csv, write_csv, last, out_path):
         kernels[name] = {"bytes_per_launch": fb + wb, "fetch_bytes": fb, "write_bytes": wb,
                          "launches_averaged": len(f)}
     data = {"kernel_source_hash": kernel_source_hash(),
+            "points_per_launch": points_per_launch,
             "calibration": {k: {"factor": res[k]["factor"], "copy_counter_kib": res[k]["copy_kib"]}
                             for k in ("fetch", "write")},
             "kernels": kernels}
@@ -135,25 +152,80 @@ def write_traffic(fetch_csv, write_csv, last, out_path):
     return data
 
 
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_leg(O, w, p, sel, its, threads):
+    """Edge-points per second of the oracle over iterations `its` of the workload restricted
+    to the edges `sel`, on `threads` host threads (the iterations before the first timed one
+    run untimed)."""
+    import numpy as np
+    O.lib().orc_set_threads(threads)
+    off, xy = O.initial_state(w.node_xy, w.src[sel], w.dst[sel], p)
+    M = np.asarray(w.M, np.float64)
+    n, dt = 0, 0.0
+    for it in range(max(its) + 1):
+        t0 = time.perf_counter()
+        r = O.iterate(off, xy, w.group[sel], M, p, it, keep_maps=False)
+        if it in its:
+            dt += time.perf_counter() - t0
+            n += int(r["off"][-1])
+        off, xy = r["off"], r["xy"]
+    return n, dt
+
+
 def cpu_baseline(w, fraction, strip=False, insdel=False, sigmas=None):
+    """The FP64 oracle, as it stands, on the host: iteration 0 of the measured workload on a
+    sample of its edges with the full maps, on all host threads (the line's value) and on one
+    thread, plus the tiny workload (10 iterations, all edges) and the mid-size one (its first
+    two iterations, every 4th edge) on all threads. The oracle's resampling, advection and
+    Laplacian run in parallel over edges and its box passes over groups; its splat runs on
+    one thread."""
     import numpy as np
     import oracle as O
-    p = O.params_for(w)
-    p.strip_splat = strip
-    p.insert_delete = insdel
-    p.sigmas = sigmas
+    import workloads
+    nthreads = int(O.lib().orc_num_threads())
+
+    def params(wl):
+        p = O.params_for(wl)
+        p.strip_splat = strip
+        p.insert_delete = insdel
+        p.sigmas = sigmas
+        return p
+
     step = max(1, int(round(1.0 / fraction)))
     sel = np.arange(0, w.n_edges, step)
-    off, xy = O.initial_state(w.node_xy, w.src[sel], w.dst[sel], p)
-    t0 = time.perf_counter()
-    r = O.iterate(off, xy, w.group[sel], w.M, p, 0, keep_maps=False)
-    dt = time.perf_counter() - t0
-    n = int(r["off"][-1])
-    return {"value": n / dt, "unit": "edge-points/s", "cores": int(O.lib().orc_num_threads()),
-            "kind": "oracle",
+    n, dt = _oracle_leg(O, w, params(w), sel, [0], nthreads)
+    legs = []
+    sel1 = np.arange(0, w.n_edges, 8 * step)
+    n1, dt1 = _oracle_leg(O, w, params(w), sel1, [0], 1)
+    legs.append({"workload": w.name, "threads": 1, "value": n1 / dt1,
+                 "sample": f"iteration 0 on every {8 * step}th edge ({len(sel1)} edges, {n1} points); {dt1:.2f} s"})
+    wt = workloads.tiny()
+    nt, dtt = _oracle_leg(O, wt, params(wt), np.arange(wt.n_edges), list(range(wt.n_iters)), nthreads)
+    legs.append({"workload": wt.name, "threads": nthreads, "value": nt / dtt,
+                 "sample": f"all {wt.n_edges} edges, iterations 0-{wt.n_iters - 1} ({nt} points); {dtt:.2f} s"})
+    wm = workloads.mid()
+    selm = np.arange(0, wm.n_edges, 4)
+    nm, dtm = _oracle_leg(O, wm, params(wm), selm, [0, 1], nthreads)
+    legs.append({"workload": wm.name, "threads": nthreads, "value": nm / dtm,
+                 "sample": f"every 4th edge ({len(selm)} edges), iterations 0-1 ({nm} points); {dtm:.2f} s"})
+    O.lib().orc_set_threads(nthreads)
+    return {"value": n / dt, "unit": "edge-points/s", "cores": nthreads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"iteration 0 (all stages) on every {step}th edge ({len(sel)} edges, "
                       f"{n} sample points) with the full {w.grid_w}x{w.grid_h}x{w.n_groups} maps; "
-                      f"{dt:.2f} s"}
+                      f"{dt:.2f} s",
+            "serial_steps": "splat (one thread); resampling, advection and smoothing in parallel "
+                            "over edges, box passes over groups",
+            "legs": legs}
 
 
 def main():
@@ -172,6 +244,9 @@ def main():
                     help="edge fraction of the workload timed on the CPU oracle (0: skip)")
     ap.add_argument("--grad-iters", type=int, default=3,
                     help="iterations of the forward+backward / plain ratio (0: skip)")
+    ap.add_argument("--grad-late", type=int, default=5,
+                    help="iteration of a second forward+backward window of one heavier "
+                         "iteration (0: skip)")
     ap.add_argument("--batched", action="store_true",
                     help="measure the batched form instead (prints its own JSON line)")
     ap.add_argument("--convergence", type=int, default=0, metavar="T",
@@ -192,10 +267,17 @@ def main():
     ap.add_argument("--widths", type=int, default=0, metavar="T",
                     help="time the density-width encoding (Section 3.4) of the polylines after T "
                          "iterations instead of the iteration")
+    ap.add_argument("--differentiation", action="store_true",
+                    help="measure the differentiation form instead (fwd+bwd / plain ratio on the "
+                         "matrix-pattern workload; prints its own JSON line)")
+    ap.add_argument("--diff-edges", type=int, default=5_000_000)
     ap.add_argument("--batch-graphs", type=int, default=64)
     ap.add_argument("--batch-emax", type=float, default=5e5)
     ap.add_argument("--batch-schedule", type=int, default=20,
                     help="iterations the radius schedule of the batched graphs spans")
+    ap.add_argument("--traffic-points", type=float, default=0.0,
+                    help="mean sample points per iteration of the counter runs (their JSON "
+                         "line's points_per_iteration_mean), stored with the traffic")
     ap.add_argument("--write-traffic", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
                     help="write profiles/hbm_traffic.json from two rocprofv3 --pmc runs "
                          "(FETCH_SIZE, WRITE_SIZE) of a --calibrate-copy bench; averages the "
@@ -203,7 +285,7 @@ def main():
     args = ap.parse_args()
     if args.write_traffic:
         d = write_traffic(args.write_traffic[0], args.write_traffic[1], args.steps,
-                          os.path.join(ROOT, "profiles", "hbm_traffic.json"))
+                          os.path.join(ROOT, "profiles", "hbm_traffic.json"), args.traffic_points)
         print(json.dumps({k: round(v["bytes_per_launch"] / 1e9, 3) for k, v in d["kernels"].items()}))
         return
 
@@ -213,6 +295,9 @@ def main():
         sys.exit(2)
     if args.batched:
         batched_main(args)
+        return
+    if args.differentiation:
+        differentiation_main(args)
         return
     if args.convergence > 0:
         convergence_main(args)
@@ -289,8 +374,9 @@ def main():
     ms_dom, n_dom = stages[dom]
     bytes_dom = stage_bytes(dom, w, counts, n_state0)
     achieved = bytes_dom / (ms_dom * 1e-3) / 1e9 if ms_dom > 0 else 0.0
-    tr = traffic_for(dom)
-    roofline = {"bound": "hbm", "kernel": KERNEL_NAMES[dom], "achieved": round(achieved, 1),
+    names = kernel_names(args.splat, args.resample)
+    tr = traffic_for(dom, names, counts)
+    roofline = {"bound": "hbm", "kernel": names[dom], "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": tr, "algorithmic_bytes_per_launch": int(bytes_dom / max(1, n_dom)),
                 "avg_launch_ms": round(ms_dom / max(1, n_dom), 4),
@@ -304,6 +390,13 @@ def main():
     if args.grad_iters > 0 and args.splat == "points" and args.resample == "uniform" and not sigmas:
         fwd_bwd = grad_ratio(hb, w, args.grad_iters, args.capacity)
         log(f"fwd+bwd / plain over {args.grad_iters} iterations: {fwd_bwd['ratio']:.2f}")
+        if args.grad_late > 0:
+            # one iteration at about 3e9 samples: its checkpoint (21 bytes per point), the
+            # adjoint buffers (24) and the state buffers and entries (18 per point of capacity)
+            # take about 200 GB; two such iterations do not fit in HBM
+            late = grad_ratio_window(hb, w, args.grad_late, 1, 8.0)
+            fwd_bwd["late_window"] = late
+            log(f"fwd+bwd / plain over iterations {late['iterations']}: {late['ratio']:.2f}")
 
     cpu = None
     if args.cpu_fraction > 0:
@@ -545,7 +638,8 @@ def measure_copy_gbs():
 
 def grad_ratio(hb, w, T, capacity):
     """Time T plain iterations, then T checkpointed iterations plus the backward pass, both
-    from the straight edges: the forward+backward / plain-forward time ratio."""
+    from the straight edges: the forward+backward / plain-forward time ratio. The gradients
+    stay in device memory (dL/dxy0 as a tensor on the GPU)."""
     import torch
     b = hb.Bundler(0)
     b.set_workload(w, capacity_factor=capacity)
@@ -562,7 +656,7 @@ def grad_ratio(hb, w, T, capacity):
     b.set_groups(w.group, w.M)
     n0 = hb.hb_get_num_points(b.ctx)
     hb.hb_forward_ckpt(b.ctx, T)                   # warm-up: checkpoint and adjoint buffers
-    hb.hb_backward(b.ctx, w.n_groups, w.passes, n0)
+    hb.hb_backward(b.ctx, w.n_groups, w.passes, n0, device="cuda:0")
     b.set_graph(w.node_xy, w.src, w.dst, w.weight)
     b.set_groups(w.group, w.M)
     torch.cuda.synchronize()
@@ -570,7 +664,7 @@ def grad_ratio(hb, w, T, capacity):
     hb.hb_forward_ckpt(b.ctx, T)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    loss, dM, da, dx = hb.hb_backward(b.ctx, w.n_groups, w.passes, n0)
+    loss, dM, da, dx = hb.hb_backward(b.ctx, w.n_groups, w.passes, n0, device="cuda:0")
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     b.close()
@@ -578,6 +672,137 @@ def grad_ratio(hb, w, T, capacity):
             "fwd_ckpt_ms": (t1 - t0) * 1e3, "bwd_ms": (t2 - t1) * 1e3,
             "ratio": (t2 - t0) / t_plain, "loss": loss,
             "dL_dM_norm": float((dM.astype("float64") ** 2).sum() ** 0.5)}
+
+
+def grad_ratio_window(hb, w, start, T, capacity):
+    """The forward+backward / plain ratio over iterations start .. start+T-1 (heavier ones:
+    the sample count has grown): the polylines after `start` untimed iterations are kept,
+    then T plain iterations are timed from them, then T checkpointed iterations and the
+    backward pass from the same polylines and iteration."""
+    import torch
+    b = hb.Bundler(0)
+    b.set_workload(w, capacity_factor=capacity)
+    b.run(start)
+    off, xy = b.points(hb.HB_POINTS_STATE, device="cuda:0")
+    off, xy = off.clone(), xy.clone()
+
+    def reset():
+        b.set_points(off, xy)
+        b.iteration = start
+
+    b.run(1)                                       # warm-up
+    reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.run(T)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    n_pts = int(b.iter_counts(T).sum())
+    reset()
+    n0 = hb.hb_get_num_points(b.ctx)
+    hb.hb_forward_ckpt(b.ctx, T)                   # warm-up: checkpoint and adjoint buffers
+    hb.hb_backward(b.ctx, w.n_groups, w.passes, n0, device="cuda:0")
+    reset()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hb.hb_forward_ckpt(b.ctx, T)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    hb.hb_backward(b.ctx, w.n_groups, w.passes, n0, device="cuda:0")
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    b.close()
+    return {"iterations": [start, start + T - 1], "points": n_pts, "plain_ms": t_plain * 1e3,
+            "fwd_ckpt_ms": (t1 - t0) * 1e3, "bwd_ms": (t2 - t1) * 1e3,
+            "ratio": (t2 - t0) / t_plain}
+
+
+def differentiation_main(args):
+    """The differentiation form (the matrix-pattern workload: 5M edges, 8 groups, 2048^2 x 8,
+    sampling step 4 px, 5 iterations): the plain iterations at full size, then the
+    checkpointed forward and the backward of the ink over the same 5 iterations on the
+    largest subset of the edges (every k-th) whose checkpoints fit in HBM beside the adjoint
+    buffers, and the fwd+bwd / plain time ratio on that subset. Memory per checkpointed run:
+    21 bytes per sample point of every iteration (polyline in 8, samples 8, decision 1, splat
+    entry source 4), 32 bytes per point of the largest iteration (adjoint of the points twice,
+    m v twice) and 18 bytes per point of capacity for the state buffers and splat entries."""
+    import numpy as np
+    import torch
+
+    import paper_1504_02687_amd as hb
+    import workloads
+
+    torch.cuda.set_device(0)
+    free, total = torch.cuda.mem_get_info()
+    t = time.time()
+    w = workloads.differentiation(n_edges=args.diff_edges)
+    T = w.n_iters
+    log(f"  {time.time() - t:.1f} s: {w.describe()}")
+
+    def plain(wl):
+        b = hb.Bundler(0)
+        b.set_workload(wl, capacity_factor=args.capacity)
+        b.run(T)                                     # untimed: sample counts and buffer sizes
+        c = b.iter_counts(T)
+        b.set_graph(wl.node_xy, wl.src, wl.dst, wl.weight)
+        b.set_groups(wl.group, wl.M)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.run(T)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        b.close()
+        return c, dt
+
+    counts, dt_full = plain(w)
+    log(f"plain, all {w.n_edges} edges: counts {list(map(int, counts))}, {dt_full * 1e3:.1f} ms")
+
+    def need(c):
+        return 21.0 * (2 * w.n_edges + float(np.sum(c))) + 32.0 * float(np.max(c)) + 18.0 * 1.1 * float(np.max(c))
+
+    budget = 0.85 * free
+    k = 1
+    while need(counts / k) > budget:
+        k += 1
+    sel = np.arange(0, w.n_edges, k)
+    ws = workloads.Workload(w.name + f"-every{k}", w.node_xy, w.src[sel], w.dst[sel], w.group[sel],
+                            w.M, w.grid_w, w.grid_h, w.radii, T, delta=w.delta, passes=w.passes,
+                            lam=w.lam, bbox=w.bbox, seed=w.seed)
+    cs, dt_plain = plain(ws)
+    b = hb.Bundler(0)
+    b.set_workload(ws, capacity_factor=1.1 * float(np.max(cs)) / float(cs[0]))
+    n0 = hb.hb_get_num_points(b.ctx)
+    hb.hb_forward_ckpt(b.ctx, T)                   # warm-up: checkpoint and adjoint buffers
+    hb.hb_backward(b.ctx, ws.n_groups, ws.passes, n0, device="cuda:0")
+    b.set_graph(ws.node_xy, ws.src, ws.dst, ws.weight)
+    b.set_groups(ws.group, ws.M)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    hb.hb_forward_ckpt(b.ctx, T)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    loss, dM, da, dx = hb.hb_backward(b.ctx, ws.n_groups, ws.passes, n0, device="cuda:0")
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    b.close()
+    ratio = (t2 - t0) / dt_plain
+    log(f"every {k}th edge ({ws.n_edges}): plain {dt_plain * 1e3:.1f} ms, fwd ckpt {(t1 - t0) * 1e3:.1f} ms, "
+        f"bwd {(t2 - t1) * 1e3:.1f} ms, ratio {ratio:.2f}")
+    print(json.dumps({
+        "metric": "fwd+bwd / plain forward time, differentiation form (5 iterations, ink loss)",
+        "value": ratio, "unit": "ratio", "n_gpus": 1, "higher_is_better": False,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": w.name, "edges": w.n_edges, "groups": w.n_groups,
+                   "grid": [w.grid_w, w.grid_h], "delta_px": w.delta, "iterations": T,
+                   "radii": w.radii},
+        "plain_full": {"edges": w.n_edges, "points": list(map(int, counts)), "ms": dt_full * 1e3,
+                       "edge_points_per_s": float(np.sum(counts)) / dt_full},
+        "fwd_bwd": {"edges": ws.n_edges, "every_kth_edge": k, "points": list(map(int, cs)),
+                    "memory_estimate_gib": round(need(counts / k) / 2**30, 1),
+                    "device_free_gib": round(free / 2**30, 1),
+                    "plain_ms": dt_plain * 1e3, "fwd_ckpt_ms": (t1 - t0) * 1e3,
+                    "bwd_ms": (t2 - t1) * 1e3, "ratio": ratio, "loss": loss,
+                    "dL_dM_norm": float((dM.astype(np.float64) ** 2).sum() ** 0.5)}}), flush=True)
 
 
 def batched_main(args):

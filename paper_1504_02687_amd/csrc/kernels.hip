@@ -115,10 +115,9 @@ __global__ __launch_bounds__(kBlock) void k_scan_top(const GDesc *__restrict__ g
         double wsum = (double)carry * (double)d.wmax;
         double grow = 1.0;
         for (int k = 1; k < d.P; ++k) grow *= (double)(2 * d.rp[k] + 1) * (double)(2 * d.rp[k] + 1);
-        // int32 counts: no pixel can reach 2^32 while N w < 2^32, so a pixel that passes 2^31
-        // shows up as a negative count in the first row pass; int64 box sums stay below
-        // N w prod_{k>=1} (2 r_k + 1)^2 (a first pass never exceeds the total).
-        if (wsum >= 4294967295.0 || wsum * grow >= 9.2e18) st |= ST_HIST_OVERFLOW;
+        // int64 box sums stay below N w prod_{k>=1} (2 r_k + 1)^2 (a first pass never exceeds
+        // the total); the int32 counts are bounded tile by tile when the samples are binned
+        if (wsum * grow >= 9.2e18) st |= ST_HIST_OVERFLOW;
         if (st) atomicOr(d.status, st);
     }
 }
@@ -558,11 +557,14 @@ __global__ __launch_bounds__(kBlock) void k_bin_scan(const GDesc *__restrict__ g
     if (stopped(d)) return;
     const int nt = d.n_tiles;
     int64_t base_off = 0, base_seg = 0;
+    bool big = false;
     for (int t0 = 0; t0 < nt; t0 += kBlock) {
         const int t = t0 + (int)threadIdx.x;
         int64_t tot = 0;
         if (t < nt)
             for (int q = 0; q < d.n_sets; ++q) tot += d.bin_cnt[(int64_t)q * nt + t];
+        // the int32 count of a pixel is at most its tile's entries times the largest weight
+        big |= (double)tot * (double)d.wmax >= 2147483647.0;
         const int64_t segs = (tot + d.item_entries - 1) / d.item_entries;
         int64_t sum_tot, sum_seg;
         const int64_t xo = block_excl_scan(tot, &sum_tot);
@@ -579,6 +581,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_scan(const GDesc *__restrict__ g
         base_off += sum_tot;
         base_seg += sum_seg;
     }
+    if (__syncthreads_or(big) && threadIdx.x == 0) atomicOr(d.status, (int32_t)ST_HIST_OVERFLOW);
     if (threadIdx.x == 0) {
         d.tile_off[nt] = base_off;
         d.seg_off[nt] = base_seg;
@@ -590,7 +593,7 @@ __global__ __launch_bounds__(kBlock) void k_bin_scan(const GDesc *__restrict__ g
             const double wsum = (double)base_off * (double)d.wmax;
             double grow = 1.0;
             for (int k = 1; k < d.P; ++k) grow *= (double)(2 * d.rp[k] + 1) * (double)(2 * d.rp[k] + 1);
-            if (wsum >= 4294967295.0 || wsum * grow >= 9.2e18) st |= ST_HIST_OVERFLOW;
+            if (wsum * grow >= 9.2e18) st |= ST_HIST_OVERFLOW;
             if (st) atomicOr(d.status, st);
         } else if (base_off != d.off_s[d.n_edges] || base_off > d.ent_cap) {
             atomicOr(d.status, ST_BIN_MISMATCH);

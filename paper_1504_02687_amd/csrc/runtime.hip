@@ -1258,9 +1258,6 @@ HB_API hb_status hb_run(hb_ctx *c, int32_t n_iters, uint32_t flags) {
     if (flags & ~kRunFlags) return fail(c, HB_EINVAL, "unknown run flags");
     c->last_counts.clear();
     if (n_iters == 0) return HB_OK;
-    if ((flags & HB_RUN_SAMPLES_GIVEN) &&
-        (double)c->n_state * (double)c->wmax >= 4294967295.0)
-        return fail(c, HB_EOVERFLOW, "histogram counts could exceed int32");
     CHKST(enqueue_run(c, n_iters, flags));
     if (flags & HB_RUN_ASYNC) return HB_OK;
     return finish_pending(c);

@@ -392,3 +392,45 @@ def test_allocation_failure_is_an_error_code(hb, monkeypatch):
         b.run(1)
         off, xy = b.points()
         assert off[-1] == len(xy) > 0
+
+
+def test_int32_count_bound_per_tile(hb):
+    """The int32 histogram is guarded tile by tile: a tile whose entries times the largest
+    edge weight could pass 2^31 gives HB_EOVERFLOW, while a graph whose total N w passes
+    2^32 but whose tiles stay below the bound runs, with the histogram equal to the oracle's
+    (int64) splat."""
+    rng = np.random.default_rng(17)
+    wmax = hb.HB_MAX_EDGE_WEIGHT
+    # spread: 4000 short edges over a 1024^2 grid, about 90 samples per 64x64 tile
+    E = 4000
+    start = rng.uniform(0.02, 0.98, (E, 2))
+    ang = rng.uniform(0, 2 * np.pi, E)
+    end = np.clip(start + 5.0 / 1024 * np.stack([np.cos(ang), np.sin(ang)], 1), 0.0, 1.0)
+    nodes = np.concatenate([start, end]).astype(np.float32)
+    src = np.arange(E, dtype=np.int32)
+    dst = (E + np.arange(E)).astype(np.int32)
+    weight = np.full(E, wmax, np.int32)
+    with hb.Bundler(0) as b:
+        b.set_params(1024, 1024, [2])
+        b.set_graph(nodes, src, dst, weight)
+        b.set_groups(np.zeros(E, np.int32), np.ones((1, 1), np.float32))
+        b.run(1)
+        off, xy = b.points(hb.HB_POINTS_SAMPLES)
+        hist = b.map(hb.HB_MAP_HIST, 0).astype(np.int64)
+    assert float(len(xy)) * wmax > 2.0 ** 32
+    ref = O.splat(off, xy.astype(np.float64), np.zeros(E, np.int32), 1, 1024, 1024, weight)[0]
+    np.testing.assert_array_equal(hist, ref)
+    # crowded: 300 edges of about 20 px inside one 64 x 64 tile (more than 2^31 / wmax entries)
+    E = 300
+    start = rng.uniform(130.0 / 1024, 140.0 / 1024, (E, 2))
+    end = start + 14.0 / 1024
+    nodes = np.concatenate([start, end]).astype(np.float32)
+    src = np.arange(E, dtype=np.int32)
+    dst = (E + np.arange(E)).astype(np.int32)
+    with hb.Bundler(0) as b:
+        b.set_params(1024, 1024, [2])
+        b.set_graph(nodes, src, dst, np.full(E, wmax, np.int32))
+        b.set_groups(np.zeros(E, np.int32), np.ones((1, 1), np.float32))
+        with pytest.raises(hb.HBError) as ei:
+            b.run(1)
+        assert ei.value.status == hb.HB_EOVERFLOW
