@@ -375,7 +375,7 @@ EXPORT void orc_splat(int64_t E, const int64_t *off, const double *xy, const int
 }
 
 /* Line-strip splat (the rasterised variant of Eq. 1): the paper's implementation draws
- * the edges with Bresenham's algorithm, like rendering lines into an accumulation buffer.
+ * the edges with Bresenham's algorithm, drawing them into the histogram as lines.
  * Reading: the polyline of an edge is drawn as a line strip through the pixels of its
  * points (the pixel of a point as in orc_splat). Segment j, from pixel (u0, v0) to pixel
  * (u1, v1), draws the n = max(|u1 - u0|, |v1 - v0|) pixels t = 0 .. n-1 of the digital line

@@ -776,6 +776,7 @@ HB_API const char *hb_last_error(const hb_ctx *c) { return c ? c->err.c_str() : 
 HB_API const char *hb_version(void) { return "hb 0.1 gfx950"; }
 
 static hb_status finish_pending(hb_ctx *c);
+static hb_status ensure_order(hb_ctx *c);
 
 HB_API hb_status hb_set_params(hb_ctx *c, const hb_params *p) {
     ENTER(c);
@@ -987,6 +988,7 @@ HB_API hb_status hb_set_graph(hb_ctx *c, int32_t n_nodes, const float *node_xy, 
     CHKST(ensure_capacity(c, (int64_t)std::ceil((double)n0 * c->P.capacity_factor) + 64));
     c->have_graph = true;
     c->ckpt_end_iter = -1;
+    if (c->have_groups) CHKST(ensure_order(c));   // the edges' midpoints have changed
     return HB_OK;
 }
 
@@ -1039,13 +1041,14 @@ HB_API hb_status hb_set_groups(hb_ctx *c, int32_t n_groups, const int32_t *group
     c->have_groups = true;
     c->ckpt_end_iter = -1;
     c->have_maps = false;
-    return HB_OK;
+    return ensure_order(c);   // the advection's edge order (host counting sort), built here
 }
 
 // ------------------------------------------------------------------ the iteration loop
 
-// Edge order of the advection kernels (by group, then position); rebuilt after the graph or
-// the groups change.
+// Edge order of the advection kernels (by group, then position): a counting sort on the host
+// of the (group, Morton cell of the straight midpoint) keys, uploaded once; built when the
+// groups are set (and again when the graph changes under them), so that no run pays for it.
 static hb_status ensure_order(hb_ctx *c) {
     if (c->d_perm_adj) return HB_OK;
     const std::vector<int32_t> order = spatial_order(c);
