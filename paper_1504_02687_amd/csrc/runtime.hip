@@ -2274,6 +2274,8 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags, int
         CHKST(read_scalar(c, c->d_totals, &ns));
         CHKST(read_status(c));
         k.ns = ns;
+        if (ns >= (int64_t(1) << 32))   // the tile bins record their samples as 32-bit indices
+            return fail_free(fail(c, HB_EOVERFLOW, "the checkpointed forward takes fewer than 2^32 samples per iteration"));
         int64_t cap_ns2 = k.cap_ns, cap_t2 = k.cap_t;
         st = grow(c, &k.xs, k.cap_ns, std::max<int64_t>(1, ns), "checkpoint");
         if (st == HB_OK) st = grow(c, &k.jacc, cap_ns2, std::max<int64_t>(1, ns), "checkpoint");
