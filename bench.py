@@ -852,9 +852,10 @@ def batched_main(args):
         pts_seq += int(c.sum())
         b.close()
     # together: per graph two FP32 point buffers (16 bytes per point of capacity) and 16-bit
-    # splat entries (2 bytes), plus the maps
+    # splat entries (2 bytes), plus the maps (histogram, box passes, density, gradient and their
+    # strip copies: about 70 bytes per pixel of a layer)
     est = sum(18.0 * f * c0 for f, c0 in zip(cap_factor, first))
-    est += sum(100.0 * w.n_groups * w.grid_w * w.grid_h for w in ws)
+    est += sum(70.0 * w.n_groups * w.grid_w * w.grid_h for w in ws)
     log(f"batched run: about {est / 2**30:.0f} GiB of point buffers, entries and maps")
     bs = [hb.Bundler(0) for _ in ws]
     for b, w, f in zip(bs, ws, cap_factor):

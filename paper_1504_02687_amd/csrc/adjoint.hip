@@ -104,7 +104,7 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
     const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
     const int l = d.group[e];
     (void)plane;
-    const HB_G Quad *__restrict__ grad = glb(d.gradq + 2 * (int64_t)l * cell_plane(W, H));
+    const HB_G float2 *__restrict__ grad = glb(d.grads + (int64_t)l * grad_strip_plane(W, H));
     const float2 *__restrict__ xs = d.samples + o0;
     const float2 *__restrict__ yb = d.adj_in + o0;
     float2 *__restrict__ xb = d.adj_out + o0;
@@ -174,10 +174,11 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
         const int jj = interior ? (int)jraw : -2;
         if (jj >= 0) {
             const float2 x = xsj;
-            const Cell t0 = cell_of(x.x, x.y, W, H);
-            const Quad q0 = ldq(grad, 2 * t0.g), q1 = ldq(grad, 2 * t0.g + 1);
-            const float2 g00 = make_float2(q0.a, q0.b), g10 = make_float2(q0.c, q0.d);
-            const float2 g01 = make_float2(q1.a, q1.b), g11 = make_float2(q1.c, q1.d);
+            const STap t0 = stap_of(x.x, x.y, W, H);
+            Quad q0, q1;
+            ld_grad(grad, t0.og, q0, q1);
+            const float2 g00 = make_float2(q0.a, q0.b), g01 = make_float2(q0.c, q0.d);
+            const float2 g10 = make_float2(q1.a, q1.b), g11 = make_float2(q1.c, q1.d);
             double gx, gy;
             interp2q(q0, q1, t0, gx, gy);   // the forward's bilinear gradient sample
             const double nrm = sqrt(gx * gx + gy * gy);

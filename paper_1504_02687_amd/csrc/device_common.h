@@ -251,7 +251,9 @@ __device__ __forceinline__ void pixel_of(float2 p, int W, int H, int &u, int &v)
 // Tile (key) of pixel (u, v) of a layer and the pixel's place inside the tile.
 __device__ __forceinline__ void tile_of(const GDesc &d, int layer, int u, int v, int &key,
                                         uint32_t &local) {
-    key = (layer * d.tiles_y + (v >> kTileShift)) * d.tiles_x + (u >> kTileShift);
+    // at most 64 layers of at most 128 x 128 tiles: every factor fits the 24-bit multiplier
+    key = (int)(__umul24(__umul24((uint32_t)layer, (uint32_t)d.tiles_y) + (uint32_t)(v >> kTileShift),
+                         (uint32_t)d.tiles_x) + (uint32_t)(u >> kTileShift));
     local = (uint32_t)(((v & (kTile - 1)) << kTileShift) | (u & (kTile - 1)));
 }
 
@@ -337,62 +339,82 @@ __device__ __forceinline__ double bilerp(double a, double b, double c, double d,
     return __builtin_fma(tx * ty, d, r);
 }
 
-// Bilinear cell of a sample and the fractions between its taps (the same taps and
-// fractions as taps_of): c indexes its density record, g its gradient record (tiled layout).
-struct Cell {
-    uint32_t c, g;
+// Bilinear sample of the strip maps (see strip_rows): od is the offset of its density taps,
+// og of its first gradient pair (the second is five pairs on); the same taps (clamped into the
+// grid by the padding) and fractions as taps_of.
+struct STap {
+    uint32_t od, og;
     float tx, ty;
 };
 
-// The cell of (fx, fy) = (x - 1/2, y - 1/2) already inside [-1, W] x [-1, H].
-__device__ __forceinline__ Cell cell_at(float fx, float fy, int W, int H) {
+// The sample at (fx, fy) = (x - 1/2, y - 1/2) already inside [-1, W] x [-1, H].
+__device__ __forceinline__ STap stap_at(float fx, float fy, int W, int H) {
     const float u0f = floorf(fx), v0f = floorf(fy);
-    Cell t;
+    STap t;
     t.tx = fx - u0f;
     t.ty = fy - v0f;
-    const uint32_t cu = (uint32_t)(min((int)u0f, W - 1) + 1), cv = (uint32_t)(min((int)v0f, H - 1) + 1);
-    const uint32_t base = (__umul24(cv >> 1, (uint32_t)cell_tiles_x(W)) + (cu >> 2)) << 3;
-    t.c = base + ((cv & 1u) << 2) + (cu & 3u);
-    t.g = base + ((cu & 2u) << 1) + ((cv & 1u) << 1) + (cu & 1u);
+    const uint32_t c = (uint32_t)(min((int)u0f, W - 1) + 1), r = (uint32_t)(min((int)v0f, H - 1) + 1);
+    // grid sides are at most 8192, so the products fit the 24-bit multiplier
+    const uint32_t s = r >> 2, k = r & 3u;
+    t.od = ((__umul24(s, (uint32_t)W + 1u) + c) * 5u + k) * 2u;
+    t.og = (__umul24(s, (uint32_t)W + 2u) + c) * 5u + k;
     return t;
 }
 
-__device__ __forceinline__ Cell cell_of(float x, float y, int W, int H) {
-    return cell_at(__builtin_amdgcn_fmed3f(x - 0.5f, -1.0f, (float)W),
+__device__ __forceinline__ STap stap_of(float x, float y, int W, int H) {
+    return stap_at(__builtin_amdgcn_fmed3f(x - 0.5f, -1.0f, (float)W),
                    __builtin_amdgcn_fmed3f(y - 0.5f, -1.0f, (float)H), W, H);
 }
 
-// The cell of a point already clamped into [0, W) x [0, H) (an advection candidate): the
-// clamp of cell_of is then the identity and is left out.
-__device__ __forceinline__ Cell cell_of_inside(float x, float y, int W, int H) {
-    return cell_at(x - 0.5f, y - 0.5f, W, H);
+// The sample of a point already clamped into [0, W) x [0, H) (an advection candidate): the
+// clamp of stap_of is then the identity and is left out.
+__device__ __forceinline__ STap stap_inside(float x, float y, int W, int H) {
+    return stap_at(x - 0.5f, y - 0.5f, W, H);
 }
 
-__device__ __forceinline__ Quad ldq(const HB_G Quad *m, uint32_t i) {
-    typedef float f4v __attribute__((ext_vector_type(4)));
-    const f4v v = *(const HB_G f4v *)((const HB_G char *)m + ((uint64_t)i << 4));
-    Quad q;
-    q.a = v.x;
-    q.b = v.y;
-    q.c = v.z;
-    q.d = v.w;
-    return q;
+// Vector loads of 8-byte-aligned words: global loads of several dwords need only dword
+// alignment.
+typedef float hb_f4u __attribute__((ext_vector_type(4), aligned(8)));
+
+// Density taps of a sample: one 16-byte load.
+__device__ __forceinline__ Quad ld_rho(const HB_G float *m, uint32_t o) {
+    const hb_f4u p = *(const HB_G hb_f4u *)(m + o);
+    Quad r;
+    r.a = p.x;
+    r.b = p.y;
+    r.c = p.z;
+    r.d = p.w;
+    return r;
 }
 
-// Density sample from the loaded taps of a cell, in FP32 (the precision of the stored map;
-// the acceptance tests).
-__device__ __forceinline__ float interp1q(const Quad &q, const Cell &t) {
+// Gradient taps of a sample: two 16-byte loads, p = g(u0, v0), g(u0, v0 + 1) and
+// q = g(u0 + 1, v0), g(u0 + 1, v0 + 1), (x, y) each.
+__device__ __forceinline__ void ld_grad(const HB_G float2 *m, uint32_t o, Quad &p, Quad &q) {
+    const hb_f4u a = *(const HB_G hb_f4u *)(m + o);
+    const hb_f4u b = *(const HB_G hb_f4u *)(m + o + 5);
+    p.a = a.x;
+    p.b = a.y;
+    p.c = a.z;
+    p.d = a.w;
+    q.a = b.x;
+    q.b = b.y;
+    q.c = b.z;
+    q.d = b.w;
+}
+
+// Density sample from its taps, in FP32 (the precision of the stored map; the acceptance
+// tests).
+__device__ __forceinline__ float interp1q(const Quad &q, const STap &t) {
     return bilerp(q.a, q.b, q.c, q.d, t.tx, t.ty);
 }
 
-// Gradient sample from the loaded taps of a cell (q0: x, y of the first two taps, q1: of
-// the last two), in FP64: the direction of a small gradient between taps of opposite sign
-// keeps the precision of the stored taps.
-__device__ __forceinline__ void interp2q(const Quad &q0, const Quad &q1, const Cell &t,
-                                         double &gx, double &gy) {
+// Gradient sample from its taps (see ld_grad), in FP64: the direction of a small gradient
+// between taps of opposite sign keeps the precision of the stored taps.
+__device__ __forceinline__ void interp2q(const Quad &p, const Quad &q, const STap &t, double &gx,
+                                         double &gy) {
     const double tx = t.tx, ty = t.ty;
-    gx = bilerp((double)q0.a, (double)q0.c, (double)q1.a, (double)q1.c, tx, ty);
-    gy = bilerp((double)q0.b, (double)q0.d, (double)q1.b, (double)q1.d, tx, ty);
+    gx = bilerp((double)p.a, (double)q.a, (double)p.c, (double)q.c, tx, ty);
+    gy = bilerp((double)p.b, (double)q.b, (double)p.d, (double)q.d, tx, ty);
 }
 
 }  // namespace hb

@@ -40,20 +40,31 @@ constexpr int kKmMaxK = HB_KMEANS_MAX_K;            // clusters of the grouping 
 constexpr int kKmMaxDim = HB_KMEANS_MAX_DIM;        // coordinates per point
 static_assert(kKmMaxK <= kBlock, "one thread per cluster in k_km_db");
 
-// Four map values of one bilinear cell (16 bytes, one load).
+// Four map values of one bilinear sample: a (u0, v0), b (u0 + 1, v0), c (u0, v0 + 1),
+// d (u0 + 1, v0 + 1).
 struct alignas(16) Quad {
     float a, b, c, d;
 };
 
-// Bilinear cells (cu, cv) = (u0 + 1, v0 + 1), cu in [0, W], cv in [0, H], are stored by tiles
-// of 4 x 2 cells, tile (cu / 4, cv / 2) at (cv / 2) * cell_tiles_x(W) + cu / 4, eight records
-// per tile: the density record of a cell at tile * 8 + (cv % 2) * 4 + cu % 4 (a tile is one
-// 128-byte line), its 32-byte gradient record at tile * 8 + ((cu / 2) % 2) * 4 + (cv % 2) * 2
-// + cu % 2 (2 x 2 cells per line). Samples that are close in the plane then share lines
-// whatever the direction of their edge.
-__host__ __device__ inline int32_t cell_tiles_x(int32_t W) { return (W + 4) >> 2; }
-__host__ __device__ inline int64_t cell_plane(int32_t W, int32_t H) {
-    return (int64_t)cell_tiles_x(W) * ((H + 2) >> 1) * 8;
+// Strip maps for bilinear sampling. The grid padded by one clamped row and column on each
+// side (stored row r = v + 1 in [0, H + 1], stored column c = u + 1 in [0, W + 1]) is cut into
+// strips of four stored rows; a strip keeps, per column, its four rows and the first row of the
+// next strip (five rows), so the two rows r, r + 1 of a bilinear sample (r in [0, H]) always
+// fall in strip r / 4.
+//   density: record (strip s, column c), c in [0, W], holds the five rows of columns c and
+//     c + 1 interleaved, (rho(c, 4s + k), rho(c + 1, 4s + k)) for k = 0..4 (ten values), so
+//     the four taps of a sample are one 16-byte load at ((s (W + 1) + c) * 5 + r % 4) * 2;
+//   gradient: record (s, c), c in [0, W + 1], holds the five rows of column c (five (x, y)
+//     pairs), so a sample's taps are two 16-byte loads at (s (W + 2) + c) * 5 + r % 4 and five
+//     pairs on.
+// A 128-byte line then covers about 3 x 4 sample positions of either map, which the samples
+// around a point share.
+__host__ __device__ inline int64_t strip_rows(int32_t H) { return (int64_t)(H >> 2) + 1; }
+__host__ __device__ inline int64_t rho_strip_plane(int32_t W, int32_t H) {
+    return strip_rows(H) * (W + 1) * 10;      // floats per layer
+}
+__host__ __device__ inline int64_t grad_strip_plane(int32_t W, int32_t H) {
+    return strip_rows(H) * (W + 2) * 5;       // (x, y) pairs per layer
 }
 
 // One graph of one iteration. Every kernel takes an array of these (one per graph of a
@@ -69,7 +80,7 @@ struct GDesc {
     int64_t blk_pxb;     // one thread per layer pixel (B * W * H)
     int64_t blk_edget;   // one thread per edge
     int64_t blk_tile;    // tile-histogram blocks (tile_blocks per graph)
-    int64_t blk_cell;    // one thread per cell record of a layer (B * cell_plane(W, H))
+    int64_t blk_strip;   // one thread per gradient strip record (B * strip_rows(H) * (W + 2))
 
     int64_t n_edges;
     int64_t cap;         // capacity of the point buffers, in points
@@ -125,10 +136,9 @@ struct GDesc {
     int64_t *tmp;               // [B][H][W] row-pass output
     float *rho;                 // [B][H][W]
     float2 *grad;               // [B][H][W]
-    // bilinear cells: cell (u0, v0), u0 in [-1, W-1], v0 in [-1, H-1], holds the taps
-    // (u0,v0), (u0+1,v0), (u0,v0+1), (u0+1,v0+1), clamped into the grid (tiled, see Quad)
-    Quad *rhoq;                 // [B][cell_plane] density taps
-    Quad *gradq;                // [B][cell_plane][2] gradient taps: (x, y) of the first two, last two
+    // strip maps of rho and grad (bilinear taps clamped into the grid; see strip_rows)
+    float *rhos;                // [B][rho_strip_plane]
+    float2 *grads;              // [B][grad_strip_plane]
     int8_t *jacc;               // [cap] accepted halving per sample (record != 0)
     int32_t *status;
 
@@ -157,7 +167,7 @@ struct GDesc {
 
 // Launch-shape block counts of one graph (host side).
 struct Shape {
-    int64_t edge, scan, row, col, px, pxb, edget, tile, cell;
+    int64_t edge, scan, row, col, px, pxb, edget, tile, strip;
 };
 // Launch shapes that the autotuner may change, per context: rows per thread of the column
 // box pass, the most tile-count sets (privatised copies of the tile counters) and the
@@ -202,8 +212,8 @@ hipError_t launch_box_pass(const GDesc *desc, int ng, const Shape &tot, int max_
 hipError_t launch_density_grad(const GDesc *desc, int ng, const Shape &tot, int bmax,
                                hipStream_t st);
 // density and gradient, then their bilinear cells (what the advection reads)
-hipError_t launch_density_cells(const GDesc *desc, int ng, const Shape &tot, int bmax,
-                                hipStream_t st);
+hipError_t launch_density_strips(const GDesc *desc, int ng, const Shape &tot, int bmax,
+                                 hipStream_t st);
 hipError_t launch_advect_smooth(const GDesc *desc, int ng, const Shape &tot, int u,
                                 hipStream_t st);
 hipError_t launch_fill_totals(const GDesc *desc, int ng, int T, hipStream_t st);

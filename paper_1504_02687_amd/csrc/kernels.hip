@@ -832,59 +832,30 @@ __global__ __launch_bounds__(kBlock) void k_density_grad(const GDesc *__restrict
     }
 }
 
-// Bilinear cells of the density and gradient maps in their tiled layout (one thread per
-// record slot of a layer: the density record and the gradient record stored at that slot,
-// which belong to different cells of the same tile): the four clamped taps of every sample
-// whose first tap is (u0, v0), so that the advection reads a density sample with one
-// 16-byte load and a gradient sample with two.
-__global__ __launch_bounds__(kBlock) void k_cells(const GDesc *__restrict__ gd, int ng) {
+// Strip maps of the density and gradient (see strip_rows): one thread per gradient record
+// (strip s, stored column c) writes its five gradient pairs and, for c <= W, the density
+// record of columns c and c + 1; rows and columns clamped into the grid.
+__global__ __launch_bounds__(kBlock) void k_strips(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
-    HB_FIND(blk_cell);
+    HB_FIND(blk_strip);
     if (stopped(d)) return;
-    const int W = d.W, H = d.H, ntx = cell_tiles_x(W);
-    const int64_t nq = cell_plane(W, H), plane = (int64_t)W * H;
-    const int64_t i = (blk - d.blk_cell) * kBlock + threadIdx.x;
-    if (i >= (int64_t)d.B * nq) return;
-    const int64_t l = i / nq, r = i - l * nq;
-    const int tile = (int)(r >> 3), p = (int)(r & 7);
-    const int tyi = tile / ntx, txi = tile - tyi * ntx;
+    const int W = d.W, H = d.H, WC = W + 2;
+    const int64_t per = strip_rows(H) * WC, plane = (int64_t)W * H;
+    const int64_t i = (blk - d.blk_strip) * kBlock + threadIdx.x;
+    if (i >= (int64_t)d.B * per) return;
+    const int64_t l = i / per, r = i - l * per;
+    const int s = (int)(r / WC), c = (int)(r - (int64_t)s * WC);
+    const int u0 = min(max(c - 1, 0), W - 1), u1 = min(c, W - 1);
     const float *rho = d.rho + l * plane;
     const float2 *grad = d.grad + l * plane;
-    {
-        // density record: cell (4 txi + p % 4, 2 tyi + p / 4)
-        const int u0 = 4 * txi + (p & 3) - 1, v0 = 2 * tyi + (p >> 2) - 1;
-        if (u0 < W && v0 < H) {
-            const int ua = min(max(u0, 0), W - 1), ub = min(max(u0 + 1, 0), W - 1);
-            const int va = min(max(v0, 0), H - 1), vb = min(max(v0 + 1, 0), H - 1);
-            const int64_t a = (int64_t)va * W, b = (int64_t)vb * W;
-            Quad q;
-            q.a = rho[a + ua];
-            q.b = rho[a + ub];
-            q.c = rho[b + ua];
-            q.d = rho[b + ub];
-            d.rhoq[i] = q;
-        }
-    }
-    {
-        // gradient record: cell (4 txi + 2 ((p / 4) % 2) + p % 2, 2 tyi + (p / 2) % 2)
-        const int u0 = 4 * txi + 2 * (p >> 2) + (p & 1) - 1, v0 = 2 * tyi + ((p >> 1) & 1) - 1;
-        if (u0 < W && v0 < H) {
-            const int ua = min(max(u0, 0), W - 1), ub = min(max(u0 + 1, 0), W - 1);
-            const int va = min(max(v0, 0), H - 1), vb = min(max(v0 + 1, 0), H - 1);
-            const int64_t a = (int64_t)va * W, b = (int64_t)vb * W;
-            const float2 g00 = grad[a + ua], g10 = grad[a + ub], g01 = grad[b + ua], g11 = grad[b + ub];
-            Quad q0, q1;
-            q0.a = g00.x;
-            q0.b = g00.y;
-            q0.c = g10.x;
-            q0.d = g10.y;
-            q1.a = g01.x;
-            q1.b = g01.y;
-            q1.c = g11.x;
-            q1.d = g11.y;
-            d.gradq[2 * i] = q0;
-            d.gradq[2 * i + 1] = q1;
-        }
+    float2 *go = d.grads + l * grad_strip_plane(W, H) + r * 5;
+    // a density record is 40 bytes at a multiple of 40 bytes: 8-byte stores
+    float2 *ro = (float2 *)(d.rhos + l * rho_strip_plane(W, H)) + ((int64_t)s * (W + 1) + c) * 5;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+        const int64_t row = (int64_t)min(max(4 * s + k - 1, 0), H - 1) * W;
+        go[k] = grad[row + u0];
+        if (c <= W) ro[k] = make_float2(rho[row + u0], rho[row + u1]);
     }
 }
 
@@ -898,11 +869,11 @@ constexpr float kRoundScale = 1.0f / (float)(1 << kTriesPerRound);   // step rat
 // sub-chunks: every candidate of the round is loaded first, then the first candidate whose
 // FP32 bilinear density is not lower than r0 is accepted (jj = its halving, act cleared).
 template <int UU>
-__device__ __forceinline__ void halving_round(const HB_G Quad *__restrict__ rho, const float2 *x,
+__device__ __forceinline__ void halving_round(const HB_G float *__restrict__ rho, const float2 *x,
                                               const float *dx, const float *dy, const float *r0,
                                               bool *act, int *jj, int k, int K, float mf,
                                               float xmaxf, float ymaxf, int W, int H) {
-    Cell c[kTriesPerRound][UU];
+    STap c[kTriesPerRound][UU];
     Quad q[kTriesPerRound][UU];
     float mt = mf;
 #pragma unroll
@@ -911,7 +882,7 @@ __device__ __forceinline__ void halving_round(const HB_G Quad *__restrict__ rho,
         for (int u = 0; u < UU; ++u) {
             const float cx = __builtin_amdgcn_fmed3f(__builtin_fmaf(mt, dx[u], x[u].x), 0.0f, xmaxf);
             const float cy = __builtin_amdgcn_fmed3f(__builtin_fmaf(mt, dy[u], x[u].y), 0.0f, ymaxf);
-            c[i][u] = cell_of_inside(cx, cy, W, H);
+            c[i][u] = stap_inside(cx, cy, W, H);
         }
         mt *= 0.5f;
     }
@@ -919,7 +890,7 @@ __device__ __forceinline__ void halving_round(const HB_G Quad *__restrict__ rho,
     for (int i = 0; i < kTriesPerRound; ++i)
 #pragma unroll
         for (int u = 0; u < UU; ++u)
-            if (act[u] && k + i <= K) q[i][u] = ldq(rho, c[i][u].c);
+            if (act[u] && k + i <= K) q[i][u] = ld_rho(rho, c[i][u].od);
 #pragma unroll
     for (int i = 0; i < kTriesPerRound; ++i) {
 #pragma unroll
@@ -939,9 +910,10 @@ __device__ __forceinline__ void halving_round(const HB_G Quad *__restrict__ rho,
 // halo on each side (U independent gather chains in flight): lane l of sub-chunk u
 // advects point j0 + 62u - 1 + l (end points stay), neighbours come from lanes l-1 and l+1,
 // and lanes 1..62 write the Laplacian-smoothed point. The FP64 length of the smoothed
-// polyline gives the next sample count.
+// polyline gives the next sample count. Up to two sub-chunks the kernel is held to five
+// waves per SIMD (at most 96 VGPRs).
 template <int U>
-__global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restrict__ gd, int ng) {
+__global__ __launch_bounds__(kBlock, U <= 2 ? 5 : 1) void k_advect_smooth(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_edge);
     if (stopped(d)) return;
@@ -957,9 +929,8 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
     const int64_t plane = (int64_t)W * H;
     const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
     (void)plane;
-    const int64_t cells = (int64_t)d.group[e] * cell_plane(W, H);
-    const HB_G Quad *__restrict__ rho = glb(d.rhoq + cells);
-    const HB_G Quad *__restrict__ grad = glb(d.gradq + 2 * cells);
+    const HB_G float *__restrict__ rho = glb(d.rhos + (int64_t)d.group[e] * rho_strip_plane(W, H));
+    const HB_G float2 *__restrict__ grad = glb(d.grads + (int64_t)d.group[e] * grad_strip_plane(W, H));
     const HB_G float2 *__restrict__ xs = glb(d.samples + o0);
     HB_G float2 *__restrict__ ys = glb(d.pnew + o0);
     HB_G int8_t *__restrict__ jrec = glb(d.jacc + o0);
@@ -988,17 +959,16 @@ __global__ __launch_bounds__(kBlock) void k_advect_smooth(const GDesc *__restric
             act[u] = inr && j > 0 && j < n - 1;
             jj[u] = act[u] ? -1 : -2;
         }
-        // every sub-chunk's cells first, then all their loads, then the arithmetic, so the
-        // U gather chains are in flight together (inactive lanes read a valid cell)
-        Cell t0[U];
+        // every sub-chunk's taps first, then all their loads, then the arithmetic, so the
+        // U gather chains are in flight together (inactive lanes read valid taps)
+        STap t0[U];
         Quad g0[U], g1[U], rq[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) t0[u] = cell_of(x[u].x, x[u].y, W, H);
+        for (int u = 0; u < U; ++u) t0[u] = stap_of(x[u].x, x[u].y, W, H);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            g0[u] = ldq(grad, 2 * t0[u].g);
-            g1[u] = ldq(grad, 2 * t0[u].g + 1);
-            rq[u] = ldq(rho, t0[u].c);
+            ld_grad(grad, t0[u].og, g0[u], g1[u]);
+            rq[u] = ld_rho(rho, t0[u].od);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1164,7 +1134,7 @@ Shape shape_of(int64_t n_edges, int32_t B, int32_t W, int32_t H, const Tiling &t
     s.pxb = ((int64_t)B * plane + kBlock - 1) / kBlock;
     s.edget = (n_edges + 1 + kBlock - 1) / kBlock;
     s.tile = tiles_of(B, W, H, tg.sets_max).blocks;
-    s.cell = ((int64_t)B * cell_plane(W, H) + kBlock - 1) / kBlock;
+    s.strip = ((int64_t)B * strip_rows(H) * (W + 2) + kBlock - 1) / kBlock;
     return s;
 }
 
@@ -1290,11 +1260,11 @@ hipError_t launch_density_grad(const GDesc *desc, int ng, const Shape &tot, int 
     return hipGetLastError();
 }
 
-hipError_t launch_density_cells(const GDesc *desc, int ng, const Shape &tot, int bmax,
-                                hipStream_t st) {
+hipError_t launch_density_strips(const GDesc *desc, int ng, const Shape &tot, int bmax,
+                                 hipStream_t st) {
     hipError_t e = launch_density_grad(desc, ng, tot, bmax, st);
-    if (e != hipSuccess || tot.cell <= 0) return e;
-    hipLaunchKernelGGL(k_cells, grid_of(tot.cell), dim3(kBlock), 0, st, desc, ng);
+    if (e != hipSuccess || tot.strip <= 0) return e;
+    hipLaunchKernelGGL(k_strips, grid_of(tot.strip), dim3(kBlock), 0, st, desc, ng);
     return hipGetLastError();
 }
 

@@ -10,9 +10,9 @@
 namespace hb {
 
 // One wave per edge, its points 64 at a time (coalesced), four such chunks in flight per
-// trip: bilinear density at each point in its edge's layer, from the density record of its
-// bilinear cell (the four clamped taps in one 16-byte load, the same taps, fractions and
-// rounding as the advection's density samples), clamped at 0; a wave maximum, then one
+// trip: bilinear density at each point in its edge's layer, from the strip map of its layer
+// (the four clamped taps in one 16-byte load, the same taps, fractions and rounding as the
+// advection's density samples), clamped at 0; a wave maximum, then one
 // atomic max on the float bits (non-negative floats order as their bits).
 constexpr int kDensChunks = 4;
 
@@ -28,7 +28,7 @@ __global__ __launch_bounds__(kBlock) void k_point_density(const GDesc *__restric
     if (e >= d.n_edges) return;
     const int W = d.W, H = d.H;
     const int64_t o0 = d.off_s[e], n = d.off_s[e + 1] - o0;
-    const HB_G Quad *__restrict__ rho = glb(d.rhoq + (int64_t)d.group[e] * cell_plane(W, H));
+    const HB_G float *__restrict__ rho = glb(d.rhos + (int64_t)d.group[e] * rho_strip_plane(W, H));
     const HB_G float2 *__restrict__ xs = glb(d.samples + o0);
     HB_G float *__restrict__ out = glb(dens + o0);
     float m = 0.0f;
@@ -40,12 +40,12 @@ __global__ __launch_bounds__(kBlock) void k_point_density(const GDesc *__restric
             x[u] = make_float2(0.5f, 0.5f);
             if (j < n) x[u] = ld2(xs + j);
         }
-        Cell c[kDensChunks];
+        STap c[kDensChunks];
         Quad q[kDensChunks];
 #pragma unroll
         for (int u = 0; u < kDensChunks; ++u) {
-            c[u] = cell_of(x[u].x, x[u].y, W, H);
-            q[u] = ldq(rho, c[u].c);
+            c[u] = stap_of(x[u].x, x[u].y, W, H);
+            q[u] = ld_rho(rho, c[u].od);
         }
 #pragma unroll
         for (int u = 0; u < kDensChunks; ++u) {

@@ -75,7 +75,8 @@ struct hb_ctx {
     int64_t *d_box = nullptr, *d_tmp = nullptr;
     float *d_rho = nullptr;
     float2 *d_grad = nullptr;
-    hb::Quad *d_rhoq = nullptr, *d_gradq = nullptr;
+    float *d_rhos = nullptr;
+    float2 *d_grads = nullptr;
     int32_t map_B = 0, map_W = 0, map_H = 0, map_P = 0;
     bool have_maps = false;
 
@@ -470,9 +471,8 @@ static hb_status ensure_maps(hb_ctx *c) {
     CHKST(dalloc(c, &c->d_tmp, plane, "row-pass scratch"));
     CHKST(dalloc(c, &c->d_rho, plane, "density"));
     CHKST(dalloc(c, &c->d_grad, plane, "gradient"));
-    const size_t cells = (size_t)B * hb::cell_plane(W, H);
-    CHKST(dalloc(c, &c->d_rhoq, cells, "density cells"));
-    CHKST(dalloc(c, &c->d_gradq, 2 * cells, "gradient cells"));
+    CHKST(dalloc(c, &c->d_rhos, (size_t)B * hb::rho_strip_plane(W, H), "density strips"));
+    CHKST(dalloc(c, &c->d_grads, (size_t)B * hb::grad_strip_plane(W, H), "gradient strips"));
     c->map_B = B;
     c->map_W = W;
     c->map_H = H;
@@ -535,8 +535,8 @@ static GDesc base_desc(const hb_ctx *c) {
     d.tmp = c->d_tmp;
     d.rho = c->d_rho;
     d.grad = c->d_grad;
-    d.rhoq = c->d_rhoq;
-    d.gradq = c->d_gradq;
+    d.rhos = c->d_rhos;
+    d.grads = c->d_grads;
     d.jacc = c->d_jacc;
     d.status = c->d_status;
     return d;
@@ -754,8 +754,8 @@ HB_API void hb_destroy(hb_ctx *c) {
         dfree(&c->d_tmp);
         dfree(&c->d_rho);
         dfree(&c->d_grad);
-        dfree(&c->d_rhoq);
-        dfree(&c->d_gradq);
+        dfree(&c->d_rhos);
+        dfree(&c->d_grads);
         dfree(&c->d_jacc);
         dfree(&c->d_render);
         free_ckpts(c);
@@ -1078,7 +1078,7 @@ static hb_status prepare_ctx(hb_ctx *c, int T, uint32_t flags) {
 
 static void shape_add(Shape &a, const Shape &b) {
     a.edge += b.edge; a.scan += b.scan; a.row += b.row; a.col += b.col;
-    a.px += b.px; a.pxb += b.pxb; a.edget += b.edget; a.tile += b.tile; a.cell += b.cell;
+    a.px += b.px; a.pxb += b.pxb; a.edget += b.edget; a.tile += b.tile; a.strip += b.strip;
 }
 
 // Enqueue T iterations of the graphs cs[0..n) on lead's stream: the descriptor table holds
@@ -1136,7 +1136,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
             d.blk_pxb = base[g].pxb;
             d.blk_edget = base[g].edget;
             d.blk_tile = base[g].tile;
-            d.blk_cell = base[g].cell;
+            d.blk_strip = base[g].strip;
             d.record = record && it == T - 1;
             d.bin_src = (d.record && (flags & kRunRecordBins)) ? c->d_binsrc : nullptr;
             // samples not made by the uniform resampling are counted in tiles afterwards
@@ -1192,7 +1192,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
                 if (strip) HIPCHK(c, hb::launch_strip_bins(dd, n, tot, false, c->stream));
                 HIPCHK(c, hb::launch_bin_hist(dd, n, tot, strip, points, c->stream));
                 for (int k = 0; k < pmax; ++k) HIPCHK(c, hb::launch_box_pass(dd, n, tot, max_w, k, c->stream));
-                HIPCHK(c, hb::launch_density_cells(dd, n, tot, bmax, c->stream));
+                HIPCHK(c, hb::launch_density_strips(dd, n, tot, bmax, c->stream));
                 HIPCHK(c, hb::launch_advect_smooth(dd, n, tot, au, c->stream));
                 continue;
             }
@@ -1209,7 +1209,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
             STAGE(c, HB_STAGE_BIN, hb::launch_bin_hist(dd, n, tot, strip, points, c->stream));
             for (int k = 0; k < pmax; ++k)
                 STAGE(c, HB_STAGE_BOX, hb::launch_box_pass(dd, n, tot, max_w, k, c->stream));
-            STAGE(c, HB_STAGE_DENSITY_GRAD, hb::launch_density_cells(dd, n, tot, bmax, c->stream));
+            STAGE(c, HB_STAGE_DENSITY_GRAD, hb::launch_density_strips(dd, n, tot, bmax, c->stream));
             STAGE(c, HB_STAGE_ADVECT_SMOOTH, hb::launch_advect_smooth(dd, n, tot, au, c->stream));
         }
         return HB_OK;
@@ -2079,7 +2079,7 @@ HB_API hb_status hb_point_widths(hb_ctx *c, int32_t iter, float w_min, float w_m
     else HIPCHK(c, hb::launch_strip_bins(dd, 1, s, false, c->stream));
     HIPCHK(c, hb::launch_bin_hist(dd, 1, s, strip, !strip, c->stream));
     for (int k = 0; k < d.P; ++k) HIPCHK(c, hb::launch_box_pass(dd, 1, s, d.W, k, c->stream));
-    HIPCHK(c, hb::launch_density_cells(dd, 1, s, d.B, c->stream));
+    HIPCHK(c, hb::launch_density_strips(dd, 1, s, d.B, c->stream));
     HIPCHK(c, hipMemsetAsync(pmax, 0, sizeof(uint32_t), c->stream));
     HIPCHK(c, hb::launch_point_density(dd, s, pd, pmax, c->stream));
     HIPCHK(c, hb::launch_widths(pd, N, pmax, (double)w_min, (double)w_max, log_scale, pw, c->stream));
@@ -2311,7 +2311,7 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags, int
         HIPCHK(c, hb::launch_bin_hist(dd, 1, sh, false, true, c->stream));
         for (int kp = 0; kp < c->P.box_passes; ++kp)
             HIPCHK(c, hb::launch_box_pass(dd, 1, sh, c->P.grid_w, kp, c->stream));
-        HIPCHK(c, hb::launch_density_cells(dd, 1, sh, std::max(1, c->B), c->stream));
+        HIPCHK(c, hb::launch_density_strips(dd, 1, sh, std::max(1, c->B), c->stream));
         HIPCHK(c, hb::launch_advect_smooth(dd, 1, sh, c->tune_au, c->stream));
         HIPCHK(c, hipMemcpyAsync(kk.hist, c->d_hist, sizeof(int32_t) * plane, hipMemcpyDeviceToDevice, c->stream));
         HIPCHK(c, hipMemcpyAsync(kk.toff, c->d_tile_off, sizeof(int64_t) * nt1, hipMemcpyDeviceToDevice, c->stream));
@@ -2445,7 +2445,7 @@ HB_API hb_status hb_backward(hb_ctx *c, int64_t generation, const float *dL_dxy_
         const GDesc *a = c->d_desc + 2 * (size_t)(T - 1 - t);
         hipEvent_t adv_done = c->adj_ev[2 * (size_t)t], par_done = c->adj_ev[2 * (size_t)t + 1];
         for (int kk = 0; kk < P; ++kk) HIPCHK(c, hb::launch_box_pass(a, 1, s, W, kk, c->stream));
-        HIPCHK(c, hb::launch_density_cells(a, 1, s, B, c->stream));
+        HIPCHK(c, hb::launch_density_strips(a, 1, s, B, c->stream));
         if (t + 2 < T) HIPCHK(c, hipStreamWaitEvent(c->stream, c->adj_ev[2 * (size_t)(t + 2) + 1], 0));
         HIPCHK(c, hb::launch_adj_maps(a, s, B, c->stream));
         HIPCHK(c, hb::launch_adj_advect(a, s, c->stream));
