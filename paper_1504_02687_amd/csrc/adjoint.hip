@@ -136,26 +136,23 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
                 nxx = pp[j + 1].x;
                 nxy = pp[j + 1].y;
             }
+            // unit vectors from the segment's reciprocal length (0 for a zero-length segment)
             double ux = 0.0, uy = 0.0;
             if (inr && j + 1 < n) {
-                const double dx = (double)nxx - c.x, dy = (double)nxy - c.y;
-                const double l = sqrt(dx * dx + dy * dy);
-                if (l > 0.0) {
-                    ux = dx / l;
-                    uy = dy / l;
-                }
+                double l, r;
+                seg_len_rcp(c, make_float2(nxx, nxy), l, r);
+                ux = ((double)nxx - c.x) * r;
+                uy = ((double)nxy - c.y) * r;
             }
             double pux = lane_prev(ux), puy = lane_prev(uy);
             if (lane == 0) {
                 pux = puy = 0.0;
                 if (inr && j >= 1) {
                     const float2 a = pp[j - 1];
-                    const double dx = (double)c.x - a.x, dy = (double)c.y - a.y;
-                    const double l = sqrt(dx * dx + dy * dy);
-                    if (l > 0.0) {
-                        pux = dx / l;
-                        puy = dy / l;
-                    }
+                    double l, r;
+                    seg_len_rcp(a, c, l, r);
+                    pux = ((double)c.x - a.x) * r;
+                    puy = ((double)c.y - a.y) * r;
                 }
             }
             if (inr) ybar = make_float2((float)(pux - ux), (float)(puy - uy));
@@ -181,9 +178,10 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
             const float2 g10 = make_float2(q1.a, q1.b), g11 = make_float2(q1.c, q1.d);
             double gx, gy;
             interp2q(q0, q1, t0, gx, gy);   // the forward's bilinear gradient sample
-            const double nrm = sqrt(gx * gx + gy * gy);
-            const bool big = nrm > eps;
-            const double inv = 1.0 / (big ? nrm : eps);   // one division for d and v
+            // 1 / max(|g|, eps) for d and v (reciprocal square root and a Newton step)
+            const double q = gx * gx + gy * gy;
+            const bool big = q > eps * eps;
+            const double inv = big ? rsqrt_nr(q) : 1.0 / eps;
             const double dx = gx * inv, dy = gy * inv;
             const double m = ldexp(h, -jj);
             const double cx = (double)x.x + m * dx, cy = (double)x.y + m * dy;
@@ -212,6 +210,13 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) mbig = fmaxf(mbig, __shfl_xor(mbig, o, 64));
     if (lane == 0 && mbig > 0.0f) atomicMax(d.mvmax, __float_as_uint(mbig));
+}
+
+// The nearest integer of v (ties to even; |v| < 2^51) as a two's-complement 64-bit value: v
+// (exact in FP64) plus 1.5 * 2^52 keeps its integer part in the low bits of the mantissa.
+__device__ __forceinline__ unsigned long long fixed64(float v) {
+    const double t = (double)v + 6755399441055744.0;
+    return (unsigned long long)(__double_as_longlong(t) - 0x4338000000000000ll);
 }
 
 // Threads of a k_adj_params block: its (64 + 2)^2 LDS grid of two 64-bit sums (70 KB) allows
@@ -244,11 +249,15 @@ __global__ __launch_bounds__(kParBlock) void k_adj_params(const GDesc *__restric
     if (mmax > 0.0f) (void)frexpf(mmax, &ex);
     const float scale = ldexpf(1.0f, 40 - ex);
     const double unit = ldexp(1.0, ex - 40);
+    const HB_G int64_t *__restrict__ aseg = glb(d.aseg_off);
+    const HB_G uint32_t *__restrict__ src = glb(d.abin_src);
+    const HB_G float2 *__restrict__ mvs = glb(d.mv);
+    const HB_G float2 *__restrict__ xs = glb(d.samples);
     for (int64_t it = blockIdx.x; it < nitems; it += gridDim.x) {
         int lo = 0, hi = nt - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
-            if (d.aseg_off[mid] <= it) lo = mid; else hi = mid - 1;
+            if (aseg[mid] <= it) lo = mid; else hi = mid - 1;
         }
         const int t = lo;
         const int64_t beg = d.atile_off[t] + (it - d.aseg_off[t]) * d.item_entries;
@@ -259,41 +268,41 @@ __global__ __launch_bounds__(kParBlock) void k_adj_params(const GDesc *__restric
         const int X0 = tx * kTile - 1, Y0 = ty * kTile - 1;   // grid cell (0, 0)
         for (int c = threadIdx.x; c < 2 * GN; c += kParBlock) (&sA[0][0])[c] = 0ull;
         __syncthreads();
-        // four entries per thread in flight (the gathers of m v and x depend on the entry)
+        // four entries per thread in flight: every index load, then every gather of m v and
+        // x (an entry past the item's end reads the item's first entry and is dropped)
         for (int64_t i0 = beg + threadIdx.x; i0 < end; i0 += 4 * kParBlock) {
             uint32_t pe[4];
+            bool ok[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int64_t i = i0 + r * kParBlock;
+                ok[r] = i < end;
+                pe[r] = src[ok[r] ? i : beg];
+            }
             float2 me[4], xe[4];
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int64_t i = i0 + r * kParBlock;
-                pe[r] = i < end ? d.abin_src[i] : 0u;
-            }
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int64_t i = i0 + r * kParBlock;
-                me[r] = make_float2(0.0f, 0.0f);
-                xe[r] = make_float2(0.0f, 0.0f);
-                if (i < end) {
-                    me[r] = d.mv[pe[r]];
-                    xe[r] = d.samples[pe[r]];
-                }
+                me[r] = ld2(mvs + pe[r]);
+                xe[r] = ld2(xs + pe[r]);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const float2 m = me[r], x = xe[r];
-                if (m.x == 0.0f && m.y == 0.0f) continue;
+                if (!ok[r] || (m.x == 0.0f && m.y == 0.0f)) continue;
                 const Taps tp = taps_of(x.x, x.y, W, H);
                 const float ftx = tp.tx, fty = tp.ty;
                 const float w[4] = {(1.0f - ftx) * (1.0f - fty), ftx * (1.0f - fty),
                                     (1.0f - ftx) * fty, ftx * fty};
-                const uint32_t o[4] = {tp.o00, tp.o10, tp.o01, tp.o11};
+                // grid cells of the taps (ua, va), (ub, va), (ua, vb), (ub, vb): rows and
+                // columns within [0, GW) of the tile's grid
+                const int ca = __mul24(tp.va - Y0, GW) - X0, cb = __mul24(tp.vb - Y0, GW) - X0;
+                const int cq[4] = {ca + tp.ua, ca + tp.ub, cb + tp.ua, cb + tp.ub};
                 const float mx = m.x * scale, my = m.y * scale;
 #pragma unroll
                 for (int q = 0; q < 4; ++q) {
-                    const int v = (int)(o[q] / (uint32_t)W), u = (int)(o[q] - (uint32_t)v * (uint32_t)W);
-                    const int c = (v - Y0) * GW + (u - X0);
-                    atomicAdd(&sA[0][c], (unsigned long long)(long long)rintf(w[q] * mx));
-                    atomicAdd(&sA[1][c], (unsigned long long)(long long)rintf(w[q] * my));
+                    const int c = cq[q];
+                    atomicAdd(&sA[0][c], fixed64(w[q] * mx));
+                    atomicAdd(&sA[1][c], fixed64(w[q] * my));
                 }
             }
         }
@@ -307,18 +316,18 @@ __global__ __launch_bounds__(kParBlock) void k_adj_params(const GDesc *__restric
             const int v = Y0 + c / GW, u = X0 + c % GW;
             const int64_t px = (int64_t)v * W + u;
             const double fx = (double)ax * unit, fy = (double)ay * unit;
-            const float2 *gb = d.gbm + px * bp;
-            const float2 *gk = d.gkm + ((int64_t)layer * plane + px) * pp;
+            const HB_G float2 *gb = glb(d.gbm) + px * bp;
+            const HB_G float2 *gk = glb(d.gkm) + ((int64_t)layer * plane + px) * pp;
 #pragma unroll
             for (int b = 0; b < BMAX; ++b) {
                 if (b >= B) break;
-                const float2 g = gb[b];
+                const float2 g = ld2(gb + b);
                 acc[b] += fx * g.x + fy * g.y;
             }
 #pragma unroll
             for (int k = 0; k < HB_MAX_PASSES; ++k) {
                 if (k >= P) break;
-                const float2 g = gk[k];
+                const float2 g = ld2(gk + k);
                 acc[BMAX + k] += fx * g.x + fy * g.y;
             }
         }
@@ -373,6 +382,7 @@ __global__ __launch_bounds__(kBlock, 6) void k_adj_resample(const GDesc *__restr
     const double nm1 = (double)(n - 1);
     const double ds = L / nm1;
     const double inv_ds = 1.0 / ds;
+    const double inv_nm1 = 1.0 / nm1;   // d s_k / d L = k / (n - 1)
 
     double Cbase = 0.0, Lbar = 0.0, carryP = 0.0;
     double carryBx = 0.0, carryBy = 0.0, carryVx = 0.0, carryVy = 0.0;
@@ -442,7 +452,7 @@ __global__ __launch_bounds__(kBlock, 6) void k_adj_resample(const GDesc *__restr
                     if (traw > 0.0 && traw < 1.0 && sR[wid][lo] > 0.0) {
                         const float2 pa = sP[wid][lo], pz = sP[wid][lo + 1];
                         tb = xv.x * ((double)pz.x - pa.x) + xv.y * ((double)pz.y - pa.y);
-                        Lbar += tb * sR[wid][lo] * ((double)k / nm1);
+                        Lbar += tb * sR[wid][lo] * ((double)k * inv_nm1);
                     }
                 }
                 v[0] = (1.0 - t) * xv.x;
@@ -538,12 +548,10 @@ __global__ __launch_bounds__(kBlock, 6) void k_adj_resample(const GDesc *__restr
         }
         double ux = 0.0, uy = 0.0;
         if (lane < 63 && i + 1 < m) {
-            const double dx = (double)nxx - c.x, dy = (double)nxy - c.y;
-            const double l = sqrt(__builtin_fma(dx, dx, mul_rn(dy, dy)));
-            if (l > 0.0) {
-                ux = dx / l;
-                uy = dy / l;
-            }
+            double l, r;
+            seg_len_rcp(c, make_float2(nxx, nxy), l, r);   // r = 0 for a zero-length segment
+            ux = ((double)nxx - c.x) * r;
+            uy = ((double)nxy - c.y) * r;
         }
         double pux = lane_prev(ux), puy = lane_prev(uy);
         if (lane == 0) {

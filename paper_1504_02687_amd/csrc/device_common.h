@@ -232,6 +232,14 @@ __device__ __forceinline__ void seg_len_rcp(float2 a, float2 b, double &len, dou
     rcp = pos ? y1 : 0.0;
 }
 
+// 1 / sqrt(q) for q > 0: the hardware FP64 reciprocal square root refined by one Newton step
+// (about 1 ulp; in place of a correctly rounded square root and a division).
+__device__ __forceinline__ double rsqrt_nr(double q) {
+    const double y0 = __builtin_amdgcn_rsq(q);
+    const double e = __builtin_fma(-mul_rn(q, y0), y0, 1.0);
+    return __builtin_fma(mul_rn(0.5, y0), e, y0);
+}
+
 // Explicit roundings (no contraction choices left to the compiler), so that every kernel
 // variant computes the same bits.
 __device__ __forceinline__ double seg_len(float2 a, float2 b) {
@@ -285,12 +293,13 @@ __device__ __forceinline__ int run_head(uint64_t heads, int lane) {
 
 // ---------------------------------------------------------------- bilinear sampling
 
-// Taps of a bilinear sample at (x - 1/2, y - 1/2), clamped into the grid: 32-bit offsets
-// into one map layer and the FP32 fractions between the taps. For x >= 1/2 the FP32
-// subtraction and the fraction are exact; below 1/2 (and at the far border) both taps of the
-// axis are the same column or row, so the fraction has no effect.
+// Taps of a bilinear sample at (x - 1/2, y - 1/2), clamped into the grid: columns ua, ub
+// and rows va, vb of the four taps (ua, va), (ub, va), (ua, vb), (ub, vb), and the FP32
+// fractions between them. For x >= 1/2 the FP32 subtraction and the fraction are exact; below
+// 1/2 (and at the far border) both taps of the axis are the same column or row, so the
+// fraction has no effect.
 struct Taps {
-    uint32_t o00, o10, o01, o11;   // (u0, v0), (u1, v0), (u0, v1), (u1, v1)
+    int ua, ub, va, vb;
     float tx, ty;
 };
 
@@ -302,14 +311,10 @@ __device__ __forceinline__ Taps taps_of(float x, float y, int W, int H) {
     t.tx = fx - u0f;
     t.ty = fy - v0f;
     const int u0 = (int)u0f, v0 = (int)v0f;
-    const int ua = min(max(u0, 0), W - 1), ub = min(max(u0 + 1, 0), W - 1);
-    const int va = min(max(v0, 0), H - 1), vb = min(max(v0 + 1, 0), H - 1);
-    // grid sides are at most 8192, so the row products fit the 24-bit multiplier
-    const uint32_t ra = __umul24((uint32_t)va, (uint32_t)W), rb = __umul24((uint32_t)vb, (uint32_t)W);
-    t.o00 = ra + (uint32_t)ua;
-    t.o10 = ra + (uint32_t)ub;
-    t.o01 = rb + (uint32_t)ua;
-    t.o11 = rb + (uint32_t)ub;
+    t.ua = min(max(u0, 0), W - 1);
+    t.ub = min(max(u0 + 1, 0), W - 1);
+    t.va = min(max(v0, 0), H - 1);
+    t.vb = min(max(v0 + 1, 0), H - 1);
     return t;
 }
 

@@ -80,7 +80,7 @@ struct GDesc {
     int64_t blk_pxb;     // one thread per layer pixel (B * W * H)
     int64_t blk_edget;   // one thread per edge
     int64_t blk_tile;    // tile-histogram blocks (tile_blocks per graph)
-    int64_t blk_strip;   // one thread per gradient strip record (B * strip_rows(H) * (W + 2))
+    int64_t blk_strip;   // one thread per gradient strip pair (B * grad_strip_plane(W, H))
 
     int64_t n_edges;
     int64_t cap;         // capacity of the point buffers, in points

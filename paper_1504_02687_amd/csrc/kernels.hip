@@ -832,30 +832,27 @@ __global__ __launch_bounds__(kBlock) void k_density_grad(const GDesc *__restrict
     }
 }
 
-// Strip maps of the density and gradient (see strip_rows): one thread per gradient record
-// (strip s, stored column c) writes its five gradient pairs and, for c <= W, the density
-// record of columns c and c + 1; rows and columns clamped into the grid.
+// Strip maps of the density and gradient (see strip_rows): one thread per row k of a gradient
+// record (strip s, stored column c) writes that row's gradient pair and, for c <= W, the
+// density pair of columns c and c + 1 (consecutive threads write consecutive 8-byte words);
+// rows and columns clamped into the grid.
 __global__ __launch_bounds__(kBlock) void k_strips(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_strip);
     if (stopped(d)) return;
     const int W = d.W, H = d.H, WC = W + 2;
-    const int64_t per = strip_rows(H) * WC, plane = (int64_t)W * H;
+    const int64_t per = strip_rows(H) * WC * 5, plane = (int64_t)W * H;
     const int64_t i = (blk - d.blk_strip) * kBlock + threadIdx.x;
     if (i >= (int64_t)d.B * per) return;
-    const int64_t l = i / per, r = i - l * per;
-    const int s = (int)(r / WC), c = (int)(r - (int64_t)s * WC);
+    const int64_t l = i / per, r = i - l * per, rec = r / 5;
+    const int k = (int)(r - rec * 5), s = (int)(rec / WC), c = (int)(rec - (int64_t)s * WC);
+    const int64_t row = (int64_t)min(max(4 * s + k - 1, 0), H - 1) * W;
     const int u0 = min(max(c - 1, 0), W - 1), u1 = min(c, W - 1);
-    const float *rho = d.rho + l * plane;
-    const float2 *grad = d.grad + l * plane;
-    float2 *go = d.grads + l * grad_strip_plane(W, H) + r * 5;
-    // a density record is 40 bytes at a multiple of 40 bytes: 8-byte stores
-    float2 *ro = (float2 *)(d.rhos + l * rho_strip_plane(W, H)) + ((int64_t)s * (W + 1) + c) * 5;
-#pragma unroll
-    for (int k = 0; k < 5; ++k) {
-        const int64_t row = (int64_t)min(max(4 * s + k - 1, 0), H - 1) * W;
-        go[k] = grad[row + u0];
-        if (c <= W) ro[k] = make_float2(rho[row + u0], rho[row + u1]);
+    d.grads[l * grad_strip_plane(W, H) + r] = d.grad[l * plane + row + u0];
+    // a density record is ten floats (five pairs) at a multiple of ten floats
+    if (c <= W) {
+        float2 *ro = (float2 *)(d.rhos + l * rho_strip_plane(W, H));
+        ro[((int64_t)s * (W + 1) + c) * 5 + k] = make_float2(d.rho[l * plane + row + u0], d.rho[l * plane + row + u1]);
     }
 }
 
@@ -1134,7 +1131,7 @@ Shape shape_of(int64_t n_edges, int32_t B, int32_t W, int32_t H, const Tiling &t
     s.pxb = ((int64_t)B * plane + kBlock - 1) / kBlock;
     s.edget = (n_edges + 1 + kBlock - 1) / kBlock;
     s.tile = tiles_of(B, W, H, tg.sets_max).blocks;
-    s.strip = ((int64_t)B * strip_rows(H) * (W + 2) + kBlock - 1) / kBlock;
+    s.strip = ((int64_t)B * strip_rows(H) * (W + 2) * 5 + kBlock - 1) / kBlock;
     return s;
 }
 
