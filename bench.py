@@ -273,6 +273,9 @@ def main():
     ap.add_argument("--diff-edges", type=int, default=5_000_000)
     ap.add_argument("--batch-graphs", type=int, default=64)
     ap.add_argument("--batch-emax", type=float, default=5e5)
+    ap.add_argument("--batch-tune-at", type=int, default=-1,
+                    help="iteration of the batch state the autotuner runs on (default: the middle "
+                         "of the timed window)")
     ap.add_argument("--batch-schedule", type=int, default=20,
                     help="iterations the radius schedule of the batched graphs spans")
     ap.add_argument("--traffic-points", type=float, default=0.0,
@@ -860,6 +863,12 @@ def batched_main(args):
     bs = [hb.Bundler(0) for _ in ws]
     for b, w, f in zip(bs, ws, cap_factor):
         b.set_workload(w, capacity_factor=f)
+    # the launch shapes are tuned on a state from the middle of the timed window: the
+    # polylines of iteration 0 are straight two-point lines, where one chunk per trip wins, but
+    # the later, longer ones carry most of the timed samples
+    tune_at = T // 2 if args.batch_tune_at < 0 else min(args.batch_tune_at, T - 1)
+    if tune_at > 0:
+        hb.batch_run(bs, tune_at)
     choice = hb.autotune(bs, 1)
     hb.batch_run(bs, 1, hb.HB_RUN_GRAPH)            # capture
     for b, w in zip(bs, ws):
@@ -881,7 +890,8 @@ def batched_main(args):
                    "edges_max": int(max(w.n_edges for w in ws)), "groups": [w.n_groups for w in ws],
                    "grids": [w.grid_w for w in ws], "schedule_iterations": ws[0].n_iters,
                    "timed_iterations": T, "memory_estimate_gib": round(est / 2**30, 1),
-                   "autotuned": dict(zip(("resample_chunks", "advect_chunks", "box_col_rows", "bin_sets", "hist_item_entries_log2"), choice))},
+                   "autotuned": dict(zip(("resample_chunks", "advect_chunks", "box_col_rows", "bin_sets", "hist_item_entries_log2"), choice)),
+                   "autotuned_at_iteration": tune_at},
         "one_at_a_time": {"value": pts_seq / t_seq, "per_graph_iter_ms_p50": float(np.percentile(per_graph_ms, 50)),
                           "per_graph_iter_ms_p99": float(np.percentile(per_graph_ms, 99))},
         "batched_iter_ms": t_bat * 1e3 / T,
