@@ -211,7 +211,7 @@ hipError_t launch_box_pass(const GDesc *desc, int ng, const Shape &tot, int max_
                            hipStream_t st);
 hipError_t launch_density_grad(const GDesc *desc, int ng, const Shape &tot, int bmax,
                                hipStream_t st);
-// density and gradient, then their bilinear cells (what the advection reads)
+// density and gradient, then their strip maps (what the advection reads)
 hipError_t launch_density_strips(const GDesc *desc, int ng, const Shape &tot, int bmax,
                                  hipStream_t st);
 hipError_t launch_advect_smooth(const GDesc *desc, int ng, const Shape &tot, int u,
