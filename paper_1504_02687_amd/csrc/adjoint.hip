@@ -105,36 +105,64 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
     const int l = d.group[e];
     (void)plane;
     const HB_G float2 *__restrict__ grad = glb(d.grads + (int64_t)l * grad_strip_plane(W, H));
-    const float2 *__restrict__ xs = d.samples + o0;
-    const float2 *__restrict__ yb = d.adj_in + o0;
-    float2 *__restrict__ xb = d.adj_out + o0;
-    float2 *__restrict__ mvp = d.mv + o0;
-    const int8_t *__restrict__ jv = d.jacc + o0;
+    const HB_G float2 *__restrict__ xs = glb(d.samples + o0);
+    HB_G float2 *__restrict__ xb = glb(d.adj_out + o0);
+    HB_G float2 *__restrict__ mvp = glb(d.mv + o0);
+    const HB_G int8_t *__restrict__ jv = glb(d.jacc + o0);
+    // the output polylines are the final ones when ink_pts is set: y_bar_j = u_(j-1) - u_j,
+    // u the unit vectors of the adjacent segments (the gradient of the ink)
+    const bool ink = d.ink_pts != nullptr;
+    const HB_G float2 *__restrict__ pp = glb((ink ? d.ink_pts : d.adj_in) + o0);
     const double h = d.h, s = d.s, eps = d.eps;
     const double xmax = (double)W - 1.0 / 256.0, ymax = (double)H - 1.0 / 256.0;
 
+    // loads of one trip (lane l: point j0 - 1 + l), which do not depend on the arithmetic of
+    // the trip before: the decision, the sample, and y_bar or the final point (lane 63 also
+    // the final point after the chunk, lane 0 the one before it)
+    struct Base {
+        int8_t jr;
+        float2 x, y, pn, pl;
+    };
+    auto load = [&](int64_t j0) {
+        Base b;
+        const int64_t j = j0 - 1 + lane;
+        b.jr = -2;
+        b.x = b.y = b.pn = b.pl = make_float2(0.0f, 0.0f);
+        if (j >= 0 && j < n) {
+            b.jr = jv[j];
+            b.x = ld2(xs + j);
+            b.y = ld2(pp + j);
+            if (ink && lane == 0 && j >= 1) b.pl = ld2(pp + (j - 1));
+            if (ink && lane == 63 && j + 1 < n) b.pn = ld2(pp + (j + 1));
+        }
+        return b;
+    };
+
     float mbig = 0.0f;
-    for (int64_t j0 = 0; j0 < n; j0 += 62) {
+    // one trip of 62 output points from the loads cu; it issues the loads of the trip after it
+    // into nx (none past the edge's end)
+    auto trip = [&](int64_t j0, const Base &cu, Base &nx) {
         const int64_t j = j0 - 1 + lane;
         const bool inr = j >= 0 && j < n;
         const bool interior = inr && j > 0 && j < n - 1;
-        // loads of this trip issued together: decisions and samples do not depend on y_bar
-        int8_t jraw = -2;
-        float2 xsj = make_float2(0.0f, 0.0f);
-        if (inr) {
-            jraw = jv[j];
-            xsj = xs[j];
+        const bool out = lane >= 1 && lane <= 62 && j < n;
+        const int jj = interior ? (int)cu.jr : -2;
+        // the gradient taps of a moved sample go out first, then the next trip's loads, so
+        // both are in flight during this trip's arithmetic
+        STap t0;
+        Quad q0, q1;
+        if (out && jj >= 0) {
+            t0 = stap_of(cu.x.x, cu.x.y, W, H);
+            ld_grad(grad, t0.og, q0, q1);
         }
-        float2 ybar = make_float2(0.0f, 0.0f);
-        if (d.ink_pts) {
-            // the output polylines are the final ones: y_bar_j = u_(j-1) - u_j, u the unit
-            // vectors of the adjacent segments (the gradient of the ink)
-            const float2 *pp = d.ink_pts + o0;
-            const float2 c = inr ? pp[j] : make_float2(0.0f, 0.0f);
+        nx = load(j0 + 62);
+        float2 ybar = cu.y;
+        if (ink) {
+            const float2 c = cu.y;
             float nxx = lane_next(c.x), nxy = lane_next(c.y);
-            if (lane == 63 && j + 1 < n) {
-                nxx = pp[j + 1].x;
-                nxy = pp[j + 1].y;
+            if (lane == 63) {
+                nxx = cu.pn.x;
+                nxy = cu.pn.y;
             }
             // unit vectors from the segment's reciprocal length (0 for a zero-length segment)
             double ux = 0.0, uy = 0.0;
@@ -148,32 +176,26 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
             if (lane == 0) {
                 pux = puy = 0.0;
                 if (inr && j >= 1) {
-                    const float2 a = pp[j - 1];
+                    const float2 a = cu.pl;
                     double l, r;
                     seg_len_rcp(a, c, l, r);
                     pux = ((double)c.x - a.x) * r;
                     puy = ((double)c.y - a.y) * r;
                 }
             }
-            if (inr) ybar = make_float2((float)(pux - ux), (float)(puy - uy));
-        } else if (inr) {
-            ybar = yb[j];
+            ybar = inr ? make_float2((float)(pux - ux), (float)(puy - uy)) : make_float2(0.0f, 0.0f);
         }
         const double qx = interior ? (double)ybar.x : 0.0, qy = interior ? (double)ybar.y : 0.0;
         const double qlx = lane_prev(qx), qly = lane_prev(qy);
         const double qrx = lane_next(qx), qry = lane_next(qy);
-        if (!(lane >= 1 && lane <= 62 && j < n)) continue;
+        if (!out) return;
         const double cf = interior ? 1.0 - s : 1.0;
         double wx = cf * (double)ybar.x + 0.5 * s * (qlx + qrx);
         double wy = cf * (double)ybar.y + 0.5 * s * (qly + qry);
         double gxb = wx, gyb = wy;
         float2 mvv = make_float2(0.0f, 0.0f);
-        const int jj = interior ? (int)jraw : -2;
         if (jj >= 0) {
-            const float2 x = xsj;
-            const STap t0 = stap_of(x.x, x.y, W, H);
-            Quad q0, q1;
-            ld_grad(grad, t0.og, q0, q1);
+            const float2 x = cu.x;
             const float2 g00 = make_float2(q0.a, q0.b), g01 = make_float2(q0.c, q0.d);
             const float2 g10 = make_float2(q1.a, q1.b), g11 = make_float2(q1.c, q1.d);
             double gx, gy;
@@ -204,8 +226,16 @@ __global__ __launch_bounds__(kBlock) void k_adj_advect(const GDesc *__restrict__
             mvv = make_float2((float)(m * vx), (float)(m * vy));
             mbig = fmaxf(mbig, fmaxf(fabsf(mvv.x), fabsf(mvv.y)));
         }
-        xb[j] = make_float2((float)gxb, (float)gyb);
-        mvp[j] = mvv;
+        st2(xb + j, make_float2((float)gxb, (float)gyb));
+        st2(mvp + j, mvv);
+    };
+    // two trips per turn with the two load buffers alternating: the next trip's loads are in
+    // flight during this trip's arithmetic, with no register copies that would wait for them
+    Base ba = load(0), bb;
+    for (int64_t j0 = 0; j0 < n; j0 += 124) {
+        trip(j0, ba, bb);
+        if (j0 + 62 >= n) break;
+        trip(j0 + 62, bb, ba);
     }
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) mbig = fmaxf(mbig, __shfl_xor(mbig, o, 64));
