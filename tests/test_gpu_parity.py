@@ -43,6 +43,8 @@ STAGE_CASES = [
     (600, 257, 130, 1, 8, None, 2),
     (400, 64, 64, 8, 2, [0.2, 0.3, 0.5], 3),
     (2000, 320, 200, 5, 6, None, 4),
+    # a small grid whose height leaves three rows in the last strip of four (H = 4k + 3)
+    (300, 37, 23, 2, 2, None, 5),
 ]
 
 
