@@ -259,6 +259,46 @@ def test_resample_parity(hb, E, W, H, delta, seed):
     assert np.abs(hist - href).sum() <= 2 * PT.near_pixel_edge(rs).sum()
 
 
+@pytest.mark.parametrize("E,W,H,B,delta,weighted,seed", [
+    (900, 300, 200, 3, 1.0, False, 31),
+    (400, 256, 256, 1, 4.0, True, 32),
+    (400, 520, 390, 2, 61.0, False, 33),
+    (400, 520, 390, 2, 80.0, True, 34),
+])
+def test_resampled_histogram_is_splat_of_samples(hb, E, W, H, B, delta, weighted, seed):
+    """The histogram of an iteration with the uniform resampling must equal the splat of the
+    GPU's own samples exactly (the tile counts made during the resampling, the binning and
+    the tile histograms): several layers, weights, ragged border tiles, and sample spacings
+    from 1 px to more than a tile (80 px: consecutive samples two tiles apart)."""
+    rng = np.random.default_rng(seed)
+    if delta > 8:
+        off, xy = PT.random_polylines(rng, E, W, H, n_min=2, n_max=4, step=150.0)
+    else:
+        off, xy = PT.random_polylines(rng, E, W, H, n_min=2, n_max=90, step=4.0)
+    group = rng.integers(0, B, E).astype(np.int32)
+    weight = rng.integers(1, 6, E).astype(np.int32) if weighted else None
+    with hb.Bundler(0) as b:
+        b.set_params(W, H, [2], delta=delta)
+        nodes = rng.random((16, 2)).astype(np.float32)
+        src = rng.integers(0, 16, E).astype(np.int32)
+        b.set_graph(nodes, src, ((src + 1) % 16).astype(np.int32), weight)
+        b.set_groups(group, np.eye(B, dtype=np.float32))
+        b.set_points(off, xy)
+        b.run(1)
+        off_s, xy_s = b.points(hb.HB_POINTS_SAMPLES)
+        hist = np.stack([b.map(hb.HB_MAP_HIST, g) for g in range(B)]).astype(np.int64)
+    ref = O.splat(off_s, xy_s.astype(np.float64), group, B, W, H, weight)
+    np.testing.assert_array_equal(hist, ref)
+    # the largest tile step between consecutive samples of one edge: one tile at most below
+    # 64 px spacing, two in the 80 px case
+    tu = np.clip(np.floor(xy_s[:, 0]), 0, W - 1).astype(np.int64) >> 6
+    tv = np.clip(np.floor(xy_s[:, 1]), 0, H - 1).astype(np.int64) >> 6
+    inner = np.ones(len(xy_s) - 1, bool)
+    inner[off_s[1:-1] - 1] = False
+    step = np.maximum(np.abs(np.diff(tu)), np.abs(np.diff(tv)))[inner].max()
+    assert (step > 1) == (delta > 64), step
+
+
 def test_end_to_end_tiny_config(hb):
     """The tiny configuration (2 000 edges, 256x256, r = 8, 10 iterations) against the oracle."""
     w = workloads.tiny()
