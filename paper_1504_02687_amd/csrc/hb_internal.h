@@ -192,9 +192,10 @@ hipError_t launch_init_state(const GDesc *desc, int ng, const Shape &tot, const 
                              double x1, double y1, hipStream_t st);
 hipError_t launch_lengths(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
 hipError_t launch_scan(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
-// u: chunks of 64 segments (resampling) / 62 points (advection) per trip: 1, 2 or 4
+// u: chunks of 64 segments (resampling) / 62 points (advection) per trip: 1, 2 or 4;
+// directed: some graph of the launch has a directed offset (the push is compiled in)
 hipError_t launch_resample_count(const GDesc *desc, int ng, const Shape &tot, int u,
-                                 hipStream_t st);
+                                 bool directed, hipStream_t st);
 hipError_t launch_count_given(const GDesc *desc, int ng, const Shape &tot, hipStream_t st);
 // insert/delete resampling: sample counts of the current polylines (write = false, into
 // counts) or the samples (write = true, at off_s)

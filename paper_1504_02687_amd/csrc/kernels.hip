@@ -148,14 +148,16 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const GDesc *__restrict__
 
 // ---------------------------------------------------------------- resample + bin
 
-// One wave per edge. The polyline (pin) is streamed U chunks of 64 segments at a time;
-// lane j of a chunk holds segment j, its FP64 length and the arclength at its start (wave
-// scans, U independent chains in flight). The samples whose arclength s_k = k L / (n-1)
-// falls in those segments are produced 64 at a time: each lane finds its segment by
-// binary search in LDS and interpolates in FP64. Every sample is stored (coalesced,
-// float2) and counted in its histogram tile: one atomic per run of consecutive samples in
-// the same tile, into the counter set of this block (block mod n_sets).
-template <int U>
+// One wave per edge. The polyline (pin) is streamed 64 U segments at a time; lane j holds
+// segments U j .. U j + U - 1, their FP64 lengths and the arclengths at their starts (the
+// lane's running sums on top of one wave scan of the lanes' sums). The samples whose
+// arclength s_k = k L / (n-1) falls in those segments are produced 64 at a time: each lane
+// finds its segment by binary search in LDS and interpolates in FP64. Every sample is
+// stored (coalesced, float2) and counted in its histogram tile: one atomic per run of
+// consecutive samples in the same tile, into the counter set of this block (block mod
+// n_sets). DIR: the directed push along the segment's normal is compiled in (launches with
+// a graph that has a directed offset).
+template <int U, bool DIR>
 __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
     HB_FIND(blk_edge);
@@ -188,45 +190,42 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
     int knext = 0;
     for (int j0 = 0; j0 < m - 1; j0 += 64 * U) {
         const int rem = m - 1 - j0;
-        float2 a[U], b[U];
-        double incl[U];
-        int ns[U];
+        const int nseg = rem < 64 * U ? rem : 64 * U;   // segments of this chunk
+        // lane l holds segments U l .. U l + U - 1 of the chunk, so its points U l .. U l + U
+        // (the last one is the next lane's first); its length sums feed one wave scan
+        const int sj = U * lane;
+        float2 a[U + 1];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int r = rem - 64 * u;
-            ns[u] = r <= 0 ? 0 : (r < 64 ? r : 64);
-            a[u] = make_float2(0.0f, 0.0f);
-            if (lane <= ns[u] && ns[u] > 0) a[u] = ld2(p + (j0 + 64 * u + lane));
+        for (int i = 0; i < U; ++i) {
+            a[i] = make_float2(0.0f, 0.0f);
+            if (sj + i <= nseg) a[i] = ld2(p + (j0 + sj + i));
         }
+        a[U].x = lane_next(a[0].x);
+        a[U].y = lane_next(a[0].y);
+        if (lane == 63 && nseg == 64 * U) a[U] = ld2(p + (j0 + 64 * U));
+        double ell[U], rcp[U], pre[U + 1];   // pre[i]: the lane's length before segment i
+        pre[0] = 0.0;
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            b[u].x = lane_next(a[u].x);
-            b[u].y = lane_next(a[u].y);
-            if (lane == 63 && ns[u] == 64) b[u] = ld2(p + (j0 + 64 * u + 64));
+        for (int i = 0; i < U; ++i) {
+            seg_len_rcp(a[i], a[i + 1], ell[i], rcp[i]);
+            if (sj + i >= nseg) ell[i] = 0.0;
+            pre[i + 1] = i == 0 ? ell[0] : pre[i] + ell[i];
         }
-        double ell[U], rcp[U];
+        const double incl = wave_incl_scan<double>(pre[U], lane);
+        const double base = Cbase + lane_prev(incl);
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            seg_len_rcp(a[u], b[u], ell[u], rcp[u]);
-            if (lane >= ns[u]) ell[u] = 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) incl[u] = wave_incl_scan<double>(ell[u], lane);
-        double cb = Cbase;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const double excl = lane_prev(incl[u]);
+        for (int i = 0; i < U; ++i) {
+            const int sg = sj + i;
             // arclengths past the chunk's last segment read as +inf: the search needs no
             // bound check
-            sC[wid][64 * u + lane] = lane < ns[u] ? cb + excl : __builtin_huge_val();
-            if (lane < ns[u]) {
-                sR[wid][64 * u + lane] = rcp[u];
-                sP[wid][64 * u + lane] = a[u];
+            sC[wid][sg] = sg < nseg ? (i == 0 ? base : base + pre[i]) : __builtin_huge_val();
+            if (sg < nseg) {
+                sR[wid][sg] = rcp[i];
+                sP[wid][sg] = a[i];
             }
-            if (lane == ns[u] - 1) sP[wid][64 * u + ns[u]] = b[u];
-            cb = cb + last_lane(incl[u]);
+            if (sg == nseg - 1) sP[wid][nseg] = a[i + 1];
         }
-        const double Cend = cb;
+        const double Cend = Cbase + last_lane(incl);
         __builtin_amdgcn_wave_barrier();
 
         const bool last = (j0 + 64 * U >= m - 1);
@@ -266,7 +265,7 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
                     t = fmin(fmax(t, 0.0), 1.0);
                     double ox = __builtin_fma(t, ex, (double)pa.x);
                     double oy = __builtin_fma(t, ey, (double)pa.y);
-                    if (doff != 0.0) {
+                    if (DIR && doff != 0.0) {
                         // directed graphs: along the left normal of the segment, doff / |e|
                         // (-ey, ex) with 1 / |e| the segment's stored reciprocal length
                         const double f = mul_rn(doff, sR[wid][lo]);
@@ -1178,13 +1177,21 @@ hipError_t launch_scan(const GDesc *desc, int ng, const Shape &tot, hipStream_t 
 }
 
 hipError_t launch_resample_count(const GDesc *desc, int ng, const Shape &tot, int u,
-                                 hipStream_t st) {
+                                 bool directed, hipStream_t st) {
     if (tot.edge <= 0) return hipSuccess;
     const dim3 gr = grid_of(tot.edge), bl(kBlock);
-    switch (u) {
-        case 1: hipLaunchKernelGGL(k_resample_count<1>, gr, bl, 0, st, desc, ng); break;
-        case 4: hipLaunchKernelGGL(k_resample_count<4>, gr, bl, 0, st, desc, ng); break;
-        default: hipLaunchKernelGGL(k_resample_count<2>, gr, bl, 0, st, desc, ng); break;
+    if (directed) {
+        switch (u) {
+            case 1: hipLaunchKernelGGL((k_resample_count<1, true>), gr, bl, 0, st, desc, ng); break;
+            case 4: hipLaunchKernelGGL((k_resample_count<4, true>), gr, bl, 0, st, desc, ng); break;
+            default: hipLaunchKernelGGL((k_resample_count<2, true>), gr, bl, 0, st, desc, ng); break;
+        }
+    } else {
+        switch (u) {
+            case 1: hipLaunchKernelGGL((k_resample_count<1, false>), gr, bl, 0, st, desc, ng); break;
+            case 4: hipLaunchKernelGGL((k_resample_count<4, false>), gr, bl, 0, st, desc, ng); break;
+            default: hipLaunchKernelGGL((k_resample_count<2, false>), gr, bl, 0, st, desc, ng); break;
+        }
     }
     return hipGetLastError();
 }

@@ -1102,6 +1102,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
     int max_w = 2, bmax = 1, pmax = 1;
     bool strip = false, points = false;   // graphs with line strips / with the point splat
     bool insdel = false;                  // graphs with the insert/delete resampling
+    bool directed = false;                // graphs with a directed offset
     for (int g = 0; g < n; ++g) {
         const hb_ctx *c = cs[g];
         base[g] = tot;
@@ -1112,6 +1113,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
         strip = strip || c->P.splat_mode == HB_SPLAT_STRIP;
         points = points || c->P.splat_mode != HB_SPLAT_STRIP;
         insdel = insdel || c->P.resample_mode == HB_RESAMPLE_INSERT_DELETE;
+        directed = directed || c->P.directed_offset_px != 0.0f;
     }
     const bool given0 = (flags & HB_RUN_SAMPLES_GIVEN) != 0;
     const bool record = (flags & HB_RUN_RECORD_DECISIONS) != 0;
@@ -1184,7 +1186,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
                 if (!given) HIPCHK(c, hb::launch_scan(dd, n, tot, c->stream));
                 HIPCHK(c, hb::launch_clear_hist(dd, n, tot, c->stream));
                 if (given) HIPCHK(c, hb::launch_count_given(dd, n, tot, c->stream));
-                else HIPCHK(c, hb::launch_resample_count(dd, n, tot, ru, c->stream));
+                else HIPCHK(c, hb::launch_resample_count(dd, n, tot, ru, directed, c->stream));
                 if (!given && insdel) {
                     HIPCHK(c, hb::launch_insdel(dd, n, tot, true, c->stream));
                     HIPCHK(c, hb::launch_count_given(dd, n, tot, c->stream));
@@ -1200,7 +1202,7 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
             if (!given) STAGE(c, HB_STAGE_SCAN, hb::launch_scan(dd, n, tot, c->stream));
             STAGE(c, HB_STAGE_CLEAR, hb::launch_clear_hist(dd, n, tot, c->stream));
             if (given) STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_count_given(dd, n, tot, c->stream));
-            else STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_resample_count(dd, n, tot, ru, c->stream));
+            else STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_resample_count(dd, n, tot, ru, directed, c->stream));
             if (!given && insdel) {
                 STAGE(c, HB_STAGE_RESAMPLE_SPLAT, hb::launch_insdel(dd, n, tot, true, c->stream));
                 STAGE(c, HB_STAGE_BIN, hb::launch_count_given(dd, n, tot, c->stream));
@@ -1222,7 +1224,8 @@ static hb_status enqueue_batch(hb_ctx *lead, hb_ctx *const *cs, int n, int T, ui
     for (int g = 0; g < n; ++g) {
         const hb_ctx *c = cs[g];
         key.insert(key.end(), {(int64_t)(intptr_t)c, c->E, c->B, c->P.grid_w, c->P.grid_h,
-                               c->P.box_passes, c->P.splat_mode, c->P.resample_mode});
+                               c->P.box_passes, c->P.splat_mode, c->P.resample_mode,
+                               (int64_t)(c->P.directed_offset_px != 0.0f)});
     }
     if (!lead->gexec || key != lead->gkey) {
         if (lead->gexec) {
@@ -2307,7 +2310,8 @@ HB_API hb_status hb_forward_ckpt(hb_ctx *c, int32_t n_iters, uint32_t flags, int
         CHKST(upload_desc(c, 1));
         const GDesc *dd = c->d_desc;
         HIPCHK(c, hb::launch_clear_hist(dd, 1, sh, c->stream));
-        HIPCHK(c, hb::launch_resample_count(dd, 1, sh, c->tune_ru, c->stream));
+        // the checkpointed forward takes no directed offset
+        HIPCHK(c, hb::launch_resample_count(dd, 1, sh, c->tune_ru, false, c->stream));
         HIPCHK(c, hb::launch_bin_hist(dd, 1, sh, false, true, c->stream));
         for (int kp = 0; kp < c->P.box_passes; ++kp)
             HIPCHK(c, hb::launch_box_pass(dd, 1, sh, c->P.grid_w, kp, c->stream));
