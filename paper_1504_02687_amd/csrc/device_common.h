@@ -153,6 +153,18 @@ __device__ __forceinline__ T wave_incl_scan(T v, int lane) {
     return v;
 }
 
+// Inclusive sum inside each half of the wave (lanes 0..31 and 32..63 separately): the same
+// steps without the lane 31 broadcast, so lane 32 + r adds in the order lane r does.
+template <typename T>
+__device__ __forceinline__ T half_incl_scan(T v) {
+    v += dpp0<kDppRowShr + 1>(v);
+    v += dpp0<kDppRowShr + 2>(v);
+    v += dpp0<kDppRowShr + 4>(v);
+    v += dpp0<kDppRowShr + 8>(v);
+    v += dpp<kDppRowBcast15, 0xa>((T)0, v);
+    return v;
+}
+
 // Sum over the wave, the same value in every lane (every lane active).
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v) {

@@ -148,11 +148,11 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const GDesc *__restrict__
 
 // ---------------------------------------------------------------- resample + bin
 
-// One wave per edge. The polyline (pin) is streamed 64 U segments at a time; lane j holds
-// segments U j .. U j + U - 1, their FP64 lengths and the arclengths at their starts (the
-// lane's running sums on top of one wave scan of the lanes' sums). The samples whose
-// arclength s_k = k L / (n-1) falls in those segments are produced 64 at a time: each lane
-// finds its segment by binary search in LDS and interpolates in FP64. Every sample is
+// One wave per edge. The polyline (pin) is streamed 64 U segments at a time, with their
+// FP64 lengths and the arclengths at their starts (pair sums, 32-lane scans per block of 64
+// segments, blocks chained). The samples whose arclength s_k = k L / (n-1) falls in those
+// segments are produced 64 at a time: each lane finds its segment by binary search in LDS
+// and interpolates in FP64. Every sample is
 // stored (coalesced, float2) and counted in its histogram tile: one atomic per run of
 // consecutive samples in the same tile, into the counter set of this block (block mod
 // n_sets). DIR: the directed push along the segment's normal is compiled in (launches with
@@ -191,41 +191,52 @@ __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__res
     for (int j0 = 0; j0 < m - 1; j0 += 64 * U) {
         const int rem = m - 1 - j0;
         const int nseg = rem < 64 * U ? rem : 64 * U;   // segments of this chunk
-        // lane l holds segments U l .. U l + U - 1 of the chunk, so its points U l .. U l + U
-        // (the last one is the next lane's first); its length sums feed one wave scan
-        const int sj = U * lane;
-        float2 a[U + 1];
+        // blocks of 64 segments, each summed the same way whatever U is (so every U gives the
+        // same bits): lane r of a half holds two consecutive segments of a block, their sum
+        // enters a 32-lane scan, and the block's base is the previous block's base plus that
+        // block's total. Pass q holds blocks 2q (lanes 0-31) and 2q + 1 (lanes 32-63), i.e.
+        // lane l holds segments 128 q + 2 l and 128 q + 2 l + 1 of the chunk.
+        double cb = Cbase;               // base of block 2q
 #pragma unroll
-        for (int i = 0; i < U; ++i) {
-            a[i] = make_float2(0.0f, 0.0f);
-            if (sj + i <= nseg) a[i] = ld2(p + (j0 + sj + i));
-        }
-        a[U].x = lane_next(a[0].x);
-        a[U].y = lane_next(a[0].y);
-        if (lane == 63 && nseg == 64 * U) a[U] = ld2(p + (j0 + 64 * U));
-        double ell[U], rcp[U], pre[U + 1];   // pre[i]: the lane's length before segment i
-        pre[0] = 0.0;
+        for (int q = 0; q < (U + 1) / 2; ++q) {
+            const int sj = 128 * q + 2 * lane;
+            float2 a[3];
 #pragma unroll
-        for (int i = 0; i < U; ++i) {
-            seg_len_rcp(a[i], a[i + 1], ell[i], rcp[i]);
-            if (sj + i >= nseg) ell[i] = 0.0;
-            pre[i + 1] = i == 0 ? ell[0] : pre[i] + ell[i];
-        }
-        const double incl = wave_incl_scan<double>(pre[U], lane);
-        const double base = Cbase + lane_prev(incl);
-#pragma unroll
-        for (int i = 0; i < U; ++i) {
-            const int sg = sj + i;
-            // arclengths past the chunk's last segment read as +inf: the search needs no
-            // bound check
-            sC[wid][sg] = sg < nseg ? (i == 0 ? base : base + pre[i]) : __builtin_huge_val();
-            if (sg < nseg) {
-                sR[wid][sg] = rcp[i];
-                sP[wid][sg] = a[i];
+            for (int i = 0; i < 2; ++i) {
+                a[i] = make_float2(0.0f, 0.0f);
+                if (sj + i <= nseg) a[i] = ld2(p + (j0 + sj + i));
             }
-            if (sg == nseg - 1) sP[wid][nseg] = a[i + 1];
+            a[2].x = lane_next(a[0].x);
+            a[2].y = lane_next(a[0].y);
+            if (lane == 63 && 128 * q + 128 <= nseg) a[2] = ld2(p + (j0 + 128 * q + 128));
+            double ell[2], rcp[2];
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                seg_len_rcp(a[i], a[i + 1], ell[i], rcp[i]);
+                if (sj + i >= nseg) ell[i] = 0.0;
+            }
+            const double incl = half_incl_scan<double>(ell[0] + ell[1]);
+            const double prev = lane_prev(incl);
+            const double t0 = read_lane(incl, 31), t1 = read_lane(incl, 63);   // block totals
+            const double bb = lane < 32 ? cb : cb + t0;                        // block base
+            const double c0 = (lane & 31) ? bb + prev : bb;
+#pragma unroll
+            for (int i = 0; i < 2; ++i) {
+                const int sg = sj + i;
+                if (sg < 64 * U) {
+                    // arclengths past the chunk's last segment read as +inf: the search
+                    // needs no bound check
+                    sC[wid][sg] = sg < nseg ? (i == 0 ? c0 : c0 + ell[0]) : __builtin_huge_val();
+                    if (sg < nseg) {
+                        sR[wid][sg] = rcp[i];
+                        sP[wid][sg] = a[i];
+                    }
+                    if (sg == nseg - 1) sP[wid][nseg] = a[i + 1];
+                }
+            }
+            cb = (cb + t0) + t1;
         }
-        const double Cend = Cbase + last_lane(incl);
+        const double Cend = cb;
         __builtin_amdgcn_wave_barrier();
 
         const bool last = (j0 + 64 * U >= m - 1);
