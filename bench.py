@@ -52,10 +52,17 @@ def log(*a):
 
 
 def kernel_source_hash():
+    """Hash of the sources the counted kernels are built from, without their comments and
+    with whitespace runs folded, so that only a change of the code itself invalidates the
+    committed traffic counters."""
+    import re
+    token = re.compile(r'"(?:\\.|[^"\\])*"|//[^\n]*|/\*.*?\*/', re.S)
     h = hashlib.sha256()
     for f in ("kernels.hip", "device_common.h", "hb_internal.h"):
-        with open(os.path.join(ROOT, "paper_1504_02687_amd", "csrc", f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, "paper_1504_02687_amd", "csrc", f), encoding="utf-8") as fh:
+            src = token.sub(lambda m: m.group(0) if m.group(0).startswith('"') else " ", fh.read())
+        h.update(" ".join(src.split()).encode())
+        h.update(b"\0")
     return h.hexdigest()[:16]
 
 

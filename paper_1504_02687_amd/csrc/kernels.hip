@@ -152,11 +152,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_apply(const GDesc *__restrict__
 // FP64 lengths and the arclengths at their starts (pair sums, 32-lane scans per block of 64
 // segments, blocks chained). The samples whose arclength s_k = k L / (n-1) falls in those
 // segments are produced 64 at a time: each lane finds its segment by binary search in LDS
-// and interpolates in FP64. Every sample is
-// stored (coalesced, float2) and counted in its histogram tile: one atomic per run of
-// consecutive samples in the same tile, into the counter set of this block (block mod
-// n_sets). DIR: the directed push along the segment's normal is compiled in (launches with
-// a graph that has a directed offset).
+// and interpolates in FP64. Every sample is stored (coalesced, float2) and counted in its
+// histogram tile: one atomic per run of consecutive samples in the same tile, into the
+// counter set of this block (block mod n_sets). DIR: the directed push along the segment's
+// normal is compiled in (launches with a graph that has a directed offset).
 template <int U, bool DIR>
 __global__ __launch_bounds__(kBlock, 7) void k_resample_count(const GDesc *__restrict__ gd, int ng) {
     const int64_t blk = blockIdx.x;
