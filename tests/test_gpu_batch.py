@@ -152,6 +152,27 @@ def test_autotune_restores_polylines_and_tuning_is_bit_identical(hb):
             assert ei.value.status == hb.HB_EINVAL
 
 
+def test_resample_chunk_counts_give_the_same_bits(hb):
+    """The resampling sums its arclengths in blocks of 64 segments whatever its chunk count
+    (64, 128 or 256 segments per trip), so its three kernels give the same polylines bit for
+    bit; a 0.25 px spacing makes polylines of many chunks."""
+    w = workloads.scaled("clustered", n_edges=2000, grid=512, groups=3, n_iters=3, seed=31,
+                         delta=0.25)
+    ref = None
+    for ru in (2, 1, 4):
+        with hb.Bundler(0) as b:
+            b.set_workload(w)
+            b.tuning(ru, 2)
+            b.run(3)
+            off, xy = b.points()
+        if ref is None:
+            ref = (off, xy)
+            assert np.diff(off).max() > 1000
+        else:
+            np.testing.assert_array_equal(off, ref[0])
+            np.testing.assert_array_equal(xy, ref[1])
+
+
 def test_batch_argument_errors(hb):
     w = small_batch(1, seed=600)[0]
     with hb.Bundler(0) as a, hb.Bundler(0) as c:
